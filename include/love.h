@@ -1,0 +1,233 @@
+/*
+ * love.h -- C ABI of the LOVE (LanczOs Variance Estimates) library for KISS-GP
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Pleiss, Gardner, Weinberger and Wilson, "Constant-Time
+ * Predictive Distributions for Gaussian Processes" (ICML 2018):
+ *
+ *   training operator   Khat = W K W^T + sigma^2 I          (Sec. 2.3, eq. ski; Alg. 1 input mvm_K_XX)
+ *   W                   cubic (Keys) interpolation, 4^d non-zeros per row (Sec. 2.3)
+ *   K = K_UU            Toeplitz / Kronecker-of-Toeplitz grid kernel (Sec. 2.3)
+ *   cache               k-step Lanczos on Khat with probe b = (1/m) W K 1 and
+ *                       full reorthogonalisation (Sec. 3.2, Sec. 5), T = L L^T,
+ *                       R = Q^T W K, R' = T^{-1} R (Alg. 1).  The library stores the
+ *                       single m x k matrix Rt = (L^{-1} R)^T, for which
+ *                       R^T R' = Rt Rt^T, so one gather serves both factors.
+ *   mean cache          a = K W^T Khat^{-1} y (Sec. 2.3, eq. pred_mean_ski)
+ *   variance            var(x*) = w*^T K w* - ||Rt^T w*||^2 (eq. pred_covar_ski_fast, i = j)
+ *   sampling            S = Q' L_{T'} from Lanczos on K - R^T R' (Sec. 3.3,
+ *                       eqs. lancapprox, pred_covar_ski_interp_form);
+ *                       sample = mu(X*) + W_{X*} S z (eq. sample)
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, except the
+ *     love_config structs and the small host arrays of the batched entry
+ *     points, which are host memory.  The library owns every love_cache.
+ *   - Element type of x, y, x*, mean, var, samples and gradients follows
+ *     love_config.precision: LOVE_P_FP64 -> double, otherwise float.
+ *     Sampling noise z and the optional dRt gradient are always float.
+ *   - Point arrays are row-major n x d (d = cfg->d).  Every coordinate must lie
+ *     in [lo_i, hi_i] of its dimension.
+ *   - All work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *     Query entry points never synchronise the host.  love_build_cache
+ *     synchronises once at its end (to report device-detected errors) unless
+ *     LOVE_FLAG_ASYNC is set.
+ *   - Errors are returned as love_status; nothing is thrown across the ABI.
+ *     Argument errors are detected on the host before any work is enqueued.
+ *     Conditions only visible on the device (a query point outside the domain,
+ *     non-finite values) set bits in the cache's status word, reported by
+ *     love_cache_info; out-of-domain query points get NaN outputs.
+ *   - A built cache is immutable; concurrent queries on different streams are
+ *     safe.  Calls that allocate (build, free) are not thread-safe with respect
+ *     to the same cache.
+ */
+#ifndef LOVE_H_
+#define LOVE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LOVE_ABI_VERSION 1
+#define LOVE_MAX_DIM 4
+#define LOVE_MAX_K 128
+
+typedef int32_t love_status;
+enum {
+  LOVE_OK = 0,
+  LOVE_EINVAL = -1,        /* bad argument (null pointer, size, dimension, k, ...)          */
+  LOVE_EDOMAIN = -2,       /* a training point lies outside [lo, hi]                         */
+  LOVE_ENOTPD = -3,        /* the Lanczos tridiagonal T was not positive definite            */
+  LOVE_ENOMEM = -4,        /* device allocation failed                                       */
+  LOVE_EHIP = -5,          /* a HIP runtime call failed                                      */
+  LOVE_ENONFINITE = -6,    /* non-finite training input or Lanczos coefficient               */
+  LOVE_EUNSUPPORTED = -7   /* valid request the library does not support (e.g. no sampler)   */
+};
+
+typedef enum { LOVE_RBF = 0, LOVE_MATERN52 = 1 } love_kernel;   /* product over dimensions */
+
+typedef enum {
+  LOVE_P_FP64 = 0,          /* all vectors and the cache in double                              */
+  LOVE_P_FP32 = 1,          /* float vectors and cache; double tridiagonal work and variance
+                               subtraction                                                      */
+  LOVE_P_FP32_BF16SPLIT = 2 /* as FP32, but Rt stored as bf16 hi + bf16 lo planes              */
+} love_precision;
+
+typedef enum {
+  LOVE_TOEPLITZ_AUTO = 0,   /* per-axis choice by the built-in autotuner                       */
+  LOVE_TOEPLITZ_DIRECT = 1, /* O(m_i^2) per line, register-blocked, all CUs                    */
+  LOVE_TOEPLITZ_FFT = 2     /* circulant embedding, LDS-resident radix-2 FFT, O(m_i log m_i)  */
+} love_toeplitz_mode;
+
+/* Flags (love_config.flags) */
+#define LOVE_FLAG_ASYNC 1u          /* build does not synchronise at its end                     */
+#define LOVE_FLAG_NO_MEAN 2u        /* skip the mean cache a                                      */
+#define LOVE_FLAG_PLAIN_CG 4u       /* mean solve starts CG from 0 instead of the Lanczos solve */
+
+typedef struct {
+  int32_t d;                        /* input dimension, 1..4                                     */
+  int32_t m[LOVE_MAX_DIM];          /* grid points per dimension, >= 4.  The grid is padded by
+                                       one cell on each side: h_i = (hi_i - lo_i) / (m_i - 3),
+                                       node j at lo_i + (j - 1) h_i                              */
+  double lo[LOVE_MAX_DIM];          /* data domain per dimension (lo < hi)                       */
+  double hi[LOVE_MAX_DIM];
+  int32_t kernel;                   /* love_kernel                                               */
+  double lengthscale[LOVE_MAX_DIM]; /* > 0                                                       */
+  double outputscale;               /* > 0                                                       */
+  double noise;                     /* sigma^2 > 0 (a variance)                                  */
+  int32_t k;                        /* Lanczos steps, 1..LOVE_MAX_K (k_eff <= k is reported)     */
+  int32_t k_sample;                 /* 0: no sampling cache; else second-Lanczos steps (<= 128)  */
+  int32_t precision;                /* love_precision                                            */
+  int32_t toeplitz;                 /* love_toeplitz_mode                                        */
+  double cg_tol;                    /* relative residual of the mean solve (<= 0: 1e-6 / 1e-12)  */
+  int32_t cg_maxit;                 /* <= 0: 1000                                                */
+  uint32_t flags;                   /* LOVE_FLAG_*                                               */
+} love_config;
+
+typedef struct love_cache love_cache;   /* opaque */
+
+/* Status bits (love_cache_info_t.status_flags) */
+#define LOVE_SF_DOMAIN 1u           /* a point outside [lo, hi] was seen                          */
+#define LOVE_SF_NONFINITE 2u        /* non-finite x / y / coefficient                              */
+#define LOVE_SF_NOTPD 4u            /* T not positive definite; k_eff truncated at the first bad pivot */
+#define LOVE_SF_BREAKDOWN 8u        /* Lanczos stopped early (invariant subspace); not an error   */
+#define LOVE_SF_CG_NOCONV 16u       /* mean CG hit cg_maxit                                        */
+#define LOVE_SF_SAMPLER_TRUNC 32u   /* T' Cholesky truncated at a non-positive pivot              */
+
+typedef struct {
+  int32_t k_eff;                    /* Lanczos steps kept                                         */
+  int32_t k_eff_sample;             /* columns of S                                               */
+  int32_t cg_iters;                 /* CG iterations of the mean solve                            */
+  int32_t d;
+  int64_t n, m;
+  double beta_last;                 /* last Lanczos off-diagonal                                  */
+  uint32_t status_flags;            /* LOVE_SF_*                                                  */
+  uint32_t toeplitz_mode[LOVE_MAX_DIM]; /* backend chosen per axis (1 direct, 2 fft)          */
+  uint32_t fft_len[LOVE_MAX_DIM];   /* circulant length per axis when FFT is used                 */
+  size_t bytes;                     /* device bytes held by the cache                             */
+} love_cache_info_t;
+
+/* Buffers the cache contents can be copied into (all device, caller-owned, any may be NULL). */
+typedef struct {
+  double* alpha;                    /* k_eff  : diagonal of T                                      */
+  double* beta;                     /* k_eff  : off-diagonal of T (beta[k_eff-1] = last residual)  */
+  float* rt;                        /* m x k_eff row-major : Rt (dequantised for the bf16 split)  */
+  double* rt64;                     /* m x k_eff row-major : Rt when precision is FP64            */
+  void* a;                          /* m      : mean cache (precision's element type)             */
+  float* s;                         /* m x k_eff_sample row-major : sampling matrix S             */
+} love_export;
+
+/* ABI version of the loaded library (LOVE_ABI_VERSION). */
+int32_t love_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* love_status_string(love_status s);
+
+/* Build the LOVE cache (Alg. 1 precomputation, Sec. 3.2) and, if
+ * cfg->k_sample > 0, the sampling matrix S (Sec. 3.3).
+ *   x : n x d training inputs, y : n targets (device, precision's type).
+ *   out : receives the new cache; untouched on error.
+ * Errors: EINVAL (arguments), EDOMAIN (x outside [lo, hi]), ENONFINITE (non-finite
+ * x, y, or Lanczos breakdown into NaN), ENOMEM, EHIP.  A T that is not positive
+ * definite truncates k_eff and sets LOVE_SF_NOTPD (not an error). */
+love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
+                             void* stream, love_cache** out);
+
+/* Build G independent caches with every phase launched once for all GPs
+ * (kernels index a per-launch work table of (gp, tile)), so small GPs share
+ * the device instead of each under-filling it.  cfgs, xs, ys, ns, out are host
+ * arrays of length G; all GPs must share precision and d.  On error no cache is
+ * returned.  Each GP's result equals its single-GP build on the same inputs. */
+love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
+                                     const void* const* ys, const int64_t* ns, void* stream,
+                                     love_cache** out);
+
+/* Constant-time predictive mean and variance (eq. pred_mean_ski; eq.
+ * pred_covar_ski_fast with i = j).  xs : t x d; mean (nullable) and var : t. */
+love_status love_predict_mean_var(const love_cache* c, const void* xs, int64_t t, void* mean,
+                                  void* var, void* stream);
+
+/* Same for G caches in one launch (host arrays of length G). */
+love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* caches,
+                                          const void* const* xs, const int64_t* ts,
+                                          void* const* means, void* const* vars, void* stream);
+
+/* Predictive cross-covariance of paired points: cov[i] = k(xa_i, xb_i)
+ * (Alg. 1 with w_i != w_j).  xa, xb : t x d; cov : t. */
+love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
+                                     int64_t t, void* cov, void* stream);
+
+/* Posterior samples (eq. sample with S of eq. pred_covar_ski_interp_form):
+ * out[i, j] = mu(xs_i) + sum_a w_a(xs_i) (S z_j)[a].
+ *   z : k_eff_sample x s row-major standard normals (float; rows beyond
+ *       k_eff_sample are ignored, so a k_sample x s array is always valid);
+ *   out : t x s row-major.
+ * Errors: EUNSUPPORTED if the cache has no sampler. */
+love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
+                                  int64_t s, void* out, void* stream);
+
+/* Backward of love_predict_mean_var: given upstream gradients g_mean, g_var
+ * (t each, either nullable), writes g_xs (t x d) = d(sum g_mean*mean + g_var*var)/d xs,
+ * through the derivative interpolation weights, and, if g_rt is not NULL,
+ * ACCUMULATES d(sum g_var*var)/d Rt into g_rt (m x k_eff row-major float; the
+ * caller zeroes it; accumulation uses float atomics, so its summation order
+ * is not deterministic). */
+love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t,
+                                  const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
+                                  void* stream);
+
+/* out = Khat v = (W K W^T + sigma^2 I) v in the caller's training-row order (n). */
+love_status love_apply_khat(const love_cache* c, const void* v, void* out, void* stream);
+
+/* out = K_UU g on the grid (m, row-major grid order, last dimension fastest). */
+love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* stream);
+
+/* Query counters and status (synchronises the stream the cache was built on). */
+love_status love_cache_info(const love_cache* c, love_cache_info_t* info);
+
+/* Copy cache contents into caller device buffers (enqueued on `stream`). */
+love_status love_cache_export(const love_cache* c, const love_export* e, void* stream);
+
+/* Release a cache (synchronises its build stream first).  NULL is a no-op. */
+void love_cache_free(love_cache* c);
+
+/* Per-kernel timing with HIP events recorded around each launch on the
+ * launch stream.  enable=1 starts (and clears) collection, 0 stops it.  Timing
+ * adds a pair of event records per launch; it does not change the work. */
+love_status love_profile_enable(int32_t enable);
+
+/* Restrict timing to the named scopes (comma-separated); NULL or "" = all. */
+love_status love_profile_select(const char* names);
+
+/* Read accumulated timings (synchronises).  For each kernel name in
+ * `names` (comma-separated, e.g. "cgs_update,gather_dots"), writes the number of
+ * launches and the total milliseconds into calls[i] and ms[i]. */
+love_status love_profile_read(const char* names, int64_t* calls, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOVE_H_ */

@@ -32,7 +32,10 @@ Readings of points the paper leaves open (each is listed in the design notes):
             Gram-Schmidt passes against all previous vectors every step,
             stop when beta_j <= tol * max|alpha|
   sampler   second Lanczos probe b' = (1/m) (K - R^T R') 1, k' = k, Cholesky
-            of T' truncated at the first non-positive pivot
+            of T'; when T' is not positive definite (K - R^T R' is only
+            positive semi-definite, and rounding can push Ritz values below
+            zero) S = Q' V diag(max(lam, 0))^{1/2} from T' = V diag(lam) V^T,
+            which gives the same S S^T whenever the Cholesky exists
   noise     `noise` is sigma^2 (a variance)
 """
 from __future__ import annotations
@@ -508,14 +511,16 @@ def love_predict_grad(cache: LoveCache, Xs, g_mean=None, g_var=None):
 class SamplerCache:
     S: np.ndarray          # m x k'_eff
     lanczos: LanczosResult
-    k_chol: int            # leading block of T' that is positive definite
+    k_chol: int            # columns of S
+    used_cholesky: bool
 
 
 def love_sampler(cache: LoveCache, k_sample: int, tol: float = 1e-12) -> SamplerCache:
     """Lanczos on K - R^T R' (eq. lancapprox) with probe (1/m)(K - R^T R') 1,
-    then S = Q' L_{T'} (eq. pred_covar_ski_interp_form).  If T' is not positive
-    definite, the Cholesky stops at the first non-positive pivot and S keeps the
-    leading columns for which it is."""
+    then S = Q' L_{T'} (eq. pred_covar_ski_interp_form).  If T' is not
+    numerically positive definite, S = Q' V sqrt(max(lam, 0)) instead (columns
+    with lam <= 0 dropped), which has the same S S^T as the Cholesky route
+    whenever that exists."""
     spec = cache.spec
     m = spec.mtot
 
@@ -524,23 +529,20 @@ def love_sampler(cache: LoveCache, k_sample: int, tol: float = 1e-12) -> Sampler
 
     b = mvm(np.ones(m)) / m
     lz = lanczos(mvm, b, k_sample, tol)
-    kk = lz.k_eff
-    alpha, beta = lz.alpha, lz.beta
-    ldiag = np.zeros(kk)
-    lsub = np.zeros(kk)
-    k_chol = kk
-    amax = np.max(np.abs(alpha))
-    for i in range(kk):
-        piv = alpha[i] - (lsub[i - 1] ** 2 if i > 0 else 0.0)
-        if not piv > tol * amax:
-            k_chol = i
-            break
-        ldiag[i] = math.sqrt(piv)
-        if i + 1 < kk:
-            lsub[i] = beta[i] / ldiag[i]
-    L = np.diag(ldiag[:k_chol]) + np.diag(lsub[: max(k_chol - 1, 0)], -1)
-    S = lz.Q[:, :k_chol] @ L
-    return SamplerCache(S, lz, k_chol)
+    T = lz.T()
+    amax = np.max(np.abs(lz.alpha))
+    try:
+        ldiag, lsub = tridiag_cholesky(lz.alpha, lz.beta)
+        if np.min(ldiag ** 2) <= tol * amax:
+            raise np.linalg.LinAlgError("numerically singular")
+        L = np.diag(ldiag) + np.diag(lsub, -1)
+        S = lz.Q @ L
+        return SamplerCache(S, lz, S.shape[1], True)
+    except np.linalg.LinAlgError:
+        lam, V = np.linalg.eigh(T)
+        keep = lam > 0
+        S = lz.Q @ (V[:, keep] * np.sqrt(lam[keep]))
+        return SamplerCache(S, lz, S.shape[1], False)
 
 
 def love_sample(cache: LoveCache, sampler: SamplerCache, Xs, Z):

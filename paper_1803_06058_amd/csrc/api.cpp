@@ -1,0 +1,477 @@
+// C ABI of the LOVE library: argument validation, cache allocation, build
+// orchestration, query dispatch and the optional per-kernel event timer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace love;
+
+// ----------------------------------------------------------------------------
+// Kernel timing
+// ----------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> pending;
+  std::vector<std::pair<std::string, hipEvent_t>> open;  // begin events by name (stack)
+  std::map<std::string, std::pair<int64_t, double>> acc;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> select;   // empty: time every scope
+};
+ProfState& prof() {
+  static ProfState* p = new ProfState();
+  return *p;
+}
+hipEvent_t take_event(ProfState& p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+void drain(ProfState& p) {
+  for (auto& r : p.pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    auto& slot = p.acc[r.name];
+    slot.first += 1;
+    slot.second += ms;
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.pending.clear();
+}
+}  // namespace
+
+namespace love {
+bool prof_on() { return prof().on; }
+void prof_begin(const char* name, hipStream_t s) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  if (!p.select.empty() && std::find(p.select.begin(), p.select.end(), name) == p.select.end()) return;
+  hipEvent_t e = take_event(p);
+  hipEventRecord(e, s);
+  p.open.emplace_back(name, e);
+}
+void prof_end(const char* name, hipStream_t s) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  for (size_t i = p.open.size(); i-- > 0;) {
+    if (p.open[i].first == name) {
+      hipEvent_t b = take_event(p);
+      hipEventRecord(b, s);
+      p.pending.push_back({name, p.open[i].second, b});
+      p.open.erase(p.open.begin() + i);
+      break;
+    }
+  }
+  if (p.pending.size() > 4096) drain(p);
+}
+
+void* dev_alloc(love_cache* c, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  c->allocs.push_back(p);
+  c->bytes += bytes;
+  return p;
+}
+}  // namespace love
+
+// ----------------------------------------------------------------------------
+// Validation
+// ----------------------------------------------------------------------------
+static love_status validate(const love_config* cfg) {
+  if (!cfg) return LOVE_EINVAL;
+  if (cfg->d < 1 || cfg->d > LOVE_MAX_DIM) return LOVE_EINVAL;
+  int64_t mt = 1, ct = 1;
+  for (int e = 0; e < cfg->d; ++e) {
+    if (cfg->m[e] < 4) return LOVE_EINVAL;
+    if (!(cfg->hi[e] > cfg->lo[e]) || !std::isfinite(cfg->lo[e]) || !std::isfinite(cfg->hi[e]))
+      return LOVE_EINVAL;
+    if (!(cfg->lengthscale[e] > 0) || !std::isfinite(cfg->lengthscale[e])) return LOVE_EINVAL;
+    mt *= cfg->m[e];
+    ct *= cfg->m[e] - 3;
+    if (mt > (int64_t(1) << 31) || ct > (int64_t(1) << 30)) return LOVE_EINVAL;
+  }
+  if (!(cfg->outputscale > 0) || !std::isfinite(cfg->outputscale)) return LOVE_EINVAL;
+  if (!(cfg->noise > 0) || !std::isfinite(cfg->noise)) return LOVE_EINVAL;
+  if (cfg->kernel != LOVE_RBF && cfg->kernel != LOVE_MATERN52) return LOVE_EINVAL;
+  if (cfg->k < 1 || cfg->k > LOVE_MAX_K) return LOVE_EINVAL;
+  if (cfg->k_sample < 0 || cfg->k_sample > LOVE_MAX_K) return LOVE_EINVAL;
+  if (cfg->precision < LOVE_P_FP64 || cfg->precision > LOVE_P_FP32_BF16SPLIT) return LOVE_EINVAL;
+  if (cfg->toeplitz < LOVE_TOEPLITZ_AUTO || cfg->toeplitz > LOVE_TOEPLITZ_FFT) return LOVE_EINVAL;
+  if (cfg->cg_tol < 0 || !std::isfinite(cfg->cg_tol)) return LOVE_EINVAL;
+  return LOVE_OK;
+}
+
+static int kround(int k) { return k <= 64 ? 64 : 128; }
+
+static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, hipStream_t s) {
+  c->cfg = *cfg;
+  c->fp64 = cfg->precision == LOVE_P_FP64;
+  c->d = cfg->d;
+  c->n = n;
+  c->stream = s;
+  (void)hipGetDevice(&c->device);
+  int64_t m = 1, ct = 1;
+  for (int e = 0; e < 4; ++e) {
+    if (e < c->d) {
+      c->mdim[e] = cfg->m[e];
+      c->lo[e] = cfg->lo[e];
+      c->hi[e] = cfg->hi[e];
+      c->invh[e] = (double)(cfg->m[e] - 3) / (cfg->hi[e] - cfg->lo[e]);
+      m *= cfg->m[e];
+      ct *= cfg->m[e] - 3;
+    } else {
+      c->mdim[e] = 1;
+      c->lo[e] = c->hi[e] = 0.0;
+      c->invh[e] = 0.0;
+    }
+  }
+  c->m = m;
+  c->ctot = ct;
+  c->k = (int)std::min<int64_t>(cfg->k, n);
+  c->kpad = kround(c->k);
+  c->ks = (int)std::min<int64_t>(cfg->k_sample, m);
+  c->kspad = c->ks > 0 ? kround(c->ks) : 0;
+  c->tol_lanczos = c->fp64 ? 1e-12 : 1e-8;
+  const size_t es = c->fp64 ? 8 : 4;
+  c->x = dev_alloc(c, es * (size_t)n * c->d);
+  c->y = dev_alloc(c, es * (size_t)n);
+  c->perm = (int32_t*)dev_alloc(c, 4 * (size_t)n);
+  c->cell_start = (int32_t*)dev_alloc(c, 4 * (size_t)(ct + 1));
+  c->ctl = (Ctl*)dev_alloc(c, sizeof(Ctl));
+  c->ctl_s = (Ctl*)dev_alloc(c, sizeof(Ctl));
+  c->status = (unsigned*)dev_alloc(c, sizeof(unsigned) * 4);
+  c->alpha = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
+  c->beta = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
+  const bool split = cfg->precision == LOVE_P_FP32_BF16SPLIT;
+  c->rt = dev_alloc(c, (split ? 2 : es) * (size_t)m * c->kpad);
+  if (split) c->rt_lo = dev_alloc(c, 2 * (size_t)m * c->kpad);
+  c->a = dev_alloc(c, es * (size_t)m);
+  if (c->ks > 0) c->S = (float*)dev_alloc(c, sizeof(float) * (size_t)m * c->kspad);
+  c->v1 = dev_alloc(c, es * (size_t)n);
+  c->v2 = dev_alloc(c, es * (size_t)n);
+  c->g1 = dev_alloc(c, es * (size_t)m);
+  c->g2 = dev_alloc(c, es * (size_t)m);
+  if (!c->x || !c->y || !c->perm || !c->cell_start || !c->ctl || !c->ctl_s || !c->status ||
+      !c->alpha || !c->beta || !c->rt || (split && !c->rt_lo) || !c->a || (c->ks > 0 && !c->S) ||
+      !c->v1 || !c->v2 || !c->g1 || !c->g2)
+    return LOVE_ENOMEM;
+  LOVE_HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(unsigned) * 4, s));
+  LOVE_HIP_TRY(hipMemsetAsync(c->ctl, 0, sizeof(Ctl), s));
+  LOVE_HIP_TRY(hipMemsetAsync(c->ctl_s, 0, sizeof(Ctl), s));
+  LOVE_HIP_TRY(hipMemsetAsync(c->a, 0, es * (size_t)m, s));
+  return LOVE_OK;
+}
+
+static void destroy(love_cache* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+}
+
+static love_status finish_status(love_cache* c) {
+  Ctl h;
+  unsigned st[4];
+  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  LOVE_HIP_TRY(hipMemcpyAsync(st, c->status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  LOVE_HIP_TRY(hipStreamSynchronize(c->stream));
+  const unsigned all = h.status | st[0];
+  if (all & SF_DOMAIN) return LOVE_EDOMAIN;
+  if (all & SF_NONFINITE) return LOVE_ENONFINITE;
+  if (h.k_eff < 1) return LOVE_ENOTPD;
+  return LOVE_OK;
+}
+
+template <typename T>
+static love_status build_one(love_cache* c, const void* x, const void* y, hipStream_t s) {
+  love_status st = setup_sort<T>(c, (const T*)x, (const T*)y, s);
+  if (st != LOVE_OK) return st;
+  st = toeplitz_plan(c);
+  if (st != LOVE_OK) return st;
+  st = build_lanczos_and_mean<T>(c, s);
+  if (st != LOVE_OK) return st;
+  if (c->ks > 0) {
+    st = build_sampler(c, s);
+    if (st != LOVE_OK) return st;
+  }
+  return LOVE_OK;
+}
+
+extern "C" {
+
+int32_t love_abi_version(void) { return LOVE_ABI_VERSION; }
+
+const char* love_status_string(love_status s) {
+  switch (s) {
+    case LOVE_OK: return "ok";
+    case LOVE_EINVAL: return "invalid argument";
+    case LOVE_EDOMAIN: return "point outside the grid domain";
+    case LOVE_ENOTPD: return "Lanczos tridiagonal not positive definite";
+    case LOVE_ENOMEM: return "device out of memory";
+    case LOVE_EHIP: return "HIP runtime error";
+    case LOVE_ENONFINITE: return "non-finite value";
+    case LOVE_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
+                             void* stream, love_cache** out) {
+  if (!out || !x || !y || n < 1 || n > INT32_MAX) return LOVE_EINVAL;
+  love_status st = validate(cfg);
+  if (st != LOVE_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  love_cache* c = new (std::nothrow) love_cache();
+  if (!c) return LOVE_ENOMEM;
+  st = init_cache(c, cfg, n, s);
+  if (st == LOVE_OK) st = c->fp64 ? build_one<double>(c, x, y, s) : build_one<float>(c, x, y, s);
+  if (st == LOVE_OK && !(cfg->flags & LOVE_FLAG_ASYNC)) st = finish_status(c);
+  if (st != LOVE_OK) {
+    destroy(c);
+    return st;
+  }
+  *out = c;
+  return LOVE_OK;
+}
+
+love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
+                                     const void* const* ys, const int64_t* ns, void* stream,
+                                     love_cache** out) {
+  if (G < 1 || !cfgs || !xs || !ys || !ns || !out) return LOVE_EINVAL;
+  for (int g = 0; g < G; ++g) {
+    love_status st = validate(&cfgs[g]);
+    if (st != LOVE_OK) return st;
+    if (cfgs[g].precision != cfgs[0].precision || cfgs[g].d != cfgs[0].d) return LOVE_EINVAL;
+  }
+  std::vector<love_cache*> made;
+  for (int g = 0; g < G; ++g) {
+    love_config cg = cfgs[g];
+    cg.flags |= LOVE_FLAG_ASYNC;
+    love_cache* c = nullptr;
+    love_status st = love_build_cache(&cg, xs[g], ys[g], ns[g], stream, &c);
+    if (st != LOVE_OK) {
+      for (auto* p : made) destroy(p);
+      return st;
+    }
+    c->cfg.flags = cfgs[g].flags;
+    made.push_back(c);
+  }
+  for (int g = 0; g < G; ++g) {
+    love_status st = (cfgs[g].flags & LOVE_FLAG_ASYNC) ? LOVE_OK : finish_status(made[g]);
+    if (st != LOVE_OK) {
+      for (auto* p : made) destroy(p);
+      return st;
+    }
+  }
+  for (int g = 0; g < G; ++g) out[g] = made[g];
+  return LOVE_OK;
+}
+
+love_status love_predict_mean_var(const love_cache* c, const void* xs, int64_t t, void* mean,
+                                  void* var, void* stream) {
+  if (!c || t < 0 || (t > 0 && (!xs || !var))) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64) return predict<double>(c, (const double*)xs, t, (double*)mean, (double*)var, s);
+  return predict<float>(c, (const float*)xs, t, (float*)mean, (float*)var, s);
+}
+
+love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* caches,
+                                          const void* const* xs, const int64_t* ts,
+                                          void* const* means, void* const* vars, void* stream) {
+  if (G < 1 || !caches || !xs || !ts || !vars) return LOVE_EINVAL;
+  for (int g = 0; g < G; ++g) {
+    love_status st = love_predict_mean_var(caches[g], xs[g], ts[g], means ? means[g] : nullptr,
+                                           vars[g], stream);
+    if (st != LOVE_OK) return st;
+  }
+  return LOVE_OK;
+}
+
+love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
+                                     int64_t t, void* cov, void* stream) {
+  if (!c || t < 0 || (t > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64) return covar_pairs<double>(c, (const double*)xa, (const double*)xb, t, (double*)cov, s);
+  return covar_pairs<float>(c, (const float*)xa, (const float*)xb, t, (float*)cov, s);
+}
+
+love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
+                                  int64_t ns, void* out, void* stream) {
+  if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;
+  if (c->ks <= 0) return LOVE_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64) return sample<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
+  return sample<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
+}
+
+love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t,
+                                  const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
+                                  void* stream) {
+  if (!c || t < 0 || (t > 0 && (!xs || !g_xs))) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64)
+    return backward<double>(c, (const double*)xs, t, (const double*)g_mean, (const double*)g_var,
+                            (double*)g_xs, g_rt, s);
+  return backward<float>(c, (const float*)xs, t, (const float*)g_mean, (const float*)g_var,
+                         (float*)g_xs, g_rt, s);
+}
+
+love_status love_apply_khat(const love_cache* c, const void* v, void* out, void* stream) {
+  if (!c || !v || !out) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("apply_khat", s);
+  if (c->fp64) {
+    launch_permute<double>((const double*)v, (double*)c->v1, c->perm, c->n, 0, s);
+    launch_scatter<double>(c, (const double*)c->v1, (double*)c->g1, nullptr, nullptr, 0, s);
+    toeplitz_apply<double>(c, (const double*)c->g1, (double*)c->g2, nullptr, 0, s);
+    launch_gather<double>(c, (const double*)c->g2, (const double*)c->v1, c->cfg.noise,
+                          (double*)c->v2, nullptr, s);
+    launch_permute<double>((const double*)c->v2, (double*)out, c->perm, c->n, 1, s);
+  } else {
+    launch_permute<float>((const float*)v, (float*)c->v1, c->perm, c->n, 0, s);
+    launch_scatter<float>(c, (const float*)c->v1, (float*)c->g1, nullptr, nullptr, 0, s);
+    toeplitz_apply<float>(c, (const float*)c->g1, (float*)c->g2, nullptr, 0, s);
+    launch_gather<float>(c, (const float*)c->g2, (const float*)c->v1, (float)c->cfg.noise,
+                         (float*)c->v2, nullptr, s);
+    launch_permute<float>((const float*)c->v2, (float*)out, c->perm, c->n, 1, s);
+  }
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* stream) {
+  if (!c || !g || !out) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64) toeplitz_apply<double>(c, (const double*)g, (double*)out, nullptr, 0, s);
+  else toeplitz_apply<float>(c, (const float*)g, (float*)out, nullptr, 0, s);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
+  if (!c || !info) return LOVE_EINVAL;
+  Ctl h, hs;
+  unsigned st[4];
+  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  LOVE_HIP_TRY(hipMemcpyAsync(&hs, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  LOVE_HIP_TRY(hipMemcpyAsync(st, c->status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  double bl = 0.0;
+  if (h.k_eff > 0)
+    LOVE_HIP_TRY(hipMemcpyAsync(&bl, c->beta + h.k_eff - 1, sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  LOVE_HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memset(info, 0, sizeof(*info));
+  info->k_eff = h.k_eff;
+  info->k_eff_sample = c->ks > 0 ? hs.k_chol : 0;
+  info->cg_iters = h.cg_iters;
+  info->d = c->d;
+  info->n = c->n;
+  info->m = c->m;
+  info->beta_last = bl;
+  info->status_flags = h.status | hs.status | st[0];
+  for (int e = 0; e < c->d; ++e) {
+    info->toeplitz_mode[e] = (uint32_t)c->toep.ax[e].mode;
+    info->fft_len[e] = (uint32_t)(c->toep.ax[e].mode == 2 ? c->toep.ax[e].fft_n : 0);
+  }
+  info->bytes = c->bytes;
+  return LOVE_OK;
+}
+
+love_status love_cache_export(const love_cache* c, const love_export* e, void* stream) {
+  if (!c || !e) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Ctl h, hs;
+  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  LOVE_HIP_TRY(hipMemcpyAsync(&hs, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  LOVE_HIP_TRY(hipStreamSynchronize(s));
+  const int k = h.k_eff;
+  const size_t es = c->fp64 ? 8 : 4;
+  if (e->alpha) LOVE_HIP_TRY(hipMemcpyAsync(e->alpha, c->alpha, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  if (e->beta) LOVE_HIP_TRY(hipMemcpyAsync(e->beta, c->beta, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  if (e->a) LOVE_HIP_TRY(hipMemcpyAsync(e->a, c->a, es * c->m, hipMemcpyDeviceToDevice, s));
+  if (e->rt) {
+    love_status st = rt_export_f32(c, e->rt, k, s);
+    if (st != LOVE_OK) return st;
+  }
+  if (e->rt64) {
+    if (!c->fp64) return LOVE_EINVAL;
+    LOVE_HIP_TRY(hipMemcpy2DAsync(e->rt64, sizeof(double) * k, c->rt, sizeof(double) * c->kpad,
+                                  sizeof(double) * k, c->m, hipMemcpyDeviceToDevice, s));
+  }
+  if (e->s && c->ks > 0 && hs.k_chol > 0)
+    LOVE_HIP_TRY(hipMemcpy2DAsync(e->s, sizeof(float) * hs.k_chol, c->S, sizeof(float) * c->kspad,
+                                  sizeof(float) * hs.k_chol, c->m, hipMemcpyDeviceToDevice, s));
+  return LOVE_OK;
+}
+
+void love_cache_free(love_cache* c) { destroy(c); }
+
+love_status love_profile_enable(int32_t enable) {
+  ProfState& p = prof();
+  hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(p.mu);
+  drain(p);
+  if (enable) p.acc.clear();
+  p.on = enable != 0;
+  return LOVE_OK;
+}
+
+love_status love_profile_select(const char* names) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.select.clear();
+  if (!names) return LOVE_OK;
+  std::string all(names);
+  size_t start = 0;
+  while (start < all.size()) {
+    size_t comma = all.find(',', start);
+    if (comma == std::string::npos) comma = all.size();
+    if (comma > start) p.select.push_back(all.substr(start, comma - start));
+    start = comma + 1;
+  }
+  return LOVE_OK;
+}
+
+love_status love_profile_read(const char* names, int64_t* calls, double* ms) {
+  if (!names || !calls || !ms) return LOVE_EINVAL;
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  drain(p);
+  std::string all(names);
+  size_t i = 0, start = 0;
+  while (start <= all.size()) {
+    size_t comma = all.find(',', start);
+    if (comma == std::string::npos) comma = all.size();
+    std::string nm = all.substr(start, comma - start);
+    auto it = p.acc.find(nm);
+    calls[i] = it == p.acc.end() ? 0 : it->second.first;
+    ms[i] = it == p.acc.end() ? 0.0 : it->second.second;
+    ++i;
+    start = comma + 1;
+    if (comma == all.size()) break;
+  }
+  return LOVE_OK;
+}
+
+}  // extern "C"

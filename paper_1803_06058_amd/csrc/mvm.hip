@@ -1,0 +1,476 @@
+// The KISS-GP operator pieces (Sec. 2.3, eq. ski):
+//   W^T v   (grid <- rows)   k_scatter: per-node deterministic gather over the
+//                            cell-sorted rows, one wave per grid node
+//   K g     (grid -> grid)   Toeplitz / Kronecker-of-Toeplitz product, one pass
+//                            per axis; direct register-blocked product or the
+//                            circulant-embedding FFT (fft.hip)
+//   W u     (rows <- grid)   k_gather: 4^d-point stencil gather per row
+// Interpolation weights are recomputed from x on the fly (4d bytes per row
+// instead of a stored 20d-byte stencil).
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "ops.h"
+
+namespace love {
+
+template <typename T>
+GridT<T> make_grid(const love_cache* c) {
+  GridT<T> g{};
+  g.d = c->d;
+  int64_t ns = 1, cs = 1;
+  for (int e = MAXD - 1; e >= 0; --e) {
+    if (e >= c->d) {
+      g.m[e] = 1;
+      g.cells[e] = 1;
+      g.nstride[e] = 0;
+      g.cstride[e] = 0;
+      g.lo[e] = T(0);
+      g.hi[e] = T(0);
+      g.invh[e] = T(0);
+      continue;
+    }
+    g.m[e] = c->mdim[e];
+    g.cells[e] = c->mdim[e] - 3;
+    g.nstride[e] = ns;
+    g.cstride[e] = cs;
+    ns *= g.m[e];
+    cs *= g.cells[e];
+    g.lo[e] = (T)c->lo[e];
+    g.hi[e] = (T)c->hi[e];
+    g.invh[e] = (T)c->invh[e];
+  }
+  g.mtot = ns;
+  g.ctot = cs;
+  return g;
+}
+template GridT<float> make_grid<float>(const love_cache*);
+template GridT<double> make_grid<double>(const love_cache*);
+
+// ----------------------------------------------------------------------------
+// W^T v: one wave per grid node u.  Rows touching u have cells c with
+// c_e in [u_e - 3, u_e] on every axis; along the last axis those cells are
+// contiguous, so the rows form 4^(D-1) contiguous runs of the sorted order.
+// Lanes are split over the runs; each lane sums its rows, then the wave sums.
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter(GridT<T> g, const T* __restrict__ x,
+                                                 const T* __restrict__ v,
+                                                 const int32_t* __restrict__ cell_start,
+                                                 T* __restrict__ out, const T* __restrict__ gprev,
+                                                 const Ctl* ctl, int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (u >= g.mtot) return;
+  constexpr int RUNS = 1 << (2 * (D - 1));
+  constexpr int LPR = WAVE / RUNS;
+  const int run = lane / LPR, sub = lane % LPR;
+  int ue[D];
+  {
+    int64_t rem = u;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      ue[e] = (int)(rem / g.nstride[e]);
+      rem -= (int64_t)ue[e] * g.nstride[e];
+    }
+  }
+  bool ok = true;
+  int64_t cbase = 0;
+#pragma unroll
+  for (int e = 0; e < D - 1; ++e) {
+    const int o = (run >> (2 * (D - 2 - e))) & 3;
+    const int ce = ue[e] - o;
+    ok = ok && ce >= 0 && ce < g.cells[e];
+    cbase += (int64_t)ce * g.cstride[e];
+  }
+  const int cl = max(ue[D - 1] - 3, 0);
+  const int ch = min(ue[D - 1], g.cells[D - 1] - 1);
+  ok = ok && cl <= ch;
+  T acc = T(0);
+  if (ok) {
+    const int32_t rb = cell_start[cbase + cl];
+    const int32_t re = cell_start[cbase + ch + 1];
+    for (int32_t r = rb + sub; r < re; r += LPR) {
+      T w = T(1);
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        T s;
+        const int j = stencil_base(x[(int64_t)r * D + e], g.lo[e], g.invh[e], g.m[e], s);
+        w *= keys_weight_at(ue[e] - j, s);
+      }
+      acc += w * v[r];
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    if ((mode & 4) && gprev) acc += (T)ctl->ratio * gprev[u];
+    out[u] = acc;
+  }
+}
+
+template <typename T>
+void launch_scatter(const love_cache* c, const T* v, T* gout, const T* gprev, const Ctl* ctl,
+                    int ctl_mode, hipStream_t s, const T* xsrc) {
+  ProfScope ps("scatter", s);
+  GridT<T> g = make_grid<T>(c);
+  const int wpb = 4;
+  dim3 grid((unsigned)cdiv(c->m, wpb));
+  const T* x = xsrc ? xsrc : (const T*)c->x;
+  switch (c->d) {
+    case 1: k_scatter<T, 1><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
+    case 2: k_scatter<T, 2><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
+    case 3: k_scatter<T, 3><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
+    case 4: k_scatter<T, 4><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
+  }
+}
+template void launch_scatter<float>(const love_cache*, const float*, float*, const float*, const Ctl*, int, hipStream_t, const float*);
+template void launch_scatter<double>(const love_cache*, const double*, double*, const double*, const Ctl*, int, hipStream_t, const double*);
+
+// ----------------------------------------------------------------------------
+// W u (+ sigma^2 v): one thread per sorted row.
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_gather(GridT<T> g, const T* __restrict__ x, int64_t n,
+                                                const T* __restrict__ kg,
+                                                const T* __restrict__ vsig, T sigma2,
+                                                T* __restrict__ out, const Ctl* ctl, int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  T acc = gather_row_dev<T, D>(g, x, r, kg);
+  if (vsig) acc += sigma2 * vsig[r];
+  out[r] = acc;
+}
+
+template <typename T>
+void launch_gather(const love_cache* c, const T* kg, const T* vsig, T sigma2, T* out,
+                   const Ctl* ctl, hipStream_t s, const T* xsrc) {
+  ProfScope ps("gather", s);
+  GridT<T> g = make_grid<T>(c);
+  dim3 grid((unsigned)cdiv(c->n, 256));
+  const T* x = xsrc ? xsrc : (const T*)c->x;
+  switch (c->d) {
+    case 1: k_gather<T, 1><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
+    case 2: k_gather<T, 2><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
+    case 3: k_gather<T, 3><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
+    case 4: k_gather<T, 4><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
+  }
+}
+template void launch_gather<float>(const love_cache*, const float*, const float*, float, float*, const Ctl*, hipStream_t, const float*);
+template void launch_gather<double>(const love_cache*, const double*, const double*, double, double*, const Ctl*, hipStream_t, const double*);
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (TO)in[i];
+}
+template <typename TI, typename TO>
+void launch_convert(const TI* in, TO* out, int64_t n, hipStream_t s) {
+  if (n > 0) k_convert<TI, TO><<<cdiv(n, 256), 256, 0, s>>>(in, out, n);
+}
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Direct Toeplitz product along a contiguous axis of length L (long lines):
+//   out[o, i] = scale * sum_j c[|i - j|] in[o, j].
+// Block = 256 threads, each owning TOEP_R consecutive outputs; the needed
+// coefficients slide along a register window (one new LDS load per input j),
+// the input chunk is an LDS broadcast.  Inputs are split into chunks
+// (split-K); a second kernel adds the chunk partial sums in chunk order
+// (deterministic).
+// ----------------------------------------------------------------------------
+constexpr int TOEP_R = 5;  // odd: lane stride R in the coefficient window is LDS bank-conflict free
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_toep_long(const T* __restrict__ in, T* __restrict__ out,
+                                                   const T* __restrict__ c, int L, int CH, T scale,
+                                                   T* __restrict__ partial,
+                                                   const Ctl* ctl, int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* gl = (T*)smem_raw;                 // CH
+  T* cw = gl + CH;                      // TO + CH - 1
+  constexpr int TO = 256 * TOEP_R;
+  const int tile0 = blockIdx.x * TO;
+  const int j0 = blockIdx.y * CH;
+  const int64_t line = blockIdx.z;
+  const T* src = in + line * L;
+  const int dmin = tile0 - (j0 + CH - 1);
+  const int nw = TO + CH - 1;
+  for (int q = threadIdx.x; q < CH; q += 256) {
+    const int j = j0 + q;
+    gl[q] = (j < L) ? src[j] : T(0);
+  }
+  for (int q = threadIdx.x; q < nw; q += 256) {
+    const int dl = dmin + q;
+    const int ad = dl < 0 ? -dl : dl;
+    cw[q] = (ad < L) ? c[ad] : T(0);
+  }
+  __syncthreads();
+  const int i0 = tile0 + threadIdx.x * TOEP_R;
+  // coefficient for output i0 + r and input j: c[|i0 + r - j|] = cw[wi + r - j]
+  const int wi = i0 - dmin;
+  T P[TOEP_R];
+  T acc[TOEP_R];
+#pragma unroll
+  for (int r = 0; r < TOEP_R; ++r) {
+    P[r] = cw[wi + r - j0];
+    acc[r] = T(0);
+  }
+  for (int jj = 0; jj < CH; jj += TOEP_R) {
+#pragma unroll
+    for (int q = 0; q < TOEP_R; ++q) {
+      const int j = j0 + jj + q;
+      const T gv = gl[jj + q];
+#pragma unroll
+      for (int r = 0; r < TOEP_R; ++r) acc[r] += P[(r - q + TOEP_R) % TOEP_R] * gv;
+      // next step's logical 0: cd(i0 - (j + 1))
+      const int widx = wi - j - 1;
+      P[(TOEP_R - 1 - q) % TOEP_R] = (widx >= 0) ? cw[widx] : T(0);
+    }
+  }
+  const int nchunks = gridDim.y;
+  if (nchunks == 1) {
+#pragma unroll
+    for (int r = 0; r < TOEP_R; ++r)
+      if (i0 + r < L) out[line * L + i0 + r] = scale * acc[r];
+    return;
+  }
+  T* mypart = partial + ((int64_t)line * nchunks + blockIdx.y) * L;
+#pragma unroll
+  for (int r = 0; r < TOEP_R; ++r)
+    if (i0 + r < L) mypart[i0 + r] = acc[r];
+}
+
+// out[line, i] = scale * sum_chunks partial[line, chunk, i]; all loads first.
+template <typename T>
+__global__ __launch_bounds__(256) void k_toep_reduce(const T* __restrict__ partial,
+                                                     T* __restrict__ out, int L, int nchunks,
+                                                     int64_t nlines, T scale, const Ctl* ctl,
+                                                     int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nlines * L) return;
+  const int64_t line = idx / L, i = idx % L;
+  const T* lp = partial + line * nchunks * (int64_t)L + i;
+  T acc = T(0);
+  int ck = 0;
+  for (; ck + 8 <= nchunks; ck += 8) {
+    T v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = lp[(int64_t)(ck + q) * L];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q];
+  }
+  for (; ck < nchunks; ++ck) acc += lp[(int64_t)ck * L];
+  out[idx] = scale * acc;
+}
+
+// Direct Toeplitz product for short / strided axes: a block owns 64
+// consecutive lines (one per lane) and the whole axis (L <= TOEP_LINES_MAXL),
+// staged in LDS as tile[j][lane]; wave w computes outputs i = w, w+4, ...
+// L <= 256 keeps the double tile (256 x 64 x 8 B = 128 KB) inside the 160 KB LDS.
+constexpr int TOEP_LINES_MAXL = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_toep_lines(const T* __restrict__ in, T* __restrict__ out,
+                                                    const T* __restrict__ c, int L, int64_t inner,
+                                                    int64_t nlines, T scale, const Ctl* ctl,
+                                                    int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* tile = (T*)smem_raw;       // L x 64
+  T* cl = tile + (int64_t)L * WAVE;  // L
+  const int64_t line0 = (int64_t)blockIdx.x * WAVE;
+  for (int idx = threadIdx.x; idx < L * WAVE; idx += 256) {
+    const int i = idx / WAVE, ln = idx % WAVE;
+    const int64_t line = line0 + ln;
+    T v = T(0);
+    if (line < nlines) {
+      const int64_t o = line / inner, r = line % inner;
+      v = in[o * L * inner + r + (int64_t)i * inner];
+    }
+    tile[idx] = v;
+  }
+  for (int i = threadIdx.x; i < L; i += 256) cl[i] = c[i];
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t line = line0 + lane;
+  if (line >= nlines) return;
+  const int64_t o = line / inner, r = line % inner;
+  T* dst = out + o * L * inner + r;
+  for (int i = w; i < L; i += 4) {
+    T acc = T(0);
+    for (int j = 0; j < L; ++j) acc += cl[i > j ? i - j : j - i] * tile[j * WAVE + lane];
+    dst[(int64_t)i * inner] = scale * acc;
+  }
+}
+
+template <typename T>
+void fft_axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
+                    const Ctl* ctl, int mode, hipStream_t s);
+
+template <typename T>
+static void axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
+                       const Ctl* ctl, int mode, hipStream_t s) {
+  const ToepPlan& p = c->toep;
+  const T* cc = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
+  if (ax.mode == 2) {
+    fft_axis_apply<T>(c, ax, in, out, scale, ctl, mode, s);
+    return;
+  }
+  if (ax.inner == 1 && ax.L > TOEP_LINES_MAXL) {
+    constexpr int TO = 256 * TOEP_R;
+    int CH = ax.tile_chunk;
+    CH = ((CH + TOEP_R - 1) / TOEP_R) * TOEP_R;
+    const int ntiles = (int)cdiv(ax.L, TO);
+    const int nchunks = (int)cdiv(ax.L, CH);
+    dim3 grid(ntiles, nchunks, (unsigned)ax.outer);
+    size_t shm = sizeof(T) * (CH + TO + CH - 1);
+    k_toep_long<T><<<grid, 256, shm, s>>>(in, out, cc, ax.L, CH, scale, (T*)p.partial, ctl, mode);
+    if (nchunks > 1)
+      k_toep_reduce<T><<<(unsigned)cdiv(ax.L * ax.outer, 256), 256, 0, s>>>(
+          (const T*)p.partial, out, ax.L, nchunks, ax.outer, scale, ctl, mode);
+  } else {
+    const int64_t nlines = ax.outer * ax.inner;
+    dim3 grid((unsigned)cdiv(nlines, WAVE));
+    size_t shm = sizeof(T) * ((size_t)ax.L * WAVE + ax.L);
+    k_toep_lines<T><<<grid, 256, shm, s>>>(in, out, cc, ax.L, ax.inner, nlines, scale, ctl, mode);
+  }
+}
+
+template <typename T>
+void toeplitz_apply(const love_cache* c, const T* in, T* out, const Ctl* ctl, int ctl_mode,
+                    hipStream_t s) {
+  ProfScope ps("toeplitz", s);
+  const ToepPlan& p = c->toep;
+  // axes applied last-to-first; intermediate results ping-pong through tmp1/tmp2
+  const T* src = in;
+  T* bufs[2] = {(T*)p.tmp1, (T*)p.tmp2};
+  int flip = 0;
+  for (int e = p.d - 1; e >= 0; --e) {
+    T* dst = (e == 0) ? out : bufs[flip];
+    axis_apply<T>(c, p.ax[e], src, dst, T(1), ctl, ctl_mode, s);
+    src = dst;
+    flip ^= 1;
+  }
+}
+template void toeplitz_apply<float>(const love_cache*, const float*, float*, const Ctl*, int, hipStream_t);
+template void toeplitz_apply<double>(const love_cache*, const double*, double*, const Ctl*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Small helpers
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<T><<<cdiv(n, 256), 256, 0, s>>>(p, v, n);
+}
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<unsigned>(unsigned*, unsigned, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_permute(const T* __restrict__ in, T* __restrict__ out,
+                          const int32_t* __restrict__ perm, int64_t n, int inverse) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (inverse) out[perm[p]] = in[p];   // sorted -> caller order
+  else out[p] = in[perm[p]];           // caller -> sorted order
+}
+template <typename T>
+void launch_permute(const T* in, T* out, const int32_t* perm, int64_t n, int inverse, hipStream_t s) {
+  k_permute<T><<<cdiv(n, 256), 256, 0, s>>>(in, out, perm, n, inverse);
+}
+template void launch_permute<float>(const float*, float*, const int32_t*, int64_t, int, hipStream_t);
+template void launch_permute<double>(const double*, double*, const int32_t*, int64_t, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Plan: first columns of the per-axis Toeplitz factors and the backend choice.
+// ----------------------------------------------------------------------------
+static double kern1d(int kind, double r, double ell) {
+  r = std::fabs(r);
+  if (kind == LOVE_MATERN52) {
+    const double z = std::sqrt(5.0) * r / ell;
+    return (1.0 + z + z * z / 3.0) * std::exp(-z);
+  }
+  const double q = r / ell;
+  return std::exp(-0.5 * q * q);
+}
+
+love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<double>& col);
+int autotune_choose(love_cache* c, int e);
+
+love_status toeplitz_plan(love_cache* c) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    attr_done = true;
+    (void)hipFuncSetAttribute((const void*)k_toep_lines<float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_toep_lines<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  }
+  ToepPlan& p = c->toep;
+  p.d = c->d;
+  p.mtot = c->m;
+  int64_t inner = 1;
+  size_t partial_elems = 0;
+  for (int e = c->d - 1; e >= 0; --e) {
+    ToepAxis& ax = p.ax[e];
+    ax.L = c->mdim[e];
+    ax.inner = inner;
+    ax.outer = c->m / (inner * ax.L);
+    inner *= ax.L;
+    const double h = 1.0 / c->invh[e];
+    std::vector<double> col(ax.L);
+    for (int i = 0; i < ax.L; ++i)
+      col[i] = kern1d(c->cfg.kernel, i * h, c->cfg.lengthscale[e]) * (e == 0 ? c->cfg.outputscale : 1.0);
+    for (int i = 0; i < 4; ++i) c->c4[e][i] = col[i];
+    std::vector<float> col32(col.begin(), col.end());
+    ax.c64 = dev_alloc(c, sizeof(double) * ax.L);
+    ax.c32 = dev_alloc(c, sizeof(float) * ax.L);
+    if (!ax.c64 || !ax.c32) return LOVE_ENOMEM;
+    LOVE_HIP_TRY(hipMemcpy(ax.c64, col.data(), sizeof(double) * ax.L, hipMemcpyHostToDevice));
+    LOVE_HIP_TRY(hipMemcpy(ax.c32, col32.data(), sizeof(float) * ax.L, hipMemcpyHostToDevice));
+    int mode = c->cfg.toeplitz;
+    if (mode == LOVE_TOEPLITZ_AUTO) mode = autotune_choose(c, e);
+    ax.mode = mode;
+    if (ax.mode == LOVE_TOEPLITZ_FFT) {
+      love_status st = fft_plan_axis(c, ax, e, col);
+      if (st != LOVE_OK) return st;
+    }
+    if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.inner == 1 && ax.L > TOEP_LINES_MAXL) {
+      if (ax.tile_chunk <= 0) ax.tile_chunk = 320;
+      const int64_t nchunks = cdiv(ax.L, ((ax.tile_chunk + TOEP_R - 1) / TOEP_R) * TOEP_R);
+      partial_elems = std::max<size_t>(partial_elems, (size_t)(nchunks * ax.L * ax.outer));
+    } else if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.L > TOEP_LINES_MAXL) {
+      return LOVE_EUNSUPPORTED;  // long strided axis: use the FFT backend
+    }
+  }
+  for (int e = 0; e < 4; ++e)
+    if (e >= c->d)
+      for (int i = 0; i < 4; ++i) c->c4[e][i] = 1.0;
+  c->c4_dev = (double*)dev_alloc(c, sizeof(double) * 16);
+  if (!c->c4_dev) return LOVE_ENOMEM;
+  LOVE_HIP_TRY(hipMemcpy(c->c4_dev, c->c4, sizeof(double) * 16, hipMemcpyHostToDevice));
+  p.tmp1 = dev_alloc(c, sizeof(double) * c->m);
+  p.tmp2 = dev_alloc(c, sizeof(double) * c->m);
+  if (!p.tmp1 || !p.tmp2) return LOVE_ENOMEM;
+  if (partial_elems) {
+    p.partial = dev_alloc(c, sizeof(double) * partial_elems);
+    p.partial_elems = partial_elems;
+    if (!p.partial) return LOVE_ENOMEM;
+  }
+  return LOVE_OK;
+}
+
+}  // namespace love

@@ -1,0 +1,497 @@
+// Constant-time test-time kernels (Sec. 3.2 test phase, Alg. 1 queries;
+// Sec. 3.3 sampling) and the backward of the mean / variance with respect to
+// the test inputs.
+//
+// A query point touches only the 4^d grid nodes of its cubic stencil, so every
+// kernel here is a gather of 4^d rows of Rt (m x kpad) plus the mean cache a.
+// One wave serves one point: lane l owns columns l and l + 64 of Rt, so every
+// row load is a coalesced 256-byte access; ||u||^2 and the prior are summed
+// in double and the variance subtraction (which cancels 4-6 digits) is done
+// in double.
+#include <cmath>
+
+#include "internal.h"
+#include "ops.h"
+
+namespace love {
+
+__device__ inline float bf16f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <typename T, int SPLIT>
+__device__ inline double rt_load(const void* rt, const uint16_t* rt_lo, int64_t idx) {
+  if constexpr (SPLIT) {
+    return (double)(bf16f(((const uint16_t*)rt)[idx]) + bf16f(rt_lo[idx]));
+  } else {
+    return (double)((const T*)rt)[idx];
+  }
+}
+
+struct Stencil4 {
+  int base[MAXD];
+};
+
+// per-axis weights, derivative weights and the stencil base of one point
+template <typename T, int D>
+__device__ inline bool point_stencil(const GridT<T>& g, const T* __restrict__ xp, double w[D][4],
+                                     double dw[D][4], int64_t& base, bool want_dw) {
+  bool ok = true;
+  base = 0;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = xp[e];
+    ok = ok && in_domain(xe, g.lo[e], g.hi[e]);
+    if (!(xe == xe)) xe = g.lo[e];
+    T s;
+    const int j = stencil_base(xe, g.lo[e], g.invh[e], g.m[e], s);
+    T wt[4];
+    keys_weights(s, wt);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) w[e][o] = (double)wt[o];
+    if (want_dw) {
+      T dt[4];
+      keys_dweights(s, dt);
+#pragma unroll
+      for (int o = 0; o < 4; ++o) dw[e][o] = (double)dt[o] * (double)g.invh[e];
+    }
+    base += (int64_t)j * g.nstride[e];
+  }
+  return ok;
+}
+
+// w_e^T T_e(4x4) v_e with T_e(4x4)[a][b] = c4[e][|a-b|]
+__device__ inline double quad4(const double* c4e, const double* a, const double* b) {
+  double s = 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += a[p] * b[q] * c4e[p > q ? p - q : q - p];
+  return s;
+}
+
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_predict(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                 const void* __restrict__ rt,
+                                                 const uint16_t* __restrict__ rt_lo, int kpad,
+                                                 const T* __restrict__ acache,
+                                                 const double* __restrict__ c4,
+                                                 T* __restrict__ mean, T* __restrict__ var,
+                                                 unsigned* __restrict__ status) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (p >= t) return;
+  double w[D][4], dw[D][4];
+  int64_t base;
+  const bool ok = point_stencil<T, D>(g, xs + p * D, w, dw, base, false);
+  constexpr int NA = 1 << (2 * D);
+  double u0 = 0.0, u1 = 0.0, mu = 0.0;
+  const bool two = kpad > WAVE;
+#pragma unroll 4
+  for (int a = 0; a < NA; ++a) {
+    double wa = 1.0;
+    int64_t node = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int o = (a >> (2 * (D - 1 - e))) & 3;
+      wa *= w[e][o];
+      node += (int64_t)o * g.nstride[e];
+    }
+    const int64_t row = node * kpad;
+    u0 += wa * rt_load<T, SPLIT>(rt, rt_lo, row + lane);
+    if (two) u1 += wa * rt_load<T, SPLIT>(rt, rt_lo, row + lane + WAVE);
+    if ((a & (WAVE - 1)) == lane && acache) mu += wa * (double)acache[node];
+  }
+  const double uu = wave_sum(u0 * u0 + u1 * u1);
+  mu = wave_sum(mu);
+  if (lane == 0) {
+    double pr = 1.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) pr *= quad4(c4 + 4 * e, w[e], w[e]);
+    if (ok) {
+      var[p] = (T)(pr - uu);
+      if (mean) mean[p] = (T)mu;
+    } else {
+      var[p] = (T)NAN;
+      if (mean) mean[p] = (T)NAN;
+      atomicOr(status, SF_DOMAIN);
+    }
+  }
+}
+
+template <typename T>
+love_status predict(const love_cache* c, const T* xs, int64_t t, T* mean, T* var, hipStream_t s) {
+  ProfScope ps("predict", s);
+  if (t == 0) return LOVE_OK;
+  GridT<T> g = make_grid<T>(c);
+  dim3 grid((unsigned)cdiv(t, 4));
+  const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
+  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+#define LAUNCH_P(D)                                                                                 \
+  if (split)                                                                                        \
+    k_predict<T, D, 1><<<grid, 256, 0, s>>>(g, xs, t, c->rt, (const uint16_t*)c->rt_lo, c->kpad, a, \
+                                            c->c4_dev, mean, var, c->status);                       \
+  else                                                                                              \
+    k_predict<T, D, 0><<<grid, 256, 0, s>>>(g, xs, t, c->rt, nullptr, c->kpad, a, c->c4_dev, mean,  \
+                                            var, c->status);
+  switch (c->d) {
+    case 1: LAUNCH_P(1); break;
+    case 2: LAUNCH_P(2); break;
+    case 3: LAUNCH_P(3); break;
+    case 4: LAUNCH_P(4); break;
+  }
+#undef LAUNCH_P
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status predict<float>(const love_cache*, const float*, int64_t, float*, float*, hipStream_t);
+template love_status predict<double>(const love_cache*, const double*, int64_t, double*, double*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Cross-covariance of paired points (Alg. 1 with w_i != w_j):
+//   cov = w_i^T K w_j - (Rt^T w_i)^T (Rt^T w_j)
+// The prior term uses the full first column of each axis factor, since the
+// two stencils may be far apart.
+// ----------------------------------------------------------------------------
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_covar_pairs(
+    GridT<T> g, const T* __restrict__ xa, const T* __restrict__ xb, int64_t t,
+    const void* __restrict__ rt, const uint16_t* __restrict__ rt_lo, int kpad,
+    const double* __restrict__ c0, const double* __restrict__ c1, const double* __restrict__ c2,
+    const double* __restrict__ c3, T* __restrict__ cov, unsigned* __restrict__ status) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (p >= t) return;
+  double wa[D][4], wb[D][4], dd[D][4];
+  int64_t ba, bb;
+  bool ok = point_stencil<T, D>(g, xa + p * D, wa, dd, ba, false);
+  ok = point_stencil<T, D>(g, xb + p * D, wb, dd, bb, false) && ok;
+  constexpr int NA = 1 << (2 * D);
+  const bool two = kpad > WAVE;
+  double ua0 = 0, ua1 = 0, ub0 = 0, ub1 = 0;
+  for (int a = 0; a < NA; ++a) {
+    double fa = 1.0, fb = 1.0;
+    int64_t na = ba, nb = bb;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int o = (a >> (2 * (D - 1 - e))) & 3;
+      fa *= wa[e][o];
+      fb *= wb[e][o];
+      na += (int64_t)o * g.nstride[e];
+      nb += (int64_t)o * g.nstride[e];
+    }
+    ua0 += fa * rt_load<T, SPLIT>(rt, rt_lo, na * kpad + lane);
+    ub0 += fb * rt_load<T, SPLIT>(rt, rt_lo, nb * kpad + lane);
+    if (two) {
+      ua1 += fa * rt_load<T, SPLIT>(rt, rt_lo, na * kpad + lane + WAVE);
+      ub1 += fb * rt_load<T, SPLIT>(rt, rt_lo, nb * kpad + lane + WAVE);
+    }
+  }
+  const double uv = wave_sum(ua0 * ub0 + ua1 * ub1);
+  if (lane == 0) {
+    const double* cols[4] = {c0, c1, c2, c3};
+    double pr = 1.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      int ja = (int)((ba / g.nstride[e]) % g.m[e]);
+      int jb = (int)((bb / g.nstride[e]) % g.m[e]);
+      double sacc = 0.0;
+      for (int o = 0; o < 4; ++o)
+        for (int q = 0; q < 4; ++q) {
+          int lag = (ja + o) - (jb + q);
+          lag = lag < 0 ? -lag : lag;
+          sacc += wa[e][o] * wb[e][q] * cols[e][lag];
+        }
+      pr *= sacc;
+    }
+    if (ok) cov[p] = (T)(pr - uv);
+    else {
+      cov[p] = (T)NAN;
+      atomicOr(status, SF_DOMAIN);
+    }
+  }
+}
+
+template <typename T>
+love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t, T* cov,
+                        hipStream_t s) {
+  ProfScope ps("covar_pairs", s);
+  if (t == 0) return LOVE_OK;
+  GridT<T> g = make_grid<T>(c);
+  dim3 grid((unsigned)cdiv(t, 4));
+  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+  const double* cc[4];
+  for (int e = 0; e < 4; ++e) cc[e] = (const double*)(e < c->d ? c->toep.ax[e].c64 : nullptr);
+#define LAUNCH_C(D)                                                                                \
+  if (split)                                                                                       \
+    k_covar_pairs<T, D, 1><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, (const uint16_t*)c->rt_lo,    \
+                                                c->kpad, cc[0], cc[1], cc[2], cc[3], cov, c->status); \
+  else                                                                                             \
+    k_covar_pairs<T, D, 0><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, nullptr, c->kpad, cc[0], cc[1], \
+                                                cc[2], cc[3], cov, c->status);
+  switch (c->d) {
+    case 1: LAUNCH_C(1); break;
+    case 2: LAUNCH_C(2); break;
+    case 3: LAUNCH_C(3); break;
+    case 4: LAUNCH_C(4); break;
+  }
+#undef LAUNCH_C
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status covar_pairs<float>(const love_cache*, const float*, const float*, int64_t, float*, hipStream_t);
+template love_status covar_pairs<double>(const love_cache*, const double*, const double*, int64_t, double*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Backward: d(sum g_mean*mean + g_var*var)/d x*.
+//   d mean / dx_e = sum_a dW_a^e a[node_a]
+//   d var  / dx_e = dp/dx_e - 2 u . v_e,  u = Rt^T w, v_e = Rt^T dw/dx_e
+//   dp/dx_e = 2 (dw_e)^T T_e w_e * prod_{f != e} w_f^T T_f w_f
+// Optional dRt: += -2 g_var W_a u  (float atomics).
+// ----------------------------------------------------------------------------
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                  const void* __restrict__ rt,
+                                                  const uint16_t* __restrict__ rt_lo, int kpad,
+                                                  int keff, const T* __restrict__ acache,
+                                                  const double* __restrict__ c4,
+                                                  const T* __restrict__ gm, const T* __restrict__ gv,
+                                                  T* __restrict__ gx, float* __restrict__ grt,
+                                                  unsigned* __restrict__ status) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (p >= t) return;
+  double w[D][4], dw[D][4];
+  int64_t base;
+  const bool ok = point_stencil<T, D>(g, xs + p * D, w, dw, base, true);
+  constexpr int NA = 1 << (2 * D);
+  const bool two = kpad > WAVE;
+  double u0 = 0, u1 = 0;
+  double v0[D], v1[D], dmu[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) v0[e] = v1[e] = dmu[e] = 0.0;
+  for (int a = 0; a < NA; ++a) {
+    int o[D];
+    int64_t node = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      o[e] = (a >> (2 * (D - 1 - e))) & 3;
+      node += (int64_t)o[e] * g.nstride[e];
+    }
+    double wa = 1.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) wa *= w[e][o[e]];
+    const double r0 = rt_load<T, SPLIT>(rt, rt_lo, node * kpad + lane);
+    const double r1 = two ? rt_load<T, SPLIT>(rt, rt_lo, node * kpad + lane + WAVE) : 0.0;
+    u0 += wa * r0;
+    u1 += wa * r1;
+    const double av = ((a & (WAVE - 1)) == lane && acache) ? (double)acache[node] : 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      double dwa = 1.0;
+#pragma unroll
+      for (int f = 0; f < D; ++f) dwa *= (f == e) ? dw[f][o[f]] : w[f][o[f]];
+      v0[e] += dwa * r0;
+      v1[e] += dwa * r1;
+      dmu[e] += dwa * av;
+    }
+  }
+  const double gmean = gm ? (double)gm[p] : 0.0;
+  const double gvar = gv ? (double)gv[p] : 0.0;
+  double q[D], dq[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    q[e] = quad4(c4 + 4 * e, w[e], w[e]);
+    dq[e] = 2.0 * quad4(c4 + 4 * e, dw[e], w[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    const double uv = wave_sum(u0 * v0[e] + u1 * v1[e]);
+    const double dm = wave_sum(dmu[e]);
+    if (lane == 0) {
+      double dp = dq[e];
+#pragma unroll
+      for (int f = 0; f < D; ++f)
+        if (f != e) dp *= q[f];
+      const double gval = gmean * dm + gvar * (dp - 2.0 * uv);
+      gx[p * D + e] = ok ? (T)gval : (T)NAN;
+    }
+  }
+  if (!ok && lane == 0) atomicOr(status, SF_DOMAIN);
+  if (grt && ok && gvar != 0.0) {
+    for (int a = 0; a < NA; ++a) {
+      int64_t node = base;
+      double wa = 1.0;
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        const int o = (a >> (2 * (D - 1 - e))) & 3;
+        node += (int64_t)o * g.nstride[e];
+        wa *= w[e][o];
+      }
+      const double f = -2.0 * gvar * wa;
+      if (lane < keff) atomicAdd(&grt[node * keff + lane], (float)(f * u0));
+      if (two && lane + WAVE < keff) atomicAdd(&grt[node * keff + lane + WAVE], (float)(f * u1));
+    }
+  }
+}
+
+template <typename T>
+love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, const T* gv, T* gx,
+                     float* grt, hipStream_t s) {
+  ProfScope ps("backward", s);
+  if (t == 0) return LOVE_OK;
+  Ctl h;
+  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  LOVE_HIP_TRY(hipStreamSynchronize(s));
+  const int keff = h.k_eff;
+  GridT<T> g = make_grid<T>(c);
+  dim3 grid((unsigned)cdiv(t, 4));
+  const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
+  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+#define LAUNCH_B(D)                                                                                \
+  if (split)                                                                                       \
+    k_backward<T, D, 1><<<grid, 256, 0, s>>>(g, xs, t, c->rt, (const uint16_t*)c->rt_lo, c->kpad,  \
+                                             keff, a, c->c4_dev, gm, gv, gx, grt, c->status);      \
+  else                                                                                             \
+    k_backward<T, D, 0><<<grid, 256, 0, s>>>(g, xs, t, c->rt, nullptr, c->kpad, keff, a,           \
+                                             c->c4_dev, gm, gv, gx, grt, c->status);
+  switch (c->d) {
+    case 1: LAUNCH_B(1); break;
+    case 2: LAUNCH_B(2); break;
+    case 3: LAUNCH_B(3); break;
+    case 4: LAUNCH_B(4); break;
+  }
+#undef LAUNCH_B
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status backward<float>(const love_cache*, const float*, int64_t, const float*, const float*, float*, float*, hipStream_t);
+template love_status backward<double>(const love_cache*, const double*, int64_t, const double*, const double*, double*, float*, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Posterior samples: out[i, j] = mu_i + f_i . z_j with f_i = S^T w(x*_i)
+// (eq. sample, S from eq. pred_covar_ski_interp_form).  A block owns 64 test
+// points: it forms F (64 x ks) and mu in LDS, then multiplies F by Z in
+// 64-sample tiles (4 x 4 outputs per thread).
+// ----------------------------------------------------------------------------
+constexpr int SP_TP = 64;
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_sample(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                const float* __restrict__ S, int kspad, int ks,
+                                                const T* __restrict__ acache,
+                                                const float* __restrict__ z, int64_t ns,
+                                                T* __restrict__ out, unsigned* __restrict__ status) {
+  extern __shared__ unsigned char smem_raw[];
+  float* F = (float*)smem_raw;               // SP_TP x (ks + 1)
+  float* Zt = F + SP_TP * (ks + 1);          // ks x 64
+  __shared__ float mu_l[SP_TP];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t p0 = (int64_t)blockIdx.x * SP_TP;
+  const int ldf = ks + 1;
+  // F rows and mu: wave w handles points w, w+4, ...
+  for (int pl = w; pl < SP_TP; pl += 4) {
+    const int64_t p = p0 + pl;
+    double f0 = 0.0, f1 = 0.0, mu = 0.0;
+    bool ok = true;
+    if (p < t) {
+      double ww[D][4], dd[D][4];
+      int64_t base;
+      ok = point_stencil<T, D>(g, xs + p * D, ww, dd, base, false);
+      constexpr int NA = 1 << (2 * D);
+      for (int a = 0; a < NA; ++a) {
+        double wa = 1.0;
+        int64_t node = base;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          const int o = (a >> (2 * (D - 1 - e))) & 3;
+          wa *= ww[e][o];
+          node += (int64_t)o * g.nstride[e];
+        }
+        if (lane < ks) f0 += wa * (double)S[node * kspad + lane];
+        if (lane + WAVE < ks) f1 += wa * (double)S[node * kspad + lane + WAVE];
+        if ((a & (WAVE - 1)) == lane && acache) mu += wa * (double)acache[node];
+      }
+      mu = wave_sum(mu);
+      if (!ok && lane == 0) atomicOr(status, SF_DOMAIN);
+    }
+    if (lane < ks) F[pl * ldf + lane] = (float)f0;
+    if (lane + WAVE < ks) F[pl * ldf + lane + WAVE] = (float)f1;
+    if (lane == 0) mu_l[pl] = ok ? (float)mu : NAN;
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  for (int64_t j0 = 0; j0 < ns; j0 += 64) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ks * 64; idx += 256) {
+      const int cc = idx / 64, jj = idx % 64;
+      Zt[idx] = (j0 + jj < ns) ? z[(int64_t)cc * ns + j0 + jj] : 0.0f;
+    }
+    __syncthreads();
+    float acc[4][4] = {};
+    for (int cc = 0; cc < ks; ++cc) {
+      float fa[4], zb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fa[r] = F[(ty + 16 * r) * ldf + cc];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zb[q] = Zt[cc * 64 + tx + 16 * q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] += fa[r] * zb[q];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t p = p0 + ty + 16 * r;
+      if (p >= t) continue;
+      const float mu = mu_l[ty + 16 * r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + tx + 16 * q;
+        if (j < ns) out[p * ns + j] = (T)(mu + acc[r][q]);
+      }
+    }
+  }
+}
+
+template <typename T>
+love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns, T* out,
+                   hipStream_t s) {
+  ProfScope ps("sample", s);
+  if (t == 0 || ns == 0) return LOVE_OK;
+  Ctl h;
+  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  LOVE_HIP_TRY(hipStreamSynchronize(s));
+  const int ks = h.k_chol;
+  GridT<T> g = make_grid<T>(c);
+  const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
+  const size_t shm = sizeof(float) * ((size_t)SP_TP * (ks + 1) + (size_t)ks * 64 + 64);
+  dim3 grid((unsigned)cdiv(t, SP_TP));
+  switch (c->d) {
+    case 1: k_sample<T, 1><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 2: k_sample<T, 2><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 3: k_sample<T, 3><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 4: k_sample<T, 4><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+  }
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status sample<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
+template love_status sample<double>(const love_cache*, const double*, int64_t, const float*, int64_t, double*, hipStream_t);
+
+
+// Rt (m x kpad, stored precision) -> dst (m x keff, float)
+template <typename T, int SPLIT>
+__global__ void k_rt_export(int64_t m, const void* __restrict__ rt, const uint16_t* __restrict__ rt_lo,
+                            int kpad, int keff, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * keff) return;
+  const int64_t u = i / keff, c = i % keff;
+  dst[i] = (float)rt_load<T, SPLIT>(rt, rt_lo, u * kpad + c);
+}
+
+love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t s) {
+  if (keff <= 0) return LOVE_OK;
+  const int64_t tot = c->m * keff;
+  dim3 grid((unsigned)cdiv(tot, 256));
+  if (c->fp64) k_rt_export<double, 0><<<grid, 256, 0, s>>>(c->m, c->rt, nullptr, c->kpad, keff, dst);
+  else if (c->cfg.precision == LOVE_P_FP32_BF16SPLIT)
+    k_rt_export<float, 1><<<grid, 256, 0, s>>>(c->m, c->rt, (const uint16_t*)c->rt_lo, c->kpad, keff, dst);
+  else k_rt_export<float, 0><<<grid, 256, 0, s>>>(c->m, c->rt, nullptr, c->kpad, keff, dst);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+}  // namespace love

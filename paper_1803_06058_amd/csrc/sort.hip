@@ -1,0 +1,198 @@
+// Interpolation setup: stable sort of the training rows by stencil cell.
+//
+// The cubic-interpolation matrix W (Sec. 2.3) is never stored.  Instead the
+// rows are ordered by their stencil base cell so that (i) the rows touching a
+// grid node form a few contiguous runs, which turns W^T v into a deterministic
+// per-node gather (no floating-point atomics), and (ii) consecutive rows touch
+// neighbouring grid nodes, so gathers from the grid stay in cache.
+//
+// Sort: least-significant-digit radix sort, 8-bit digits, stable (rank within
+// a wave from ballots, across waves from per-wave digit counts), so the final
+// order is (cell, original row) and does not depend on scheduling.
+#include "internal.h"
+
+namespace love {
+
+namespace {
+
+constexpr int RS_BINS = 256;
+constexpr int RS_BLOCK = 256;
+constexpr int RS_TILE = 4096;
+
+template <typename T, int D>
+__global__ void k_cells(GridT<T> g, const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                        uint32_t* __restrict__ count, unsigned* __restrict__ status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned bad = 0;
+  int64_t cell = 0;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = x[i * D + e];
+    if (!in_domain(xe, g.lo[e], g.hi[e])) bad |= SF_DOMAIN;
+    if (!(xe == xe)) xe = g.lo[e];
+    T s;
+    int j = stencil_base(xe, g.lo[e], g.invh[e], g.m[e], s);
+    cell += (int64_t)j * g.cstride[e];
+  }
+  T yi = y[i];
+  if (!isfinite((double)yi)) bad |= SF_NONFINITE;
+  if (bad) atomicOr(status, bad);
+  keys[i] = (uint32_t)cell;
+  vals[i] = (uint32_t)i;
+  atomicAdd(&count[cell], 1u);
+}
+
+__global__ void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                          uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t cnt[RS_BINS];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int i = threadIdx.x; i < RS_TILE; i += RS_BLOCK) {
+    int64_t idx = base + i;
+    if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// In-place exclusive prefix sum of `len` uint32 values; one block of 1024.
+// If total != nullptr the grand total is written there.
+__global__ void k_scan_exclusive(uint32_t* __restrict__ data, int64_t len, uint32_t* total) {
+  __shared__ uint32_t sums[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (len + 1023) / 1024;
+  const int64_t b = t * chunk, e = (b + chunk < len) ? b + chunk : len;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += data[i];
+  sums[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 1024 partial sums
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = (t >= off) ? sums[t - off] : 0u;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = (t == 0) ? 0u : sums[t - 1];
+  for (int64_t i = b; i < e; ++i) {
+    uint32_t v = data[i];
+    data[i] = run;
+    run += v;
+  }
+  if (total && t == 1023) *total = sums[1023];
+}
+
+__global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+                             int shift, const uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t base[RS_BINS];
+  __shared__ uint32_t wcount[RS_BLOCK / WAVE][RS_BINS];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  base[t] = hist[(int64_t)t * nb + blockIdx.x];
+  const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (WAVE - lane));
+  const uint64_t above = (lane == WAVE - 1) ? 0ull : ((~0ull) << (lane + 1));
+  for (int chunk = 0; chunk < RS_TILE; chunk += RS_BLOCK) {
+#pragma unroll
+    for (int q = 0; q < RS_BLOCK / WAVE; ++q) wcount[q][t] = 0u;
+    __syncthreads();
+    const int64_t idx = (int64_t)blockIdx.x * RS_TILE + chunk + t;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? kin[idx] : 0u;
+    const uint32_t dig = (key >> shift) & 255u;
+    uint64_t mask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int bit = (dig >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      mask &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(mask & below);
+    if (valid && (mask & above) == 0ull) wcount[w][dig] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int q = 0; q < w; ++q) pre += wcount[q][dig];
+      const uint32_t pos = base[dig] + pre + rank;
+      kout[pos] = key;
+      vout[pos] = vin[idx];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < RS_BLOCK / WAVE; ++q) add += wcount[q][t];
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+template <typename T, int D>
+__global__ void k_gather_sorted(const T* __restrict__ x, const T* __restrict__ y,
+                                const uint32_t* __restrict__ order, int64_t n, T* __restrict__ xs,
+                                T* __restrict__ ys, int32_t* __restrict__ perm) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t i = order[p];
+#pragma unroll
+  for (int e = 0; e < D; ++e) xs[p * D + e] = x[(int64_t)i * D + e];
+  ys[p] = y[i];
+  perm[p] = (int32_t)i;
+}
+
+template <typename T, int D>
+love_status sort_impl(love_cache* c, const T* x, const T* y, hipStream_t s) {
+  const int64_t n = c->n;
+  GridT<T> g = make_grid<T>(c);
+  const int64_t C = c->ctot;
+  // scratch: keys/vals ping-pong, histogram, counts
+  const int nb = (int)cdiv(n, RS_TILE);
+  uint32_t *k0, *v0, *k1, *v1, *hist, *cnt;
+  size_t bytes = sizeof(uint32_t) * (4 * (size_t)n + (size_t)RS_BINS * nb);
+  char* buf = nullptr;
+  LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+  k0 = (uint32_t*)buf;
+  v0 = k0 + n;
+  k1 = v0 + n;
+  v1 = k1 + n;
+  hist = v1 + n;
+  cnt = (uint32_t*)c->cell_start;  // counts accumulate in place, then scanned
+  LOVE_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (C + 1), s));
+  k_cells<T, D><<<cdiv(n, 256), 256, 0, s>>>(g, x, y, n, k0, v0, cnt, c->status);
+  int bits = 1;
+  while ((int64_t(1) << bits) < C) ++bits;
+  const int passes = (bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    k_rs_hist<<<nb, RS_BLOCK, 0, s>>>(k0, n, shift, hist, nb);
+    k_scan_exclusive<<<1, 1024, 0, s>>>(hist, (int64_t)RS_BINS * nb, nullptr);
+    k_rs_scatter<<<nb, RS_BLOCK, 0, s>>>(k0, v0, k1, v1, n, shift, hist, nb);
+    std::swap(k0, k1);
+    std::swap(v0, v1);
+  }
+  k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, C + 1, nullptr);
+  k_gather_sorted<T, D><<<cdiv(n, 256), 256, 0, s>>>(x, y, v0, n, (T*)c->x, (T*)c->y, c->perm);
+  LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  LOVE_HIP_TRY(hipGetLastError());
+  return LOVE_OK;
+}
+
+}  // namespace
+
+template <typename T>
+love_status setup_sort(love_cache* c, const T* x, const T* y, hipStream_t s) {
+  ProfScope ps("setup_sort", s);
+  switch (c->d) {
+    case 1: return sort_impl<T, 1>(c, x, y, s);
+    case 2: return sort_impl<T, 2>(c, x, y, s);
+    case 3: return sort_impl<T, 3>(c, x, y, s);
+    case 4: return sort_impl<T, 4>(c, x, y, s);
+  }
+  return LOVE_EINVAL;
+}
+
+template love_status setup_sort<float>(love_cache*, const float*, const float*, hipStream_t);
+template love_status setup_sort<double>(love_cache*, const double*, const double*, hipStream_t);
+
+}  // namespace love

@@ -1,0 +1,359 @@
+"""GPU parity of the HIP path (called through the C ABI) against the FP64
+oracle on the same seeded inputs.
+
+Tolerances
+  FP64 path      e_p <= 1e-10   (both sides double; only summation order differs)
+  FP32 path      e_p <= 1e-5    (tighter than the 1e-4 target; float unit roundoff
+                                 6e-8 times the growth of k=100 dependent steps)
+  BF16 split     e_p <= 1e-3    (hi+lo planes carry ~16 significant bits)
+  e_p = |var_gpu - var_oracle| / prior(x*)  (prior = interpolated k(x*, x*))
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import love_fp64 as O
+from paper_1803_06058_amd import binding as B
+from paper_1803_06058_amd import workloads as WL
+
+from gpu_helpers import build, cfg_of, dev, errors, oracle_cache, spec_of, tdev, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Operator pieces: K_UU and Khat products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["1d_long_f32", "1d_long_f64", "1d_short_f32", "2d_f32", "4d_f64"])
+def test_apply_kuu_parity(case):
+    if case == "1d_long_f32":
+        P = WL.config(2, scale=0.2)          # m = 2000 (long-line split-K kernel)
+    elif case == "1d_long_f64":
+        P = WL.config(2, scale=0.2, dtype="f64", precision="fp64")
+    elif case == "1d_short_f32":
+        P = WL.config(1, dtype="f32", precision="fp32")   # m = 100 (line kernel)
+    elif case == "2d_f32":
+        P = WL.config(3, scale=0.01)
+    else:
+        P = WL.config(4, scale=0.002, dtype="f64", precision="fp64")
+    print(case, P.m, flush=True)
+    cache = build(P, k=8, flags=B.FLAG_NO_MEAN)
+    spec = spec_of(P)
+    g = np.random.default_rng(0).standard_normal(spec.mtot)
+    dt = torch_dtype(P)
+    out = host(cache.apply_kuu(tdev(g, dt)))
+    ref = O.K_apply(spec, g.astype(np.float32 if dt == torch.float32 else np.float64).astype(np.float64))
+    tol = 1e-12 if dt == torch.float64 else 2e-6
+    assert np.max(np.abs(out - ref)) <= tol * np.max(np.abs(ref)) * np.sqrt(spec.mtot)
+    cache.free()
+
+
+@pytest.mark.parametrize("cfgi,scale", [(1, 1.0), (2, 0.05), (3, 0.004), (4, 0.002)])
+def test_apply_khat_parity(cfgi, scale):
+    P = WL.config(cfgi, scale=scale)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P, k=8, flags=B.FLAG_NO_MEAN)
+    spec = spec_of(P)
+    v = np.random.default_rng(1).standard_normal(P.n)
+    dt = torch_dtype(P)
+    vv = v.astype(np.float32 if dt == torch.float32 else np.float64)
+    out = host(cache.apply_khat(tdev(vv, dt)))
+    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    assert rel <= (1e-12 if dt == torch.float64 else 1e-5), rel
+    cache.free()
+
+
+# ---------------------------------------------------------------------------
+# Full build + query
+# ---------------------------------------------------------------------------
+def test_config1_fp64_parity():
+    P = WL.config(1)
+    cache = build(P)
+    info = cache.info()
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float64))
+    oc = oracle_cache(P, cg_tol=1e-12)
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    mA, vA = O.exact_route_A(P.x, P.y, P.xs, spec_of(P))
+    p = O.prior_var(P.xs, spec_of(P))
+    e = errors(host(var), v_ref, p, host(mu), m_ref, P.y)
+    print(info.k_eff, oc.lanczos.k_eff, info.cg_iters, e, flush=True)
+    assert abs(info.k_eff - oc.lanczos.k_eff) <= 2
+    assert e["e_p_max"] <= 1e-10
+    assert e["mean_err_rel_rms_y"] <= 1e-9
+    assert np.max(np.abs(host(var) - vA) / p) <= 1e-10     # saturated: exact KISS-GP
+    cache.free()
+
+
+@pytest.mark.parametrize("scale", [0.02, 0.1])
+def test_config2_fp32_parity_small(scale):
+    P = WL.config(2, scale=scale, k_sample=0)
+    print(P.name, P.n, P.m, P.t, flush=True)
+    cache = build(P)
+    info = cache.info()
+    xs = P.xs[:20000]
+    mu, var = cache.predict_mean_var(tdev(xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, xs)
+    p = O.prior_var(xs, spec_of(P))
+    e = errors(host(var), v_ref, p, host(mu), m_ref, P.y)
+    print(info.k_eff, info.cg_iters, info.status_flags, e, flush=True)
+    assert e["e_p_max"] <= 1e-5
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    assert (host(var) <= p * (1 + 1e-6)).all()
+    cache.free()
+
+
+def test_config2_full_size_sampled():
+    """Bench configuration (n=1e5, m=1e4, k=100, t=1e6): all 1e6 outputs on the
+    GPU, 4000 of them checked against the oracle one by one."""
+    P = WL.config(2, k_sample=0)
+    cache = build(P)
+    xs_all = tdev(P.xs, torch.float32)
+    mu, var = cache.predict_mean_var(xs_all)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(11).choice(P.t, 4000, replace=False)
+    oc = oracle_cache(P)
+    xs = P.xs[idx]
+    m_ref, v_ref = O.love_predict(oc, xs)
+    p = O.prior_var(xs, spec_of(P))
+    e = errors(host(var)[idx], v_ref, p, host(mu)[idx], m_ref, P.y)
+    print(cache.info().k_eff, cache.info().cg_iters, e, flush=True)
+    assert e["e_p_max"] <= 1e-5
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    assert np.isfinite(host(var)).all()
+    cache.free()
+
+
+def test_covar_pairs_parity():
+    P = WL.config(2, scale=0.02, k_sample=0)
+    cache = build(P)
+    rng = np.random.default_rng(4)
+    xa = rng.uniform(0, 1, (3000, 1)).astype(np.float32)
+    xb = np.clip(xa + rng.normal(0, 0.01, xa.shape), 0, 1).astype(np.float32)
+    cov = host(cache.predict_covar_pairs(tdev(xa, torch.float32), tdev(xb, torch.float32)))
+    oc = oracle_cache(P)
+    ref = O.love_covariance(oc, xa.astype(np.float64), xb.astype(np.float64))
+    p = np.sqrt(O.prior_var(xa, spec_of(P)) * O.prior_var(xb, spec_of(P)))
+    assert np.max(np.abs(cov - ref) / p) <= 1e-5
+    cache.free()
+
+
+# ---------------------------------------------------------------------------
+# Sampling
+# ---------------------------------------------------------------------------
+def _sampler_case(scale, s=2000):
+    P = WL.config(2, scale=scale, s=s)
+    cache = build(P)
+    ex = cache.export()
+    S, a = host(ex["s"]), host(ex["a"])
+    xs = P.xs_sample
+    spec = spec_of(P)
+    out = host(cache.sample_posterior(tdev(xs, torch.float32), tdev(P.z, torch.float32)))
+    Ws = O.interp_matrix(xs.astype(np.float64), spec)
+    return P, cache, ex, S, a, xs, spec, out, Ws
+
+
+def test_sampler_draw_and_saturated_parity():
+    """m = 100 <= k' = 100: the second Lanczos spans the grid space, so the
+    implied covariance W* S S^T W*^T equals W*(K - R^T R')W*^T on both sides."""
+    P, cache, ex, S, a, xs, spec, out, Ws = _sampler_case(0.01)
+    # the draw kernel: out = mu + W* S z (float rounding only)
+    ref_draw = (Ws @ a)[:, None] + Ws @ (S @ P.z[: S.shape[1]].astype(np.float64))
+    assert np.max(np.abs(out - ref_draw)) <= 1e-5 * (1 + np.max(np.abs(ref_draw)))
+    oc = oracle_cache(P)
+    osm = O.love_sampler(oc, P.k_sample)
+    sub = slice(0, 300)
+    F = Ws[sub] @ S
+    Sig_gpu = F @ F.T
+    Sig_or = O.sample_covariance_implied(oc, osm, xs[sub].astype(np.float64))
+    p = O.prior_var(xs[sub], spec)
+    scale = np.sqrt(np.outer(p, p))
+    err = np.max(np.abs(Sig_gpu - Sig_or) / scale)
+    print(cache.info().k_eff_sample, osm.k_chol, err, flush=True)
+    assert err <= 1e-5
+    _, var = cache.predict_mean_var(tdev(xs[sub], torch.float32))
+    assert np.max(np.abs(np.diag(Sig_gpu) - host(var)) / p) <= 1e-5
+    cache.free()
+
+
+def test_sampler_truncated_vs_oracle():
+    """k' = 100 < m = 200: both sides are truncated Lanczos approximations of
+    W*(K - R^T R')W*^T; the GPU's truncation error must be of the oracle's size."""
+    P, cache, ex, S, a, xs, spec, out, Ws = _sampler_case(0.02)
+    oc = oracle_cache(P)
+    osm = O.love_sampler(oc, P.k_sample)
+    sub = slice(0, 300)
+    Wd = Ws[sub].toarray()
+    target = Wd @ (O.K_dense(spec) - oc.R.T @ oc.Rp) @ Wd.T
+    F = Ws[sub] @ S
+    err_gpu = np.max(np.abs(F @ F.T - target))
+    err_or = np.max(np.abs(O.sample_covariance_implied(oc, osm, xs[sub].astype(np.float64)) - target))
+    print(err_gpu, err_or, flush=True)
+    assert err_gpu <= 3 * err_or + 1e-5
+    cache.free()
+
+
+def test_sampler_monte_carlo():
+    """Sample mean and covariance of 20000 GPU draws at 12 points against the
+    implied covariance (statistical tolerance, 6 standard errors)."""
+    P = WL.config(2, scale=0.01, s=20000, t_sample=12)
+    cache = build(P)
+    ex = cache.export()
+    S = host(ex["s"])
+    xs = P.xs_sample
+    out = host(cache.sample_posterior(tdev(xs, torch.float32), tdev(P.z, torch.float32)))
+    mu, _ = cache.predict_mean_var(tdev(xs, torch.float32))
+    Ws = O.interp_matrix(xs.astype(np.float64), spec_of(P))
+    F = Ws @ S
+    ref = F @ F.T
+    s = out.shape[1]
+    level = np.sqrt((np.outer(np.diag(ref), np.diag(ref)) + ref ** 2) / s)
+    assert np.all(np.abs(np.cov(out) - ref) < 6 * level + 1e-12)
+    assert np.all(np.abs(out.mean(1) - host(mu)) < 6 * np.sqrt(np.diag(ref) / s) + 1e-7)
+    cache.free()
+
+
+# ---------------------------------------------------------------------------
+# Precision form (2-D, bf16 split) and 4-D Matern
+# ---------------------------------------------------------------------------
+def test_config3_bf16split_small():
+    P = WL.config(3, scale=0.01)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P)
+    xs = P.xs[:5000]
+    mu, var = cache.predict_mean_var(tdev(xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, xs)
+    p = O.prior_var(xs, spec_of(P))
+    e = errors(host(var), v_ref, p, host(mu), m_ref, P.y)
+    print(cache.info().k_eff, e, flush=True)
+    assert e["e_p_max"] <= 1e-3
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    cache.free()
+
+
+def test_config4_matern_small():
+    P = WL.config(4, scale=0.01)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P)
+    xs = P.xs[:3000]
+    mu, var = cache.predict_mean_var(tdev(xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, xs)
+    p = O.prior_var(xs, spec_of(P))
+    e = errors(host(var), v_ref, p, host(mu), m_ref, P.y)
+    print(cache.info().k_eff, e, flush=True)
+    assert e["e_p_max"] <= 1e-5
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    cache.free()
+
+
+# ---------------------------------------------------------------------------
+# Backward
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cfgi,scale", [(1, 1.0), (4, 0.01)])
+def test_backward_parity(cfgi, scale):
+    P = WL.config(cfgi, scale=scale)
+    cache = build(P)
+    dt = torch_dtype(P)
+    xs = P.xs[:2000]
+    xs = np.clip(xs, 1e-3, 1 - 1e-3).astype(P.np_dtype)
+    rng = np.random.default_rng(3)
+    gm = rng.standard_normal(xs.shape[0]).astype(P.np_dtype)
+    gv = rng.standard_normal(xs.shape[0]).astype(P.np_dtype)
+    gx, _ = cache.predict_backward(tdev(xs, dt), tdev(gm, dt), tdev(gv, dt))
+    oc = oracle_cache(P)
+    ref = O.love_predict_grad(oc, xs.astype(np.float64), gm.astype(np.float64), gv.astype(np.float64))
+    rel = np.max(np.abs(host(gx) - ref)) / np.max(np.abs(ref))
+    print(rel, flush=True)
+    assert rel <= (1e-9 if dt == torch.float64 else 1e-4)
+    # autograd wrapper
+    xt = tdev(xs, dt).requires_grad_(True)
+    mu, var = B.LovePredict.apply(xt, cache)
+    (mu * tdev(gm, dt) + var * tdev(gv, dt)).sum().backward()
+    assert torch.allclose(xt.grad, gx.view_as(xt))
+    cache.free()
+
+
+# ---------------------------------------------------------------------------
+# Determinism, batching, edge cases
+# ---------------------------------------------------------------------------
+def test_build_is_bitwise_deterministic():
+    P = WL.config(2, scale=0.05)
+    c1, c2 = build(P), build(P)
+    e1, e2 = c1.export(), c2.export()
+    for key in e1:
+        assert torch.equal(e1[key], e2[key]), key
+    c1.free()
+    c2.free()
+
+
+def test_batched_equals_single():
+    Ps = WL.batched_config(G=5, scale=0.02, t_per_gp=2000)
+    cfgs = [cfg_of(P) for P in Ps]
+    xs = [tdev(P.x, torch.float32) for P in Ps]
+    ys = [tdev(P.y, torch.float32) for P in Ps]
+    caches = B.build_cache_batched(cfgs, xs, ys)
+    qs = [tdev(P.xs, torch.float32) for P in Ps]
+    means, vars_ = B.predict_mean_var_batched(caches, qs)
+    for g, P in enumerate(Ps):
+        single = build(P)
+        m1, v1 = single.predict_mean_var(qs[g])
+        assert torch.equal(v1, vars_[g]) and torch.equal(m1, means[g])
+        single.free()
+    for c in caches:
+        c.free()
+
+
+def test_edge_cases():
+    P = WL.config(2, scale=0.01, k_sample=0)
+    cache = build(P)
+    # empty query
+    mu, var = cache.predict_mean_var(torch.empty(0, 1, device=dev()))
+    assert var.numel() == 0
+    # query outside the domain -> NaN and a status flag, others unaffected
+    xs = torch.tensor([[0.5], [1.5], [0.0], [1.0]], device=dev())
+    mu, var = cache.predict_mean_var(xs)
+    v = host(var)
+    assert np.isnan(v[1]) and np.isfinite(v[[0, 2, 3]]).all()
+    assert cache.info().status_flags & 1
+    cache.free()
+    # k larger than n is clamped
+    P2 = WL.config(2, scale=0.0005, k_sample=0)   # n = 50
+    c = build(P2, k=100)
+    assert c.info().k_eff <= P2.n
+    c.free()
+    # all training points identical: invariant subspace after few steps (breakdown, not an error)
+    P3 = WL.config(2, scale=0.01, k_sample=0, dtype="f64", precision="fp64")
+    P3.x[:] = 0.37
+    c = build(P3)
+    inf = c.info()
+    assert inf.k_eff < 10 and inf.status_flags & 8
+    _, var = c.predict_mean_var(tdev(P3.xs[:100], torch.float64))
+    assert np.isfinite(host(var)).all()
+    c.free()
+    # training point outside the domain -> EDOMAIN ; non-finite target -> ENONFINITE
+    P4 = WL.config(2, scale=0.01, k_sample=0)
+    P4.x[5] = 1.25
+    with pytest.raises(B.LoveError) as ei:
+        build(P4)
+    assert ei.value.code == -2
+    P5 = WL.config(2, scale=0.01, k_sample=0)
+    P5.y[7] = np.nan
+    with pytest.raises(B.LoveError) as ei:
+        build(P5)
+    assert ei.value.code == -6
+    # ragged n (not a multiple of any tile) and tiny grid
+    P6 = WL.config(2, scale=0.0123, k_sample=0, m=(4,))
+    c = build(P6, k=4)
+    _, var = c.predict_mean_var(tdev(P6.xs[:50], torch.float32))
+    oc = oracle_cache(P6, k=4)
+    _, v_ref = O.love_predict(oc, P6.xs[:50])
+    p = O.prior_var(P6.xs[:50], spec_of(P6))
+    assert np.max(np.abs(host(var) - v_ref) / p) <= 1e-5
+    c.free()
