@@ -173,6 +173,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->v2 = dev_alloc(c, es * (size_t)n);
   c->g1 = dev_alloc(c, es * (size_t)m);
   c->g2 = dev_alloc(c, es * (size_t)m);
+  c->tscr = nullptr;  // allocated after the Toeplitz plan
   if (!c->x || !c->y || !c->perm || !c->cell_start || !c->ctl || !c->ctl_s || !c->status ||
       !c->alpha || !c->beta || !c->rt || (split && !c->rt_lo) || !c->a || (c->ks > 0 && !c->S) ||
       !c->v1 || !c->v2 || !c->g1 || !c->g2)
@@ -205,19 +206,30 @@ static love_status finish_status(love_cache* c) {
   return LOVE_OK;
 }
 
+// One non-blocking side stream per device for the sampler chain (default priority).
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  streams[dev] = st;
+  return st;
+}
+
 template <typename T>
 static love_status build_one(love_cache* c, const void* x, const void* y, hipStream_t s) {
   love_status st = setup_sort<T>(c, (const T*)x, (const T*)y, s);
   if (st != LOVE_OK) return st;
   st = toeplitz_plan(c);
   if (st != LOVE_OK) return st;
-  st = build_lanczos_and_mean<T>(c, s);
-  if (st != LOVE_OK) return st;
-  if (c->ks > 0) {
-    st = build_sampler(c, s);
-    if (st != LOVE_OK) return st;
-  }
-  return LOVE_OK;
+  c->tscr = dev_alloc(c, sizeof(double) * (size_t)toeplitz_scratch_elems(c));
+  if (!c->tscr) return LOVE_ENOMEM;
+  return build_lanczos_and_mean<T>(c, s, c->ks > 0 ? side_stream() : nullptr);
 }
 
 extern "C" {
@@ -346,14 +358,14 @@ love_status love_apply_khat(const love_cache* c, const void* v, void* out, void*
   if (c->fp64) {
     launch_permute<double>((const double*)v, (double*)c->v1, c->perm, c->n, 0, s);
     launch_scatter<double>(c, (const double*)c->v1, (double*)c->g1, nullptr, nullptr, 0, s);
-    toeplitz_apply<double>(c, (const double*)c->g1, (double*)c->g2, nullptr, 0, s);
+    toeplitz_apply<double>(c, (const double*)c->g1, (double*)c->g2, (double*)c->tscr, nullptr, 0, s);
     launch_gather<double>(c, (const double*)c->g2, (const double*)c->v1, c->cfg.noise,
                           (double*)c->v2, nullptr, s);
     launch_permute<double>((const double*)c->v2, (double*)out, c->perm, c->n, 1, s);
   } else {
     launch_permute<float>((const float*)v, (float*)c->v1, c->perm, c->n, 0, s);
     launch_scatter<float>(c, (const float*)c->v1, (float*)c->g1, nullptr, nullptr, 0, s);
-    toeplitz_apply<float>(c, (const float*)c->g1, (float*)c->g2, nullptr, 0, s);
+    toeplitz_apply<float>(c, (const float*)c->g1, (float*)c->g2, (float*)c->tscr, nullptr, 0, s);
     launch_gather<float>(c, (const float*)c->g2, (const float*)c->v1, (float)c->cfg.noise,
                          (float*)c->v2, nullptr, s);
     launch_permute<float>((const float*)c->v2, (float*)out, c->perm, c->n, 1, s);
@@ -364,8 +376,8 @@ love_status love_apply_khat(const love_cache* c, const void* v, void* out, void*
 love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* stream) {
   if (!c || !g || !out) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (c->fp64) toeplitz_apply<double>(c, (const double*)g, (double*)out, nullptr, 0, s);
-  else toeplitz_apply<float>(c, (const float*)g, (float*)out, nullptr, 0, s);
+  if (c->fp64) toeplitz_apply<double>(c, (const double*)g, (double*)out, (double*)c->tscr, nullptr, 0, s);
+  else toeplitz_apply<float>(c, (const float*)g, (float*)out, (float*)c->tscr, nullptr, 0, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 

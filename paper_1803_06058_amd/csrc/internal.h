@@ -40,7 +40,8 @@ struct ToepAxis {
   int64_t outer = 1;     // product of m over earlier axes
   int fft_n = 0;         // complex FFT length (power of two) when mode == 2
   int fft_single = 0;    // 1: real line packed into a half-length complex FFT
-  int tile_chunk = 256;  // direct, contiguous long lines: inputs per split-K chunk
+  int bw32 = 0;          // coefficient band that matters in float  (|d| <= bw32)
+  int bw64 = 0;          // ... and in double
   void* c32 = nullptr;   // float  first column (L), outputscale folded into axis 0
   void* c64 = nullptr;   // double first column (L)
   void* spec32 = nullptr;  // float  circulant eigenvalues (fft_n [+1] reals)
@@ -51,11 +52,6 @@ struct ToepPlan {
   int d = 1;
   int64_t mtot = 0;
   ToepAxis ax[MAXD];
-  // scratch owned by the plan
-  void* tmp1 = nullptr;      // m (double-sized so either precision fits)
-  void* tmp2 = nullptr;
-  void* partial = nullptr;   // split-K partial sums (double-sized)
-  size_t partial_elems = 0;
 };
 
 // ----------------------------------------------------------------------------
@@ -100,6 +96,7 @@ struct love_cache {
   void* v2 = nullptr;         // n
   void* g1 = nullptr;         // m
   void* g2 = nullptr;         // m
+  void* tscr = nullptr;       // 2 m (double-sized): Toeplitz scratch of apply_khat / apply_kuu
   size_t bytes = 0;
   std::vector<void*> allocs;
 };
@@ -129,18 +126,21 @@ void launch_gather(const love_cache* c, const T* kg, const T* vsig, T sigma2, T*
 template <typename TI, typename TO>
 void launch_convert(const TI* in, TO* out, int64_t n, hipStream_t s);
 
+// K_UU in -> out; `scratch` holds toeplitz_scratch_elems(c) elements of T
+// (intermediate axis passes and per-segment partial sums).  Concurrent calls
+// need distinct scratch.
+int64_t toeplitz_scratch_elems(const love_cache* c);
 template <typename T>
-void toeplitz_apply(const love_cache* c, const T* in, T* out, const Ctl* ctl, int ctl_mode,
-                    hipStream_t s);
+void toeplitz_apply(const love_cache* c, const T* in, T* out, T* scratch, const Ctl* ctl,
+                    int ctl_mode, hipStream_t s);
 
 love_status toeplitz_plan(love_cache* c);
 
 // --- Lanczos / CG (lanczos.hip) ---------------------------------------------
+// Lanczos, Rt, and (concurrently) the mean CG on `s` and the sampler on
+// `s_side` (nullptr: everything on `s`).
 template <typename T>
-love_status build_lanczos_and_mean(love_cache* c, hipStream_t s);
-
-// --- sampler (sampler.hip) ---------------------------------------------------
-love_status build_sampler(love_cache* c, hipStream_t s);
+love_status build_lanczos_and_mean(love_cache* c, hipStream_t s, hipStream_t s_side);
 
 // --- queries (query.hip) -----------------------------------------------------
 template <typename T>

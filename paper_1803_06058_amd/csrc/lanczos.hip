@@ -1,17 +1,21 @@
 // Lanczos with full reorthogonalisation on Khat = W K W^T + sigma^2 I, the
-// LOVE cache, and the mean cache (Sec. 2.2, Sec. 3.2, Alg. 1, Sec. 5).
+// LOVE cache, the mean cache and the sampling cache (Sec. 2.2, Sec. 3.2,
+// Alg. 1, Sec. 3.3, Sec. 5).
 //
 // One Lanczos step j (0-based), all on device, no host synchronisation:
 //   scatter   g = W^T q_j                                  (grid, m)
 //   toeplitz  R_j = K g          -- kept as row j of R = Q^T W^T K (Alg. 1)
-//   gdots     v = W R_j + sigma^2 q_j ;  c = Q_{0..j}^T v   (first Gram-Schmidt pass;
-//             c_j = alpha_j, c_{j-1} = beta_{j-1} up to rounding)
-//   udots     r' = v - Q c ;  c2 = Q^T r' ; ||r'||^2        (second pass; Q tile staged in LDS)
-//             alpha_j = c_j + c2_j ; beta_j = sqrt(||r'||^2 - ||c2||^2)
-//   finalize  q_{j+1} = (r' - Q c2) / beta_j
-// Every reduction is a two-level "last block" reduction in a fixed order, so
-// results are bitwise reproducible.  The Lanczos vectors stay in float (or
-// double for the FP64 precision); all coefficients are double.
+//   gdots     v = W R_j + sigma^2 q_j ;  per-block partials of Q_{0..j}^T v
+//   colsum    c = Q_{0..j}^T v   (first Gram-Schmidt pass; c_j = alpha_j)
+//   udots     r' = v - Q c ; per-block partials of Q^T r' and ||r'||^2 (Q tile in LDS)
+//   colsum    c2, ||r'||^2       (second pass)
+//   finalize  alpha_j = c_j + c2_j, beta_j = sqrt(||r'||^2 - ||c2||^2),
+//             stop test, q_{j+1} = (r' - Q c2) / beta_j
+// Grid-wide sums never use device-scope fences inside a kernel (on this GPU a
+// device-scope release writes back the whole L2 of the issuing XCD, once per
+// block); instead a producer kernel writes one partial row per block and a
+// second small kernel adds the rows in a fixed order, so results are
+// bitwise reproducible and the kernel boundary provides visibility.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -23,62 +27,105 @@ namespace love {
 
 constexpr int BLK = 256;
 constexpr int LDP = MAXK + 8;   // row stride of the partial-sum arrays
-constexpr int RGS = 16;         // blocks per first-level reduction group
 
 // ----------------------------------------------------------------------------
-// Two-level deterministic reduction of per-block partial vectors.
-// Each block has written partial[blockIdx.x * LDP + 0..nv).  Blocks form
-// groups of RGS; the last block of a group sums the group's rows, the last
-// group sums the group rows.  In both levels every lane loads its values
-// before any reduction (W lanes per value, fixed shuffle tree), so a level
-// costs one memory round trip, and the order of the sums never changes.
-// Returns true in exactly one block, whose `red` (shared, >= nv doubles)
-// then holds the sums.  Requires gridDim.x <= RGS * 32.
+// Column sums of the per-block partial rows: out[c] = sum_b partial[b][c].
+// One wave per value; every lane issues all its loads before adding.
 // ----------------------------------------------------------------------------
-template <int W>
-__device__ inline void sum_rows(const double* __restrict__ src, int P, int nv, double* dst,
-                                bool dst_shared) {
-  constexpr int VPW = WAVE / W;                       // values per wave per pass
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-  const int q = lane % W, sub = lane / W;
-  constexpr int MAXIT = (MAXK + 1 + VPW * 4 - 1) / (VPW * 4);
-  double vals[MAXIT];
+__device__ inline double colsum_wave(const double* __restrict__ partial, int nb, int c) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double acc = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += WAVE * 8) {
+    double v[8];
 #pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    const int c = (it * nw + w) * VPW + sub;
-    vals[it] = (q < P && c < nv) ? src[(size_t)q * LDP + c] : 0.0;
+    for (int q = 0; q < 8; ++q) {
+      const int b = b0 + lane + WAVE * q;
+      v[q] = (b < nb) ? partial[(size_t)b * LDP + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += v[q];
   }
-#pragma unroll
-  for (int it = 0; it < MAXIT; ++it) {
-    double v = vals[it];
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-    const int c = (it * nw + w) * VPW + sub;
-    if (q == 0 && c < nv) dst[c] = v;
-  }
-  (void)dst_shared;
+  return wave_sum(acc);
 }
 
-__device__ bool reduce_partials(double* __restrict__ partial, double* __restrict__ gpartial,
-                                unsigned* __restrict__ counters, int nv, double* red) {
-  const unsigned nb = gridDim.x, b = blockIdx.x;
-  const unsigned grp = b / RGS, ng = (nb + RGS - 1) / RGS;
-  const unsigned gsz = min((unsigned)RGS, nb - grp * RGS);
-  if (!last_block_arrive(&counters[grp], gsz)) return false;
-  sum_rows<RGS>(partial + (size_t)grp * RGS * LDP, (int)gsz, nv, gpartial + (size_t)grp * LDP, false);
-  if (!last_block_arrive(&counters[ng], ng)) return false;
-  sum_rows<32>(gpartial, (int)ng, nv, red, true);
+__global__ __launch_bounds__(BLK) void k_colsum(const double* __restrict__ partial, int nb,
+                                                int nv, double* __restrict__ out) {
+  const int c = blockIdx.x * (BLK / WAVE) + threadIdx.x / WAVE;
+  if (c >= nv) return;
+  const double s = colsum_wave(partial, nb, c);
+  if ((threadIdx.x & (WAVE - 1)) == 0) out[c] = s;
+}
+
+static void launch_colsum(const double* partial, int nb, int nv, double* out, hipStream_t s) {
+  k_colsum<<<(unsigned)cdiv(nv, BLK / WAVE), BLK, 0, s>>>(partial, nb, nv, out);
+}
+
+// Column sums in one block followed by a scalar epilogue on thread 0.
+enum : int { EP_NONE = 0, EP_BNORM = 1, EP_TRISOLVE = 2, EP_CG_INIT = 3, EP_CG_STEP = 4 };
+
+__global__ __launch_bounds__(BLK) void k_colsum_ep(const double* __restrict__ partial, int nb,
+                                                   int nv, int ep, double* __restrict__ out,
+                                                   const double* __restrict__ ldiag,
+                                                   const double* __restrict__ lsub, double tol2,
+                                                   int maxit, Ctl* ctl) {
+  __shared__ double sums[LDP];
+  const int w = threadIdx.x / WAVE;
+  for (int c = w; c < nv; c += BLK / WAVE) {
+    const double s = colsum_wave(partial, nb, c);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sums[c] = s;
+  }
   __syncthreads();
-  return true;
+  if (threadIdx.x != 0) return;
+  if (ep == EP_NONE) {
+    for (int c = 0; c < nv; ++c) out[c] = sums[c];
+  } else if (ep == EP_BNORM) {
+    ctl->bnorm = sqrt(sums[0]);
+  } else if (ep == EP_TRISOLVE) {
+    // T z = Q^T y with T = L L^T (bidiagonal L): forward then backward substitution
+    const int k = min(ctl->k_eff, nv - 1);
+    double zz[MAXK];
+    for (int i = 0; i < k; ++i) {
+      const double t = sums[i] - (i > 0 ? lsub[i - 1] * zz[i - 1] : 0.0);
+      zz[i] = t / ldiag[i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      const double t = zz[i] - (i + 1 < k ? lsub[i] * zz[i + 1] : 0.0);
+      zz[i] = t / ldiag[i];
+    }
+    for (int i = 0; i < k; ++i) out[i] = zz[i];
+    for (int i = k; i < nv - 1; ++i) out[i] = 0.0;
+    ctl->rr0 = sums[nv - 1];
+  } else if (ep == EP_CG_INIT) {
+    ctl->rr = sums[0];
+    ctl->ratio = 0.0;
+    ctl->cg_iters = 0;
+    ctl->cg_done = (sums[0] > tol2 * ctl->rr0) ? 0 : 1;
+  } else if (ep == EP_CG_STEP) {
+    if (ctl->cg_done) return;
+    const double rrn = sums[0];
+    ctl->ratio = rrn / ctl->rr;
+    ctl->rr = rrn;
+    ctl->cg_iters += 1;
+    if (!(rrn > tol2 * ctl->rr0)) ctl->cg_done = 1;
+    else if (ctl->cg_iters >= maxit) {
+      ctl->cg_done = 1;
+      ctl->status |= SF_CG_NOCONV;
+    }
+    if (!isfinite(rrn)) {
+      ctl->cg_done = 1;
+      ctl->status |= SF_NONFINITE;
+    }
+  }
 }
 
 // Dots of the block's rows [r0, r0 + nrows) with columns 0..ncols-1 of Q
-// (column-major, stride ldq).  vl holds the block's vector values (LDS).
-// Wave w handles columns w, w+4, ...; results go to prow[col].
+// (column-major, stride ldq); vl holds the block's vector (LDS).  Wave w takes
+// column groups w, w + nw, ... of CG columns whose loads are all in flight
+// together; results go to prow[col].
 template <typename T, typename V>
 __device__ inline void block_dots(const T* __restrict__ Q, int64_t ldq, int ncols, int64_t r0,
                                   int nrows, const V* vl, double* __restrict__ prow) {
-  constexpr int CG = 8;   // columns per wave pass; all their loads are in flight together
+  constexpr int CG = 8;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   for (int c0 = w * CG; c0 < ncols; c0 += nw * CG) {
     double acc[CG];
@@ -102,19 +149,17 @@ __device__ inline void block_dots(const T* __restrict__ Q, int64_t ldq, int ncol
 }
 
 // ----------------------------------------------------------------------------
-// First pass: v = W R_j + sigma^2 q_j (rows), c = Q_{0..j}^T v.
+// First pass: v = W R_j + sigma^2 q_j (rows), partial rows of Q_{0..j}^T v.
 // ----------------------------------------------------------------------------
 template <typename T, int D>
 __global__ __launch_bounds__(BLK) void k_lz_gdots(GridT<T> g, const T* __restrict__ x, int64_t n,
                                                   const T* __restrict__ kg, const T* __restrict__ Q,
                                                   int64_t ldq, int j, T sigma2, T* __restrict__ vout,
-                                                  int rpb, double* partial, double* gpartial,
-                                                  unsigned* counters, double* __restrict__ coef,
-                                                  Ctl* ctl) {
+                                                  int rpb, double* __restrict__ partial,
+                                                  const Ctl* ctl) {
   if (ctl->stop) return;
   extern __shared__ unsigned char smem_raw[];
   T* vl = (T*)smem_raw;  // rpb
-  __shared__ double red[LDP];
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   const T* qj = Q + (int64_t)j * ldq;
   for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
@@ -129,24 +174,18 @@ __global__ __launch_bounds__(BLK) void k_lz_gdots(GridT<T> g, const T* __restric
   __syncthreads();
   const int nrows = (int)min<int64_t>(rpb, n - r0);
   block_dots(Q, ldq, j + 1, r0, nrows, vl, partial + (size_t)blockIdx.x * LDP);
-  if (!reduce_partials(partial, gpartial, counters, j + 1, red)) return;
-  for (int c = threadIdx.x; c <= j; c += BLK) coef[c] = red[c];
 }
 
 // ----------------------------------------------------------------------------
-// Second pass: r' = v - Q c ; c2 = Q^T r' ; ||r'||^2 ; then alpha_j, beta_j.
+// Second pass: r' = v - Q c ; partial rows of Q^T r' and ||r'||^2.
 // The Q tile of STR rows x ncols is staged in LDS so Q is read once.
 // ----------------------------------------------------------------------------
 template <typename T, int STR>
 __global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict__ v,
                                                   const T* __restrict__ Q, int64_t ldq, int j,
                                                   const double* __restrict__ coef,
-                                                  T* __restrict__ rout, int rpb, double* partial,
-                                                  double* gpartial, unsigned* counters,
-                                                  double* __restrict__ c2out,
-                                                  double* __restrict__ alpha,
-                                                  double* __restrict__ beta, double tol, int klast,
-                                                  Ctl* ctl) {
+                                                  T* __restrict__ rout, int rpb,
+                                                  double* __restrict__ partial, const Ctl* ctl) {
   if (ctl->stop) return;
   const int ncols = j + 1;
   extern __shared__ unsigned char smem_raw[];
@@ -154,7 +193,6 @@ __global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict
   __shared__ double cl[MAXK];
   __shared__ double dacc[MAXK + 1];
   __shared__ T rl[STR];
-  __shared__ double red[LDP];
   __shared__ double scr[16];
   for (int c = threadIdx.x; c < ncols; c += BLK) {
     cl[c] = coef[c];
@@ -173,13 +211,13 @@ __global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict
       for (int c0 = 0; c0 < ncols; c0 += 16) {
         T qv[16];
 #pragma unroll
-        for (int g = 0; g < 16; ++g)
-          qv[g] = (ok && c0 + g < ncols) ? Q[(int64_t)(c0 + g) * ldq + row] : T(0);
+        for (int gq = 0; gq < 16; ++gq)
+          qv[gq] = (ok && c0 + gq < ncols) ? Q[(int64_t)(c0 + gq) * ldq + row] : T(0);
 #pragma unroll
-        for (int g = 0; g < 16; ++g) {
-          if (c0 + g < ncols) {
-            qt[(c0 + g) * STR + t] = qv[g];
-            proj += (double)qv[g] * cl[c0 + g];
+        for (int gq = 0; gq < 16; ++gq) {
+          if (c0 + gq < ncols) {
+            qt[(c0 + gq) * STR + t] = qv[gq];
+            proj += (double)qv[gq] * cl[c0 + gq];
           }
         }
       }
@@ -195,7 +233,8 @@ __global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict
     for (int c = w; c < ncols; c += BLK / WAVE) {
       double a = 0.0;
 #pragma unroll
-      for (int q = 0; q < STR / WAVE; ++q) a += (double)qt[c * STR + lane + q * WAVE] * (double)rl[lane + q * WAVE];
+      for (int q = 0; q < STR / WAVE; ++q)
+        a += (double)qt[c * STR + lane + q * WAVE] * (double)rl[lane + q * WAVE];
       a = wave_sum(a);
       if (lane == 0) dacc[c] += a;
     }
@@ -205,69 +244,80 @@ __global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict
   double* prow = partial + (size_t)blockIdx.x * LDP;
   for (int c = threadIdx.x; c < ncols; c += BLK) prow[c] = dacc[c];
   if (threadIdx.x == 0) prow[ncols] = rrb;
-  if (!reduce_partials(partial, gpartial, counters, ncols + 1, red)) return;
-  for (int c = threadIdx.x; c < ncols; c += BLK) c2out[c] = red[c];
-  if (threadIdx.x == 0) {
-    double c2n = 0.0;
-    for (int c = 0; c < ncols; ++c) c2n += red[c] * red[c];
-    const double a = coef[j] + red[j];
-    const double b2 = red[ncols] - c2n;
-    const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
-    alpha[j] = a;
-    beta[j] = b;
-    const double amax = fmax(ctl->amax, fabs(a));
-    ctl->amax = amax;
-    if (!isfinite(a) || !isfinite(b)) {
-      ctl->status |= SF_NONFINITE;
-      ctl->stop = 1;
-      ctl->k_eff = j;
-    } else {
-      ctl->k_eff = j + 1;
-      if (j < klast && !(b > tol * amax)) {
-        ctl->stop = 1;
-        ctl->status |= SF_BREAKDOWN;
-      }
-    }
-  }
 }
 
-// q_{j+1} = (r' - Q c2) / beta_j
+// alpha_j, beta_j, stop test (every block, identically), then
+// q_{j+1} = (r' - Q c2) / beta_j.  Block 0 records the step.
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_lz_finalize(int64_t n, const T* __restrict__ r,
                                                      T* __restrict__ Q, int64_t ldq, int j,
-                                                     const double* __restrict__ c2,
-                                                     const double* __restrict__ beta, Ctl* ctl) {
+                                                     const double* __restrict__ coef,
+                                                     const double* __restrict__ c2rr,
+                                                     double* __restrict__ alpha,
+                                                     double* __restrict__ beta,
+                                                     double* __restrict__ amax_hist, double tol,
+                                                     int klast, Ctl* ctl) {
   if (ctl->stop) return;
   __shared__ double cl[MAXK];
-  for (int c = threadIdx.x; c <= j; c += BLK) cl[c] = c2[c];
+  __shared__ double s_beta;
+  __shared__ int s_stop;
+  for (int c = threadIdx.x; c <= j; c += BLK) cl[c] = c2rr[c];
+  if (threadIdx.x == 0) {
+    double c2n = 0.0;
+    for (int c = 0; c <= j; ++c) c2n += c2rr[c] * c2rr[c];
+    const double a = coef[j] + c2rr[j];
+    const double b2 = c2rr[j + 1] - c2n;
+    const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
+    const double amax = fmax(j > 0 ? amax_hist[j - 1] : 0.0, fabs(a));
+    int stop = 0;
+    unsigned st = 0;
+    int keff = j + 1;
+    if (!isfinite(a) || !isfinite(b)) {
+      stop = 1;
+      st = SF_NONFINITE;
+      keff = j;
+    } else if (j < klast && !(b > tol * amax)) {
+      stop = 1;
+      st = SF_BREAKDOWN;
+    }
+    s_beta = b;
+    s_stop = stop;
+    if (blockIdx.x == 0) {
+      alpha[j] = a;
+      beta[j] = b;
+      amax_hist[j] = amax;
+      ctl->k_eff = keff;
+      if (stop) {
+        ctl->stop = 1;
+        ctl->status |= st;
+      }
+    }
+  }
   __syncthreads();
+  if (s_stop || j >= klast) return;
+  const double inv = 1.0 / s_beta;
   const int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x;
   if (row >= n) return;
   double acc = (double)r[row];
 #pragma unroll 16
   for (int c = 0; c <= j; ++c) acc -= (double)Q[(int64_t)c * ldq + row] * cl[c];
-  Q[(int64_t)(j + 1) * ldq + row] = (T)(acc / beta[j]);
+  Q[(int64_t)(j + 1) * ldq + row] = (T)(acc * inv);
 }
 
 // ----------------------------------------------------------------------------
-// Generic dots of a given vector v with columns 0..ncols-1 of Q plus v^T v.
-// mode 0: coef[c] = q_c^T v ; scalar[0] = v^T v.
-// mode 1 (probe): also ctl->bnorm = ||v||.
-// mode 2 (mean jump start): z = T^{-1} (Q^T v) written to coef; ctl->rr0 = v^T v.
+// Dots of a given vector v with columns 0..ncols-1 of Q, plus v^T v, as
+// partial rows: [q_0^T v, ..., q_{ncols-1}^T v, v^T v].  With use_keff the
+// number of columns is min(ncols_max, k_eff) (missing ones written as 0).
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_dots(int64_t n, const T* __restrict__ v,
                                               const T* __restrict__ Q, int64_t ldq, int ncols_max,
-                                              int rpb, double* partial, double* gpartial,
-                                              unsigned* counters, double* __restrict__ coef,
-                                              double* __restrict__ scalar, int mode,
-                                              const double* __restrict__ ldiag,
-                                              const double* __restrict__ lsub, Ctl* ctl) {
+                                              int use_keff, int rpb, double* __restrict__ partial,
+                                              const Ctl* ctl) {
   extern __shared__ unsigned char smem_raw[];
   T* vl = (T*)smem_raw;
-  __shared__ double red[LDP];
   __shared__ double scr[16];
-  const int ncols = (mode == 2) ? min(ncols_max, ctl->k_eff) : ncols_max;
+  const int ncols = use_keff ? min(ncols_max, ctl->k_eff) : ncols_max;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   double ss = 0.0;
   for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
@@ -281,38 +331,14 @@ __global__ __launch_bounds__(BLK) void k_dots(int64_t n, const T* __restrict__ v
   const int nrows = (int)min<int64_t>(rpb, n - r0);
   double* prow = partial + (size_t)blockIdx.x * LDP;
   if (ncols > 0) block_dots(Q, ldq, ncols, r0, nrows, vl, prow);
-  if (threadIdx.x == 0) prow[ncols] = ssb;
-  if (!reduce_partials(partial, gpartial, counters, ncols + 1, red)) return;
-  if (mode == 2) {
-    if (threadIdx.x == 0) {
-      // T z = Q^T y with T = L L^T (bidiagonal L): forward then backward substitution
-      const int k = ncols;
-      double zz[MAXK];
-      for (int i = 0; i < k; ++i) {
-        double t = red[i] - (i > 0 ? lsub[i - 1] * zz[i - 1] : 0.0);
-        zz[i] = t / ldiag[i];
-      }
-      for (int i = k - 1; i >= 0; --i) {
-        double t = zz[i] - (i + 1 < k ? lsub[i] * zz[i + 1] : 0.0);
-        zz[i] = t / ldiag[i];
-      }
-      for (int i = 0; i < k; ++i) coef[i] = zz[i];
-      for (int i = k; i < ncols_max; ++i) coef[i] = 0.0;
-      ctl->rr0 = red[ncols];
-    }
-    return;
-  }
-  for (int c = threadIdx.x; c < ncols; c += BLK) coef[c] = red[c];
-  if (threadIdx.x == 0) {
-    if (scalar) scalar[0] = red[ncols];
-    if (mode == 1) ctl->bnorm = sqrt(red[ncols]);
-  }
+  for (int c = ncols + threadIdx.x; c < ncols_max; c += BLK) prow[c] = 0.0;
+  if (threadIdx.x == 0) prow[ncols_max] = ssb;
 }
 
 // out = v / ctl->bnorm
 template <typename T>
 __global__ void k_scale_by_bnorm(int64_t n, const T* __restrict__ v, T* __restrict__ out,
-                                 Ctl* ctl) {
+                                 const Ctl* ctl) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double b = ctl->bnorm;
@@ -403,21 +429,21 @@ __global__ void k_rtilde(int64_t m, const T* __restrict__ R, const double* __res
 }
 
 // ----------------------------------------------------------------------------
-// CG for the mean cache: Khat x = y, started from the Lanczos solve
-// x0 = Q T^{-1} Q^T y (eq. lanczos_solve).  Per iteration:
+// CG for the mean cache: Khat x = y.  Per iteration:
 //   scatter  g_p = W^T r + ratio * g_p        (= W^T p_new without forming p first)
 //   toeplitz kg = K g_p
-//   ap       p = r + ratio * p ; Ap = W kg + sigma^2 p ; gamma = rr / p^T Ap
-//   update   x += gamma p ; r -= gamma Ap ; ratio = rr_new / rr
+//   ap       p = r + ratio * p ; Ap = W kg + sigma^2 p ; partial rows of p^T Ap
+//   colsum   p^T Ap
+//   update   gamma = rr / p^T Ap ; x += gamma p ; r -= gamma Ap ; partial rows of r^T r
+//   colsum + epilogue: ratio = rr_new / rr, convergence test
 // ----------------------------------------------------------------------------
 template <typename T, int D>
 __global__ __launch_bounds__(BLK) void k_cg_ap(GridT<T> g, const T* __restrict__ x, int64_t n,
                                                const T* __restrict__ kg, const T* __restrict__ r,
                                                T* __restrict__ p, T* __restrict__ ap, T sigma2,
-                                               int rpb, double* partial, double* gpartial,
-                                               unsigned* counters, Ctl* ctl) {
+                                               int rpb, double* __restrict__ partial,
+                                               const Ctl* ctl) {
   if (ctl->cg_done) return;
-  __shared__ double red[LDP];
   __shared__ double scr[16];
   const double ratio = ctl->ratio;
   double d = 0.0;
@@ -433,21 +459,26 @@ __global__ __launch_bounds__(BLK) void k_cg_ap(GridT<T> g, const T* __restrict__
   }
   const double db = block_sum(d, scr);
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
-  if (!reduce_partials(partial, gpartial, counters, 1, red)) return;
-  if (threadIdx.x == 0) ctl->gamma = ctl->rr / red[0];
 }
 
+// gamma = rr / p^T Ap, with p^T Ap summed by every block from the partial
+// rows of k_cg_ap (a few hundred doubles, one wave, fixed order).
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_cg_update(int64_t n, T* __restrict__ xs,
                                                    T* __restrict__ r, const T* __restrict__ p,
-                                                   const T* __restrict__ ap, int rpb,
-                                                   double* partial, double* gpartial,
-                                                   unsigned* counters, double tol2, int maxit,
-                                                   Ctl* ctl) {
+                                                   const T* __restrict__ ap,
+                                                   const double* __restrict__ pap_partial, int nb,
+                                                   int rpb, double* __restrict__ partial,
+                                                   const Ctl* ctl) {
   if (ctl->cg_done) return;
-  __shared__ double red[LDP];
   __shared__ double scr[16];
-  const double gm = ctl->gamma;
+  __shared__ double s_pap;
+  if (threadIdx.x < WAVE) {
+    const double sum = colsum_wave(pap_partial, nb, 0);
+    if (threadIdx.x == 0) s_pap = sum;
+  }
+  __syncthreads();
+  const double gm = ctl->rr / s_pap;
   double d = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
   for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
@@ -460,33 +491,15 @@ __global__ __launch_bounds__(BLK) void k_cg_update(int64_t n, T* __restrict__ xs
   }
   const double db = block_sum(d, scr);
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
-  if (!reduce_partials(partial, gpartial, counters, 1, red)) return;
-  if (threadIdx.x == 0) {
-    const double rrn = red[0];
-    ctl->ratio = rrn / ctl->rr;
-    ctl->rr = rrn;
-    ctl->cg_iters += 1;
-    if (!(rrn > tol2 * ctl->rr0)) ctl->cg_done = 1;
-    else if (ctl->cg_iters >= maxit) {
-      ctl->cg_done = 1;
-      ctl->status |= SF_CG_NOCONV;
-    }
-    if (!isfinite(rrn)) {
-      ctl->cg_done = 1;
-      ctl->status |= SF_NONFINITE;
-    }
-  }
 }
 
-// r = y - A x0 ; p = 0 ; rr = r^T r ; ratio = 0
+// r = y - A x0 ; p = 0 ; partial rows of r^T r
 template <typename T, int D>
 __global__ __launch_bounds__(BLK) void k_cg_init(GridT<T> g, const T* __restrict__ x, int64_t n,
                                                  const T* __restrict__ kg, const T* __restrict__ y,
                                                  const T* __restrict__ x0, T* __restrict__ r,
                                                  T* __restrict__ p, T sigma2, int rpb,
-                                                 double* partial, double* gpartial,
-                                                 unsigned* counters, double tol2, Ctl* ctl) {
-  __shared__ double red[LDP];
+                                                 double* __restrict__ partial) {
   __shared__ double scr[16];
   double d = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
@@ -501,13 +514,6 @@ __global__ __launch_bounds__(BLK) void k_cg_init(GridT<T> g, const T* __restrict
   }
   const double db = block_sum(d, scr);
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
-  if (!reduce_partials(partial, gpartial, counters, 1, red)) return;
-  if (threadIdx.x == 0) {
-    ctl->rr = red[0];
-    ctl->ratio = 0.0;
-    ctl->cg_iters = 0;
-    ctl->cg_done = (red[0] > tol2 * ctl->rr0) ? 0 : 1;
-  }
 }
 
 __global__ void k_ctl_init(Ctl* ctl) {
@@ -519,39 +525,35 @@ __global__ void k_ctl_init(Ctl* ctl) {
 // Host orchestration
 // ----------------------------------------------------------------------------
 struct Work {
-  double* partial = nullptr;
-  double* gpartial = nullptr;
-  unsigned* counters = nullptr;
-  double* coef = nullptr;
-  double* c2 = nullptr;
+  double* partial = nullptr;   // nb x LDP
+  double* coef = nullptr;      // LDP
+  double* c2 = nullptr;        // LDP
   double* ldiag = nullptr;
   double* lsub = nullptr;
-  double* scalar = nullptr;
+  double* scalar = nullptr;    // LDP
+  double* amax = nullptr;      // LDP
   int rpb = BLK;
   int nb = 0;
 };
 
 static love_status work_alloc(love_cache* c, Work& wk, int64_t rows, std::vector<void*>& tmp,
                               hipStream_t s) {
-  int rpt = (int)cdiv(rows, (int64_t)BLK * 512);
-  if (rpt < 1) rpt = 1;
-  wk.rpb = BLK * rpt;
+  // rows per block: 256 x t for big row counts (at most ~512 blocks), else a
+  // multiple of 64 giving ~256-384 blocks so small problems still fill the chip
+  if (rows >= (int64_t)BLK * 256) wk.rpb = (int)(BLK * cdiv(rows, (int64_t)BLK * 512));
+  else wk.rpb = (int)(64 * std::max<int64_t>(1, cdiv(rows, (int64_t)64 * 256)));
   wk.nb = (int)cdiv(rows, wk.rpb);
-  const int ng = (int)cdiv(wk.nb, RGS);
-  size_t bytes = sizeof(double) * ((size_t)wk.nb * LDP + (size_t)ng * LDP + 5 * LDP) +
-                 sizeof(unsigned) * (ng + 1);
+  size_t bytes = sizeof(double) * ((size_t)wk.nb * LDP + 6 * LDP);
   char* p = nullptr;
   LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
   tmp.push_back(p);
   wk.partial = (double*)p;
-  wk.gpartial = wk.partial + (size_t)wk.nb * LDP;
-  wk.coef = wk.gpartial + (size_t)ng * LDP;
+  wk.coef = wk.partial + (size_t)wk.nb * LDP;
   wk.c2 = wk.coef + LDP;
   wk.ldiag = wk.c2 + LDP;
   wk.lsub = wk.ldiag + LDP;
   wk.scalar = wk.lsub + LDP;
-  wk.counters = (unsigned*)(wk.scalar + LDP);
-  LOVE_HIP_TRY(hipMemsetAsync(wk.counters, 0, sizeof(unsigned) * (ng + 1), s));
+  wk.amax = wk.scalar + LDP;
   return LOVE_OK;
 }
 
@@ -561,15 +563,15 @@ static void set_smem_limits() {
   if (done) return;
   done = true;
   (void)hipFuncSetAttribute((const void*)k_lz_udots<T, (sizeof(T) == 8 ? 128 : 256)>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
 }
 
 // Mean cache a = K W^T Khat^{-1} y (eq. pred_mean_ski).  The solve runs in
 // double whatever the cache precision: in float the true residual of CG
 // stalls at ~1e-3 relative on the 1e5-point workload (rounding of the
 // operator's float sums times its condition number ~1e5), which leaves the
-// mean wrong in the third digit; in double, CG started from the Lanczos solve
-// x0 = Q T^{-1} Q^T y (eq. lanczos_solve) needs about a dozen iterations.
+// mean wrong in the third digit.  CG starts from the Lanczos solve
+// x0 = Q T^{-1} Q^T y (eq. lanczos_solve).
 template <typename T, int D>
 static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
                               std::vector<void*>& tmp, hipStream_t s) {
@@ -578,10 +580,11 @@ static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
   const int k = c->k;
   const unsigned nbr = (unsigned)cdiv(n, BLK);
   Ctl* ctl = c->ctl;
-  double *x64, *y64, *xs, *rr, *pp, *ap, *gv, *gm;
+  double *x64, *y64, *xs, *rr, *pp, *ap, *gv, *gm, *tsc;
   {
     const bool own = sizeof(T) != 8;
-    size_t bytes = sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 4 * (size_t)ldq + 2 * (size_t)m);
+    size_t bytes = sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 4 * (size_t)ldq +
+                                     2 * (size_t)m + (size_t)toeplitz_scratch_elems(c));
     char* p = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
     tmp.push_back(p);
@@ -602,24 +605,27 @@ static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
     ap = pp + ldq;
     gv = ap + ldq;
     gm = gv + m;
+    tsc = gm + m;
   }
   GridT<double> g = make_grid<double>(c);
   const double sigma2 = c->cfg.noise;
   const bool plain = (c->cfg.flags & LOVE_FLAG_PLAIN_CG) != 0;
-  // jump start: z = T^{-1} Q^T y, x0 = Q z (float Q, double z and x0)
-  const T* yT = (const T*)c->y;
-  k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, yT, Q, ldq, plain ? 0 : k, wk.rpb,
-                                                   wk.partial, wk.gpartial, wk.counters, wk.coef,
-                                                   wk.scalar, 2, wk.ldiag, wk.lsub, ctl);
-  if (plain) launch_fill<double>(xs, 0.0, n, s);
-  else k_q_times<T, double><<<nbr, BLK, 0, s>>>(n, Q, ldq, wk.coef, xs, ctl);
   const double cgtol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
   const int maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
+  // jump start: z = T^{-1} Q^T y, x0 = Q z (float Q, double z and x0)
+  const T* yT = (const T*)c->y;
+  const int kk = plain ? 0 : k;
+  k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, yT, Q, ldq, kk, 1, wk.rpb, wk.partial, ctl);
+  k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, kk + 1, EP_TRISOLVE, wk.coef, wk.ldiag, wk.lsub,
+                                0.0, 0, ctl);
+  if (plain) launch_fill<double>(xs, 0.0, n, s);
+  else k_q_times<T, double><<<nbr, BLK, 0, s>>>(n, Q, ldq, wk.coef, xs, ctl);
   launch_scatter<double>(c, xs, gv, nullptr, nullptr, 0, s, x64);
-  toeplitz_apply<double>(c, gv, gm, nullptr, 0, s);
+  toeplitz_apply<double>(c, gv, gm, tsc, nullptr, 0, s);
   k_cg_init<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, y64, xs, rr, pp, sigma2, wk.rpb,
-                                             wk.partial, wk.gpartial, wk.counters, cgtol * cgtol,
-                                             ctl);
+                                             wk.partial);
+  k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_CG_INIT, nullptr, nullptr, nullptr,
+                                cgtol * cgtol, maxit, ctl);
   launch_fill<double>(gv, 0.0, m, s);   // W^T p with p = 0
   Ctl hctl;
   int it = 0;
@@ -627,26 +633,31 @@ static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
   while (it < maxit) {
     for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
       launch_scatter<double>(c, rr, gv, gv, ctl, 2 | 4, s, x64);
-      toeplitz_apply<double>(c, gv, gm, ctl, 2, s);
+      toeplitz_apply<double>(c, gv, gm, tsc, ctl, 2, s);
       k_cg_ap<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, rr, pp, ap, sigma2, wk.rpb,
-                                               wk.partial, wk.gpartial, wk.counters, ctl);
-      k_cg_update<double><<<wk.nb, BLK, 0, s>>>(n, xs, rr, pp, ap, wk.rpb, wk.partial,
-                                                wk.gpartial, wk.counters, cgtol * cgtol, maxit,
-                                                ctl);
+                                               wk.partial, ctl);
+      k_cg_update<double><<<wk.nb, BLK, 0, s>>>(n, xs, rr, pp, ap, wk.partial, wk.nb, wk.rpb,
+                                                wk.partial + 1, ctl);
+      k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial + 1, wk.nb, 1, EP_CG_STEP, nullptr, nullptr,
+                                    nullptr, cgtol * cgtol, maxit, ctl);
     }
     LOVE_HIP_TRY(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     LOVE_HIP_TRY(hipStreamSynchronize(s));
     if (hctl.cg_done) break;
   }
   launch_scatter<double>(c, xs, gv, nullptr, nullptr, 0, s, x64);
-  toeplitz_apply<double>(c, gv, gm, nullptr, 0, s);
+  toeplitz_apply<double>(c, gv, gm, tsc, nullptr, 0, s);
   if (sizeof(T) == 8) launch_convert<double, double>(gm, (double*)c->a, m, s);
   else launch_convert<double, float>(gm, (float*)c->a, m, s);
   return LOVE_OK;
 }
 
+template <typename TR, int SPLIT>
+static love_status sampler_impl(love_cache* c, hipStream_t s);
+static love_status sampler_dispatch(love_cache* c, hipStream_t s);
+
 template <typename T, int D>
-static love_status lanczos_impl(love_cache* c, hipStream_t s) {
+static love_status lanczos_impl(love_cache* c, hipStream_t s, hipStream_t s_side) {
   constexpr int STR = (sizeof(T) == 8) ? 128 : 256;
   set_smem_limits<T>();
   const int64_t n = c->n, m = c->m;
@@ -660,9 +671,10 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s) {
   love_status st = work_alloc(c, wk, n, tmp, s);
   if (st != LOVE_OK) return st;
   // transient buffers: Q (n x k), R (k x m), v, r, grid vectors
-  T *Q, *R, *v, *r, *gv, *gm;
+  T *Q, *R, *v, *r, *gv, *gm, *tsc;
   {
-    size_t bytes = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m);
+    size_t bytes = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
+                                (size_t)toeplitz_scratch_elems(c));
     char* p = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
     tmp.push_back(p);
@@ -672,6 +684,7 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s) {
     r = v + ldq;
     gv = r + ldq;
     gm = gv + m;
+    tsc = gm + m;
   }
   Ctl* ctl = c->ctl;
   k_ctl_init<<<1, 1, 0, s>>>(ctl);
@@ -680,33 +693,34 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s) {
   {
     ProfScope ps("probe", s);
     launch_fill<T>(gv, T(1.0 / (double)m), m, s);
-    toeplitz_apply<T>(c, gv, gm, nullptr, 0, s);
+    toeplitz_apply<T>(c, gv, gm, tsc, nullptr, 0, s);
     launch_gather<T>(c, gm, nullptr, T(0), v, nullptr, s);
-    k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, v, Q, ldq, 0, wk.rpb, wk.partial, wk.gpartial,
-                                                     wk.counters, wk.coef, wk.scalar, 1, nullptr,
-                                                     nullptr, ctl);
+    k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
+    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, nullptr, nullptr, 0.0, 0,
+                                  ctl);
     k_scale_by_bnorm<T><<<nbr, BLK, 0, s>>>(n, v, Q, ctl);
   }
   const double tol = c->tol_lanczos;
   for (int j = 0; j < k; ++j) {
     launch_scatter<T>(c, Q + (size_t)j * ldq, gv, nullptr, ctl, 1, s);
-    toeplitz_apply<T>(c, gv, R + (size_t)j * m, ctl, 1, s);
+    toeplitz_apply<T>(c, gv, R + (size_t)j * m, tsc, ctl, 1, s);
     {
       ProfScope ps("lz_gdots", s);
       k_lz_gdots<T, D><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(
-          g, x, n, R + (size_t)j * m, Q, ldq, j, sigma2, v, wk.rpb, wk.partial, wk.gpartial,
-          wk.counters, wk.coef, ctl);
+          g, x, n, R + (size_t)j * m, Q, ldq, j, sigma2, v, wk.rpb, wk.partial, ctl);
     }
+    launch_colsum(wk.partial, wk.nb, j + 1, wk.coef, s);
     {
       ProfScope ps("lz_udots", s);
       const size_t shm = sizeof(T) * (size_t)(j + 1) * STR;
       k_lz_udots<T, STR><<<wk.nb, BLK, shm, s>>>(n, v, Q, ldq, j, wk.coef, r, wk.rpb, wk.partial,
-                                                 wk.gpartial, wk.counters, wk.c2, c->alpha,
-                                                 c->beta, tol, k - 1, ctl);
+                                                 ctl);
     }
-    if (j + 1 < k) {
+    launch_colsum(wk.partial, wk.nb, j + 2, wk.c2, s);
+    {
       ProfScope ps("lz_finalize", s);
-      k_lz_finalize<T><<<nbr, BLK, 0, s>>>(n, r, Q, ldq, j, wk.c2, c->beta, ctl);
+      k_lz_finalize<T><<<nbr, BLK, 0, s>>>(n, r, Q, ldq, j, wk.coef, wk.c2, c->alpha, c->beta,
+                                           wk.amax, tol, k - 1, ctl);
     }
   }
   // T = L L^T ; Rt = (L^{-1} R)^T
@@ -717,10 +731,31 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s) {
     k_rtilde<T><<<cdiv(m, 256), 256, 0, s>>>(m, R, wk.ldiag, wk.lsub, c->rt, (uint16_t*)c->rt_lo,
                                              c->kpad, split, ctl);
   }
+  // The sampler (grid space, needs Rt) and the mean solve (needs Q) are
+  // independent chains of small kernels: the sampler runs on a side stream
+  // concurrently with the mean CG, and the caller's stream waits for it.
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  const bool side = c->ks > 0 && s_side != nullptr;
+  if (c->ks > 0) {
+    if (side) {
+      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+      LOVE_HIP_TRY(hipEventRecord(ev_fork, s));
+      LOVE_HIP_TRY(hipStreamWaitEvent(s_side, ev_fork, 0));
+    }
+    love_status ss = sampler_dispatch(c, side ? s_side : s);
+    if (ss != LOVE_OK) return ss;
+    if (side) LOVE_HIP_TRY(hipEventRecord(ev_join, s_side));
+  }
   // mean cache a = K W^T Khat^{-1} y
   if (!(c->cfg.flags & LOVE_FLAG_NO_MEAN)) {
     love_status ms = mean_solve<T, D>(c, Q, ldq, wk, tmp, s);
     if (ms != LOVE_OK) return ms;
+  }
+  if (side) {
+    LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(ev_join);
   }
   for (void* p : tmp) (void)hipFreeAsync(p, s);
   LOVE_HIP_TRY(hipGetLastError());
@@ -728,26 +763,25 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s) {
 }
 
 template <typename T>
-love_status build_lanczos_and_mean(love_cache* c, hipStream_t s) {
+love_status build_lanczos_and_mean(love_cache* c, hipStream_t s, hipStream_t s_side) {
   switch (c->d) {
-    case 1: return lanczos_impl<T, 1>(c, s);
-    case 2: return lanczos_impl<T, 2>(c, s);
-    case 3: return lanczos_impl<T, 3>(c, s);
-    case 4: return lanczos_impl<T, 4>(c, s);
+    case 1: return lanczos_impl<T, 1>(c, s, s_side);
+    case 2: return lanczos_impl<T, 2>(c, s, s_side);
+    case 3: return lanczos_impl<T, 3>(c, s, s_side);
+    case 4: return lanczos_impl<T, 4>(c, s, s_side);
   }
   return LOVE_EINVAL;
 }
-template love_status build_lanczos_and_mean<float>(love_cache*, hipStream_t);
-template love_status build_lanczos_and_mean<double>(love_cache*, hipStream_t);
-
+template love_status build_lanczos_and_mean<float>(love_cache*, hipStream_t, hipStream_t);
+template love_status build_lanczos_and_mean<double>(love_cache*, hipStream_t, hipStream_t);
 
 // ============================================================================
 // Sampling cache (Sec. 3.3): Lanczos on B = K - R^T R' = K - Rt Rt^T in grid
-// space (eq. lancapprox), probe b' = (1/m) B 1, then S = Q' L_{T'}
-// (eq. pred_covar_ski_interp_form).  B is the difference of two nearly equal
-// matrices (the posterior covariance is 1e-4..1e-6 of the prior here), so
-// this Lanczos runs in double whatever the cache precision; Rt is read in its
-// stored precision and widened.
+// space (eq. lancapprox), probe b' = (1/m) B 1, then a factor S with
+// S S^T = Q' T' Q'^T (eq. pred_covar_ski_interp_form).  B is the difference
+// of two nearly equal matrices (the posterior covariance is 1e-4..1e-6 of the
+// prior here), so this Lanczos runs in double whatever the cache precision;
+// Rt is read in its stored precision and widened.
 // ============================================================================
 template <typename TR, int SPLIT>
 __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t idx) {
@@ -759,16 +793,14 @@ __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t i
   }
 }
 
-// s = Rt^T v (columns < keff); lanes own columns, waves split the rows.
+// partial rows of s = Rt^T v (columns < keff); lanes own columns, waves split the rows.
 template <typename TR, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
                                                  const void* __restrict__ rt,
                                                  const uint16_t* __restrict__ rt_lo, int kpad,
-                                                 const Ctl* ctl_main, int rpb, double* partial,
-                                                 double* gpartial, unsigned* counters,
-                                                 double* __restrict__ sout, const Ctl* ctl) {
+                                                 const Ctl* ctl_main, int rpb,
+                                                 double* __restrict__ partial, const Ctl* ctl) {
   if (ctl && ctl->stop) return;
-  __shared__ double red[LDP];
   __shared__ double wsum[BLK / WAVE][MAXK];
   const int keff = ctl_main->k_eff;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
@@ -789,11 +821,9 @@ __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __rest
     for (int q = 0; q < BLK / WAVE; ++q) s += wsum[q][c];
     prow[c] = s;
   }
-  if (!reduce_partials(partial, gpartial, counters, keff, red)) return;
-  for (int c = threadIdx.x; c < keff; c += BLK) sout[c] = red[c];
 }
 
-// v = kv - Rt s (grid rows); then c = Q'_{0..j}^T v  (ncols = j + 1; 0 = probe)
+// v = kv - Rt s (grid rows); partial rows of Q'_{0..ncols-1}^T v (none for ncols = 0)
 template <typename TR, int SPLIT>
 __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* __restrict__ kv,
                                                        const void* __restrict__ rt,
@@ -802,165 +832,176 @@ __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* 
                                                        const double* __restrict__ sv,
                                                        const double* __restrict__ Q, int64_t ldq,
                                                        int ncols, double* __restrict__ vout,
-                                                       int rpb, double* partial, double* gpartial,
-                                                       unsigned* counters,
-                                                       double* __restrict__ coef, Ctl* ctl) {
+                                                       int rpb, double* __restrict__ partial,
+                                                       const Ctl* ctl) {
   if (ctl->stop) return;
   extern __shared__ unsigned char smem_raw[];
   double* vl = (double*)smem_raw;
-  __shared__ double red[LDP];
   __shared__ double sl[MAXK];
   const int keff = ctl_main->k_eff;
   for (int c = threadIdx.x; c < keff; c += BLK) sl[c] = sv[c];
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const double s0 = lane < keff ? sl[lane] : 0.0;
+  const double s1 = lane + WAVE < keff ? sl[lane + WAVE] : 0.0;
+  for (int rr = w; rr < rpb; rr += BLK / WAVE) {   // one wave per grid row
     const int64_t u = r0 + rr;
     double val = 0.0;
     if (u < m) {
-      double acc = kv[u];
-#pragma unroll 16
-      for (int c = 0; c < keff; ++c) acc -= rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + c) * sl[c];
-      val = acc;
-      vout[u] = val;
+      double part = 0.0;
+      if (lane < keff) part += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane) * s0;
+      if (lane + WAVE < keff) part += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE) * s1;
+      val = kv[u] - wave_sum(part);
+      if (lane == 0) vout[u] = val;
     }
-    vl[rr] = val;
+    if (lane == 0) vl[rr] = val;
   }
   __syncthreads();
   if (ncols == 0) return;
   const int nrows = (int)min<int64_t>(rpb, m - r0);
   block_dots(Q, ldq, ncols, r0, nrows, vl, partial + (size_t)blockIdx.x * LDP);
-  if (!reduce_partials(partial, gpartial, counters, ncols, red)) return;
-  for (int c = threadIdx.x; c < ncols; c += BLK) coef[c] = red[c];
 }
 
 // Eigen-decomposition T' = V diag(lam) V^T of the sampler's symmetric
 // tridiagonal (k' <= 128) by implicit QL with Wilkinson shifts (Bowdler,
-// Martin, Reinsch and Wilkinson, 1968).  One block of MAXK threads: thread 0
-// runs the scalar chase of a sweep and records its plane rotations; then each
-// thread applies the sweep's rotations, in order, to its own row of V (held in
-// LDS).  Eigenpairs are returned sorted by decreasing eigenvalue; k_chol
-// counts the strictly positive ones (negative Ritz values of K - Rt Rt^T are
-// rounding noise of the float cache and are clipped to zero).
+// Martin, Reinsch and Wilkinson, 1968).  One wave does everything: lane i
+// holds d[i], d[i+64], e[i], e[i+64] in registers; the scalar chase runs
+// uniformly on all lanes (values fetched with readlane), and every plane
+// rotation is applied at once to the lane's two rows of V (held in LDS), the
+// updated column carried in registers.  Eigenpairs are returned sorted by
+// decreasing eigenvalue; k_chol counts the strictly positive ones (negative
+// Ritz values of K - Rt Rt^T come from rounding of the float cache and are
+// clipped to zero).
 constexpr int EIG_MAXSWEEP = 40;
 
-__global__ __launch_bounds__(MAXK) void k_tri_eig(const double* __restrict__ alpha,
+__device__ inline double rl64(double v, int lane) {
+  const int2 u = *reinterpret_cast<const int2*>(&v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(u.x, lane);
+  r.y = __builtin_amdgcn_readlane(u.y, lane);
+  return *reinterpret_cast<const double*>(&r);
+}
+// value of a 128-entry array held as (lo: entries 0..63, hi: entries 64..127)
+__device__ inline double get128(double lo, double hi, int i) {
+  return i < WAVE ? rl64(lo, i) : rl64(hi, i - WAVE);
+}
+__device__ inline void set128(double& lo, double& hi, int i, double v, int lane) {
+  if (i < WAVE) lo = (lane == i) ? v : lo;
+  else hi = (lane == i - WAVE) ? v : hi;
+}
+
+__global__ __launch_bounds__(WAVE) void k_tri_eig(const double* __restrict__ alpha,
                                                   const double* __restrict__ beta,
                                                   double* __restrict__ vout,
                                                   double* __restrict__ lam, Ctl* ctl) {
   extern __shared__ unsigned char smem_raw[];
-  double* V = (double*)smem_raw;   // MAXK x MAXK, column c of V at V[c * MAXK + row]
-  __shared__ double d[MAXK], e[MAXK], rc[MAXK], rs[MAXK];
-  __shared__ int ri[MAXK];
-  __shared__ int nrot, done, lcur, iters;
+  double* V = (double*)smem_raw;   // column c of V at V[c * MAXK + row]
+  __shared__ double dsh[MAXK];
   __shared__ int perm[MAXK];
-  const int t = threadIdx.x;
+  const int lane = threadIdx.x;
   const int k = ctl->k_eff;
-  for (int cidx = 0; cidx < k; ++cidx) V[cidx * MAXK + t] = (cidx == t) ? 1.0 : 0.0;
-  if (t == 0) {
-    for (int i = 0; i < k; ++i) {
-      d[i] = alpha[i];
-      e[i] = (i + 1 < k) ? beta[i] : 0.0;
-    }
-    lcur = 0;
-    iters = 0;
-    done = (k <= 0);
+  for (int cidx = 0; cidx < k; ++cidx) {
+    V[cidx * MAXK + lane] = (cidx == lane) ? 1.0 : 0.0;
+    V[cidx * MAXK + lane + WAVE] = (cidx == lane + WAVE) ? 1.0 : 0.0;
   }
+  double dlo = lane < k ? alpha[lane] : 0.0;
+  double dhi = lane + WAVE < k ? alpha[lane + WAVE] : 0.0;
+  double elo = lane + 1 < k ? beta[lane] : 0.0;
+  double ehi = lane + WAVE + 1 < k ? beta[lane + WAVE] : 0.0;
+  unsigned bad = 0;
+  for (int l = 0; l < k; ++l) {
+    int iter = 0;
+    while (true) {
+      int mm = l;
+      for (; mm < k - 1; ++mm) {
+        const double dd = fabs(get128(dlo, dhi, mm)) + fabs(get128(dlo, dhi, mm + 1));
+        if (fabs(get128(elo, ehi, mm)) <= 2.220446049250313e-16 * dd) break;
+      }
+      if (mm == l) break;
+      if (++iter > EIG_MAXSWEEP) {
+        bad = 1;
+        break;
+      }
+      const double dl = get128(dlo, dhi, l), el = get128(elo, ehi, l);
+      double g = (get128(dlo, dhi, l + 1) - dl) / (2.0 * el);
+      double r = hypot(g, 1.0);
+      g = get128(dlo, dhi, mm) - dl + el / (g + copysign(r, g));
+      double sv = 1.0, cv = 1.0, p = 0.0;
+      // eigenvector rows of this lane: column mm is the running carry
+      double car0 = V[mm * MAXK + lane], car1 = V[mm * MAXK + lane + WAVE];
+      int last = -1;
+      bool underflow = false;
+      for (int i = mm - 1; i >= l; --i) {
+        const double ei = get128(elo, ehi, i);
+        const double f = sv * ei, b = cv * ei;
+        const double ss = f * f + g * g;
+        double inv = 0.0;
+        if (ss > 0.0) {
+          inv = rsqrt(ss);
+          inv = inv * (1.5 - 0.5 * ss * inv * inv);   // one Newton step
+        }
+        r = ss * inv;
+        set128(elo, ehi, i + 1, r, lane);
+        if (r == 0.0) {
+          set128(dlo, dhi, i + 1, get128(dlo, dhi, i + 1) - p, lane);
+          set128(elo, ehi, mm, 0.0, lane);
+          underflow = true;
+          break;
+        }
+        sv = f * inv;
+        cv = g * inv;
+        g = get128(dlo, dhi, i + 1) - p;
+        r = (get128(dlo, dhi, i) - g) * sv + 2.0 * cv * b;
+        p = sv * r;
+        set128(dlo, dhi, i + 1, g + p, lane);
+        g = cv * r - b;
+        // V[:, i+1] <- s V[:, i] + c V[:, i+1] ; V[:, i] <- c V[:, i] - s V[:, i+1]
+        const double v0 = V[i * MAXK + lane], v1 = V[i * MAXK + lane + WAVE];
+        V[(i + 1) * MAXK + lane] = sv * v0 + cv * car0;
+        V[(i + 1) * MAXK + lane + WAVE] = sv * v1 + cv * car1;
+        car0 = cv * v0 - sv * car0;
+        car1 = cv * v1 - sv * car1;
+        last = i;
+      }
+      if (last >= 0) {
+        V[last * MAXK + lane] = car0;
+        V[last * MAXK + lane + WAVE] = car1;
+      }
+      if (!underflow) {
+        set128(dlo, dhi, l, get128(dlo, dhi, l) - p, lane);
+        set128(elo, ehi, l, g, lane);
+        set128(elo, ehi, mm, 0.0, lane);
+      }
+    }
+  }
+  dsh[lane] = dlo;
+  dsh[lane + WAVE] = dhi;
   __syncthreads();
-  while (true) {
-    if (t == 0) {
-      nrot = 0;
-      // advance l over converged eigenvalues; stop at the first one needing a sweep
-      while (lcur < k) {
-        int mm = lcur;
-        for (; mm < k - 1; ++mm) {
-          const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-          if (fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
-        }
-        if (mm == lcur) {
-          ++lcur;
-          iters = 0;
-          continue;
-        }
-        if (++iters > EIG_MAXSWEEP) {   // give up on this eigenvalue (flagged)
-          ctl->status |= SF_NONFINITE;
-          ++lcur;
-          iters = 0;
-          continue;
-        }
-        const int l = lcur;
-        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-        double r = hypot(g, 1.0);
-        g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
-        double sv = 1.0, cv = 1.0, p = 0.0;
-        int i = mm - 1;
-        bool underflow = false;
-        for (; i >= l; --i) {
-          const double f = sv * e[i], b = cv * e[i];
-          r = hypot(f, g);
-          e[i + 1] = r;
-          if (r == 0.0) {
-            d[i + 1] -= p;
-            e[mm] = 0.0;
-            underflow = true;
-            break;
-          }
-          sv = f / r;
-          cv = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * sv + 2.0 * cv * b;
-          p = sv * r;
-          d[i + 1] = g + p;
-          g = cv * r - b;
-          ri[nrot] = i;
-          rc[nrot] = cv;
-          rs[nrot] = sv;
-          ++nrot;
-        }
-        if (!underflow) {
-          d[l] -= p;
-          e[l] = g;
-          e[mm] = 0.0;
-        }
-        break;   // one sweep recorded
-      }
-      done = (lcur >= k) ? 1 : 0;
-    }
-    __syncthreads();
-    const int nr = nrot;
-    if (t < k) {
-      for (int q = 0; q < nr; ++q) {
-        const int i = ri[q];
-        const double cv = rc[q], sv = rs[q];
-        const double f = V[(i + 1) * MAXK + t];
-        const double vi = V[i * MAXK + t];
-        V[(i + 1) * MAXK + t] = sv * vi + cv * f;
-        V[i * MAXK + t] = cv * vi - sv * f;
-      }
-    }
-    __syncthreads();
-    if (done) break;
-  }
-  if (t == 0) {
+  if (lane == 0) {
     for (int i = 0; i < k; ++i) perm[i] = i;
     for (int i = 0; i < k; ++i) {          // selection sort, decreasing
       int best = i;
       for (int j = i + 1; j < k; ++j)
-        if (d[perm[j]] > d[perm[best]]) best = j;
+        if (dsh[perm[j]] > dsh[perm[best]]) best = j;
       const int tmpi = perm[i];
       perm[i] = perm[best];
       perm[best] = tmpi;
     }
     int pos = 0;
     for (int i = 0; i < k; ++i) {
-      lam[i] = d[perm[i]];
-      if (d[perm[i]] > 0.0 && isfinite(d[perm[i]])) pos = i + 1;
+      lam[i] = dsh[perm[i]];
+      if (dsh[perm[i]] > 0.0 && isfinite(dsh[perm[i]])) pos = i + 1;
     }
     ctl->k_chol = pos;
     if (pos < k) ctl->status |= SF_SAMPLER_TRUNC;
+    if (bad) ctl->status |= SF_NONFINITE;
   }
   __syncthreads();
-  for (int cidx = 0; cidx < k; ++cidx) vout[cidx * MAXK + t] = V[perm[cidx] * MAXK + t];
+  for (int cidx = 0; cidx < k; ++cidx) {
+    vout[cidx * MAXK + lane] = V[perm[cidx] * MAXK + lane];
+    vout[cidx * MAXK + lane + WAVE] = V[perm[cidx] * MAXK + lane + WAVE];
+  }
 }
 
 // S[u, c] = sqrt(lam_c) * sum_i Q'[i][u] V[c][i]  for c < k_chol (zero beyond kspad).
@@ -969,33 +1010,30 @@ __global__ __launch_bounds__(256) void k_s_from_eig(int64_t m, const double* __r
                                                     const double* __restrict__ lam,
                                                     float* __restrict__ S, int kspad,
                                                     const Ctl* ctl) {
-  extern __shared__ unsigned char smem_raw[];
-  double* Vl = (double*)smem_raw;   // kc x k (row c = eigenvector c)
+  constexpr int CT = 16;                      // columns of S per block (blockIdx.y)
+  __shared__ double Vl[CT][MAXK];             // sqrt(lam_c) * eigenvector c
   const int k = ctl->k_eff, kc = ctl->k_chol;
-  for (int idx = threadIdx.x; idx < kc * k; idx += blockDim.x) {
-    const int c = idx / k, i = idx % k;
-    Vl[idx] = vout[c * MAXK + i] * sqrt(lam[c]);
+  const int c0 = blockIdx.y * CT;
+  for (int idx = threadIdx.x; idx < CT * k; idx += blockDim.x) {
+    const int q = idx / k, i = idx % k;
+    Vl[q][i] = (c0 + q < kc) ? vout[(c0 + q) * MAXK + i] * sqrt(lam[c0 + q]) : 0.0;
   }
   __syncthreads();
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= m) return;
-  constexpr int CT = 16;
-  for (int c0 = 0; c0 < kspad; c0 += CT) {
-    double acc[CT];
+  double acc[CT];
 #pragma unroll
-    for (int q = 0; q < CT; ++q) acc[q] = 0.0;
-    if (c0 < kc) {
-      for (int i = 0; i < k; ++i) {
-        const double qv = Q[(int64_t)i * ldq + u];
+  for (int q = 0; q < CT; ++q) acc[q] = 0.0;
+  if (c0 < kc) {
+    for (int i = 0; i < k; ++i) {
+      const double qv = Q[(int64_t)i * ldq + u];
 #pragma unroll
-        for (int q = 0; q < CT; ++q)
-          if (c0 + q < kc) acc[q] += qv * Vl[(c0 + q) * k + i];
-      }
+      for (int q = 0; q < CT; ++q) acc[q] += qv * Vl[q][i];
     }
-#pragma unroll
-    for (int q = 0; q < CT; ++q)
-      if (c0 + q < kspad) S[u * kspad + c0 + q] = (float)acc[q];
   }
+#pragma unroll
+  for (int q = 0; q < CT; ++q)
+    if (c0 + q < kspad) S[u * kspad + c0 + q] = (float)acc[q];
 }
 
 template <typename TR, int SPLIT>
@@ -1008,9 +1046,10 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   Work wk;
   love_status st = work_alloc(c, wk, m, tmp, s);
   if (st != LOVE_OK) return st;
-  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam;
+  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *tsc;
   {
-    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 4 * LDP + MAXK * MAXK);
+    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 4 * LDP + MAXK * MAXK +
+                                     (size_t)toeplitz_scratch_elems(c));
     char* p = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
     tmp.push_back(p);
@@ -1024,60 +1063,59 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     beta = alpha + LDP;
     lam = beta + LDP;
     vout = lam + LDP;
+    tsc = vout + MAXK * MAXK;
   }
   Ctl* ctl = c->ctl_s;
   const Ctl* cm = c->ctl;
   k_ctl_init<<<1, 1, 0, s>>>(ctl);
   const unsigned nbm = (unsigned)cdiv(m, BLK);
   const size_t shm = sizeof(double) * wk.rpb;
+  const uint16_t* rlo = (const uint16_t*)c->rt_lo;
   {
     ProfScope ps("sampler_probe", s);
     launch_fill<double>(gv, 1.0 / (double)m, m, s);
-    toeplitz_apply<double>(c, gv, kv, nullptr, 0, s);
-    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, gv, c->rt, (const uint16_t*)c->rt_lo, c->kpad, cm,
-                                               wk.rpb, wk.partial, wk.gpartial, wk.counters, sv,
+    toeplitz_apply<double>(c, gv, kv, tsc, nullptr, 0, s);
+    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm, wk.rpb, wk.partial,
                                                nullptr);
-    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, (const uint16_t*)c->rt_lo,
-                                                      c->kpad, cm, sv, Q, ldq, 0, v, wk.rpb,
-                                                      wk.partial, wk.gpartial, wk.counters,
-                                                      wk.coef, ctl);
-    k_dots<double><<<wk.nb, BLK, shm, s>>>(m, v, Q, ldq, 0, wk.rpb, wk.partial, wk.gpartial,
-                                           wk.counters, wk.coef, wk.scalar, 1, nullptr, nullptr, ctl);
+    launch_colsum(wk.partial, wk.nb, c->k, sv, s);
+    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq,
+                                                      0, v, wk.rpb, wk.partial, ctl);
+    k_dots<double><<<wk.nb, BLK, shm, s>>>(m, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
+    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, nullptr, nullptr, 0.0,
+                                  0, ctl);
     k_scale_by_bnorm<double><<<nbm, BLK, 0, s>>>(m, v, Q, ctl);
   }
   const double tol = 1e-12;
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
-    toeplitz_apply<double>(c, qj, kv, ctl, 1, s);
-    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, qj, c->rt, (const uint16_t*)c->rt_lo, c->kpad, cm,
-                                               wk.rpb, wk.partial, wk.gpartial, wk.counters, sv,
+    toeplitz_apply<double>(c, qj, kv, tsc, ctl, 1, s);
+    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm, wk.rpb, wk.partial,
                                                ctl);
-    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, (const uint16_t*)c->rt_lo,
-                                                      c->kpad, cm, sv, Q, ldq, j + 1, v, wk.rpb,
-                                                      wk.partial, wk.gpartial, wk.counters,
-                                                      wk.coef, ctl);
+    launch_colsum(wk.partial, wk.nb, c->k, sv, s);
+    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq,
+                                                      j + 1, v, wk.rpb, wk.partial, ctl);
+    launch_colsum(wk.partial, wk.nb, j + 1, wk.coef, s);
     k_lz_udots<double, 128><<<wk.nb, BLK, sizeof(double) * (size_t)(j + 1) * 128, s>>>(
-        m, v, Q, ldq, j, wk.coef, r, wk.rpb, wk.partial, wk.gpartial, wk.counters, wk.c2, alpha,
-        beta, tol, ks - 1, ctl);
-    if (j + 1 < ks) k_lz_finalize<double><<<nbm, BLK, 0, s>>>(m, r, Q, ldq, j, wk.c2, beta, ctl);
+        m, v, Q, ldq, j, wk.coef, r, wk.rpb, wk.partial, ctl);
+    launch_colsum(wk.partial, wk.nb, j + 2, wk.c2, s);
+    k_lz_finalize<double><<<nbm, BLK, 0, s>>>(m, r, Q, ldq, j, wk.coef, wk.c2, alpha, beta,
+                                              wk.amax, tol, ks - 1, ctl);
   }
   {
     ProfScope pe("sampler_eig", s);
     (void)hipFuncSetAttribute((const void*)k_tri_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
                               sizeof(double) * MAXK * MAXK);
-    (void)hipFuncSetAttribute((const void*)k_s_from_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              sizeof(double) * MAXK * MAXK);
-    k_tri_eig<<<1, MAXK, sizeof(double) * MAXK * MAXK, s>>>(alpha, beta, vout, lam, ctl);
-    k_s_from_eig<<<cdiv(m, 256), 256, sizeof(double) * MAXK * MAXK, s>>>(m, Q, ldq, vout, lam, c->S,
-                                                                        c->kspad, ctl);
+    k_tri_eig<<<1, WAVE, sizeof(double) * MAXK * MAXK, s>>>(alpha, beta, vout, lam, ctl);
+    dim3 sgrid((unsigned)cdiv(m, 256), (unsigned)cdiv(c->kspad, 16));
+    k_s_from_eig<<<sgrid, 256, 0, s>>>(m, Q, ldq, vout, lam, c->S, c->kspad, ctl);
   }
   for (void* p : tmp) (void)hipFreeAsync(p, s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }
 
-love_status build_sampler(love_cache* c, hipStream_t s) {
+static love_status sampler_dispatch(love_cache* c, hipStream_t s) {
   ProfScope ps("sampler_build", s);
   if (c->fp64) return sampler_impl<double, 0>(c, s);
   if (c->cfg.precision == LOVE_P_FP32_BF16SPLIT) return sampler_impl<float, 1>(c, s);

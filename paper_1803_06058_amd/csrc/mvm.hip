@@ -176,97 +176,116 @@ template void launch_convert<double, double>(const double*, double*, int64_t, hi
 
 // ----------------------------------------------------------------------------
 // Direct Toeplitz product along a contiguous axis of length L (long lines):
-//   out[o, i] = scale * sum_j c[|i - j|] in[o, j].
-// Block = 256 threads, each owning TOEP_R consecutive outputs; the needed
-// coefficients slide along a register window (one new LDS load per input j),
-// the input chunk is an LDS broadcast.  Inputs are split into chunks
-// (split-K); a second kernel adds the chunk partial sums in chunk order
-// (deterministic).
+//   out[o, i] = scale * sum_j c[|i - j|] in[o, j],   |i - j| <= bw.
+// Grid = (output tiles of TB_OUT = 64 * TB_R outputs) x (input segments) x
+// lines.  A block stages its input segment and the matching strip of signed
+// coefficients cd[delta] = c[|delta|] in LDS; its waves take equal slices of
+// the segment.  Each lane owns TB_R consecutive outputs whose coefficients
+// slide along a register window (one LDS load per input; the input itself is
+// an LDS broadcast).  Wave sums are added in LDS in wave order; with several
+// segments, k_toep_reduce adds the segment sums in segment order
+// (deterministic throughout).  Coefficients beyond the band bw are below the
+// working precision's rounding of the largest term (set at plan time).
 // ----------------------------------------------------------------------------
-constexpr int TOEP_R = 5;  // odd: lane stride R in the coefficient window is LDS bank-conflict free
+constexpr int TB_WAVES = 8;
+constexpr int TB_R = 3;                   // odd: lane stride TB_R keeps LDS reads near conflict-free
+constexpr int TB_OUT = WAVE * TB_R;       // 192
+constexpr int TB_SEG = 2048;              // max inputs per block (one LDS window)
+constexpr int TB_NSEG_MAX = 16;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_toep_long(const T* __restrict__ in, T* __restrict__ out,
-                                                   const T* __restrict__ c, int L, int CH, T scale,
-                                                   T* __restrict__ partial,
-                                                   const Ctl* ctl, int mode) {
+__global__ __launch_bounds__(TB_WAVES * WAVE) void k_toep_band(const T* __restrict__ in,
+                                                               T* __restrict__ out,
+                                                               const T* __restrict__ c, int L,
+                                                               int bw, int seglen, T scale,
+                                                               T* __restrict__ partial,
+                                                               const Ctl* ctl, int mode) {
   if (ctl_skip(ctl, mode)) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* gl = (T*)smem_raw;                 // CH
-  T* cw = gl + CH;                      // TO + CH - 1
-  constexpr int TO = 256 * TOEP_R;
-  const int tile0 = blockIdx.x * TO;
-  const int j0 = blockIdx.y * CH;
+  __shared__ T gl[TB_SEG];
+  __shared__ T cd[TB_SEG + TB_OUT];
+  __shared__ T red[TB_WAVES][TB_OUT];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int i0 = blockIdx.x * TB_OUT;
+  const int nseg = gridDim.y;
   const int64_t line = blockIdx.z;
-  const T* src = in + line * L;
-  const int dmin = tile0 - (j0 + CH - 1);
-  const int nw = TO + CH - 1;
-  for (int q = threadIdx.x; q < CH; q += 256) {
-    const int j = j0 + q;
-    gl[q] = (j < L) ? src[j] : T(0);
-  }
-  for (int q = threadIdx.x; q < nw; q += 256) {
-    const int dl = dmin + q;
-    const int ad = dl < 0 ? -dl : dl;
-    cw[q] = (ad < L) ? c[ad] : T(0);
-  }
-  __syncthreads();
-  const int i0 = tile0 + threadIdx.x * TOEP_R;
-  // coefficient for output i0 + r and input j: c[|i0 + r - j|] = cw[wi + r - j]
-  const int wi = i0 - dmin;
-  T P[TOEP_R];
-  T acc[TOEP_R];
+  const T* g = in + line * L;
+  const int jlo = max(0, i0 - bw);
+  const int jhi = min(L - 1, i0 + TB_OUT - 1 + bw);
+  const int jw = jlo + blockIdx.y * seglen;
+  const int nwin = max(0, min(seglen, jhi + 1 - jw));
+  const int il = i0 + lane * TB_R;          // first output of this lane
+  T acc[TB_R];
 #pragma unroll
-  for (int r = 0; r < TOEP_R; ++r) {
-    P[r] = cw[wi + r - j0];
-    acc[r] = T(0);
-  }
-  for (int jj = 0; jj < CH; jj += TOEP_R) {
+  for (int r = 0; r < TB_R; ++r) acc[r] = T(0);
+  if (nwin > 0) {
+    // cd[q] = c[|delta|] for delta = dmin + q, dmin = i0 - (jw + nwin - 1)
+    const int dmin = i0 - (jw + nwin - 1);
+    const int ncd = nwin + TB_OUT - 1;
+    for (int q = threadIdx.x; q < nwin; q += TB_WAVES * WAVE) gl[q] = g[jw + q];
+    for (int q = threadIdx.x; q < ncd; q += TB_WAVES * WAVE) {
+      const int dl = dmin + q;
+      const int ad = dl < 0 ? -dl : dl;
+      cd[q] = (ad <= bw && ad < L) ? c[ad] : T(0);
+    }
+    __syncthreads();
+    const int per = (nwin + TB_WAVES - 1) / TB_WAVES;
+    const int qb = w * per, qe = min(nwin, qb + per);
+    if (qb < qe) {
+      // coefficient of output il + r and input jw + q: cd[il + r - jw - q - dmin]
+      const int base = il - jw - dmin;
+      T P[TB_R];
 #pragma unroll
-    for (int q = 0; q < TOEP_R; ++q) {
-      const int j = j0 + jj + q;
-      const T gv = gl[jj + q];
+      for (int r = 0; r < TB_R; ++r) P[r] = cd[base + r - qb];
+      int q = qb;
+      for (; q + TB_R <= qe; q += TB_R) {
 #pragma unroll
-      for (int r = 0; r < TOEP_R; ++r) acc[r] += P[(r - q + TOEP_R) % TOEP_R] * gv;
-      // next step's logical 0: cd(i0 - (j + 1))
-      const int widx = wi - j - 1;
-      P[(TOEP_R - 1 - q) % TOEP_R] = (widx >= 0) ? cw[widx] : T(0);
+        for (int u = 0; u < TB_R; ++u) {
+          const T gv = gl[q + u];
+#pragma unroll
+          for (int r = 0; r < TB_R; ++r) acc[r] += P[(r - u + TB_R) % TB_R] * gv;
+          const int ni = base - (q + u) - 1;
+          P[(TB_R - 1 - u) % TB_R] = ni >= 0 ? cd[ni] : T(0);
+        }
+      }
+      for (; q < qe; ++q) {   // tail (fewer than TB_R inputs): direct indexing
+        const T gv = gl[q];
+#pragma unroll
+        for (int r = 0; r < TB_R; ++r) acc[r] += cd[base + r - q] * gv;
+      }
     }
   }
-  const int nchunks = gridDim.y;
-  if (nchunks == 1) {
 #pragma unroll
-    for (int r = 0; r < TOEP_R; ++r)
-      if (i0 + r < L) out[line * L + i0 + r] = scale * acc[r];
-    return;
+  for (int r = 0; r < TB_R; ++r) red[w][lane * TB_R + r] = acc[r];
+  __syncthreads();
+  for (int o = threadIdx.x; o < TB_OUT; o += TB_WAVES * WAVE) {
+    T s = T(0);
+#pragma unroll
+    for (int q = 0; q < TB_WAVES; ++q) s += red[q][o];
+    const int i = i0 + o;
+    if (i < L) {
+      if (nseg == 1) out[line * L + i] = scale * s;
+      else partial[((int64_t)line * nseg + blockIdx.y) * L + i] = s;
+    }
   }
-  T* mypart = partial + ((int64_t)line * nchunks + blockIdx.y) * L;
-#pragma unroll
-  for (int r = 0; r < TOEP_R; ++r)
-    if (i0 + r < L) mypart[i0 + r] = acc[r];
 }
 
-// out[line, i] = scale * sum_chunks partial[line, chunk, i]; all loads first.
+// out[line, i] = scale * sum_seg partial[line, seg, i] (segment order)
 template <typename T>
 __global__ __launch_bounds__(256) void k_toep_reduce(const T* __restrict__ partial,
-                                                     T* __restrict__ out, int L, int nchunks,
+                                                     T* __restrict__ out, int L, int nseg,
                                                      int64_t nlines, T scale, const Ctl* ctl,
                                                      int mode) {
   if (ctl_skip(ctl, mode)) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nlines * L) return;
   const int64_t line = idx / L, i = idx % L;
-  const T* lp = partial + line * nchunks * (int64_t)L + i;
+  const T* lp = partial + line * nseg * (int64_t)L + i;
+  T v[TB_NSEG_MAX];
+#pragma unroll
+  for (int q = 0; q < TB_NSEG_MAX; ++q) v[q] = q < nseg ? lp[(int64_t)q * L] : T(0);
   T acc = T(0);
-  int ck = 0;
-  for (; ck + 8 <= nchunks; ck += 8) {
-    T v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = lp[(int64_t)(ck + q) * L];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc += v[q];
-  }
-  for (; ck < nchunks; ++ck) acc += lp[(int64_t)ck * L];
+  for (int q = 0; q < TB_NSEG_MAX; ++q) acc += v[q];
   out[idx] = scale * acc;
 }
 
@@ -314,27 +333,34 @@ template <typename T>
 void fft_axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
                     const Ctl* ctl, int mode, hipStream_t s);
 
+int64_t toeplitz_scratch_elems(const love_cache* c) { return (2 + TB_NSEG_MAX) * c->m; }
+
 template <typename T>
 static void axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
-                       const Ctl* ctl, int mode, hipStream_t s) {
-  const ToepPlan& p = c->toep;
+                       T* scratch, const Ctl* ctl, int mode, hipStream_t s) {
   const T* cc = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
   if (ax.mode == 2) {
     fft_axis_apply<T>(c, ax, in, out, scale, ctl, mode, s);
     return;
   }
   if (ax.inner == 1 && ax.L > TOEP_LINES_MAXL) {
-    constexpr int TO = 256 * TOEP_R;
-    int CH = ax.tile_chunk;
-    CH = ((CH + TOEP_R - 1) / TOEP_R) * TOEP_R;
-    const int ntiles = (int)cdiv(ax.L, TO);
-    const int nchunks = (int)cdiv(ax.L, CH);
-    dim3 grid(ntiles, nchunks, (unsigned)ax.outer);
-    size_t shm = sizeof(T) * (CH + TO + CH - 1);
-    k_toep_long<T><<<grid, 256, shm, s>>>(in, out, cc, ax.L, CH, scale, (T*)p.partial, ctl, mode);
-    if (nchunks > 1)
+    const int bw = sizeof(T) == 8 ? ax.bw64 : ax.bw32;
+    const int ntiles = (int)cdiv(ax.L, TB_OUT);
+    const int band = std::min(ax.L, TB_OUT + 2 * bw);
+    // segments: enough blocks to cover the chip (~512), each at least 256 inputs
+    int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
+                                                           cdiv(band, 256)));
+    nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
+    nseg = std::min(nseg, TB_NSEG_MAX);
+    const int seglen = (int)cdiv(band, nseg);
+    T* partial = scratch ? scratch + 2 * c->m : nullptr;
+    if (seglen > TB_SEG || (nseg > 1 && !partial)) nseg = 0;   // cannot happen for planned sizes
+    dim3 grid((unsigned)ntiles, (unsigned)std::max(nseg, 1), (unsigned)ax.outer);
+    k_toep_band<T><<<grid, TB_WAVES * WAVE, 0, s>>>(in, out, cc, ax.L, bw, seglen, scale, partial,
+                                                    ctl, mode);
+    if (nseg > 1)
       k_toep_reduce<T><<<(unsigned)cdiv(ax.L * ax.outer, 256), 256, 0, s>>>(
-          (const T*)p.partial, out, ax.L, nchunks, ax.outer, scale, ctl, mode);
+          partial, out, ax.L, nseg, ax.outer, scale, ctl, mode);
   } else {
     const int64_t nlines = ax.outer * ax.inner;
     dim3 grid((unsigned)cdiv(nlines, WAVE));
@@ -344,23 +370,23 @@ static void axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* 
 }
 
 template <typename T>
-void toeplitz_apply(const love_cache* c, const T* in, T* out, const Ctl* ctl, int ctl_mode,
-                    hipStream_t s) {
+void toeplitz_apply(const love_cache* c, const T* in, T* out, T* scratch, const Ctl* ctl,
+                    int ctl_mode, hipStream_t s) {
   ProfScope ps("toeplitz", s);
   const ToepPlan& p = c->toep;
-  // axes applied last-to-first; intermediate results ping-pong through tmp1/tmp2
+  // axes applied last-to-first; intermediate results ping-pong through the scratch halves
   const T* src = in;
-  T* bufs[2] = {(T*)p.tmp1, (T*)p.tmp2};
+  T* bufs[2] = {scratch, scratch ? scratch + c->m : nullptr};
   int flip = 0;
   for (int e = p.d - 1; e >= 0; --e) {
     T* dst = (e == 0) ? out : bufs[flip];
-    axis_apply<T>(c, p.ax[e], src, dst, T(1), ctl, ctl_mode, s);
+    axis_apply<T>(c, p.ax[e], src, dst, T(1), scratch, ctl, ctl_mode, s);
     src = dst;
     flip ^= 1;
   }
 }
-template void toeplitz_apply<float>(const love_cache*, const float*, float*, const Ctl*, int, hipStream_t);
-template void toeplitz_apply<double>(const love_cache*, const double*, double*, const Ctl*, int, hipStream_t);
+template void toeplitz_apply<float>(const love_cache*, const float*, float*, float*, const Ctl*, int, hipStream_t);
+template void toeplitz_apply<double>(const love_cache*, const double*, double*, double*, const Ctl*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Small helpers
@@ -423,7 +449,6 @@ love_status toeplitz_plan(love_cache* c) {
   p.d = c->d;
   p.mtot = c->m;
   int64_t inner = 1;
-  size_t partial_elems = 0;
   for (int e = c->d - 1; e >= 0; --e) {
     ToepAxis& ax = p.ax[e];
     ax.L = c->mdim[e];
@@ -448,13 +473,23 @@ love_status toeplitz_plan(love_cache* c) {
       love_status st = fft_plan_axis(c, ax, e, col);
       if (st != LOVE_OK) return st;
     }
-    if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.inner == 1 && ax.L > TOEP_LINES_MAXL) {
-      if (ax.tile_chunk <= 0) ax.tile_chunk = 320;
-      const int64_t nchunks = cdiv(ax.L, ((ax.tile_chunk + TOEP_R - 1) / TOEP_R) * TOEP_R);
-      partial_elems = std::max<size_t>(partial_elems, (size_t)(nchunks * ax.L * ax.outer));
-    } else if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.L > TOEP_LINES_MAXL) {
-      return LOVE_EUNSUPPORTED;  // long strided axis: use the FFT backend
+    // band of coefficients that can matter at each working precision:
+    // sum_{|d| > bw} |c_d| |g_j| <= L * thr * max|g|, with thr = eps * c_0 / L
+    {
+      auto band = [&](double eps) {
+        const double thr = eps * std::fabs(col[0]) / (double)ax.L;
+        int bw = ax.L - 1;
+        while (bw > 0 && std::fabs(col[bw]) <= thr) --bw;
+        return bw;
+      };
+      ax.bw32 = band(5.96e-8);
+      ax.bw64 = band(1.12e-16);
     }
+    if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.inner != 1 && ax.L > TOEP_LINES_MAXL)
+      return LOVE_EUNSUPPORTED;  // long strided axis: use the FFT backend
+    if (ax.mode == LOVE_TOEPLITZ_DIRECT && ax.inner == 1 && ax.L > TOEP_LINES_MAXL &&
+        std::min(ax.L, TB_OUT + 2 * std::max(ax.bw32, ax.bw64)) > TB_NSEG_MAX * TB_SEG)
+      return LOVE_EUNSUPPORTED;  // band wider than the segmented kernel covers: use the FFT
   }
   for (int e = 0; e < 4; ++e)
     if (e >= c->d)
@@ -462,14 +497,6 @@ love_status toeplitz_plan(love_cache* c) {
   c->c4_dev = (double*)dev_alloc(c, sizeof(double) * 16);
   if (!c->c4_dev) return LOVE_ENOMEM;
   LOVE_HIP_TRY(hipMemcpy(c->c4_dev, c->c4, sizeof(double) * 16, hipMemcpyHostToDevice));
-  p.tmp1 = dev_alloc(c, sizeof(double) * c->m);
-  p.tmp2 = dev_alloc(c, sizeof(double) * c->m);
-  if (!p.tmp1 || !p.tmp2) return LOVE_ENOMEM;
-  if (partial_elems) {
-    p.partial = dev_alloc(c, sizeof(double) * partial_elems);
-    p.partial_elems = partial_elems;
-    if (!p.partial) return LOVE_ENOMEM;
-  }
   return LOVE_OK;
 }
 
