@@ -1,27 +1,296 @@
-// Circulant-embedding FFT backend for the Toeplitz factors of K_UU and the
-// per-axis backend choice.  (Filled in below; the direct backend is used
-// until an axis selects the FFT.)
+// Circulant-embedding FFT backend for the Toeplitz factors of K_UU (Sec. 2.3:
+// a regular grid makes K_UU Toeplitz, so K g costs O(m log m)), and the
+// per-axis choice between it and the direct banded product.
+//
+// A symmetric Toeplitz matrix with first column c (length L) is the leading
+// L x L block of the circulant C of size N >= 2L - 1 whose first column is
+// [c_0, ..., c_{L-1}, 0, ..., 0, c_{L-1}, ..., c_1].  C = F^{-1} diag(lam) F with
+// lam = F c_ext real and even, so for two real lines x1, x2 packed as
+// z = x1 + i x2,  F^{-1}(lam * F z) = C x1 + i C x2: one complex FFT pair
+// serves two lines and needs no post-processing.
+//
+// Kernel: one block per line pair, the whole length-N complex signal in LDS,
+// iterative radix-2 decimation in time (bit-reversed load) for the forward
+// transform, multiply by lam / N, decimation in frequency for the inverse
+// (bit-reversed store).  Twiddles exp(-2 pi i k / N) and lam are tabulated on
+// the host in double.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
+#include "ops.h"
 
 namespace love {
 
-love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<double>& col) {
-  (void)c; (void)e; (void)col;
-  ax.mode = LOVE_TOEPLITZ_DIRECT;
-  return LOVE_OK;
+constexpr int FFT_BLK = 256;
+
+template <typename T>
+struct Cx {
+  T re, im;
+};
+
+__device__ inline unsigned bitrev(unsigned x, int bits) { return __brev(x) >> (32 - bits); }
+
+template <typename T>
+__global__ __launch_bounds__(FFT_BLK) void k_fft_conv(const T* __restrict__ in, T* __restrict__ out,
+                                                      int L, int64_t inner, int64_t nlines, int N,
+                                                      int logN, const T* __restrict__ tw,
+                                                      const T* __restrict__ lam, T scale,
+                                                      const Ctl* ctl, int mode) {
+  if (ctl_skip(ctl, mode)) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* zr = (T*)smem_raw;        // N
+  T* zi = zr + N;              // N
+  const int64_t l1 = 2 * (int64_t)blockIdx.x, l2 = l1 + 1;
+  const bool has2 = l2 < nlines;
+  const int64_t o1 = l1 / inner, r1 = l1 % inner, o2 = l2 / inner, r2 = l2 % inner;
+  const T* s1 = in + o1 * L * inner + r1;
+  const T* s2 = in + o2 * L * inner + r2;
+  for (int i = threadIdx.x; i < N; i += FFT_BLK) {
+    const unsigned p = bitrev((unsigned)i, logN);
+    zr[p] = i < L ? s1[(int64_t)i * inner] : T(0);
+    zi[p] = (i < L && has2) ? s2[(int64_t)i * inner] : T(0);
+  }
+  __syncthreads();
+  // forward, decimation in time
+  for (int st = 1; st <= logN; ++st) {
+    const int half = 1 << (st - 1);
+    const int tstep = N >> st;   // twiddle index stride
+    for (int b = threadIdx.x; b < N / 2; b += FFT_BLK) {
+      const int grp = b >> (st - 1), j = b & (half - 1);
+      const int i1 = grp * 2 * half + j, i2 = i1 + half;
+      const T wr = tw[2 * (j * tstep)], wi = tw[2 * (j * tstep) + 1];
+      const T xr = zr[i2], xi = zi[i2];
+      const T tr = wr * xr - wi * xi, ti = wr * xi + wi * xr;
+      const T ur = zr[i1], ui = zi[i1];
+      zr[i1] = ur + tr;
+      zi[i1] = ui + ti;
+      zr[i2] = ur - tr;
+      zi[i2] = ui - ti;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < N; i += FFT_BLK) {
+    const T lv = lam[i];
+    zr[i] *= lv;
+    zi[i] *= lv;
+  }
+  __syncthreads();
+  // inverse, decimation in frequency with conjugate twiddles
+  for (int st = logN; st >= 1; --st) {
+    const int half = 1 << (st - 1);
+    const int tstep = N >> st;
+    for (int b = threadIdx.x; b < N / 2; b += FFT_BLK) {
+      const int grp = b >> (st - 1), j = b & (half - 1);
+      const int i1 = grp * 2 * half + j, i2 = i1 + half;
+      const T wr = tw[2 * (j * tstep)], wi = -tw[2 * (j * tstep) + 1];
+      const T ur = zr[i1], ui = zi[i1], vr = zr[i2], vi = zi[i2];
+      zr[i1] = ur + vr;
+      zi[i1] = ui + vi;
+      const T dr = ur - vr, di = ui - vi;
+      zr[i2] = wr * dr - wi * di;
+      zi[i2] = wr * di + wi * dr;
+    }
+    __syncthreads();
+  }
+  T* d1 = out + o1 * L * inner + r1;
+  T* d2 = out + o2 * L * inner + r2;
+  for (int i = threadIdx.x; i < L; i += FFT_BLK) {
+    const unsigned p = bitrev((unsigned)i, logN);
+    d1[(int64_t)i * inner] = scale * zr[p];
+    if (has2) d2[(int64_t)i * inner] = scale * zi[p];
+  }
 }
 
-int autotune_choose(love_cache* c, int e) {
-  (void)c; (void)e;
-  return LOVE_TOEPLITZ_DIRECT;
+// ----------------------------------------------------------------------------
+// Host: tables
+// ----------------------------------------------------------------------------
+static int fft_max_n(bool dbl) { return dbl ? 8192 : 16384; }   // N complex values in LDS
+
+// iterative radix-2 complex FFT in double (host, table building only)
+static void host_fft(std::vector<std::complex<double>>& a) {
+  const int n = (int)a.size();
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    const double ang = -2.0 * M_PI / len;
+    for (int i = 0; i < n; i += len)
+      for (int j = 0; j < len / 2; ++j) {
+        const std::complex<double> w(std::cos(ang * j), std::sin(ang * j));
+        const std::complex<double> u = a[i + j], v = a[i + j + len / 2] * w;
+        a[i + j] = u + v;
+        a[i + j + len / 2] = u - v;
+      }
+  }
+}
+
+love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<double>& col) {
+  (void)e;
+  int N = 1, logN = 0;
+  while (N < 2 * ax.L - 1) {
+    N <<= 1;
+    ++logN;
+  }
+  if (N > fft_max_n(true)) {   // the double tables must fit too (sampler and mean run in double)
+    ax.mode = LOVE_TOEPLITZ_DIRECT;
+    return LOVE_OK;
+  }
+  std::vector<std::complex<double>> cext(N, 0.0);
+  for (int i = 0; i < ax.L; ++i) cext[i] = col[i];
+  for (int i = 1; i < ax.L; ++i) cext[N - i] = col[i];
+  host_fft(cext);
+  std::vector<double> lam64(N), tw64(N);
+  std::vector<float> lam32(N), tw32(N);
+  for (int i = 0; i < N; ++i) {
+    lam64[i] = cext[i].real() / N;
+    lam32[i] = (float)lam64[i];
+  }
+  for (int k = 0; k < N / 2; ++k) {
+    tw64[2 * k] = std::cos(-2.0 * M_PI * k / N);
+    tw64[2 * k + 1] = std::sin(-2.0 * M_PI * k / N);
+    tw32[2 * k] = (float)tw64[2 * k];
+    tw32[2 * k + 1] = (float)tw64[2 * k + 1];
+  }
+  ax.spec64 = dev_alloc(c, sizeof(double) * 2 * N);   // [lam | twiddles]
+  ax.spec32 = dev_alloc(c, sizeof(float) * 2 * N);
+  if (!ax.spec64 || !ax.spec32) return LOVE_ENOMEM;
+  LOVE_HIP_TRY(hipMemcpy(ax.spec64, lam64.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  LOVE_HIP_TRY(hipMemcpy((double*)ax.spec64 + N, tw64.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  LOVE_HIP_TRY(hipMemcpy(ax.spec32, lam32.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+  LOVE_HIP_TRY(hipMemcpy((float*)ax.spec32 + N, tw32.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+  ax.fft_n = N;
+  ax.fft_single = 0;
+  ax.mode = LOVE_TOEPLITZ_FFT;
+  return LOVE_OK;
 }
 
 template <typename T>
 void fft_axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
                     const Ctl* ctl, int mode, hipStream_t s) {
-  (void)c; (void)ax; (void)in; (void)out; (void)scale; (void)ctl; (void)mode; (void)s;
+  (void)c;
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute((const void*)k_fft_conv<float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 16384 * 4);
+    (void)hipFuncSetAttribute((const void*)k_fft_conv<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 8192 * 8);
+  }
+  const int N = ax.fft_n;
+  int logN = 0;
+  while ((1 << logN) < N) ++logN;
+  const T* tab = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
+  const int64_t nlines = ax.outer * ax.inner;
+  const unsigned nblk = (unsigned)cdiv(nlines, 2);
+  k_fft_conv<T><<<nblk, FFT_BLK, sizeof(T) * 2 * (size_t)N, s>>>(
+      in, out, ax.L, ax.inner, nlines, N, logN, tab + N, tab, scale, ctl, mode);
 }
 template void fft_axis_apply<float>(const love_cache*, const ToepAxis&, const float*, float*, float, const Ctl*, int, hipStream_t);
 template void fft_axis_apply<double>(const love_cache*, const ToepAxis&, const double*, double*, double, const Ctl*, int, hipStream_t);
+
+// ----------------------------------------------------------------------------
+// Autotuner: per axis shape (L, lines), time the direct and the FFT backend
+// on the device once per process (float, on a private stream) and keep the
+// faster.  LOVE_AUTOTUNE=0 switches measuring off and uses a size rule.
+// ----------------------------------------------------------------------------
+int64_t toeplitz_scratch_elems(const love_cache* c);
+template <typename T>
+void axis_apply_public(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T* scratch,
+                       hipStream_t s);
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int64_t, int64_t, int, int>, int> g_tune;
+
+int autotune_choose(love_cache* c, int e) {
+  ToepAxis ax = c->toep.ax[e];
+  const char* env = std::getenv("LOVE_AUTOTUNE");
+  const bool measure = !(env && env[0] == '0');
+  int N = 1;
+  while (N < 2 * ax.L - 1) N <<= 1;
+  if (N > fft_max_n(true)) return LOVE_TOEPLITZ_DIRECT;
+  const int64_t lines = ax.outer * ax.inner;
+  if (ax.inner != 1 && ax.L > 256) return LOVE_TOEPLITZ_FFT;   // the direct kernel covers L <= 256 here
+  if (!measure) return (ax.L >= 256 && lines >= 64) ? LOVE_TOEPLITZ_FFT : LOVE_TOEPLITZ_DIRECT;
+  // temporary plans for both backends on this axis
+  const double h = 1.0 / c->invh[e];
+  std::vector<double> col(ax.L);
+  for (int i = 0; i < ax.L; ++i)
+    col[i] = std::exp(-0.5 * (i * h / c->cfg.lengthscale[e]) * (i * h / c->cfg.lengthscale[e]));
+  if (c->cfg.kernel == LOVE_MATERN52)
+    for (int i = 0; i < ax.L; ++i) {
+      const double z = std::sqrt(5.0) * i * h / c->cfg.lengthscale[e];
+      col[i] = (1.0 + z + z * z / 3.0) * std::exp(-z);
+    }
+  int bw = ax.L - 1;
+  {
+    const double thr = 5.96e-8 * std::fabs(col[0]) / (double)ax.L;
+    while (bw > 0 && std::fabs(col[bw]) <= thr) --bw;
+  }
+  const auto key = std::make_tuple(ax.L, ax.inner, ax.outer, bw, (int)sizeof(float));
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  ToepAxis axd = ax, axf = ax;
+  axd.mode = LOVE_TOEPLITZ_DIRECT;
+  if (fft_plan_axis(c, axf, e, col) != LOVE_OK || axf.mode != LOVE_TOEPLITZ_FFT)
+    return LOVE_TOEPLITZ_DIRECT;
+  {
+    axd.bw32 = axd.bw64 = bw;
+    std::vector<float> c32(col.begin(), col.end());
+    axd.c32 = dev_alloc(c, sizeof(float) * ax.L);
+    if (!axd.c32) return LOVE_TOEPLITZ_DIRECT;
+    if (hipMemcpy(axd.c32, c32.data(), sizeof(float) * ax.L, hipMemcpyHostToDevice) != hipSuccess)
+      return LOVE_TOEPLITZ_DIRECT;
+    axf.c32 = axd.c32;
+  }
+  hipStream_t s = nullptr;
+  float *bin = nullptr, *bout = nullptr, *bscr = nullptr;
+  const int64_t mt = c->m;
+  int choice = LOVE_TOEPLITZ_DIRECT;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+      hipMalloc(&bin, sizeof(float) * mt) == hipSuccess &&
+      hipMalloc(&bout, sizeof(float) * mt) == hipSuccess &&
+      hipMalloc(&bscr, sizeof(float) * toeplitz_scratch_elems(c)) == hipSuccess) {
+    (void)hipMemsetAsync(bin, 0, sizeof(float) * mt, s);
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    float best[2] = {1e30f, 1e30f};
+    for (int which = 0; which < 2; ++which) {
+      const ToepAxis& use = which == 0 ? axd : axf;
+      for (int rep = 0; rep < 4; ++rep) {
+        (void)hipEventRecord(a, s);
+        axis_apply_public<float>(c, use, bin, bout, bscr, s);
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (rep > 0) best[which] = std::min(best[which], ms);
+      }
+    }
+    choice = best[1] < best[0] ? LOVE_TOEPLITZ_FFT : LOVE_TOEPLITZ_DIRECT;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  if (bin) (void)hipFree(bin);
+  if (bout) (void)hipFree(bout);
+  if (bscr) (void)hipFree(bscr);
+  if (s) (void)hipStreamDestroy(s);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = choice;
+  return choice;
+}
 
 }  // namespace love

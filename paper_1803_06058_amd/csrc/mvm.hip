@@ -369,6 +369,14 @@ static void axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* 
   }
 }
 
+// one axis with an explicit backend (used by the autotuner)
+template <typename T>
+void axis_apply_public(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T* scratch,
+                       hipStream_t s) {
+  axis_apply<T>(c, ax, in, out, T(1), scratch, nullptr, 0, s);
+}
+template void axis_apply_public<float>(const love_cache*, const ToepAxis&, const float*, float*, float*, hipStream_t);
+
 template <typename T>
 void toeplitz_apply(const love_cache* c, const T* in, T* out, T* scratch, const Ctl* ctl,
                     int ctl_mode, hipStream_t s) {

@@ -28,8 +28,9 @@ def host(t):
 # ---------------------------------------------------------------------------
 # Operator pieces: K_UU and Khat products
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("toeplitz", ["direct", "fft", "auto"])
 @pytest.mark.parametrize("case", ["1d_long_f32", "1d_long_f64", "1d_short_f32", "2d_f32", "4d_f64"])
-def test_apply_kuu_parity(case):
+def test_apply_kuu_parity(case, toeplitz):
     if case == "1d_long_f32":
         P = WL.config(2, scale=0.2)          # m = 2000 (long-line split-K kernel)
     elif case == "1d_long_f64":
@@ -40,8 +41,11 @@ def test_apply_kuu_parity(case):
         P = WL.config(3, scale=0.01)
     else:
         P = WL.config(4, scale=0.002, dtype="f64", precision="fp64")
-    print(case, P.m, flush=True)
-    cache = build(P, k=8, flags=B.FLAG_NO_MEAN)
+    print(case, toeplitz, P.m, flush=True)
+    cache = build(P, k=8, flags=B.FLAG_NO_MEAN, toeplitz=toeplitz)
+    info = cache.info()
+    if toeplitz == "fft":
+        assert all(info.toeplitz_mode[e] == 2 for e in range(P.d))
     spec = spec_of(P)
     g = np.random.default_rng(0).standard_normal(spec.mtot)
     dt = torch_dtype(P)
@@ -89,11 +93,11 @@ def test_config1_fp64_parity():
     cache.free()
 
 
-@pytest.mark.parametrize("scale", [0.02, 0.1])
-def test_config2_fp32_parity_small(scale):
+@pytest.mark.parametrize("scale,toeplitz", [(0.02, "auto"), (0.1, "auto"), (0.1, "fft")])
+def test_config2_fp32_parity_small(scale, toeplitz):
     P = WL.config(2, scale=scale, k_sample=0)
-    print(P.name, P.n, P.m, P.t, flush=True)
-    cache = build(P)
+    print(P.name, P.n, P.m, P.t, toeplitz, flush=True)
+    cache = build(P, toeplitz=toeplitz)
     info = cache.info()
     xs = P.xs[:20000]
     mu, var = cache.predict_mean_var(tdev(xs, torch.float32))
@@ -221,10 +225,11 @@ def test_sampler_monte_carlo():
 # ---------------------------------------------------------------------------
 # Precision form (2-D, bf16 split) and 4-D Matern
 # ---------------------------------------------------------------------------
-def test_config3_bf16split_small():
+@pytest.mark.parametrize("toeplitz", ["direct", "fft"])
+def test_config3_bf16split_small(toeplitz):
     P = WL.config(3, scale=0.01)
     print(P.name, P.n, P.m, flush=True)
-    cache = build(P)
+    cache = build(P, toeplitz=toeplitz)
     xs = P.xs[:5000]
     mu, var = cache.predict_mean_var(tdev(xs, torch.float32))
     oc = oracle_cache(P)
