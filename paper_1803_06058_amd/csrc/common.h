@@ -24,6 +24,14 @@ struct GridT {
   int64_t cstride[MAXD];   // cell strides
   int64_t mtot, ctot;
   T lo[MAXD], hi[MAXD], invh[MAXD];
+  // The training rows were sorted by stencil cell computed in float when
+  // cell_f != 0.  Every kernel then takes the stencil base from that same
+  // float computation (so W^T and W agree row by row) and only the fraction
+  // s in precision T; s may then leave [0, 1] by a float rounding of
+  // (x - lo) / h, where the cubic pieces extend smoothly (weights still sum
+  // to 1).
+  int cell_f;
+  float lo_f[MAXD], invh_f[MAXD];
 };
 
 // Keys cubic convolution weights (a = -1/2) for a point at fraction s in [0,1]
@@ -61,6 +69,18 @@ __device__ inline int stencil_base(T x, T lo, T invh, int m, T& s) {
   return (int)f;
 }
 
+// Stencil base and fraction along axis e, consistent with the cell sort.
+template <typename T>
+__device__ inline int stencil_at(const GridT<T>& g, int e, T x, T& s) {
+  if (g.cell_f) {
+    float sf;
+    const int j = stencil_base<float>((float)x, g.lo_f[e], g.invh_f[e], g.m[e], sf);
+    s = (x - g.lo[e]) * g.invh[e] - (T)j;
+    return j;
+  }
+  return stencil_base<T>(x, g.lo[e], g.invh[e], g.m[e], s);
+}
+
 template <typename T>
 __device__ inline bool in_domain(T x, T lo, T hi) {
   return x >= lo && x <= hi;   // false for NaN
@@ -93,25 +113,6 @@ __device__ inline T block_sum(T v, T* scratch /* >= 16 */) {
   T s = T(0);
   for (int i = 0; i < nw; ++i) s += scratch[i];
   return s;
-}
-
-// Last-arriving block of a grid: every block calls this after writing its
-// partial results; exactly one block (the last) gets true and may then read
-// all partials.  The counter is reset by that block.
-__device__ inline bool last_block_arrive(unsigned* counter, unsigned nblocks) {
-  __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    am_last = (prev == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (am_last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0u;
-  }
-  return am_last != 0;
 }
 
 // Status bits shared with the host (mirrors LOVE_SF_* in love.h).

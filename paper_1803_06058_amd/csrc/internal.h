@@ -115,8 +115,9 @@ template <typename T>
 GridT<T> make_grid(const love_cache* c);
 
 // `xsrc` (sorted coordinates in precision T) defaults to the cache's own copy
+// g = W^T v; with ctl_mode bit 4, g = W^T (v + ctl->ratio * v2)
 template <typename T>
-void launch_scatter(const love_cache* c, const T* v, T* g, const T* gprev, const Ctl* ctl,
+void launch_scatter(const love_cache* c, const T* v, T* g, const T* v2, const Ctl* ctl,
                     int ctl_mode, hipStream_t s, const T* xsrc = nullptr);
 
 template <typename T>

@@ -430,7 +430,7 @@ __global__ void k_rtilde(int64_t m, const T* __restrict__ R, const double* __res
 
 // ----------------------------------------------------------------------------
 // CG for the mean cache: Khat x = y.  Per iteration:
-//   scatter  g_p = W^T r + ratio * g_p        (= W^T p_new without forming p first)
+//   scatter  g_p = W^T (r + ratio * p)        (the new direction, formed on the fly)
 //   toeplitz kg = K g_p
 //   ap       p = r + ratio * p ; Ap = W kg + sigma^2 p ; partial rows of p^T Ap
 //   colsum   p^T Ap
@@ -626,13 +626,12 @@ static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
                                              wk.partial);
   k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_CG_INIT, nullptr, nullptr, nullptr,
                                 cgtol * cgtol, maxit, ctl);
-  launch_fill<double>(gv, 0.0, m, s);   // W^T p with p = 0
   Ctl hctl;
   int it = 0;
   const int chunk = 8;
   while (it < maxit) {
     for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
-      launch_scatter<double>(c, rr, gv, gv, ctl, 2 | 4, s, x64);
+      launch_scatter<double>(c, rr, gv, pp, ctl, 2 | 4, s, x64);
       toeplitz_apply<double>(c, gv, gm, tsc, ctl, 2, s);
       k_cg_ap<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, rr, pp, ap, sigma2, wk.rpb,
                                                wk.partial, ctl);

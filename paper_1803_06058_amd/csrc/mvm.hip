@@ -29,6 +29,8 @@ GridT<T> make_grid(const love_cache* c) {
       g.lo[e] = T(0);
       g.hi[e] = T(0);
       g.invh[e] = T(0);
+      g.lo_f[e] = 0.f;
+      g.invh_f[e] = 0.f;
       continue;
     }
     g.m[e] = c->mdim[e];
@@ -40,9 +42,12 @@ GridT<T> make_grid(const love_cache* c) {
     g.lo[e] = (T)c->lo[e];
     g.hi[e] = (T)c->hi[e];
     g.invh[e] = (T)c->invh[e];
+    g.lo_f[e] = (float)c->lo[e];
+    g.invh_f[e] = (float)c->invh[e];
   }
   g.mtot = ns;
   g.ctot = cs;
+  g.cell_f = c->fp64 ? 0 : 1;
   return g;
 }
 template GridT<float> make_grid<float>(const love_cache*);
@@ -54,13 +59,16 @@ template GridT<double> make_grid<double>(const love_cache*);
 // contiguous, so the rows form 4^(D-1) contiguous runs of the sorted order.
 // Lanes are split over the runs; each lane sums its rows, then the wave sums.
 // ----------------------------------------------------------------------------
+// mode bit 4: the gathered vector is v + ratio * v2 (CG direction p = r + ratio p),
+// formed on the fly so W^T p is exact for the p the next kernel writes.
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter(GridT<T> g, const T* __restrict__ x,
                                                  const T* __restrict__ v,
                                                  const int32_t* __restrict__ cell_start,
-                                                 T* __restrict__ out, const T* __restrict__ gprev,
+                                                 T* __restrict__ out, const T* __restrict__ v2,
                                                  const Ctl* ctl, int mode) {
   if (ctl_skip(ctl, mode)) return;
+  const T ratio = ((mode & 4) && v2) ? (T)ctl->ratio : T(0);
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (u >= g.mtot) return;
@@ -97,21 +105,19 @@ __global__ __launch_bounds__(256) void k_scatter(GridT<T> g, const T* __restrict
 #pragma unroll
       for (int e = 0; e < D; ++e) {
         T s;
-        const int j = stencil_base(x[(int64_t)r * D + e], g.lo[e], g.invh[e], g.m[e], s);
+        const int j = stencil_at(g, e, x[(int64_t)r * D + e], s);
         w *= keys_weight_at(ue[e] - j, s);
       }
-      acc += w * v[r];
+      const T val = ((mode & 4) && v2) ? (T)(v[r] + ratio * v2[r]) : v[r];
+      acc += w * val;
     }
   }
   acc = wave_sum(acc);
-  if (lane == 0) {
-    if ((mode & 4) && gprev) acc += (T)ctl->ratio * gprev[u];
-    out[u] = acc;
-  }
+  if (lane == 0) out[u] = acc;
 }
 
 template <typename T>
-void launch_scatter(const love_cache* c, const T* v, T* gout, const T* gprev, const Ctl* ctl,
+void launch_scatter(const love_cache* c, const T* v, T* gout, const T* v2, const Ctl* ctl,
                     int ctl_mode, hipStream_t s, const T* xsrc) {
   ProfScope ps("scatter", s);
   GridT<T> g = make_grid<T>(c);
@@ -119,10 +125,10 @@ void launch_scatter(const love_cache* c, const T* v, T* gout, const T* gprev, co
   dim3 grid((unsigned)cdiv(c->m, wpb));
   const T* x = xsrc ? xsrc : (const T*)c->x;
   switch (c->d) {
-    case 1: k_scatter<T, 1><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
-    case 2: k_scatter<T, 2><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
-    case 3: k_scatter<T, 3><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
-    case 4: k_scatter<T, 4><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, gprev, ctl, ctl_mode); break;
+    case 1: k_scatter<T, 1><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
+    case 2: k_scatter<T, 2><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
+    case 3: k_scatter<T, 3><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
+    case 4: k_scatter<T, 4><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
   }
 }
 template void launch_scatter<float>(const love_cache*, const float*, float*, const float*, const Ctl*, int, hipStream_t, const float*);

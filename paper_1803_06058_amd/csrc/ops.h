@@ -34,7 +34,7 @@ __device__ inline T gather_row_dev(const GridT<T>& g, const T* __restrict__ x, i
 #pragma unroll
   for (int e = 0; e < D; ++e) {
     T s;
-    const int j = stencil_base(x[r * D + e], g.lo[e], g.invh[e], g.m[e], s);
+    const int j = stencil_at(g, e, x[r * D + e], s);
     keys_weights(s, w[e]);
     base += (int64_t)j * g.nstride[e];
   }

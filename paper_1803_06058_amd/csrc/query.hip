@@ -42,7 +42,7 @@ __device__ inline bool point_stencil(const GridT<T>& g, const T* __restrict__ xp
     ok = ok && in_domain(xe, g.lo[e], g.hi[e]);
     if (!(xe == xe)) xe = g.lo[e];
     T s;
-    const int j = stencil_base(xe, g.lo[e], g.invh[e], g.m[e], s);
+    const int j = stencil_at(g, e, xe, s);
     T wt[4];
     keys_weights(s, wt);
 #pragma unroll

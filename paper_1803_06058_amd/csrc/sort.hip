@@ -33,7 +33,7 @@ __global__ void k_cells(GridT<T> g, const T* __restrict__ x, const T* __restrict
     if (!in_domain(xe, g.lo[e], g.hi[e])) bad |= SF_DOMAIN;
     if (!(xe == xe)) xe = g.lo[e];
     T s;
-    int j = stencil_base(xe, g.lo[e], g.invh[e], g.m[e], s);
+    int j = stencil_at(g, e, xe, s);
     cell += (int64_t)j * g.cstride[e];
   }
   T yi = y[i];
