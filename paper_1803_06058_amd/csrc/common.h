@@ -134,8 +134,8 @@ struct Ctl {
   double amax;       // running max |alpha|
   double rr;         // CG: current r^T r
   double rr0;        // CG: ||y||^2
-  double gamma;      // CG: step
-  double ratio;      // CG: rr_new / rr_old (direction update)
+  double rz;         // CG: current r^T M^{-1} r (preconditioned)
+  double ratio;      // CG: rz_new / rz_old (direction update)
   double bnorm;      // probe norm
 };
 

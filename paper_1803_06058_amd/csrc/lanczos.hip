@@ -61,13 +61,11 @@ static void launch_colsum(const double* partial, int nb, int nv, double* out, hi
 }
 
 // Column sums in one block followed by a scalar epilogue on thread 0.
-enum : int { EP_NONE = 0, EP_BNORM = 1, EP_TRISOLVE = 2, EP_CG_INIT = 3, EP_CG_STEP = 4 };
+enum : int { EP_NONE = 0, EP_BNORM = 1 };
 
 __global__ __launch_bounds__(BLK) void k_colsum_ep(const double* __restrict__ partial, int nb,
                                                    int nv, int ep, double* __restrict__ out,
-                                                   const double* __restrict__ ldiag,
-                                                   const double* __restrict__ lsub, double tol2,
-                                                   int maxit, Ctl* ctl) {
+                                                   Ctl* ctl) {
   __shared__ double sums[LDP];
   const int w = threadIdx.x / WAVE;
   for (int c = w; c < nv; c += BLK / WAVE) {
@@ -80,41 +78,6 @@ __global__ __launch_bounds__(BLK) void k_colsum_ep(const double* __restrict__ pa
     for (int c = 0; c < nv; ++c) out[c] = sums[c];
   } else if (ep == EP_BNORM) {
     ctl->bnorm = sqrt(sums[0]);
-  } else if (ep == EP_TRISOLVE) {
-    // T z = Q^T y with T = L L^T (bidiagonal L): forward then backward substitution
-    const int k = min(ctl->k_eff, nv - 1);
-    double zz[MAXK];
-    for (int i = 0; i < k; ++i) {
-      const double t = sums[i] - (i > 0 ? lsub[i - 1] * zz[i - 1] : 0.0);
-      zz[i] = t / ldiag[i];
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      const double t = zz[i] - (i + 1 < k ? lsub[i] * zz[i + 1] : 0.0);
-      zz[i] = t / ldiag[i];
-    }
-    for (int i = 0; i < k; ++i) out[i] = zz[i];
-    for (int i = k; i < nv - 1; ++i) out[i] = 0.0;
-    ctl->rr0 = sums[nv - 1];
-  } else if (ep == EP_CG_INIT) {
-    ctl->rr = sums[0];
-    ctl->ratio = 0.0;
-    ctl->cg_iters = 0;
-    ctl->cg_done = (sums[0] > tol2 * ctl->rr0) ? 0 : 1;
-  } else if (ep == EP_CG_STEP) {
-    if (ctl->cg_done) return;
-    const double rrn = sums[0];
-    ctl->ratio = rrn / ctl->rr;
-    ctl->rr = rrn;
-    ctl->cg_iters += 1;
-    if (!(rrn > tol2 * ctl->rr0)) ctl->cg_done = 1;
-    else if (ctl->cg_iters >= maxit) {
-      ctl->cg_done = 1;
-      ctl->status |= SF_CG_NOCONV;
-    }
-    if (!isfinite(rrn)) {
-      ctl->cg_done = 1;
-      ctl->status |= SF_NONFINITE;
-    }
   }
 }
 
@@ -345,23 +308,6 @@ __global__ void k_scale_by_bnorm(int64_t n, const T* __restrict__ v, T* __restri
   out[i] = (T)((double)v[i] / b);
 }
 
-// x0 = Q z (first k_eff columns)
-template <typename T, typename TO>
-__global__ __launch_bounds__(BLK) void k_q_times(int64_t n, const T* __restrict__ Q, int64_t ldq,
-                                                 const double* __restrict__ z,
-                                                 TO* __restrict__ out, const Ctl* ctl) {
-  __shared__ double zl[MAXK];
-  const int k = ctl->k_eff;
-  for (int c = threadIdx.x; c < k; c += BLK) zl[c] = z[c];
-  __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (row >= n) return;
-  double acc = 0.0;
-#pragma unroll 16
-  for (int c = 0; c < k; ++c) acc += (double)Q[(int64_t)c * ldq + row] * zl[c];
-  out[row] = (TO)acc;
-}
-
 // Cholesky of the tridiagonal T (alpha, beta) of size ctl->k_eff (one thread).
 // A non-positive pivot truncates k_eff there (SF_NOTPD, or SF_SAMPLER_TRUNC
 // when `sampler`).  rel_tol: a pivot must exceed rel_tol * max|alpha|.
@@ -429,17 +375,35 @@ __global__ void k_rtilde(int64_t m, const T* __restrict__ R, const double* __res
 }
 
 // ----------------------------------------------------------------------------
-// CG for the mean cache: Khat x = y.  Per iteration:
-//   scatter  g_p = W^T (r + ratio * p)        (the new direction, formed on the fly)
+// Mean cache: preconditioned CG on Khat x = y (double vectors).
+//
+// Preconditioner from the Lanczos decomposition Khat Q ~ Q T that the build
+// already holds (Sec. 2.2; the Lanczos solve Q T^{-1} Q^T b of eq.
+// lanczos_solve is its action on span(Q)):
+//   M^{-1} = Q T^{-1} Q^T + (I - Q Q^T)^2 / sigma^2
+//          = I / sigma^2 + Q C Q^T,   C = T^{-1} - (2 I - G) / sigma^2,  G = Q^T Q.
+// Both terms are positive semidefinite and their null spaces meet only in 0,
+// so M^{-1} is positive definite for any Q (also when the float Lanczos
+// vectors are orthonormal only to ~1e-7); on span(Q) it inverts T, and on the
+// rest Khat is sigma^2 I plus the spectrum the Lanczos run did not reach.
+// With c = Q^T r and d = C c, z = M^{-1} r = r / sigma^2 + Q d and
+// r^T z = r^T r / sigma^2 + c^T d, so no extra pass is needed for r^T z.
+// Per iteration:
+//   scatter  g_p = W^T (z + ratio * p)         (new direction, formed on the fly)
 //   toeplitz kg = K g_p
-//   ap       p = r + ratio * p ; Ap = W kg + sigma^2 p ; partial rows of p^T Ap
-//   colsum   p^T Ap
-//   update   gamma = rr / p^T Ap ; x += gamma p ; r -= gamma Ap ; partial rows of r^T r
-//   colsum + epilogue: ratio = rr_new / rr, convergence test
+//   ap       p = z + ratio * p ; Ap = W kg + sigma^2 p ; partial rows of p^T Ap
+//   update   gamma = rz / p^T Ap ; x += gamma p ; r -= gamma Ap ;
+//            partial rows of [Q^T r, r^T r]
+//   colsum   c, r^T r
+//   pcg_ep   convergence test; d = C c ; rz_new ; ratio = rz_new / rz
+//   apply    z = r / sigma^2 + Q d
+// With the identity preconditioner (plain CG) c and d are empty and z = r.
 // ----------------------------------------------------------------------------
+constexpr int PAP_COL = LDP - 1;   // partial-row column of p^T Ap (clear of the dot columns)
+
 template <typename T, int D>
 __global__ __launch_bounds__(BLK) void k_cg_ap(GridT<T> g, const T* __restrict__ x, int64_t n,
-                                               const T* __restrict__ kg, const T* __restrict__ r,
+                                               const T* __restrict__ kg, const T* __restrict__ z,
                                                T* __restrict__ p, T* __restrict__ ap, T sigma2,
                                                int rpb, double* __restrict__ partial,
                                                const Ctl* ctl) {
@@ -451,69 +415,257 @@ __global__ __launch_bounds__(BLK) void k_cg_ap(GridT<T> g, const T* __restrict__
   for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
     const int64_t row = r0 + rr;
     if (row >= n) break;
-    const T pn = (T)((double)r[row] + ratio * (double)p[row]);
+    const T pn = (T)((double)z[row] + ratio * (double)p[row]);
     p[row] = pn;
     const T a = gather_row_dev<T, D>(g, x, row, kg) + sigma2 * pn;
     ap[row] = a;
     d += (double)pn * (double)a;
   }
   const double db = block_sum(d, scr);
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP + PAP_COL] = db;
 }
 
-// gamma = rr / p^T Ap, with p^T Ap summed by every block from the partial
-// rows of k_cg_ap (a few hundred doubles, one wave, fixed order).
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_cg_update(int64_t n, T* __restrict__ xs,
-                                                   T* __restrict__ r, const T* __restrict__ p,
-                                                   const T* __restrict__ ap,
-                                                   const double* __restrict__ pap_partial, int nb,
-                                                   int rpb, double* __restrict__ partial,
-                                                   const Ctl* ctl) {
+// Stage the block's new residual rows in LDS, then partial rows of
+// [q_0^T r, ..., q_{kq-1}^T r, r^T r] (columns past k_eff written as 0).
+template <typename TQ>
+__device__ inline void pcg_block_dots(const double* rl, double ssb, const TQ* __restrict__ Q,
+                                      int64_t ldq, int kq, int64_t r0, int nrows,
+                                      double* __restrict__ prow, const Ctl* ctl) {
+  const int ncols = min(kq, ctl->k_eff);
+  if (ncols > 0) block_dots(Q, ldq, ncols, r0, nrows, rl, prow);
+  for (int c = max(ncols, 0) + threadIdx.x; c < kq; c += BLK) prow[c] = 0.0;
+  if (threadIdx.x == 0) prow[kq] = ssb;
+}
+
+// x = 0, r = y, p = 0, partial rows of [Q^T y, y^T y]
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const double* __restrict__ y,
+                                                  double* __restrict__ xs, double* __restrict__ r,
+                                                  double* __restrict__ p,
+                                                  const TQ* __restrict__ Q, int64_t ldq, int kq,
+                                                  int rpb, double* __restrict__ partial,
+                                                  const Ctl* ctl) {
+  extern __shared__ double rl[];
+  __shared__ double scr[16];
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  double d = 0.0;
+  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
+    const int64_t row = r0 + rr;
+    double v = 0.0;
+    if (row < n) {
+      v = y[row];
+      xs[row] = 0.0;
+      r[row] = v;
+      p[row] = 0.0;
+    }
+    rl[rr] = v;
+    d += v * v;
+  }
+  const double ssb = block_sum(d, scr);
+  __syncthreads();
+  const int nrows = (int)min<int64_t>(rpb, n - r0);
+  pcg_block_dots(rl, ssb, Q, ldq, kq, r0, nrows, partial + (size_t)blockIdx.x * LDP, ctl);
+}
+
+// gamma = rz / p^T Ap (p^T Ap re-summed by every block from the partial rows
+// of k_cg_ap, one wave, fixed order); x += gamma p ; r -= gamma Ap ; dots.
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_update(int64_t n, double* __restrict__ xs,
+                                                    double* __restrict__ r,
+                                                    const double* __restrict__ p,
+                                                    const double* __restrict__ ap, int nb,
+                                                    const TQ* __restrict__ Q, int64_t ldq, int kq,
+                                                    int rpb, double* __restrict__ partial,
+                                                    const Ctl* ctl) {
   if (ctl->cg_done) return;
+  extern __shared__ double rl[];
   __shared__ double scr[16];
   __shared__ double s_pap;
   if (threadIdx.x < WAVE) {
-    const double sum = colsum_wave(pap_partial, nb, 0);
+    const double sum = colsum_wave(partial, nb, PAP_COL);
     if (threadIdx.x == 0) s_pap = sum;
   }
   __syncthreads();
-  const double gm = ctl->rr / s_pap;
-  double d = 0.0;
+  const double gm = ctl->rz / s_pap;
   const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  double d = 0.0;
   for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
     const int64_t row = r0 + rr;
-    if (row >= n) break;
-    xs[row] = (T)((double)xs[row] + gm * (double)p[row]);
-    const T rn = (T)((double)r[row] - gm * (double)ap[row]);
-    r[row] = rn;
-    d += (double)rn * (double)rn;
+    double v = 0.0;
+    if (row < n) {
+      xs[row] += gm * p[row];
+      v = r[row] - gm * ap[row];
+      r[row] = v;
+    }
+    rl[rr] = v;
+    d += v * v;
   }
-  const double db = block_sum(d, scr);
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
+  const double ssb = block_sum(d, scr);
+  __syncthreads();
+  const int nrows = (int)min<int64_t>(rpb, n - r0);
+  pcg_block_dots(rl, ssb, Q, ldq, kq, r0, nrows, partial + (size_t)blockIdx.x * LDP, ctl);
 }
 
-// r = y - A x0 ; p = 0 ; partial rows of r^T r
-template <typename T, int D>
-__global__ __launch_bounds__(BLK) void k_cg_init(GridT<T> g, const T* __restrict__ x, int64_t n,
-                                                 const T* __restrict__ kg, const T* __restrict__ y,
-                                                 const T* __restrict__ x0, T* __restrict__ r,
-                                                 T* __restrict__ p, T sigma2, int rpb,
-                                                 double* __restrict__ partial) {
+// One block.  sums = [c_0 .. c_{kq-1}, r^T r] (column sums of the update's
+// partial rows).  Convergence test on ||r|| <= tol ||y||, then d = C c,
+// rz = r^T r * rscale + c^T d and the direction ratio.  init: first call
+// (sets ||y||^2, ratio 0).
+__global__ __launch_bounds__(BLK) void k_pcg_ep(const double* __restrict__ sums, int kq,
+                                                const double* __restrict__ C, int ldc,
+                                                double* __restrict__ dout, double rscale,
+                                                double tol2, int maxit, int init, Ctl* ctl) {
+  if (ctl->cg_done) return;
+  __shared__ double cl[MAXK];
   __shared__ double scr[16];
-  double d = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    if (row >= n) break;
-    const T ax = gather_row_dev<T, D>(g, x, row, kg) + sigma2 * x0[row];
-    const T rv = (T)((double)y[row] - (double)ax);
-    r[row] = rv;
-    p[row] = T(0);
-    d += (double)rv * (double)rv;
+  const int k = min(kq, ctl->k_eff);
+  const int t = threadIdx.x;
+  if (t < k) cl[t] = sums[t];
+  __syncthreads();
+  double cd = 0.0;
+  if (t < k) {
+    double acc = 0.0;
+    const double* row = C + (size_t)t * ldc;
+    for (int j = 0; j < k; ++j) acc += row[j] * cl[j];
+    dout[t] = acc;
+    cd = cl[t] * acc;
   }
-  const double db = block_sum(d, scr);
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP] = db;
+  const double cdb = block_sum(cd, scr);
+  if (t != 0) return;
+  const double rr = sums[kq];
+  if (init) {
+    ctl->rr0 = rr;
+    ctl->cg_iters = 0;
+  } else {
+    ctl->cg_iters += 1;
+  }
+  ctl->rr = rr;
+  const double rz = rr * rscale + cdb;
+  if (!isfinite(rr) || !isfinite(rz)) {
+    ctl->cg_done = 1;
+    ctl->status |= SF_NONFINITE;
+    return;
+  }
+  if (!(rr > tol2 * ctl->rr0)) {
+    ctl->cg_done = 1;
+    return;
+  }
+  if (!init && ctl->cg_iters >= maxit) {
+    ctl->cg_done = 1;
+    ctl->status |= SF_CG_NOCONV;
+    return;
+  }
+  if (!(rz > 0.0)) {   // cannot happen for a positive definite M^{-1}; stop cleanly
+    ctl->cg_done = 1;
+    ctl->status |= SF_CG_NOCONV;
+    return;
+  }
+  ctl->ratio = init ? 0.0 : rz / ctl->rz;
+  ctl->rz = rz;
+}
+
+// z = r * rscale + Q d  (first min(kq, k_eff) columns)
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_apply(int64_t n, const double* __restrict__ r,
+                                                   const TQ* __restrict__ Q, int64_t ldq, int kq,
+                                                   const double* __restrict__ dv, double rscale,
+                                                   double* __restrict__ z, const Ctl* ctl) {
+  if (ctl->cg_done) return;
+  __shared__ double dl[MAXK];
+  const int k = min(kq, ctl->k_eff);
+  for (int c = threadIdx.x; c < k; c += BLK) dl[c] = dv[c];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (row >= n) return;
+  double acc = r[row] * rscale;
+#pragma unroll 16
+  for (int c = 0; c < k; ++c) acc += (double)Q[(int64_t)c * ldq + row] * dl[c];
+  z[row] = acc;
+}
+
+// Gram matrix G = Q^T Q of the first k_eff columns, in double: per-block
+// partial kpad x kpad matrices over row slices.  Thread (ti, tj) of a 16 x 16
+// layout owns entries (ti + 16a, tj + 16b), a, b < NA = kpad / 16; rows are
+// staged through LDS in tiles of GR_TR.
+constexpr int GR_TR = 32;
+template <typename TQ, int NA>
+__global__ __launch_bounds__(256) void k_gram(int64_t n, const TQ* __restrict__ Q, int64_t ldq,
+                                              int64_t rpb, double* __restrict__ pg,
+                                              const Ctl* ctl) {
+  constexpr int KP = 16 * NA;
+  __shared__ double tile[GR_TR][KP + 1];
+  const int t = threadIdx.x, ti = t / 16, tj = t % 16;
+  const int k = ctl->k_eff;
+  double acc[NA][NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NA; ++b) acc[a][b] = 0.0;
+  const int64_t rb = (int64_t)blockIdx.x * rpb;
+  const int64_t re = min<int64_t>(rb + rpb, n);
+  for (int64_t r0 = rb; r0 < re; r0 += GR_TR) {
+    for (int e = t; e < GR_TR * KP; e += 256) {
+      const int rr = e % GR_TR, cc = e / GR_TR;
+      const int64_t row = r0 + rr;
+      tile[rr][cc] = (row < re && cc < k) ? (double)Q[(int64_t)cc * ldq + row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < GR_TR; ++rr) {
+      double qi[NA], qj[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) qi[a] = tile[rr][ti + 16 * a];
+#pragma unroll
+      for (int b = 0; b < NA; ++b) qj[b] = tile[rr][tj + 16 * b];
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NA; ++b) acc[a][b] += qi[a] * qj[b];
+    }
+    __syncthreads();
+  }
+  double* out = pg + (size_t)blockIdx.x * KP * KP;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NA; ++b) out[(size_t)(ti + 16 * a) * KP + tj + 16 * b] = acc[a][b];
+}
+
+// T^{-1} from T = L L^T (bidiagonal L): thread i solves T x = e_i.
+__global__ void k_tinv(const double* __restrict__ ldiag, const double* __restrict__ lsub,
+                       double* __restrict__ tinv, int kpad, const Ctl* ctl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kpad) return;
+  const int k = ctl->k_eff;
+  double* col = tinv + (size_t)i * kpad;
+  for (int j = 0; j < kpad; ++j) col[j] = 0.0;
+  if (i >= k) return;
+  // forward: L w = e_i (w_j = 0 for j < i)
+  double w = 1.0 / ldiag[i];
+  col[i] = w;
+  for (int j = i + 1; j < k; ++j) {
+    w = -lsub[j - 1] * w / ldiag[j];
+    col[j] = w;
+  }
+  // backward: L^T x = w
+  double xn = col[k - 1] / ldiag[k - 1];
+  col[k - 1] = xn;
+  for (int j = k - 2; j >= 0; --j) {
+    xn = (col[j] - lsub[j] * xn) / ldiag[j];
+    col[j] = xn;
+  }
+}
+
+// C = T^{-1} - (2 I - G) / sigma^2 with G summed from the k_gram partials in
+// block order.
+__global__ void k_pcg_matrix(const double* __restrict__ pg, int nbg, const double* __restrict__ tinv,
+                             double* __restrict__ cm, int kpad, double inv_s2, const Ctl* ctl) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kpad * kpad) return;
+  const int i = e / kpad, j = e % kpad;
+  const int k = ctl->k_eff;
+  double gsum = 0.0;
+  for (int b = 0; b < nbg; ++b) gsum += pg[(size_t)b * kpad * kpad + e];
+  cm[e] = (i < k && j < k) ? tinv[e] - ((i == j ? 2.0 : 0.0) - gsum) * inv_s2 : 0.0;
 }
 
 __global__ void k_ctl_init(Ctl* ctl) {
@@ -570,21 +722,27 @@ static void set_smem_limits() {
 // double whatever the cache precision: in float the true residual of CG
 // stalls at ~1e-3 relative on the 1e5-point workload (rounding of the
 // operator's float sums times its condition number ~1e5), which leaves the
-// mean wrong in the third digit.  CG starts from the Lanczos solve
-// x0 = Q T^{-1} Q^T y (eq. lanczos_solve).
+// mean wrong in the third digit.  Preconditioned by the Lanczos
+// decomposition unless LOVE_FLAG_PLAIN_CG.
 template <typename T, int D>
 static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
                               std::vector<void*>& tmp, hipStream_t s) {
   ProfScope ps("mean_cg", s);
   const int64_t n = c->n, m = c->m;
-  const int k = c->k;
+  const bool plain = (c->cfg.flags & LOVE_FLAG_PLAIN_CG) != 0;
+  const int kq = plain ? 0 : c->k;          // preconditioner columns (<= k_eff at run time)
+  const int kpad = c->kpad;
   const unsigned nbr = (unsigned)cdiv(n, BLK);
+  const int nbg = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(n, 128)));
+  const int64_t rpbg = cdiv(n, (int64_t)nbg);
   Ctl* ctl = c->ctl;
-  double *x64, *y64, *xs, *rr, *pp, *ap, *gv, *gm, *tsc;
+  double *x64, *y64, *xs, *rr, *zz, *pp, *ap, *gv, *gm, *tsc, *pg = nullptr, *tinv = nullptr,
+                                                              *cm = nullptr;
   {
     const bool own = sizeof(T) != 8;
-    size_t bytes = sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 4 * (size_t)ldq +
-                                     2 * (size_t)m + (size_t)toeplitz_scratch_elems(c));
+    const size_t pre = plain ? 0 : ((size_t)nbg + 2) * kpad * kpad;
+    size_t bytes = sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 5 * (size_t)ldq +
+                                     2 * (size_t)m + (size_t)toeplitz_scratch_elems(c) + pre);
     char* p = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
     tmp.push_back(p);
@@ -601,44 +759,52 @@ static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
     }
     xs = q;
     rr = xs + ldq;
-    pp = rr + ldq;
+    zz = rr + ldq;
+    pp = zz + ldq;
     ap = pp + ldq;
     gv = ap + ldq;
     gm = gv + m;
     tsc = gm + m;
+    if (!plain) {
+      pg = tsc + toeplitz_scratch_elems(c);
+      tinv = pg + (size_t)nbg * kpad * kpad;
+      cm = tinv + (size_t)kpad * kpad;
+    }
   }
   GridT<double> g = make_grid<double>(c);
   const double sigma2 = c->cfg.noise;
-  const bool plain = (c->cfg.flags & LOVE_FLAG_PLAIN_CG) != 0;
+  const double rscale = plain ? 1.0 : 1.0 / sigma2;
   const double cgtol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
+  const double tol2 = cgtol * cgtol;
   const int maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
-  // jump start: z = T^{-1} Q^T y, x0 = Q z (float Q, double z and x0)
-  const T* yT = (const T*)c->y;
-  const int kk = plain ? 0 : k;
-  k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, yT, Q, ldq, kk, 1, wk.rpb, wk.partial, ctl);
-  k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, kk + 1, EP_TRISOLVE, wk.coef, wk.ldiag, wk.lsub,
-                                0.0, 0, ctl);
-  if (plain) launch_fill<double>(xs, 0.0, n, s);
-  else k_q_times<T, double><<<nbr, BLK, 0, s>>>(n, Q, ldq, wk.coef, xs, ctl);
-  launch_scatter<double>(c, xs, gv, nullptr, nullptr, 0, s, x64);
-  toeplitz_apply<double>(c, gv, gm, tsc, nullptr, 0, s);
-  k_cg_init<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, y64, xs, rr, pp, sigma2, wk.rpb,
-                                             wk.partial);
-  k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_CG_INIT, nullptr, nullptr, nullptr,
-                                cgtol * cgtol, maxit, ctl);
+  const size_t shm = sizeof(double) * (size_t)wk.rpb;
+  if (!plain) {
+    if (kpad == 64)
+      k_gram<T, 4><<<nbg, 256, 0, s>>>(n, Q, ldq, rpbg, pg, ctl);
+    else
+      k_gram<T, 8><<<nbg, 256, 0, s>>>(n, Q, ldq, rpbg, pg, ctl);
+    k_tinv<<<1, kpad, 0, s>>>(wk.ldiag, wk.lsub, tinv, kpad, ctl);
+    k_pcg_matrix<<<(unsigned)cdiv(kpad * kpad, 256), 256, 0, s>>>(pg, nbg, tinv, cm, kpad,
+                                                                   1.0 / sigma2, ctl);
+  }
+  k_pcg_init<T><<<wk.nb, BLK, shm, s>>>(n, y64, xs, rr, pp, Q, ldq, kq, wk.rpb, wk.partial, ctl);
+  launch_colsum(wk.partial, wk.nb, kq + 1, wk.coef, s);
+  k_pcg_ep<<<1, BLK, 0, s>>>(wk.coef, kq, cm, kpad, wk.c2, rscale, tol2, maxit, 1, ctl);
+  k_pcg_apply<T><<<nbr, BLK, 0, s>>>(n, rr, Q, ldq, kq, wk.c2, rscale, zz, ctl);
   Ctl hctl;
   int it = 0;
-  const int chunk = 8;
+  const int chunk = plain ? 8 : 4;
   while (it < maxit) {
     for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
-      launch_scatter<double>(c, rr, gv, pp, ctl, 2 | 4, s, x64);
+      launch_scatter<double>(c, zz, gv, pp, ctl, 2 | 4, s, x64);
       toeplitz_apply<double>(c, gv, gm, tsc, ctl, 2, s);
-      k_cg_ap<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, rr, pp, ap, sigma2, wk.rpb,
+      k_cg_ap<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, zz, pp, ap, sigma2, wk.rpb,
                                                wk.partial, ctl);
-      k_cg_update<double><<<wk.nb, BLK, 0, s>>>(n, xs, rr, pp, ap, wk.partial, wk.nb, wk.rpb,
-                                                wk.partial + 1, ctl);
-      k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial + 1, wk.nb, 1, EP_CG_STEP, nullptr, nullptr,
-                                    nullptr, cgtol * cgtol, maxit, ctl);
+      k_pcg_update<T><<<wk.nb, BLK, shm, s>>>(n, xs, rr, pp, ap, wk.nb, Q, ldq, kq, wk.rpb,
+                                              wk.partial, ctl);
+      launch_colsum(wk.partial, wk.nb, kq + 1, wk.coef, s);
+      k_pcg_ep<<<1, BLK, 0, s>>>(wk.coef, kq, cm, kpad, wk.c2, rscale, tol2, maxit, 0, ctl);
+      k_pcg_apply<T><<<nbr, BLK, 0, s>>>(n, rr, Q, ldq, kq, wk.c2, rscale, zz, ctl);
     }
     LOVE_HIP_TRY(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     LOVE_HIP_TRY(hipStreamSynchronize(s));
@@ -695,8 +861,7 @@ static love_status lanczos_impl(love_cache* c, hipStream_t s, hipStream_t s_side
     toeplitz_apply<T>(c, gv, gm, tsc, nullptr, 0, s);
     launch_gather<T>(c, gm, nullptr, T(0), v, nullptr, s);
     k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
-    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, nullptr, nullptr, 0.0, 0,
-                                  ctl);
+    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, ctl);
     k_scale_by_bnorm<T><<<nbr, BLK, 0, s>>>(n, v, Q, ctl);
   }
   const double tol = c->tol_lanczos;
@@ -1080,8 +1245,7 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq,
                                                       0, v, wk.rpb, wk.partial, ctl);
     k_dots<double><<<wk.nb, BLK, shm, s>>>(m, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
-    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, nullptr, nullptr, 0.0,
-                                  0, ctl);
+    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, ctl);
     k_scale_by_bnorm<double><<<nbm, BLK, 0, s>>>(m, v, Q, ctl);
   }
   const double tol = 1e-12;
