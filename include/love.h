@@ -15,8 +15,10 @@
  *                       R^T R' = Rt Rt^T, so one gather serves both factors.
  *   mean cache          a = K W^T Khat^{-1} y (Sec. 2.3, eq. pred_mean_ski)
  *   variance            var(x*) = w*^T K w* - ||Rt^T w*||^2 (eq. pred_covar_ski_fast, i = j)
- *   sampling            S = Q' L_{T'} from Lanczos on K - R^T R' (Sec. 3.3,
- *                       eqs. lancapprox, pred_covar_ski_interp_form);
+ *   sampling            S = Q' V Lambda_+^{1/2} from Lanczos on K - R^T R' and
+ *                       T' = V Lambda V^T (Sec. 3.3, eqs. lancapprox,
+ *                       pred_covar_ski_interp_form; S S^T = Q' T' Q'^T when T'
+ *                       is positive semidefinite);
  *                       sample = mu(X*) + W_{X*} S z (eq. sample)
  *
  * Conventions shared by every entry point
@@ -85,7 +87,8 @@ typedef enum {
 /* Flags (love_config.flags) */
 #define LOVE_FLAG_ASYNC 1u          /* build does not synchronise at its end                     */
 #define LOVE_FLAG_NO_MEAN 2u        /* skip the mean cache a                                      */
-#define LOVE_FLAG_PLAIN_CG 4u       /* mean solve starts CG from 0 instead of the Lanczos solve */
+#define LOVE_FLAG_PLAIN_CG 4u       /* mean solve: CG without the Lanczos preconditioner         */
+#define LOVE_FLAG_EIG_QL 8u         /* sampler: eigenvectors of T' by implicit QL (slow path)     */
 
 typedef struct {
   int32_t d;                        /* input dimension, 1..4                                     */
@@ -115,7 +118,7 @@ typedef struct love_cache love_cache;   /* opaque */
 #define LOVE_SF_NOTPD 4u            /* T not positive definite; k_eff truncated at the first bad pivot */
 #define LOVE_SF_BREAKDOWN 8u        /* Lanczos stopped early (invariant subspace); not an error   */
 #define LOVE_SF_CG_NOCONV 16u       /* mean CG hit cg_maxit                                        */
-#define LOVE_SF_SAMPLER_TRUNC 32u   /* T' Cholesky truncated at a non-positive pivot              */
+#define LOVE_SF_SAMPLER_TRUNC 32u   /* T' had non-positive eigenvalues, clipped to zero           */
 
 typedef struct {
   int32_t k_eff;                    /* Lanczos steps kept                                         */

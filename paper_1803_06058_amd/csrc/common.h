@@ -130,7 +130,8 @@ struct Ctl {
   int cg_done;       // CG converged (or failed)
   int cg_iters;
   unsigned status;   // SF_* bits
-  int k_chol;        // sampler: PD leading block of T'
+  int k_chol;        // sampler: number of positive eigenvalues of T'
+  int eig_fallback;  // sampler: eigenvectors must come from the QL solver
   double amax;       // running max |alpha|
   double rr;         // CG: current r^T r
   double rr0;        // CG: ||y||^2

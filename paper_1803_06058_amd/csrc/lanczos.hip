@@ -1028,15 +1028,205 @@ __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* 
 }
 
 // Eigen-decomposition T' = V diag(lam) V^T of the sampler's symmetric
-// tridiagonal (k' <= 128) by implicit QL with Wilkinson shifts (Bowdler,
-// Martin, Reinsch and Wilkinson, 1968).  One wave does everything: lane i
-// holds d[i], d[i+64], e[i], e[i+64] in registers; the scalar chase runs
-// uniformly on all lanes (values fetched with readlane), and every plane
-// rotation is applied at once to the lane's two rows of V (held in LDS), the
-// updated column carried in registers.  Eigenpairs are returned sorted by
-// decreasing eigenvalue; k_chol counts the strictly positive ones (negative
-// Ritz values of K - Rt Rt^T come from rounding of the float cache and are
-// clipped to zero).
+// tridiagonal (k' <= 128), returned sorted by decreasing eigenvalue in
+// vout (column c at vout[c * MAXK + row]) and lam.  k_chol counts the strictly
+// positive eigenvalues: negative Ritz values of K - Rt Rt^T come from the
+// rounding of the float cache and are clipped to zero.
+//
+// Fast path, parallel over eigenvalues:
+//  * eigenvalues by multisection of Sturm counts (the count of negative
+//    pivots of the LDL^T factorisation of T' - x I is the number of
+//    eigenvalues below x): one wave per eigenvalue index, its 64 lanes count
+//    at 64 interior points of the current bracket, so each round narrows the
+//    bracket 65-fold; ten rounds take the Gershgorin interval to rounding
+//    level;
+//  * eigenvectors by a twisted factorisation (one lane per eigenvalue):
+//    forward and backward LDL^T of T' - lam I give
+//    gamma_r = D+_r + D-_r - (alpha_r - lam); with r = argmin |gamma_r|, z_r = 1
+//    and the two one-term recurrences outward from r solve
+//    (T' - lam I) z = gamma_r e_r.  The error of z is ~ eps ||T'|| / gap.
+// What matters downstream is V Lambda V^T, to which an eigenvalue lam
+// contributes lam * z z^T; so when a neighbour of a non-negligible eigenvalue
+// (lam > 1e-9 ||T'||) is closer than 1e-6 lam, or a vector is not finite, the
+// fast path hands over to the implicit QL solver below, whose eigenvectors
+// are orthogonal to rounding whatever the gaps.
+constexpr int EIG_ROUNDS = 10;
+
+__device__ inline int sturm_count(const double* a, const double* b2, int k, double x,
+                                  double pivmin) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < k; ++i) {
+    q = (a[i] - x) - b2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Gershgorin interval [gl, gu] of T' and the pivot floor, per thread (k steps).
+__device__ inline void tri_bounds(const double* a, const double* b, int k, double& gl, double& gu,
+                                  double& pivmin) {
+  gl = 1e300;
+  gu = -1e300;
+  double bmax2 = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double off = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
+    gl = fmin(gl, a[i] - off);
+    gu = fmax(gu, a[i] + off);
+    if (i + 1 < k) bmax2 = fmax(bmax2, b[i] * b[i]);
+  }
+  pivmin = 2.2250738585072014e-308 * fmax(1.0, bmax2);
+  const double tn = fmax(fabs(gl), fabs(gu));
+  const double fudge = 4.0 * 2.220446049250313e-16 * tn * (double)k + 4.0 * pivmin;
+  gl -= fudge;
+  gu += fudge;
+}
+
+// lam_asc[e] = e-th smallest eigenvalue; block of EIG_WPB waves, wave per index.
+constexpr int EIG_WPB = 4;
+__global__ __launch_bounds__(WAVE * EIG_WPB) void k_eig_bisect(const double* __restrict__ alpha,
+                                                               const double* __restrict__ beta,
+                                                               double* __restrict__ lam_asc,
+                                                               const Ctl* ctl) {
+  __shared__ double a[MAXK], b[MAXK], b2[MAXK];
+  const int k = ctl->k_eff;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    a[i] = alpha[i];
+    const double bi = (i + 1 < k) ? beta[i] : 0.0;
+    b[i] = bi;
+    b2[i] = bi * bi;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int e = blockIdx.x * EIG_WPB + threadIdx.x / WAVE;
+  if (e >= k) return;
+  double lo, hi, pivmin;
+  tri_bounds(a, b, k, lo, hi, pivmin);
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < EIG_ROUNDS; ++it) {
+    const double w = hi - lo;
+    if (!(w > 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin)) break;   // uniform
+    const double step = w / (double)(WAVE + 1);
+    const double x = lo + step * (double)(lane + 1);
+    const int cnt = sturm_count(a, b2, k, x, pivmin);
+    const uint64_t mask = __ballot(cnt > e);   // lanes whose point lies above lam_e
+    if (mask == 0ull) {
+      lo = lo + step * (double)WAVE;
+    } else {
+      const int f = __ffsll((unsigned long long)mask) - 1;
+      const double nlo = f > 0 ? lo + step * (double)f : lo;
+      hi = lo + step * (double)(f + 1);
+      lo = nlo;
+    }
+  }
+  if (lane == 0) lam_asc[e] = 0.5 * (lo + hi);
+}
+
+// Eigenvectors by twisted factorisation; one block, one thread per eigenvalue
+// (blockDim >= k).  dscr: 2 * MAXK * MAXK doubles (forward / backward pivots,
+// [i][e] so a wave's accesses coalesce).  force_ql: always hand over to QL.
+__global__ __launch_bounds__(MAXK) void k_eig_vectors(const double* __restrict__ alpha,
+                                                      const double* __restrict__ beta,
+                                                      const double* __restrict__ lam_asc,
+                                                      double* __restrict__ vout,
+                                                      double* __restrict__ lam,
+                                                      double* __restrict__ dscr, int force_ql,
+                                                      Ctl* ctl) {
+  __shared__ double a[MAXK], b[MAXK];
+  __shared__ int s_bad, s_pos;
+  const int k = ctl->k_eff;
+  const int e = threadIdx.x;
+  for (int i = e; i < k; i += blockDim.x) {
+    a[i] = alpha[i];
+    b[i] = (i + 1 < k) ? beta[i] : 0.0;
+  }
+  if (e == 0) {
+    s_bad = force_ql;
+    s_pos = 0;
+  }
+  __syncthreads();
+  if (e < k) {
+    double gl, gu, pivmin;
+    tri_bounds(a, b, k, gl, gu, pivmin);
+    const double tn = fmax(fabs(gl), fabs(gu));
+    const double lm = lam_asc[e];
+    int bad = 0;
+    if (e + 1 < k) {
+      const double ln = lam_asc[e + 1];
+      const double big = fmax(fabs(lm), fabs(ln));
+      if (big > 1e-9 * tn && (ln - lm) < 1e-6 * big) bad = 1;
+    }
+    double* dp = dscr;
+    double* dm = dscr + MAXK * MAXK;
+    // forward pivots D+
+    double q = a[0] - lm;
+    if (fabs(q) < pivmin) q = -pivmin;
+    dp[e] = q;
+    for (int i = 1; i < k; ++i) {
+      q = (a[i] - lm) - b[i - 1] * b[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      dp[i * MAXK + e] = q;
+    }
+    // backward pivots D- and the twist index
+    q = a[k - 1] - lm;
+    if (fabs(q) < pivmin) q = -pivmin;
+    dm[(k - 1) * MAXK + e] = q;
+    int r = k - 1;
+    double gbest = fabs(dp[(k - 1) * MAXK + e] + q - (a[k - 1] - lm));
+    for (int i = k - 2; i >= 0; --i) {
+      q = (a[i] - lm) - b[i] * b[i] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      dm[i * MAXK + e] = q;
+      const double gm = fabs(dp[i * MAXK + e] + q - (a[i] - lm));
+      if (gm < gbest) {
+        gbest = gm;
+        r = i;
+      }
+    }
+    // z_r = 1, recurrences outward; column c = k-1-e of vout (decreasing order)
+    const int c = k - 1 - e;
+    double* col = vout + (size_t)c * MAXK;
+    double z = 1.0, nrm = 1.0;
+    col[r] = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      z = -(b[i] / dp[i * MAXK + e]) * z;
+      col[i] = z;
+      nrm += z * z;
+    }
+    z = 1.0;
+    for (int i = r; i + 1 < k; ++i) {
+      z = -(b[i] / dm[(i + 1) * MAXK + e]) * z;
+      col[i + 1] = z;
+      nrm += z * z;
+    }
+    if (!isfinite(nrm) || !isfinite(lm)) bad = 1;
+    const double inv = 1.0 / sqrt(nrm);
+    for (int i = 0; i < k; ++i) col[i] *= inv;
+    for (int i = k; i < MAXK; ++i) col[i] = 0.0;
+    lam[c] = lm;
+    if (bad) atomicOr(&s_bad, 1);
+    if (lm > 0.0 && isfinite(lm)) atomicAdd(&s_pos, 1);
+  }
+  __syncthreads();
+  if (e == 0) {
+    if (s_bad) {
+      ctl->eig_fallback = 1;
+    } else {
+      ctl->k_chol = s_pos;
+      if (s_pos < k) ctl->status |= SF_SAMPLER_TRUNC;
+    }
+  }
+}
+
+// Implicit QL with Wilkinson shifts (Bowdler, Martin, Reinsch and Wilkinson,
+// 1968), the fallback above; does nothing unless ctl->eig_fallback.  One wave
+// does everything: lane i holds d[i], d[i+64], e[i], e[i+64] in registers; the
+// scalar chase runs uniformly on all lanes (values fetched with readlane), and
+// every plane rotation is applied at once to the lane's two rows of V (held in
+// LDS), the updated column carried in registers.
 constexpr int EIG_MAXSWEEP = 40;
 
 __device__ inline double rl64(double v, int lane) {
@@ -1059,6 +1249,7 @@ __global__ __launch_bounds__(WAVE) void k_tri_eig(const double* __restrict__ alp
                                                   const double* __restrict__ beta,
                                                   double* __restrict__ vout,
                                                   double* __restrict__ lam, Ctl* ctl) {
+  if (!ctl->eig_fallback) return;
   extern __shared__ unsigned char smem_raw[];
   double* V = (double*)smem_raw;   // column c of V at V[c * MAXK + row]
   __shared__ double dsh[MAXK];
@@ -1210,10 +1401,10 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   Work wk;
   love_status st = work_alloc(c, wk, m, tmp, s);
   if (st != LOVE_OK) return st;
-  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *tsc;
+  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *lasc, *dscr, *tsc;
   {
-    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 4 * LDP + MAXK * MAXK +
-                                     (size_t)toeplitz_scratch_elems(c));
+    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 5 * LDP +
+                                     3 * MAXK * MAXK + (size_t)toeplitz_scratch_elems(c));
     char* p = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
     tmp.push_back(p);
@@ -1226,8 +1417,10 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     alpha = sv + LDP;
     beta = alpha + LDP;
     lam = beta + LDP;
-    vout = lam + LDP;
-    tsc = vout + MAXK * MAXK;
+    lasc = lam + LDP;
+    vout = lasc + LDP;
+    dscr = vout + MAXK * MAXK;
+    tsc = dscr + 2 * MAXK * MAXK;
   }
   Ctl* ctl = c->ctl_s;
   const Ctl* cm = c->ctl;
@@ -1267,8 +1460,16 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   }
   {
     ProfScope pe("sampler_eig", s);
-    (void)hipFuncSetAttribute((const void*)k_tri_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              sizeof(double) * MAXK * MAXK);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)k_tri_eig,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                sizeof(double) * MAXK * MAXK);
+      attr = true;
+    }
+    const int force_ql = (c->cfg.flags & LOVE_FLAG_EIG_QL) ? 1 : 0;
+    k_eig_bisect<<<(unsigned)cdiv(ks, EIG_WPB), WAVE * EIG_WPB, 0, s>>>(alpha, beta, lasc, ctl);
+    k_eig_vectors<<<1, MAXK, 0, s>>>(alpha, beta, lasc, vout, lam, dscr, force_ql, ctl);
     k_tri_eig<<<1, WAVE, sizeof(double) * MAXK * MAXK, s>>>(alpha, beta, vout, lam, ctl);
     dim3 sgrid((unsigned)cdiv(m, 256), (unsigned)cdiv(c->kspad, 16));
     k_s_from_eig<<<sgrid, 256, 0, s>>>(m, Q, ldq, vout, lam, c->S, c->kspad, ctl);

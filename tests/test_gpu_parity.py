@@ -202,6 +202,31 @@ def test_sampler_truncated_vs_oracle():
     cache.free()
 
 
+@pytest.mark.parametrize("scale", [0.02, 1.0])
+def test_sampler_eigensolver_paths_agree(scale):
+    """The sampler's T' eigen-decomposition has a parallel fast path
+    (multisection + twisted factorisation) and an implicit-QL path; the
+    implied covariance W* S S^T W*^T must agree between them."""
+    P = WL.config(2, scale=scale, s=16)
+    xs = P.xs_sample[:300]
+    spec = spec_of(P)
+    Ws = O.interp_matrix(xs.astype(np.float64), spec)
+    p = O.prior_var(xs, spec)
+    covs, kk = [], []
+    for flags in (0, B.FLAG_EIG_QL):
+        cache = build(P, flags=flags)
+        inf = cache.info()
+        kk.append((inf.k_eff_sample, inf.status_flags & ~32))
+        F = Ws @ host(cache.export()["s"])
+        covs.append(F @ F.T)
+        cache.free()
+    print(kk, flush=True)
+    assert kk[0] == kk[1]
+    err = np.max(np.abs(covs[0] - covs[1]) / np.sqrt(np.outer(p, p)))
+    print(err, flush=True)
+    assert err <= 1e-6
+
+
 def test_sampler_monte_carlo():
     """Sample mean and covariance of 20000 GPU draws at 12 points against the
     implied covariance (statistical tolerance, 6 standard errors)."""
