@@ -127,6 +127,8 @@ typedef struct {
   int32_t d;
   int64_t n, m;
   double beta_last;                 /* last Lanczos off-diagonal                                  */
+  double ortho_loss;                /* max |Q^T Q - I| of the Lanczos vectors (NaN: not computed,
+                                       i.e. without the preconditioned mean solve)                */
   uint32_t status_flags;            /* LOVE_SF_*                                                  */
   uint32_t toeplitz_mode[LOVE_MAX_DIM]; /* backend chosen per axis (1 direct, 2 fft)          */
   uint32_t fft_len[LOVE_MAX_DIM];   /* circulant length per axis when FFT is used                 */

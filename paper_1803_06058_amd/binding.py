@@ -42,7 +42,7 @@ class love_cache_info_t(C.Structure):
     _fields_ = [
         ("k_eff", C.c_int32), ("k_eff_sample", C.c_int32), ("cg_iters", C.c_int32),
         ("d", C.c_int32), ("n", C.c_int64), ("m", C.c_int64), ("beta_last", C.c_double),
-        ("status_flags", C.c_uint32), ("toeplitz_mode", C.c_uint32 * 4),
+        ("ortho_loss", C.c_double), ("status_flags", C.c_uint32), ("toeplitz_mode", C.c_uint32 * 4),
         ("fft_len", C.c_uint32 * 4), ("bytes", C.c_size_t),
     ]
 

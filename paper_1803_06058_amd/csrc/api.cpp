@@ -149,6 +149,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   }
   c->m = m;
   c->ctot = ct;
+  c->ldq = cdiv(n, RB) * RB;
   c->k = (int)std::min<int64_t>(cfg->k, n);
   c->kpad = kround(c->k);
   c->ks = (int)std::min<int64_t>(cfg->k_sample, m);
@@ -162,6 +163,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->ctl = (Ctl*)dev_alloc(c, sizeof(Ctl));
   c->ctl_s = (Ctl*)dev_alloc(c, sizeof(Ctl));
   c->status = (unsigned*)dev_alloc(c, sizeof(unsigned) * 4);
+  c->ortho = (double*)dev_alloc(c, sizeof(double));
   c->alpha = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
   c->beta = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
   const bool split = cfg->precision == LOVE_P_FP32_BF16SPLIT;
@@ -174,7 +176,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->g1 = dev_alloc(c, es * (size_t)m);
   c->g2 = dev_alloc(c, es * (size_t)m);
   c->tscr = nullptr;  // allocated after the Toeplitz plan
-  if (!c->x || !c->y || !c->perm || !c->cell_start || !c->ctl || !c->ctl_s || !c->status ||
+  if (!c->x || !c->y || !c->perm || !c->cell_start || !c->ctl || !c->ctl_s || !c->status || !c->ortho ||
       !c->alpha || !c->beta || !c->rt || (split && !c->rt_lo) || !c->a || (c->ks > 0 && !c->S) ||
       !c->v1 || !c->v2 || !c->g1 || !c->g2)
     return LOVE_ENOMEM;
@@ -221,15 +223,74 @@ static hipStream_t side_stream() {
   return st;
 }
 
+// Build a batch of caches (same d and precision) with one launch per phase.
 template <typename T>
-static love_status build_one(love_cache* c, const void* x, const void* y, hipStream_t s) {
-  love_status st = setup_sort<T>(c, (const T*)x, (const T*)y, s);
+static love_status build_batch(const std::vector<love_cache*>& cs, const void* const* xs,
+                               const void* const* ys, hipStream_t s) {
+  const int G = (int)cs.size();
+  std::vector<const T*> xv(G), yv(G);
+  for (int g = 0; g < G; ++g) {
+    xv[g] = (const T*)xs[g];
+    yv[g] = (const T*)ys[g];
+  }
+  love_status st = setup_sort<T>(cs, xv, yv, s);
   if (st != LOVE_OK) return st;
-  st = toeplitz_plan(c);
+  bool any_s = false;
+  for (auto* c : cs) {
+    st = toeplitz_plan(c);
+    if (st != LOVE_OK) return st;
+    c->tscr = dev_alloc(c, sizeof(double) * (size_t)toeplitz_scratch_elems(c));
+    if (!c->tscr) return LOVE_ENOMEM;
+    any_s = any_s || c->ks > 0;
+  }
+  return build_batch_lanczos<T>(cs, s, any_s ? side_stream() : nullptr);
+}
+
+template <typename T>
+static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStream_t s) {
+  love_cache* cm = const_cast<love_cache*>(c);
+  std::vector<love_cache*> one{cm};
+  JobArena A;
+  ScatterJob<T> S{};
+  S.g = make_grid<T>(c);
+  S.x = (const T*)c->x;
+  S.cell_start = c->cell_start;
+  S.v = (const T*)c->v1;
+  S.out = (T*)c->g1;
+  GatherJob<T> Ga{};
+  Ga.g = S.g;
+  Ga.x = S.x;
+  Ga.n = c->n;
+  Ga.kg = (const T*)c->g2;
+  Ga.vsig = (const T*)c->v1;
+  Ga.sigma2 = (T)c->cfg.noise;
+  Ga.out = (T*)c->v2;
+  const size_t os = A.add(std::vector<ScatterJob<T>>{S});
+  const size_t og = A.add(std::vector<GatherJob<T>>{Ga});
+  ToepRun<T> run;
+  toep_prepare<T>(A, run, one, {(const T*)c->g1}, {0}, {(T*)c->g2}, {0}, {(T*)c->tscr}, {nullptr});
+  love_status st = A.upload(s);
   if (st != LOVE_OK) return st;
-  c->tscr = dev_alloc(c, sizeof(double) * (size_t)toeplitz_scratch_elems(c));
-  if (!c->tscr) return LOVE_ENOMEM;
-  return build_lanczos_and_mean<T>(c, s, c->ks > 0 ? side_stream() : nullptr);
+  launch_permute<T>(v, (T*)c->v1, c->perm, c->n, 0, s);
+  launch_scatter<T>(tab1(cdiv(c->m, 4)), A.at<ScatterJob<T>>(os), c->d, 0, 0, s);
+  toep_run<T>(A, run, 0, 0, s);
+  launch_gather<T>(tab1(cdiv(c->n, 256)), A.at<GatherJob<T>>(og), c->d, 0, s);
+  launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);
+  A.release(s);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+template <typename T>
+static love_status apply_kuu_t(const love_cache* c, const T* g, T* out, hipStream_t s) {
+  std::vector<love_cache*> one{const_cast<love_cache*>(c)};
+  JobArena A;
+  ToepRun<T> run;
+  toep_prepare<T>(A, run, one, {g}, {0}, {out}, {0}, {(T*)c->tscr}, {nullptr});
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  toep_run<T>(A, run, 0, 0, s);
+  A.release(s);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 
 extern "C" {
@@ -252,21 +313,7 @@ const char* love_status_string(love_status s) {
 
 love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
                              void* stream, love_cache** out) {
-  if (!out || !x || !y || n < 1 || n > INT32_MAX) return LOVE_EINVAL;
-  love_status st = validate(cfg);
-  if (st != LOVE_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  love_cache* c = new (std::nothrow) love_cache();
-  if (!c) return LOVE_ENOMEM;
-  st = init_cache(c, cfg, n, s);
-  if (st == LOVE_OK) st = c->fp64 ? build_one<double>(c, x, y, s) : build_one<float>(c, x, y, s);
-  if (st == LOVE_OK && !(cfg->flags & LOVE_FLAG_ASYNC)) st = finish_status(c);
-  if (st != LOVE_OK) {
-    destroy(c);
-    return st;
-  }
-  *out = c;
-  return LOVE_OK;
+  return love_build_cache_batched(1, cfg, &x, &y, &n, stream, out);
 }
 
 love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
@@ -277,26 +324,34 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
     love_status st = validate(&cfgs[g]);
     if (st != LOVE_OK) return st;
     if (cfgs[g].precision != cfgs[0].precision || cfgs[g].d != cfgs[0].d) return LOVE_EINVAL;
+    if (!xs[g] || !ys[g] || ns[g] < 1 || ns[g] > INT32_MAX) return LOVE_EINVAL;
+    if ((cfgs[g].flags & LOVE_FLAG_NO_MEAN) != (cfgs[0].flags & LOVE_FLAG_NO_MEAN))
+      return LOVE_EINVAL;
   }
+  hipStream_t s = (hipStream_t)stream;
   std::vector<love_cache*> made;
+  auto fail = [&](love_status st) {
+    for (auto* p : made) destroy(p);
+    return st;
+  };
   for (int g = 0; g < G; ++g) {
-    love_config cg = cfgs[g];
-    cg.flags |= LOVE_FLAG_ASYNC;
-    love_cache* c = nullptr;
-    love_status st = love_build_cache(&cg, xs[g], ys[g], ns[g], stream, &c);
-    if (st != LOVE_OK) {
-      for (auto* p : made) destroy(p);
-      return st;
-    }
-    c->cfg.flags = cfgs[g].flags;
+    love_cache* c = new (std::nothrow) love_cache();
+    if (!c) return fail(LOVE_ENOMEM);
     made.push_back(c);
+    love_status st = init_cache(c, &cfgs[g], ns[g], s);
+    if (st != LOVE_OK) return fail(st);
+  }
+  // lock-step groups of at most MAXG GPs
+  for (int g0 = 0; g0 < G; g0 += MAXG) {
+    const int g1 = std::min(G, g0 + MAXG);
+    std::vector<love_cache*> grp(made.begin() + g0, made.begin() + g1);
+    love_status st = made[0]->fp64 ? build_batch<double>(grp, xs + g0, ys + g0, s)
+                                    : build_batch<float>(grp, xs + g0, ys + g0, s);
+    if (st != LOVE_OK) return fail(st);
   }
   for (int g = 0; g < G; ++g) {
     love_status st = (cfgs[g].flags & LOVE_FLAG_ASYNC) ? LOVE_OK : finish_status(made[g]);
-    if (st != LOVE_OK) {
-      for (auto* p : made) destroy(p);
-      return st;
-    }
+    if (st != LOVE_OK) return fail(st);
   }
   for (int g = 0; g < G; ++g) out[g] = made[g];
   return LOVE_OK;
@@ -304,10 +359,7 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
 
 love_status love_predict_mean_var(const love_cache* c, const void* xs, int64_t t, void* mean,
                                   void* var, void* stream) {
-  if (!c || t < 0 || (t > 0 && (!xs || !var))) return LOVE_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  if (c->fp64) return predict<double>(c, (const double*)xs, t, (double*)mean, (double*)var, s);
-  return predict<float>(c, (const float*)xs, t, (float*)mean, (float*)var, s);
+  return love_predict_mean_var_batched(1, &c, &xs, &t, &mean, &var, stream);
 }
 
 love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* caches,
@@ -315,11 +367,32 @@ love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* ca
                                           void* const* means, void* const* vars, void* stream) {
   if (G < 1 || !caches || !xs || !ts || !vars) return LOVE_EINVAL;
   for (int g = 0; g < G; ++g) {
-    love_status st = love_predict_mean_var(caches[g], xs[g], ts[g], means ? means[g] : nullptr,
-                                           vars[g], stream);
-    if (st != LOVE_OK) return st;
+    if (!caches[g] || ts[g] < 0 || (ts[g] > 0 && (!xs[g] || !vars[g]))) return LOVE_EINVAL;
+    if (caches[g]->fp64 != caches[0]->fp64 || caches[g]->d != caches[0]->d ||
+        caches[g]->cfg.precision != caches[0]->cfg.precision)
+      return LOVE_EINVAL;
   }
-  return LOVE_OK;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<const love_cache*> cs(caches, caches + G);
+  std::vector<int64_t> tv(ts, ts + G);
+  if (caches[0]->fp64) {
+    std::vector<const double*> x(G);
+    std::vector<double*> mu(G), va(G);
+    for (int g = 0; g < G; ++g) {
+      x[g] = (const double*)xs[g];
+      mu[g] = means ? (double*)means[g] : nullptr;
+      va[g] = (double*)vars[g];
+    }
+    return predict_batch<double>(cs, x, tv, mu, va, s);
+  }
+  std::vector<const float*> x(G);
+  std::vector<float*> mu(G), va(G);
+  for (int g = 0; g < G; ++g) {
+    x[g] = (const float*)xs[g];
+    mu[g] = means ? (float*)means[g] : nullptr;
+    va[g] = (float*)vars[g];
+  }
+  return predict_batch<float>(cs, x, tv, mu, va, s);
 }
 
 love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
@@ -355,30 +428,15 @@ love_status love_apply_khat(const love_cache* c, const void* v, void* out, void*
   if (!c || !v || !out) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   ProfScope ps("apply_khat", s);
-  if (c->fp64) {
-    launch_permute<double>((const double*)v, (double*)c->v1, c->perm, c->n, 0, s);
-    launch_scatter<double>(c, (const double*)c->v1, (double*)c->g1, nullptr, nullptr, 0, s);
-    toeplitz_apply<double>(c, (const double*)c->g1, (double*)c->g2, (double*)c->tscr, nullptr, 0, s);
-    launch_gather<double>(c, (const double*)c->g2, (const double*)c->v1, c->cfg.noise,
-                          (double*)c->v2, nullptr, s);
-    launch_permute<double>((const double*)c->v2, (double*)out, c->perm, c->n, 1, s);
-  } else {
-    launch_permute<float>((const float*)v, (float*)c->v1, c->perm, c->n, 0, s);
-    launch_scatter<float>(c, (const float*)c->v1, (float*)c->g1, nullptr, nullptr, 0, s);
-    toeplitz_apply<float>(c, (const float*)c->g1, (float*)c->g2, (float*)c->tscr, nullptr, 0, s);
-    launch_gather<float>(c, (const float*)c->g2, (const float*)c->v1, (float)c->cfg.noise,
-                         (float*)c->v2, nullptr, s);
-    launch_permute<float>((const float*)c->v2, (float*)out, c->perm, c->n, 1, s);
-  }
-  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+  if (c->fp64) return apply_khat_t<double>(c, (const double*)v, (double*)out, s);
+  return apply_khat_t<float>(c, (const float*)v, (float*)out, s);
 }
 
 love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* stream) {
   if (!c || !g || !out) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (c->fp64) toeplitz_apply<double>(c, (const double*)g, (double*)out, (double*)c->tscr, nullptr, 0, s);
-  else toeplitz_apply<float>(c, (const float*)g, (float*)out, (float*)c->tscr, nullptr, 0, s);
-  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+  if (c->fp64) return apply_kuu_t<double>(c, (const double*)g, (double*)out, s);
+  return apply_kuu_t<float>(c, (const float*)g, (float*)out, s);
 }
 
 love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
@@ -388,10 +446,11 @@ love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
   LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   LOVE_HIP_TRY(hipMemcpyAsync(&hs, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   LOVE_HIP_TRY(hipMemcpyAsync(st, c->status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
-  double bl = 0.0;
+  double bl = 0.0, orth = 0.0;
   if (h.k_eff > 0)
     LOVE_HIP_TRY(hipMemcpyAsync(&bl, c->beta + h.k_eff - 1, sizeof(double), hipMemcpyDeviceToHost,
                                 c->stream));
+  LOVE_HIP_TRY(hipMemcpyAsync(&orth, c->ortho, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LOVE_HIP_TRY(hipStreamSynchronize(c->stream));
   std::memset(info, 0, sizeof(*info));
   info->k_eff = h.k_eff;
@@ -401,6 +460,7 @@ love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
   info->n = c->n;
   info->m = c->m;
   info->beta_last = bl;
+  info->ortho_loss = (c->cfg.flags & (LOVE_FLAG_NO_MEAN | LOVE_FLAG_PLAIN_CG)) ? NAN : orth;
   info->status_flags = h.status | hs.status | st[0];
   for (int e = 0; e < c->d; ++e) {
     info->toeplitz_mode[e] = (uint32_t)c->toep.ax[e].mode;

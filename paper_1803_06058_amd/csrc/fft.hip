@@ -38,16 +38,23 @@ struct Cx {
 __device__ inline unsigned bitrev(unsigned x, int bits) { return __brev(x) >> (32 - bits); }
 
 template <typename T>
-__global__ __launch_bounds__(FFT_BLK) void k_fft_conv(const T* __restrict__ in, T* __restrict__ out,
-                                                      int L, int64_t inner, int64_t nlines, int N,
-                                                      int logN, const T* __restrict__ tw,
-                                                      const T* __restrict__ lam, T scale,
-                                                      const Ctl* ctl, int mode) {
-  if (ctl_skip(ctl, mode)) return;
+__global__ __launch_bounds__(FFT_BLK) void k_fft_conv(Tab tab, const ToepJob<T>* __restrict__ jobs,
+                                                      int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ToepJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
   extern __shared__ unsigned char smem_raw[];
+  const int N = J.N, logN = J.logN, L = J.L;
+  const int64_t inner = J.inner, nlines = J.outer * J.inner;
+  const T* __restrict__ lam = J.spec;
+  const T* __restrict__ tw = J.spec + N;
+  const T scale = J.scale;
   T* zr = (T*)smem_raw;        // N
   T* zi = zr + N;              // N
-  const int64_t l1 = 2 * (int64_t)blockIdx.x, l2 = l1 + 1;
+  const T* in = J.in + (int64_t)j * J.in_js;
+  T* out = J.out + (int64_t)j * J.out_js;
+  const int64_t l1 = 2 * (int64_t)lb, l2 = l1 + 1;
   const bool has2 = l2 < nlines;
   const int64_t o1 = l1 / inner, r1 = l1 % inner, o2 = l2 / inner, r2 = l2 % inner;
   const T* s1 = in + o1 * L * inner + r1;
@@ -63,9 +70,9 @@ __global__ __launch_bounds__(FFT_BLK) void k_fft_conv(const T* __restrict__ in, 
     const int half = 1 << (st - 1);
     const int tstep = N >> st;   // twiddle index stride
     for (int b = threadIdx.x; b < N / 2; b += FFT_BLK) {
-      const int grp = b >> (st - 1), j = b & (half - 1);
-      const int i1 = grp * 2 * half + j, i2 = i1 + half;
-      const T wr = tw[2 * (j * tstep)], wi = tw[2 * (j * tstep) + 1];
+      const int grp = b >> (st - 1), jj = b & (half - 1);
+      const int i1 = grp * 2 * half + jj, i2 = i1 + half;
+      const T wr = tw[2 * (jj * tstep)], wi = tw[2 * (jj * tstep) + 1];
       const T xr = zr[i2], xi = zi[i2];
       const T tr = wr * xr - wi * xi, ti = wr * xi + wi * xr;
       const T ur = zr[i1], ui = zi[i1];
@@ -87,9 +94,9 @@ __global__ __launch_bounds__(FFT_BLK) void k_fft_conv(const T* __restrict__ in, 
     const int half = 1 << (st - 1);
     const int tstep = N >> st;
     for (int b = threadIdx.x; b < N / 2; b += FFT_BLK) {
-      const int grp = b >> (st - 1), j = b & (half - 1);
-      const int i1 = grp * 2 * half + j, i2 = i1 + half;
-      const T wr = tw[2 * (j * tstep)], wi = -tw[2 * (j * tstep) + 1];
+      const int grp = b >> (st - 1), jj = b & (half - 1);
+      const int i1 = grp * 2 * half + jj, i2 = i1 + half;
+      const T wr = tw[2 * (jj * tstep)], wi = -tw[2 * (jj * tstep) + 1];
       const T ur = zr[i1], ui = zi[i1], vr = zr[i2], vi = zi[i2];
       zr[i1] = ur + vr;
       zi[i1] = ui + vi;
@@ -107,6 +114,22 @@ __global__ __launch_bounds__(FFT_BLK) void k_fft_conv(const T* __restrict__ in, 
     if (has2) d2[(int64_t)i * inner] = scale * zi[p];
   }
 }
+
+template <typename T>
+void launch_fft_conv(const Tab& tab, const ToepJob<T>* jobs, size_t smem, int j, int mode,
+                     hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute((const void*)k_fft_conv<float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 16384 * 4);
+    (void)hipFuncSetAttribute((const void*)k_fft_conv<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 8192 * 8);
+  }
+  k_fft_conv<T><<<tab_blocks(tab), FFT_BLK, smem, s>>>(tab, jobs, j, mode);
+}
+template void launch_fft_conv<float>(const Tab&, const ToepJob<float>*, size_t, int, int, hipStream_t);
+template void launch_fft_conv<double>(const Tab&, const ToepJob<double>*, size_t, int, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Host: tables
@@ -169,44 +192,41 @@ love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<
   LOVE_HIP_TRY(hipMemcpy(ax.spec32, lam32.data(), sizeof(float) * N, hipMemcpyHostToDevice));
   LOVE_HIP_TRY(hipMemcpy((float*)ax.spec32 + N, tw32.data(), sizeof(float) * N, hipMemcpyHostToDevice));
   ax.fft_n = N;
-  ax.fft_single = 0;
   ax.mode = LOVE_TOEPLITZ_FFT;
   return LOVE_OK;
 }
-
-template <typename T>
-void fft_axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
-                    const Ctl* ctl, int mode, hipStream_t s) {
-  (void)c;
-  static bool attr = false;
-  if (!attr) {
-    attr = true;
-    (void)hipFuncSetAttribute((const void*)k_fft_conv<float>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 16384 * 4);
-    (void)hipFuncSetAttribute((const void*)k_fft_conv<double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * 8192 * 8);
-  }
-  const int N = ax.fft_n;
-  int logN = 0;
-  while ((1 << logN) < N) ++logN;
-  const T* tab = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
-  const int64_t nlines = ax.outer * ax.inner;
-  const unsigned nblk = (unsigned)cdiv(nlines, 2);
-  k_fft_conv<T><<<nblk, FFT_BLK, sizeof(T) * 2 * (size_t)N, s>>>(
-      in, out, ax.L, ax.inner, nlines, N, logN, tab + N, tab, scale, ctl, mode);
-}
-template void fft_axis_apply<float>(const love_cache*, const ToepAxis&, const float*, float*, float, const Ctl*, int, hipStream_t);
-template void fft_axis_apply<double>(const love_cache*, const ToepAxis&, const double*, double*, double, const Ctl*, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Autotuner: per axis shape (L, lines), time the direct and the FFT backend
 // on the device once per process (float, on a private stream) and keep the
 // faster.  LOVE_AUTOTUNE=0 switches measuring off and uses a size rule.
 // ----------------------------------------------------------------------------
-int64_t toeplitz_scratch_elems(const love_cache* c);
-template <typename T>
-void axis_apply_public(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T* scratch,
-                       hipStream_t s);
+// Time one axis backend: a one-GP, one-axis view of the cache.
+static float time_axis(love_cache* c, const ToepAxis& ax, float* bin, float* bout, float* bscr,
+                       hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  love_cache view = *c;
+  view.d = 1;
+  view.toep.d = 1;
+  view.toep.ax[0] = ax;
+  JobArena A;
+  ToepRun<float> run;
+  std::vector<love_cache*> cs{&view};
+  toep_prepare<float>(A, run, cs, {bin}, {0}, {bout}, {0}, {bscr}, {nullptr});
+  if (A.upload(s) != LOVE_OK) return 1e30f;
+  float best = 1e30f;
+  for (int rep = 0; rep < 4; ++rep) {
+    (void)hipEventRecord(a, s);
+    toep_run<float>(A, run, 0, 0, s);
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (rep > 0) best = std::min(best, ms);
+  }
+  A.release(s);
+  (void)hipStreamSynchronize(s);
+  return best;
+}
 
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int64_t, int64_t, int, int>, int> g_tune;
@@ -267,19 +287,9 @@ int autotune_choose(love_cache* c, int e) {
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    float best[2] = {1e30f, 1e30f};
-    for (int which = 0; which < 2; ++which) {
-      const ToepAxis& use = which == 0 ? axd : axf;
-      for (int rep = 0; rep < 4; ++rep) {
-        (void)hipEventRecord(a, s);
-        axis_apply_public<float>(c, use, bin, bout, bscr, s);
-        (void)hipEventRecord(b, s);
-        (void)hipEventSynchronize(b);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (rep > 0) best[which] = std::min(best[which], ms);
-      }
-    }
+    float best[2];
+    best[0] = time_axis(c, axd, bin, bout, bscr, s, a, b);
+    best[1] = time_axis(c, axf, bin, bout, bscr, s, a, b);
     choice = best[1] < best[0] ? LOVE_TOEPLITZ_FFT : LOVE_TOEPLITZ_DIRECT;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

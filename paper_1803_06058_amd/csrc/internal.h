@@ -1,13 +1,17 @@
 // Host-side internals of the LOVE library: the cache object, device buffers,
-// Toeplitz plans and the launchers implemented in the .hip translation units.
+// Toeplitz plans, batched-launch helpers and the launchers implemented in the
+// .hip translation units.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/love.h"
 #include "common.h"
+#include "jobs.h"
 
 namespace love {
 
@@ -39,12 +43,11 @@ struct ToepAxis {
   int64_t inner = 1;     // product of m over later axes
   int64_t outer = 1;     // product of m over earlier axes
   int fft_n = 0;         // complex FFT length (power of two) when mode == 2
-  int fft_single = 0;    // 1: real line packed into a half-length complex FFT
   int bw32 = 0;          // coefficient band that matters in float  (|d| <= bw32)
   int bw64 = 0;          // ... and in double
   void* c32 = nullptr;   // float  first column (L), outputscale folded into axis 0
   void* c64 = nullptr;   // double first column (L)
-  void* spec32 = nullptr;  // float  circulant eigenvalues (fft_n [+1] reals)
+  void* spec32 = nullptr;  // float  [circulant eigenvalues / N | twiddles], 2 N values
   void* spec64 = nullptr;  // double
 };
 
@@ -54,9 +57,6 @@ struct ToepPlan {
   ToepAxis ax[MAXD];
 };
 
-// ----------------------------------------------------------------------------
-// The cache
-// ----------------------------------------------------------------------------
 }  // namespace love
 
 struct love_cache {
@@ -64,6 +64,7 @@ struct love_cache {
   bool fp64 = false;
   int d = 1;
   int64_t n = 0, m = 0;
+  int64_t ldq = 0;            // n rounded up to the row-block size
   int k = 0, kpad = 0;        // Lanczos steps requested; row stride of Rt
   int ks = 0, kspad = 0;      // sampler steps; row stride of S
   hipStream_t stream = nullptr;
@@ -91,12 +92,13 @@ struct love_cache {
   love::Ctl* ctl = nullptr;   // device control block of the main Lanczos / CG
   love::Ctl* ctl_s = nullptr; // sampler Lanczos
   unsigned* status = nullptr; // device status word of queries (SF_* bits)
+  double* ortho = nullptr;    // device: max |Q^T Q - I| of the Lanczos vectors
   // scratch for apply_khat
   void* v1 = nullptr;         // n
   void* v2 = nullptr;         // n
   void* g1 = nullptr;         // m
   void* g2 = nullptr;         // m
-  void* tscr = nullptr;       // 2 m (double-sized): Toeplitz scratch of apply_khat / apply_kuu
+  void* tscr = nullptr;       // toeplitz_scratch_elems doubles: scratch of apply_khat / apply_kuu
   size_t bytes = 0;
   std::vector<void*> allocs;
 };
@@ -106,46 +108,127 @@ namespace love {
 // allocation helper (tracks bytes); returns nullptr on failure
 void* dev_alloc(love_cache* c, size_t bytes);
 
-// --- setup (sort.hip) -------------------------------------------------------
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+#define LOVE_HIP_TRY(expr)                         \
+  do {                                             \
+    hipError_t _e = (expr);                        \
+    if (_e != hipSuccess) return LOVE_EHIP;        \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// Batched launches (host side)
+// ----------------------------------------------------------------------------
+// Work table from per-GP block counts (GP g: blocks[g] blocks, may be 0).
+inline Tab make_tab(const std::vector<int64_t>& blocks) {
+  Tab t{};
+  t.G = (int)blocks.size();
+  t.off[0] = 0;
+  for (int g = 0; g < t.G; ++g) t.off[g + 1] = t.off[g] + (int)blocks[g];
+  return t;
+}
+inline unsigned tab_blocks(const Tab& t) { return (unsigned)t.off[t.G]; }
+
+// Job arrays of a build (or of one call), staged on the host and uploaded
+// with one copy; device addresses are valid after upload().
+class JobArena {
+ public:
+  template <class J>
+  size_t add(const std::vector<J>& items) {
+    const size_t off = (host_.size() + 63) & ~size_t(63);
+    host_.resize(off + sizeof(J) * items.size());
+    if (!items.empty()) std::memcpy(host_.data() + off, items.data(), sizeof(J) * items.size());
+    return off;
+  }
+  love_status upload(hipStream_t s) {
+    if (host_.empty()) return LOVE_OK;
+    if (hipMallocAsync((void**)&dev_, host_.size(), s) != hipSuccess) return LOVE_ENOMEM;
+    LOVE_HIP_TRY(hipMemcpyAsync(dev_, host_.data(), host_.size(), hipMemcpyHostToDevice, s));
+    return LOVE_OK;
+  }
+  template <class J>
+  const J* at(size_t off) const {
+    return reinterpret_cast<const J*>(dev_ + off);
+  }
+  void release(hipStream_t s) {
+    if (dev_) (void)hipFreeAsync(dev_, s);
+    dev_ = nullptr;
+  }
+  ~JobArena() = default;
+
+ private:
+  std::vector<char> host_;
+  char* dev_ = nullptr;
+};
+
+// A K_UU application prepared for G GPs (one entry per axis; each backend is
+// launched once for the GPs that use it on that axis).
 template <typename T>
-love_status setup_sort(love_cache* c, const T* x, const T* y, hipStream_t s);
+struct ToepRun {
+  struct Axis {
+    size_t jobs = 0;
+    Tab band{}, reduce{}, lines{}, fft{};
+    size_t smem_lines = 0, smem_fft = 0;
+  };
+  int d = 0;
+  Axis ax[MAXD];
+};
+
+// in/out per GP with per-step strides; scratch per GP holds
+// toeplitz_scratch_elems(c) elements of T; ctl per GP (nullable).
+template <typename T>
+void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& cs,
+                  const std::vector<const T*>& in, const std::vector<int64_t>& in_js,
+                  const std::vector<T*>& out, const std::vector<int64_t>& out_js,
+                  const std::vector<T*>& scratch, const std::vector<const Ctl*>& ctl);
+template <typename T>
+void toep_run(const JobArena& A, const ToepRun<T>& run, int j, int mode, hipStream_t s);
+
+int64_t toeplitz_scratch_elems(const love_cache* c);
+love_status toeplitz_plan(love_cache* c);
+void toeplitz_set_attrs();
+
+// --- setup (sort.hip) -------------------------------------------------------
+// Sort the rows of every GP of the batch by stencil cell (one sort for all).
+template <typename T>
+love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,
+                       const std::vector<const T*>& ys, hipStream_t s);
 
 // --- operator pieces (mvm.hip) ---------------------------------------------
 template <typename T>
 GridT<T> make_grid(const love_cache* c);
 
-// `xsrc` (sorted coordinates in precision T) defaults to the cache's own copy
-// g = W^T v; with ctl_mode bit 4, g = W^T (v + ctl->ratio * v2)
 template <typename T>
-void launch_scatter(const love_cache* c, const T* v, T* g, const T* v2, const Ctl* ctl,
-                    int ctl_mode, hipStream_t s, const T* xsrc = nullptr);
-
+void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
+                    hipStream_t s);
 template <typename T>
-void launch_gather(const love_cache* c, const T* kg, const T* vsig, T sigma2, T* out,
-                   const Ctl* ctl, hipStream_t s, const T* xsrc = nullptr);
-
+void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s);
+template <typename T>
+void launch_fill(const Tab& tab, const FillJob<T>* jobs, hipStream_t s);
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s);
 template <typename TI, typename TO>
 void launch_convert(const TI* in, TO* out, int64_t n, hipStream_t s);
-
-// K_UU in -> out; `scratch` holds toeplitz_scratch_elems(c) elements of T
-// (intermediate axis passes and per-segment partial sums).  Concurrent calls
-// need distinct scratch.
-int64_t toeplitz_scratch_elems(const love_cache* c);
 template <typename T>
-void toeplitz_apply(const love_cache* c, const T* in, T* out, T* scratch, const Ctl* ctl,
-                    int ctl_mode, hipStream_t s);
+void launch_permute(const T* in, T* out, const int32_t* perm, int64_t n, int inverse,
+                    hipStream_t s);
+// tables for one GP
+inline Tab tab1(int64_t blocks) { return make_tab(std::vector<int64_t>{blocks}); }
 
-love_status toeplitz_plan(love_cache* c);
-
-// --- Lanczos / CG (lanczos.hip) ---------------------------------------------
-// Lanczos, Rt, and (concurrently) the mean CG on `s` and the sampler on
-// `s_side` (nullptr: everything on `s`).
+// --- Lanczos / CG / sampler (lanczos.hip) -------------------------------------
+// Lanczos, Rt and the mean cache for every GP of the batch (lock step, one
+// launch per phase); the samplers run on `s_side` concurrently with the mean
+// solve (nullptr: on `s`).
 template <typename T>
-love_status build_lanczos_and_mean(love_cache* c, hipStream_t s, hipStream_t s_side);
+love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t s,
+                                hipStream_t s_side);
 
 // --- queries (query.hip) -----------------------------------------------------
 template <typename T>
-love_status predict(const love_cache* c, const T* xs, int64_t t, T* mean, T* var, hipStream_t s);
+love_status predict_batch(const std::vector<const love_cache*>& cs,
+                          const std::vector<const T*>& xs, const std::vector<int64_t>& ts,
+                          const std::vector<T*>& means, const std::vector<T*>& vars,
+                          hipStream_t s);
 
 template <typename T>
 love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t, T* cov,
@@ -160,21 +243,5 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
                      T* gx, float* grt, hipStream_t s);
 
 love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t s);
-
-// --- small helpers -------------------------------------------------------------
-template <typename T>
-void launch_fill(T* p, T v, int64_t n, hipStream_t s);
-
-template <typename T>
-void launch_permute(const T* in, T* out, const int32_t* perm, int64_t n, int inverse,
-                    hipStream_t s);
-
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-#define LOVE_HIP_TRY(expr)                         \
-  do {                                             \
-    hipError_t _e = (expr);                        \
-    if (_e != hipSuccess) return LOVE_EHIP;        \
-  } while (0)
 
 }  // namespace love

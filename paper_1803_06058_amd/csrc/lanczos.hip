@@ -1,23 +1,29 @@
 // Lanczos with full reorthogonalisation on Khat = W K W^T + sigma^2 I, the
 // LOVE cache, the mean cache and the sampling cache (Sec. 2.2, Sec. 3.2,
-// Alg. 1, Sec. 3.3, Sec. 5).
+// Alg. 1, Sec. 3.3, Sec. 5), for a batch of independent GPs run in lock step
+// (one launch per phase covers every GP; a single GP is the batch of one).
 //
 // One Lanczos step j (0-based), all on device, no host synchronisation:
 //   scatter   g = W^T q_j                                  (grid, m)
 //   toeplitz  R_j = K g          -- kept as row j of R = Q^T W^T K (Alg. 1)
 //   gdots     v = W R_j + sigma^2 q_j ;  per-block partials of Q_{0..j}^T v
 //   colsum    c = Q_{0..j}^T v   (first Gram-Schmidt pass; c_j = alpha_j)
-//   udots     r' = v - Q c ; per-block partials of Q^T r' and ||r'||^2 (Q tile in LDS)
+//   udots     r' = v - Q c ; per-block partials of Q^T r' and ||r'||^2
 //   colsum    c2, ||r'||^2       (second pass)
 //   finalize  alpha_j = c_j + c2_j, beta_j = sqrt(||r'||^2 - ||c2||^2),
 //             stop test, q_{j+1} = (r' - Q c2) / beta_j
-// Grid-wide sums never use device-scope fences inside a kernel (on this GPU a
-// device-scope release writes back the whole L2 of the issuing XCD, once per
-// block); instead a producer kernel writes one partial row per block and a
-// second small kernel adds the rows in a fixed order, so results are
-// bitwise reproducible and the kernel boundary provides visibility.
+// Row kernels work on blocks of 256 rows: lane l of every wave owns rows
+// 4l..4l+3 (one 16-byte load per column), the block's 4 waves split the
+// columns of Q, and a wave reduces 8 columns at once with a transposing
+// butterfly (10 shuffles instead of 48).  Grid-wide sums never use
+// device-scope fences inside a kernel (on this GPU a device-scope release
+// writes back the whole L2 of the issuing XCD, once per block); instead a
+// producer kernel writes one partial row per block and a second small kernel
+// adds the rows in a fixed order, so results are bitwise reproducible and the
+// kernel boundary provides visibility.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.h"
@@ -26,13 +32,12 @@
 namespace love {
 
 constexpr int BLK = 256;
-constexpr int LDP = MAXK + 8;   // row stride of the partial-sum arrays
 
 // ----------------------------------------------------------------------------
-// Column sums of the per-block partial rows: out[c] = sum_b partial[b][c].
-// One wave per value; every lane issues all its loads before adding.
+// Reductions
 // ----------------------------------------------------------------------------
-__device__ inline double colsum_wave(const double* __restrict__ partial, int nb, int c) {
+// sum_b partial[b][c], one wave; every lane issues all its loads before adding
+__device__ __forceinline__ double colsum_wave(const double* __restrict__ partial, int nb, int c) {
   const int lane = threadIdx.x & (WAVE - 1);
   double acc = 0.0;
   for (int b0 = 0; b0 < nb; b0 += WAVE * 8) {
@@ -48,190 +53,315 @@ __device__ inline double colsum_wave(const double* __restrict__ partial, int nb,
   return wave_sum(acc);
 }
 
-__global__ __launch_bounds__(BLK) void k_colsum(const double* __restrict__ partial, int nb,
-                                                int nv, double* __restrict__ out) {
-  const int c = blockIdx.x * (BLK / WAVE) + threadIdx.x / WAVE;
-  if (c >= nv) return;
-  const double s = colsum_wave(partial, nb, c);
-  if ((threadIdx.x & (WAVE - 1)) == 0) out[c] = s;
-}
-
-static void launch_colsum(const double* partial, int nb, int nv, double* out, hipStream_t s) {
-  k_colsum<<<(unsigned)cdiv(nv, BLK / WAVE), BLK, 0, s>>>(partial, nb, nv, out);
-}
-
-// Column sums in one block followed by a scalar epilogue on thread 0.
-enum : int { EP_NONE = 0, EP_BNORM = 1 };
-
-__global__ __launch_bounds__(BLK) void k_colsum_ep(const double* __restrict__ partial, int nb,
-                                                   int nv, int ep, double* __restrict__ out,
-                                                   Ctl* ctl) {
-  __shared__ double sums[LDP];
-  const int w = threadIdx.x / WAVE;
-  for (int c = w; c < nv; c += BLK / WAVE) {
-    const double s = colsum_wave(partial, nb, c);
-    if ((threadIdx.x & (WAVE - 1)) == 0) sums[c] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  if (ep == EP_NONE) {
-    for (int c = 0; c < nv; ++c) out[c] = sums[c];
-  } else if (ep == EP_BNORM) {
-    ctl->bnorm = sqrt(sums[0]);
-  }
-}
-
-// Dots of the block's rows [r0, r0 + nrows) with columns 0..ncols-1 of Q
-// (column-major, stride ldq); vl holds the block's vector (LDS).  Wave w takes
-// column groups w, w + nw, ... of CG columns whose loads are all in flight
-// together; results go to prow[col].
-template <typename T, typename V>
-__device__ inline void block_dots(const T* __restrict__ Q, int64_t ldq, int ncols, int64_t r0,
-                                  int nrows, const V* vl, double* __restrict__ prow) {
-  constexpr int CG = 8;
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-  for (int c0 = w * CG; c0 < ncols; c0 += nw * CG) {
-    double acc[CG];
+// Sum of NV per-lane values over the wave, all at once: each butterfly stage
+// exchanges half of the remaining values with the partner lane, so after
+// log2(NV) stages a lane holds one partial sum, of value index
+// (lane >> (6 - log2 NV)) & (NV - 1); plain xor stages finish the sum.
+template <int NV>
+__device__ __forceinline__ double bfly_sum(double (&a)[NV]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  int mask = WAVE / 2;
 #pragma unroll
-    for (int g = 0; g < CG; ++g) acc[g] = 0.0;
-    for (int rr = lane; rr < nrows; rr += WAVE) {
-      const double vv = (double)vl[rr];
-      T qv[CG];
+  for (int h = NV / 2; h >= 1; h /= 2) {
+    const bool upper = (lane & mask) != 0;
 #pragma unroll
-      for (int g = 0; g < CG; ++g)
-        qv[g] = (c0 + g < ncols) ? Q[(int64_t)(c0 + g) * ldq + r0 + rr] : T(0);
-#pragma unroll
-      for (int g = 0; g < CG; ++g) acc[g] += (double)qv[g] * vv;
+    for (int i = 0; i < h; ++i) {
+      const double send = upper ? a[i] : a[i + h];
+      const double keep = upper ? a[i + h] : a[i];
+      a[i] = keep + __shfl_xor(send, mask, WAVE);
     }
-#pragma unroll
-    for (int g = 0; g < CG; ++g) {
-      const double sum = wave_sum(acc[g]);
-      if (lane == 0 && c0 + g < ncols) prow[c0 + g] = sum;
-    }
+    mask >>= 1;
+  }
+  double s = a[0];
+  for (int off = mask; off >= 1; off >>= 1) s += __shfl_xor(s, off, WAVE);
+  return s;
+}
+constexpr int BF_NV = 8;
+constexpr int BF_SHIFT = 3;   // 6 - log2(BF_NV)
+
+// RPL consecutive rows of one column starting at `row` (aligned: ldq and
+// the lane's first row are multiples of RPL)
+template <int RPL>
+__device__ __forceinline__ void loadr(const float* __restrict__ col, int64_t row,
+                                      float (&q)[RPL]) {
+  if constexpr (RPL == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(col + row);
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+  } else if constexpr (RPL == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(col + row);
+    q[0] = v.x;
+    q[1] = v.y;
+  } else {
+    q[0] = col[row];
+  }
+}
+template <int RPL>
+__device__ __forceinline__ void loadr(const double* __restrict__ col, int64_t row,
+                                      double (&q)[RPL]) {
+  if constexpr (RPL == 4) {
+    const double2 a = *reinterpret_cast<const double2*>(col + row);
+    const double2 b = *reinterpret_cast<const double2*>(col + row + 2);
+    q[0] = a.x;
+    q[1] = a.y;
+    q[2] = b.x;
+    q[3] = b.y;
+  } else if constexpr (RPL == 2) {
+    const double2 a = *reinterpret_cast<const double2*>(col + row);
+    q[0] = a.x;
+    q[1] = a.y;
+  } else {
+    q[0] = col[row];
   }
 }
 
-// ----------------------------------------------------------------------------
-// First pass: v = W R_j + sigma^2 q_j (rows), partial rows of Q_{0..j}^T v.
-// ----------------------------------------------------------------------------
-template <typename T, int D>
-__global__ __launch_bounds__(BLK) void k_lz_gdots(GridT<T> g, const T* __restrict__ x, int64_t n,
-                                                  const T* __restrict__ kg, const T* __restrict__ Q,
-                                                  int64_t ldq, int j, T sigma2, T* __restrict__ vout,
-                                                  int rpb, double* __restrict__ partial,
-                                                  const Ctl* ctl) {
-  if (ctl->stop) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* vl = (T*)smem_raw;  // rpb
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  const T* qj = Q + (int64_t)j * ldq;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    T val = T(0);
-    if (row < n) {
-      val = gather_row_dev<T, D>(g, x, row, kg) + sigma2 * qj[row];
-      vout[row] = val;
-    }
-    vl[rr] = val;
-  }
-  __syncthreads();
-  const int nrows = (int)min<int64_t>(rpb, n - r0);
-  block_dots(Q, ldq, j + 1, r0, nrows, vl, partial + (size_t)blockIdx.x * LDP);
-}
-
-// ----------------------------------------------------------------------------
-// Second pass: r' = v - Q c ; partial rows of Q^T r' and ||r'||^2.
-// The Q tile of STR rows x ncols is staged in LDS so Q is read once.
-// ----------------------------------------------------------------------------
-template <typename T, int STR>
-__global__ __launch_bounds__(BLK) void k_lz_udots(int64_t n, const T* __restrict__ v,
-                                                  const T* __restrict__ Q, int64_t ldq, int j,
-                                                  const double* __restrict__ coef,
-                                                  T* __restrict__ rout, int rpb,
-                                                  double* __restrict__ partial, const Ctl* ctl) {
-  if (ctl->stop) return;
-  const int ncols = j + 1;
-  extern __shared__ unsigned char smem_raw[];
-  T* qt = (T*)smem_raw;           // ncols x STR
-  __shared__ double cl[MAXK];
-  __shared__ double dacc[MAXK + 1];
-  __shared__ T rl[STR];
-  __shared__ double scr[16];
-  for (int c = threadIdx.x; c < ncols; c += BLK) {
-    cl[c] = coef[c];
-    dacc[c] = 0.0;
-  }
-  __syncthreads();
+// prow[c] = sum over the block's 64 RPL rows of Q[c][row] * vv (c < ncols);
+// the lane's rows are rowL..rowL+RPL-1 with values vv; wave w takes
+// c = w, w+4, ...  Rows past the GP's n hold zeros in Q and vv.
+template <typename T, int RPL>
+__device__ __forceinline__ void coldots(const T* __restrict__ Q, int64_t ldq, int ncols,
+                                        int64_t rowL, const double (&vv)[RPL],
+                                        double* __restrict__ prow) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  double rr_acc = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  for (int st = 0; st < rpb; st += STR) {
-    const int64_t rs = r0 + st;
-    for (int t = threadIdx.x; t < STR; t += BLK) {
-      const int64_t row = rs + t;
-      const bool ok = row < n && st + t < rpb;
-      double proj = 0.0;
-      for (int c0 = 0; c0 < ncols; c0 += 16) {
-        T qv[16];
+  for (int base = w; base < ncols; base += 4 * BF_NV) {
+    T q[BF_NV][RPL];
 #pragma unroll
-        for (int gq = 0; gq < 16; ++gq)
-          qv[gq] = (ok && c0 + gq < ncols) ? Q[(int64_t)(c0 + gq) * ldq + row] : T(0);
-#pragma unroll
-        for (int gq = 0; gq < 16; ++gq) {
-          if (c0 + gq < ncols) {
-            qt[(c0 + gq) * STR + t] = qv[gq];
-            proj += (double)qv[gq] * cl[c0 + gq];
-          }
-        }
-      }
-      T r = T(0);
-      if (ok) {
-        r = (T)((double)v[row] - proj);
-        rout[row] = r;
-        rr_acc += (double)r * (double)r;
-      }
-      rl[t] = r;
+    for (int i = 0; i < BF_NV; ++i) {
+      const int c = min(base + 4 * i, ncols - 1);
+      loadr<RPL>(Q + (int64_t)c * ldq, rowL, q[i]);
     }
-    __syncthreads();
-    for (int c = w; c < ncols; c += BLK / WAVE) {
-      double a = 0.0;
+    double a[BF_NV];
 #pragma unroll
-      for (int q = 0; q < STR / WAVE; ++q)
-        a += (double)qt[c * STR + lane + q * WAVE] * (double)rl[lane + q * WAVE];
-      a = wave_sum(a);
-      if (lane == 0) dacc[c] += a;
+    for (int i = 0; i < BF_NV; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) s += (double)q[i][r] * vv[r];
+      a[i] = (base + 4 * i < ncols) ? s : 0.0;
     }
-    __syncthreads();
+    const double tot = bfly_sum<BF_NV>(a);
+    const int c = base + 4 * ((lane >> BF_SHIFT) & (BF_NV - 1));
+    if ((lane & ((1 << BF_SHIFT) - 1)) == 0 && c < ncols) prow[c] = tot;
   }
-  const double rrb = block_sum(rr_acc, scr);
-  double* prow = partial + (size_t)blockIdx.x * LDP;
-  for (int c = threadIdx.x; c < ncols; c += BLK) prow[c] = dacc[c];
+}
+
+// red[w][RPL lane + r] = sum over the wave's columns c (w, w+4, ...) of
+// Q[c][rowL + r] * cl[c]; the caller adds the four waves' rows in wave order.
+template <typename T, int RPL>
+__device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, int ncols,
+                                        int64_t rowL, const double* __restrict__ cl,
+                                        double (*red)[RB]) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  double acc[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) acc[r] = 0.0;
+  for (int base = w; base < ncols; base += 4 * BF_NV) {
+    T q[BF_NV][RPL];
+#pragma unroll
+    for (int i = 0; i < BF_NV; ++i) {
+      const int c = min(base + 4 * i, ncols - 1);
+      loadr<RPL>(Q + (int64_t)c * ldq, rowL, q[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < BF_NV; ++i) {
+      const int c = base + 4 * i;
+      const double f = c < ncols ? cl[min(c, ncols - 1)] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r] += (double)q[i][r] * f;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
+}
+
+// this lane's RPL values of a per-block row vector staged in LDS
+template <int RPL>
+__device__ __forceinline__ void lane_rows(const double* vl, double (&vv)[RPL]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) vv[r] = vl[RPL * lane + r];
+}
+
+// Column sums of per-block partial rows, batched: out[c] = sum_b partial[b][c]
+// for c < nv + nv_add; one wave per column.
+struct SumJob {
+  const double* partial;
+  double* out;
+  const Ctl* ctl;
+  int nb;
+  int nv;
+};
+
+__global__ __launch_bounds__(BLK) void k_colsum(Tab tab, const SumJob* __restrict__ jobs,
+                                                int nv_add, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SumJob& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const int c = lb * (BLK / WAVE) + threadIdx.x / WAVE;
+  if (c >= J.nv + nv_add) return;
+  const double s = colsum_wave(J.partial, J.nb, c);
+  if ((threadIdx.x & (WAVE - 1)) == 0) J.out[c] = s;
+}
+
+// Rows per lane of the row kernels for a run over `rows` rows in total: 4
+// (256-row blocks, 16-byte loads) while that still gives >= 256 blocks,
+// else 1 (64-row blocks) so small problems still spread over the chip.
+// LOVE_ROWS_PER_LANE=1|4 overrides (tuning).
+static int rows_per_lane(int64_t rows) {
+  const char* env = std::getenv("LOVE_ROWS_PER_LANE");
+  if (env && (env[0] == '1' || env[0] == '4')) return env[0] - '0';
+  return cdiv(rows, 256) >= 256 ? 4 : 1;
+}
+
+// launch over G GPs with nv_g + nv_add columns each (nv_g equal to the jobs' nv)
+static void launch_colsum(const SumJob* jobs, const std::vector<int>& nv, int nv_add, int mode,
+                          hipStream_t s) {
+  std::vector<int64_t> nbk(nv.size());
+  for (size_t g = 0; g < nv.size(); ++g) nbk[g] = cdiv(std::max(nv[g] + nv_add, 0), BLK / WAVE);
+  const Tab t = make_tab(nbk);
+  if (tab_blocks(t)) k_colsum<<<tab_blocks(t), BLK, 0, s>>>(t, jobs, nv_add, mode);
+}
+
+// ----------------------------------------------------------------------------
+// Lanczos steps (batched over GPs; LzJob per GP)
+// ----------------------------------------------------------------------------
+// Row kernels run on blocks of 64 RPL rows (RPL rows per lane): threads
+// t < 64 RPL own row r0 + t in the per-row phases; ldq is a multiple of 256.
+// partial[lb][0] = sum of v^2 over the block's rows
+template <typename T, int RPL>
+__global__ __launch_bounds__(BLK) void k_lz_norm(Tab tab, const LzJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  __shared__ double scr[16];
+  constexpr int RBK = WAVE * RPL;
+  const int64_t row = (int64_t)lb * RBK + threadIdx.x;
+  const double v = (threadIdx.x < RBK && row < J.n) ? (double)J.v[row] : 0.0;
+  const double s = block_sum(v * v, scr);
+  if (threadIdx.x == 0) J.partial[(size_t)lb * LDP] = s;
+}
+
+// ctl->bnorm = sqrt(sum_b partial[b][0]); one block of one wave per GP
+template <typename T>
+__global__ void k_lz_bnorm(Tab tab, const LzJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  const double s = colsum_wave(J.partial, J.nb, 0);
+  if (threadIdx.x == 0) J.ctl->bnorm = sqrt(s);
+}
+
+// q_0 = v / ||v|| (zeros on the padding rows n..ldq-1)
+template <typename T, int RPL>
+__global__ __launch_bounds__(BLK) void k_lz_start(Tab tab, const LzJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  constexpr int RBK = WAVE * RPL;
+  if (threadIdx.x >= RBK) return;
+  const int64_t row = (int64_t)lb * RBK + threadIdx.x;
+  const double b = J.ctl->bnorm;
+  J.Q[row] = row < J.n ? (T)((double)J.v[row] / b) : T(0);
+}
+
+// First pass: v = W R_j + sigma^2 q_j (rows), partial rows of Q_{0..j}^T v.
+template <typename T, int D, int RPL>
+__global__ __launch_bounds__(BLK) void k_lz_gdots(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                  int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.ctl->stop) return;
+  constexpr int RBK = WAVE * RPL;
+  __shared__ double vl[RBK];
+  const int64_t r0 = (int64_t)lb * RBK;
+  const int64_t n = J.n;
+  if (threadIdx.x < RBK) {
+    const int64_t row = r0 + threadIdx.x;
+    double val = 0.0;
+    if (row < n) {
+      const T* qj = J.Q + (int64_t)j * J.ldq;
+      const T vv = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) + J.sigma2 * qj[row];
+      J.v[row] = vv;
+      val = (double)vv;
+    }
+    vl[threadIdx.x] = val;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  double vv[RPL];
+  lane_rows<RPL>(vl, vv);
+  coldots<T, RPL>(J.Q, J.ldq, j + 1, r0 + RPL * lane, vv, J.partial + (size_t)lb * LDP);
+}
+
+// Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].
+template <typename T, int RPL>
+__global__ __launch_bounds__(BLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                  int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.ctl->stop) return;
+  constexpr int RBK = WAVE * RPL;
+  __shared__ double cl[MAXK];
+  __shared__ double red[4][RB];
+  __shared__ double rl[RBK];
+  __shared__ double scr[16];
+  const int ncols = j + 1;
+  for (int c = threadIdx.x; c < ncols; c += BLK) cl[c] = J.coef[c];
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
+  colproj<T, RPL>(J.Q, J.ldq, ncols, rowL, cl, red);
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int64_t row = r0 + t;
+  double rv = 0.0;
+  if (t < RBK) {
+    if (row < J.n) {
+      const double proj = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+      const T r = (T)((double)J.v[row] - proj);
+      J.r[row] = r;
+      rv = (double)r;
+    }
+    rl[t] = rv;
+  }
+  const double rrb = block_sum(rv * rv, scr);
+  __syncthreads();
+  double vv[RPL];
+  lane_rows<RPL>(rl, vv);
+  double* prow = J.partial + (size_t)lb * LDP;
+  coldots<T, RPL>(J.Q, J.ldq, ncols, rowL, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
 
 // alpha_j, beta_j, stop test (every block, identically), then
-// q_{j+1} = (r' - Q c2) / beta_j.  Block 0 records the step.
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_lz_finalize(int64_t n, const T* __restrict__ r,
-                                                     T* __restrict__ Q, int64_t ldq, int j,
-                                                     const double* __restrict__ coef,
-                                                     const double* __restrict__ c2rr,
-                                                     double* __restrict__ alpha,
-                                                     double* __restrict__ beta,
-                                                     double* __restrict__ amax_hist, double tol,
-                                                     int klast, Ctl* ctl) {
+// q_{j+1} = (r' - Q c2) / beta_j on rows 0..ldq-1 (zeros past n).  Block 0
+// records the step.  At j = k - 1 the run stops (no new vector).
+template <typename T, int RPL>
+__global__ __launch_bounds__(BLK) void k_lz_finalize(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                     int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  Ctl* ctl = J.ctl;
   if (ctl->stop) return;
+  constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
+  __shared__ double red[4][RB];
   __shared__ double s_beta;
   __shared__ int s_stop;
+  const double* c2rr = J.c2;
   for (int c = threadIdx.x; c <= j; c += BLK) cl[c] = c2rr[c];
   if (threadIdx.x == 0) {
     double c2n = 0.0;
     for (int c = 0; c <= j; ++c) c2n += c2rr[c] * c2rr[c];
-    const double a = coef[j] + c2rr[j];
+    const double a = J.coef[j] + c2rr[j];
     const double b2 = c2rr[j + 1] - c2n;
     const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
-    const double amax = fmax(j > 0 ? amax_hist[j - 1] : 0.0, fabs(a));
+    const double amax = fmax(j > 0 ? J.amax[j - 1] : 0.0, fabs(a));
     int stop = 0;
     unsigned st = 0;
     int keff = j + 1;
@@ -239,16 +369,20 @@ __global__ __launch_bounds__(BLK) void k_lz_finalize(int64_t n, const T* __restr
       stop = 1;
       st = SF_NONFINITE;
       keff = j;
-    } else if (j < klast && !(b > tol * amax)) {
+    } else if (j < J.klast && !(b > J.tol * amax)) {
       stop = 1;
       st = SF_BREAKDOWN;
+    } else if (j >= J.klast) {
+      stop = 1;
     }
     s_beta = b;
     s_stop = stop;
-    if (blockIdx.x == 0) {
-      alpha[j] = a;
-      beta[j] = b;
-      amax_hist[j] = amax;
+    // Block 0 records; other blocks of this launch that read ctl->stop after
+    // it is set reach the same decision from the same inputs.
+    if (lb == 0) {
+      J.alpha[j] = a;
+      J.beta[j] = b;
+      J.amax[j] = amax;
       ctl->k_eff = keff;
       if (stop) {
         ctl->stop = 1;
@@ -257,82 +391,20 @@ __global__ __launch_bounds__(BLK) void k_lz_finalize(int64_t n, const T* __restr
     }
   }
   __syncthreads();
-  if (s_stop || j >= klast) return;
-  const double inv = 1.0 / s_beta;
-  const int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (row >= n) return;
-  double acc = (double)r[row];
-#pragma unroll 16
-  for (int c = 0; c <= j; ++c) acc -= (double)Q[(int64_t)c * ldq + row] * cl[c];
-  Q[(int64_t)(j + 1) * ldq + row] = (T)(acc * inv);
-}
-
-// ----------------------------------------------------------------------------
-// Dots of a given vector v with columns 0..ncols-1 of Q, plus v^T v, as
-// partial rows: [q_0^T v, ..., q_{ncols-1}^T v, v^T v].  With use_keff the
-// number of columns is min(ncols_max, k_eff) (missing ones written as 0).
-// ----------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_dots(int64_t n, const T* __restrict__ v,
-                                              const T* __restrict__ Q, int64_t ldq, int ncols_max,
-                                              int use_keff, int rpb, double* __restrict__ partial,
-                                              const Ctl* ctl) {
-  extern __shared__ unsigned char smem_raw[];
-  T* vl = (T*)smem_raw;
-  __shared__ double scr[16];
-  const int ncols = use_keff ? min(ncols_max, ctl->k_eff) : ncols_max;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  double ss = 0.0;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    const T val = row < n ? v[row] : T(0);
-    vl[rr] = val;
-    ss += (double)val * (double)val;
-  }
-  const double ssb = block_sum(ss, scr);
+  if (s_stop) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
+  colproj<T, RPL>(J.Q, J.ldq, j + 1, rowL, cl, red);
   __syncthreads();
-  const int nrows = (int)min<int64_t>(rpb, n - r0);
-  double* prow = partial + (size_t)blockIdx.x * LDP;
-  if (ncols > 0) block_dots(Q, ldq, ncols, r0, nrows, vl, prow);
-  for (int c = ncols + threadIdx.x; c < ncols_max; c += BLK) prow[c] = 0.0;
-  if (threadIdx.x == 0) prow[ncols_max] = ssb;
-}
-
-// out = v / ctl->bnorm
-template <typename T>
-__global__ void k_scale_by_bnorm(int64_t n, const T* __restrict__ v, T* __restrict__ out,
-                                 const Ctl* ctl) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double b = ctl->bnorm;
-  out[i] = (T)((double)v[i] / b);
-}
-
-// Cholesky of the tridiagonal T (alpha, beta) of size ctl->k_eff (one thread).
-// A non-positive pivot truncates k_eff there (SF_NOTPD, or SF_SAMPLER_TRUNC
-// when `sampler`).  rel_tol: a pivot must exceed rel_tol * max|alpha|.
-__global__ void k_tri_chol(const double* __restrict__ alpha, const double* __restrict__ beta,
-                           double* __restrict__ ldiag, double* __restrict__ lsub, Ctl* ctl,
-                           double rel_tol, int sampler) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int k = ctl->k_eff;
-  double amax = 0.0;
-  for (int i = 0; i < k; ++i) amax = fmax(amax, fabs(alpha[i]));
-  int keep = k;
-  double prev = 0.0;
-  for (int i = 0; i < k; ++i) {
-    const double piv = alpha[i] - prev * prev;
-    if (!(piv > rel_tol * amax) || !isfinite(piv)) {
-      keep = i;
-      ctl->status |= sampler ? SF_SAMPLER_TRUNC : SF_NOTPD;
-      break;
-    }
-    ldiag[i] = sqrt(piv);
-    prev = (i + 1 < k) ? beta[i] / ldiag[i] : 0.0;
-    lsub[i] = prev;
+  const int t = threadIdx.x;
+  if (t >= RBK) return;
+  const int64_t row = r0 + t;
+  double q = 0.0;
+  if (row < J.n) {
+    const double proj = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    q = ((double)J.r[row] - proj) / s_beta;
   }
-  if (sampler) ctl->k_chol = keep;
-  else ctl->k_eff = keep;
+  J.Q[(int64_t)(j + 1) * J.ldq + row] = (T)q;
 }
 
 // bf16 round-to-nearest-even from the IEEE-754 bit pattern
@@ -345,37 +417,71 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Cholesky of the tridiagonal T (alpha, beta) of size ctl->k_eff; one block
+// per GP, one thread working.  A non-positive pivot truncates k_eff there
+// (SF_NOTPD).  rel_tol: a pivot must exceed rel_tol * max|alpha|.
+template <typename T>
+__global__ void k_tri_chol(Tab tab, const LzJob<T>* __restrict__ jobs, double rel_tol) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  if (threadIdx.x != 0) return;
+  const LzJob<T>& J = jobs[gp];
+  Ctl* ctl = J.ctl;
+  const double* alpha = J.alpha;
+  const double* beta = J.beta;
+  const int k = ctl->k_eff;
+  double amax = 0.0;
+  for (int i = 0; i < k; ++i) amax = fmax(amax, fabs(alpha[i]));
+  int keep = k;
+  double prev = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double piv = alpha[i] - prev * prev;
+    if (!(piv > rel_tol * amax) || !isfinite(piv)) {
+      keep = i;
+      ctl->status |= SF_NOTPD;
+      break;
+    }
+    const double l = sqrt(piv);
+    J.ldiag[i] = l;
+    prev = (i + 1 < k) ? beta[i] / l : 0.0;
+    J.lsub[i] = prev;
+  }
+  ctl->k_eff = keep;
+}
+
 // Rt[u, :] = (L^{-1} R[:, u])^T : bidiagonal forward substitution per grid node.
 // split = 1 stores bf16 hi = rne(z), lo = rne(z - hi).
 template <typename T>
-__global__ void k_rtilde(int64_t m, const T* __restrict__ R, const double* __restrict__ ldiag,
-                         const double* __restrict__ lsub, void* __restrict__ rt,
-                         uint16_t* __restrict__ rt_lo, int kpad, int split, const Ctl* ctl) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_rtilde(Tab tab, const RtJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const RtJob<T>& J = jobs[gp];
+  const int64_t u = (int64_t)lb * blockDim.x + threadIdx.x;
+  const int64_t m = J.m;
   if (u >= m) return;
-  const int k = ctl->k_eff;
+  const int k = J.ctl->k_eff, kpad = J.kpad;
   double z = 0.0;
   for (int i = 0; i < kpad; ++i) {
     double val = 0.0;
     if (i < k) {
-      const double rv = (double)R[(int64_t)i * m + u];
-      z = (rv - (i > 0 ? lsub[i - 1] * z : 0.0)) / ldiag[i];
+      const double rv = (double)J.R[(int64_t)i * m + u];
+      z = (rv - (i > 0 ? J.lsub[i - 1] * z : 0.0)) / J.ldiag[i];
       val = z;
     }
-    if (split) {
+    if (J.split) {
       const float f = (float)val;
       const uint16_t hi = f32_to_bf16_rne(f);
       const uint16_t lo = f32_to_bf16_rne(f - bf16_to_f32(hi));
-      ((uint16_t*)rt)[u * kpad + i] = hi;
-      rt_lo[u * kpad + i] = lo;
+      ((uint16_t*)J.rt)[u * kpad + i] = hi;
+      J.rt_lo[u * kpad + i] = lo;
     } else {
-      ((T*)rt)[u * kpad + i] = (T)val;
+      ((T*)J.rt)[u * kpad + i] = (T)val;
     }
   }
 }
 
 // ----------------------------------------------------------------------------
-// Mean cache: preconditioned CG on Khat x = y (double vectors).
+// Mean cache: preconditioned CG on Khat x = y (double vectors), batched.
 //
 // Preconditioner from the Lanczos decomposition Khat Q ~ Q T that the build
 // already holds (Sec. 2.2; the Lanczos solve Q T^{-1} Q^T b of eq.
@@ -401,132 +507,141 @@ __global__ void k_rtilde(int64_t m, const T* __restrict__ R, const double* __res
 // ----------------------------------------------------------------------------
 constexpr int PAP_COL = LDP - 1;   // partial-row column of p^T Ap (clear of the dot columns)
 
-template <typename T, int D>
-__global__ __launch_bounds__(BLK) void k_cg_ap(GridT<T> g, const T* __restrict__ x, int64_t n,
-                                               const T* __restrict__ kg, const T* __restrict__ z,
-                                               T* __restrict__ p, T* __restrict__ ap, T sigma2,
-                                               int rpb, double* __restrict__ partial,
-                                               const Ctl* ctl) {
-  if (ctl->cg_done) return;
-  __shared__ double scr[16];
-  const double ratio = ctl->ratio;
-  double d = 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    if (row >= n) break;
-    const T pn = (T)((double)z[row] + ratio * (double)p[row]);
-    p[row] = pn;
-    const T a = gather_row_dev<T, D>(g, x, row, kg) + sigma2 * pn;
-    ap[row] = a;
-    d += (double)pn * (double)a;
-  }
-  const double db = block_sum(d, scr);
-  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * LDP + PAP_COL] = db;
+struct ConvJob {
+  const float* in;
+  double* out;
+  int64_t n;
+};
+__global__ void k_convert_b(Tab tab, const ConvJob* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ConvJob& J = jobs[gp];
+  const int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (i < J.n) J.out[i] = (double)J.in[i];
 }
 
-// Stage the block's new residual rows in LDS, then partial rows of
-// [q_0^T r, ..., q_{kq-1}^T r, r^T r] (columns past k_eff written as 0).
-template <typename TQ>
-__device__ inline void pcg_block_dots(const double* rl, double ssb, const TQ* __restrict__ Q,
-                                      int64_t ldq, int kq, int64_t r0, int nrows,
-                                      double* __restrict__ prow, const Ctl* ctl) {
-  const int ncols = min(kq, ctl->k_eff);
-  if (ncols > 0) block_dots(Q, ldq, ncols, r0, nrows, rl, prow);
+template <typename TQ, int D, int RPL>
+__global__ __launch_bounds__(BLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.ctl->cg_done) return;
+  __shared__ double scr[16];
+  constexpr int RBK = WAVE * RPL;
+  const double ratio = J.ctl->ratio;
+  const int64_t row = (int64_t)lb * RBK + threadIdx.x;
+  double d = 0.0;
+  if (threadIdx.x < RBK && row < J.n) {
+    const double pn = J.z[row] + ratio * J.p[row];
+    J.p[row] = pn;
+    const double a = gather_row_dev<double, D>(J.g, J.x, row, J.gm) + J.sigma2 * pn;
+    J.ap[row] = a;
+    d = pn * a;
+  }
+  const double db = block_sum(d, scr);
+  if (threadIdx.x == 0) J.partial[(size_t)lb * LDP + PAP_COL] = db;
+}
+
+// partial rows of [Q^T r, r^T r] from the block's residual rows (rl in LDS)
+template <typename TQ, int RPL>
+__device__ __forceinline__ void pcg_dots(const CgJob<TQ>& J, const double* rl, double ssb, int lb) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int kq = J.kq;
+  const int ncols = min(kq, J.ctl->k_eff);
+  double* prow = J.partial + (size_t)lb * LDP;
+  if (ncols > 0) {
+    double vv[RPL];
+    lane_rows<RPL>(rl, vv);
+    coldots<TQ, RPL>(J.Q, J.ldq, ncols, (int64_t)lb * (WAVE * RPL) + RPL * lane, vv, prow);
+  }
   for (int c = max(ncols, 0) + threadIdx.x; c < kq; c += BLK) prow[c] = 0.0;
   if (threadIdx.x == 0) prow[kq] = ssb;
 }
 
 // x = 0, r = y, p = 0, partial rows of [Q^T y, y^T y]
-template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const double* __restrict__ y,
-                                                  double* __restrict__ xs, double* __restrict__ r,
-                                                  double* __restrict__ p,
-                                                  const TQ* __restrict__ Q, int64_t ldq, int kq,
-                                                  int rpb, double* __restrict__ partial,
-                                                  const Ctl* ctl) {
-  extern __shared__ double rl[];
+template <typename TQ, int RPL>
+__global__ __launch_bounds__(BLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  constexpr int RBK = WAVE * RPL;
+  __shared__ double rl[RBK];
   __shared__ double scr[16];
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  double d = 0.0;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    double v = 0.0;
-    if (row < n) {
-      v = y[row];
-      xs[row] = 0.0;
-      r[row] = v;
-      p[row] = 0.0;
+  const int64_t row = (int64_t)lb * RBK + threadIdx.x;
+  double v = 0.0;
+  if (threadIdx.x < RBK) {
+    if (row < J.n) {
+      v = J.y[row];
+      J.xs[row] = 0.0;
+      J.r[row] = v;
+      J.p[row] = 0.0;
     }
-    rl[rr] = v;
-    d += v * v;
+    rl[threadIdx.x] = v;
   }
-  const double ssb = block_sum(d, scr);
+  const double ssb = block_sum(v * v, scr);
   __syncthreads();
-  const int nrows = (int)min<int64_t>(rpb, n - r0);
-  pcg_block_dots(rl, ssb, Q, ldq, kq, r0, nrows, partial + (size_t)blockIdx.x * LDP, ctl);
+  pcg_dots<TQ, RPL>(J, rl, ssb, lb);
 }
 
 // gamma = rz / p^T Ap (p^T Ap re-summed by every block from the partial rows
 // of k_cg_ap, one wave, fixed order); x += gamma p ; r -= gamma Ap ; dots.
-template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_update(int64_t n, double* __restrict__ xs,
-                                                    double* __restrict__ r,
-                                                    const double* __restrict__ p,
-                                                    const double* __restrict__ ap, int nb,
-                                                    const TQ* __restrict__ Q, int64_t ldq, int kq,
-                                                    int rpb, double* __restrict__ partial,
-                                                    const Ctl* ctl) {
-  if (ctl->cg_done) return;
-  extern __shared__ double rl[];
+template <typename TQ, int RPL>
+__global__ __launch_bounds__(BLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.ctl->cg_done) return;
+  constexpr int RBK = WAVE * RPL;
+  __shared__ double rl[RBK];
   __shared__ double scr[16];
   __shared__ double s_pap;
   if (threadIdx.x < WAVE) {
-    const double sum = colsum_wave(partial, nb, PAP_COL);
+    const double sum = colsum_wave(J.partial, J.nb, PAP_COL);
     if (threadIdx.x == 0) s_pap = sum;
   }
   __syncthreads();
-  const double gm = ctl->rz / s_pap;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  double d = 0.0;
-  for (int rr = threadIdx.x; rr < rpb; rr += BLK) {
-    const int64_t row = r0 + rr;
-    double v = 0.0;
-    if (row < n) {
-      xs[row] += gm * p[row];
-      v = r[row] - gm * ap[row];
-      r[row] = v;
+  const double gm = J.ctl->rz / s_pap;
+  const int64_t row = (int64_t)lb * RBK + threadIdx.x;
+  double v = 0.0;
+  if (threadIdx.x < RBK) {
+    if (row < J.n) {
+      J.xs[row] += gm * J.p[row];
+      v = J.r[row] - gm * J.ap[row];
+      J.r[row] = v;
     }
-    rl[rr] = v;
-    d += v * v;
+    rl[threadIdx.x] = v;
   }
-  const double ssb = block_sum(d, scr);
+  const double ssb = block_sum(v * v, scr);
   __syncthreads();
-  const int nrows = (int)min<int64_t>(rpb, n - r0);
-  pcg_block_dots(rl, ssb, Q, ldq, kq, r0, nrows, partial + (size_t)blockIdx.x * LDP, ctl);
+  pcg_dots<TQ, RPL>(J, rl, ssb, lb);
 }
 
-// One block.  sums = [c_0 .. c_{kq-1}, r^T r] (column sums of the update's
-// partial rows).  Convergence test on ||r|| <= tol ||y||, then d = C c,
-// rz = r^T r * rscale + c^T d and the direction ratio.  init: first call
-// (sets ||y||^2, ratio 0).
-__global__ __launch_bounds__(BLK) void k_pcg_ep(const double* __restrict__ sums, int kq,
-                                                const double* __restrict__ C, int ldc,
-                                                double* __restrict__ dout, double rscale,
-                                                double tol2, int maxit, int init, Ctl* ctl) {
+// One block per GP.  coef = [c_0 .. c_{kq-1}, r^T r] (column sums of the
+// update's partial rows).  Convergence test on ||r|| <= tol ||y||, then
+// d = C c, rz = r^T r * rscale + c^T d and the direction ratio.  init: first
+// call (sets ||y||^2, ratio 0).
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_ep(Tab tab, const CgJob<TQ>* __restrict__ jobs,
+                                                int init) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  Ctl* ctl = J.ctl;
   if (ctl->cg_done) return;
   __shared__ double cl[MAXK];
   __shared__ double scr[16];
+  const int kq = J.kq;
   const int k = min(kq, ctl->k_eff);
+  const double* sums = J.coef;
   const int t = threadIdx.x;
   if (t < k) cl[t] = sums[t];
   __syncthreads();
   double cd = 0.0;
   if (t < k) {
     double acc = 0.0;
-    const double* row = C + (size_t)t * ldc;
-    for (int j = 0; j < k; ++j) acc += row[j] * cl[j];
-    dout[t] = acc;
+    const double* row = J.cm + (size_t)t * J.kpad;
+    for (int jj = 0; jj < k; ++jj) acc += row[jj] * cl[jj];
+    J.dvec[t] = acc;
     cd = cl[t] * acc;
   }
   const double cdb = block_sum(cd, scr);
@@ -539,17 +654,17 @@ __global__ __launch_bounds__(BLK) void k_pcg_ep(const double* __restrict__ sums,
     ctl->cg_iters += 1;
   }
   ctl->rr = rr;
-  const double rz = rr * rscale + cdb;
+  const double rz = rr * J.rscale + cdb;
   if (!isfinite(rr) || !isfinite(rz)) {
     ctl->cg_done = 1;
     ctl->status |= SF_NONFINITE;
     return;
   }
-  if (!(rr > tol2 * ctl->rr0)) {
+  if (!(rr > J.tol2 * ctl->rr0)) {
     ctl->cg_done = 1;
     return;
   }
-  if (!init && ctl->cg_iters >= maxit) {
+  if (!init && ctl->cg_iters >= J.maxit) {
     ctl->cg_done = 1;
     ctl->status |= SF_CG_NOCONV;
     return;
@@ -564,49 +679,59 @@ __global__ __launch_bounds__(BLK) void k_pcg_ep(const double* __restrict__ sums,
 }
 
 // z = r * rscale + Q d  (first min(kq, k_eff) columns)
-template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_apply(int64_t n, const double* __restrict__ r,
-                                                   const TQ* __restrict__ Q, int64_t ldq, int kq,
-                                                   const double* __restrict__ dv, double rscale,
-                                                   double* __restrict__ z, const Ctl* ctl) {
-  if (ctl->cg_done) return;
+template <typename TQ, int RPL>
+__global__ __launch_bounds__(BLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.ctl->cg_done) return;
   __shared__ double dl[MAXK];
-  const int k = min(kq, ctl->k_eff);
-  for (int c = threadIdx.x; c < k; c += BLK) dl[c] = dv[c];
+  __shared__ double red[4][BLK];
+  const int k = min(J.kq, J.ctl->k_eff);
+  for (int c = threadIdx.x; c < k; c += BLK) dl[c] = J.dvec[c];
   __syncthreads();
-  const int64_t row = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (row >= n) return;
-  double acc = r[row] * rscale;
-#pragma unroll 16
-  for (int c = 0; c < k; ++c) acc += (double)Q[(int64_t)c * ldq + row] * dl[c];
-  z[row] = acc;
+  const int lane = threadIdx.x & (WAVE - 1);
+  constexpr int RBK = WAVE * RPL;
+  const int64_t r0 = (int64_t)lb * RBK;
+  if (k > 0) {
+    colproj<TQ, RPL>(J.Q, J.ldq, k, r0 + RPL * lane, dl, red);
+    __syncthreads();
+  }
+  const int t = threadIdx.x;
+  const int64_t row = r0 + t;
+  if (t >= RBK || row >= J.n) return;
+  double acc = J.r[row] * J.rscale;
+  if (k > 0) acc += red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  J.z[row] = acc;
 }
 
 // Gram matrix G = Q^T Q of the first k_eff columns, in double: per-block
 // partial kpad x kpad matrices over row slices.  Thread (ti, tj) of a 16 x 16
-// layout owns entries (ti + 16a, tj + 16b), a, b < NA = kpad / 16; rows are
-// staged through LDS in tiles of GR_TR.
+// layout owns entries (ti + 16a, tj + 16b), a, b < 8; rows are staged through
+// LDS in tiles of GR_TR.
 constexpr int GR_TR = 32;
-template <typename TQ, int NA>
-__global__ __launch_bounds__(256) void k_gram(int64_t n, const TQ* __restrict__ Q, int64_t ldq,
-                                              int64_t rpb, double* __restrict__ pg,
-                                              const Ctl* ctl) {
-  constexpr int KP = 16 * NA;
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_gram(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  constexpr int NA = 8, KP = 16 * NA;
   __shared__ double tile[GR_TR][KP + 1];
   const int t = threadIdx.x, ti = t / 16, tj = t % 16;
-  const int k = ctl->k_eff;
+  const int k = min(J.kq, J.ctl->k_eff);
+  const int kpad = J.kpad;
   double acc[NA][NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NA; ++b) acc[a][b] = 0.0;
-  const int64_t rb = (int64_t)blockIdx.x * rpb;
-  const int64_t re = min<int64_t>(rb + rpb, n);
+  const int64_t rb = (int64_t)lb * J.rpbg;
+  const int64_t re = min<int64_t>(rb + J.rpbg, J.n);
   for (int64_t r0 = rb; r0 < re; r0 += GR_TR) {
     for (int e = t; e < GR_TR * KP; e += 256) {
       const int rr = e % GR_TR, cc = e / GR_TR;
       const int64_t row = r0 + rr;
-      tile[rr][cc] = (row < re && cc < k) ? (double)Q[(int64_t)cc * ldq + row] : 0.0;
+      tile[rr][cc] = (row < re && cc < k) ? (double)J.Q[(int64_t)cc * J.ldq + row] : 0.0;
     }
     __syncthreads();
 #pragma unroll 4
@@ -623,49 +748,93 @@ __global__ __launch_bounds__(256) void k_gram(int64_t n, const TQ* __restrict__ 
     }
     __syncthreads();
   }
-  double* out = pg + (size_t)blockIdx.x * KP * KP;
+  double* out = J.pg + (size_t)lb * kpad * kpad;
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < NA; ++b) out[(size_t)(ti + 16 * a) * KP + tj + 16 * b] = acc[a][b];
+    for (int b = 0; b < NA; ++b) {
+      const int i = ti + 16 * a, jj = tj + 16 * b;
+      if (i < kpad && jj < kpad) out[(size_t)i * kpad + jj] = acc[a][b];
+    }
 }
 
-// T^{-1} from T = L L^T (bidiagonal L): thread i solves T x = e_i.
-__global__ void k_tinv(const double* __restrict__ ldiag, const double* __restrict__ lsub,
-                       double* __restrict__ tinv, int kpad, const Ctl* ctl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// T^{-1} from T = L L^T (bidiagonal L): thread i solves T x = e_i; one block
+// of MAXK threads per GP.
+template <typename TQ>
+__global__ void k_tinv(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  const int i = threadIdx.x;
+  const int kpad = J.kpad;
   if (i >= kpad) return;
-  const int k = ctl->k_eff;
-  double* col = tinv + (size_t)i * kpad;
-  for (int j = 0; j < kpad; ++j) col[j] = 0.0;
+  const int k = min(J.kq, J.ctl->k_eff);
+  const double* ldiag = J.ldiag;
+  const double* lsub = J.lsub;
+  double* col = J.tinv + (size_t)i * kpad;
+  for (int jj = 0; jj < kpad; ++jj) col[jj] = 0.0;
   if (i >= k) return;
   // forward: L w = e_i (w_j = 0 for j < i)
   double w = 1.0 / ldiag[i];
   col[i] = w;
-  for (int j = i + 1; j < k; ++j) {
-    w = -lsub[j - 1] * w / ldiag[j];
-    col[j] = w;
+  for (int jj = i + 1; jj < k; ++jj) {
+    w = -lsub[jj - 1] * w / ldiag[jj];
+    col[jj] = w;
   }
   // backward: L^T x = w
   double xn = col[k - 1] / ldiag[k - 1];
   col[k - 1] = xn;
-  for (int j = k - 2; j >= 0; --j) {
-    xn = (col[j] - lsub[j] * xn) / ldiag[j];
-    col[j] = xn;
+  for (int jj = k - 2; jj >= 0; --jj) {
+    xn = (col[jj] - lsub[jj] * xn) / ldiag[jj];
+    col[jj] = xn;
   }
 }
 
 // C = T^{-1} - (2 I - G) / sigma^2 with G summed from the k_gram partials in
-// block order.
-__global__ void k_pcg_matrix(const double* __restrict__ pg, int nbg, const double* __restrict__ tinv,
-                             double* __restrict__ cm, int kpad, double inv_s2, const Ctl* ctl) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// block order; ortho = max |G - I| (bit patterns of non-negative doubles
+// order like unsigned integers).
+template <typename TQ>
+__global__ void k_pcg_matrix(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  const int kpad = J.kpad;
+  const int e = lb * blockDim.x + threadIdx.x;
   if (e >= kpad * kpad) return;
-  const int i = e / kpad, j = e % kpad;
-  const int k = ctl->k_eff;
+  const int i = e / kpad, jj = e % kpad;
+  const int k = min(J.kq, J.ctl->k_eff);
   double gsum = 0.0;
-  for (int b = 0; b < nbg; ++b) gsum += pg[(size_t)b * kpad * kpad + e];
-  cm[e] = (i < k && j < k) ? tinv[e] - ((i == j ? 2.0 : 0.0) - gsum) * inv_s2 : 0.0;
+  for (int b = 0; b < J.nbg; ++b) gsum += J.pg[(size_t)b * kpad * kpad + e];
+  const bool in = i < k && jj < k;
+  J.cm[e] = in ? J.tinv[e] - ((i == jj ? 2.0 : 0.0) - gsum) / J.sigma2 : 0.0;
+  if (in && J.ortho) {
+    const double dev = fabs(gsum - (i == jj ? 1.0 : 0.0));
+    atomicMax((unsigned long long*)J.ortho, (unsigned long long)__double_as_longlong(dev));
+  }
+}
+
+// flag = 1 when every GP's CG is done; one block
+template <typename TQ>
+__global__ void k_cg_alldone(int G, const CgJob<TQ>* __restrict__ jobs, int* flag) {
+  __shared__ int all;
+  if (threadIdx.x == 0) all = 1;
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += blockDim.x)
+    if (!jobs[g].ctl->cg_done) atomicAnd(&all, 0);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = all;
+}
+
+// a[u] = gm[u] in the cache precision
+template <typename TQ>
+__global__ void k_cg_store_a(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  const int64_t u = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (u >= J.m) return;
+  if (J.a_fp64) ((double*)J.a)[u] = J.gm[u];
+  else ((float*)J.a)[u] = (float)J.gm[u];
 }
 
 __global__ void k_ctl_init(Ctl* ctl) {
@@ -673,279 +842,13 @@ __global__ void k_ctl_init(Ctl* ctl) {
   *ctl = z;
 }
 
-// ----------------------------------------------------------------------------
-// Host orchestration
-// ----------------------------------------------------------------------------
-struct Work {
-  double* partial = nullptr;   // nb x LDP
-  double* coef = nullptr;      // LDP
-  double* c2 = nullptr;        // LDP
-  double* ldiag = nullptr;
-  double* lsub = nullptr;
-  double* scalar = nullptr;    // LDP
-  double* amax = nullptr;      // LDP
-  int rpb = BLK;
-  int nb = 0;
-};
-
-static love_status work_alloc(love_cache* c, Work& wk, int64_t rows, std::vector<void*>& tmp,
-                              hipStream_t s) {
-  // rows per block: 256 x t for big row counts (at most ~512 blocks), else a
-  // multiple of 64 giving ~256-384 blocks so small problems still fill the chip
-  if (rows >= (int64_t)BLK * 256) wk.rpb = (int)(BLK * cdiv(rows, (int64_t)BLK * 512));
-  else wk.rpb = (int)(64 * std::max<int64_t>(1, cdiv(rows, (int64_t)64 * 256)));
-  wk.nb = (int)cdiv(rows, wk.rpb);
-  size_t bytes = sizeof(double) * ((size_t)wk.nb * LDP + 6 * LDP);
-  char* p = nullptr;
-  LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
-  tmp.push_back(p);
-  wk.partial = (double*)p;
-  wk.coef = wk.partial + (size_t)wk.nb * LDP;
-  wk.c2 = wk.coef + LDP;
-  wk.ldiag = wk.c2 + LDP;
-  wk.lsub = wk.ldiag + LDP;
-  wk.scalar = wk.lsub + LDP;
-  wk.amax = wk.scalar + LDP;
-  return LOVE_OK;
-}
-
-template <typename T>
-static void set_smem_limits() {
-  static bool done = false;
-  if (done) return;
-  done = true;
-  (void)hipFuncSetAttribute((const void*)k_lz_udots<T, (sizeof(T) == 8 ? 128 : 256)>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192);
-}
-
-// Mean cache a = K W^T Khat^{-1} y (eq. pred_mean_ski).  The solve runs in
-// double whatever the cache precision: in float the true residual of CG
-// stalls at ~1e-3 relative on the 1e5-point workload (rounding of the
-// operator's float sums times its condition number ~1e5), which leaves the
-// mean wrong in the third digit.  Preconditioned by the Lanczos
-// decomposition unless LOVE_FLAG_PLAIN_CG.
-template <typename T, int D>
-static love_status mean_solve(love_cache* c, const T* Q, int64_t ldq, Work& wk,
-                              std::vector<void*>& tmp, hipStream_t s) {
-  ProfScope ps("mean_cg", s);
-  const int64_t n = c->n, m = c->m;
-  const bool plain = (c->cfg.flags & LOVE_FLAG_PLAIN_CG) != 0;
-  const int kq = plain ? 0 : c->k;          // preconditioner columns (<= k_eff at run time)
-  const int kpad = c->kpad;
-  const unsigned nbr = (unsigned)cdiv(n, BLK);
-  const int nbg = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(n, 128)));
-  const int64_t rpbg = cdiv(n, (int64_t)nbg);
-  Ctl* ctl = c->ctl;
-  double *x64, *y64, *xs, *rr, *zz, *pp, *ap, *gv, *gm, *tsc, *pg = nullptr, *tinv = nullptr,
-                                                              *cm = nullptr;
-  {
-    const bool own = sizeof(T) != 8;
-    const size_t pre = plain ? 0 : ((size_t)nbg + 2) * kpad * kpad;
-    size_t bytes = sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 5 * (size_t)ldq +
-                                     2 * (size_t)m + (size_t)toeplitz_scratch_elems(c) + pre);
-    char* p = nullptr;
-    LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
-    tmp.push_back(p);
-    double* q = (double*)p;
-    if (own) {
-      x64 = q;
-      y64 = x64 + (size_t)n * c->d;
-      q = y64 + n;
-      launch_convert<T, double>((const T*)c->x, x64, n * c->d, s);
-      launch_convert<T, double>((const T*)c->y, y64, n, s);
-    } else {
-      x64 = (double*)c->x;
-      y64 = (double*)c->y;
-    }
-    xs = q;
-    rr = xs + ldq;
-    zz = rr + ldq;
-    pp = zz + ldq;
-    ap = pp + ldq;
-    gv = ap + ldq;
-    gm = gv + m;
-    tsc = gm + m;
-    if (!plain) {
-      pg = tsc + toeplitz_scratch_elems(c);
-      tinv = pg + (size_t)nbg * kpad * kpad;
-      cm = tinv + (size_t)kpad * kpad;
-    }
-  }
-  GridT<double> g = make_grid<double>(c);
-  const double sigma2 = c->cfg.noise;
-  const double rscale = plain ? 1.0 : 1.0 / sigma2;
-  const double cgtol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
-  const double tol2 = cgtol * cgtol;
-  const int maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
-  const size_t shm = sizeof(double) * (size_t)wk.rpb;
-  if (!plain) {
-    if (kpad == 64)
-      k_gram<T, 4><<<nbg, 256, 0, s>>>(n, Q, ldq, rpbg, pg, ctl);
-    else
-      k_gram<T, 8><<<nbg, 256, 0, s>>>(n, Q, ldq, rpbg, pg, ctl);
-    k_tinv<<<1, kpad, 0, s>>>(wk.ldiag, wk.lsub, tinv, kpad, ctl);
-    k_pcg_matrix<<<(unsigned)cdiv(kpad * kpad, 256), 256, 0, s>>>(pg, nbg, tinv, cm, kpad,
-                                                                   1.0 / sigma2, ctl);
-  }
-  k_pcg_init<T><<<wk.nb, BLK, shm, s>>>(n, y64, xs, rr, pp, Q, ldq, kq, wk.rpb, wk.partial, ctl);
-  launch_colsum(wk.partial, wk.nb, kq + 1, wk.coef, s);
-  k_pcg_ep<<<1, BLK, 0, s>>>(wk.coef, kq, cm, kpad, wk.c2, rscale, tol2, maxit, 1, ctl);
-  k_pcg_apply<T><<<nbr, BLK, 0, s>>>(n, rr, Q, ldq, kq, wk.c2, rscale, zz, ctl);
-  Ctl hctl;
-  int it = 0;
-  const int chunk = plain ? 8 : 4;
-  while (it < maxit) {
-    for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
-      launch_scatter<double>(c, zz, gv, pp, ctl, 2 | 4, s, x64);
-      toeplitz_apply<double>(c, gv, gm, tsc, ctl, 2, s);
-      k_cg_ap<double, D><<<wk.nb, BLK, 0, s>>>(g, x64, n, gm, zz, pp, ap, sigma2, wk.rpb,
-                                               wk.partial, ctl);
-      k_pcg_update<T><<<wk.nb, BLK, shm, s>>>(n, xs, rr, pp, ap, wk.nb, Q, ldq, kq, wk.rpb,
-                                              wk.partial, ctl);
-      launch_colsum(wk.partial, wk.nb, kq + 1, wk.coef, s);
-      k_pcg_ep<<<1, BLK, 0, s>>>(wk.coef, kq, cm, kpad, wk.c2, rscale, tol2, maxit, 0, ctl);
-      k_pcg_apply<T><<<nbr, BLK, 0, s>>>(n, rr, Q, ldq, kq, wk.c2, rscale, zz, ctl);
-    }
-    LOVE_HIP_TRY(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    LOVE_HIP_TRY(hipStreamSynchronize(s));
-    if (hctl.cg_done) break;
-  }
-  launch_scatter<double>(c, xs, gv, nullptr, nullptr, 0, s, x64);
-  toeplitz_apply<double>(c, gv, gm, tsc, nullptr, 0, s);
-  if (sizeof(T) == 8) launch_convert<double, double>(gm, (double*)c->a, m, s);
-  else launch_convert<double, float>(gm, (float*)c->a, m, s);
-  return LOVE_OK;
-}
-
-template <typename TR, int SPLIT>
-static love_status sampler_impl(love_cache* c, hipStream_t s);
-static love_status sampler_dispatch(love_cache* c, hipStream_t s);
-
-template <typename T, int D>
-static love_status lanczos_impl(love_cache* c, hipStream_t s, hipStream_t s_side) {
-  constexpr int STR = (sizeof(T) == 8) ? 128 : 256;
-  set_smem_limits<T>();
-  const int64_t n = c->n, m = c->m;
-  const int k = c->k;
-  const int64_t ldq = cdiv(n, 64) * 64;
-  GridT<T> g = make_grid<T>(c);
-  const T* x = (const T*)c->x;
-  const T sigma2 = (T)c->cfg.noise;
-  std::vector<void*> tmp;
-  Work wk;
-  love_status st = work_alloc(c, wk, n, tmp, s);
-  if (st != LOVE_OK) return st;
-  // transient buffers: Q (n x k), R (k x m), v, r, grid vectors
-  T *Q, *R, *v, *r, *gv, *gm, *tsc;
-  {
-    size_t bytes = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
-                                (size_t)toeplitz_scratch_elems(c));
-    char* p = nullptr;
-    LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
-    tmp.push_back(p);
-    Q = (T*)p;
-    R = Q + (size_t)ldq * k;
-    v = R + (size_t)k * m;
-    r = v + ldq;
-    gv = r + ldq;
-    gm = gv + m;
-    tsc = gm + m;
-  }
-  Ctl* ctl = c->ctl;
-  k_ctl_init<<<1, 1, 0, s>>>(ctl);
-  const unsigned nbr = (unsigned)cdiv(n, BLK);
-  // probe b = (1/m) W K 1 ; q_0 = b / ||b||
-  {
-    ProfScope ps("probe", s);
-    launch_fill<T>(gv, T(1.0 / (double)m), m, s);
-    toeplitz_apply<T>(c, gv, gm, tsc, nullptr, 0, s);
-    launch_gather<T>(c, gm, nullptr, T(0), v, nullptr, s);
-    k_dots<T><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(n, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
-    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, ctl);
-    k_scale_by_bnorm<T><<<nbr, BLK, 0, s>>>(n, v, Q, ctl);
-  }
-  const double tol = c->tol_lanczos;
-  for (int j = 0; j < k; ++j) {
-    launch_scatter<T>(c, Q + (size_t)j * ldq, gv, nullptr, ctl, 1, s);
-    toeplitz_apply<T>(c, gv, R + (size_t)j * m, tsc, ctl, 1, s);
-    {
-      ProfScope ps("lz_gdots", s);
-      k_lz_gdots<T, D><<<wk.nb, BLK, sizeof(T) * wk.rpb, s>>>(
-          g, x, n, R + (size_t)j * m, Q, ldq, j, sigma2, v, wk.rpb, wk.partial, ctl);
-    }
-    launch_colsum(wk.partial, wk.nb, j + 1, wk.coef, s);
-    {
-      ProfScope ps("lz_udots", s);
-      const size_t shm = sizeof(T) * (size_t)(j + 1) * STR;
-      k_lz_udots<T, STR><<<wk.nb, BLK, shm, s>>>(n, v, Q, ldq, j, wk.coef, r, wk.rpb, wk.partial,
-                                                 ctl);
-    }
-    launch_colsum(wk.partial, wk.nb, j + 2, wk.c2, s);
-    {
-      ProfScope ps("lz_finalize", s);
-      k_lz_finalize<T><<<nbr, BLK, 0, s>>>(n, r, Q, ldq, j, wk.coef, wk.c2, c->alpha, c->beta,
-                                           wk.amax, tol, k - 1, ctl);
-    }
-  }
-  // T = L L^T ; Rt = (L^{-1} R)^T
-  k_tri_chol<<<1, 64, 0, s>>>(c->alpha, c->beta, wk.ldiag, wk.lsub, ctl, 0.0, 0);
-  {
-    ProfScope ps("rtilde", s);
-    const int split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
-    k_rtilde<T><<<cdiv(m, 256), 256, 0, s>>>(m, R, wk.ldiag, wk.lsub, c->rt, (uint16_t*)c->rt_lo,
-                                             c->kpad, split, ctl);
-  }
-  // The sampler (grid space, needs Rt) and the mean solve (needs Q) are
-  // independent chains of small kernels: the sampler runs on a side stream
-  // concurrently with the mean CG, and the caller's stream waits for it.
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  const bool side = c->ks > 0 && s_side != nullptr;
-  if (c->ks > 0) {
-    if (side) {
-      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
-      LOVE_HIP_TRY(hipEventRecord(ev_fork, s));
-      LOVE_HIP_TRY(hipStreamWaitEvent(s_side, ev_fork, 0));
-    }
-    love_status ss = sampler_dispatch(c, side ? s_side : s);
-    if (ss != LOVE_OK) return ss;
-    if (side) LOVE_HIP_TRY(hipEventRecord(ev_join, s_side));
-  }
-  // mean cache a = K W^T Khat^{-1} y
-  if (!(c->cfg.flags & LOVE_FLAG_NO_MEAN)) {
-    love_status ms = mean_solve<T, D>(c, Q, ldq, wk, tmp, s);
-    if (ms != LOVE_OK) return ms;
-  }
-  if (side) {
-    LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
-    (void)hipEventDestroy(ev_fork);
-    (void)hipEventDestroy(ev_join);
-  }
-  for (void* p : tmp) (void)hipFreeAsync(p, s);
-  LOVE_HIP_TRY(hipGetLastError());
-  return LOVE_OK;
-}
-
-template <typename T>
-love_status build_lanczos_and_mean(love_cache* c, hipStream_t s, hipStream_t s_side) {
-  switch (c->d) {
-    case 1: return lanczos_impl<T, 1>(c, s, s_side);
-    case 2: return lanczos_impl<T, 2>(c, s, s_side);
-    case 3: return lanczos_impl<T, 3>(c, s, s_side);
-    case 4: return lanczos_impl<T, 4>(c, s, s_side);
-  }
-  return LOVE_EINVAL;
-}
-template love_status build_lanczos_and_mean<float>(love_cache*, hipStream_t, hipStream_t);
-template love_status build_lanczos_and_mean<double>(love_cache*, hipStream_t, hipStream_t);
-
 // ============================================================================
 // Sampling cache (Sec. 3.3): Lanczos on B = K - R^T R' = K - Rt Rt^T in grid
 // space (eq. lancapprox), probe b' = (1/m) B 1, then a factor S with
 // S S^T = Q' T' Q'^T (eq. pred_covar_ski_interp_form).  B is the difference
 // of two nearly equal matrices (the posterior covariance is 1e-4..1e-6 of the
 // prior here), so this Lanczos runs in double whatever the cache precision;
-// Rt is read in its stored precision and widened.
+// Rt is read in its stored precision and widened.  One GP at a time.
 // ============================================================================
 template <typename TR, int SPLIT>
 __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t idx) {
@@ -957,19 +860,22 @@ __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t i
   }
 }
 
-// partial rows of s = Rt^T v (columns < keff); lanes own columns, waves split the rows.
-template <typename TR, int SPLIT>
+
+// partial rows of s = Rt^T v (columns < keff) over blocks of 64 RPL grid
+// rows; lanes own columns, waves split the rows.
+template <typename TR, int SPLIT, int RPL>
 __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
                                                  const void* __restrict__ rt,
                                                  const uint16_t* __restrict__ rt_lo, int kpad,
-                                                 const Ctl* ctl_main, int rpb,
+                                                 const Ctl* ctl_main,
                                                  double* __restrict__ partial, const Ctl* ctl) {
-  if (ctl && ctl->stop) return;
+  if (ctl->stop) return;
+  constexpr int RBK = WAVE * RPL;
   __shared__ double wsum[BLK / WAVE][MAXK];
   const int keff = ctl_main->k_eff;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
-  const int64_t r1 = min<int64_t>(r0 + rpb, m);
+  const int64_t r0 = (int64_t)blockIdx.x * RBK;
+  const int64_t r1 = min<int64_t>(r0 + RBK, m);
   double a0 = 0.0, a1 = 0.0;
   for (int64_t u = r0 + w; u < r1; u += BLK / WAVE) {
     const double vu = v[u];
@@ -987,8 +893,10 @@ __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __rest
   }
 }
 
-// v = kv - Rt s (grid rows); partial rows of Q'_{0..ncols-1}^T v (none for ncols = 0)
-template <typename TR, int SPLIT>
+// v = kv - Rt s on the block's 64 RPL grid rows, then partial rows of
+// Q'_{0..ncols-1}^T v (none for ncols = 0).  Wave w takes 16 rows at a time:
+// lanes own columns of Rt, the 16 row dots are reduced by one butterfly.
+template <typename TR, int SPLIT, int RPL>
 __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* __restrict__ kv,
                                                        const void* __restrict__ rt,
                                                        const uint16_t* __restrict__ rt_lo,
@@ -996,35 +904,47 @@ __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* 
                                                        const double* __restrict__ sv,
                                                        const double* __restrict__ Q, int64_t ldq,
                                                        int ncols, double* __restrict__ vout,
-                                                       int rpb, double* __restrict__ partial,
+                                                       double* __restrict__ partial,
                                                        const Ctl* ctl) {
   if (ctl->stop) return;
-  extern __shared__ unsigned char smem_raw[];
-  double* vl = (double*)smem_raw;
+  constexpr int RBK = WAVE * RPL;
+  constexpr int NR = 16;                 // rows per butterfly
+  __shared__ double vl[RBK];
   __shared__ double sl[MAXK];
   const int keff = ctl_main->k_eff;
   for (int c = threadIdx.x; c < keff; c += BLK) sl[c] = sv[c];
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r0 = (int64_t)blockIdx.x * RBK;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const double s0 = lane < keff ? sl[lane] : 0.0;
   const double s1 = lane + WAVE < keff ? sl[lane + WAVE] : 0.0;
-  for (int rr = w; rr < rpb; rr += BLK / WAVE) {   // one wave per grid row
-    const int64_t u = r0 + rr;
-    double val = 0.0;
-    if (u < m) {
-      double part = 0.0;
-      if (lane < keff) part += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane) * s0;
-      if (lane + WAVE < keff) part += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE) * s1;
-      val = kv[u] - wave_sum(part);
-      if (lane == 0) vout[u] = val;
+  for (int rb = w * NR; rb < RBK; rb += 4 * NR) {
+    double part[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int64_t u = min<int64_t>(r0 + rb + i, m - 1);
+      double p = 0.0;
+      if (lane < keff) p += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane) * s0;
+      if (lane + WAVE < keff) p += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE) * s1;
+      part[i] = p;
     }
-    if (lane == 0) vl[rr] = val;
+    const double tot = bfly_sum<NR>(part);
+    if ((lane & 3) == 0) {
+      const int i = (lane >> 2) & (NR - 1);
+      const int64_t u = r0 + rb + i;
+      double val = 0.0;
+      if (u < m) {
+        val = kv[u] - tot;
+        vout[u] = val;
+      }
+      vl[rb + i] = val;
+    }
   }
   __syncthreads();
   if (ncols == 0) return;
-  const int nrows = (int)min<int64_t>(rpb, m - r0);
-  block_dots(Q, ldq, ncols, r0, nrows, vl, partial + (size_t)blockIdx.x * LDP);
+  double vv[RPL];
+  lane_rows<RPL>(vl, vv);
+  coldots<double, RPL>(Q, ldq, ncols, r0 + RPL * lane, vv, partial + (size_t)blockIdx.x * LDP);
 }
 
 // Eigen-decomposition T' = V diag(lam) V^T of the sampler's symmetric
@@ -1226,7 +1146,7 @@ __global__ __launch_bounds__(MAXK) void k_eig_vectors(const double* __restrict__
 // does everything: lane i holds d[i], d[i+64], e[i], e[i+64] in registers; the
 // scalar chase runs uniformly on all lanes (values fetched with readlane), and
 // every plane rotation is applied at once to the lane's two rows of V (held in
-// LDS), the updated column carried in registers.
+// global scratch), the updated column carried in registers.
 constexpr int EIG_MAXSWEEP = 40;
 
 __device__ inline double rl64(double v, int lane) {
@@ -1248,10 +1168,10 @@ __device__ inline void set128(double& lo, double& hi, int i, double v, int lane)
 __global__ __launch_bounds__(WAVE) void k_tri_eig(const double* __restrict__ alpha,
                                                   const double* __restrict__ beta,
                                                   double* __restrict__ vout,
-                                                  double* __restrict__ lam, Ctl* ctl) {
+                                                  double* __restrict__ lam,
+                                                  double* __restrict__ V, Ctl* ctl) {
   if (!ctl->eig_fallback) return;
-  extern __shared__ unsigned char smem_raw[];
-  double* V = (double*)smem_raw;   // column c of V at V[c * MAXK + row]
+  // V: column c at V[c * MAXK + row] (global scratch: this path is the rare one)
   __shared__ double dsh[MAXK];
   __shared__ int perm[MAXK];
   const int lane = threadIdx.x;
@@ -1391,24 +1311,21 @@ __global__ __launch_bounds__(256) void k_s_from_eig(int64_t m, const double* __r
     if (c0 + q < kspad) S[u * kspad + c0 + q] = (float)acc[q];
 }
 
-template <typename TR, int SPLIT>
+template <typename TR, int SPLIT, int RPL>
 static love_status sampler_impl(love_cache* c, hipStream_t s) {
-  set_smem_limits<double>();
   const int64_t m = c->m;
   const int ks = c->ks;
-  const int64_t ldq = cdiv(m, 64) * 64;
-  std::vector<void*> tmp;
-  Work wk;
-  love_status st = work_alloc(c, wk, m, tmp, s);
-  if (st != LOVE_OK) return st;
-  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *lasc, *dscr, *tsc;
+  const int64_t ldq = cdiv(m, RB) * RB;
+  const int64_t nb = ldq / (WAVE * RPL);
+  double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *lasc, *dscr, *tsc, *partial,
+      *coef, *c2, *amax;
+  char* buf = nullptr;
   {
-    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 5 * LDP +
-                                     3 * MAXK * MAXK + (size_t)toeplitz_scratch_elems(c));
-    char* p = nullptr;
-    LOVE_HIP_TRY(hipMallocAsync((void**)&p, bytes, s));
-    tmp.push_back(p);
-    Q = (double*)p;
+    size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 8 * LDP +
+                                     3 * MAXK * MAXK + (size_t)toeplitz_scratch_elems(c) +
+                                     (size_t)nb * LDP);
+    LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+    Q = (double*)buf;
     v = Q + (size_t)ldq * ks;
     r = v + ldq;
     kv = r + ldq;
@@ -1418,72 +1335,536 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     beta = alpha + LDP;
     lam = beta + LDP;
     lasc = lam + LDP;
-    vout = lasc + LDP;
+    coef = lasc + LDP;
+    c2 = coef + LDP;
+    amax = c2 + LDP;
+    vout = amax + LDP;
     dscr = vout + MAXK * MAXK;
     tsc = dscr + 2 * MAXK * MAXK;
+    partial = tsc + toeplitz_scratch_elems(c);
   }
   Ctl* ctl = c->ctl_s;
   const Ctl* cm = c->ctl;
+  LzJob<double> J{};
+  J.n = m;
+  J.ldq = ldq;
+  J.Q = Q;
+  J.v = v;
+  J.r = r;
+  J.partial = partial;
+  J.coef = coef;
+  J.c2 = c2;
+  J.amax = amax;
+  J.alpha = alpha;
+  J.beta = beta;
+  J.ctl = ctl;
+  J.tol = 1e-12;
+  J.klast = ks - 1;
+  J.nb = (int)nb;
+  SumJob js_rt{partial, sv, ctl, (int)nb, c->k};
+  SumJob js_coef{partial, coef, ctl, (int)nb, 1};
+  SumJob js_c2{partial, c2, ctl, (int)nb, 2};
+  JobArena A;
+  const size_t o_lz = A.add(std::vector<LzJob<double>>{J});
+  const size_t o_rt = A.add(std::vector<SumJob>{js_rt});
+  const size_t o_coef = A.add(std::vector<SumJob>{js_coef});
+  const size_t o_c2 = A.add(std::vector<SumJob>{js_c2});
+  ToepRun<double> t_probe, t_step;
+  std::vector<love_cache*> one{c};
+  toep_prepare<double>(A, t_probe, one, {gv}, {0}, {kv}, {0}, {tsc}, {ctl});
+  toep_prepare<double>(A, t_step, one, {Q}, {ldq}, {kv}, {0}, {tsc}, {ctl});
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  const LzJob<double>* dJ = A.at<LzJob<double>>(o_lz);
+  const Tab t1 = tab1(1), tnb = tab1(nb);
+  const std::vector<int> nv1{1}, nv2{2}, nvk{c->k};   // must match the jobs' nv
   k_ctl_init<<<1, 1, 0, s>>>(ctl);
-  const unsigned nbm = (unsigned)cdiv(m, BLK);
-  const size_t shm = sizeof(double) * wk.rpb;
   const uint16_t* rlo = (const uint16_t*)c->rt_lo;
   {
     ProfScope ps("sampler_probe", s);
     launch_fill<double>(gv, 1.0 / (double)m, m, s);
-    toeplitz_apply<double>(c, gv, kv, tsc, nullptr, 0, s);
-    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm, wk.rpb, wk.partial,
-                                               nullptr);
-    launch_colsum(wk.partial, wk.nb, c->k, sv, s);
-    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq,
-                                                      0, v, wk.rpb, wk.partial, ctl);
-    k_dots<double><<<wk.nb, BLK, shm, s>>>(m, v, Q, ldq, 0, 0, wk.rpb, wk.partial, ctl);
-    k_colsum_ep<<<1, BLK, 0, s>>>(wk.partial, wk.nb, 1, EP_BNORM, nullptr, ctl);
-    k_scale_by_bnorm<double><<<nbm, BLK, 0, s>>>(m, v, Q, ctl);
+    toep_run<double>(A, t_probe, 0, 1, s);
+    k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm,
+                                                            partial, ctl);
+    launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
+    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
+                                                                  sv, Q, ldq, 0, v, partial, ctl);
+    k_lz_norm<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
+    k_lz_bnorm<double><<<1, WAVE, 0, s>>>(t1, dJ);
+    k_lz_start<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
   }
-  const double tol = 1e-12;
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
-    toeplitz_apply<double>(c, qj, kv, tsc, ctl, 1, s);
-    k_rt_dots<TR, SPLIT><<<wk.nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm, wk.rpb, wk.partial,
-                                               ctl);
-    launch_colsum(wk.partial, wk.nb, c->k, sv, s);
-    k_sp_apply_dots<TR, SPLIT><<<wk.nb, BLK, shm, s>>>(m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq,
-                                                      j + 1, v, wk.rpb, wk.partial, ctl);
-    launch_colsum(wk.partial, wk.nb, j + 1, wk.coef, s);
-    k_lz_udots<double, 128><<<wk.nb, BLK, sizeof(double) * (size_t)(j + 1) * 128, s>>>(
-        m, v, Q, ldq, j, wk.coef, r, wk.rpb, wk.partial, ctl);
-    launch_colsum(wk.partial, wk.nb, j + 2, wk.c2, s);
-    k_lz_finalize<double><<<nbm, BLK, 0, s>>>(m, r, Q, ldq, j, wk.coef, wk.c2, alpha, beta,
-                                              wk.amax, tol, ks - 1, ctl);
+    toep_run<double>(A, t_step, j, 1, s);
+    k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
+                                                            partial, ctl);
+    launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
+    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
+                                                                  sv, Q, ldq, j + 1, v, partial,
+                                                                  ctl);
+    launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+    k_lz_udots<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
+    k_lz_finalize<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
   }
   {
     ProfScope pe("sampler_eig", s);
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void*)k_tri_eig,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                sizeof(double) * MAXK * MAXK);
-      attr = true;
-    }
     const int force_ql = (c->cfg.flags & LOVE_FLAG_EIG_QL) ? 1 : 0;
     k_eig_bisect<<<(unsigned)cdiv(ks, EIG_WPB), WAVE * EIG_WPB, 0, s>>>(alpha, beta, lasc, ctl);
     k_eig_vectors<<<1, MAXK, 0, s>>>(alpha, beta, lasc, vout, lam, dscr, force_ql, ctl);
-    k_tri_eig<<<1, WAVE, sizeof(double) * MAXK * MAXK, s>>>(alpha, beta, vout, lam, ctl);
+    k_tri_eig<<<1, WAVE, 0, s>>>(alpha, beta, vout, lam, dscr, ctl);
     dim3 sgrid((unsigned)cdiv(m, 256), (unsigned)cdiv(c->kspad, 16));
     k_s_from_eig<<<sgrid, 256, 0, s>>>(m, Q, ldq, vout, lam, c->S, c->kspad, ctl);
   }
-  for (void* p : tmp) (void)hipFreeAsync(p, s);
+  A.release(s);
+  LOVE_HIP_TRY(hipFreeAsync(buf, s));
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }
 
+template <int RPL>
+static love_status sampler_rpl(love_cache* c, hipStream_t s) {
+  if (c->fp64) return sampler_impl<double, 0, RPL>(c, s);
+  if (c->cfg.precision == LOVE_P_FP32_BF16SPLIT) return sampler_impl<float, 1, RPL>(c, s);
+  return sampler_impl<float, 0, RPL>(c, s);
+}
+
 static love_status sampler_dispatch(love_cache* c, hipStream_t s) {
   ProfScope ps("sampler_build", s);
-  if (c->fp64) return sampler_impl<double, 0>(c, s);
-  if (c->cfg.precision == LOVE_P_FP32_BF16SPLIT) return sampler_impl<float, 1>(c, s);
-  return sampler_impl<float, 0>(c, s);
+  return rows_per_lane(c->m) == 4 ? sampler_rpl<4>(c, s) : sampler_rpl<1>(c, s);
 }
+
+// ============================================================================
+// Batched build: Lanczos + Rt + mean cache for G GPs in lock step.
+// ============================================================================
+namespace {
+
+// Device buffers of one GP's main run (cache precision T) and mean solve.
+template <typename T>
+struct GpBufs {
+  T *Q = nullptr, *R = nullptr, *v = nullptr, *r = nullptr, *gv = nullptr, *gm = nullptr,
+    *tsc = nullptr;
+  double *partial = nullptr, *coef = nullptr, *c2 = nullptr, *amax = nullptr, *ldiag = nullptr,
+         *lsub = nullptr;
+  // mean solve (double)
+  double *x64 = nullptr, *y64 = nullptr, *xs = nullptr, *cr = nullptr, *cz = nullptr,
+         *cp = nullptr, *cap = nullptr, *cgv = nullptr, *cgm = nullptr, *ctsc = nullptr,
+         *pg = nullptr, *tinv = nullptr, *cm = nullptr, *cpart = nullptr, *ccoef = nullptr,
+         *cdvec = nullptr;
+  int nbg = 0;
+  int64_t rpbg = 0;
+  char* mem = nullptr;
+};
+
+template <typename T>
+love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStream_t s) {
+  const int64_t n = c->n, m = c->m, ldq = c->ldq, k = c->k, kpad = c->kpad;
+  const int64_t nb = ldq / WAVE;   // row blocks at one row per lane (the most)
+  const int64_t ts = toeplitz_scratch_elems(c);
+  b.nbg = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(n, 128)));
+  b.rpbg = cdiv(n, (int64_t)b.nbg);
+  size_t tb = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
+                           (size_t)ts);
+  tb = (tb + 255) & ~size_t(255);
+  size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP);
+  if (mean) {
+    const bool own = sizeof(T) != 8;
+    db += sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 5 * (size_t)ldq +
+                            2 * (size_t)m + (size_t)ts + (size_t)nb * LDP + 2 * LDP);
+    if (!plain) db += sizeof(double) * ((size_t)b.nbg + 2) * kpad * kpad;
+  }
+  LOVE_HIP_TRY(hipMallocAsync((void**)&b.mem, tb + db, s));
+  T* t = (T*)b.mem;
+  b.Q = t;
+  b.R = b.Q + (size_t)ldq * k;
+  b.v = b.R + (size_t)k * m;
+  b.r = b.v + ldq;
+  b.gv = b.r + ldq;
+  b.gm = b.gv + m;
+  b.tsc = b.gm + m;
+  double* q = (double*)(b.mem + tb);
+  b.partial = q;
+  b.coef = b.partial + (size_t)nb * LDP;
+  b.c2 = b.coef + LDP;
+  b.amax = b.c2 + LDP;
+  b.ldiag = b.amax + LDP;
+  b.lsub = b.ldiag + LDP;
+  q = b.lsub + LDP + LDP;
+  if (mean) {
+    if (sizeof(T) != 8) {
+      b.x64 = q;
+      b.y64 = b.x64 + (size_t)n * c->d;
+      q = b.y64 + n;
+    } else {
+      b.x64 = (double*)c->x;
+      b.y64 = (double*)c->y;
+    }
+    b.xs = q;
+    b.cr = b.xs + ldq;
+    b.cz = b.cr + ldq;
+    b.cp = b.cz + ldq;
+    b.cap = b.cp + ldq;
+    b.cgv = b.cap + ldq;
+    b.cgm = b.cgv + m;
+    b.ctsc = b.cgm + m;
+    b.cpart = b.ctsc + ts;
+    b.ccoef = b.cpart + (size_t)nb * LDP;
+    b.cdvec = b.ccoef + LDP;
+    q = b.cdvec + LDP;
+    if (!plain) {
+      b.pg = q;
+      b.tinv = b.pg + (size_t)b.nbg * kpad * kpad;
+      b.cm = b.tinv + (size_t)kpad * kpad;
+    }
+  }
+  return LOVE_OK;
+}
+
+}  // namespace
+
+template <typename T, int D, int RPL>
+static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
+                              hipStream_t s_side) {
+  constexpr int RBK = WAVE * RPL;
+  const int G = (int)cs.size();
+  std::vector<GpBufs<T>> bufs(G);
+  const bool mean = !(cs[0]->cfg.flags & LOVE_FLAG_NO_MEAN);
+  std::vector<bool> plain(G);
+  for (int g = 0; g < G; ++g) {
+    plain[g] = (cs[g]->cfg.flags & LOVE_FLAG_PLAIN_CG) != 0;
+    love_status st = alloc_gp<T>(cs[g], bufs[g], mean, plain[g], s);
+    if (st != LOVE_OK) {
+      for (auto& b : bufs)
+        if (b.mem) (void)hipFreeAsync(b.mem, s);
+      return st;
+    }
+  }
+  // --- jobs --------------------------------------------------------------------
+  std::vector<LzJob<T>> lz(G);
+  std::vector<ScatterJob<T>> sc(G);
+  std::vector<GatherJob<T>> ga(G);
+  std::vector<FillJob<T>> fi(G);
+  std::vector<RtJob<T>> rj(G);
+  std::vector<SumJob> s_coef(G), s_c2(G);
+  std::vector<const T*> t_in_probe(G), t_in_step(G);
+  std::vector<T*> t_out_probe(G), t_out_step(G), t_scr(G);
+  std::vector<int64_t> js0(G, 0), js_m(G);
+  std::vector<const Ctl*> ctls(G);
+  std::vector<int64_t> b_rows(G), b_nodes(G), b_m(G), b_one(G, 1), b_grid(G);
+  const std::vector<int> nv1(G, 1), nv2(G, 2);   // columns of the coef / c2 sums at j = 0
+  int kmax = 0;
+  for (int g = 0; g < G; ++g) {
+    love_cache* c = cs[g];
+    GpBufs<T>& b = bufs[g];
+    const int64_t nb = c->ldq / RBK;
+    LzJob<T> J{};
+    J.g = make_grid<T>(c);
+    J.x = (const T*)c->x;
+    J.cell_start = c->cell_start;
+    J.sigma2 = (T)c->cfg.noise;
+    J.m = c->m;
+    J.R = b.R;
+    J.n = c->n;
+    J.ldq = c->ldq;
+    J.Q = b.Q;
+    J.v = b.v;
+    J.r = b.r;
+    J.gv = b.gv;
+    J.gm = b.gm;
+    J.partial = b.partial;
+    J.coef = b.coef;
+    J.c2 = b.c2;
+    J.amax = b.amax;
+    J.alpha = c->alpha;
+    J.beta = c->beta;
+    J.ldiag = b.ldiag;
+    J.lsub = b.lsub;
+    J.ctl = c->ctl;
+    J.tol = c->tol_lanczos;
+    J.klast = c->k - 1;
+    J.nb = (int)nb;
+    lz[g] = J;
+    ScatterJob<T> S{};
+    S.g = J.g;
+    S.x = J.x;
+    S.cell_start = c->cell_start;
+    S.v = b.Q;
+    S.v_js = c->ldq;
+    S.out = b.gv;
+    S.ctl = c->ctl;
+    sc[g] = S;
+    GatherJob<T> Ga{};
+    Ga.g = J.g;
+    Ga.x = J.x;
+    Ga.n = c->n;
+    Ga.kg = b.gm;
+    Ga.out = b.v;
+    ga[g] = Ga;
+    fi[g] = FillJob<T>{b.gv, c->m, (T)(1.0 / (double)c->m)};
+    RtJob<T> Rj{};
+    Rj.R = b.R;
+    Rj.ldiag = b.ldiag;
+    Rj.lsub = b.lsub;
+    Rj.rt = c->rt;
+    Rj.rt_lo = (uint16_t*)c->rt_lo;
+    Rj.m = c->m;
+    Rj.kpad = c->kpad;
+    Rj.split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+    Rj.ctl = c->ctl;
+    rj[g] = Rj;
+    s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
+    s_c2[g] = SumJob{b.partial, b.c2, c->ctl, (int)nb, 2};
+    t_in_probe[g] = b.gv;
+    t_out_probe[g] = b.gm;
+    t_in_step[g] = b.gv;
+    t_out_step[g] = b.R;
+    js_m[g] = c->m;
+    t_scr[g] = b.tsc;
+    ctls[g] = c->ctl;
+    b_rows[g] = nb;
+    b_nodes[g] = cdiv(c->m, 4);
+    b_m[g] = cdiv(c->m, 256);
+    b_grid[g] = cdiv(c->n, 256);
+    kmax = std::max(kmax, c->k);
+  }
+  JobArena A;
+  const size_t o_lz = A.add(lz), o_sc = A.add(sc), o_ga = A.add(ga), o_fi = A.add(fi),
+               o_rj = A.add(rj), o_coef = A.add(s_coef), o_c2 = A.add(s_c2);
+  ToepRun<T> t_probe, t_step;
+  toep_prepare<T>(A, t_probe, cs, t_in_probe, js0, t_out_probe, js0, t_scr,
+                  std::vector<const Ctl*>(G, nullptr));
+  toep_prepare<T>(A, t_step, cs, t_in_step, js0, t_out_step, js_m, t_scr, ctls);
+  // mean solve jobs
+  std::vector<CgJob<T>> cg(G);
+  std::vector<ScatterJob<double>> csc(G), cfin(G);
+  std::vector<ConvJob> cvx(G), cvy(G);
+  std::vector<int64_t> b_cvx(G, 0), b_cvy(G, 0), b_gram(G), b_cmat(G);
+  std::vector<int> nvq(G);
+  ToepRun<double> t_cg;
+  if (mean) {
+    std::vector<const double*> ci(G);
+    std::vector<double*> co(G), cscr(G);
+    for (int g = 0; g < G; ++g) {
+      love_cache* c = cs[g];
+      GpBufs<T>& b = bufs[g];
+      CgJob<T> C{};
+      C.g = make_grid<double>(c);
+      C.x = b.x64;
+      C.y = b.y64;
+      C.n = c->n;
+      C.m = c->m;
+      C.ldq = c->ldq;
+      C.xs = b.xs;
+      C.r = b.cr;
+      C.z = b.cz;
+      C.p = b.cp;
+      C.ap = b.cap;
+      C.gv = b.cgv;
+      C.gm = b.cgm;
+      C.Q = b.Q;
+      C.kq = plain[g] ? 0 : c->k;
+      C.kpad = c->kpad;
+      C.ldiag = b.ldiag;
+      C.lsub = b.lsub;
+      C.pg = b.pg;
+      C.tinv = b.tinv;
+      C.cm = b.cm;
+      C.nbg = b.nbg;
+      C.rpbg = b.rpbg;
+      C.partial = b.cpart;
+      C.coef = b.ccoef;
+      C.dvec = b.cdvec;
+      C.sigma2 = c->cfg.noise;
+      C.rscale = plain[g] ? 1.0 : 1.0 / c->cfg.noise;
+      const double cgtol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
+      C.tol2 = cgtol * cgtol;
+      C.maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
+      C.nb = (int)(c->ldq / RBK);
+      C.ctl = c->ctl;
+      C.ortho = plain[g] ? nullptr : c->ortho;
+      C.a = c->a;
+      C.a_fp64 = c->fp64 ? 1 : 0;
+      cg[g] = C;
+      ScatterJob<double> S{};
+      S.g = C.g;
+      S.x = b.x64;
+      S.cell_start = c->cell_start;
+      S.v = b.cz;
+      S.v2 = b.cp;
+      S.out = b.cgv;
+      S.ctl = c->ctl;
+      csc[g] = S;
+      S.v = b.xs;
+      S.v2 = nullptr;
+      S.ctl = nullptr;
+      cfin[g] = S;
+      if (sizeof(T) != 8) {
+        cvx[g] = ConvJob{(const float*)c->x, b.x64, c->n * c->d};
+        cvy[g] = ConvJob{(const float*)c->y, b.y64, c->n};
+        b_cvx[g] = cdiv(c->n * c->d, 256);
+        b_cvy[g] = cdiv(c->n, 256);
+      }
+      b_gram[g] = plain[g] ? 0 : b.nbg;
+      b_cmat[g] = plain[g] ? 0 : cdiv((int64_t)c->kpad * c->kpad, 256);
+      nvq[g] = C.kq + 1;
+      ci[g] = b.cgv;
+      co[g] = b.cgm;
+      cscr[g] = b.ctsc;
+    }
+    toep_prepare<double>(A, t_cg, cs, ci, js0, co, js0, cscr, ctls);
+  }
+  const size_t o_cg = A.add(cg), o_csc = A.add(csc), o_cfin = A.add(cfin), o_cvx = A.add(cvx),
+               o_cvy = A.add(cvy);
+  std::vector<SumJob> s_cg(G);
+  for (int g = 0; g < G; ++g) s_cg[g] = SumJob{bufs[g].cpart, bufs[g].ccoef, cs[g]->ctl,
+                                                (int)(cs[g]->ldq / RBK), nvq[g]};
+  const size_t o_scg = A.add(s_cg);
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  const LzJob<T>* dlz = A.at<LzJob<T>>(o_lz);
+  const Tab t_rows = make_tab(b_rows), t_nodes = make_tab(b_nodes), t_m = make_tab(b_m),
+            t_one = make_tab(b_one);
+  for (int g = 0; g < G; ++g) k_ctl_init<<<1, 1, 0, s>>>(cs[g]->ctl);
+  // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
+  {
+    ProfScope ps("probe", s);
+    launch_fill<T>(t_m, A.at<FillJob<T>>(o_fi), s);
+    toep_run<T>(A, t_probe, 0, 0, s);
+    launch_gather<T>(make_tab(b_grid), A.at<GatherJob<T>>(o_ga), D, 0, s);
+    k_lz_norm<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+    k_lz_bnorm<T><<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dlz);
+    k_lz_start<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+  }
+  // --- Lanczos steps -------------------------------------------------------------
+  for (int j = 0; j < kmax; ++j) {
+    launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s);
+    toep_run<T>(A, t_step, j, 1, s);
+    {
+      ProfScope ps("lz_gdots", s);
+      k_lz_gdots<T, D, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+    }
+    launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+    {
+      ProfScope ps("lz_udots", s);
+      k_lz_udots<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+    }
+    launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
+    {
+      ProfScope ps("lz_finalize", s);
+      k_lz_finalize<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+    }
+  }
+  // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
+  k_tri_chol<T><<<tab_blocks(t_one), 64, 0, s>>>(t_one, dlz, 0.0);
+  {
+    ProfScope ps("rtilde", s);
+    k_rtilde<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, A.at<RtJob<T>>(o_rj));
+  }
+  // The samplers (grid space, need Rt) and the mean solve (needs Q) are
+  // independent chains of small kernels: the samplers run on a side stream
+  // concurrently with the mean CG, and the caller's stream waits for them.
+  bool any_s = false;
+  for (auto* c : cs) any_s = any_s || c->ks > 0;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  const bool side = any_s && s_side != nullptr;
+  if (any_s) {
+    if (side) {
+      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+      LOVE_HIP_TRY(hipEventRecord(ev_fork, s));
+      LOVE_HIP_TRY(hipStreamWaitEvent(s_side, ev_fork, 0));
+    }
+    for (auto* c : cs) {
+      if (c->ks <= 0) continue;
+      love_status ss = sampler_dispatch(c, side ? s_side : s);
+      if (ss != LOVE_OK) return ss;
+    }
+    if (side) LOVE_HIP_TRY(hipEventRecord(ev_join, s_side));
+  }
+  // --- mean cache a = K W^T Khat^{-1} y --------------------------------------------
+  if (mean) {
+    ProfScope ps("mean_cg", s);
+    const CgJob<T>* dcg = A.at<CgJob<T>>(o_cg);
+    const Tab t_cvx = make_tab(b_cvx), t_cvy = make_tab(b_cvy), t_gram = make_tab(b_gram),
+              t_cmat = make_tab(b_cmat);
+    if (tab_blocks(t_cvx)) {
+      k_convert_b<<<tab_blocks(t_cvx), 256, 0, s>>>(t_cvx, A.at<ConvJob>(o_cvx));
+      k_convert_b<<<tab_blocks(t_cvy), 256, 0, s>>>(t_cvy, A.at<ConvJob>(o_cvy));
+    }
+    if (tab_blocks(t_gram)) {
+      for (int g = 0; g < G; ++g)
+        if (!plain[g]) LOVE_HIP_TRY(hipMemsetAsync(cs[g]->ortho, 0, sizeof(double), s));
+      k_gram<T><<<tab_blocks(t_gram), 256, 0, s>>>(t_gram, dcg);
+      k_tinv<T><<<tab_blocks(t_one), MAXK, 0, s>>>(t_one, dcg);
+      k_pcg_matrix<T><<<tab_blocks(t_cmat), 256, 0, s>>>(t_cmat, dcg);
+    }
+    const SumJob* dscg = A.at<SumJob>(o_scg);
+    const std::vector<int> nv0(G, 0);
+    k_pcg_init<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    launch_colsum(dscg, nvq, 0, 0, s);
+    k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 1);
+    k_pcg_apply<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    int* dflag = nullptr;
+    LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int), s));
+    int hflag = 0;
+    int maxit = 0;
+    bool any_plain = false;
+    for (int g = 0; g < G; ++g) {
+      maxit = std::max(maxit, cg[g].maxit);
+      any_plain = any_plain || plain[g];
+    }
+    const int chunk = any_plain ? 8 : 4;
+    int it = 0;
+    while (it < maxit) {
+      for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
+        launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s);
+        toep_run<double>(A, t_cg, 0, 2, s);
+        k_cg_ap<T, D, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_pcg_update<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        launch_colsum(dscg, nvq, 0, 2, s);
+        k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 0);
+        k_pcg_apply<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+      }
+      k_cg_alldone<T><<<1, 64, 0, s>>>(G, dcg, dflag);
+      LOVE_HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      LOVE_HIP_TRY(hipStreamSynchronize(s));
+      if (hflag) break;
+    }
+    (void)hipFreeAsync(dflag, s);
+    launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s);
+    toep_run<double>(A, t_cg, 0, 0, s);
+    k_cg_store_a<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, dcg);
+  }
+  if (side) {
+    LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(ev_join);
+  }
+  A.release(s);
+  for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
+  LOVE_HIP_TRY(hipGetLastError());
+  return LOVE_OK;
+}
+
+template <typename T>
+love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t s,
+                                hipStream_t s_side) {
+  int64_t rows = 0;
+  for (auto* c : cs) rows += c->ldq;
+  const bool r4 = rows_per_lane(rows) == 4;
+#define LOVE_BATCH_D(D) \
+  return r4 ? batch_impl<T, D, 4>(cs, s, s_side) : batch_impl<T, D, 1>(cs, s, s_side);
+  switch (cs[0]->d) {
+    case 1: LOVE_BATCH_D(1)
+    case 2: LOVE_BATCH_D(2)
+    case 3: LOVE_BATCH_D(3)
+    case 4: LOVE_BATCH_D(4)
+  }
+#undef LOVE_BATCH_D
+  return LOVE_EINVAL;
+}
+template love_status build_batch_lanczos<float>(const std::vector<love_cache*>&, hipStream_t, hipStream_t);
+template love_status build_batch_lanczos<double>(const std::vector<love_cache*>&, hipStream_t, hipStream_t);
 
 }  // namespace love

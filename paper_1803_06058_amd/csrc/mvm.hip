@@ -58,19 +58,24 @@ template GridT<double> make_grid<double>(const love_cache*);
 // c_e in [u_e - 3, u_e] on every axis; along the last axis those cells are
 // contiguous, so the rows form 4^(D-1) contiguous runs of the sorted order.
 // Lanes are split over the runs; each lane sums its rows, then the wave sums.
-// ----------------------------------------------------------------------------
-// mode bit 4: the gathered vector is v + ratio * v2 (CG direction p = r + ratio p),
+// mode bit 4: the gathered vector is v + ratio * v2 (CG direction p = z + ratio p),
 // formed on the fly so W^T p is exact for the p the next kernel writes.
+// ----------------------------------------------------------------------------
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_scatter(GridT<T> g, const T* __restrict__ x,
-                                                 const T* __restrict__ v,
-                                                 const int32_t* __restrict__ cell_start,
-                                                 T* __restrict__ out, const T* __restrict__ v2,
-                                                 const Ctl* ctl, int mode) {
-  if (ctl_skip(ctl, mode)) return;
-  const T ratio = ((mode & 4) && v2) ? (T)ctl->ratio : T(0);
+__global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* __restrict__ jobs,
+                                                 int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const GridT<T>& g = J.g;
+  const T* __restrict__ x = J.x;
+  const T* __restrict__ v = J.v + (int64_t)j * J.v_js;
+  const T* __restrict__ v2 = J.v2;
+  const bool comb = (mode & 4) && v2;
+  const T ratio = comb ? (T)J.ctl->ratio : T(0);
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t u = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  const int64_t u = (int64_t)lb * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (u >= g.mtot) return;
   constexpr int RUNS = 1 << (2 * (D - 1));
   constexpr int LPR = WAVE / RUNS;
@@ -98,74 +103,71 @@ __global__ __launch_bounds__(256) void k_scatter(GridT<T> g, const T* __restrict
   ok = ok && cl <= ch;
   T acc = T(0);
   if (ok) {
-    const int32_t rb = cell_start[cbase + cl];
-    const int32_t re = cell_start[cbase + ch + 1];
+    const int32_t rb = J.cell_start[cbase + cl];
+    const int32_t re = J.cell_start[cbase + ch + 1];
     for (int32_t r = rb + sub; r < re; r += LPR) {
       T w = T(1);
 #pragma unroll
       for (int e = 0; e < D; ++e) {
         T s;
-        const int j = stencil_at(g, e, x[(int64_t)r * D + e], s);
-        w *= keys_weight_at(ue[e] - j, s);
+        const int jj = stencil_at(g, e, x[(int64_t)r * D + e], s);
+        w *= keys_weight_at(ue[e] - jj, s);
       }
-      const T val = ((mode & 4) && v2) ? (T)(v[r] + ratio * v2[r]) : v[r];
+      const T val = comb ? (T)(v[r] + ratio * v2[r]) : v[r];
       acc += w * val;
     }
   }
   acc = wave_sum(acc);
-  if (lane == 0) out[u] = acc;
+  if (lane == 0) J.out[u] = acc;
 }
 
 template <typename T>
-void launch_scatter(const love_cache* c, const T* v, T* gout, const T* v2, const Ctl* ctl,
-                    int ctl_mode, hipStream_t s, const T* xsrc) {
+void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
+                    hipStream_t s) {
   ProfScope ps("scatter", s);
-  GridT<T> g = make_grid<T>(c);
-  const int wpb = 4;
-  dim3 grid((unsigned)cdiv(c->m, wpb));
-  const T* x = xsrc ? xsrc : (const T*)c->x;
-  switch (c->d) {
-    case 1: k_scatter<T, 1><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
-    case 2: k_scatter<T, 2><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
-    case 3: k_scatter<T, 3><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
-    case 4: k_scatter<T, 4><<<grid, 256, 0, s>>>(g, x, v, c->cell_start, gout, v2, ctl, ctl_mode); break;
+  const unsigned nb = tab_blocks(tab);
+  if (nb == 0) return;
+  switch (d) {
+    case 1: k_scatter<T, 1><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
+    case 2: k_scatter<T, 2><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
+    case 3: k_scatter<T, 3><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
+    case 4: k_scatter<T, 4><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
   }
 }
-template void launch_scatter<float>(const love_cache*, const float*, float*, const float*, const Ctl*, int, hipStream_t, const float*);
-template void launch_scatter<double>(const love_cache*, const double*, double*, const double*, const Ctl*, int, hipStream_t, const double*);
+template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t);
+template void launch_scatter<double>(const Tab&, const ScatterJob<double>*, int, int, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // W u (+ sigma^2 v): one thread per sorted row.
 // ----------------------------------------------------------------------------
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_gather(GridT<T> g, const T* __restrict__ x, int64_t n,
-                                                const T* __restrict__ kg,
-                                                const T* __restrict__ vsig, T sigma2,
-                                                T* __restrict__ out, const Ctl* ctl, int mode) {
-  if (ctl_skip(ctl, mode)) return;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  T acc = gather_row_dev<T, D>(g, x, r, kg);
-  if (vsig) acc += sigma2 * vsig[r];
-  out[r] = acc;
+__global__ __launch_bounds__(256) void k_gather(Tab tab, const GatherJob<T>* __restrict__ jobs,
+                                                int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const GatherJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const int64_t r = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (r >= J.n) return;
+  T acc = gather_row_dev<T, D>(J.g, J.x, r, J.kg);
+  if (J.vsig) acc += J.sigma2 * J.vsig[r];
+  J.out[r] = acc;
 }
 
 template <typename T>
-void launch_gather(const love_cache* c, const T* kg, const T* vsig, T sigma2, T* out,
-                   const Ctl* ctl, hipStream_t s, const T* xsrc) {
+void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s) {
   ProfScope ps("gather", s);
-  GridT<T> g = make_grid<T>(c);
-  dim3 grid((unsigned)cdiv(c->n, 256));
-  const T* x = xsrc ? xsrc : (const T*)c->x;
-  switch (c->d) {
-    case 1: k_gather<T, 1><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
-    case 2: k_gather<T, 2><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
-    case 3: k_gather<T, 3><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
-    case 4: k_gather<T, 4><<<grid, 256, 0, s>>>(g, x, c->n, kg, vsig, sigma2, out, ctl, 0); break;
+  const unsigned nb = tab_blocks(tab);
+  if (nb == 0) return;
+  switch (d) {
+    case 1: k_gather<T, 1><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
+    case 2: k_gather<T, 2><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
+    case 3: k_gather<T, 3><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
+    case 4: k_gather<T, 4><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
   }
 }
-template void launch_gather<float>(const love_cache*, const float*, const float*, float, float*, const Ctl*, hipStream_t, const float*);
-template void launch_gather<double>(const love_cache*, const double*, const double*, double, double*, const Ctl*, hipStream_t, const double*);
+template void launch_gather<float>(const Tab&, const GatherJob<float>*, int, int, hipStream_t);
+template void launch_gather<double>(const Tab&, const GatherJob<double>*, int, int, hipStream_t);
 
 template <typename TI, typename TO>
 __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t n) {
@@ -183,15 +185,16 @@ template void launch_convert<double, double>(const double*, double*, int64_t, hi
 // ----------------------------------------------------------------------------
 // Direct Toeplitz product along a contiguous axis of length L (long lines):
 //   out[o, i] = scale * sum_j c[|i - j|] in[o, j],   |i - j| <= bw.
-// Grid = (output tiles of TB_OUT = 64 * TB_R outputs) x (input segments) x
-// lines.  A block stages its input segment and the matching strip of signed
-// coefficients cd[delta] = c[|delta|] in LDS; its waves take equal slices of
-// the segment.  Each lane owns TB_R consecutive outputs whose coefficients
-// slide along a register window (one LDS load per input; the input itself is
-// an LDS broadcast).  Wave sums are added in LDS in wave order; with several
-// segments, k_toep_reduce adds the segment sums in segment order
-// (deterministic throughout).  Coefficients beyond the band bw are below the
-// working precision's rounding of the largest term (set at plan time).
+// A GP's blocks are (output tile of TB_OUT = 64 * TB_R outputs, input
+// segment, line).  A block stages its input segment and the matching strip of
+// signed coefficients cd[delta] = c[|delta|] in LDS; its waves take equal
+// slices of the segment.  Each lane owns TB_R consecutive outputs whose
+// coefficients slide along a register window (one LDS load per input; the
+// input itself is an LDS broadcast).  Wave sums are added in LDS in wave
+// order; with several segments, k_toep_reduce adds the segment sums in
+// segment order (deterministic throughout).  Coefficients beyond the band bw
+// are below the working precision's rounding of the largest term (set at
+// plan time).
 // ----------------------------------------------------------------------------
 constexpr int TB_WAVES = 8;
 constexpr int TB_R = 3;                   // odd: lane stride TB_R keeps LDS reads near conflict-free
@@ -200,24 +203,28 @@ constexpr int TB_SEG = 2048;              // max inputs per block (one LDS windo
 constexpr int TB_NSEG_MAX = 16;
 
 template <typename T>
-__global__ __launch_bounds__(TB_WAVES * WAVE) void k_toep_band(const T* __restrict__ in,
-                                                               T* __restrict__ out,
-                                                               const T* __restrict__ c, int L,
-                                                               int bw, int seglen, T scale,
-                                                               T* __restrict__ partial,
-                                                               const Ctl* ctl, int mode) {
-  if (ctl_skip(ctl, mode)) return;
+__global__ __launch_bounds__(TB_WAVES * WAVE) void k_toep_band(Tab tab,
+                                                               const ToepJob<T>* __restrict__ jobs,
+                                                               int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ToepJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
   __shared__ T gl[TB_SEG];
   __shared__ T cd[TB_SEG + TB_OUT];
   __shared__ T red[TB_WAVES][TB_OUT];
+  const int L = J.L, bw = J.bw, seglen = J.seglen, nseg = J.nseg;
+  const int tile = lb % J.ntiles;
+  const int rest = lb / J.ntiles;
+  const int seg = rest % nseg;
+  const int64_t line = rest / nseg;
+  const T* __restrict__ c = J.c;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  const int i0 = blockIdx.x * TB_OUT;
-  const int nseg = gridDim.y;
-  const int64_t line = blockIdx.z;
-  const T* g = in + line * L;
+  const int i0 = tile * TB_OUT;
+  const T* g = J.in + (int64_t)j * J.in_js + line * L;
   const int jlo = max(0, i0 - bw);
   const int jhi = min(L - 1, i0 + TB_OUT - 1 + bw);
-  const int jw = jlo + blockIdx.y * seglen;
+  const int jw = jlo + seg * seglen;
   const int nwin = max(0, min(seglen, jhi + 1 - jw));
   const int il = i0 + lane * TB_R;          // first output of this lane
   T acc[TB_R];
@@ -269,30 +276,32 @@ __global__ __launch_bounds__(TB_WAVES * WAVE) void k_toep_band(const T* __restri
     for (int q = 0; q < TB_WAVES; ++q) s += red[q][o];
     const int i = i0 + o;
     if (i < L) {
-      if (nseg == 1) out[line * L + i] = scale * s;
-      else partial[((int64_t)line * nseg + blockIdx.y) * L + i] = s;
+      if (nseg == 1) J.out[(int64_t)j * J.out_js + line * L + i] = J.scale * s;
+      else J.partial[(line * nseg + seg) * L + i] = s;
     }
   }
 }
 
 // out[line, i] = scale * sum_seg partial[line, seg, i] (segment order)
 template <typename T>
-__global__ __launch_bounds__(256) void k_toep_reduce(const T* __restrict__ partial,
-                                                     T* __restrict__ out, int L, int nseg,
-                                                     int64_t nlines, T scale, const Ctl* ctl,
-                                                     int mode) {
-  if (ctl_skip(ctl, mode)) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nlines * L) return;
+__global__ __launch_bounds__(256) void k_toep_reduce(Tab tab, const ToepJob<T>* __restrict__ jobs,
+                                                     int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ToepJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const int L = J.L, nseg = J.nseg;
+  const int64_t idx = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (idx >= J.outer * L) return;
   const int64_t line = idx / L, i = idx % L;
-  const T* lp = partial + line * nseg * (int64_t)L + i;
+  const T* lp = J.partial + line * nseg * (int64_t)L + i;
   T v[TB_NSEG_MAX];
 #pragma unroll
   for (int q = 0; q < TB_NSEG_MAX; ++q) v[q] = q < nseg ? lp[(int64_t)q * L] : T(0);
   T acc = T(0);
 #pragma unroll
   for (int q = 0; q < TB_NSEG_MAX; ++q) acc += v[q];
-  out[idx] = scale * acc;
+  J.out[(int64_t)j * J.out_js + idx] = J.scale * acc;
 }
 
 // Direct Toeplitz product for short / strided axes: a block owns 64
@@ -302,15 +311,19 @@ __global__ __launch_bounds__(256) void k_toep_reduce(const T* __restrict__ parti
 constexpr int TOEP_LINES_MAXL = 256;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_toep_lines(const T* __restrict__ in, T* __restrict__ out,
-                                                    const T* __restrict__ c, int L, int64_t inner,
-                                                    int64_t nlines, T scale, const Ctl* ctl,
-                                                    int mode) {
-  if (ctl_skip(ctl, mode)) return;
+__global__ __launch_bounds__(256) void k_toep_lines(Tab tab, const ToepJob<T>* __restrict__ jobs,
+                                                    int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ToepJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
   extern __shared__ unsigned char smem_raw[];
-  T* tile = (T*)smem_raw;       // L x 64
+  const int L = J.L;
+  const int64_t inner = J.inner, nlines = J.outer * J.inner;
+  T* tile = (T*)smem_raw;            // L x 64
   T* cl = tile + (int64_t)L * WAVE;  // L
-  const int64_t line0 = (int64_t)blockIdx.x * WAVE;
+  const T* in = J.in + (int64_t)j * J.in_js;
+  const int64_t line0 = (int64_t)lb * WAVE;
   for (int idx = threadIdx.x; idx < L * WAVE; idx += 256) {
     const int i = idx / WAVE, ln = idx % WAVE;
     const int64_t line = line0 + ln;
@@ -321,90 +334,158 @@ __global__ __launch_bounds__(256) void k_toep_lines(const T* __restrict__ in, T*
     }
     tile[idx] = v;
   }
-  for (int i = threadIdx.x; i < L; i += 256) cl[i] = c[i];
+  for (int i = threadIdx.x; i < L; i += 256) cl[i] = J.c[i];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t line = line0 + lane;
   if (line >= nlines) return;
   const int64_t o = line / inner, r = line % inner;
-  T* dst = out + o * L * inner + r;
+  T* dst = J.out + (int64_t)j * J.out_js + o * L * inner + r;
   for (int i = w; i < L; i += 4) {
     T acc = T(0);
-    for (int j = 0; j < L; ++j) acc += cl[i > j ? i - j : j - i] * tile[j * WAVE + lane];
-    dst[(int64_t)i * inner] = scale * acc;
+    for (int q = 0; q < L; ++q) acc += cl[i > q ? i - q : q - i] * tile[q * WAVE + lane];
+    dst[(int64_t)i * inner] = J.scale * acc;
   }
 }
 
 template <typename T>
-void fft_axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
-                    const Ctl* ctl, int mode, hipStream_t s);
+void launch_fft_conv(const Tab& tab, const ToepJob<T>* jobs, size_t smem, int j, int mode,
+                     hipStream_t s);
 
 int64_t toeplitz_scratch_elems(const love_cache* c) { return (2 + TB_NSEG_MAX) * c->m; }
 
-template <typename T>
-static void axis_apply(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T scale,
-                       T* scratch, const Ctl* ctl, int mode, hipStream_t s) {
-  const T* cc = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
-  if (ax.mode == 2) {
-    fft_axis_apply<T>(c, ax, in, out, scale, ctl, mode, s);
-    return;
-  }
-  if (ax.inner == 1 && ax.L > TOEP_LINES_MAXL) {
-    const int bw = sizeof(T) == 8 ? ax.bw64 : ax.bw32;
-    const int ntiles = (int)cdiv(ax.L, TB_OUT);
-    const int band = std::min(ax.L, TB_OUT + 2 * bw);
-    // segments: enough blocks to cover the chip (~512), each at least 256 inputs
-    int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
-                                                           cdiv(band, 256)));
-    nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
-    nseg = std::min(nseg, TB_NSEG_MAX);
-    const int seglen = (int)cdiv(band, nseg);
-    T* partial = scratch ? scratch + 2 * c->m : nullptr;
-    if (seglen > TB_SEG || (nseg > 1 && !partial)) nseg = 0;   // cannot happen for planned sizes
-    dim3 grid((unsigned)ntiles, (unsigned)std::max(nseg, 1), (unsigned)ax.outer);
-    k_toep_band<T><<<grid, TB_WAVES * WAVE, 0, s>>>(in, out, cc, ax.L, bw, seglen, scale, partial,
-                                                    ctl, mode);
-    if (nseg > 1)
-      k_toep_reduce<T><<<(unsigned)cdiv(ax.L * ax.outer, 256), 256, 0, s>>>(
-          partial, out, ax.L, nseg, ax.outer, scale, ctl, mode);
-  } else {
-    const int64_t nlines = ax.outer * ax.inner;
-    dim3 grid((unsigned)cdiv(nlines, WAVE));
-    size_t shm = sizeof(T) * ((size_t)ax.L * WAVE + ax.L);
-    k_toep_lines<T><<<grid, 256, shm, s>>>(in, out, cc, ax.L, ax.inner, nlines, scale, ctl, mode);
-  }
+void toeplitz_set_attrs() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  (void)hipFuncSetAttribute((const void*)k_toep_lines<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  (void)hipFuncSetAttribute((const void*)k_toep_lines<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
 
-// one axis with an explicit backend (used by the autotuner)
-template <typename T>
-void axis_apply_public(const love_cache* c, const ToepAxis& ax, const T* in, T* out, T* scratch,
-                       hipStream_t s) {
-  axis_apply<T>(c, ax, in, out, T(1), scratch, nullptr, 0, s);
+// Backend of one axis at working precision T: 0 band, 1 lines, 2 fft.
+static int axis_backend(const ToepAxis& ax) {
+  if (ax.mode == LOVE_TOEPLITZ_FFT) return 2;
+  return (ax.inner == 1 && ax.L > TOEP_LINES_MAXL) ? 0 : 1;
 }
-template void axis_apply_public<float>(const love_cache*, const ToepAxis&, const float*, float*, float*, hipStream_t);
 
 template <typename T>
-void toeplitz_apply(const love_cache* c, const T* in, T* out, T* scratch, const Ctl* ctl,
-                    int ctl_mode, hipStream_t s) {
-  ProfScope ps("toeplitz", s);
-  const ToepPlan& p = c->toep;
+void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& cs,
+                  const std::vector<const T*>& in, const std::vector<int64_t>& in_js,
+                  const std::vector<T*>& out, const std::vector<int64_t>& out_js,
+                  const std::vector<T*>& scratch, const std::vector<const Ctl*>& ctl) {
+  const int G = (int)cs.size();
+  const int d = cs[0]->d;
+  run.d = d;
   // axes applied last-to-first; intermediate results ping-pong through the scratch halves
-  const T* src = in;
-  T* bufs[2] = {scratch, scratch ? scratch + c->m : nullptr};
-  int flip = 0;
-  for (int e = p.d - 1; e >= 0; --e) {
-    T* dst = (e == 0) ? out : bufs[flip];
-    axis_apply<T>(c, p.ax[e], src, dst, T(1), scratch, ctl, ctl_mode, s);
-    src = dst;
-    flip ^= 1;
+  for (int e = d - 1, step = 0; e >= 0; --e, ++step) {
+    std::vector<ToepJob<T>> jobs(G);
+    std::vector<int64_t> nband(G, 0), nred(G, 0), nlines(G, 0), nfft(G, 0);
+    size_t smem_lines = 0, smem_fft = 0;
+    for (int g = 0; g < G; ++g) {
+      const love_cache* c = cs[g];
+      const ToepAxis& ax = c->toep.ax[e];
+      ToepJob<T> J{};
+      T* buf0 = scratch[g];
+      T* buf1 = scratch[g] + c->m;
+      const bool first = (e == d - 1), last = (e == 0);
+      J.in = first ? in[g] : ((step - 1) % 2 == 0 ? buf0 : buf1);
+      J.in_js = first ? in_js[g] : 0;
+      J.out = last ? out[g] : (step % 2 == 0 ? buf0 : buf1);
+      J.out_js = last ? out_js[g] : 0;
+      J.c = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
+      J.spec = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
+      J.partial = scratch[g] + 2 * c->m;
+      J.L = ax.L;
+      J.bw = sizeof(T) == 8 ? ax.bw64 : ax.bw32;
+      J.inner = ax.inner;
+      J.outer = ax.outer;
+      J.scale = T(1);
+      J.ctl = ctl[g];
+      const int be = axis_backend(ax);
+      if (be == 0) {
+        const int ntiles = (int)cdiv(ax.L, TB_OUT);
+        const int band = std::min(ax.L, TB_OUT + 2 * J.bw);
+        // segments: enough blocks to cover the chip (~512), each at least 256 inputs
+        int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
+                                                               cdiv(band, 256)));
+        nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
+        nseg = std::min(nseg, TB_NSEG_MAX);
+        J.ntiles = ntiles;
+        J.nseg = nseg;
+        J.seglen = (int)cdiv(band, nseg);
+        nband[g] = (int64_t)ntiles * nseg * ax.outer;
+        if (nseg > 1) nred[g] = cdiv((int64_t)ax.L * ax.outer, 256);
+      } else if (be == 1) {
+        nlines[g] = cdiv(ax.outer * ax.inner, WAVE);
+        smem_lines = std::max(smem_lines, sizeof(T) * ((size_t)ax.L * WAVE + ax.L));
+      } else {
+        int N = ax.fft_n, logN = 0;
+        while ((1 << logN) < N) ++logN;
+        J.N = N;
+        J.logN = logN;
+        nfft[g] = cdiv(ax.outer * ax.inner, 2);
+        smem_fft = std::max(smem_fft, sizeof(T) * 2 * (size_t)N);
+      }
+      jobs[g] = J;
+    }
+    auto& A_ = run.ax[step];
+    A_.jobs = A.add(jobs);
+    A_.band = make_tab(nband);
+    A_.reduce = make_tab(nred);
+    A_.lines = make_tab(nlines);
+    A_.fft = make_tab(nfft);
+    A_.smem_lines = smem_lines;
+    A_.smem_fft = smem_fft;
   }
 }
-template void toeplitz_apply<float>(const love_cache*, const float*, float*, float*, const Ctl*, int, hipStream_t);
-template void toeplitz_apply<double>(const love_cache*, const double*, double*, double*, const Ctl*, int, hipStream_t);
+
+template <typename T>
+void toep_run(const JobArena& A, const ToepRun<T>& run, int j, int mode, hipStream_t s) {
+  ProfScope ps("toeplitz", s);
+  for (int step = 0; step < run.d; ++step) {
+    const auto& ax = run.ax[step];
+    const ToepJob<T>* jobs = A.at<ToepJob<T>>(ax.jobs);
+    if (tab_blocks(ax.band))
+      k_toep_band<T><<<tab_blocks(ax.band), TB_WAVES * WAVE, 0, s>>>(ax.band, jobs, j, mode);
+    if (tab_blocks(ax.reduce))
+      k_toep_reduce<T><<<tab_blocks(ax.reduce), 256, 0, s>>>(ax.reduce, jobs, j, mode);
+    if (tab_blocks(ax.lines))
+      k_toep_lines<T><<<tab_blocks(ax.lines), 256, ax.smem_lines, s>>>(ax.lines, jobs, j, mode);
+    if (tab_blocks(ax.fft)) launch_fft_conv<T>(ax.fft, jobs, ax.smem_fft, j, mode, s);
+  }
+}
+
+template void toep_prepare<float>(JobArena&, ToepRun<float>&, const std::vector<love_cache*>&,
+                                  const std::vector<const float*>&, const std::vector<int64_t>&,
+                                  const std::vector<float*>&, const std::vector<int64_t>&,
+                                  const std::vector<float*>&, const std::vector<const Ctl*>&);
+template void toep_prepare<double>(JobArena&, ToepRun<double>&, const std::vector<love_cache*>&,
+                                   const std::vector<const double*>&, const std::vector<int64_t>&,
+                                   const std::vector<double*>&, const std::vector<int64_t>&,
+                                   const std::vector<double*>&, const std::vector<const Ctl*>&);
+template void toep_run<float>(const JobArena&, const ToepRun<float>&, int, int, hipStream_t);
+template void toep_run<double>(const JobArena&, const ToepRun<double>&, int, int, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Small helpers
 // ----------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill_b(Tab tab, const FillJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const FillJob<T>& J = jobs[gp];
+  const int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (i < J.n) J.p[i] = J.val;
+}
+template <typename T>
+void launch_fill(const Tab& tab, const FillJob<T>* jobs, hipStream_t s) {
+  if (tab_blocks(tab)) k_fill_b<T><<<tab_blocks(tab), 256, 0, s>>>(tab, jobs);
+}
+template void launch_fill<float>(const Tab&, const FillJob<float>*, hipStream_t);
+template void launch_fill<double>(const Tab&, const FillJob<double>*, hipStream_t);
+
 template <typename T>
 __global__ void k_fill(T* p, T v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -451,14 +532,7 @@ love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<
 int autotune_choose(love_cache* c, int e);
 
 love_status toeplitz_plan(love_cache* c) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    attr_done = true;
-    (void)hipFuncSetAttribute((const void*)k_toep_lines<float>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_toep_lines<double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-  }
+  toeplitz_set_attrs();
   ToepPlan& p = c->toep;
   p.d = c->d;
   p.mtot = c->m;

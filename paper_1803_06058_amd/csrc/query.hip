@@ -8,7 +8,9 @@
 // row load is a coalesced 256-byte access; ||u||^2 and the prior are summed
 // in double and the variance subtraction (which cancels 4-6 digits) is done
 // in double.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 #include "ops.h"
@@ -68,20 +70,35 @@ __device__ inline double quad4(const double* c4e, const double* a, const double*
   return s;
 }
 
+template <typename T>
+struct PredJob {
+  GridT<T> g;
+  const T* xs;
+  int64_t t;
+  const void* rt;
+  const uint16_t* rt_lo;
+  int kpad;
+  const T* a;          // mean cache (nullable)
+  const double* c4;
+  T* mean;             // nullable
+  T* var;
+  unsigned* status;
+};
+
+// One wave per point p (points 4 lb .. 4 lb + 3 of the block).
 template <typename T, int D, int SPLIT>
-__global__ __launch_bounds__(256) void k_predict(GridT<T> g, const T* __restrict__ xs, int64_t t,
-                                                 const void* __restrict__ rt,
-                                                 const uint16_t* __restrict__ rt_lo, int kpad,
-                                                 const T* __restrict__ acache,
-                                                 const double* __restrict__ c4,
-                                                 T* __restrict__ mean, T* __restrict__ var,
-                                                 unsigned* __restrict__ status) {
+__device__ inline void predict_body(const PredJob<T>& J, int64_t lb) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (p >= t) return;
+  const int64_t p = lb * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (p >= J.t) return;
+  const GridT<T>& g = J.g;
+  const int kpad = J.kpad;
+  const void* rt = J.rt;
+  const uint16_t* rt_lo = J.rt_lo;
+  const T* acache = J.a;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, xs + p * D, w, dw, base, false);
+  const bool ok = point_stencil<T, D>(g, J.xs + p * D, w, dw, base, false);
   constexpr int NA = 1 << (2 * D);
   double u0 = 0.0, u1 = 0.0, mu = 0.0;
   const bool two = kpad > WAVE;
@@ -105,44 +122,105 @@ __global__ __launch_bounds__(256) void k_predict(GridT<T> g, const T* __restrict
   if (lane == 0) {
     double pr = 1.0;
 #pragma unroll
-    for (int e = 0; e < D; ++e) pr *= quad4(c4 + 4 * e, w[e], w[e]);
+    for (int e = 0; e < D; ++e) pr *= quad4(J.c4 + 4 * e, w[e], w[e]);
     if (ok) {
-      var[p] = (T)(pr - uu);
-      if (mean) mean[p] = (T)mu;
+      J.var[p] = (T)(pr - uu);
+      if (J.mean) J.mean[p] = (T)mu;
     } else {
-      var[p] = (T)NAN;
-      if (mean) mean[p] = (T)NAN;
-      atomicOr(status, SF_DOMAIN);
+      J.var[p] = (T)NAN;
+      if (J.mean) J.mean[p] = (T)NAN;
+      atomicOr(J.status, SF_DOMAIN);
     }
   }
 }
 
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_predict(PredJob<T> J) {
+  predict_body<T, D, SPLIT>(J, blockIdx.x);
+}
+
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_predict_b(Tab tab, const PredJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  predict_body<T, D, SPLIT>(jobs[gp], lb);
+}
+
 template <typename T>
-love_status predict(const love_cache* c, const T* xs, int64_t t, T* mean, T* var, hipStream_t s) {
+static PredJob<T> pred_job(const love_cache* c, const T* xs, int64_t t, T* mean, T* var) {
+  PredJob<T> J{};
+  J.g = make_grid<T>(c);
+  J.xs = xs;
+  J.t = t;
+  J.rt = c->rt;
+  J.rt_lo = (const uint16_t*)c->rt_lo;
+  J.kpad = c->kpad;
+  J.a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
+  J.c4 = c->c4_dev;
+  J.mean = mean;
+  J.var = var;
+  J.status = c->status;
+  return J;
+}
+
+// G == 1: arguments by value (no upload); otherwise one launch for all GPs.
+template <typename T>
+love_status predict_batch(const std::vector<const love_cache*>& cs,
+                          const std::vector<const T*>& xs, const std::vector<int64_t>& ts,
+                          const std::vector<T*>& means, const std::vector<T*>& vars,
+                          hipStream_t s) {
   ProfScope ps("predict", s);
-  if (t == 0) return LOVE_OK;
-  GridT<T> g = make_grid<T>(c);
-  dim3 grid((unsigned)cdiv(t, 4));
-  const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
-  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
-#define LAUNCH_P(D)                                                                                 \
-  if (split)                                                                                        \
-    k_predict<T, D, 1><<<grid, 256, 0, s>>>(g, xs, t, c->rt, (const uint16_t*)c->rt_lo, c->kpad, a, \
-                                            c->c4_dev, mean, var, c->status);                       \
-  else                                                                                              \
-    k_predict<T, D, 0><<<grid, 256, 0, s>>>(g, xs, t, c->rt, nullptr, c->kpad, a, c->c4_dev, mean,  \
-                                            var, c->status);
-  switch (c->d) {
-    case 1: LAUNCH_P(1); break;
-    case 2: LAUNCH_P(2); break;
-    case 3: LAUNCH_P(3); break;
-    case 4: LAUNCH_P(4); break;
-  }
+  const int G = (int)cs.size();
+  const int d = cs[0]->d;
+  const bool split = cs[0]->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+  if (G == 1) {
+    if (ts[0] == 0) return LOVE_OK;
+    const PredJob<T> J = pred_job<T>(cs[0], xs[0], ts[0], means[0], vars[0]);
+    const unsigned nb = (unsigned)cdiv(ts[0], 4);
+#define LAUNCH_P(D)                                                   \
+  if (split) k_predict<T, D, 1><<<nb, 256, 0, s>>>(J);                \
+  else k_predict<T, D, 0><<<nb, 256, 0, s>>>(J);
+    switch (d) {
+      case 1: LAUNCH_P(1); break;
+      case 2: LAUNCH_P(2); break;
+      case 3: LAUNCH_P(3); break;
+      case 4: LAUNCH_P(4); break;
+    }
 #undef LAUNCH_P
+    return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+  }
+  for (int g0 = 0; g0 < G; g0 += MAXG) {
+    const int g1 = std::min(G, g0 + MAXG);
+    std::vector<PredJob<T>> jobs;
+    std::vector<int64_t> blocks;
+    for (int g = g0; g < g1; ++g) {
+      jobs.push_back(pred_job<T>(cs[g], xs[g], ts[g], means[g], vars[g]));
+      blocks.push_back(cdiv(ts[g], 4));
+    }
+    const Tab tab = make_tab(blocks);
+    if (!tab_blocks(tab)) continue;
+    JobArena A;
+    const size_t o = A.add(jobs);
+    love_status st = A.upload(s);
+    if (st != LOVE_OK) return st;
+    const PredJob<T>* dj = A.at<PredJob<T>>(o);
+    const unsigned nb = tab_blocks(tab);
+#define LAUNCH_PB(D)                                                  \
+  if (split) k_predict_b<T, D, 1><<<nb, 256, 0, s>>>(tab, dj);        \
+  else k_predict_b<T, D, 0><<<nb, 256, 0, s>>>(tab, dj);
+    switch (d) {
+      case 1: LAUNCH_PB(1); break;
+      case 2: LAUNCH_PB(2); break;
+      case 3: LAUNCH_PB(3); break;
+      case 4: LAUNCH_PB(4); break;
+    }
+#undef LAUNCH_PB
+    A.release(s);
+  }
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
-template love_status predict<float>(const love_cache*, const float*, int64_t, float*, float*, hipStream_t);
-template love_status predict<double>(const love_cache*, const double*, int64_t, double*, double*, hipStream_t);
+template love_status predict_batch<float>(const std::vector<const love_cache*>&, const std::vector<const float*>&, const std::vector<int64_t>&, const std::vector<float*>&, const std::vector<float*>&, hipStream_t);
+template love_status predict_batch<double>(const std::vector<const love_cache*>&, const std::vector<const double*>&, const std::vector<int64_t>&, const std::vector<double*>&, const std::vector<double*>&, hipStream_t);
 
 // ----------------------------------------------------------------------------
 // Cross-covariance of paired points (Alg. 1 with w_i != w_j):

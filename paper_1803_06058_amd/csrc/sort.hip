@@ -8,7 +8,9 @@
 //
 // Sort: least-significant-digit radix sort, 8-bit digits, stable (rank within
 // a wave from ballots, across waves from per-wave digit counts), so the final
-// order is (cell, original row) and does not depend on scheduling.
+// order is (cell, original row) and does not depend on scheduling.  A batch of
+// GPs is sorted at once: GP g's cells are keyed cell_off[g] + cell, so its
+// rows land in one contiguous range, in the same order as a sort of its own.
 #include "internal.h"
 
 namespace love {
@@ -19,29 +21,47 @@ constexpr int RS_BINS = 256;
 constexpr int RS_BLOCK = 256;
 constexpr int RS_TILE = 4096;
 
+template <typename T>
+struct SortJob {
+  GridT<T> g;
+  const T* x;                 // caller rows, n x d
+  const T* y;
+  T* xs;                      // sorted copies (cache)
+  T* ys;
+  int32_t* perm;
+  int32_t* cell_start;        // ctot + 1
+  int64_t n, row_off, ctot;
+  uint32_t cell_off;
+  unsigned* status;
+};
+
 template <typename T, int D>
-__global__ void k_cells(GridT<T> g, const T* __restrict__ x, const T* __restrict__ y, int64_t n,
-                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                        uint32_t* __restrict__ count, unsigned* __restrict__ status) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ void k_cells(Tab tab, const SortJob<T>* __restrict__ jobs, uint32_t* __restrict__ keys,
+                        uint32_t* __restrict__ vals, uint32_t* __restrict__ count) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SortJob<T>& J = jobs[gp];
+  const int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (i >= J.n) return;
+  const GridT<T>& g = J.g;
   unsigned bad = 0;
   int64_t cell = 0;
 #pragma unroll
   for (int e = 0; e < D; ++e) {
-    T xe = x[i * D + e];
+    T xe = J.x[i * D + e];
     if (!in_domain(xe, g.lo[e], g.hi[e])) bad |= SF_DOMAIN;
     if (!(xe == xe)) xe = g.lo[e];
     T s;
-    int j = stencil_at(g, e, xe, s);
-    cell += (int64_t)j * g.cstride[e];
+    int jj = stencil_at(g, e, xe, s);
+    cell += (int64_t)jj * g.cstride[e];
   }
-  T yi = y[i];
+  T yi = J.y[i];
   if (!isfinite((double)yi)) bad |= SF_NONFINITE;
-  if (bad) atomicOr(status, bad);
-  keys[i] = (uint32_t)cell;
-  vals[i] = (uint32_t)i;
-  atomicAdd(&count[cell], 1u);
+  if (bad) atomicOr(J.status, bad);
+  const uint32_t key = J.cell_off + (uint32_t)cell;
+  keys[J.row_off + i] = key;
+  vals[J.row_off + i] = (uint32_t)(J.row_off + i);
+  atomicAdd(&count[key], 1u);
 }
 
 __global__ void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
@@ -128,52 +148,98 @@ __global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* _
   }
 }
 
-template <typename T, int D>
-__global__ void k_gather_sorted(const T* __restrict__ x, const T* __restrict__ y,
-                                const uint32_t* __restrict__ order, int64_t n, T* __restrict__ xs,
-                                T* __restrict__ ys, int32_t* __restrict__ perm) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const uint32_t i = order[p];
-#pragma unroll
-  for (int e = 0; e < D; ++e) xs[p * D + e] = x[(int64_t)i * D + e];
-  ys[p] = y[i];
-  perm[p] = (int32_t)i;
+// per GP: cell_start[c] = scan[cell_off + c] - row_off
+template <typename T>
+__global__ void k_cell_start(Tab tab, const SortJob<T>* __restrict__ jobs,
+                             const uint32_t* __restrict__ scan) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SortJob<T>& J = jobs[gp];
+  const int64_t c = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (c > J.ctot) return;
+  J.cell_start[c] = (int32_t)((int64_t)scan[J.cell_off + c] - J.row_off);
 }
 
 template <typename T, int D>
-love_status sort_impl(love_cache* c, const T* x, const T* y, hipStream_t s) {
-  const int64_t n = c->n;
-  GridT<T> g = make_grid<T>(c);
-  const int64_t C = c->ctot;
-  // scratch: keys/vals ping-pong, histogram, counts
-  const int nb = (int)cdiv(n, RS_TILE);
+__global__ void k_gather_sorted(Tab tab, const SortJob<T>* __restrict__ jobs,
+                                const uint32_t* __restrict__ order) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SortJob<T>& J = jobs[gp];
+  const int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (p >= J.n) return;
+  const int64_t i = (int64_t)order[J.row_off + p] - J.row_off;
+#pragma unroll
+  for (int e = 0; e < D; ++e) J.xs[p * D + e] = J.x[i * D + e];
+  J.ys[p] = J.y[i];
+  J.perm[p] = (int32_t)i;
+}
+
+template <typename T, int D>
+love_status sort_impl(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,
+                      const std::vector<const T*>& ys, hipStream_t s) {
+  const int G = (int)cs.size();
+  std::vector<SortJob<T>> jobs(G);
+  std::vector<int64_t> brow(G), bcell(G);
+  int64_t N = 0, K = 0;
+  for (int g = 0; g < G; ++g) {
+    love_cache* c = cs[g];
+    SortJob<T> J{};
+    J.g = make_grid<T>(c);
+    J.x = xs[g];
+    J.y = ys[g];
+    J.xs = (T*)c->x;
+    J.ys = (T*)c->y;
+    J.perm = c->perm;
+    J.cell_start = c->cell_start;
+    J.n = c->n;
+    J.row_off = N;
+    J.ctot = c->ctot;
+    J.cell_off = (uint32_t)K;
+    J.status = c->status;
+    jobs[g] = J;
+    brow[g] = cdiv(c->n, 256);
+    bcell[g] = cdiv(c->ctot + 1, 256);
+    N += c->n;
+    K += c->ctot;
+  }
+  if (N >= (int64_t(1) << 31) || K >= (int64_t(1) << 31)) return LOVE_EINVAL;
+  JobArena A;
+  const size_t jo = A.add(jobs);
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  const SortJob<T>* dj = A.at<SortJob<T>>(jo);
+  const Tab trow = make_tab(brow), tcell = make_tab(bcell);
+  // scratch: keys/vals ping-pong, histogram, counts (K + 1)
+  const int nb = (int)cdiv(N, RS_TILE);
   uint32_t *k0, *v0, *k1, *v1, *hist, *cnt;
-  size_t bytes = sizeof(uint32_t) * (4 * (size_t)n + (size_t)RS_BINS * nb);
+  size_t bytes = sizeof(uint32_t) * (4 * (size_t)N + (size_t)RS_BINS * nb + (size_t)K + 1);
   char* buf = nullptr;
   LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
   k0 = (uint32_t*)buf;
-  v0 = k0 + n;
-  k1 = v0 + n;
-  v1 = k1 + n;
-  hist = v1 + n;
-  cnt = (uint32_t*)c->cell_start;  // counts accumulate in place, then scanned
-  LOVE_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (C + 1), s));
-  k_cells<T, D><<<cdiv(n, 256), 256, 0, s>>>(g, x, y, n, k0, v0, cnt, c->status);
+  v0 = k0 + N;
+  k1 = v0 + N;
+  v1 = k1 + N;
+  hist = v1 + N;
+  cnt = hist + (size_t)RS_BINS * nb;
+  LOVE_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (K + 1), s));
+  k_cells<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, k0, v0, cnt);
   int bits = 1;
-  while ((int64_t(1) << bits) < C) ++bits;
+  while ((int64_t(1) << bits) < K) ++bits;
   const int passes = (bits + 7) / 8;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    k_rs_hist<<<nb, RS_BLOCK, 0, s>>>(k0, n, shift, hist, nb);
+    k_rs_hist<<<nb, RS_BLOCK, 0, s>>>(k0, N, shift, hist, nb);
     k_scan_exclusive<<<1, 1024, 0, s>>>(hist, (int64_t)RS_BINS * nb, nullptr);
-    k_rs_scatter<<<nb, RS_BLOCK, 0, s>>>(k0, v0, k1, v1, n, shift, hist, nb);
+    k_rs_scatter<<<nb, RS_BLOCK, 0, s>>>(k0, v0, k1, v1, N, shift, hist, nb);
     std::swap(k0, k1);
     std::swap(v0, v1);
   }
-  k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, C + 1, nullptr);
-  k_gather_sorted<T, D><<<cdiv(n, 256), 256, 0, s>>>(x, y, v0, n, (T*)c->x, (T*)c->y, c->perm);
+  k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, K + 1, nullptr);
+  k_cell_start<T><<<tab_blocks(tcell), 256, 0, s>>>(tcell, dj, cnt);
+  k_gather_sorted<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, v0);
   LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  A.release(s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }
@@ -181,18 +247,19 @@ love_status sort_impl(love_cache* c, const T* x, const T* y, hipStream_t s) {
 }  // namespace
 
 template <typename T>
-love_status setup_sort(love_cache* c, const T* x, const T* y, hipStream_t s) {
+love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,
+                       const std::vector<const T*>& ys, hipStream_t s) {
   ProfScope ps("setup_sort", s);
-  switch (c->d) {
-    case 1: return sort_impl<T, 1>(c, x, y, s);
-    case 2: return sort_impl<T, 2>(c, x, y, s);
-    case 3: return sort_impl<T, 3>(c, x, y, s);
-    case 4: return sort_impl<T, 4>(c, x, y, s);
+  switch (cs[0]->d) {
+    case 1: return sort_impl<T, 1>(cs, xs, ys, s);
+    case 2: return sort_impl<T, 2>(cs, xs, ys, s);
+    case 3: return sort_impl<T, 3>(cs, xs, ys, s);
+    case 4: return sort_impl<T, 4>(cs, xs, ys, s);
   }
   return LOVE_EINVAL;
 }
 
-template love_status setup_sort<float>(love_cache*, const float*, const float*, hipStream_t);
-template love_status setup_sort<double>(love_cache*, const double*, const double*, hipStream_t);
+template love_status setup_sort<float>(const std::vector<love_cache*>&, const std::vector<const float*>&, const std::vector<const float*>&, hipStream_t);
+template love_status setup_sort<double>(const std::vector<love_cache*>&, const std::vector<const double*>&, const std::vector<const double*>&, hipStream_t);
 
 }  // namespace love
