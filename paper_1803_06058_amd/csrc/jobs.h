@@ -84,7 +84,7 @@ struct FillJob {
 };
 
 // Lanczos run with full reorthogonalisation on rows 0..n-1 (Q column-major,
-// column stride ldq = 256 * nb).  The operator part (g, x, R, m, sigma2) is
+// column stride ldq, a multiple of 256).  The operator part (g, x, R, m, sigma2) is
 // used by the main run on Khat only.
 template <typename T>
 struct LzJob {
@@ -111,7 +111,8 @@ struct LzJob {
   Ctl* ctl;
   double tol;
   int klast;                  // k - 1
-  int nb;                     // row blocks
+  int nb;                     // row blocks of 64 rpl rows
+  int rpl;                    // rows per lane of the row kernels (1 or 4)
 };
 
 // Rt[u, :] = (L^{-1} R[:, u])^T
@@ -157,7 +158,8 @@ struct CgJob {
   double* dvec;               // LDP
   double sigma2, rscale, tol2;
   int maxit;
-  int nb;
+  int nb;                     // row blocks of 64 rpl rows
+  int rpl;                    // rows per lane (1 or 4)
   Ctl* ctl;
   double* ortho;              // max |G - I| (nullable)
   void* a;                    // cache mean vector (m, cache precision)

@@ -205,9 +205,11 @@ __global__ __launch_bounds__(BLK) void k_colsum(Tab tab, const SumJob* __restric
   if ((threadIdx.x & (WAVE - 1)) == 0) J.out[c] = s;
 }
 
-// Rows per lane of the row kernels for a run over `rows` rows in total: 4
-// (256-row blocks, 16-byte loads) while that still gives >= 256 blocks,
-// else 1 (64-row blocks) so small problems still spread over the chip.
+// Rows per lane of the row kernels for a run over `rows` rows: 4 (256-row
+// blocks, 16-byte loads) while that still gives >= 256 blocks, else 1
+// (64-row blocks) so small problems still spread over the chip.  Chosen per
+// GP, so a GP's row blocking (hence its summation order) is the same in a
+// batch as in its own build.
 // LOVE_ROWS_PER_LANE=1|4 overrides (tuning).
 static int rows_per_lane(int64_t rows) {
   const char* env = std::getenv("LOVE_ROWS_PER_LANE");
@@ -231,16 +233,21 @@ static void launch_colsum(const SumJob* jobs, const std::vector<int>& nv, int nv
 // t < 64 RPL own row r0 + t in the per-row phases; ldq is a multiple of 256.
 // partial[lb][0] = sum of v^2 over the block's rows
 template <typename T, int RPL>
-__global__ __launch_bounds__(BLK) void k_lz_norm(Tab tab, const LzJob<T>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const LzJob<T>& J = jobs[gp];
+__device__ __forceinline__ void lz_norm_body(const LzJob<T>& J, int lb) {
   __shared__ double scr[16];
   constexpr int RBK = WAVE * RPL;
   const int64_t row = (int64_t)lb * RBK + threadIdx.x;
   const double v = (threadIdx.x < RBK && row < J.n) ? (double)J.v[row] : 0.0;
   const double s = block_sum(v * v, scr);
   if (threadIdx.x == 0) J.partial[(size_t)lb * LDP] = s;
+}
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lz_norm(Tab tab, const LzJob<T>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.rpl == 4) lz_norm_body<T, 4>(J, lb);
+  else lz_norm_body<T, 1>(J, lb);
 }
 
 // ctl->bnorm = sqrt(sum_b partial[b][0]); one block of one wave per GP
@@ -255,24 +262,25 @@ __global__ void k_lz_bnorm(Tab tab, const LzJob<T>* __restrict__ jobs) {
 
 // q_0 = v / ||v|| (zeros on the padding rows n..ldq-1)
 template <typename T, int RPL>
-__global__ __launch_bounds__(BLK) void k_lz_start(Tab tab, const LzJob<T>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const LzJob<T>& J = jobs[gp];
+__device__ __forceinline__ void lz_start_body(const LzJob<T>& J, int lb) {
   constexpr int RBK = WAVE * RPL;
   if (threadIdx.x >= RBK) return;
   const int64_t row = (int64_t)lb * RBK + threadIdx.x;
   const double b = J.ctl->bnorm;
   J.Q[row] = row < J.n ? (T)((double)J.v[row] / b) : T(0);
 }
-
-// First pass: v = W R_j + sigma^2 q_j (rows), partial rows of Q_{0..j}^T v.
-template <typename T, int D, int RPL>
-__global__ __launch_bounds__(BLK) void k_lz_gdots(Tab tab, const LzJob<T>* __restrict__ jobs,
-                                                  int j) {
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lz_start(Tab tab, const LzJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
+  if (J.rpl == 4) lz_start_body<T, 4>(J, lb);
+  else lz_start_body<T, 1>(J, lb);
+}
+
+// First pass: v = W R_j + sigma^2 q_j (rows), partial rows of Q_{0..j}^T v.
+template <typename T, int D, int RPL>
+__device__ __forceinline__ void lz_gdots_body(const LzJob<T>& J, int lb, int j) {
   if (J.ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double vl[RBK];
@@ -295,14 +303,19 @@ __global__ __launch_bounds__(BLK) void k_lz_gdots(Tab tab, const LzJob<T>* __res
   lane_rows<RPL>(vl, vv);
   coldots<T, RPL>(J.Q, J.ldq, j + 1, r0 + RPL * lane, vv, J.partial + (size_t)lb * LDP);
 }
-
-// Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].
-template <typename T, int RPL>
-__global__ __launch_bounds__(BLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
+template <typename T, int D>
+__global__ __launch_bounds__(BLK) void k_lz_gdots(Tab tab, const LzJob<T>* __restrict__ jobs,
                                                   int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
+  if (J.rpl == 4) lz_gdots_body<T, D, 4>(J, lb, j);
+  else lz_gdots_body<T, D, 1>(J, lb, j);
+}
+
+// Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].
+template <typename T, int RPL>
+__device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) {
   if (J.ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
@@ -336,16 +349,21 @@ __global__ __launch_bounds__(BLK) void k_lz_udots(Tab tab, const LzJob<T>* __res
   coldots<T, RPL>(J.Q, J.ldq, ncols, rowL, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                  int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.rpl == 4) lz_udots_body<T, 4>(J, lb, j);
+  else lz_udots_body<T, 1>(J, lb, j);
+}
 
 // alpha_j, beta_j, stop test (every block, identically), then
 // q_{j+1} = (r' - Q c2) / beta_j on rows 0..ldq-1 (zeros past n).  Block 0
 // records the step.  At j = k - 1 the run stops (no new vector).
 template <typename T, int RPL>
-__global__ __launch_bounds__(BLK) void k_lz_finalize(Tab tab, const LzJob<T>* __restrict__ jobs,
-                                                     int j) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const LzJob<T>& J = jobs[gp];
+__device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int j) {
   Ctl* ctl = J.ctl;
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
@@ -405,6 +423,15 @@ __global__ __launch_bounds__(BLK) void k_lz_finalize(Tab tab, const LzJob<T>* __
     q = ((double)J.r[row] - proj) / s_beta;
   }
   J.Q[(int64_t)(j + 1) * J.ldq + row] = (T)q;
+}
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_lz_finalize(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                     int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.rpl == 4) lz_finalize_body<T, 4>(J, lb, j);
+  else lz_finalize_body<T, 1>(J, lb, j);
 }
 
 // bf16 round-to-nearest-even from the IEEE-754 bit pattern
@@ -521,10 +548,7 @@ __global__ void k_convert_b(Tab tab, const ConvJob* __restrict__ jobs) {
 }
 
 template <typename TQ, int D, int RPL>
-__global__ __launch_bounds__(BLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const CgJob<TQ>& J = jobs[gp];
+__device__ __forceinline__ void cg_ap_body(const CgJob<TQ>& J, int lb) {
   if (J.ctl->cg_done) return;
   __shared__ double scr[16];
   constexpr int RBK = WAVE * RPL;
@@ -540,6 +564,14 @@ __global__ __launch_bounds__(BLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restr
   }
   const double db = block_sum(d, scr);
   if (threadIdx.x == 0) J.partial[(size_t)lb * LDP + PAP_COL] = db;
+}
+template <typename TQ, int D>
+__global__ __launch_bounds__(BLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.rpl == 4) cg_ap_body<TQ, D, 4>(J, lb);
+  else cg_ap_body<TQ, D, 1>(J, lb);
 }
 
 // partial rows of [Q^T r, r^T r] from the block's residual rows (rl in LDS)
@@ -560,10 +592,7 @@ __device__ __forceinline__ void pcg_dots(const CgJob<TQ>& J, const double* rl, d
 
 // x = 0, r = y, p = 0, partial rows of [Q^T y, y^T y]
 template <typename TQ, int RPL>
-__global__ __launch_bounds__(BLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const CgJob<TQ>& J = jobs[gp];
+__device__ __forceinline__ void pcg_init_body(const CgJob<TQ>& J, int lb) {
   constexpr int RBK = WAVE * RPL;
   __shared__ double rl[RBK];
   __shared__ double scr[16];
@@ -582,14 +611,19 @@ __global__ __launch_bounds__(BLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __re
   __syncthreads();
   pcg_dots<TQ, RPL>(J, rl, ssb, lb);
 }
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.rpl == 4) pcg_init_body<TQ, 4>(J, lb);
+  else pcg_init_body<TQ, 1>(J, lb);
+}
 
 // gamma = rz / p^T Ap (p^T Ap re-summed by every block from the partial rows
 // of k_cg_ap, one wave, fixed order); x += gamma p ; r -= gamma Ap ; dots.
 template <typename TQ, int RPL>
-__global__ __launch_bounds__(BLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const CgJob<TQ>& J = jobs[gp];
+__device__ __forceinline__ void pcg_update_body(const CgJob<TQ>& J, int lb) {
   if (J.ctl->cg_done) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double rl[RBK];
@@ -614,6 +648,14 @@ __global__ __launch_bounds__(BLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __
   const double ssb = block_sum(v * v, scr);
   __syncthreads();
   pcg_dots<TQ, RPL>(J, rl, ssb, lb);
+}
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.rpl == 4) pcg_update_body<TQ, 4>(J, lb);
+  else pcg_update_body<TQ, 1>(J, lb);
 }
 
 // One block per GP.  coef = [c_0 .. c_{kq-1}, r^T r] (column sums of the
@@ -680,10 +722,7 @@ __global__ __launch_bounds__(BLK) void k_pcg_ep(Tab tab, const CgJob<TQ>* __rest
 
 // z = r * rscale + Q d  (first min(kq, k_eff) columns)
 template <typename TQ, int RPL>
-__global__ __launch_bounds__(BLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
-  int gp, lb;
-  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const CgJob<TQ>& J = jobs[gp];
+__device__ __forceinline__ void pcg_apply_body(const CgJob<TQ>& J, int lb) {
   if (J.ctl->cg_done) return;
   __shared__ double dl[MAXK];
   __shared__ double red[4][BLK];
@@ -703,6 +742,14 @@ __global__ __launch_bounds__(BLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __r
   double acc = J.r[row] * J.rscale;
   if (k > 0) acc += red[0][t] + red[1][t] + red[2][t] + red[3][t];
   J.z[row] = acc;
+}
+template <typename TQ>
+__global__ __launch_bounds__(BLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const CgJob<TQ>& J = jobs[gp];
+  if (J.rpl == 4) pcg_apply_body<TQ, 4>(J, lb);
+  else pcg_apply_body<TQ, 1>(J, lb);
 }
 
 // Gram matrix G = Q^T Q of the first k_eff columns, in double: per-block
@@ -1361,6 +1408,7 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   J.tol = 1e-12;
   J.klast = ks - 1;
   J.nb = (int)nb;
+  J.rpl = RPL;
   SumJob js_rt{partial, sv, ctl, (int)nb, c->k};
   SumJob js_coef{partial, coef, ctl, (int)nb, 1};
   SumJob js_c2{partial, c2, ctl, (int)nb, 2};
@@ -1389,9 +1437,9 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
     k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
                                                                   sv, Q, ldq, 0, v, partial, ctl);
-    k_lz_norm<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
+    k_lz_norm<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
     k_lz_bnorm<double><<<1, WAVE, 0, s>>>(t1, dJ);
-    k_lz_start<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
+    k_lz_start<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
   }
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
@@ -1404,9 +1452,9 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
                                                                   sv, Q, ldq, j + 1, v, partial,
                                                                   ctl);
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    k_lz_udots<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    k_lz_udots<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
-    k_lz_finalize<double, RPL><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    k_lz_finalize<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
   }
   {
     ProfScope pe("sampler_eig", s);
@@ -1523,10 +1571,9 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
 
 }  // namespace
 
-template <typename T, int D, int RPL>
+template <typename T, int D>
 static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
                               hipStream_t s_side) {
-  constexpr int RBK = WAVE * RPL;
   const int G = (int)cs.size();
   std::vector<GpBufs<T>> bufs(G);
   const bool mean = !(cs[0]->cfg.flags & LOVE_FLAG_NO_MEAN);
@@ -1557,8 +1604,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   for (int g = 0; g < G; ++g) {
     love_cache* c = cs[g];
     GpBufs<T>& b = bufs[g];
-    const int64_t nb = c->ldq / RBK;
+    // rows per lane chosen per GP (as for its own single build)
+    const int rpl = rows_per_lane(c->ldq);
+    const int64_t nb = c->ldq / (WAVE * rpl);
     LzJob<T> J{};
+    J.rpl = rpl;
     J.g = make_grid<T>(c);
     J.x = (const T*)c->x;
     J.cell_start = c->cell_start;
@@ -1680,7 +1730,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       const double cgtol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
       C.tol2 = cgtol * cgtol;
       C.maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
-      C.nb = (int)(c->ldq / RBK);
+      C.rpl = lz[g].rpl;
+      C.nb = lz[g].nb;
       C.ctl = c->ctl;
       C.ortho = plain[g] ? nullptr : c->ortho;
       C.a = c->a;
@@ -1718,7 +1769,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
                o_cvy = A.add(cvy);
   std::vector<SumJob> s_cg(G);
   for (int g = 0; g < G; ++g) s_cg[g] = SumJob{bufs[g].cpart, bufs[g].ccoef, cs[g]->ctl,
-                                                (int)(cs[g]->ldq / RBK), nvq[g]};
+                                                lz[g].nb, nvq[g]};
   const size_t o_scg = A.add(s_cg);
   love_status st = A.upload(s);
   if (st != LOVE_OK) return st;
@@ -1732,9 +1783,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     launch_fill<T>(t_m, A.at<FillJob<T>>(o_fi), s);
     toep_run<T>(A, t_probe, 0, 0, s);
     launch_gather<T>(make_tab(b_grid), A.at<GatherJob<T>>(o_ga), D, 0, s);
-    k_lz_norm<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+    k_lz_norm<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
     k_lz_bnorm<T><<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dlz);
-    k_lz_start<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+    k_lz_start<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
   }
   // --- Lanczos steps -------------------------------------------------------------
   for (int j = 0; j < kmax; ++j) {
@@ -1742,17 +1793,17 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     toep_run<T>(A, t_step, j, 1, s);
     {
       ProfScope ps("lz_gdots", s);
-      k_lz_gdots<T, D, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_gdots<T, D><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
     }
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
     {
       ProfScope ps("lz_udots", s);
-      k_lz_udots<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_udots<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
     }
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     {
       ProfScope ps("lz_finalize", s);
-      k_lz_finalize<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_finalize<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
     }
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
@@ -1801,10 +1852,10 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     }
     const SumJob* dscg = A.at<SumJob>(o_scg);
     const std::vector<int> nv0(G, 0);
-    k_pcg_init<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    k_pcg_init<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
     launch_colsum(dscg, nvq, 0, 0, s);
     k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 1);
-    k_pcg_apply<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    k_pcg_apply<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
     int* dflag = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int), s));
     int hflag = 0;
@@ -1820,11 +1871,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
         launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s);
         toep_run<double>(A, t_cg, 0, 2, s);
-        k_cg_ap<T, D, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
-        k_pcg_update<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_cg_ap<T, D><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_pcg_update<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
         launch_colsum(dscg, nvq, 0, 2, s);
         k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 0);
-        k_pcg_apply<T, RPL><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_pcg_apply<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
       }
       k_cg_alldone<T><<<1, 64, 0, s>>>(G, dcg, dflag);
       LOVE_HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1850,18 +1901,12 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
 template <typename T>
 love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t s,
                                 hipStream_t s_side) {
-  int64_t rows = 0;
-  for (auto* c : cs) rows += c->ldq;
-  const bool r4 = rows_per_lane(rows) == 4;
-#define LOVE_BATCH_D(D) \
-  return r4 ? batch_impl<T, D, 4>(cs, s, s_side) : batch_impl<T, D, 1>(cs, s, s_side);
   switch (cs[0]->d) {
-    case 1: LOVE_BATCH_D(1)
-    case 2: LOVE_BATCH_D(2)
-    case 3: LOVE_BATCH_D(3)
-    case 4: LOVE_BATCH_D(4)
+    case 1: return batch_impl<T, 1>(cs, s, s_side);
+    case 2: return batch_impl<T, 2>(cs, s, s_side);
+    case 3: return batch_impl<T, 3>(cs, s, s_side);
+    case 4: return batch_impl<T, 4>(cs, s, s_side);
   }
-#undef LOVE_BATCH_D
   return LOVE_EINVAL;
 }
 template love_status build_batch_lanczos<float>(const std::vector<love_cache*>&, hipStream_t, hipStream_t);

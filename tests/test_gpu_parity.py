@@ -340,6 +340,36 @@ def test_batched_equals_single():
         c.free()
 
 
+def test_batched_mixed_sizes_equal_single():
+    """A batch whose GPs span n = 3.7e3 .. 1.2e5 (the large ones run the row
+    kernels with 4 rows per lane, the small ones with 1): every GP's cache
+    equals its single build bit for bit, and matches the FP64 oracle."""
+    Ps = WL.batched_config(G=6, seed=1, scale=1.0, t_per_gp=2000, n_lo=2000, n_hi=150000)
+    print([(P.n, P.m[0], P.k) for P in Ps], flush=True)
+    cfgs = [cfg_of(P) for P in Ps]
+    xs = [tdev(P.x, torch.float32) for P in Ps]
+    ys = [tdev(P.y, torch.float32) for P in Ps]
+    caches = B.build_cache_batched(cfgs, xs, ys)
+    qs = [tdev(P.xs, torch.float32) for P in Ps]
+    means, vars_ = B.predict_mean_var_batched(caches, qs)
+    for g, P in enumerate(Ps):
+        single = build(P)
+        m1, v1 = single.predict_mean_var(qs[g])
+        assert torch.equal(v1, vars_[g]) and torch.equal(m1, means[g])
+        assert single.info().k_eff == caches[g].info().k_eff
+        single.free()
+    # the smallest GP against the oracle (same k)
+    g = int(np.argmin([P.n for P in Ps]))
+    P = Ps[g]
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(vars_[g]), v_ref, O.prior_var(P.xs, spec_of(P)), host(means[g]), m_ref, P.y)
+    print(e, flush=True)
+    assert e["e_p_max"] <= 1e-4 and e["mean_err_rel_rms_y"] <= 1e-4
+    for c in caches:
+        c.free()
+
+
 def test_edge_cases():
     P = WL.config(2, scale=0.01, k_sample=0)
     cache = build(P)
