@@ -11,10 +11,12 @@ with every input already resident in device memory.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Prints one JSON line.  `value` is predictive variances per second over the
-whole step (cache built from scratch each step).  The `roofline` object is
-for the kernel with the largest share of the step's device time, timed with
-HIP events around each of its launches (on its launch stream) during the
-timed steps; `cpu_baseline` is the FP64 oracle on this host's cores.
+whole step (cache built from scratch each step), from K steps timed without
+any event records.  The `roofline` object is for the kernel with the largest
+share of the step's device time, timed with HIP events around each of its
+launches (on its launch stream) over a second pass of the same K steps;
+`cpu_baseline` is the FP64 oracle on this host's cores.  `batched` compares
+a lock-step batched build of 64 GPs with 64 single builds.
 """
 import argparse
 import json
@@ -31,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; MVM HBM GB/s"
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
 KERNELS = ["lz_udots", "lz_gdots", "lz_finalize", "scatter", "gather", "predict", "sample",
-           "rtilde", "setup_sort"]
+           "rtilde", "setup_sort", "colsum", "sp_apply", "rt_dots", "sp_udots", "sp_finalize",
+           "toep_band", "toep_reduce", "toep_band64", "toep_reduce64"]
 
 
 def parse():
@@ -41,13 +44,30 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-GP batched-build measurement")
     return ap.parse_args()
 
 
-def alg_bytes(name, P, k_eff, calls_per_step):
-    """Algorithmic bytes of all launches of `name` in one step (float data)."""
+def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
+    """Algorithmic bytes of all launches of `name` in one step (float data;
+    the sampler's m-space vectors are double)."""
     n, m, d = P.n, int(math.prod(P.m)), P.d
     f = 4
+    nb = -(-n // 256) if -(-n // 256) >= 256 else -(-n // 64)   # row blocks of the main run
+    mb = -(-m // 256) if -(-m // 256) >= 256 else -(-m // 64)   # row blocks of the sampler
+    if name == "colsum":        # partial rows read, sums written (main: 2 per step, sampler: 3)
+        main = sum(8 * nb * (j + 1) + 8 * nb * (j + 2) for j in range(k_eff))
+        samp = sum(8 * mb * (k_eff + (j + 1) + (j + 2)) for j in range(ks_eff))
+        return main + samp
+    if name == "sp_apply":      # Rt (float), kv, v, Q'_{0..j} (double)
+        return sum(f * m * k_eff + 16 * m + 8 * m * (j + 1) for j in range(ks_eff))
+    if name == "rt_dots":
+        return ks_eff * (f * m * k_eff + 8 * m)
+    if name == "sp_udots":
+        return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff))
+    if name == "sp_finalize":
+        return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff - 1))
     if name == "lz_udots":      # read Q_{0..j}, v ; write r'
         return sum(f * n * (j + 1) + 2 * f * n for j in range(k_eff))
     if name == "lz_gdots":      # read x, R_j, q_j, Q_{0..j}; write v
@@ -120,6 +140,65 @@ def cpu_baseline(P, gpu_mean, gpu_var, nq):
     return base, acc
 
 
+def batched_section(B, WL, torch, dev):
+    """64 independent 1-D GPs of uneven size (n log-uniform on [2e3, 2e5],
+    m = n/10 clamped to [500, 2e4], k in {50, 100}): one lock-step batched
+    build plus 100k variance queries per GP in one launch, against 64 single
+    builds and 64 single predicts back to back on the same stream."""
+    Ps = WL.batched_config(G=64)
+    cfgs = [B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
+                            lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
+                            precision=P.precision) for P in Ps]
+    xs = [torch.from_numpy(P.x).to(dev) for P in Ps]
+    ys = [torch.from_numpy(P.y).to(dev) for P in Ps]
+    qs = [torch.from_numpy(P.xs).to(dev) for P in Ps]
+    outs = [(torch.empty(P.xs.shape[0], device=dev), torch.empty(P.xs.shape[0], device=dev))
+            for P in Ps]
+
+    def batched():
+        cs = B.build_cache_batched(cfgs, xs, ys)
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        B.predict_mean_var_batched(cs, qs, outs=outs)
+        torch.cuda.synchronize()
+        tq1 = time.perf_counter()
+        return cs, tq1 - tq0
+
+    def sequential():
+        cs = [B.build_cache(cfg, x, y) for cfg, x, y in zip(cfgs, xs, ys)]
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for c, q, o in zip(cs, qs, outs):
+            c.predict_mean_var(q, out=o)
+        torch.cuda.synchronize()
+        tq1 = time.perf_counter()
+        return cs, tq1 - tq0
+
+    res = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        cs, _ = fn()                        # warm-up (autotuner, module load)
+        for c in cs:
+            c.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cs, tq = fn()
+        t1 = time.perf_counter()
+        res[name] = ((t1 - t0) - tq, tq, [c.info().k_eff for c in cs])
+        for c in cs:
+            c.free()
+    nq = sum(P.xs.shape[0] for P in Ps)
+    bb, bq, kb = res["batched"]
+    sb, sq, ks = res["sequential"]
+    return {"workload": "64 independent 1-D KISS-GP GPs, sum n = %d, sum m = %d, k in {50,100}, "
+                        "100k variance queries per GP" % (sum(P.n for P in Ps),
+                                                         sum(P.m[0] for P in Ps)),
+            "build_ms_batched": round(bb * 1e3, 2), "build_ms_sequential": round(sb * 1e3, 2),
+            "build_speedup": round(sb / bb, 2),
+            "query_ms_batched": round(bq * 1e3, 3), "query_ms_sequential": round(sq * 1e3, 3),
+            "variances_per_s_batched": round(nq / bq, 1),
+            "k_eff_equal": kb == ks}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -151,21 +230,22 @@ def main():
         c.sample_posterior(xss, z, out=smp)
         return c
 
-    # warm-up: all single-kernel scopes timed, to find the dominant kernel
+    # warm-up: one cold step, then the single-kernel scopes timed over the
+    # remaining warm-up steps to find the dominant kernel
+    c = step()
+    info = c.info()
+    c.free()
+    torch.cuda.synchronize()
     B.profile_select(KERNELS)
     B.profile_enable(True)
-    info = None
-    for _ in range(max(1, a.warmup)):
+    nwarm = max(1, a.warmup - 1)
+    for _ in range(nwarm):
         c = step()
-        info = c.info()
         c.free()
     torch.cuda.synchronize()
     warm = B.profile_read(KERNELS)
     dominant = max(KERNELS, key=lambda k_: warm[k_][1])
-    # timed region: events only around the dominant kernel's launches
-    B.profile_enable(False)
-    B.profile_select([dominant])
-    B.profile_enable(True)
+    # timed region: K clean steps (no event records) give ms_per_step and value
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
@@ -173,9 +253,18 @@ def main():
         c.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    # the same K steps again with HIP events around every launch of the dominant
+    # kernel (recorded on its launch stream): its average launch duration
+    B.profile_enable(False)
+    B.profile_select([dominant])
+    B.profile_enable(True)
+    for _ in range(a.steps):
+        c = step()
+        c.free()
+    torch.cuda.synchronize()
     dom = B.profile_read([dominant])[dominant]
     B.profile_enable(False)
-    ms_per_step = (t1 - t0) * 1e3 / a.steps
 
     # component timings (separate, after the timed region): build alone, queries alone, one MVM
     B.profile_select(["scatter", "toeplitz", "gather", "predict"])
@@ -215,7 +304,7 @@ def main():
 
     k_eff = info.k_eff
     calls_step = dom[0] / a.steps
-    bytes_step = alg_bytes(dominant, P, k_eff, calls_step)
+    bytes_step = alg_bytes(dominant, P, k_eff, calls_step, info.k_eff_sample)
     roof = None
     if bytes_step is not None and dom[1] > 0:
         achieved = bytes_step * a.steps / (dom[1] * 1e-3) / 1e9
@@ -242,8 +331,10 @@ def main():
         "mvm_us": round(mvm_ms * 1e3, 2),
         "k_eff": k_eff, "k_eff_sample": info.k_eff_sample, "cg_iters": info.cg_iters,
         "roofline": roof,
-        "kernel_ms_warmup": {k_: round(v_[1] / max(1, a.warmup), 4) for k_, v_ in warm.items()},
+        "kernel_ms_per_step": {k_: round(v_[1] / nwarm, 4) for k_, v_ in warm.items()},
     }
+    if not a.no_batched:
+        out["batched"] = batched_section(B, WL, torch, dev)
     if not a.no_cpu_baseline:
         base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries)
         out["cpu_baseline"] = base

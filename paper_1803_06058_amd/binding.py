@@ -326,14 +326,25 @@ def build_cache_batched(cfgs: List[love_config], xs: List[torch.Tensor],
     return [LoveCache(out[g], cfgs[g]) for g in range(G)]
 
 
-def predict_mean_var_batched(caches: List[LoveCache], xs: List[torch.Tensor]):
+def predict_mean_var_batched(caches: List[LoveCache], xs: List[torch.Tensor], outs=None):
+    """Mean and variance for G caches in one launch; outs: optional list of
+    (mean, var) tensors to write into."""
     L = load_library()
     G = len(caches)
     hs = (C.c_void_p * G)(*[c.handle.value for c in caches])
+    for c, x in zip(caches, xs):
+        _need(x, c.dtype, (x.shape[0], c.cfg.d), "xs")
     xp = (C.c_void_p * G)(*[x.data_ptr() for x in xs])
     ts = (C.c_int64 * G)(*[x.shape[0] for x in xs])
-    means = [torch.empty(x.shape[0], device=x.device, dtype=c.dtype) for c, x in zip(caches, xs)]
-    vars_ = [torch.empty(x.shape[0], device=x.device, dtype=c.dtype) for c, x in zip(caches, xs)]
+    if outs is None:
+        means = [torch.empty(x.shape[0], device=x.device, dtype=c.dtype) for c, x in zip(caches, xs)]
+        vars_ = [torch.empty(x.shape[0], device=x.device, dtype=c.dtype) for c, x in zip(caches, xs)]
+    else:
+        means = [o[0] for o in outs]
+        vars_ = [o[1] for o in outs]
+        for c, x, m, v in zip(caches, xs, means, vars_):
+            _need(m, c.dtype, (x.shape[0],), "mean")
+            _need(v, c.dtype, (x.shape[0],), "var")
     mp = (C.c_void_p * G)(*[m.data_ptr() for m in means])
     vp = (C.c_void_p * G)(*[v.data_ptr() for v in vars_])
     _check(L.love_predict_mean_var_batched(G, hs, xp, ts, mp, vp, C.c_void_p(_stream())),

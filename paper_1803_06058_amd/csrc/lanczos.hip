@@ -223,6 +223,7 @@ static void launch_colsum(const SumJob* jobs, const std::vector<int>& nv, int nv
   std::vector<int64_t> nbk(nv.size());
   for (size_t g = 0; g < nv.size(); ++g) nbk[g] = cdiv(std::max(nv[g] + nv_add, 0), BLK / WAVE);
   const Tab t = make_tab(nbk);
+  ProfScope ps("colsum", s);
   if (tab_blocks(t)) k_colsum<<<tab_blocks(t), BLK, 0, s>>>(t, jobs, nv_add, mode);
 }
 
@@ -1445,16 +1446,28 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
     toep_run<double>(A, t_step, j, 1, s);
-    k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
-                                                            partial, ctl);
+    {
+      ProfScope pk("rt_dots", s);
+      k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
+                                                              partial, ctl);
+    }
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
-    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
-                                                                  sv, Q, ldq, j + 1, v, partial,
-                                                                  ctl);
+    {
+      ProfScope pk("sp_apply", s);
+      k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad,
+                                                                    cm, sv, Q, ldq, j + 1, v,
+                                                                    partial, ctl);
+    }
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    k_lz_udots<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    {
+      ProfScope pk("sp_udots", s);
+      k_lz_udots<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    }
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
-    k_lz_finalize<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    {
+      ProfScope pk("sp_finalize", s);
+      k_lz_finalize<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+    }
   }
   {
     ProfScope pe("sampler_eig", s);

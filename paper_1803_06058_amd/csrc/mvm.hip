@@ -9,6 +9,7 @@
 // instead of a stored 20d-byte stencil).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.h"
 #include "ops.h"
@@ -410,6 +411,14 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
         // segments: enough blocks to cover the chip (~512), each at least 256 inputs
         int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
                                                                cdiv(band, 256)));
+        {
+          // LOVE_TOEP_NSEG=q fixes the segment count (tuning)
+          static const int forced = [] {
+            const char* e = std::getenv("LOVE_TOEP_NSEG");
+            return e ? std::atoi(e) : 0;
+          }();
+          if (forced > 0) nseg = forced;
+        }
         nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
         nseg = std::min(nseg, TB_NSEG_MAX);
         J.ntiles = ntiles;
@@ -447,10 +456,14 @@ void toep_run(const JobArena& A, const ToepRun<T>& run, int j, int mode, hipStre
   for (int step = 0; step < run.d; ++step) {
     const auto& ax = run.ax[step];
     const ToepJob<T>* jobs = A.at<ToepJob<T>>(ax.jobs);
-    if (tab_blocks(ax.band))
+    if (tab_blocks(ax.band)) {
+      ProfScope pb(sizeof(T) == 8 ? "toep_band64" : "toep_band", s);
       k_toep_band<T><<<tab_blocks(ax.band), TB_WAVES * WAVE, 0, s>>>(ax.band, jobs, j, mode);
-    if (tab_blocks(ax.reduce))
+    }
+    if (tab_blocks(ax.reduce)) {
+      ProfScope pr(sizeof(T) == 8 ? "toep_reduce64" : "toep_reduce", s);
       k_toep_reduce<T><<<tab_blocks(ax.reduce), 256, 0, s>>>(ax.reduce, jobs, j, mode);
+    }
     if (tab_blocks(ax.lines))
       k_toep_lines<T><<<tab_blocks(ax.lines), 256, ax.smem_lines, s>>>(ax.lines, jobs, j, mode);
     if (tab_blocks(ax.fft)) launch_fft_conv<T>(ax.fft, jobs, ax.smem_fft, j, mode, s);
