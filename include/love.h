@@ -161,11 +161,17 @@ const char* love_status_string(love_status s);
 love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
                              void* stream, love_cache** out);
 
-/* Build G independent caches with every phase launched once for all GPs
- * (kernels index a per-launch work table of (gp, tile)), so small GPs share
- * the device instead of each under-filling it.  cfgs, xs, ys, ns, out are host
- * arrays of length G; all GPs must share precision and d.  On error no cache is
- * returned.  Each GP's result equals its single-GP build on the same inputs. */
+/* Build G independent caches (a1-a11 of the build for every GP) with every
+ * phase launched once for all GPs, in lock step over the Lanczos and CG
+ * steps: each kernel maps its blocks to (GP, local block) through a
+ * per-launch work table and reads the GP's arguments from a device array, so
+ * small GPs share the device instead of each under-filling it.  cfgs, xs, ys,
+ * ns, out are host arrays of length G; all GPs must share precision, d and the
+ * LOVE_FLAG_NO_MEAN bit (EINVAL otherwise).  Batches beyond 64 GPs run in
+ * groups of 64.  Samplers (k_sample > 0) are built one GP after another on a
+ * side stream.  On error no cache is returned.  Each GP's cache equals its
+ * single-GP build on the same inputs bit for bit (love_build_cache is the
+ * batch of one). */
 love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
                                      const void* const* ys, const int64_t* ns, void* stream,
                                      love_cache** out);
@@ -175,7 +181,8 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
 love_status love_predict_mean_var(const love_cache* c, const void* xs, int64_t t, void* mean,
                                   void* var, void* stream);
 
-/* Same for G caches in one launch (host arrays of length G). */
+/* Same for G caches in one launch (host arrays of length G; means may be
+ * NULL, or hold NULL entries).  All caches must share precision and d. */
 love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* caches,
                                           const void* const* xs, const int64_t* ts,
                                           void* const* means, void* const* vars, void* stream);
