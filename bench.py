@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-GP batched-build measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run three 256 MiB device-to-device copies (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -207,6 +210,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if a.calibrate_copy:
+        nf = 64 << 20
+        src = torch.ones(nf, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * nf, "copies": 3}), flush=True)
+        return
     from paper_1803_06058_amd import binding as B
     from paper_1803_06058_amd import workloads as WL
 
@@ -244,6 +257,7 @@ def main():
         c.free()
     torch.cuda.synchronize()
     warm = B.profile_read(KERNELS)
+    B.profile_enable(False)
     dominant = max(KERNELS, key=lambda k_: warm[k_][1])
     # timed region: K clean steps (no event records) give ms_per_step and value
     torch.cuda.synchronize()

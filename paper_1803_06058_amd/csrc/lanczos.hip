@@ -31,7 +31,9 @@
 
 namespace love {
 
-constexpr int BLK = 256;
+constexpr int BLK = 256;          // small kernels
+constexpr int CWV = 8;            // column waves of a row-kernel block
+constexpr int RBLK = CWV * WAVE;  // threads of a row-kernel block
 
 // ----------------------------------------------------------------------------
 // Reductions
@@ -119,17 +121,17 @@ __device__ __forceinline__ void loadr(const double* __restrict__ col, int64_t ro
 
 // prow[c] = sum over the block's 64 RPL rows of Q[c][row] * vv (c < ncols);
 // the lane's rows are rowL..rowL+RPL-1 with values vv; wave w takes
-// c = w, w+4, ...  Rows past the GP's n hold zeros in Q and vv.
+// c = w, w+CWV, ...  Rows past the GP's n hold zeros in Q and vv.
 template <typename T, int RPL>
 __device__ __forceinline__ void coldots(const T* __restrict__ Q, int64_t ldq, int ncols,
                                         int64_t rowL, const double (&vv)[RPL],
                                         double* __restrict__ prow) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  for (int base = w; base < ncols; base += 4 * BF_NV) {
+  for (int base = w; base < ncols; base += CWV * BF_NV) {
     T q[BF_NV][RPL];
 #pragma unroll
     for (int i = 0; i < BF_NV; ++i) {
-      const int c = min(base + 4 * i, ncols - 1);
+      const int c = min(base + CWV * i, ncols - 1);
       loadr<RPL>(Q + (int64_t)c * ldq, rowL, q[i]);
     }
     double a[BF_NV];
@@ -138,16 +140,16 @@ __device__ __forceinline__ void coldots(const T* __restrict__ Q, int64_t ldq, in
       double s = 0.0;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) s += (double)q[i][r] * vv[r];
-      a[i] = (base + 4 * i < ncols) ? s : 0.0;
+      a[i] = (base + CWV * i < ncols) ? s : 0.0;
     }
     const double tot = bfly_sum<BF_NV>(a);
-    const int c = base + 4 * ((lane >> BF_SHIFT) & (BF_NV - 1));
+    const int c = base + CWV * ((lane >> BF_SHIFT) & (BF_NV - 1));
     if ((lane & ((1 << BF_SHIFT) - 1)) == 0 && c < ncols) prow[c] = tot;
   }
 }
 
-// red[w][RPL lane + r] = sum over the wave's columns c (w, w+4, ...) of
-// Q[c][rowL + r] * cl[c]; the caller adds the four waves' rows in wave order.
+// red[w][RPL lane + r] = sum over the wave's columns c (w, w+CWV, ...) of
+// Q[c][rowL + r] * cl[c]; the caller adds the CWV waves' rows in wave order.
 template <typename T, int RPL>
 __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, int ncols,
                                         int64_t rowL, const double* __restrict__ cl,
@@ -156,16 +158,16 @@ __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, in
   double acc[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) acc[r] = 0.0;
-  for (int base = w; base < ncols; base += 4 * BF_NV) {
+  for (int base = w; base < ncols; base += CWV * BF_NV) {
     T q[BF_NV][RPL];
 #pragma unroll
     for (int i = 0; i < BF_NV; ++i) {
-      const int c = min(base + 4 * i, ncols - 1);
+      const int c = min(base + CWV * i, ncols - 1);
       loadr<RPL>(Q + (int64_t)c * ldq, rowL, q[i]);
     }
 #pragma unroll
     for (int i = 0; i < BF_NV; ++i) {
-      const int c = base + 4 * i;
+      const int c = base + CWV * i;
       const double f = c < ncols ? cl[min(c, ncols - 1)] : 0.0;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[r] += (double)q[i][r] * f;
@@ -173,6 +175,14 @@ __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, in
   }
 #pragma unroll
   for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
+}
+
+// sum of the column waves' projections of local row t, in wave order
+__device__ __forceinline__ double red_sum(const double (*red)[RB], int t) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < CWV; ++q) s += red[q][t];
+  return s;
 }
 
 // this lane's RPL values of a per-block row vector staged in LDS
@@ -243,7 +253,7 @@ __device__ __forceinline__ void lz_norm_body(const LzJob<T>& J, int lb) {
   if (threadIdx.x == 0) J.partial[(size_t)lb * LDP] = s;
 }
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_lz_norm(Tab tab, const LzJob<T>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_lz_norm(Tab tab, const LzJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
@@ -271,7 +281,7 @@ __device__ __forceinline__ void lz_start_body(const LzJob<T>& J, int lb) {
   J.Q[row] = row < J.n ? (T)((double)J.v[row] / b) : T(0);
 }
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_lz_start(Tab tab, const LzJob<T>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_lz_start(Tab tab, const LzJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
@@ -305,7 +315,7 @@ __device__ __forceinline__ void lz_gdots_body(const LzJob<T>& J, int lb, int j) 
   coldots<T, RPL>(J.Q, J.ldq, j + 1, r0 + RPL * lane, vv, J.partial + (size_t)lb * LDP);
 }
 template <typename T, int D>
-__global__ __launch_bounds__(BLK) void k_lz_gdots(Tab tab, const LzJob<T>* __restrict__ jobs,
+__global__ __launch_bounds__(RBLK) void k_lz_gdots(Tab tab, const LzJob<T>* __restrict__ jobs,
                                                   int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
@@ -320,11 +330,11 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   if (J.ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
-  __shared__ double red[4][RB];
+  __shared__ double red[CWV][RB];
   __shared__ double rl[RBK];
   __shared__ double scr[16];
   const int ncols = j + 1;
-  for (int c = threadIdx.x; c < ncols; c += BLK) cl[c] = J.coef[c];
+  for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
@@ -335,7 +345,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   double rv = 0.0;
   if (t < RBK) {
     if (row < J.n) {
-      const double proj = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+      const double proj = red_sum(red, t);
       const T r = (T)((double)J.v[row] - proj);
       J.r[row] = r;
       rv = (double)r;
@@ -351,7 +361,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
+__global__ __launch_bounds__(RBLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
                                                   int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
@@ -369,11 +379,11 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
-  __shared__ double red[4][RB];
+  __shared__ double red[CWV][RB];
   __shared__ double s_beta;
   __shared__ int s_stop;
   const double* c2rr = J.c2;
-  for (int c = threadIdx.x; c <= j; c += BLK) cl[c] = c2rr[c];
+  for (int c = threadIdx.x; c <= j; c += RBLK) cl[c] = c2rr[c];
   if (threadIdx.x == 0) {
     double c2n = 0.0;
     for (int c = 0; c <= j; ++c) c2n += c2rr[c] * c2rr[c];
@@ -420,13 +430,13 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   const int64_t row = r0 + t;
   double q = 0.0;
   if (row < J.n) {
-    const double proj = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    const double proj = red_sum(red, t);
     q = ((double)J.r[row] - proj) / s_beta;
   }
   J.Q[(int64_t)(j + 1) * J.ldq + row] = (T)q;
 }
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_lz_finalize(Tab tab, const LzJob<T>* __restrict__ jobs,
+__global__ __launch_bounds__(RBLK) void k_lz_finalize(Tab tab, const LzJob<T>* __restrict__ jobs,
                                                      int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
@@ -567,7 +577,7 @@ __device__ __forceinline__ void cg_ap_body(const CgJob<TQ>& J, int lb) {
   if (threadIdx.x == 0) J.partial[(size_t)lb * LDP + PAP_COL] = db;
 }
 template <typename TQ, int D>
-__global__ __launch_bounds__(BLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_cg_ap(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const CgJob<TQ>& J = jobs[gp];
@@ -587,7 +597,7 @@ __device__ __forceinline__ void pcg_dots(const CgJob<TQ>& J, const double* rl, d
     lane_rows<RPL>(rl, vv);
     coldots<TQ, RPL>(J.Q, J.ldq, ncols, (int64_t)lb * (WAVE * RPL) + RPL * lane, vv, prow);
   }
-  for (int c = max(ncols, 0) + threadIdx.x; c < kq; c += BLK) prow[c] = 0.0;
+  for (int c = max(ncols, 0) + threadIdx.x; c < kq; c += RBLK) prow[c] = 0.0;
   if (threadIdx.x == 0) prow[kq] = ssb;
 }
 
@@ -613,7 +623,7 @@ __device__ __forceinline__ void pcg_init_body(const CgJob<TQ>& J, int lb) {
   pcg_dots<TQ, RPL>(J, rl, ssb, lb);
 }
 template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_pcg_init(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const CgJob<TQ>& J = jobs[gp];
@@ -651,7 +661,7 @@ __device__ __forceinline__ void pcg_update_body(const CgJob<TQ>& J, int lb) {
   pcg_dots<TQ, RPL>(J, rl, ssb, lb);
 }
 template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_pcg_update(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const CgJob<TQ>& J = jobs[gp];
@@ -726,9 +736,9 @@ template <typename TQ, int RPL>
 __device__ __forceinline__ void pcg_apply_body(const CgJob<TQ>& J, int lb) {
   if (J.ctl->cg_done) return;
   __shared__ double dl[MAXK];
-  __shared__ double red[4][BLK];
+  __shared__ double red[CWV][RB];
   const int k = min(J.kq, J.ctl->k_eff);
-  for (int c = threadIdx.x; c < k; c += BLK) dl[c] = J.dvec[c];
+  for (int c = threadIdx.x; c < k; c += RBLK) dl[c] = J.dvec[c];
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
   constexpr int RBK = WAVE * RPL;
@@ -741,11 +751,11 @@ __device__ __forceinline__ void pcg_apply_body(const CgJob<TQ>& J, int lb) {
   const int64_t row = r0 + t;
   if (t >= RBK || row >= J.n) return;
   double acc = J.r[row] * J.rscale;
-  if (k > 0) acc += red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  if (k > 0) acc += red_sum(red, t);
   J.z[row] = acc;
 }
 template <typename TQ>
-__global__ __launch_bounds__(BLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
+__global__ __launch_bounds__(RBLK) void k_pcg_apply(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const CgJob<TQ>& J = jobs[gp];
@@ -912,20 +922,20 @@ __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t i
 // partial rows of s = Rt^T v (columns < keff) over blocks of 64 RPL grid
 // rows; lanes own columns, waves split the rows.
 template <typename TR, int SPLIT, int RPL>
-__global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
+__global__ __launch_bounds__(RBLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
                                                  const void* __restrict__ rt,
                                                  const uint16_t* __restrict__ rt_lo, int kpad,
                                                  const Ctl* ctl_main,
                                                  double* __restrict__ partial, const Ctl* ctl) {
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
-  __shared__ double wsum[BLK / WAVE][MAXK];
+  __shared__ double wsum[RBLK / WAVE][MAXK];
   const int keff = ctl_main->k_eff;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int64_t r0 = (int64_t)blockIdx.x * RBK;
   const int64_t r1 = min<int64_t>(r0 + RBK, m);
   double a0 = 0.0, a1 = 0.0;
-  for (int64_t u = r0 + w; u < r1; u += BLK / WAVE) {
+  for (int64_t u = r0 + w; u < r1; u += RBLK / WAVE) {
     const double vu = v[u];
     if (lane < keff) a0 += vu * rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane);
     if (lane + WAVE < keff) a1 += vu * rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE);
@@ -934,9 +944,9 @@ __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __rest
   wsum[w][lane + WAVE] = a1;
   __syncthreads();
   double* prow = partial + (size_t)blockIdx.x * LDP;
-  for (int c = threadIdx.x; c < keff; c += BLK) {
+  for (int c = threadIdx.x; c < keff; c += RBLK) {
     double s = 0.0;
-    for (int q = 0; q < BLK / WAVE; ++q) s += wsum[q][c];
+    for (int q = 0; q < RBLK / WAVE; ++q) s += wsum[q][c];
     prow[c] = s;
   }
 }
@@ -945,7 +955,7 @@ __global__ __launch_bounds__(BLK) void k_rt_dots(int64_t m, const double* __rest
 // Q'_{0..ncols-1}^T v (none for ncols = 0).  Wave w takes 16 rows at a time:
 // lanes own columns of Rt, the 16 row dots are reduced by one butterfly.
 template <typename TR, int SPLIT, int RPL>
-__global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* __restrict__ kv,
+__global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double* __restrict__ kv,
                                                        const void* __restrict__ rt,
                                                        const uint16_t* __restrict__ rt_lo,
                                                        int kpad, const Ctl* ctl_main,
@@ -960,13 +970,13 @@ __global__ __launch_bounds__(BLK) void k_sp_apply_dots(int64_t m, const double* 
   __shared__ double vl[RBK];
   __shared__ double sl[MAXK];
   const int keff = ctl_main->k_eff;
-  for (int c = threadIdx.x; c < keff; c += BLK) sl[c] = sv[c];
+  for (int c = threadIdx.x; c < keff; c += RBLK) sl[c] = sv[c];
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * RBK;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const double s0 = lane < keff ? sl[lane] : 0.0;
   const double s1 = lane + WAVE < keff ? sl[lane + WAVE] : 0.0;
-  for (int rb = w * NR; rb < RBK; rb += 4 * NR) {
+  for (int rb = w * NR; rb < RBK; rb += (RBLK / WAVE) * NR) {
     double part[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
@@ -1433,14 +1443,14 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     ProfScope ps("sampler_probe", s);
     launch_fill<double>(gv, 1.0 / (double)m, m, s);
     toep_run<double>(A, t_probe, 0, 1, s);
-    k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm,
+    k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm,
                                                             partial, ctl);
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
-    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
+    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
                                                                   sv, Q, ldq, 0, v, partial, ctl);
-    k_lz_norm<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
+    k_lz_norm<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ);
     k_lz_bnorm<double><<<1, WAVE, 0, s>>>(t1, dJ);
-    k_lz_start<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ);
+    k_lz_start<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ);
   }
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
@@ -1448,25 +1458,25 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     toep_run<double>(A, t_step, j, 1, s);
     {
       ProfScope pk("rt_dots", s);
-      k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
+      k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
                                                               partial, ctl);
     }
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
     {
       ProfScope pk("sp_apply", s);
-      k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, BLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad,
+      k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad,
                                                                     cm, sv, Q, ldq, j + 1, v,
                                                                     partial, ctl);
     }
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
     {
       ProfScope pk("sp_udots", s);
-      k_lz_udots<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+      k_lz_udots<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ, j);
     }
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     {
       ProfScope pk("sp_finalize", s);
-      k_lz_finalize<double><<<(unsigned)nb, BLK, 0, s>>>(tnb, dJ, j);
+      k_lz_finalize<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ, j);
     }
   }
   {
@@ -1796,9 +1806,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     launch_fill<T>(t_m, A.at<FillJob<T>>(o_fi), s);
     toep_run<T>(A, t_probe, 0, 0, s);
     launch_gather<T>(make_tab(b_grid), A.at<GatherJob<T>>(o_ga), D, 0, s);
-    k_lz_norm<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+    k_lz_norm<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz);
     k_lz_bnorm<T><<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dlz);
-    k_lz_start<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz);
+    k_lz_start<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz);
   }
   // --- Lanczos steps -------------------------------------------------------------
   for (int j = 0; j < kmax; ++j) {
@@ -1806,17 +1816,17 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     toep_run<T>(A, t_step, j, 1, s);
     {
       ProfScope ps("lz_gdots", s);
-      k_lz_gdots<T, D><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_gdots<T, D><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
     }
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
     {
       ProfScope ps("lz_udots", s);
-      k_lz_udots<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_udots<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
     }
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     {
       ProfScope ps("lz_finalize", s);
-      k_lz_finalize<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dlz, j);
+      k_lz_finalize<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
     }
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
@@ -1865,10 +1875,10 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     }
     const SumJob* dscg = A.at<SumJob>(o_scg);
     const std::vector<int> nv0(G, 0);
-    k_pcg_init<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    k_pcg_init<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
     launch_colsum(dscg, nvq, 0, 0, s);
     k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 1);
-    k_pcg_apply<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+    k_pcg_apply<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
     int* dflag = nullptr;
     LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int), s));
     int hflag = 0;
@@ -1884,11 +1894,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
         launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s);
         toep_run<double>(A, t_cg, 0, 2, s);
-        k_cg_ap<T, D><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
-        k_pcg_update<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_cg_ap<T, D><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
+        k_pcg_update<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
         launch_colsum(dscg, nvq, 0, 2, s);
         k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 0);
-        k_pcg_apply<T><<<tab_blocks(t_rows), BLK, 0, s>>>(t_rows, dcg);
+        k_pcg_apply<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
       }
       k_cg_alldone<T><<<1, 64, 0, s>>>(G, dcg, dflag);
       LOVE_HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
