@@ -11,10 +11,12 @@ with every input already resident in device memory.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Prints one JSON line.  `value` is predictive variances per second over the
-whole step (cache built from scratch each step), from K steps timed without
-any event records.  The `roofline` object is for the kernel with the largest
-share of the step's device time, timed with HIP events around each of its
-launches (on its launch stream) over a second pass of the same K steps;
+whole step (cache built from scratch each step), from K steps timed with
+kernel timing off.  The `roofline` object is for the kernel with the largest
+share of the step's device time (found over the warm-up steps); over a second
+pass of K steps each of its launches carries a HIP event pair that takes the
+kernel's own start and end timestamps on its launch stream
+(hipExtLaunchKernel), which gives its average duration;
 `cpu_baseline` is the FP64 oracle on this host's cores.  `batched` compares
 a lock-step batched build of 64 GPs with 64 single builds.
 """
@@ -30,6 +32,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+# source file of each timing scope (the stored counter readings are void once it changes)
+SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": "lanczos.hip",
+                "lz_finalize": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
+                "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip", "rtilde": "lanczos.hip",
+                "scatter": "mvm.hip", "gather": "mvm.hip", "toep_band": "mvm.hip",
+                "toep_reduce": "mvm.hip", "toep_band64": "mvm.hip", "toep_reduce64": "mvm.hip",
+                "predict": "query.hip", "sample": "query.hip", "setup_sort": "sort.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_pmc_traffic.txt")
 METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; MVM HBM GB/s"
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
 KERNELS = ["lz_udots", "lz_gdots", "lz_finalize", "scatter", "gather", "predict", "sample",
@@ -90,6 +102,30 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
     return None
 
 
+def stored_traffic(scope):
+    """HBM bytes per launch of `scope` from the committed rocprofv3 counter
+    readings (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
+    calibration), or None if absent or if the kernel's source has changed."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE) or scope not in SCOPE_SOURCE:
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if len(parts) >= 2 and parts[0] in ("scale", "sha256", "kernel"):
+            fields.setdefault(parts[0], []).append(parts[1:])
+    src = SCOPE_SOURCE[scope]
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1803_06058_amd", "csrc", src), "rb").read()).hexdigest()
+    if [src, sha] not in fields.get("sha256", []):
+        return None
+    scale = {k: float(v) for k, v in fields.get("scale", [])}
+    for rec in fields.get("kernel", []):
+        if rec[0] == scope:
+            fetch_kib, write_kib = float(rec[1]), float(rec[2])
+            return int(1024 * (fetch_kib * scale["FETCH_SIZE"] + write_kib * scale["WRITE_SIZE"]))
+    return None
+
+
 def cpu_baseline(P, gpu_mean, gpu_var, nq):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     import numpy as np
@@ -141,6 +177,19 @@ def cpu_baseline(P, gpu_mean, gpu_var, nq):
         "build_s": t1 - t0, "sampler_s": t2 - t1,
     }
     return base, acc
+
+
+def dominant_bw(P, dbl):
+    """Coefficient band of the 1-D Toeplitz factor kept at the working
+    precision: the largest d with |c_d| > eps c_0 / L (eps the unit roundoff)."""
+    L = P.m[0]
+    h = (P.hi[0] - P.lo[0]) / (L - 3)
+    eps = 1.12e-16 if dbl else 5.96e-8
+    thr = eps / L
+    bw = L - 1
+    while bw > 0 and math.exp(-0.5 * (bw * h / P.lengthscale[0]) ** 2) <= thr:
+        bw -= 1
+    return bw
 
 
 def batched_section(B, WL, torch, dev):
@@ -259,7 +308,8 @@ def main():
     warm = B.profile_read(KERNELS)
     B.profile_enable(False)
     dominant = max(KERNELS, key=lambda k_: warm[k_][1])
-    # timed region: K clean steps (no event records) give ms_per_step and value
+    # timed region: K steps with timing off give ms_per_step and value (event
+    # objects on thousands of launches per step would slow the host down)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
@@ -268,9 +318,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
-    # the same K steps again with HIP events around every launch of the dominant
-    # kernel (recorded on its launch stream): its average launch duration
-    B.profile_enable(False)
+    # the same K steps again, each launch of the dominant kernel carrying a HIP
+    # event pair that takes the kernel's own start and end timestamps on its
+    # launch stream (hipExtLaunchKernel): its average duration
     B.profile_select([dominant])
     B.profile_enable(True)
     for _ in range(a.steps):
@@ -318,15 +368,30 @@ def main():
 
     k_eff = info.k_eff
     calls_step = dom[0] / a.steps
-    bytes_step = alg_bytes(dominant, P, k_eff, calls_step, info.k_eff_sample)
+    avg_us = dom[1] * 1e3 / max(1, dom[0])
     roof = None
-    if bytes_step is not None and dom[1] > 0:
-        achieved = bytes_step * a.steps / (dom[1] * 1e-3) / 1e9
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": int(dom[0]),
-                "avg_launch_us": round(dom[1] * 1e3 / max(1, dom[0]), 3),
-                "alg_bytes_per_launch": int(bytes_step / max(1.0, calls_step))}
+    if dominant in ("toep_band", "toep_band64"):
+        # VALU-bound banded product: 2 (2 bw + 1) flops per output, m outputs per step
+        m_tot = int(math.prod(P.m))
+        bw = int(round(dominant_bw(P, dominant == "toep_band64")))
+        flops = 2.0 * (2 * bw + 1) * m_tot
+        achieved = flops / (avg_us * 1e-6) / 1e12
+        peak = FP64_PEAK_TFLOPS if dominant == "toep_band64" else FP32_PEAK_TFLOPS
+        roof = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                "traffic": stored_traffic(dominant), "launches": int(dom[0]),
+                "avg_launch_us": round(avg_us, 3), "alg_flops_per_launch": int(flops)}
+    else:
+        bytes_step = alg_bytes(dominant, P, k_eff, calls_step, info.k_eff_sample)
+        if bytes_step is not None and dom[1] > 0:
+            achieved = bytes_step * a.steps / (dom[1] * 1e-3) / 1e9
+            roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic(dominant), "launches": int(dom[0]),
+                    "avg_launch_us": round(avg_us, 3),
+                    "alg_bytes_per_launch": int(bytes_step / max(1.0, calls_step))}
+    if roof is not None and roof["traffic"] is not None:
+        roof["traffic_gbps"] = round(roof["traffic"] / (avg_us * 1e-6) / 1e9, 1)
 
     out = {
         "metric": METRIC, "value": round(P.t / (ms_per_step * 1e-3), 1),

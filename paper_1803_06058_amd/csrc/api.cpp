@@ -71,6 +71,17 @@ void prof_begin(const char* name, hipStream_t s) {
   hipEventRecord(e, s);
   p.open.emplace_back(name, e);
 }
+bool prof_kernel_events(const char* name, hipEvent_t* start, hipEvent_t* stop) {
+  ProfState& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  if (!p.select.empty() && std::find(p.select.begin(), p.select.end(), name) == p.select.end())
+    return false;
+  if (p.pending.size() > 4096) drain(p);   // before the new pair: its kernel is not queued yet
+  *start = take_event(p);
+  *stop = take_event(p);
+  p.pending.push_back({name, *start, *stop});
+  return true;
+}
 void prof_end(const char* name, hipStream_t s) {
   ProfState& p = prof();
   std::lock_guard<std::mutex> g(p.mu);

@@ -2,6 +2,7 @@
 // Toeplitz plans, batched-launch helpers and the launchers implemented in the
 // .hip translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <cstring>
@@ -21,6 +22,19 @@ namespace love {
 bool prof_on();
 void prof_begin(const char* name, hipStream_t s);
 void prof_end(const char* name, hipStream_t s);
+
+// Kernel-level timing: when `name` is being timed, an event pair takes the
+// launched kernel's own start and end timestamps (no extra stream packets).
+bool prof_kernel_events(const char* name, hipEvent_t* start, hipEvent_t* stop);
+
+// Launch `kernel` on `s`, timed under `name` when timing is on.
+template <typename F, typename... Args>
+inline void tlaunch(const char* name, F kernel, dim3 grid, dim3 block, uint32_t smem,
+                    hipStream_t s, Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (!prof_on() || !prof_kernel_events(name, &a, &b)) a = b = nullptr;
+  hipExtLaunchKernelGGL(kernel, grid, block, smem, s, a, b, 0, args...);
+}
 
 struct ProfScope {
   const char* name;

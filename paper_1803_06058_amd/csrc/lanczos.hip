@@ -233,8 +233,7 @@ static void launch_colsum(const SumJob* jobs, const std::vector<int>& nv, int nv
   std::vector<int64_t> nbk(nv.size());
   for (size_t g = 0; g < nv.size(); ++g) nbk[g] = cdiv(std::max(nv[g] + nv_add, 0), BLK / WAVE);
   const Tab t = make_tab(nbk);
-  ProfScope ps("colsum", s);
-  if (tab_blocks(t)) k_colsum<<<tab_blocks(t), BLK, 0, s>>>(t, jobs, nv_add, mode);
+  if (tab_blocks(t)) tlaunch("colsum", k_colsum, tab_blocks(t), BLK, 0, s, t, jobs, nv_add, mode);
 }
 
 // ----------------------------------------------------------------------------
@@ -1456,28 +1455,15 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
     toep_run<double>(A, t_step, j, 1, s);
-    {
-      ProfScope pk("rt_dots", s);
-      k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, qj, c->rt, rlo, c->kpad, cm,
-                                                              partial, ctl);
-    }
+    tlaunch("rt_dots", k_rt_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, qj, c->rt, rlo,
+            c->kpad, cm, partial, (const Ctl*)ctl);
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
-    {
-      ProfScope pk("sp_apply", s);
-      k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad,
-                                                                    cm, sv, Q, ldq, j + 1, v,
-                                                                    partial, ctl);
-    }
+    tlaunch("sp_apply", k_sp_apply_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, kv, c->rt,
+            rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl);
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    {
-      ProfScope pk("sp_udots", s);
-      k_lz_udots<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ, j);
-    }
+    tlaunch("sp_udots", k_lz_udots<double>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
-    {
-      ProfScope pk("sp_finalize", s);
-      k_lz_finalize<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ, j);
-    }
+    tlaunch("sp_finalize", k_lz_finalize<double>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
   }
   {
     ProfScope pe("sampler_eig", s);
@@ -1814,27 +1800,15 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   for (int j = 0; j < kmax; ++j) {
     launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s);
     toep_run<T>(A, t_step, j, 1, s);
-    {
-      ProfScope ps("lz_gdots", s);
-      k_lz_gdots<T, D><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
-    }
+    tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    {
-      ProfScope ps("lz_udots", s);
-      k_lz_udots<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
-    }
+    tlaunch("lz_udots", k_lz_udots<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
-    {
-      ProfScope ps("lz_finalize", s);
-      k_lz_finalize<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz, j);
-    }
+    tlaunch("lz_finalize", k_lz_finalize<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
   k_tri_chol<T><<<tab_blocks(t_one), 64, 0, s>>>(t_one, dlz, 0.0);
-  {
-    ProfScope ps("rtilde", s);
-    k_rtilde<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, A.at<RtJob<T>>(o_rj));
-  }
+  tlaunch("rtilde", k_rtilde<T>, tab_blocks(t_m), 256, 0, s, t_m, A.at<RtJob<T>>(o_rj));
   // The samplers (grid space, need Rt) and the mean solve (needs Q) are
   // independent chains of small kernels: the samplers run on a side stream
   // concurrently with the mean CG, and the caller's stream waits for them.

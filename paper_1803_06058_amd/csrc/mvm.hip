@@ -125,14 +125,13 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
                     hipStream_t s) {
-  ProfScope ps("scatter", s);
   const unsigned nb = tab_blocks(tab);
   if (nb == 0) return;
   switch (d) {
-    case 1: k_scatter<T, 1><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
-    case 2: k_scatter<T, 2><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
-    case 3: k_scatter<T, 3><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
-    case 4: k_scatter<T, 4><<<nb, 256, 0, s>>>(tab, jobs, j, mode); break;
+    case 1: tlaunch("scatter", k_scatter<T, 1>, nb, 256, 0, s, tab, jobs, j, mode); break;
+    case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
+    case 3: tlaunch("scatter", k_scatter<T, 3>, nb, 256, 0, s, tab, jobs, j, mode); break;
+    case 4: tlaunch("scatter", k_scatter<T, 4>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
 template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t);
@@ -157,14 +156,13 @@ __global__ __launch_bounds__(256) void k_gather(Tab tab, const GatherJob<T>* __r
 
 template <typename T>
 void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s) {
-  ProfScope ps("gather", s);
   const unsigned nb = tab_blocks(tab);
   if (nb == 0) return;
   switch (d) {
-    case 1: k_gather<T, 1><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
-    case 2: k_gather<T, 2><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
-    case 3: k_gather<T, 3><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
-    case 4: k_gather<T, 4><<<nb, 256, 0, s>>>(tab, jobs, mode); break;
+    case 1: tlaunch("gather", k_gather<T, 1>, nb, 256, 0, s, tab, jobs, mode); break;
+    case 2: tlaunch("gather", k_gather<T, 2>, nb, 256, 0, s, tab, jobs, mode); break;
+    case 3: tlaunch("gather", k_gather<T, 3>, nb, 256, 0, s, tab, jobs, mode); break;
+    case 4: tlaunch("gather", k_gather<T, 4>, nb, 256, 0, s, tab, jobs, mode); break;
   }
 }
 template void launch_gather<float>(const Tab&, const GatherJob<float>*, int, int, hipStream_t);
@@ -456,14 +454,12 @@ void toep_run(const JobArena& A, const ToepRun<T>& run, int j, int mode, hipStre
   for (int step = 0; step < run.d; ++step) {
     const auto& ax = run.ax[step];
     const ToepJob<T>* jobs = A.at<ToepJob<T>>(ax.jobs);
-    if (tab_blocks(ax.band)) {
-      ProfScope pb(sizeof(T) == 8 ? "toep_band64" : "toep_band", s);
-      k_toep_band<T><<<tab_blocks(ax.band), TB_WAVES * WAVE, 0, s>>>(ax.band, jobs, j, mode);
-    }
-    if (tab_blocks(ax.reduce)) {
-      ProfScope pr(sizeof(T) == 8 ? "toep_reduce64" : "toep_reduce", s);
-      k_toep_reduce<T><<<tab_blocks(ax.reduce), 256, 0, s>>>(ax.reduce, jobs, j, mode);
-    }
+    if (tab_blocks(ax.band))
+      tlaunch(sizeof(T) == 8 ? "toep_band64" : "toep_band", k_toep_band<T>, tab_blocks(ax.band),
+              TB_WAVES * WAVE, 0, s, ax.band, jobs, j, mode);
+    if (tab_blocks(ax.reduce))
+      tlaunch(sizeof(T) == 8 ? "toep_reduce64" : "toep_reduce", k_toep_reduce<T>,
+              tab_blocks(ax.reduce), 256, 0, s, ax.reduce, jobs, j, mode);
     if (tab_blocks(ax.lines))
       k_toep_lines<T><<<tab_blocks(ax.lines), 256, ax.smem_lines, s>>>(ax.lines, jobs, j, mode);
     if (tab_blocks(ax.fft)) launch_fft_conv<T>(ax.fft, jobs, ax.smem_fft, j, mode, s);

@@ -169,7 +169,6 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
                           const std::vector<const T*>& xs, const std::vector<int64_t>& ts,
                           const std::vector<T*>& means, const std::vector<T*>& vars,
                           hipStream_t s) {
-  ProfScope ps("predict", s);
   const int G = (int)cs.size();
   const int d = cs[0]->d;
   const bool split = cs[0]->cfg.precision == LOVE_P_FP32_BF16SPLIT;
@@ -178,8 +177,8 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
     const PredJob<T> J = pred_job<T>(cs[0], xs[0], ts[0], means[0], vars[0]);
     const unsigned nb = (unsigned)cdiv(ts[0], 4);
 #define LAUNCH_P(D)                                                   \
-  if (split) k_predict<T, D, 1><<<nb, 256, 0, s>>>(J);                \
-  else k_predict<T, D, 0><<<nb, 256, 0, s>>>(J);
+  if (split) tlaunch("predict", k_predict<T, D, 1>, nb, 256, 0, s, J); \
+  else tlaunch("predict", k_predict<T, D, 0>, nb, 256, 0, s, J);
     switch (d) {
       case 1: LAUNCH_P(1); break;
       case 2: LAUNCH_P(2); break;
@@ -206,8 +205,8 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
     const PredJob<T>* dj = A.at<PredJob<T>>(o);
     const unsigned nb = tab_blocks(tab);
 #define LAUNCH_PB(D)                                                  \
-  if (split) k_predict_b<T, D, 1><<<nb, 256, 0, s>>>(tab, dj);        \
-  else k_predict_b<T, D, 0><<<nb, 256, 0, s>>>(tab, dj);
+  if (split) tlaunch("predict", k_predict_b<T, D, 1>, nb, 256, 0, s, tab, dj); \
+  else tlaunch("predict", k_predict_b<T, D, 0>, nb, 256, 0, s, tab, dj);
     switch (d) {
       case 1: LAUNCH_PB(1); break;
       case 2: LAUNCH_PB(2); break;
@@ -529,7 +528,6 @@ __global__ __launch_bounds__(256) void k_sample(GridT<T> g, const T* __restrict_
 template <typename T>
 love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns, T* out,
                    hipStream_t s) {
-  ProfScope ps("sample", s);
   if (t == 0 || ns == 0) return LOVE_OK;
   Ctl h;
   LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -540,10 +538,10 @@ love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, 
   const size_t shm = sizeof(float) * ((size_t)SP_TP * (ks + 1) + (size_t)ks * 64 + 64);
   dim3 grid((unsigned)cdiv(t, SP_TP));
   switch (c->d) {
-    case 1: k_sample<T, 1><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 2: k_sample<T, 2><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 3: k_sample<T, 3><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 4: k_sample<T, 4><<<grid, 256, shm, s>>>(g, xs, t, c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 1: tlaunch("sample", k_sample<T, 1>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 2: tlaunch("sample", k_sample<T, 2>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 3: tlaunch("sample", k_sample<T, 3>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 4: tlaunch("sample", k_sample<T, 4>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
   }
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
