@@ -36,7 +36,7 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 # source file of each timing scope (the stored counter readings are void once it changes)
 SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": "lanczos.hip",
-                "lz_finalize": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
+                "lz_finalize": "lanczos.hip", "lz_cdots": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
                 "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip", "rtilde": "lanczos.hip",
                 "scatter": "mvm.hip", "gather": "mvm.hip", "toep_band": "mvm.hip",
                 "toep_reduce": "mvm.hip", "toep_band64": "mvm.hip", "toep_reduce64": "mvm.hip",
@@ -44,7 +44,7 @@ SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_pmc_traffic.txt")
 METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; MVM HBM GB/s"
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
-KERNELS = ["lz_udots", "lz_gdots", "lz_finalize", "scatter", "gather", "predict", "sample",
+KERNELS = ["lz_udots", "lz_gdots", "lz_cdots", "lz_finalize", "scatter", "gather", "predict", "sample",
            "rtilde", "setup_sort", "colsum", "sp_apply", "rt_dots", "sp_udots", "sp_finalize",
            "toep_band", "toep_reduce", "toep_band64", "toep_reduce64"]
 

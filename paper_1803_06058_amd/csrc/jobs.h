@@ -34,7 +34,8 @@ __device__ inline bool tab_find(const Tab& t, int b, int& gp, int& lb) {
   return b < t.off[t.G];
 }
 
-// g = W^T v with v = v_base + j * v_js (mode bit 4: W^T (v + ctl->ratio * v2))
+// g = W^T v with v = v_base + j * v_js, into out + j * out_js
+// (mode bit 4: W^T (v + ctl->ratio * v2))
 template <typename T>
 struct ScatterJob {
   GridT<T> g;
@@ -44,6 +45,7 @@ struct ScatterJob {
   int64_t v_js;
   const T* v2;
   T* out;                     // m
+  int64_t out_js;
   const Ctl* ctl;
 };
 
@@ -101,6 +103,13 @@ struct LzJob {
   T* gv;                      // m: W^T q_j
   T* gm;                      // m
   double* partial;            // nb x LDP
+  // grid-space first pass (gpath = 1, used when m <= n): G = W^T Q, column j
+  // at G + j ldg (rows m..ldg-1 zero), and nbc partial rows of G^T R_j
+  int gpath;
+  const T* G;
+  int64_t ldg;
+  double* gpart;              // nbc x LDP
+  int nbc;
   double* coef;               // LDP
   double* c2;                 // LDP
   double* amax;               // LDP

@@ -9,6 +9,11 @@
 //   gdots     v = W R_j + sigma^2 q_j ;  per-block partials of Q_{0..j}^T v
 //   colsum    c = Q_{0..j}^T v   (first Gram-Schmidt pass; c_j = alpha_j)
 //   udots     r' = v - Q c ; per-block partials of Q^T r' and ||r'||^2
+//   (when m <= n the first pass runs in grid space instead: with G = W^T Q,
+//   kept column by column from the scatter, Q^T v = G^T R_j + sigma^2 Q^T q_j,
+//   and Q^T q_j is taken as e_j -- the second pass removes what that leaves --
+//   so one small kernel (cdots, partial rows over grid blocks) replaces
+//   gdots + colsum, and udots forms v itself and adds the cdots rows)
 //   colsum    c2, ||r'||^2       (second pass)
 //   finalize  alpha_j = c_j + c2_j, beta_j = sqrt(||r'||^2 - ||c2||^2),
 //             stop test, q_{j+1} = (r' - Q c2) / beta_j
@@ -323,8 +328,87 @@ __global__ __launch_bounds__(RBLK) void k_lz_gdots(Tab tab, const LzJob<T>* __re
   else lz_gdots_body<T, D, 1>(J, lb, j);
 }
 
-// Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].
-template <typename T, int RPL>
+// Grid-space first pass: partial rows of G_{0..j}^T R_j over the GP's nbc
+// blocks; block lb takes the 256-row tiles lb, lb + nbc, ... (lane: 4 rows),
+// the waves split the columns as in coldots and keep one running sum per
+// column group across tiles.  R_j has no padding rows (masked); G's padding
+// rows are zero.
+template <typename T>
+__global__ __launch_bounds__(RBLK) void k_lz_cdots(Tab tab, const LzJob<T>* __restrict__ jobs,
+                                                  int j) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const LzJob<T>& J = jobs[gp];
+  if (J.ctl->stop) return;
+  static_assert(MAXK <= 2 * CWV * BF_NV, "two column groups per wave");
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int ncols = j + 1;
+  const T* Rj = J.R + (int64_t)j * J.m;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t t0 = (int64_t)lb * RB; t0 < J.m; t0 += (int64_t)J.nbc * RB) {
+    const int64_t row = t0 + 4 * lane;
+    double vv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) vv[r] = row + r < J.m ? (double)Rj[row + r] : 0.0;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int base = w + it * CWV * BF_NV;
+      if (base >= ncols) break;
+      T q[BF_NV][4];
+#pragma unroll
+      for (int i = 0; i < BF_NV; ++i) {
+        const int c = min(base + CWV * i, ncols - 1);
+        loadr<4>(J.G + (int64_t)c * J.ldg, row, q[i]);
+      }
+      double a[BF_NV];
+#pragma unroll
+      for (int i = 0; i < BF_NV; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s += (double)q[i][r] * vv[r];
+        a[i] = (base + CWV * i < ncols) ? s : 0.0;
+      }
+      acc[it] += bfly_sum<BF_NV>(a);
+    }
+  }
+  if ((lane & ((1 << BF_SHIFT) - 1)) == 0) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int c = w + it * CWV * BF_NV + CWV * ((lane >> BF_SHIFT) & (BF_NV - 1));
+      if (c < ncols) J.gpart[(size_t)lb * LDP + c] = acc[it];
+    }
+  }
+}
+
+// c_i = sum of the nbc cdots rows (+ sigma^2 at i = j), into cl; block 0
+// also stores them as the first-pass coefficients.  Rows are added in a
+// fixed order (4 interleaved parts, then the parts in order).
+template <typename T>
+__device__ __forceinline__ void gpass_coef(const LzJob<T>& J, int j, int lb, double* cl) {
+  __shared__ double part[RBLK / 128][128];
+  const int ncols = j + 1;
+  const int c = threadIdx.x & 127, p = threadIdx.x >> 7;
+  double s = 0.0;
+  if (c < ncols) {
+#pragma unroll 4
+    for (int b = p; b < J.nbc; b += RBLK / 128) s += J.gpart[(size_t)b * LDP + c];
+  }
+  part[p][c] = s;
+  __syncthreads();
+  if (threadIdx.x < ncols) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < RBLK / 128; ++q) t += part[q][threadIdx.x];
+    if ((int)threadIdx.x == j) t += (double)J.sigma2;
+    cl[threadIdx.x] = t;
+    if (lb == 0) J.coef[threadIdx.x] = t;
+  }
+}
+
+// Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].  With the
+// grid-space first pass, v = W R_j + sigma^2 q_j is formed here and c comes
+// from the cdots rows.
+template <typename T, int D, int RPL>
 __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) {
   if (J.ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
@@ -333,19 +417,29 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   __shared__ double rl[RBK];
   __shared__ double scr[16];
   const int ncols = j + 1;
-  for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)lb * RBK;
+  const int64_t row = r0 + t;
+  T vrow = T(0);
+  if (J.gpath) {
+    if (t < RBK && row < J.n)
+      vrow = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) +
+             J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
+    gpass_coef<T>(J, j, lb, cl);
+  } else {
+    if (t < RBK && row < J.n) vrow = J.v[row];
+    for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
+  }
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
+  const int64_t rowL = r0 + RPL * lane;
   colproj<T, RPL>(J.Q, J.ldq, ncols, rowL, cl, red);
   __syncthreads();
-  const int t = threadIdx.x;
-  const int64_t row = r0 + t;
   double rv = 0.0;
   if (t < RBK) {
     if (row < J.n) {
       const double proj = red_sum(red, t);
-      const T r = (T)((double)J.v[row] - proj);
+      const T r = (T)((double)vrow - proj);
       J.r[row] = r;
       rv = (double)r;
     }
@@ -359,14 +453,14 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   coldots<T, RPL>(J.Q, J.ldq, ncols, rowL, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(RBLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
                                                   int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
-  if (J.rpl == 4) lz_udots_body<T, 4>(J, lb, j);
-  else lz_udots_body<T, 1>(J, lb, j);
+  if (J.rpl == 4) lz_udots_body<T, D, 4>(J, lb, j);
+  else lz_udots_body<T, D, 1>(J, lb, j);
 }
 
 // alpha_j, beta_j, stop test (every block, identically), then
@@ -1461,7 +1555,7 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     tlaunch("sp_apply", k_sp_apply_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, kv, c->rt,
             rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl);
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    tlaunch("sp_udots", k_lz_udots<double>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
+    tlaunch("sp_udots", k_lz_udots<double, 1>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     tlaunch("sp_finalize", k_lz_finalize<double>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
   }
@@ -1501,7 +1595,9 @@ namespace {
 template <typename T>
 struct GpBufs {
   T *Q = nullptr, *R = nullptr, *v = nullptr, *r = nullptr, *gv = nullptr, *gm = nullptr,
-    *tsc = nullptr;
+    *tsc = nullptr, *G = nullptr;
+  double* gpart = nullptr;
+  int64_t ldg = 0;     // 0: no grid-space first pass
   double *partial = nullptr, *coef = nullptr, *c2 = nullptr, *amax = nullptr, *ldiag = nullptr,
          *lsub = nullptr;
   // mean solve (double)
@@ -1521,10 +1617,12 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   const int64_t ts = toeplitz_scratch_elems(c);
   b.nbg = (int)std::min<int64_t>(256, std::max<int64_t>(1, cdiv(n, 128)));
   b.rpbg = cdiv(n, (int64_t)b.nbg);
+  // grid-space first pass when the grid is no larger than the data
+  b.ldg = m <= n ? cdiv(m, RB) * RB : 0;
   size_t tb = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
-                           (size_t)ts);
+                           (size_t)ts + (size_t)b.ldg * k);
   tb = (tb + 255) & ~size_t(255);
-  size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP);
+  size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP + (b.ldg ? (size_t)64 * LDP : 0));
   if (mean) {
     const bool own = sizeof(T) != 8;
     db += sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 5 * (size_t)ldq +
@@ -1533,8 +1631,12 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   }
   LOVE_HIP_TRY(hipMallocAsync((void**)&b.mem, tb + db, s));
   T* t = (T*)b.mem;
-  b.Q = t;
-  b.R = b.Q + (size_t)ldq * k;
+  b.Q = t;   // Q and G first: their columns start on 16-byte boundaries
+  if (b.ldg) {
+    b.G = b.Q + (size_t)ldq * k;
+    LOVE_HIP_TRY(hipMemsetAsync(b.G, 0, sizeof(T) * (size_t)b.ldg * k, s));
+  }
+  b.R = b.Q + (size_t)ldq * k + (size_t)b.ldg * k;
   b.v = b.R + (size_t)k * m;
   b.r = b.v + ldq;
   b.gv = b.r + ldq;
@@ -1548,6 +1650,10 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   b.ldiag = b.amax + LDP;
   b.lsub = b.ldiag + LDP;
   q = b.lsub + LDP + LDP;
+  if (b.ldg) {
+    b.gpart = q;
+    q += (size_t)64 * LDP;
+  }
   if (mean) {
     if (sizeof(T) != 8) {
       b.x64 = q;
@@ -1608,7 +1714,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   std::vector<int64_t> js0(G, 0), js_m(G);
   std::vector<const Ctl*> ctls(G);
   std::vector<int64_t> b_rows(G), b_nodes(G), b_m(G), b_one(G, 1), b_grid(G);
-  const std::vector<int> nv1(G, 1), nv2(G, 2);   // columns of the coef / c2 sums at j = 0
+  std::vector<int> nv1(G, 1);
+  const std::vector<int> nv2(G, 2);   // columns of the coef / c2 sums at j = 0
+  std::vector<int64_t> b_gd(G), b_cd(G), js_in(G);
   int kmax = 0;
   for (int g = 0; g < G; ++g) {
     love_cache* c = cs[g];
@@ -1643,6 +1751,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     J.tol = c->tol_lanczos;
     J.klast = c->k - 1;
     J.nb = (int)nb;
+    J.gpath = b.ldg ? 1 : 0;
+    J.G = b.G;
+    J.ldg = b.ldg;
+    J.gpart = b.gpart;
+    J.nbc = b.ldg ? (int)std::min<int64_t>(64, cdiv(c->m, RB)) : 0;
     lz[g] = J;
     ScatterJob<T> S{};
     S.g = J.g;
@@ -1650,7 +1763,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     S.cell_start = c->cell_start;
     S.v = b.Q;
     S.v_js = c->ldq;
-    S.out = b.gv;
+    S.out = J.gpath ? b.G : b.gv;
+    S.out_js = J.gpath ? b.ldg : 0;
     S.ctl = c->ctl;
     sc[g] = S;
     GatherJob<T> Ga{};
@@ -1673,10 +1787,14 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     Rj.ctl = c->ctl;
     rj[g] = Rj;
     s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
+    nv1[g] = J.gpath ? -(1 << 20) : 1;   // no first-pass sums on the grid-space path
+    b_gd[g] = J.gpath ? 0 : nb;
+    b_cd[g] = J.nbc;
+    js_in[g] = J.gpath ? b.ldg : 0;
     s_c2[g] = SumJob{b.partial, b.c2, c->ctl, (int)nb, 2};
     t_in_probe[g] = b.gv;
     t_out_probe[g] = b.gm;
-    t_in_step[g] = b.gv;
+    t_in_step[g] = J.gpath ? b.G : b.gv;
     t_out_step[g] = b.R;
     js_m[g] = c->m;
     t_scr[g] = b.tsc;
@@ -1693,7 +1811,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   ToepRun<T> t_probe, t_step;
   toep_prepare<T>(A, t_probe, cs, t_in_probe, js0, t_out_probe, js0, t_scr,
                   std::vector<const Ctl*>(G, nullptr));
-  toep_prepare<T>(A, t_step, cs, t_in_step, js0, t_out_step, js_m, t_scr, ctls);
+  toep_prepare<T>(A, t_step, cs, t_in_step, js_in, t_out_step, js_m, t_scr, ctls);
   // mean solve jobs
   std::vector<CgJob<T>> cg(G);
   std::vector<ScatterJob<double>> csc(G), cfin(G);
@@ -1784,7 +1902,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   if (st != LOVE_OK) return st;
   const LzJob<T>* dlz = A.at<LzJob<T>>(o_lz);
   const Tab t_rows = make_tab(b_rows), t_nodes = make_tab(b_nodes), t_m = make_tab(b_m),
-            t_one = make_tab(b_one);
+            t_one = make_tab(b_one), t_gd = make_tab(b_gd), t_cd = make_tab(b_cd);
   for (int g = 0; g < G; ++g) k_ctl_init<<<1, 1, 0, s>>>(cs[g]->ctl);
   // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
   {
@@ -1800,9 +1918,13 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   for (int j = 0; j < kmax; ++j) {
     launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s);
     toep_run<T>(A, t_step, j, 1, s);
-    tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
-    launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
-    tlaunch("lz_udots", k_lz_udots<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
+    if (tab_blocks(t_cd))
+      tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(t_cd), RBLK, 0, s, t_cd, dlz, j);
+    if (tab_blocks(t_gd)) {
+      tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_gd), RBLK, 0, s, t_gd, dlz, j);
+      launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+    }
+    tlaunch("lz_udots", k_lz_udots<T, D>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
     launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     tlaunch("lz_finalize", k_lz_finalize<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
   }

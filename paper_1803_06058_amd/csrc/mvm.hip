@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
     }
   }
   acc = wave_sum(acc);
-  if (lane == 0) J.out[u] = acc;
+  if (lane == 0) J.out[(int64_t)j * J.out_js + u] = acc;
 }
 
 template <typename T>
