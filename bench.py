@@ -37,7 +37,8 @@ FP64_PEAK_TFLOPS = 78.6
 # source file of each timing scope (the stored counter readings are void once it changes)
 SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": "lanczos.hip",
                 "lz_finalize": "lanczos.hip", "lz_cdots": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
-                "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip", "rtilde": "lanczos.hip",
+                "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip",
+                "sp_band_rt": "lanczos.hip", "sp_reduce_sum": "lanczos.hip", "rtilde": "lanczos.hip",
                 "scatter": "mvm.hip", "gather": "mvm.hip", "toep_band": "mvm.hip",
                 "toep_reduce": "mvm.hip", "toep_band64": "mvm.hip", "toep_reduce64": "mvm.hip",
                 "predict": "query.hip", "sample": "query.hip", "setup_sort": "sort.hip"}
@@ -46,7 +47,8 @@ METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; M
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
 KERNELS = ["lz_udots", "lz_gdots", "lz_cdots", "lz_finalize", "scatter", "gather", "predict", "sample",
            "rtilde", "setup_sort", "colsum", "sp_apply", "rt_dots", "sp_udots", "sp_finalize",
-           "toep_band", "toep_reduce", "toep_band64", "toep_reduce64"]
+           "toep_band", "toep_reduce", "toep_band64", "toep_reduce64", "sp_band_rt",
+           "sp_reduce_sum"]
 
 
 def parse():

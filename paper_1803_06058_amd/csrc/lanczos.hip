@@ -33,6 +33,7 @@
 
 #include "internal.h"
 #include "ops.h"
+#include "toep_dev.h"
 
 namespace love {
 
@@ -208,16 +209,19 @@ struct SumJob {
   int nv;
 };
 
+__device__ __forceinline__ void colsum_block(const SumJob& J, int lb, int nv_add) {
+  const int c = lb * (BLK / WAVE) + threadIdx.x / WAVE;
+  if (c >= J.nv + nv_add) return;
+  const double s = colsum_wave(J.partial, J.nb, c);
+  if ((threadIdx.x & (WAVE - 1)) == 0) J.out[c] = s;
+}
 __global__ __launch_bounds__(BLK) void k_colsum(Tab tab, const SumJob* __restrict__ jobs,
                                                 int nv_add, int mode) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const SumJob& J = jobs[gp];
   if (ctl_skip(J.ctl, mode)) return;
-  const int c = lb * (BLK / WAVE) + threadIdx.x / WAVE;
-  if (c >= J.nv + nv_add) return;
-  const double s = colsum_wave(J.partial, J.nb, c);
-  if ((threadIdx.x & (WAVE - 1)) == 0) J.out[c] = s;
+  colsum_block(J, lb, nv_add);
 }
 
 // Rows per lane of the row kernels for a run over `rows` rows: 4 (256-row
@@ -1015,17 +1019,16 @@ __device__ inline double rt_val(const void* rt, const uint16_t* rt_lo, int64_t i
 // partial rows of s = Rt^T v (columns < keff) over blocks of 64 RPL grid
 // rows; lanes own columns, waves split the rows.
 template <typename TR, int SPLIT, int RPL>
-__global__ __launch_bounds__(RBLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
-                                                 const void* __restrict__ rt,
-                                                 const uint16_t* __restrict__ rt_lo, int kpad,
-                                                 const Ctl* ctl_main,
-                                                 double* __restrict__ partial, const Ctl* ctl) {
-  if (ctl->stop) return;
+__device__ __forceinline__ void rt_dots_block(int b, int64_t m, const double* __restrict__ v,
+                                              const void* __restrict__ rt,
+                                              const uint16_t* __restrict__ rt_lo, int kpad,
+                                              const Ctl* ctl_main,
+                                              double* __restrict__ partial) {
   constexpr int RBK = WAVE * RPL;
   __shared__ double wsum[RBLK / WAVE][MAXK];
   const int keff = ctl_main->k_eff;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  const int64_t r0 = (int64_t)blockIdx.x * RBK;
+  const int64_t r0 = (int64_t)b * RBK;
   const int64_t r1 = min<int64_t>(r0 + RBK, m);
   double a0 = 0.0, a1 = 0.0;
   for (int64_t u = r0 + w; u < r1; u += RBLK / WAVE) {
@@ -1036,11 +1039,60 @@ __global__ __launch_bounds__(RBLK) void k_rt_dots(int64_t m, const double* __res
   wsum[w][lane] = a0;
   wsum[w][lane + WAVE] = a1;
   __syncthreads();
-  double* prow = partial + (size_t)blockIdx.x * LDP;
+  double* prow = partial + (size_t)b * LDP;
   for (int c = threadIdx.x; c < keff; c += RBLK) {
     double s = 0.0;
     for (int q = 0; q < RBLK / WAVE; ++q) s += wsum[q][c];
     prow[c] = s;
+  }
+}
+template <typename TR, int SPLIT, int RPL>
+__global__ __launch_bounds__(RBLK) void k_rt_dots(int64_t m, const double* __restrict__ v,
+                                                 const void* __restrict__ rt,
+                                                 const uint16_t* __restrict__ rt_lo, int kpad,
+                                                 const Ctl* ctl_main,
+                                                 double* __restrict__ partial, const Ctl* ctl) {
+  if (ctl->stop) return;
+  rt_dots_block<TR, SPLIT, RPL>(blockIdx.x, m, v, rt, rt_lo, kpad, ctl_main, partial);
+}
+
+// Sampler step, first launch: K q_j by the banded product (blocks [0, nbb),
+// the axis job tj) and the partial rows of s = Rt^T q_j (the row blocks after
+// them) -- independent work on the same vector, one launch.
+static_assert(TB_WAVES * WAVE == RBLK, "band blocks and row blocks have one size");
+template <typename TR, int SPLIT, int RPL>
+__global__ __launch_bounds__(RBLK) void k_sp_band_rt(Tab tband, const ToepJob<double>* __restrict__ tj,
+                                                    int j, int nbb, int64_t m,
+                                                    const double* __restrict__ v,
+                                                    const void* __restrict__ rt,
+                                                    const uint16_t* __restrict__ rt_lo, int kpad,
+                                                    const Ctl* ctl_main,
+                                                    double* __restrict__ partial, const Ctl* ctl) {
+  if (ctl->stop) return;
+  if ((int)blockIdx.x < nbb) {
+    int gp, lb;
+    if (!tab_find(tband, blockIdx.x, gp, lb)) return;
+    toep_band_block<double>(tj[gp], lb, j);
+  } else {
+    rt_dots_block<TR, SPLIT, RPL>(blockIdx.x - nbb, m, v, rt, rt_lo, kpad, ctl_main, partial);
+  }
+}
+
+// Second launch: the segment sums of the banded product (blocks [0, nrb)) and
+// the column sums giving s (the blocks after them).
+static_assert(TB_RED == BLK, "reduce blocks and colsum blocks have one size");
+__global__ __launch_bounds__(BLK) void k_sp_reduce_sum(Tab tred,
+                                                      const ToepJob<double>* __restrict__ tj,
+                                                      int j, int nrb,
+                                                      const SumJob* __restrict__ sj,
+                                                      const Ctl* ctl) {
+  if (ctl->stop) return;
+  if ((int)blockIdx.x < nrb) {
+    int gp, lb;
+    if (!tab_find(tred, blockIdx.x, gp, lb)) return;
+    toep_reduce_block<double>(tj[gp], lb, j);
+  } else {
+    colsum_block(*sj, blockIdx.x - nrb, 0);
   }
 }
 
@@ -1545,13 +1597,27 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     k_lz_bnorm<double><<<1, WAVE, 0, s>>>(t1, dJ);
     k_lz_start<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ);
   }
+  // one banded axis: K q_j and s = Rt^T q_j share two launches
+  const auto& ax0 = t_step.ax[0];
+  const bool fuse = t_step.d == 1 && tab_blocks(ax0.band) > 0 && tab_blocks(ax0.lines) == 0 &&
+                    tab_blocks(ax0.fft) == 0;
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
-    toep_run<double>(A, t_step, j, 1, s);
-    tlaunch("rt_dots", k_rt_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, qj, c->rt, rlo,
-            c->kpad, cm, partial, (const Ctl*)ctl);
-    launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
+    if (fuse) {
+      const ToepJob<double>* tj = A.at<ToepJob<double>>(ax0.jobs);
+      const unsigned nbb = tab_blocks(ax0.band), nrb = tab_blocks(ax0.reduce);
+      tlaunch("sp_band_rt", k_sp_band_rt<TR, SPLIT, RPL>, nbb + (unsigned)nb, RBLK, 0, s,
+              ax0.band, tj, j, (int)nbb, m, qj, c->rt, rlo, c->kpad, cm, partial,
+              (const Ctl*)ctl);
+      tlaunch("sp_reduce_sum", k_sp_reduce_sum, nrb + (unsigned)cdiv(c->k, BLK / WAVE), BLK, 0,
+              s, ax0.reduce, tj, j, (int)nrb, A.at<SumJob>(o_rt), (const Ctl*)ctl);
+    } else {
+      toep_run<double>(A, t_step, j, 1, s);
+      tlaunch("rt_dots", k_rt_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, qj, c->rt, rlo,
+              c->kpad, cm, partial, (const Ctl*)ctl);
+      launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
+    }
     tlaunch("sp_apply", k_sp_apply_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, kv, c->rt,
             rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl);
     launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
