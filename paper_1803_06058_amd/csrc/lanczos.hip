@@ -183,6 +183,90 @@ __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, in
   for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
 }
 
+// A block's 64 RPL rows of the columns of Q that wave w handles (w + CWV i,
+// i < 2 BF_NV), loaded once into registers: a pass's projection and its dot
+// products share one read of Q, and the loads go out before the
+// coefficients they meet are known.  Same column order as colproj / coldots.
+static_assert(MAXK <= 2 * CWV * BF_NV, "two column groups per wave cover MAXK");
+template <typename T, int RPL>
+struct QRegs {
+  T q[2][BF_NV][RPL];
+};
+template <typename T, int RPL>
+__device__ __forceinline__ void qregs_load(QRegs<T, RPL>& R, const T* __restrict__ Q, int64_t ldq,
+                                           int ncols, int64_t rowL) {
+  const int w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int base = w + it * CWV * BF_NV;
+    if (base < ncols) {
+#pragma unroll
+      for (int i = 0; i < BF_NV; ++i) {
+        const int c = min(base + CWV * i, ncols - 1);
+        loadr<RPL>(Q + (int64_t)c * ldq, rowL, R.q[it][i]);
+      }
+    }
+  }
+}
+// colproj on the register tile (REWIDEN: widen each value at its use, which
+// keeps the register count down where the tile has no later use)
+template <typename T, int RPL, bool REWIDEN = false>
+__device__ __forceinline__ void colproj_regs(const QRegs<T, RPL>& R, int ncols,
+                                             const double* __restrict__ cl, double (*red)[RB]) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  double acc[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) acc[r] = 0.0;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int base = w + it * CWV * BF_NV;
+    if (base < ncols) {
+#pragma unroll
+      for (int i = 0; i < BF_NV; ++i) {
+        const int c = base + CWV * i;
+        const double f = c < ncols ? cl[min(c, ncols - 1)] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          T qv = R.q[it][i][r];
+          if constexpr (REWIDEN) asm volatile("" : "+v"(qv));
+          acc[r] += (double)qv * f;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
+}
+// coldots on the register tile
+template <typename T, int RPL>
+__device__ __forceinline__ void coldots_regs(const QRegs<T, RPL>& R, int ncols,
+                                             const double (&vv)[RPL], double* __restrict__ prow) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int base = w + it * CWV * BF_NV;
+    if (base < ncols) {
+      double a[BF_NV];
+#pragma unroll
+      for (int i = 0; i < BF_NV; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          // widen again here rather than keep colproj's widened copies alive
+          // (twice the registers of the tile)
+          T qv = R.q[it][i][r];
+          asm volatile("" : "+v"(qv));
+          s += (double)qv * vv[r];
+        }
+        a[i] = (base + CWV * i < ncols) ? s : 0.0;
+      }
+      const double tot = bfly_sum<BF_NV>(a);
+      const int c = base + CWV * ((lane >> BF_SHIFT) & (BF_NV - 1));
+      if ((lane & ((1 << BF_SHIFT) - 1)) == 0 && c < ncols) prow[c] = tot;
+    }
+  }
+}
+
 // sum of the column waves' projections of local row t, in wave order
 __device__ __forceinline__ double red_sum(const double (*red)[RB], int t) {
   double s = 0.0;
@@ -424,6 +508,10 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)lb * RBK;
   const int64_t row = r0 + t;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t rowL = r0 + RPL * lane;
+  QRegs<T, RPL> qr;
+  qregs_load<T, RPL>(qr, J.Q, J.ldq, ncols, rowL);
   T vrow = T(0);
   if (J.gpath) {
     if (t < RBK && row < J.n)
@@ -435,9 +523,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
     for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
   }
   __syncthreads();
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t rowL = r0 + RPL * lane;
-  colproj<T, RPL>(J.Q, J.ldq, ncols, rowL, cl, red);
+  colproj_regs<T, RPL>(qr, ncols, cl, red);
   __syncthreads();
   double rv = 0.0;
   if (t < RBK) {
@@ -454,7 +540,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   double vv[RPL];
   lane_rows<RPL>(rl, vv);
   double* prow = J.partial + (size_t)lb * LDP;
-  coldots<T, RPL>(J.Q, J.ldq, ncols, rowL, vv, prow);
+  coldots_regs<T, RPL>(qr, ncols, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
 template <typename T, int D>
@@ -479,48 +565,53 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   __shared__ double red[CWV][RB];
   __shared__ double s_beta;
   __shared__ int s_stop;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
+  QRegs<T, RPL> qr;
+  qregs_load<T, RPL>(qr, J.Q, J.ldq, j + 1, rowL);
   const double* c2rr = J.c2;
   for (int c = threadIdx.x; c <= j; c += RBLK) cl[c] = c2rr[c];
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < WAVE) {
     double c2n = 0.0;
-    for (int c = 0; c <= j; ++c) c2n += c2rr[c] * c2rr[c];
-    const double a = J.coef[j] + c2rr[j];
-    const double b2 = c2rr[j + 1] - c2n;
-    const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
-    const double amax = fmax(j > 0 ? J.amax[j - 1] : 0.0, fabs(a));
-    int stop = 0;
-    unsigned st = 0;
-    int keff = j + 1;
-    if (!isfinite(a) || !isfinite(b)) {
-      stop = 1;
-      st = SF_NONFINITE;
-      keff = j;
-    } else if (j < J.klast && !(b > J.tol * amax)) {
-      stop = 1;
-      st = SF_BREAKDOWN;
-    } else if (j >= J.klast) {
-      stop = 1;
-    }
-    s_beta = b;
-    s_stop = stop;
-    // Block 0 records; other blocks of this launch that read ctl->stop after
-    // it is set reach the same decision from the same inputs.
-    if (lb == 0) {
-      J.alpha[j] = a;
-      J.beta[j] = b;
-      J.amax[j] = amax;
-      ctl->k_eff = keff;
-      if (stop) {
-        ctl->stop = 1;
-        ctl->status |= st;
+    for (int c = lane; c <= j; c += WAVE) c2n += c2rr[c] * c2rr[c];
+    c2n = wave_sum(c2n);
+    if (threadIdx.x == 0) {
+      const double a = J.coef[j] + c2rr[j];
+      const double b2 = c2rr[j + 1] - c2n;
+      const double b = b2 > 0.0 ? sqrt(b2) : 0.0;
+      const double amax = fmax(j > 0 ? J.amax[j - 1] : 0.0, fabs(a));
+      int stop = 0;
+      unsigned st = 0;
+      int keff = j + 1;
+      if (!isfinite(a) || !isfinite(b)) {
+        stop = 1;
+        st = SF_NONFINITE;
+        keff = j;
+      } else if (j < J.klast && !(b > J.tol * amax)) {
+        stop = 1;
+        st = SF_BREAKDOWN;
+      } else if (j >= J.klast) {
+        stop = 1;
+      }
+      s_beta = b;
+      s_stop = stop;
+      // Block 0 records; other blocks of this launch that read ctl->stop after
+      // it is set reach the same decision from the same inputs.
+      if (lb == 0) {
+        J.alpha[j] = a;
+        J.beta[j] = b;
+        J.amax[j] = amax;
+        ctl->k_eff = keff;
+        if (stop) {
+          ctl->stop = 1;
+          ctl->status |= st;
+        }
       }
     }
   }
   __syncthreads();
   if (s_stop) return;
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
-  colproj<T, RPL>(J.Q, J.ldq, j + 1, rowL, cl, red);
+  colproj_regs<T, RPL, true>(qr, j + 1, cl, red);
   __syncthreads();
   const int t = threadIdx.x;
   if (t >= RBK) return;
@@ -1114,11 +1205,13 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
   constexpr int NR = 16;                 // rows per butterfly
   __shared__ double vl[RBK];
   __shared__ double sl[MAXK];
+  const int64_t r0 = (int64_t)blockIdx.x * RBK;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  QRegs<double, RPL> qr;   // Q' tile for the dots, loaded while Rt s is formed
+  qregs_load<double, RPL>(qr, Q, ldq, ncols, r0 + RPL * lane);
   const int keff = ctl_main->k_eff;
   for (int c = threadIdx.x; c < keff; c += RBLK) sl[c] = sv[c];
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * RBK;
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const double s0 = lane < keff ? sl[lane] : 0.0;
   const double s1 = lane + WAVE < keff ? sl[lane + WAVE] : 0.0;
   for (int rb = w * NR; rb < RBK; rb += (RBLK / WAVE) * NR) {
@@ -1147,7 +1240,7 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
   if (ncols == 0) return;
   double vv[RPL];
   lane_rows<RPL>(vl, vv);
-  coldots<double, RPL>(Q, ldq, ncols, r0 + RPL * lane, vv, partial + (size_t)blockIdx.x * LDP);
+  coldots_regs<double, RPL>(qr, ncols, vv, partial + (size_t)blockIdx.x * LDP);
 }
 
 // Eigen-decomposition T' = V diag(lam) V^T of the sampler's symmetric
