@@ -1188,8 +1188,19 @@ __global__ __launch_bounds__(BLK) void k_sp_reduce_sum(Tab tred,
 }
 
 // v = kv - Rt s on the block's 64 RPL grid rows, then partial rows of
-// Q'_{0..ncols-1}^T v (none for ncols = 0).  Wave w takes 16 rows at a time:
-// lanes own columns of Rt, the 16 row dots are reduced by one butterfly.
+// Q'_{0..ncols-1}^T v (none for ncols = 0).  Each wave takes NR rows per
+// butterfly: lanes own columns lane and lane + 64 of Rt (columns past k_eff
+// hold zeros, and s is zero there), and the NR row dots are reduced by one
+// butterfly.  The Rt values, kv and the Q' tile are loaded before s is read.
+template <typename TR, int SPLIT>
+__device__ __forceinline__ auto rt_raw(const void* rt, const uint16_t* rt_lo, int64_t idx) {
+  if constexpr (SPLIT) {
+    const uint16_t* hi = (const uint16_t*)rt;
+    return bf16_to_f32(hi[idx]) + bf16_to_f32(rt_lo[idx]);
+  } else {
+    return ((const TR*)rt)[idx];
+  }
+}
 template <typename TR, int SPLIT, int RPL>
 __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double* __restrict__ kv,
                                                        const void* __restrict__ rt,
@@ -1202,31 +1213,42 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
                                                        const Ctl* ctl) {
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
-  constexpr int NR = 16;                 // rows per butterfly
+  constexpr int NW = RBLK / WAVE;
+  constexpr int NR = RPL == 1 ? 8 : 16;        // rows per butterfly
+  constexpr int NIT = RBK / (NW * NR);         // butterflies per wave
+  constexpr int SH = NR == 8 ? 3 : 2;          // 6 - log2(NR)
+  static_assert(NIT * NW * NR == RBK, "rows split evenly over the waves");
+  using RV = decltype(rt_raw<TR, SPLIT>(nullptr, nullptr, 0));
   __shared__ double vl[RBK];
-  __shared__ double sl[MAXK];
+  __shared__ double sl[2 * WAVE];
   const int64_t r0 = (int64_t)blockIdx.x * RBK;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  QRegs<double, RPL> qr;   // Q' tile for the dots, loaded while Rt s is formed
+  QRegs<double, RPL> qr;   // Q' tile for the dots
   qregs_load<double, RPL>(qr, Q, ldq, ncols, r0 + RPL * lane);
-  const int keff = ctl_main->k_eff;
-  for (int c = threadIdx.x; c < keff; c += RBLK) sl[c] = sv[c];
-  __syncthreads();
-  const double s0 = lane < keff ? sl[lane] : 0.0;
-  const double s1 = lane + WAVE < keff ? sl[lane + WAVE] : 0.0;
-  for (int rb = w * NR; rb < RBK; rb += (RBLK / WAVE) * NR) {
-    double part[NR];
+  RV a0[NIT][NR], a1[NIT][NR];
+  const bool hi_cols = kpad > WAVE;            // kpad is 64 or 128
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      const int64_t u = min<int64_t>(r0 + rb + i, m - 1);
-      double p = 0.0;
-      if (lane < keff) p += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane) * s0;
-      if (lane + WAVE < keff) p += rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE) * s1;
-      part[i] = p;
+      const int64_t u = min<int64_t>(r0 + (it * NW + w) * NR + i, m - 1);
+      a0[it][i] = rt_raw<TR, SPLIT>(rt, rt_lo, u * kpad + lane);
+      a1[it][i] = hi_cols ? rt_raw<TR, SPLIT>(rt, rt_lo, u * kpad + lane + WAVE) : RV(0);
     }
+  }
+  const int keff = ctl_main->k_eff;
+  for (int c = threadIdx.x; c < 2 * WAVE; c += RBLK) sl[c] = c < keff ? sv[c] : 0.0;
+  __syncthreads();
+  const double s0 = sl[lane], s1 = sl[lane + WAVE];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int rb = (it * NW + w) * NR;
+    double part[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) part[i] = (double)a0[it][i] * s0 + (double)a1[it][i] * s1;
     const double tot = bfly_sum<NR>(part);
-    if ((lane & 3) == 0) {
-      const int i = (lane >> 2) & (NR - 1);
+    if ((lane & ((1 << SH) - 1)) == 0) {
+      const int i = (lane >> SH) & (NR - 1);
       const int64_t u = r0 + rb + i;
       double val = 0.0;
       if (u < m) {
