@@ -154,12 +154,22 @@ __device__ __forceinline__ void coldots(const T* __restrict__ Q, int64_t ldq, in
   }
 }
 
-// red[w][RPL lane + r] = sum over the wave's columns c (w, w+CWV, ...) of
+// Per-wave projection rows in LDS: local row t = RPL lane + r is kept at
+// r * RPAD + lane, so that the RPL-strided rows of a lane do not fall on the
+// same LDS banks when written (lanes contiguous) or read (row order).
+constexpr int RPAD = WAVE + 4;
+constexpr int REDW = 4 * RPAD;    // doubles per wave (RPL <= 4)
+template <int RPL>
+__device__ __forceinline__ int red_at(int t) {
+  return (t % RPL) * RPAD + t / RPL;
+}
+
+// row RPL lane + r of red[w] (at red_at) = sum over the wave's columns c (w, w+CWV, ...) of
 // Q[c][rowL + r] * cl[c]; the caller adds the CWV waves' rows in wave order.
 template <typename T, int RPL>
 __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, int ncols,
                                         int64_t rowL, const double* __restrict__ cl,
-                                        double (*red)[RB]) {
+                                        double (*red)[REDW]) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   double acc[RPL];
 #pragma unroll
@@ -180,7 +190,7 @@ __device__ __forceinline__ void colproj(const T* __restrict__ Q, int64_t ldq, in
     }
   }
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
+  for (int r = 0; r < RPL; ++r) red[w][r * RPAD + lane] = acc[r];
 }
 
 // A block's 64 RPL rows of the columns of Q that wave w handles (w + CWV i,
@@ -212,7 +222,7 @@ __device__ __forceinline__ void qregs_load(QRegs<T, RPL>& R, const T* __restrict
 // keeps the register count down where the tile has no later use)
 template <typename T, int RPL, bool REWIDEN = false>
 __device__ __forceinline__ void colproj_regs(const QRegs<T, RPL>& R, int ncols,
-                                             const double* __restrict__ cl, double (*red)[RB]) {
+                                             const double* __restrict__ cl, double (*red)[REDW]) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   double acc[RPL];
 #pragma unroll
@@ -235,7 +245,7 @@ __device__ __forceinline__ void colproj_regs(const QRegs<T, RPL>& R, int ncols,
     }
   }
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) red[w][RPL * lane + r] = acc[r];
+  for (int r = 0; r < RPL; ++r) red[w][r * RPAD + lane] = acc[r];
 }
 // coldots on the register tile
 template <typename T, int RPL>
@@ -268,10 +278,12 @@ __device__ __forceinline__ void coldots_regs(const QRegs<T, RPL>& R, int ncols,
 }
 
 // sum of the column waves' projections of local row t, in wave order
-__device__ __forceinline__ double red_sum(const double (*red)[RB], int t) {
+template <int RPL>
+__device__ __forceinline__ double red_sum(const double (*red)[REDW], int t) {
+  const int at = red_at<RPL>(t);
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < CWV; ++q) s += red[q][t];
+  for (int q = 0; q < CWV; ++q) s += red[q][at];
   return s;
 }
 
@@ -501,7 +513,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   if (J.ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
-  __shared__ double red[CWV][RB];
+  __shared__ double red[CWV][REDW];
   __shared__ double rl[RBK];
   __shared__ double scr[16];
   const int ncols = j + 1;
@@ -528,7 +540,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   double rv = 0.0;
   if (t < RBK) {
     if (row < J.n) {
-      const double proj = red_sum(red, t);
+      const double proj = red_sum<RPL>(red, t);
       const T r = (T)((double)vrow - proj);
       J.r[row] = r;
       rv = (double)r;
@@ -562,7 +574,7 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   __shared__ double cl[MAXK];
-  __shared__ double red[CWV][RB];
+  __shared__ double red[CWV][REDW];
   __shared__ double s_beta;
   __shared__ int s_stop;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -618,7 +630,7 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   const int64_t row = r0 + t;
   double q = 0.0;
   if (row < J.n) {
-    const double proj = red_sum(red, t);
+    const double proj = red_sum<RPL>(red, t);
     q = ((double)J.r[row] - proj) / s_beta;
   }
   J.Q[(int64_t)(j + 1) * J.ldq + row] = (T)q;
@@ -924,7 +936,7 @@ template <typename TQ, int RPL>
 __device__ __forceinline__ void pcg_apply_body(const CgJob<TQ>& J, int lb) {
   if (J.ctl->cg_done) return;
   __shared__ double dl[MAXK];
-  __shared__ double red[CWV][RB];
+  __shared__ double red[CWV][REDW];
   const int k = min(J.kq, J.ctl->k_eff);
   for (int c = threadIdx.x; c < k; c += RBLK) dl[c] = J.dvec[c];
   __syncthreads();
@@ -939,7 +951,7 @@ __device__ __forceinline__ void pcg_apply_body(const CgJob<TQ>& J, int lb) {
   const int64_t row = r0 + t;
   if (t >= RBK || row >= J.n) return;
   double acc = J.r[row] * J.rscale;
-  if (k > 0) acc += red_sum(red, t);
+  if (k > 0) acc += red_sum<RPL>(red, t);
   J.z[row] = acc;
 }
 template <typename TQ>
