@@ -73,9 +73,9 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
     f = 4
     nb = -(-n // 256) if -(-n // 256) >= 256 else -(-n // 64)   # row blocks of the main run
     mb = -(-m // 256) if -(-m // 256) >= 256 else -(-m // 64)   # row blocks of the sampler
-    if name == "colsum":        # partial rows read, sums written (main: 2 per step, sampler: 3)
-        main = sum(8 * nb * (j + 1) + 8 * nb * (j + 2) for j in range(k_eff))
-        samp = sum(8 * mb * (k_eff + (j + 1) + (j + 2)) for j in range(ks_eff))
+    if name == "colsum":        # partial rows read (main: c2, and c unless m <= n; sampler: c, c2)
+        main = sum(8 * nb * (j + 2) + (0 if m <= n else 8 * nb * (j + 1)) for j in range(k_eff))
+        samp = sum(8 * mb * ((j + 1) + (j + 2)) for j in range(ks_eff))
         return main + samp
     if name == "sp_apply":      # Rt (float), kv, v, Q'_{0..j} (double)
         return sum(f * m * k_eff + 16 * m + 8 * m * (j + 1) for j in range(ks_eff))
@@ -85,8 +85,13 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
         return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff))
     if name == "sp_finalize":
         return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff - 1))
-    if name == "lz_udots":      # read Q_{0..j}, v ; write r'
-        return sum(f * n * (j + 1) + 2 * f * n for j in range(k_eff))
+    if name == "lz_udots":      # read Q_{0..j} once; v from x and R_j (m <= n) or v; write r',
+        gpath = m <= n          # partial rows
+        return sum(f * n * (j + 1) + (f * n * d + f * m if gpath else f * n) + f * n +
+                   8 * nb * (j + 2) for j in range(k_eff))
+    if name == "lz_cdots":      # read G_{0..j} (m rows) and R_j; partial rows
+        return sum(f * m * (j + 1) + f * m + 8 * min(64, -(-m // 256)) * (j + 1)
+                   for j in range(k_eff))
     if name == "lz_gdots":      # read x, R_j, q_j, Q_{0..j}; write v
         return sum(f * n * d + f * m + f * n * (j + 1) + 2 * f * n for j in range(k_eff))
     if name == "lz_finalize":   # read r', Q_{0..j}; write q_{j+1}
@@ -104,28 +109,43 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
     return None
 
 
-def stored_traffic(scope):
-    """HBM bytes per launch of `scope` from the committed rocprofv3 counter
-    readings (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
-    calibration), or None if absent or if the kernel's source has changed."""
+def _stored_profile():
+    """The committed rocprofv3 readings of the step kernels: per-kernel
+    FETCH_SIZE / WRITE_SIZE per dispatch, the copy calibration, and the kernel
+    with the largest total time in the kernel trace; a kernel's entry counts
+    only while its source file hashes as recorded (the dominant entry only
+    while every recorded source does)."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE) or scope not in SCOPE_SOURCE:
-        return None
+    out = {"scale": {}, "kernels": {}, "dominant": None}
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
     fields = {}
     for line in open(TRAFFIC_FILE):
         parts = line.split()
-        if len(parts) >= 2 and parts[0] in ("scale", "sha256", "kernel"):
+        if len(parts) >= 2 and parts[0] in ("scale", "sha256", "kernel", "dominant"):
             fields.setdefault(parts[0], []).append(parts[1:])
-    src = SCOPE_SOURCE[scope]
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1803_06058_amd", "csrc", src), "rb").read()).hexdigest()
-    if [src, sha] not in fields.get("sha256", []):
-        return None
-    scale = {k: float(v) for k, v in fields.get("scale", [])}
+    same = {}
+    for src, sha in fields.get("sha256", []):
+        path = os.path.join(ROOT, "paper_1803_06058_amd", "csrc", src)
+        same[src] = os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == sha
+    out["scale"] = {k: float(v) for k, v in fields.get("scale", [])}
     for rec in fields.get("kernel", []):
-        if rec[0] == scope:
-            fetch_kib, write_kib = float(rec[1]), float(rec[2])
-            return int(1024 * (fetch_kib * scale["FETCH_SIZE"] + write_kib * scale["WRITE_SIZE"]))
-    return None
+        if same.get(SCOPE_SOURCE.get(rec[0], ""), False):
+            out["kernels"][rec[0]] = (float(rec[1]), float(rec[2]))
+    if fields.get("dominant") and same and all(same.values()):
+        out["dominant"] = fields["dominant"][0][0]
+    return out
+
+
+def stored_traffic(scope):
+    """HBM bytes per launch of `scope` from the committed counter readings
+    (scaled by the copy calibration), or None if absent or stale."""
+    prof = _stored_profile()
+    if scope not in prof["kernels"] or not prof["scale"]:
+        return None
+    fetch_kib, write_kib = prof["kernels"][scope]
+    return int(1024 * (fetch_kib * prof["scale"]["FETCH_SIZE"] +
+                       write_kib * prof["scale"]["WRITE_SIZE"]))
 
 
 def cpu_baseline(P, gpu_mean, gpu_var, nq):
@@ -309,7 +329,13 @@ def main():
     torch.cuda.synchronize()
     warm = B.profile_read(KERNELS)
     B.profile_enable(False)
-    dominant = max(KERNELS, key=lambda k_: warm[k_][1])
+    # the kernel with the largest total time per step: from the committed
+    # kernel trace of this same code when there is one (event pairs add the
+    # dispatch latency to every launch, which would favour kernels launched
+    # often), else from the event timings of the warm-up steps
+    dominant = _stored_profile()["dominant"]
+    if dominant not in KERNELS:
+        dominant = max(KERNELS, key=lambda k_: warm[k_][1])
     # timed region: K steps with timing off give ms_per_step and value (event
     # objects on thousands of launches per step would slow the host down)
     torch.cuda.synchronize()
