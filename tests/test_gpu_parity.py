@@ -370,6 +370,37 @@ def test_batched_mixed_sizes_equal_single():
         c.free()
 
 
+def test_batched_grid_and_row_first_pass_equal_single():
+    """A batch mixing GPs whose first Gram-Schmidt pass runs in grid space
+    (m <= n) with GPs whose pass runs over the data rows (m > n): each GP's
+    cache equals its single build bit for bit, and the m > n GP matches the
+    FP64 oracle."""
+    Pa = WL.config(2, scale=0.02, k_sample=0)                 # n = 2000, m = 200
+    Pb = WL.config(2, scale=0.02, k_sample=0, m=(3000,))      # n = 2000, m = 3000
+    Pc = WL.config(2, scale=0.05, k_sample=0)                 # n = 5000, m = 500
+    Ps = [Pa, Pb, Pc]
+    print([(P.n, P.m[0], P.k) for P in Ps], flush=True)
+    cfgs = [cfg_of(P) for P in Ps]
+    xs = [tdev(P.x, torch.float32) for P in Ps]
+    ys = [tdev(P.y, torch.float32) for P in Ps]
+    caches = B.build_cache_batched(cfgs, xs, ys)
+    qs = [tdev(P.xs, torch.float32) for P in Ps]
+    means, vars_ = B.predict_mean_var_batched(caches, qs)
+    for g, P in enumerate(Ps):
+        single = build(P)
+        m1, v1 = single.predict_mean_var(qs[g])
+        assert torch.equal(v1, vars_[g]) and torch.equal(m1, means[g])
+        assert single.info().k_eff == caches[g].info().k_eff
+        single.free()
+    oc = oracle_cache(Pb)
+    m_ref, v_ref = O.love_predict(oc, Pb.xs)
+    e = errors(host(vars_[1]), v_ref, O.prior_var(Pb.xs, spec_of(Pb)), host(means[1]), m_ref, Pb.y)
+    print(e, flush=True)
+    assert e["e_p_max"] <= 1e-4 and e["mean_err_rel_rms_y"] <= 1e-4
+    for c in caches:
+        c.free()
+
+
 def test_edge_cases():
     P = WL.config(2, scale=0.01, k_sample=0)
     cache = build(P)
