@@ -97,12 +97,27 @@ void prof_end(const char* name, hipStream_t s) {
   if (p.pending.size() > 4096) drain(p);
 }
 
-void* dev_alloc(love_cache* c, size_t bytes) {
+bool dev_reserve(love_cache* c, size_t bytes) {
   void* p = nullptr;
-  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) return false;
+  c->allocs.push_back(p);
+  c->block = (char*)p;
+  c->block_size = bytes;
+  c->block_used = 0;
+  return true;
+}
+
+void* dev_alloc(love_cache* c, size_t bytes) {
+  bytes = dev_round(bytes);
+  c->bytes += bytes;
+  if (c->block && c->block_used + bytes <= c->block_size) {
+    void* p = c->block + c->block_used;
+    c->block_used += bytes;
+    return p;
+  }
+  void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
   c->allocs.push_back(p);
-  c->bytes += bytes;
   return p;
 }
 }  // namespace love
@@ -167,17 +182,35 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->kspad = c->ks > 0 ? kround(c->ks) : 0;
   c->tol_lanczos = c->fp64 ? 1e-12 : 1e-8;
   const size_t es = c->fp64 ? 8 : 4;
+  const bool split = cfg->precision == LOVE_P_FP32_BF16SPLIT;
+  {
+    // everything the cache keeps, in one block: the buffers below, the
+    // Toeplitz coefficient columns and first-four table, the Toeplitz scratch
+    size_t want = dev_round(es * (size_t)n * c->d) + dev_round(es * (size_t)n) +
+                  dev_round(4 * (size_t)n) + dev_round(4 * (size_t)(ct + 1)) +
+                  dev_round(2 * sizeof(Ctl) + 4 * sizeof(unsigned)) + dev_round(sizeof(double)) +
+                  2 * dev_round(sizeof(double) * LOVE_MAX_K) +
+                  dev_round((split ? 2 : es) * (size_t)m * c->kpad) +
+                  (split ? dev_round(2 * (size_t)m * c->kpad) : 0) + dev_round(es * (size_t)m) +
+                  (c->ks > 0 ? dev_round(sizeof(float) * (size_t)m * c->kspad) : 0) +
+                  2 * dev_round(es * (size_t)n) + 2 * dev_round(es * (size_t)m) +
+                  dev_round(sizeof(double) * 16) +
+                  dev_round(sizeof(double) * (size_t)toeplitz_scratch_elems(c));
+    for (int e = 0; e < c->d; ++e)
+      want += dev_round(8 * (size_t)cfg->m[e]) + dev_round(4 * (size_t)cfg->m[e]);
+    if (!dev_reserve(c, want)) return LOVE_ENOMEM;
+  }
   c->x = dev_alloc(c, es * (size_t)n * c->d);
   c->y = dev_alloc(c, es * (size_t)n);
   c->perm = (int32_t*)dev_alloc(c, 4 * (size_t)n);
   c->cell_start = (int32_t*)dev_alloc(c, 4 * (size_t)(ct + 1));
-  c->ctl = (Ctl*)dev_alloc(c, sizeof(Ctl));
-  c->ctl_s = (Ctl*)dev_alloc(c, sizeof(Ctl));
-  c->status = (unsigned*)dev_alloc(c, sizeof(unsigned) * 4);
+  // the two control blocks and the status words are contiguous (one clear)
+  c->ctl = (Ctl*)dev_alloc(c, 2 * sizeof(Ctl) + 4 * sizeof(unsigned));
+  c->ctl_s = c->ctl ? c->ctl + 1 : nullptr;
+  c->status = c->ctl ? (unsigned*)(c->ctl + 2) : nullptr;
   c->ortho = (double*)dev_alloc(c, sizeof(double));
   c->alpha = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
   c->beta = (double*)dev_alloc(c, sizeof(double) * LOVE_MAX_K);
-  const bool split = cfg->precision == LOVE_P_FP32_BF16SPLIT;
   c->rt = dev_alloc(c, (split ? 2 : es) * (size_t)m * c->kpad);
   if (split) c->rt_lo = dev_alloc(c, 2 * (size_t)m * c->kpad);
   c->a = dev_alloc(c, es * (size_t)m);
@@ -191,9 +224,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
       !c->alpha || !c->beta || !c->rt || (split && !c->rt_lo) || !c->a || (c->ks > 0 && !c->S) ||
       !c->v1 || !c->v2 || !c->g1 || !c->g2)
     return LOVE_ENOMEM;
-  LOVE_HIP_TRY(hipMemsetAsync(c->status, 0, sizeof(unsigned) * 4, s));
-  LOVE_HIP_TRY(hipMemsetAsync(c->ctl, 0, sizeof(Ctl), s));
-  LOVE_HIP_TRY(hipMemsetAsync(c->ctl_s, 0, sizeof(Ctl), s));
+  LOVE_HIP_TRY(hipMemsetAsync(c->ctl, 0, 2 * sizeof(Ctl) + 4 * sizeof(unsigned), s));
   LOVE_HIP_TRY(hipMemsetAsync(c->a, 0, es * (size_t)m, s));
   return LOVE_OK;
 }
@@ -217,6 +248,25 @@ static love_status finish_status(love_cache* c) {
   if (all & SF_NONFINITE) return LOVE_ENONFINITE;
   if (h.k_eff < 1) return LOVE_ENOTPD;
   return LOVE_OK;
+}
+
+// Once per device: the stream-ordered allocator keeps freed memory in its pool
+// instead of returning it to the driver at every synchronisation, so the
+// per-build scratch (hipMallocAsync / hipFreeAsync) is reused without driver
+// calls.
+static void device_setup() {
+  static std::mutex mu;
+  static std::map<int, bool> done;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  if (done[dev]) return;
+  done[dev] = true;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
 }
 
 // One non-blocking side stream per device for the sampler chain (default priority).
@@ -340,6 +390,7 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
       return LOVE_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
+  device_setup();
   std::vector<love_cache*> made;
   auto fail = [&](love_status st) {
     for (auto* p : made) destroy(p);

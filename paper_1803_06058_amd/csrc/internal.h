@@ -115,12 +115,20 @@ struct love_cache {
   void* tscr = nullptr;       // toeplitz_scratch_elems doubles: scratch of apply_khat / apply_kuu
   size_t bytes = 0;
   std::vector<void*> allocs;
+  // one device block for the cache's buffers, handed out in order (dev_alloc)
+  char* block = nullptr;
+  size_t block_size = 0, block_used = 0;
 };
 
 namespace love {
 
-// allocation helper (tracks bytes); returns nullptr on failure
+// allocation helper (tracks bytes): the next 256-byte aligned piece of the
+// cache's device block, or a separate hipMalloc once the block is used up;
+// returns nullptr on failure
 void* dev_alloc(love_cache* c, size_t bytes);
+// reserve the cache's device block (call before the first dev_alloc)
+bool dev_reserve(love_cache* c, size_t bytes);
+inline size_t dev_round(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~size_t(255); }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -441,11 +441,53 @@ static double kern1d(int kind, double r, double ell) {
 love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<double>& col);
 int autotune_choose(love_cache* c, int e);
 
+// The same columns evaluated on the device (no host-to-device copies in the
+// build): c64 in double, c32 rounded from it, and c4 = the first four
+// entries of every axis (1 for axes past d).
+struct CoefAxis {
+  double* c64;
+  float* c32;
+  int L;
+  double h, ell, scale;
+};
+struct CoefJob {
+  CoefAxis ax[MAXD];
+  int d, kind;
+  double* c4;
+};
+__device__ inline double kern1d_dev(int kind, double r, double ell) {
+  r = fabs(r);
+  if (kind == LOVE_MATERN52) {
+    const double z = sqrt(5.0) * r / ell;
+    return (1.0 + z + z * z / 3.0) * exp(-z);
+  }
+  const double q = r / ell;
+  return exp(-0.5 * q * q);
+}
+__global__ void k_toep_coef(CoefJob J) {
+  const int e = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= J.d) {
+    if (i < 4) J.c4[4 * e + i] = 1.0;
+    return;
+  }
+  const CoefAxis& A = J.ax[e];
+  if (i >= A.L) return;
+  const double v = kern1d_dev(J.kind, i * A.h, A.ell) * A.scale;
+  A.c64[i] = v;
+  A.c32[i] = (float)v;
+  if (i < 4) J.c4[4 * e + i] = v;
+}
+
 love_status toeplitz_plan(love_cache* c) {
   toeplitz_set_attrs();
   ToepPlan& p = c->toep;
   p.d = c->d;
   p.mtot = c->m;
+  CoefJob cj{};
+  cj.d = c->d;
+  cj.kind = c->cfg.kernel;
+  int maxL = 4;
   int64_t inner = 1;
   for (int e = c->d - 1; e >= 0; --e) {
     ToepAxis& ax = p.ax[e];
@@ -458,12 +500,12 @@ love_status toeplitz_plan(love_cache* c) {
     for (int i = 0; i < ax.L; ++i)
       col[i] = kern1d(c->cfg.kernel, i * h, c->cfg.lengthscale[e]) * (e == 0 ? c->cfg.outputscale : 1.0);
     for (int i = 0; i < 4; ++i) c->c4[e][i] = col[i];
-    std::vector<float> col32(col.begin(), col.end());
     ax.c64 = dev_alloc(c, sizeof(double) * ax.L);
     ax.c32 = dev_alloc(c, sizeof(float) * ax.L);
     if (!ax.c64 || !ax.c32) return LOVE_ENOMEM;
-    LOVE_HIP_TRY(hipMemcpy(ax.c64, col.data(), sizeof(double) * ax.L, hipMemcpyHostToDevice));
-    LOVE_HIP_TRY(hipMemcpy(ax.c32, col32.data(), sizeof(float) * ax.L, hipMemcpyHostToDevice));
+    cj.ax[e] = CoefAxis{(double*)ax.c64, (float*)ax.c32, ax.L, h, c->cfg.lengthscale[e],
+                        e == 0 ? c->cfg.outputscale : 1.0};
+    maxL = std::max(maxL, ax.L);
     int mode = c->cfg.toeplitz;
     if (mode == LOVE_TOEPLITZ_AUTO) mode = autotune_choose(c, e);
     ax.mode = mode;
@@ -494,7 +536,9 @@ love_status toeplitz_plan(love_cache* c) {
       for (int i = 0; i < 4; ++i) c->c4[e][i] = 1.0;
   c->c4_dev = (double*)dev_alloc(c, sizeof(double) * 16);
   if (!c->c4_dev) return LOVE_ENOMEM;
-  LOVE_HIP_TRY(hipMemcpy(c->c4_dev, c->c4, sizeof(double) * 16, hipMemcpyHostToDevice));
+  cj.c4 = c->c4_dev;
+  k_toep_coef<<<dim3((unsigned)cdiv(maxL, 256), MAXD), 256, 0, c->stream>>>(cj);
+  LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }
 
