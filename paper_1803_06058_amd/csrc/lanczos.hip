@@ -662,58 +662,96 @@ template <typename T>
 __global__ void k_tri_chol(Tab tab, const LzJob<T>* __restrict__ jobs, double rel_tol) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  if (threadIdx.x != 0) return;
   const LzJob<T>& J = jobs[gp];
   Ctl* ctl = J.ctl;
-  const double* alpha = J.alpha;
-  const double* beta = J.beta;
+  // alpha, beta staged in LDS by the whole block; the recurrence (one thread)
+  // then reads and writes LDS only, and the factors go out in parallel
+  __shared__ double a[MAXK], b[MAXK], ld[MAXK], ls[MAXK];
+  __shared__ int s_keep;
   const int k = ctl->k_eff;
-  double amax = 0.0;
-  for (int i = 0; i < k; ++i) amax = fmax(amax, fabs(alpha[i]));
-  int keep = k;
-  double prev = 0.0;
-  for (int i = 0; i < k; ++i) {
-    const double piv = alpha[i] - prev * prev;
-    if (!(piv > rel_tol * amax) || !isfinite(piv)) {
-      keep = i;
-      ctl->status |= SF_NOTPD;
-      break;
-    }
-    const double l = sqrt(piv);
-    J.ldiag[i] = l;
-    prev = (i + 1 < k) ? beta[i] / l : 0.0;
-    J.lsub[i] = prev;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    a[i] = J.alpha[i];
+    b[i] = J.beta[i];
   }
-  ctl->k_eff = keep;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double amax = 0.0;
+    for (int i = 0; i < k; ++i) amax = fmax(amax, fabs(a[i]));
+    int keep = k;
+    double prev = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double piv = a[i] - prev * prev;
+      if (!(piv > rel_tol * amax) || !isfinite(piv)) {
+        keep = i;
+        ctl->status |= SF_NOTPD;
+        break;
+      }
+      const double l = sqrt(piv);
+      ld[i] = l;
+      prev = (i + 1 < k) ? b[i] / l : 0.0;
+      ls[i] = prev;
+    }
+    s_keep = keep;
+    ctl->k_eff = keep;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < s_keep; i += blockDim.x) {
+    J.ldiag[i] = ld[i];
+    J.lsub[i] = ls[i];
+  }
 }
 
 // Rt[u, :] = (L^{-1} R[:, u])^T : bidiagonal forward substitution per grid node.
 // split = 1 stores bf16 hi = rne(z), lo = rne(z - hi).
+// Rt[u, :] = (L^{-1} R[:, u])^T.  One wave per 64 grid rows, lane = row: the
+// forward substitution runs down the k columns (loads of R coalesced over the
+// rows), the rows are staged in LDS and leave as one contiguous 64 x kpad slab
+// (coalesced stores), in the cache precision or as bf16 hi + bf16 lo.
+constexpr int RT_ROWS = WAVE;
 template <typename T>
-__global__ void k_rtilde(Tab tab, const RtJob<T>* __restrict__ jobs) {
+__global__ __launch_bounds__(RT_ROWS) void k_rtilde(Tab tab, const RtJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const RtJob<T>& J = jobs[gp];
-  const int64_t u = (int64_t)lb * blockDim.x + threadIdx.x;
-  const int64_t m = J.m;
-  if (u >= m) return;
+  constexpr int TS = MAXK + 1;   // tile row stride (odd: rows fall on different banks)
+  __shared__ T tile[RT_ROWS * TS];
+  __shared__ double ld[MAXK], ls[MAXK];
   const int k = J.ctl->k_eff, kpad = J.kpad;
+  const int64_t m = J.m;
+  const int t = threadIdx.x;
+  for (int i = t; i < k; i += RT_ROWS) {
+    ld[i] = J.ldiag[i];
+    ls[i] = J.lsub[i];
+  }
+  __syncthreads();
+  const int64_t u0 = (int64_t)lb * RT_ROWS, u = u0 + t;
   double z = 0.0;
+  // unrolled so that the loads of R for several columns are in flight while
+  // the substitution (one divide per column) runs
+#pragma unroll 8
   for (int i = 0; i < kpad; ++i) {
     double val = 0.0;
-    if (i < k) {
+    if (i < k && u < m) {
       const double rv = (double)J.R[(int64_t)i * m + u];
-      z = (rv - (i > 0 ? J.lsub[i - 1] * z : 0.0)) / J.ldiag[i];
+      z = (rv - (i > 0 ? ls[i - 1] * z : 0.0)) / ld[i];
       val = z;
     }
+    tile[t * TS + i] = (T)val;
+  }
+  __syncthreads();
+  const int rows = (int)min<int64_t>(RT_ROWS, m - u0);
+  for (int q = t; q < rows * kpad; q += RT_ROWS) {
+    const int r = q / kpad, i = q - r * kpad;
+    const T val = tile[r * TS + i];
+    const int64_t idx = (u0 + r) * kpad + i;
     if (J.split) {
       const float f = (float)val;
       const uint16_t hi = f32_to_bf16_rne(f);
       const uint16_t lo = f32_to_bf16_rne(f - bf16_to_f32(hi));
-      ((uint16_t*)J.rt)[u * kpad + i] = hi;
-      J.rt_lo[u * kpad + i] = lo;
+      ((uint16_t*)J.rt)[idx] = hi;
+      J.rt_lo[idx] = lo;
     } else {
-      ((T*)J.rt)[u * kpad + i] = (T)val;
+      ((T*)J.rt)[idx] = val;
     }
   }
 }
@@ -1409,8 +1447,10 @@ __global__ __launch_bounds__(MAXK) void k_eig_vectors(const double* __restrict__
       const double big = fmax(fabs(lm), fabs(ln));
       if (big > 1e-9 * tn && (ln - lm) < 1e-6 * big) bad = 1;
     }
-    double* dp = dscr;
-    double* dm = dscr + MAXK * MAXK;
+    // the two pivot tables do not overlap each other or vout: restrict lets
+    // the loads of one iteration be issued ahead of the previous stores
+    double* __restrict__ dp = dscr;
+    double* __restrict__ dm = dscr + MAXK * MAXK;
     // forward pivots D+
     double q = a[0] - lm;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -1426,6 +1466,7 @@ __global__ __launch_bounds__(MAXK) void k_eig_vectors(const double* __restrict__
     dm[(k - 1) * MAXK + e] = q;
     int r = k - 1;
     double gbest = fabs(dp[(k - 1) * MAXK + e] + q - (a[k - 1] - lm));
+#pragma unroll 8
     for (int i = k - 2; i >= 0; --i) {
       q = (a[i] - lm) - b[i] * b[i] / q;
       if (fabs(q) < pivmin) q = -pivmin;
@@ -1438,15 +1479,17 @@ __global__ __launch_bounds__(MAXK) void k_eig_vectors(const double* __restrict__
     }
     // z_r = 1, recurrences outward; column c = k-1-e of vout (decreasing order)
     const int c = k - 1 - e;
-    double* col = vout + (size_t)c * MAXK;
+    double* __restrict__ col = vout + (size_t)c * MAXK;
     double z = 1.0, nrm = 1.0;
     col[r] = 1.0;
+#pragma unroll 8
     for (int i = r - 1; i >= 0; --i) {
       z = -(b[i] / dp[i * MAXK + e]) * z;
       col[i] = z;
       nrm += z * z;
     }
     z = 1.0;
+#pragma unroll 8
     for (int i = r; i + 1 < k; ++i) {
       z = -(b[i] / dm[(i + 1) * MAXK + e]) * z;
       col[i + 1] = z;
@@ -2123,7 +2166,12 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
   k_tri_chol<T><<<tab_blocks(t_one), 64, 0, s>>>(t_one, dlz, 0.0);
-  tlaunch("rtilde", k_rtilde<T>, tab_blocks(t_m), 256, 0, s, t_m, A.at<RtJob<T>>(o_rj));
+  {
+    std::vector<int64_t> b_rt(G);
+    for (int g = 0; g < G; ++g) b_rt[g] = cdiv(cs[g]->m, RT_ROWS);
+    const Tab t_rt = make_tab(b_rt);
+    tlaunch("rtilde", k_rtilde<T>, tab_blocks(t_rt), RT_ROWS, 0, s, t_rt, A.at<RtJob<T>>(o_rj));
+  }
   // The samplers (grid space, need Rt) and the mean solve (needs Q) are
   // independent chains of small kernels: the samplers run on a side stream
   // concurrently with the mean CG, and the caller's stream waits for them.
