@@ -85,23 +85,57 @@ struct PredJob {
   unsigned* status;
 };
 
-// One wave per point p (points 4 lb .. 4 lb + 3 of the block).
-template <typename T, int D, int SPLIT>
+// Each query point is served by PLQ = 16 lanes, four points per wave and
+// sixteen per block: lane sub of a point holds the CPL = kpad / 16 consecutive
+// columns sub CPL .. sub CPL + CPL - 1 of every stencil row of Rt (one or two
+// 16-byte loads per row), so a wave keeps four points' gathers in flight
+// instead of one.  u = Rt^T w accumulates per column over the stencil rows in
+// row order; ||u||^2 and the mean are then summed over the 16 lanes.
+constexpr int PLQ = 16;
+constexpr int PPB = 256 / PLQ;   // points per block
+
+template <typename T, int SPLIT, int CPL>
+__device__ __forceinline__ void rt_row(const void* rt, const uint16_t* rt_lo, int64_t idx,
+                                       double (&v)[CPL]) {
+  if constexpr (!SPLIT && sizeof(T) == 4) {
+#pragma unroll
+    for (int q = 0; q < CPL; q += 4) {
+      const float4 f = *reinterpret_cast<const float4*>((const float*)rt + idx + q);
+      v[q] = f.x;
+      v[q + 1] = f.y;
+      v[q + 2] = f.z;
+      v[q + 3] = f.w;
+    }
+  } else if constexpr (!SPLIT) {
+#pragma unroll
+    for (int q = 0; q < CPL; q += 2) {
+      const double2 f = *reinterpret_cast<const double2*>((const double*)rt + idx + q);
+      v[q] = f.x;
+      v[q + 1] = f.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) v[q] = rt_load<T, SPLIT>(rt, rt_lo, idx + q);
+  }
+}
+
+template <typename T, int D, int SPLIT, int CPL>
 __device__ inline void predict_body(const PredJob<T>& J, int64_t lb) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t p = lb * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (p >= J.t) return;
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int64_t p = lb * PPB + threadIdx.x / PLQ;
+  const bool live = p < J.t;
+  const int64_t pc = live ? p : J.t - 1;   // spare lanes redo the last point, write nothing
   const GridT<T>& g = J.g;
   const int kpad = J.kpad;
-  const void* rt = J.rt;
-  const uint16_t* rt_lo = J.rt_lo;
   const T* acache = J.a;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, J.xs + p * D, w, dw, base, false);
+  const bool ok = point_stencil<T, D>(g, J.xs + pc * D, w, dw, base, false);
   constexpr int NA = 1 << (2 * D);
-  double u0 = 0.0, u1 = 0.0, mu = 0.0;
-  const bool two = kpad > WAVE;
+  double u[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) u[q] = 0.0;
+  double mu = 0.0;
 #pragma unroll 4
   for (int a = 0; a < NA; ++a) {
     double wa = 1.0;
@@ -112,14 +146,18 @@ __device__ inline void predict_body(const PredJob<T>& J, int64_t lb) {
       wa *= w[e][o];
       node += (int64_t)o * g.nstride[e];
     }
-    const int64_t row = node * kpad;
-    u0 += wa * rt_load<T, SPLIT>(rt, rt_lo, row + lane);
-    if (two) u1 += wa * rt_load<T, SPLIT>(rt, rt_lo, row + lane + WAVE);
-    if ((a & (WAVE - 1)) == lane && acache) mu += wa * (double)acache[node];
+    double r[CPL];
+    rt_row<T, SPLIT, CPL>(J.rt, J.rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) u[q] += wa * r[q];
+    if ((a & (PLQ - 1)) == sub && acache) mu += wa * (double)acache[node];
   }
-  const double uu = wave_sum(u0 * u0 + u1 * u1);
-  mu = wave_sum(mu);
-  if (lane == 0) {
+  double uu = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) uu += u[q] * u[q];
+  uu = group_sum(uu, PLQ);
+  mu = group_sum(mu, PLQ);
+  if (sub == 0 && live) {
     double pr = 1.0;
 #pragma unroll
     for (int e = 0; e < D; ++e) pr *= quad4(J.c4 + 4 * e, w[e], w[e]);
@@ -136,14 +174,17 @@ __device__ inline void predict_body(const PredJob<T>& J, int64_t lb) {
 
 template <typename T, int D, int SPLIT>
 __global__ __launch_bounds__(256) void k_predict(PredJob<T> J) {
-  predict_body<T, D, SPLIT>(J, blockIdx.x);
+  if (J.kpad > 64) predict_body<T, D, SPLIT, 8>(J, blockIdx.x);
+  else predict_body<T, D, SPLIT, 4>(J, blockIdx.x);
 }
 
 template <typename T, int D, int SPLIT>
 __global__ __launch_bounds__(256) void k_predict_b(Tab tab, const PredJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  predict_body<T, D, SPLIT>(jobs[gp], lb);
+  const PredJob<T>& J = jobs[gp];
+  if (J.kpad > 64) predict_body<T, D, SPLIT, 8>(J, lb);
+  else predict_body<T, D, SPLIT, 4>(J, lb);
 }
 
 template <typename T>
@@ -175,7 +216,7 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
   if (G == 1) {
     if (ts[0] == 0) return LOVE_OK;
     const PredJob<T> J = pred_job<T>(cs[0], xs[0], ts[0], means[0], vars[0]);
-    const unsigned nb = (unsigned)cdiv(ts[0], 4);
+    const unsigned nb = (unsigned)cdiv(ts[0], PPB);
 #define LAUNCH_P(D)                                                   \
   if (split) tlaunch("predict", k_predict<T, D, 1>, nb, 256, 0, s, J); \
   else tlaunch("predict", k_predict<T, D, 0>, nb, 256, 0, s, J);
@@ -194,7 +235,7 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
     std::vector<int64_t> blocks;
     for (int g = g0; g < g1; ++g) {
       jobs.push_back(pred_job<T>(cs[g], xs[g], ts[g], means[g], vars[g]));
-      blocks.push_back(cdiv(ts[g], 4));
+      blocks.push_back(cdiv(ts[g], PPB));
     }
     const Tab tab = make_tab(blocks);
     if (!tab_blocks(tab)) continue;
