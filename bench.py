@@ -41,11 +41,12 @@ SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": 
                 "sp_band_rt": "lanczos.hip", "sp_reduce_sum": "lanczos.hip", "rtilde": "lanczos.hip",
                 "scatter": "mvm.hip", "gather": "mvm.hip", "toep_band": "mvm.hip",
                 "toep_reduce": "mvm.hip", "toep_band64": "mvm.hip", "toep_reduce64": "mvm.hip",
-                "predict": "query.hip", "sample": "query.hip", "setup_sort": "sort.hip"}
+                "predict": "query.hip", "sample": "query.hip", "sample_f": "query.hip", "setup_sort": "sort.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_pmc_traffic.txt")
 METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; MVM HBM GB/s"
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
 KERNELS = ["lz_udots", "lz_gdots", "lz_cdots", "lz_finalize", "scatter", "gather", "predict", "sample",
+           "sample_f",
            "rtilde", "setup_sort", "colsum", "sp_apply", "rt_dots", "sp_udots", "sp_finalize",
            "toep_band", "toep_reduce", "toep_band64", "toep_reduce64", "sp_band_rt",
            "sp_reduce_sum"]

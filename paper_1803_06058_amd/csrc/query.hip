@@ -483,70 +483,102 @@ template love_status backward<double>(const love_cache*, const double*, int64_t,
 
 // ----------------------------------------------------------------------------
 // Posterior samples: out[i, j] = mu_i + f_i . z_j with f_i = S^T w(x*_i)
-// (eq. sample, S from eq. pred_covar_ski_interp_form).  A block owns 64 test
-// points: it forms F (64 x ks) and mu in LDS, then multiplies F by Z in
-// 64-sample tiles (4 x 4 outputs per thread).
+// (eq. sample, S from eq. pred_covar_ski_interp_form), in two launches:
+//   k_sample_f   F = W_{X*} S (t x kspad, float) and mu, 16 lanes per point as
+//                for the predictive variances (lane sub: columns sub CPL ..);
+//   k_sample_mm  out = mu 1^T + F Z over 64-point x 64-sample tiles, F and Z
+//                tiles in LDS, 4 x 4 outputs per thread; the number of
+//                factor columns (k_chol) is read on the device.
 // ----------------------------------------------------------------------------
-constexpr int SP_TP = 64;
-
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_sample(GridT<T> g, const T* __restrict__ xs, int64_t t,
-                                                const float* __restrict__ S, int kspad, int ks,
-                                                const T* __restrict__ acache,
-                                                const float* __restrict__ z, int64_t ns,
-                                                T* __restrict__ out, unsigned* __restrict__ status) {
-  extern __shared__ unsigned char smem_raw[];
-  float* F = (float*)smem_raw;               // SP_TP x (ks + 1)
-  float* Zt = F + SP_TP * (ks + 1);          // ks x 64
-  __shared__ float mu_l[SP_TP];
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  const int64_t p0 = (int64_t)blockIdx.x * SP_TP;
-  const int ldf = ks + 1;
-  // F rows and mu: wave w handles points w, w+4, ...
-  for (int pl = w; pl < SP_TP; pl += 4) {
-    const int64_t p = p0 + pl;
-    double f0 = 0.0, f1 = 0.0, mu = 0.0;
-    bool ok = true;
-    if (p < t) {
-      double ww[D][4], dd[D][4];
-      int64_t base;
-      ok = point_stencil<T, D>(g, xs + p * D, ww, dd, base, false);
-      constexpr int NA = 1 << (2 * D);
-      for (int a = 0; a < NA; ++a) {
-        double wa = 1.0;
-        int64_t node = base;
+template <typename T, int D, int CPL>
+__device__ inline void sample_f_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
+                                     const float* __restrict__ S, int kspad,
+                                     const T* __restrict__ acache, float* __restrict__ F,
+                                     float* __restrict__ mu_out, unsigned* __restrict__ status,
+                                     int64_t lb) {
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int64_t p = lb * PPB + threadIdx.x / PLQ;
+  const bool live = p < t;
+  const int64_t pc = live ? p : t - 1;
+  double w[D][4], dw[D][4];
+  int64_t base;
+  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, false);
+  constexpr int NA = 1 << (2 * D);
+  double f[CPL];
 #pragma unroll
-        for (int e = 0; e < D; ++e) {
-          const int o = (a >> (2 * (D - 1 - e))) & 3;
-          wa *= ww[e][o];
-          node += (int64_t)o * g.nstride[e];
-        }
-        if (lane < ks) f0 += wa * (double)S[node * kspad + lane];
-        if (lane + WAVE < ks) f1 += wa * (double)S[node * kspad + lane + WAVE];
-        if ((a & (WAVE - 1)) == lane && acache) mu += wa * (double)acache[node];
-      }
-      mu = wave_sum(mu);
-      if (!ok && lane == 0) atomicOr(status, SF_DOMAIN);
+  for (int q = 0; q < CPL; ++q) f[q] = 0.0;
+  double mu = 0.0;
+#pragma unroll 4
+  for (int a = 0; a < NA; ++a) {
+    double wa = 1.0;
+    int64_t node = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int o = (a >> (2 * (D - 1 - e))) & 3;
+      wa *= w[e][o];
+      node += (int64_t)o * g.nstride[e];
     }
-    if (lane < ks) F[pl * ldf + lane] = (float)f0;
-    if (lane + WAVE < ks) F[pl * ldf + lane + WAVE] = (float)f1;
-    if (lane == 0) mu_l[pl] = ok ? (float)mu : NAN;
+    double r[CPL];
+    rt_row<float, 0, CPL>(S, nullptr, node * kspad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) f[q] += wa * r[q];
+    if ((a & (PLQ - 1)) == sub && acache) mu += wa * (double)acache[node];
   }
+  mu = group_sum(mu, PLQ);
+  if (!live) return;
+#pragma unroll
+  for (int q = 0; q < CPL; q += 4)
+    *reinterpret_cast<float4*>(F + p * kspad + sub * CPL + q) =
+        make_float4((float)f[q], (float)f[q + 1], (float)f[q + 2], (float)f[q + 3]);
+  if (sub == 0) {
+    mu_out[p] = ok ? (float)mu : NAN;
+    if (!ok) atomicOr(status, SF_DOMAIN);
+  }
+}
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_sample_f(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                  const float* __restrict__ S, int kspad,
+                                                  const T* __restrict__ acache,
+                                                  float* __restrict__ F, float* __restrict__ mu,
+                                                  unsigned* __restrict__ status) {
+  if (kspad > 64) sample_f_body<T, D, 128 / PLQ>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
+  else sample_f_body<T, D, 64 / PLQ>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
+}
+
+constexpr int SM_T = 64;   // points per output tile
+constexpr int SM_J = 64;   // samples per output tile
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
+                                                   const float* __restrict__ mu, int kspad,
+                                                   const Ctl* ctl, const float* __restrict__ z,
+                                                   int64_t ns, int64_t t, int64_t njt,
+                                                   T* __restrict__ out) {
+  __shared__ float Fl[SM_T][MAXK + 1];
+  __shared__ float Zl[MAXK][SM_J];
+  __shared__ float ml[SM_T];
+  const int ks = ctl->k_chol;
+  const int64_t p0 = (int64_t)blockIdx.x * SM_T;
+  for (int idx = threadIdx.x; idx < SM_T * ks; idx += blockDim.x) {
+    const int r = idx / ks, c = idx - r * ks;
+    Fl[r][c] = p0 + r < t ? F[(p0 + r) * kspad + c] : 0.0f;
+  }
+  if (threadIdx.x < SM_T) ml[threadIdx.x] = p0 + threadIdx.x < t ? mu[p0 + threadIdx.x] : 0.0f;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int64_t j0 = 0; j0 < ns; j0 += 64) {
+  for (int64_t jt = blockIdx.y; jt < njt; jt += gridDim.y) {
+    const int64_t j0 = jt * SM_J;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < ks * 64; idx += 256) {
-      const int cc = idx / 64, jj = idx % 64;
-      Zt[idx] = (j0 + jj < ns) ? z[(int64_t)cc * ns + j0 + jj] : 0.0f;
+    for (int idx = threadIdx.x; idx < ks * SM_J; idx += blockDim.x) {
+      const int c = idx / SM_J, jj = idx - c * SM_J;
+      Zl[c][jj] = j0 + jj < ns ? z[(int64_t)c * ns + j0 + jj] : 0.0f;
     }
     __syncthreads();
     float acc[4][4] = {};
     for (int cc = 0; cc < ks; ++cc) {
       float fa[4], zb[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) fa[r] = F[(ty + 16 * r) * ldf + cc];
+      for (int r = 0; r < 4; ++r) fa[r] = Fl[ty + 16 * r][cc];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) zb[q] = Zt[cc * 64 + tx + 16 * q];
+      for (int q = 0; q < 4; ++q) zb[q] = Zl[cc][tx + 16 * q];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -556,11 +588,11 @@ __global__ __launch_bounds__(256) void k_sample(GridT<T> g, const T* __restrict_
     for (int r = 0; r < 4; ++r) {
       const int64_t p = p0 + ty + 16 * r;
       if (p >= t) continue;
-      const float mu = mu_l[ty + 16 * r];
+      const float m0 = ml[ty + 16 * r];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t j = j0 + tx + 16 * q;
-        if (j < ns) out[p * ns + j] = (T)(mu + acc[r][q]);
+        if (j < ns) out[p * ns + j] = (T)(m0 + acc[r][q]);
       }
     }
   }
@@ -570,20 +602,24 @@ template <typename T>
 love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns, T* out,
                    hipStream_t s) {
   if (t == 0 || ns == 0) return LOVE_OK;
-  Ctl h;
-  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl_s, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  LOVE_HIP_TRY(hipStreamSynchronize(s));
-  const int ks = h.k_chol;
   GridT<T> g = make_grid<T>(c);
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
-  const size_t shm = sizeof(float) * ((size_t)SP_TP * (ks + 1) + (size_t)ks * 64 + 64);
-  dim3 grid((unsigned)cdiv(t, SP_TP));
+  const int kspad = c->kspad;
+  float* F = nullptr;
+  LOVE_HIP_TRY(hipMallocAsync((void**)&F, sizeof(float) * (size_t)t * (kspad + 1), s));
+  float* mu = F + (size_t)t * kspad;
+  const unsigned nbf = (unsigned)cdiv(t, PPB);
   switch (c->d) {
-    case 1: tlaunch("sample", k_sample<T, 1>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 2: tlaunch("sample", k_sample<T, 2>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 3: tlaunch("sample", k_sample<T, 3>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
-    case 4: tlaunch("sample", k_sample<T, 4>, grid, 256, shm, s, g, xs, t, (const float*)c->S, c->kspad, ks, a, z, ns, out, c->status); break;
+    case 1: tlaunch("sample_f", k_sample_f<T, 1>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
+    case 2: tlaunch("sample_f", k_sample_f<T, 2>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
+    case 3: tlaunch("sample_f", k_sample_f<T, 3>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
+    case 4: tlaunch("sample_f", k_sample_f<T, 4>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
   }
+  const int64_t njt = cdiv(ns, SM_J);
+  dim3 grid((unsigned)cdiv(t, SM_T), (unsigned)std::min<int64_t>(njt, 65535));
+  tlaunch("sample", k_sample_mm<T>, grid, 256, 0, s, (const float*)F, (const float*)mu, kspad,
+          (const Ctl*)c->ctl_s, z, ns, t, njt, out);
+  LOVE_HIP_TRY(hipFreeAsync(F, s));
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 template love_status sample<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
