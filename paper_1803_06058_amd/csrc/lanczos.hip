@@ -1172,6 +1172,7 @@ __device__ __forceinline__ void rt_dots_block(int b, int64_t m, const double* __
   const int64_t r0 = (int64_t)b * RBK;
   const int64_t r1 = min<int64_t>(r0 + RBK, m);
   double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
   for (int64_t u = r0 + w; u < r1; u += RBLK / WAVE) {
     const double vu = v[u];
     if (lane < keff) a0 += vu * rt_val<TR, SPLIT>(rt, rt_lo, u * kpad + lane);

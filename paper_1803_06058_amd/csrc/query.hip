@@ -558,21 +558,44 @@ __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
   __shared__ float ml[SM_T];
   const int ks = ctl->k_chol;
   const int64_t p0 = (int64_t)blockIdx.x * SM_T;
-  for (int idx = threadIdx.x; idx < SM_T * ks; idx += blockDim.x) {
-    const int r = idx / ks, c = idx - r * ks;
-    Fl[r][c] = p0 + r < t ? F[(p0 + r) * kspad + c] : 0.0f;
+  // tile loads: a fixed number per thread, all issued before any LDS store
+  // (a loop with a run-time trip count waits for each load in turn)
+  constexpr int NLD = SM_T * MAXK / 256;
+  static_assert(SM_J * MAXK / 256 == NLD, "both tiles hold the same number of elements");
+  {
+    float v[NLD];
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx / MAXK, c = idx % MAXK;
+      v[q] = (c < ks && p0 + r < t) ? F[(p0 + r) * kspad + c] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      Fl[idx / MAXK][idx % MAXK] = v[q];
+    }
   }
   if (threadIdx.x < SM_T) ml[threadIdx.x] = p0 + threadIdx.x < t ? mu[p0 + threadIdx.x] : 0.0f;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   for (int64_t jt = blockIdx.y; jt < njt; jt += gridDim.y) {
     const int64_t j0 = jt * SM_J;
     __syncthreads();
-    for (int idx = threadIdx.x; idx < ks * SM_J; idx += blockDim.x) {
-      const int c = idx / SM_J, jj = idx - c * SM_J;
-      Zl[c][jj] = j0 + jj < ns ? z[(int64_t)c * ns + j0 + jj] : 0.0f;
+    {
+      float v[NLD];
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) {
+        const int idx = threadIdx.x + 256 * q, c = idx / SM_J, jj = idx % SM_J;
+        v[q] = (c < ks && j0 + jj < ns) ? z[(int64_t)c * ns + j0 + jj] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) {
+        const int idx = threadIdx.x + 256 * q;
+        Zl[idx / SM_J][idx % SM_J] = v[q];
+      }
     }
     __syncthreads();
     float acc[4][4] = {};
+#pragma unroll 4
     for (int cc = 0; cc < ks; ++cc) {
       float fa[4], zb[4];
 #pragma unroll

@@ -53,7 +53,9 @@ __device__ __forceinline__ void toep_band_block(const ToepJob<T>& J, int lb, int
     // cd[q] = c[|delta|] for delta = dmin + q, dmin = i0 - (jw + nwin - 1)
     const int dmin = i0 - (jw + nwin - 1);
     const int ncd = nwin + TB_OUT - 1;
+#pragma unroll 4
     for (int q = threadIdx.x; q < nwin; q += TB_WAVES * WAVE) gl[q] = g[jw + q];
+#pragma unroll 5
     for (int q = threadIdx.x; q < ncd; q += TB_WAVES * WAVE) {
       const int dl = dmin + q;
       const int ad = dl < 0 ? -dl : dl;
