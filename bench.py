@@ -18,7 +18,8 @@ pass of K steps each of its launches carries a HIP event pair that takes the
 kernel's own start and end timestamps on its launch stream
 (hipExtLaunchKernel), which gives its average duration;
 `cpu_baseline` is the FP64 oracle on this host's cores.  `batched` compares
-a lock-step batched build of 64 GPs with 64 single builds.
+a lock-step batched build of 64 GPs with 64 single builds; `forms` times the
+bf16-split 2-D and the differentiable 4-D workloads at full size.
 """
 import argparse
 import json
@@ -61,6 +62,8 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=20000)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-GP batched-build measurement")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the bf16-split (2-D) and differentiable (4-D) timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 256 MiB device-to-device copies (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -274,6 +277,59 @@ def batched_section(B, WL, torch, dev):
             "k_eff_equal": kb == ks}
 
 
+def forms_section(B, WL, torch, dev, reps=3):
+    """The other forms of the path at their full sizes, timed on this GPU (median
+    of `reps` after one warm-up, host clock around synchronised calls):
+    bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances) and
+    differentiable (4-D product Matern-5/2, n = 2e5, m = 20^4, k = 64, forward
+    and backward at 262,144 points)."""
+    import statistics
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            if hasattr(r, "free"):
+                r.free()
+        return statistics.median(ts)
+
+    for name, idx in (("bf16split_2d", 3), ("differentiable_4d", 4)):
+        P = WL.config(idx)
+        cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
+                              lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
+                              precision=P.precision)
+        x = torch.from_numpy(P.x).to(dev)
+        y = torch.from_numpy(P.y).to(dev)
+        xs = torch.from_numpy(P.xs).to(dev)
+        t_build = timed(lambda: B.build_cache(cfg, x, y))
+        c = B.build_cache(cfg, x, y)
+        mu = torch.empty(P.t, device=dev, dtype=x.dtype)
+        var = torch.empty(P.t, device=dev, dtype=x.dtype)
+        t_fwd = timed(lambda: c.predict_mean_var(xs, out=(mu, var)))
+        rec = {"n": P.n, "m": int(math.prod(P.m)), "d": P.d, "k": P.k, "t": P.t,
+               "precision": P.precision, "build_ms": round(t_build * 1e3, 3),
+               "predict_ms": round(t_fwd * 1e3, 4),
+               "variances_per_s": round(P.t / t_fwd, 1)}
+        inf = c.info()
+        rec.update({"k_eff": inf.k_eff, "cg_iters": inf.cg_iters,
+                    "cg_converged": not (inf.status_flags & 16)})
+        if idx == 4:
+            gm = torch.ones(P.t, device=dev, dtype=x.dtype)
+            gv = torch.ones(P.t, device=dev, dtype=x.dtype)
+            t_bwd = timed(lambda: c.predict_backward(xs, gm, gv))
+            rec["backward_ms"] = round(t_bwd * 1e3, 4)
+            rec["backward_over_forward"] = round(t_bwd / t_fwd, 2)
+        c.free()
+        out[name] = rec
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -443,6 +499,8 @@ def main():
     }
     if not a.no_batched:
         out["batched"] = batched_section(B, WL, torch, dev)
+    if not a.no_forms:
+        out["forms"] = forms_section(B, WL, torch, dev)
     if not a.no_cpu_baseline:
         base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries)
         out["cpu_baseline"] = base

@@ -63,6 +63,47 @@ template GridT<double> make_grid<double>(const love_cache*);
 // mode bit 4: the gathered vector is v + ratio * v2 (CG direction p = z + ratio p),
 // formed on the fly so W^T p is exact for the p the next kernel writes.
 // ----------------------------------------------------------------------------
+// Sum over rows r = r0, r0 + LPR, ... < re of w_node(x_r) * val_r for one
+// lane: rows go in batches of four whose loads (global address space) are
+// all issued before any weight is formed, so a lane walking many rows (d > 1)
+// overlaps their latencies; rows past re add exact zeros, so the sum equals
+// the row-by-row one.
+template <typename T, int D, int LPR, bool COMB>
+__device__ __forceinline__ T scatter_rows(const GridT<T>& g, const T* x, const T* v, const T* v2,
+                                          T ratio, const int (&ue)[D], int32_t r0, int32_t re) {
+  using GT = const __attribute__((address_space(1))) T;
+  GT* gx = (GT*)x;
+  GT* gv = (GT*)v;
+  GT* gv2 = (GT*)v2;
+  constexpr int UB = 4;
+  T acc = T(0);
+  for (int32_t rs = r0; rs < re; rs += UB * LPR) {
+    T xr[UB][D], vr[UB], v2r[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      const int64_t r = min(rs + q * LPR, re - 1);
+#pragma unroll
+      for (int e = 0; e < D; ++e) xr[q][e] = gx[r * D + e];
+      vr[q] = gv[r];
+      if constexpr (COMB) v2r[q] = gv2[r];
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      T w = T(1);
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        T s;
+        const int jj = stencil_at(g, e, xr[q][e], s);
+        w *= keys_weight_at(ue[e] - jj, s);
+      }
+      T val = vr[q];
+      if constexpr (COMB) val = (T)(vr[q] + ratio * v2r[q]);
+      acc += (rs + q * LPR < re) ? w * val : T(0);
+    }
+  }
+  return acc;
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* __restrict__ jobs,
                                                  int j, int mode) {
@@ -107,17 +148,8 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
   if (ok) {
     const int32_t rb = J.cell_start[cbase + cl];
     const int32_t re = J.cell_start[cbase + ch + 1];
-    for (int32_t r = rb + sub; r < re; r += LPR) {
-      T w = T(1);
-#pragma unroll
-      for (int e = 0; e < D; ++e) {
-        T s;
-        const int jj = stencil_at(g, e, x[(int64_t)r * D + e], s);
-        w *= keys_weight_at(ue[e] - jj, s);
-      }
-      const T val = comb ? (T)(v[r] + ratio * v2[r]) : v[r];
-      acc += w * val;
-    }
+    if (comb) acc = scatter_rows<T, D, LPR, true>(g, x, v, v2, ratio, ue, rb + sub, re);
+    else acc = scatter_rows<T, D, LPR, false>(g, x, v, v2, ratio, ue, rb + sub, re);
   }
   acc = wave_sum(acc);
   if (lane == 0) J.out[(int64_t)j * J.out_js + u] = acc;
