@@ -547,6 +547,13 @@ __global__ __launch_bounds__(256) void k_sample_f(GridT<T> g, const T* __restric
 
 constexpr int SM_T = 64;   // points per output tile
 constexpr int SM_J = 64;   // samples per output tile
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+// out tile = mu 1^T + F_tile Z_tile on the matrix cores: wave w computes the
+// 32 x 32 sub-tile (rows 32 (w / 2), columns 32 (w % 2)) with
+// v_mfma_f32_32x32x2f32 over the k_chol factor columns, two per instruction
+// (lane l supplies F[row l % 32][kk + l / 32] and Z[kk + l / 32][col l % 32];
+// its 16 results are rows 8 (i / 4) + 4 (l / 32) + i % 4 of column l % 32).
+// The tiles sit in LDS with zero padding past k_chol.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
                                                    const float* __restrict__ mu, int kspad,
@@ -557,6 +564,7 @@ __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
   __shared__ float Zl[MAXK][SM_J];
   __shared__ float ml[SM_T];
   const int ks = ctl->k_chol;
+  const int kk2 = (ks + 1) & ~1;   // k_chol rounded up to the MFMA depth (zero column)
   const int64_t p0 = (int64_t)blockIdx.x * SM_T;
   // tile loads: a fixed number per thread, all issued before any LDS store
   // (a loop with a run-time trip count waits for each load in turn)
@@ -576,7 +584,9 @@ __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
     }
   }
   if (threadIdx.x < SM_T) ml[threadIdx.x] = p0 + threadIdx.x < t ? mu[p0 + threadIdx.x] : 0.0f;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int rw = 32 * (w >> 1), cw = 32 * (w & 1);
+  const int li = lane & 31, lk = lane >> 5;
   for (int64_t jt = blockIdx.y; jt < njt; jt += gridDim.y) {
     const int64_t j0 = jt * SM_J;
     __syncthreads();
@@ -594,29 +604,17 @@ __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
       }
     }
     __syncthreads();
-    float acc[4][4] = {};
+    f32x16 acc = {};
 #pragma unroll 4
-    for (int cc = 0; cc < ks; ++cc) {
-      float fa[4], zb[4];
+    for (int kk = 0; kk < kk2; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Fl[rw + li][kk + lk], Zl[kk + lk][cw + li], acc,
+                                                 0, 0, 0);
+    const int64_t j = j0 + cw + li;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) fa[r] = Fl[ty + 16 * r][cc];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) zb[q] = Zl[cc][tx + 16 * q];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[r][q] += fa[r] * zb[q];
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t p = p0 + ty + 16 * r;
-      if (p >= t) continue;
-      const float m0 = ml[ty + 16 * r];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t j = j0 + tx + 16 * q;
-        if (j < ns) out[p * ns + j] = (T)(m0 + acc[r][q]);
-      }
+    for (int i = 0; i < 16; ++i) {
+      const int r = rw + 8 * (i / 4) + 4 * lk + (i % 4);
+      const int64_t p = p0 + r;
+      if (p < t && j < ns) out[p * ns + j] = (T)(ml[r] + acc[i]);
     }
   }
 }
