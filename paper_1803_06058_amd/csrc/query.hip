@@ -362,28 +362,34 @@ template love_status covar_pairs<double>(const love_cache*, const double*, const
 //   d var  / dx_e = dp/dx_e - 2 u . v_e,  u = Rt^T w, v_e = Rt^T dw/dx_e
 //   dp/dx_e = 2 (dw_e)^T T_e w_e * prod_{f != e} w_f^T T_f w_f
 // Optional dRt: += -2 g_var W_a u  (float atomics).
+// Lanes as in the predictive variances: 16 per point, lane sub holding the
+// CPL = kpad / 16 consecutive columns from sub CPL of every stencil row.
 // ----------------------------------------------------------------------------
-template <typename T, int D, int SPLIT>
-__global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
-                                                  const void* __restrict__ rt,
-                                                  const uint16_t* __restrict__ rt_lo, int kpad,
-                                                  int keff, const T* __restrict__ acache,
-                                                  const double* __restrict__ c4,
-                                                  const T* __restrict__ gm, const T* __restrict__ gv,
-                                                  T* __restrict__ gx, float* __restrict__ grt,
-                                                  unsigned* __restrict__ status) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (p >= t) return;
+template <typename T, int D, int SPLIT, int CPL>
+__device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
+                                     const void* __restrict__ rt,
+                                     const uint16_t* __restrict__ rt_lo, int kpad,
+                                     const Ctl* __restrict__ ctl, const T* __restrict__ acache,
+                                     const double* __restrict__ c4, const T* __restrict__ gm,
+                                     const T* __restrict__ gv, T* __restrict__ gx,
+                                     float* __restrict__ grt, unsigned* __restrict__ status) {
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int64_t p = (int64_t)blockIdx.x * PPB + threadIdx.x / PLQ;
+  const bool live = p < t;
+  const int64_t pc = live ? p : t - 1;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, xs + p * D, w, dw, base, true);
+  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, true);
   constexpr int NA = 1 << (2 * D);
-  const bool two = kpad > WAVE;
-  double u0 = 0, u1 = 0;
-  double v0[D], v1[D], dmu[D];
+  double u[CPL], v[D][CPL], dmu[D];
 #pragma unroll
-  for (int e = 0; e < D; ++e) v0[e] = v1[e] = dmu[e] = 0.0;
+  for (int q = 0; q < CPL; ++q) {
+    u[q] = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) v[e][q] = 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) dmu[e] = 0.0;
   for (int a = 0; a < NA; ++a) {
     int o[D];
     int64_t node = base;
@@ -395,44 +401,48 @@ __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restric
     double wa = 1.0;
 #pragma unroll
     for (int e = 0; e < D; ++e) wa *= w[e][o[e]];
-    const double r0 = rt_load<T, SPLIT>(rt, rt_lo, node * kpad + lane);
-    const double r1 = two ? rt_load<T, SPLIT>(rt, rt_lo, node * kpad + lane + WAVE) : 0.0;
-    u0 += wa * r0;
-    u1 += wa * r1;
-    const double av = ((a & (WAVE - 1)) == lane && acache) ? (double)acache[node] : 0.0;
+    double r[CPL];
+    rt_row<T, SPLIT, CPL>(rt, rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) u[q] += wa * r[q];
+    const double av = ((a & (PLQ - 1)) == sub && acache) ? (double)acache[node] : 0.0;
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       double dwa = 1.0;
 #pragma unroll
       for (int f = 0; f < D; ++f) dwa *= (f == e) ? dw[f][o[f]] : w[f][o[f]];
-      v0[e] += dwa * r0;
-      v1[e] += dwa * r1;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) v[e][q] += dwa * r[q];
       dmu[e] += dwa * av;
     }
   }
-  const double gmean = gm ? (double)gm[p] : 0.0;
-  const double gvar = gv ? (double)gv[p] : 0.0;
-  double q[D], dq[D];
+  const double gmean = (gm && live) ? (double)gm[p] : 0.0;
+  const double gvar = (gv && live) ? (double)gv[p] : 0.0;
+  double qd[D], dq[D];
 #pragma unroll
   for (int e = 0; e < D; ++e) {
-    q[e] = quad4(c4 + 4 * e, w[e], w[e]);
+    qd[e] = quad4(c4 + 4 * e, w[e], w[e]);
     dq[e] = 2.0 * quad4(c4 + 4 * e, dw[e], w[e]);
   }
 #pragma unroll
   for (int e = 0; e < D; ++e) {
-    const double uv = wave_sum(u0 * v0[e] + u1 * v1[e]);
-    const double dm = wave_sum(dmu[e]);
-    if (lane == 0) {
+    double uv = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) uv += u[q] * v[e][q];
+    uv = group_sum(uv, PLQ);
+    const double dm = group_sum(dmu[e], PLQ);
+    if (sub == 0 && live) {
       double dp = dq[e];
 #pragma unroll
       for (int f = 0; f < D; ++f)
-        if (f != e) dp *= q[f];
+        if (f != e) dp *= qd[f];
       const double gval = gmean * dm + gvar * (dp - 2.0 * uv);
       gx[p * D + e] = ok ? (T)gval : (T)NAN;
     }
   }
-  if (!ok && lane == 0) atomicOr(status, SF_DOMAIN);
-  if (grt && ok && gvar != 0.0) {
+  if (!ok && live && sub == 0) atomicOr(status, SF_DOMAIN);
+  if (grt && live && ok && gvar != 0.0) {
+    const int keff = ctl->k_eff;
     for (int a = 0; a < NA; ++a) {
       int64_t node = base;
       double wa = 1.0;
@@ -443,32 +453,50 @@ __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restric
         wa *= w[e][o];
       }
       const double f = -2.0 * gvar * wa;
-      if (lane < keff) atomicAdd(&grt[node * keff + lane], (float)(f * u0));
-      if (two && lane + WAVE < keff) atomicAdd(&grt[node * keff + lane + WAVE], (float)(f * u1));
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int col = sub * CPL + q;
+        if (col < keff) atomicAdd(&grt[node * keff + col], (float)(f * u[q]));
+      }
     }
   }
+}
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                  const void* __restrict__ rt,
+                                                  const uint16_t* __restrict__ rt_lo, int kpad,
+                                                  const Ctl* __restrict__ ctl,
+                                                  const T* __restrict__ acache,
+                                                  const double* __restrict__ c4,
+                                                  const T* __restrict__ gm, const T* __restrict__ gv,
+                                                  T* __restrict__ gx, float* __restrict__ grt,
+                                                  unsigned* __restrict__ status) {
+  if (kpad > 64)
+    backward_body<T, D, SPLIT, 128 / PLQ>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv, gx,
+                                          grt, status);
+  else
+    backward_body<T, D, SPLIT, 64 / PLQ>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv, gx,
+                                         grt, status);
 }
 
 template <typename T>
 love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, const T* gv, T* gx,
                      float* grt, hipStream_t s) {
-  ProfScope ps("backward", s);
   if (t == 0) return LOVE_OK;
-  Ctl h;
-  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  LOVE_HIP_TRY(hipStreamSynchronize(s));
-  const int keff = h.k_eff;
   GridT<T> g = make_grid<T>(c);
-  dim3 grid((unsigned)cdiv(t, 4));
+  const unsigned nb = (unsigned)cdiv(t, PPB);
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
   const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
-#define LAUNCH_B(D)                                                                                \
-  if (split)                                                                                       \
-    k_backward<T, D, 1><<<grid, 256, 0, s>>>(g, xs, t, c->rt, (const uint16_t*)c->rt_lo, c->kpad,  \
-                                             keff, a, c->c4_dev, gm, gv, gx, grt, c->status);      \
-  else                                                                                             \
-    k_backward<T, D, 0><<<grid, 256, 0, s>>>(g, xs, t, c->rt, nullptr, c->kpad, keff, a,           \
-                                             c->c4_dev, gm, gv, gx, grt, c->status);
+  const Ctl* ctl = c->ctl;
+#define LAUNCH_B(D)                                                                               \
+  if (split)                                                                                      \
+    tlaunch("backward", k_backward<T, D, 1>, nb, 256, 0, s, g, xs, t, c->rt,                      \
+            (const uint16_t*)c->rt_lo, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt, \
+            c->status);                                                                           \
+  else                                                                                            \
+    tlaunch("backward", k_backward<T, D, 0>, nb, 256, 0, s, g, xs, t, c->rt,                      \
+            (const uint16_t*)nullptr, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt,  \
+            c->status);
   switch (c->d) {
     case 1: LAUNCH_B(1); break;
     case 2: LAUNCH_B(2); break;
