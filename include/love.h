@@ -192,6 +192,17 @@ love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* ca
 love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
                                      int64_t t, void* cov, void* stream);
 
+/* Predictive covariance of every pair: cov[i * tb + j] = k(xa_i, xb_j)
+ * (Alg. 1 with w_i != w_j, eq. pred_covar_ski_fast):
+ * prod_e w_{a,e}^T T_e w_{b,e} - (Rt^T w_a) . (Rt^T w_b), the dot product in
+ * double.  xa : ta x d, xb : tb x d (cache precision, device); cov : ta x tb
+ * row-major, caller-owned.  ta <= 65535 * 32.  A point outside [lo, hi]
+ * gives NaN in its row / column and sets LOVE_SF_DOMAIN.  The call allocates
+ * (ta + tb) (kpad + 5 d + 1) doubles of stream-ordered scratch and frees it
+ * on the stream.  Errors: EINVAL for bad sizes or NULL buffers. */
+love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
+                                     const void* xb, int64_t tb, void* cov, void* stream);
+
 /* Posterior samples (eq. sample with S of eq. pred_covar_ski_interp_form):
  * out[i, j] = mu(xs_i) + sum_a w_a(xs_i) (S z_j)[a].
  *   z : k_eff_sample x s row-major standard normals (float; rows beyond

@@ -55,6 +55,7 @@ class love_export(C.Structure):
 SYMBOLS = [
     "love_abi_version", "love_status_string", "love_build_cache", "love_build_cache_batched",
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
+    "love_predict_covar_block",
     "love_sample_posterior", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
     "love_cache_info", "love_cache_export", "love_cache_free", "love_profile_enable",
     "love_profile_read", "love_profile_select",
@@ -92,6 +93,8 @@ def load_library():
                                                 C.POINTER(vp), C.POINTER(vp), vp]
     L.love_predict_covar_pairs.restype = i32
     L.love_predict_covar_pairs.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.love_predict_covar_block.restype = i32
+    L.love_predict_covar_block.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     L.love_sample_posterior.restype = i32
     L.love_sample_posterior.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     L.love_predict_backward.restype = i32
@@ -221,6 +224,16 @@ class LoveCache:
         cov = torch.empty(t, device=xa.device, dtype=self.dtype)
         _check(load_library().love_predict_covar_pairs(self._h, _ptr(xa), _ptr(xb), t, _ptr(cov),
                                                        C.c_void_p(_stream())), "predict_covar_pairs")
+        return cov
+
+    def predict_covar_block(self, xa: torch.Tensor, xb: torch.Tensor):
+        """cov[i, j] = k(xa_i, xb_j) for every pair (ta x tb)."""
+        ta = self._xs(xa, "xa")
+        tb = self._xs(xb, "xb")
+        cov = torch.empty(ta, tb, device=xa.device, dtype=self.dtype)
+        _check(load_library().love_predict_covar_block(self._h, _ptr(xa), ta, _ptr(xb), tb,
+                                                       _ptr(cov), C.c_void_p(_stream())),
+               "predict_covar_block")
         return cov
 
     def sample_posterior(self, xs: torch.Tensor, z: torch.Tensor, out=None):

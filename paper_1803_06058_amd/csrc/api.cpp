@@ -465,6 +465,15 @@ love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const 
   return covar_pairs<float>(c, (const float*)xa, (const float*)xb, t, (float*)cov, s);
 }
 
+love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
+                                     const void* xb, int64_t tb, void* cov, void* stream) {
+  if (!c || ta < 0 || tb < 0 || (ta > 0 && tb > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64)
+    return covar_block<double>(c, (const double*)xa, ta, (const double*)xb, tb, (double*)cov, s);
+  return covar_block<float>(c, (const float*)xa, ta, (const float*)xb, tb, (float*)cov, s);
+}
+
 love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
                                   int64_t ns, void* out, void* stream) {
   if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;

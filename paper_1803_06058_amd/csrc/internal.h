@@ -253,6 +253,10 @@ love_status predict_batch(const std::vector<const love_cache*>& cs,
                           hipStream_t s);
 
 template <typename T>
+love_status covar_block(const love_cache* c, const T* xa, int64_t ta, const T* xb, int64_t tb,
+                        T* cov, hipStream_t s);
+
+template <typename T>
 love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t, T* cov,
                         hipStream_t s);
 

@@ -353,6 +353,188 @@ love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t
 #undef LAUNCH_C
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
+// ----------------------------------------------------------------------------
+// Predictive covariance block: cov[i, j] = k(xa_i, xb_j) for all pairs
+// (Alg. 1 with w_i != w_j; eq. pred_covar_ski_fast):
+//   cov = prod_e w_a,e^T T_e w_b,e  -  u_a . u_b,   u = Rt^T w (double).
+//   k_covar_u      per point: u (double, kpad wide) and the stencil record
+//                  [w (4 per axis) | base per axis | in-domain flag], 16 lanes
+//                  per point as for the variances;
+//   k_covar_block  32 x 32 pairs per block from LDS tiles of u.
+// ----------------------------------------------------------------------------
+template <int D>
+struct CovRec {
+  static constexpr int W = 0, J = 4 * D, OK = 5 * D, N = 5 * D + 1;   // doubles per point
+};
+template <typename T, int D, int SPLIT, int CPL>
+__device__ inline void covar_u_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
+                                    const void* __restrict__ rt,
+                                    const uint16_t* __restrict__ rt_lo, int kpad,
+                                    double* __restrict__ U, double* __restrict__ rec) {
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int64_t p = (int64_t)blockIdx.x * PPB + threadIdx.x / PLQ;
+  const bool live = p < t;
+  const int64_t pc = live ? p : t - 1;
+  double w[D][4], dw[D][4];
+  int64_t base;
+  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, false);
+  constexpr int NA = 1 << (2 * D);
+  double u[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) u[q] = 0.0;
+#pragma unroll 4
+  for (int a = 0; a < NA; ++a) {
+    double wa = 1.0;
+    int64_t node = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int o = (a >> (2 * (D - 1 - e))) & 3;
+      wa *= w[e][o];
+      node += (int64_t)o * g.nstride[e];
+    }
+    double r[CPL];
+    rt_row<T, SPLIT, CPL>(rt, rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) u[q] += wa * r[q];
+  }
+  if (!live) return;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) U[p * kpad + sub * CPL + q] = u[q];
+  if (sub == 0) {
+    double* rp = rec + p * CovRec<D>::N;
+    int64_t rem = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+#pragma unroll
+      for (int o = 0; o < 4; ++o) rp[CovRec<D>::W + 4 * e + o] = w[e][o];
+      const int64_t je = rem / g.nstride[e];
+      rem -= je * g.nstride[e];
+      rp[CovRec<D>::J + e] = (double)je;
+    }
+    rp[CovRec<D>::OK] = ok ? 1.0 : 0.0;
+  }
+}
+template <typename T, int D, int SPLIT>
+__global__ __launch_bounds__(256) void k_covar_u(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                                                 const void* __restrict__ rt,
+                                                 const uint16_t* __restrict__ rt_lo, int kpad,
+                                                 double* __restrict__ U, double* __restrict__ rec) {
+  if (kpad > 64) covar_u_body<T, D, SPLIT, 128 / PLQ>(g, xs, t, rt, rt_lo, kpad, U, rec);
+  else covar_u_body<T, D, SPLIT, 64 / PLQ>(g, xs, t, rt, rt_lo, kpad, U, rec);
+}
+
+constexpr int CB = 32;   // pairs per tile side
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_covar_block(
+    const double* __restrict__ Ua, const double* __restrict__ ra, int64_t ta,
+    const double* __restrict__ Ub, const double* __restrict__ rb, int64_t tb, int kpad,
+    const Ctl* __restrict__ ctl, const double* __restrict__ c0, const double* __restrict__ c1,
+    const double* __restrict__ c2, const double* __restrict__ c3, T* __restrict__ cov,
+    unsigned* __restrict__ status) {
+  __shared__ double A[CB][MAXK + 1], Bt[CB][MAXK + 1];
+  __shared__ double RA[CB][CovRec<D>::N], RB[CB][CovRec<D>::N];
+  const int keff = ctl->k_eff;
+  const int64_t i0 = (int64_t)blockIdx.y * CB, j0 = (int64_t)blockIdx.x * CB;
+  {
+    // fixed-count unrolled loads, all issued before the LDS stores
+    constexpr int NL = CB * MAXK / 256;
+    double va[NL], vb[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx / MAXK, c = idx % MAXK;
+      va[q] = (c < keff && i0 + r < ta) ? Ua[(i0 + r) * kpad + c] : 0.0;
+      vb[q] = (c < keff && j0 + r < tb) ? Ub[(j0 + r) * kpad + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = threadIdx.x + 256 * q;
+      A[idx / MAXK][idx % MAXK] = va[q];
+      Bt[idx / MAXK][idx % MAXK] = vb[q];
+    }
+  }
+  for (int idx = threadIdx.x; idx < CB * CovRec<D>::N; idx += blockDim.x) {
+    const int r = idx / CovRec<D>::N, c = idx - r * CovRec<D>::N;
+    RA[r][c] = i0 + r < ta ? ra[(i0 + r) * CovRec<D>::N + c] : 0.0;
+    RB[r][c] = j0 + r < tb ? rb[(j0 + r) * CovRec<D>::N + c] : 0.0;
+  }
+  __syncthreads();
+  const double* cols[4] = {c0, c1, c2, c3};
+  const int jj = threadIdx.x % CB;
+  const int64_t j = j0 + jj;
+  bool flag = false;
+  for (int ii = threadIdx.x / CB; ii < CB; ii += blockDim.x / CB) {
+    const int64_t i = i0 + ii;
+    if (i >= ta || j >= tb) continue;
+    double dot = 0.0;
+    for (int c = 0; c < keff; ++c) dot += A[ii][c] * Bt[jj][c];
+    double pr = 1.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int ja = (int)RA[ii][CovRec<D>::J + e], jb = (int)RB[jj][CovRec<D>::J + e];
+      double se = 0.0;
+#pragma unroll
+      for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int lag = (ja + o) - (jb + q);
+          lag = lag < 0 ? -lag : lag;
+          se += RA[ii][CovRec<D>::W + 4 * e + o] * RB[jj][CovRec<D>::W + 4 * e + q] * cols[e][lag];
+        }
+      pr *= se;
+    }
+    const bool ok = RA[ii][CovRec<D>::OK] != 0.0 && RB[jj][CovRec<D>::OK] != 0.0;
+    cov[i * tb + j] = ok ? (T)(pr - dot) : (T)NAN;
+    flag = flag || !ok;
+  }
+  if (flag) atomicOr(status, SF_DOMAIN);
+}
+
+template <typename T>
+love_status covar_block(const love_cache* c, const T* xa, int64_t ta, const T* xb, int64_t tb,
+                        T* cov, hipStream_t s) {
+  if (ta == 0 || tb == 0) return LOVE_OK;
+  if (cdiv(ta, CB) > 65535) return LOVE_EINVAL;
+  GridT<T> g = make_grid<T>(c);
+  const int d = c->d, kpad = c->kpad, nrec = 5 * d + 1;
+  double* U = nullptr;
+  const size_t per = (size_t)kpad + nrec;
+  LOVE_HIP_TRY(hipMallocAsync((void**)&U, sizeof(double) * per * (size_t)(ta + tb), s));
+  double* Ua = U;
+  double* Ub = Ua + (size_t)kpad * ta;
+  double* ra = Ub + (size_t)kpad * tb;
+  double* rb = ra + (size_t)nrec * ta;
+  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+  const uint16_t* lo = (const uint16_t*)c->rt_lo;
+  const double* cc[4];
+  for (int e = 0; e < 4; ++e) cc[e] = (const double*)(e < d ? c->toep.ax[e].c64 : nullptr);
+  dim3 grid((unsigned)cdiv(tb, CB), (unsigned)cdiv(ta, CB));
+#define LAUNCH_CV(D)                                                                              \
+  {                                                                                               \
+    const unsigned na = (unsigned)cdiv(ta, PPB), nb = (unsigned)cdiv(tb, PPB);                     \
+    if (split) {                                                                                  \
+      tlaunch("covar_u", k_covar_u<T, D, 1>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra);   \
+      tlaunch("covar_u", k_covar_u<T, D, 1>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb);   \
+    } else {                                                                                      \
+      tlaunch("covar_u", k_covar_u<T, D, 0>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra);   \
+      tlaunch("covar_u", k_covar_u<T, D, 0>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb);   \
+    }                                                                                             \
+    tlaunch("covar_block", k_covar_block<T, D>, grid, 256, 0, s, (const double*)Ua,               \
+            (const double*)ra, ta, (const double*)Ub, (const double*)rb, tb, kpad,                \
+            (const Ctl*)c->ctl, cc[0], cc[1], cc[2], cc[3], cov, c->status);                      \
+  }
+  switch (d) {
+    case 1: LAUNCH_CV(1); break;
+    case 2: LAUNCH_CV(2); break;
+    case 3: LAUNCH_CV(3); break;
+    case 4: LAUNCH_CV(4); break;
+  }
+#undef LAUNCH_CV
+  LOVE_HIP_TRY(hipFreeAsync(U, s));
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status covar_block<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
+template love_status covar_block<double>(const love_cache*, const double*, int64_t, const double*, int64_t, double*, hipStream_t);
+
 template love_status covar_pairs<float>(const love_cache*, const float*, const float*, int64_t, float*, hipStream_t);
 template love_status covar_pairs<double>(const love_cache*, const double*, const double*, int64_t, double*, hipStream_t);
 

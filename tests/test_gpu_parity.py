@@ -147,6 +147,37 @@ def test_covar_pairs_parity():
     cache.free()
 
 
+def test_covar_block_parity():
+    """Every pair of two ragged point sets (300 x 200: partial 32 x 32 tiles)
+    against the oracle's paired covariance on the expanded pairs; the block of
+    a set with itself is symmetric and its diagonal is the variance."""
+    P = WL.config(2, scale=0.02, k_sample=0)
+    cache = build(P)
+    rng = np.random.default_rng(7)
+    xa = rng.uniform(0, 1, (300, 1)).astype(np.float32)
+    xb = rng.uniform(0, 1, (200, 1)).astype(np.float32)
+    cov = host(cache.predict_covar_block(tdev(xa, torch.float32), tdev(xb, torch.float32)))
+    assert cov.shape == (300, 200)
+    oc = oracle_cache(P)
+    xi = np.repeat(xa, 200, axis=0).astype(np.float64)
+    xj = np.tile(xb, (300, 1)).astype(np.float64)
+    ref = O.love_covariance(oc, xi, xj).reshape(300, 200)
+    spec = spec_of(P)
+    p = np.sqrt(np.outer(O.prior_var(xa, spec), O.prior_var(xb, spec)))
+    assert np.max(np.abs(cov - ref) / p) <= 1e-5
+    same = host(cache.predict_covar_block(tdev(xa, torch.float32), tdev(xa, torch.float32)))
+    pa = O.prior_var(xa, spec)
+    assert np.max(np.abs(same - same.T) / np.sqrt(np.outer(pa, pa))) <= 1e-6
+    _, var = cache.predict_mean_var(tdev(xa, torch.float32))
+    assert np.max(np.abs(np.diag(same) - host(var)) / pa) <= 1e-6
+    # an out-of-domain point gives a NaN row; empty sets are a no-op
+    xo = np.array([[0.5], [1.5], [0.25]], np.float32)
+    blk = host(cache.predict_covar_block(tdev(xo, torch.float32), tdev(xb[:5], torch.float32)))
+    assert np.isnan(blk[1]).all() and np.isfinite(blk[[0, 2]]).all()
+    assert cache.predict_covar_block(tdev(xa[:0], torch.float32), tdev(xb, torch.float32)).numel() == 0
+    cache.free()
+
+
 # ---------------------------------------------------------------------------
 # Sampling
 # ---------------------------------------------------------------------------
