@@ -444,6 +444,15 @@ def main():
     B.profile_enable(False)
     B.profile_select(None)
     mvm_ms = sum(mv[k_][1] for k_ in mv) / 20
+    # covariance of every pair of two 2000-point sets (4e6 entries)
+    xa_c, xb_c = xs[:2000].contiguous(), xs[2000:4000].contiguous()
+    c.predict_covar_block(xa_c, xb_c)
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    for _ in range(5):
+        c.predict_covar_block(xa_c, xb_c)
+    torch.cuda.synchronize()
+    cov_ms = (time.perf_counter() - tc0) * 1e3 / 5
     m_tot = int(math.prod(P.m))
     mvm_bytes = 4 * P.n * P.d * 2 + 4 * P.n * 3 + 16 * m_tot
     gpu_mean = mu.cpu().numpy()
@@ -493,6 +502,7 @@ def main():
         "query_ms": round(q_ms, 4),
         "mvm_gbps": round(mvm_bytes / (mvm_ms * 1e-3) / 1e9, 1) if mvm_ms > 0 else None,
         "mvm_us": round(mvm_ms * 1e3, 2),
+        "covar_block_2000x2000_ms": round(cov_ms, 4),
         "k_eff": k_eff, "k_eff_sample": info.k_eff_sample, "cg_iters": info.cg_iters,
         "roofline": roof,
         "kernel_ms_per_step": {k_: round(v_[1] / nwarm, 4) for k_, v_ in warm.items()},
