@@ -145,6 +145,19 @@ typedef struct {
   float* s;                         /* m x k_eff_sample row-major : sampling matrix S             */
 } love_export;
 
+/* Cache contents to rebuild a cache from (all device, caller-owned; the
+ * layouts are those of love_export, so an exported cache imports as is). */
+typedef struct {
+  int32_t k_eff;                    /* columns of rt, 1..LOVE_MAX_K                               */
+  int32_t k_eff_sample;             /* columns of s, 0..LOVE_MAX_K (0: no sampler)                */
+  const double* alpha;              /* k_eff (nullable: then zeros)                               */
+  const double* beta;               /* k_eff (nullable: then zeros)                               */
+  const float* rt;                  /* m x k_eff row-major (FP32 and BF16-split precisions)       */
+  const double* rt64;               /* m x k_eff row-major (FP64 precision)                       */
+  const void* a;                    /* m, precision's element type (NULL: zero mean cache)        */
+  const float* s;                   /* m x k_eff_sample row-major (NULL iff k_eff_sample = 0)     */
+} love_import;
+
 /* ABI version of the loaded library (LOVE_ABI_VERSION). */
 int32_t love_abi_version(void);
 
@@ -233,6 +246,19 @@ love_status love_cache_info(const love_cache* c, love_cache_info_t* info);
 
 /* Copy cache contents into caller device buffers (enqueued on `stream`). */
 love_status love_cache_export(const love_cache* c, const love_export* e, void* stream);
+
+/* Rebuild a cache from its contents (love_export layout) without the
+ * training data: the LOVE query (Alg. 1, eq. pred_covar_ski_fast), the
+ * covariance calls, the backward and, with s, the sampler (eq. sample) then
+ * work as on the cache that was exported; love_apply_khat needs the training
+ * rows and returns LOVE_EUNSUPPORTED.  cfg gives the grid, kernel and
+ * precision (cfg->k and cfg->k_sample are replaced by the imported column
+ * counts).  For the BF16 split the float Rt is split again into hi + lo,
+ * whose sum reproduces it.  Enqueued on `stream`; the imported buffers may be
+ * released once the stream has passed this call.
+ * Errors: EINVAL (bad config, counts or NULL buffers), ENOMEM, EHIP. */
+love_status love_cache_import(const love_config* cfg, const love_import* im, void* stream,
+                              love_cache** out);
 
 /* Release a cache (synchronises its build stream first).  NULL is a no-op. */
 void love_cache_free(love_cache* c);

@@ -52,12 +52,19 @@ class love_export(C.Structure):
                 ("rt64", C.c_void_p), ("a", C.c_void_p), ("s", C.c_void_p)]
 
 
+class love_import(C.Structure):
+    _fields_ = [("k_eff", C.c_int32), ("k_eff_sample", C.c_int32), ("alpha", C.c_void_p),
+                ("beta", C.c_void_p), ("rt", C.c_void_p), ("rt64", C.c_void_p),
+                ("a", C.c_void_p), ("s", C.c_void_p)]
+
+
 SYMBOLS = [
     "love_abi_version", "love_status_string", "love_build_cache", "love_build_cache_batched",
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
     "love_predict_covar_block",
     "love_sample_posterior", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
-    "love_cache_info", "love_cache_export", "love_cache_free", "love_profile_enable",
+    "love_cache_info", "love_cache_export", "love_cache_import", "love_cache_free",
+    "love_profile_enable",
     "love_profile_read", "love_profile_select",
 ]
 
@@ -107,6 +114,9 @@ def load_library():
     L.love_cache_info.argtypes = [vp, C.POINTER(love_cache_info_t)]
     L.love_cache_export.restype = i32
     L.love_cache_export.argtypes = [vp, C.POINTER(love_export), vp]
+    L.love_cache_import.restype = i32
+    L.love_cache_import.argtypes = [C.POINTER(love_config), C.POINTER(love_import), vp,
+                                    C.POINTER(vp)]
     L.love_cache_free.restype = None
     L.love_cache_free.argtypes = [vp]
     L.love_profile_enable.restype = i32
@@ -318,6 +328,25 @@ def build_cache(cfg: love_config, x: torch.Tensor, y: torch.Tensor) -> LoveCache
     h = C.c_void_p()
     _check(L.love_build_cache(C.byref(cfg), _ptr(x), _ptr(y), n, C.c_void_p(_stream()), C.byref(h)),
            "build_cache")
+    return LoveCache(h.value, cfg)
+
+
+def import_cache(cfg: love_config, parts: Dict[str, torch.Tensor]) -> LoveCache:
+    """love_cache_import from the dict LoveCache.export() returns (device
+    tensors: rt (m x k_eff float) or rt64, a, optional alpha, beta, s)."""
+    L = load_library()
+    rt = parts.get("rt64") if cfg.precision == 0 else parts.get("rt")
+    if rt is None or rt.dim() != 2:
+        raise ValueError("parts needs rt (rt64 for FP64) as an m x k_eff tensor")
+    s = parts.get("s")
+    im = love_import(int(rt.shape[1]), int(s.shape[1]) if s is not None else 0,
+                     _ptr(parts.get("alpha")), _ptr(parts.get("beta")),
+                     _ptr(parts.get("rt")) if cfg.precision != 0 else None,
+                     _ptr(parts.get("rt64")) if cfg.precision == 0 else None,
+                     _ptr(parts.get("a")), _ptr(s))
+    h = C.c_void_p()
+    _check(L.love_cache_import(C.byref(cfg), C.byref(im), C.c_void_p(_stream()), C.byref(h)),
+           "cache_import")
     return LoveCache(h.value, cfg)
 
 

@@ -497,6 +497,7 @@ love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t
 
 love_status love_apply_khat(const love_cache* c, const void* v, void* out, void* stream) {
   if (!c || !v || !out) return LOVE_EINVAL;
+  if (c->n == 0) return LOVE_EUNSUPPORTED;   // imported cache: no training rows
   hipStream_t s = (hipStream_t)stream;
   ProfScope ps("apply_khat", s);
   if (c->fp64) return apply_khat_t<double>(c, (const double*)v, (double*)out, s);
@@ -565,6 +566,63 @@ love_status love_cache_export(const love_cache* c, const love_export* e, void* s
   if (e->s && c->ks > 0 && hs.k_chol > 0)
     LOVE_HIP_TRY(hipMemcpy2DAsync(e->s, sizeof(float) * hs.k_chol, c->S, sizeof(float) * c->kspad,
                                   sizeof(float) * hs.k_chol, c->m, hipMemcpyDeviceToDevice, s));
+  return LOVE_OK;
+}
+
+love_status love_cache_import(const love_config* cfg, const love_import* im, void* stream,
+                              love_cache** out) {
+  if (!cfg || !im || !out) return LOVE_EINVAL;
+  *out = nullptr;
+  love_status st = validate(cfg);
+  if (st != LOVE_OK) return st;
+  if (im->k_eff < 1 || im->k_eff > LOVE_MAX_K || im->k_eff_sample < 0 ||
+      im->k_eff_sample > LOVE_MAX_K)
+    return LOVE_EINVAL;
+  const bool fp64 = cfg->precision == LOVE_P_FP64;
+  if (fp64 ? !im->rt64 : !im->rt) return LOVE_EINVAL;
+  if ((im->k_eff_sample > 0) != (im->s != nullptr)) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  device_setup();
+  love_config cf = *cfg;
+  cf.k = im->k_eff;
+  cf.k_sample = im->k_eff_sample;
+  love_cache* c = new (std::nothrow) love_cache();
+  if (!c) return LOVE_ENOMEM;
+  // the row-sized buffers are sized for k_eff rows (unused: no training data)
+  st = init_cache(c, &cf, im->k_eff, s);
+  if (st == LOVE_OK) st = toeplitz_plan(c);
+  if (st == LOVE_OK) {
+    c->tscr = dev_alloc(c, sizeof(double) * (size_t)toeplitz_scratch_elems(c));
+    if (!c->tscr) st = LOVE_ENOMEM;
+  }
+  if (st == LOVE_OK) st = rt_import(c, im->rt, im->rt64, im->k_eff, im->k_eff_sample, s);
+  const size_t es = c->fp64 ? 8 : 4;
+  auto copy = [&](void* dst, const void* src, size_t bytes) {
+    if (st == LOVE_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      st = LOVE_EHIP;
+  };
+  auto clear = [&](void* dst, size_t bytes) {
+    if (st == LOVE_OK && hipMemsetAsync(dst, 0, bytes, s) != hipSuccess) st = LOVE_EHIP;
+  };
+  clear(c->alpha, sizeof(double) * LOVE_MAX_K);
+  clear(c->beta, sizeof(double) * LOVE_MAX_K);
+  if (im->alpha) copy(c->alpha, im->alpha, sizeof(double) * im->k_eff);
+  if (im->beta) copy(c->beta, im->beta, sizeof(double) * im->k_eff);
+  if (im->a) copy(c->a, im->a, es * (size_t)c->m);
+  if (c->ks > 0) {
+    clear(c->S, sizeof(float) * (size_t)c->m * c->kspad);
+    if (st == LOVE_OK &&
+        hipMemcpy2DAsync(c->S, sizeof(float) * c->kspad, im->s, sizeof(float) * im->k_eff_sample,
+                         sizeof(float) * im->k_eff_sample, c->m, hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+      st = LOVE_EHIP;
+  }
+  if (st != LOVE_OK) {
+    destroy(c);
+    return st;
+  }
+  c->n = 0;   // no training rows: love_apply_khat is unavailable
+  *out = c;
   return LOVE_OK;
 }
 

@@ -86,6 +86,16 @@ __device__ inline bool in_domain(T x, T lo, T hi) {
   return x >= lo && x <= hi;   // false for NaN
 }
 
+// bf16 round-to-nearest-even from the IEEE-754 bit pattern
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
 // ----------------------------------------------------------------------------
 // Wave / block reductions
 // ----------------------------------------------------------------------------

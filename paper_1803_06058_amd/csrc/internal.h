@@ -269,5 +269,8 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
                      T* gx, float* grt, hipStream_t s);
 
 love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t s);
+// imported Rt into the cache layout and the control blocks of an imported cache
+love_status rt_import(love_cache* c, const float* rt, const double* rt64, int keff, int kchol,
+                      hipStream_t s);
 
 }  // namespace love

@@ -645,15 +645,6 @@ __global__ __launch_bounds__(RBLK) void k_lz_finalize(Tab tab, const LzJob<T>* _
   else lz_finalize_body<T, 1>(J, lb, j);
 }
 
-// bf16 round-to-nearest-even from the IEEE-754 bit pattern
-__device__ inline uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-  const uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // Cholesky of the tridiagonal T (alpha, beta) of size ctl->k_eff; one block
 // per GP, one thread working.  A non-positive pivot truncates k_eff there

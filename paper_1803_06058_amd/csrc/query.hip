@@ -867,6 +867,54 @@ __global__ void k_rt_export(int64_t m, const void* __restrict__ rt, const uint16
   dst[i] = (float)rt_load<T, SPLIT>(rt, rt_lo, u * kpad + c);
 }
 
+// Import: Rt (m x keff row-major, float or double) into the cache layout
+// (m x kpad, zero columns past keff; bf16 hi + lo for the split), and the
+// control blocks of an imported cache.
+template <typename T, int SPLIT>
+__global__ void k_rt_import(int64_t m, const float* __restrict__ src,
+                            const double* __restrict__ src64, int keff, int kpad,
+                            void* __restrict__ rt, uint16_t* __restrict__ rt_lo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * kpad) return;
+  const int64_t u = i / kpad;
+  const int c = (int)(i - u * kpad);
+  if constexpr (SPLIT) {
+    const float f = c < keff ? src[u * keff + c] : 0.0f;
+    const uint16_t hi = f32_to_bf16_rne(f);
+    ((uint16_t*)rt)[i] = hi;
+    rt_lo[i] = f32_to_bf16_rne(f - bf16_to_f32(hi));
+  } else if constexpr (sizeof(T) == 8) {
+    ((double*)rt)[i] = c < keff ? src64[u * keff + c] : 0.0;
+  } else {
+    ((float*)rt)[i] = c < keff ? src[u * keff + c] : 0.0f;
+  }
+}
+__global__ void k_import_ctl(Ctl* ctl, Ctl* ctl_s, double* ortho, int keff, int kchol) {
+  Ctl z{};
+  z.k_eff = keff;
+  z.stop = 1;
+  *ctl = z;
+  Ctl zs{};
+  zs.k_eff = kchol;
+  zs.k_chol = kchol;
+  zs.stop = 1;
+  *ctl_s = zs;
+  *ortho = NAN;
+}
+love_status rt_import(love_cache* c, const float* rt, const double* rt64, int keff, int kchol,
+                      hipStream_t s) {
+  const int64_t tot = c->m * c->kpad;
+  dim3 grid((unsigned)cdiv(tot, 256));
+  if (c->fp64)
+    k_rt_import<double, 0><<<grid, 256, 0, s>>>(c->m, rt, rt64, keff, c->kpad, c->rt, nullptr);
+  else if (c->cfg.precision == LOVE_P_FP32_BF16SPLIT)
+    k_rt_import<float, 1><<<grid, 256, 0, s>>>(c->m, rt, rt64, keff, c->kpad, c->rt,
+                                               (uint16_t*)c->rt_lo);
+  else k_rt_import<float, 0><<<grid, 256, 0, s>>>(c->m, rt, rt64, keff, c->kpad, c->rt, nullptr);
+  k_import_ctl<<<1, 1, 0, s>>>(c->ctl, c->ctl_s, c->ortho, keff, kchol);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
 love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t s) {
   if (keff <= 0) return LOVE_OK;
   const int64_t tot = c->m * keff;

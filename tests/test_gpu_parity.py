@@ -432,6 +432,39 @@ def test_batched_grid_and_row_first_pass_equal_single():
         c.free()
 
 
+@pytest.mark.parametrize("case", ["fp32_sampler", "fp64", "bf16split"])
+def test_cache_import_roundtrip(case):
+    """export -> import: the imported cache (no training data) answers every
+    query bit for bit like the built one."""
+    if case == "fp32_sampler":
+        P = WL.config(2, scale=0.02, k_sample=40, s=64)
+    elif case == "fp64":
+        P = WL.config(1)
+    else:
+        P = WL.config(3, scale=0.01)
+    dt = torch.float64 if P.precision == "fp64" else torch.float32
+    cache = build(P)
+    parts = cache.export()
+    imp = B.import_cache(cfg_of(P), parts)
+    i0, i1 = cache.info(), imp.info()
+    assert (i1.k_eff, i1.k_eff_sample, i1.n) == (i0.k_eff, i0.k_eff_sample, 0)
+    xs = tdev(P.xs[:5000], dt)
+    m0, v0 = cache.predict_mean_var(xs)
+    m1, v1 = imp.predict_mean_var(xs)
+    assert torch.equal(m0, m1) and torch.equal(v0, v1)
+    assert torch.equal(cache.predict_covar_block(xs[:100], xs[100:300]),
+                       imp.predict_covar_block(xs[:100], xs[100:300]))
+    g = torch.ones(xs.shape[0], device=xs.device, dtype=dt)
+    assert torch.equal(cache.predict_backward(xs, g, g)[0], imp.predict_backward(xs, g, g)[0])
+    if i0.k_eff_sample > 0:
+        xss, z = tdev(P.xs_sample, dt), tdev(P.z, torch.float32)
+        assert torch.equal(cache.sample_posterior(xss, z), imp.sample_posterior(xss, z))
+    with pytest.raises(B.LoveError):
+        imp.apply_khat(torch.zeros(P.n, device=xs.device, dtype=dt))
+    imp.free()
+    cache.free()
+
+
 def test_edge_cases():
     P = WL.config(2, scale=0.01, k_sample=0)
     cache = build(P)
