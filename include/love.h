@@ -89,6 +89,8 @@ typedef enum {
 #define LOVE_FLAG_NO_MEAN 2u        /* skip the mean cache a                                      */
 #define LOVE_FLAG_PLAIN_CG 4u       /* mean solve: CG without the Lanczos preconditioner         */
 #define LOVE_FLAG_EIG_QL 8u         /* sampler: eigenvectors of T' by implicit QL (slow path)     */
+#define LOVE_FLAG_MEAN_KRYLOV 16u   /* mean solve: data-space CG even where the grid-space solve
+                                       applies (d >= 2 with every m_i <= 128)                     */
 
 typedef struct {
   int32_t d;                        /* input dimension, 1..4                                     */
@@ -105,7 +107,10 @@ typedef struct {
   int32_t k_sample;                 /* 0: no sampling cache; else second-Lanczos steps (<= 128)  */
   int32_t precision;                /* love_precision                                            */
   int32_t toeplitz;                 /* love_toeplitz_mode                                        */
-  double cg_tol;                    /* relative residual of the mean solve (<= 0: 1e-6 / 1e-12)  */
+  double cg_tol;                    /* mean solve tolerance (<= 0: 1e-6 / 1e-12).  Data-space CG:
+                                       ||Khat x - y|| <= tol ||y||.  Grid-space solve: residual
+                                       <= tol sigma ||y||, so the training-point mean is within
+                                       tol ||y|| (2-norm) of the exact solve                     */
   int32_t cg_maxit;                 /* <= 0: 1000                                                */
   uint32_t flags;                   /* LOVE_FLAG_*                                               */
 } love_config;

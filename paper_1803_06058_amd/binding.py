@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16split": 2}
 KERNELS = {"rbf": 0, "matern52": 1}
 TOEPLITZ_MODES = {"auto": 0, "direct": 1, "fft": 2}
-FLAG_ASYNC, FLAG_NO_MEAN, FLAG_PLAIN_CG, FLAG_EIG_QL = 1, 2, 4, 8
+FLAG_ASYNC, FLAG_NO_MEAN, FLAG_PLAIN_CG, FLAG_EIG_QL, FLAG_MEAN_KRYLOV = 1, 2, 4, 8, 16
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "EDOMAIN", -3: "ENOTPD", -4: "ENOMEM", -5: "EHIP",
           -6: "ENONFINITE", -7: "EUNSUPPORTED"}

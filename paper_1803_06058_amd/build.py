@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblove.so")
 
-SOURCES = ["api.cpp", "sort.hip", "mvm.hip", "fft.hip", "lanczos.hip", "query.hip"]
+SOURCES = ["api.cpp", "sort.hip", "mvm.hip", "fft.hip", "lanczos.hip", "mean.hip", "query.hip"]
 
 
 def hipcc() -> str:

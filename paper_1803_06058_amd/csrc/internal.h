@@ -245,6 +245,17 @@ template <typename T>
 love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t s,
                                 hipStream_t s_side);
 
+// --- grid-space mean solve (mean.hip) -----------------------------------------
+// true when the cache's mean is solved in grid space (d >= 2, every axis at
+// most SPEC_MAXM points, no flag asking for the data-space CG)
+bool spectral_mean_applies(const love_cache* c);
+// a = K W^T Khat^{-1} y for every GP of the batch; x64 / y64: sorted training
+// data in double, un: n doubles of scratch per GP; sets ctl->cg_iters and the
+// CG status bits.  Synchronises `s` every few iterations.
+love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
+                          const std::vector<const double*>& y64, const std::vector<double*>& un,
+                          hipStream_t s);
+
 // --- queries (query.hip) -----------------------------------------------------
 template <typename T>
 love_status predict_batch(const std::vector<const love_cache*>& cs,

@@ -175,4 +175,37 @@ struct CgJob {
   int a_fp64;
 };
 
+// Grid-space mean solve (d >= 2, every axis m_e <= SPEC_MAXM): CG on
+// (sigma^2 I + B^T W^T W B) z = B^T W^T y with B = kron(B_e), B_e B_e^T = T_e
+// and K = kron(T_e); then a = B z.  B_e = V_e diag(sqrt lam_e) U_e, where
+// T_e = V_e diag(lam_e) V_e^T and U_e diagonalises the axis's expected
+// weight Gram matrix in those coordinates (eigenvalues D_e).
+constexpr int SPEC_MAXM = 128;
+constexpr int SPW = 4;        // columns of the spectral solve's partial-sum rows
+struct SpecJob {
+  GridT<double> g;
+  const double* x;            // sorted coordinates in double, n x d
+  const int32_t* cell_start;
+  const double* y;            // sorted targets in double
+  int64_t n, mtot;
+  int d;
+  int m[MAXD];                // grid points per axis
+  int ldv[MAXD];              // row stride of the per-axis matrices (m_e rounded up to even)
+  int64_t inner[MAXD];        // product of m over later axes
+  const double* c64[MAXD];    // first column of T_e (outputscale folded into axis 0)
+  double* B[MAXD];            // B_e, ldv x ldv (row: grid node, column: mode)
+  double* W[MAXD];            // three ldv x ldv work matrices per axis
+  double* D[MAXD];            // D_e
+  double* pinv;               // mtot: 1 / (sigma^2 + n prod_e D_e)
+  double *z, *r, *p, *q, *t0, *t1;   // mtot
+  double* un;                 // n: W u
+  double* part;               // partial-sum rows (SPW columns)
+  int nbm, nbn;               // row counts of the partials over m and over n
+  double sigma2, tol2;
+  int maxit;
+  Ctl* ctl;
+  void* a;                    // cache mean vector (m, cache precision)
+  int a_fp64;
+};
+
 }  // namespace love

@@ -2202,6 +2202,24 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       k_tinv<T><<<tab_blocks(t_one), MAXK, 0, s>>>(t_one, dcg);
       k_pcg_matrix<T><<<tab_blocks(t_cmat), 256, 0, s>>>(t_cmat, dcg);
     }
+    bool spec = true;
+    for (auto* c : cs) spec = spec && spectral_mean_applies(c);
+    if (spec) {
+      std::vector<const double*> sx(G), sy(G);
+      std::vector<double*> su(G);
+      for (int g = 0; g < G; ++g) {
+        sx[g] = bufs[g].x64;
+        sy[g] = bufs[g].y64;
+        su[g] = bufs[g].cz;
+      }
+      love_status ss = spectral_mean(cs, sx, sy, su, s);
+      if (ss != LOVE_OK) {
+        A.release(s);
+        for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
+        return ss;
+      }
+    }
+    if (!spec) {
     const SumJob* dscg = A.at<SumJob>(o_scg);
     const std::vector<int> nv0(G, 0);
     k_pcg_init<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
@@ -2238,6 +2256,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s);
     toep_run<double>(A, t_cg, 0, 0, s);
     k_cg_store_a<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, dcg);
+    }
   }
   if (side) {
     LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));

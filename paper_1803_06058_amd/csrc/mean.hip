@@ -1,0 +1,620 @@
+// Mean cache by a grid-space solve, for Kronecker grids (d >= 2) whose axes
+// have at most SPEC_MAXM points.
+//
+// The mean cache is a = K W^T Khat^{-1} y, the SKI predictive mean of Sec. 3
+// with W the cubic interpolation and K = kron(T_1, ..., T_d).  For any B with
+// K = B B^T the push-through identity gives
+//   a = B (sigma^2 I + B^T W^T W B)^{-1} B^T W^T y,
+// an m-space system whose matrix is sigma^2 I plus the nonzero spectrum of
+// W K W^T.  B is taken as kron(B_e) with B_e B_e^T = T_e, chosen so that the
+// system's expectation over evenly spread data is diagonal:
+//   E[W^T W] = n kron(S_e), S_e the mean Gram matrix of one axis's four Keys
+//   weights over a cell;  T_e = V_e diag(lam) V_e^T;
+//   M_e = diag(sqrt lam) V_e^T S_e V_e diag(sqrt lam) = U_e diag(D_e) U_e^T;
+//   B_e = V_e diag(sqrt lam) U_e,  so B_e B_e^T = T_e and B_e^T S_e B_e = D_e.
+// Both eigen-decompositions are one-block parallel Jacobi runs in double
+// (m_e <= 128).  CG then takes the diagonal preconditioner
+// 1 / (sigma^2 + n prod_e D_e), the exact inverse of the expected matrix; only
+// the sampling fluctuation of W^T W about its mean is left for CG.  CG on the
+// data-space system Khat x = y needs about sqrt(cond(Khat)) iterations, which
+// reaches thousands for 2-D and 4-D grids at these noise levels.
+//
+// Stopping rule: ||r|| <= tol sigma ||y||.  Since the matrix is at least
+// sigma^2 I, the training-point mean W a then differs from the exact solve
+// by at most tol ||y|| in the 2-norm.
+//
+// One iteration: u = B p (d axis passes), W u (gather), W^T (scatter),
+// B^T (d axis passes) + sigma^2 p, the CG update, the scalar step, the new
+// direction.  The CG scalars stay on the device (Ctl); the host checks for
+// convergence every few iterations.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "ops.h"
+
+namespace love {
+
+namespace {
+
+constexpr int EIG_THREADS = 512;
+constexpr int SPB = 256;   // threads of the m- and n-length kernels
+
+// buffer codes of the axis passes
+enum : int { SB_Z = 0, SB_R, SB_P, SB_Q, SB_T0, SB_T1 };
+__device__ inline double* spec_buf(const SpecJob& J, int b) {
+  switch (b) {
+    case SB_Z: return J.z;
+    case SB_R: return J.r;
+    case SB_P: return J.p;
+    case SB_Q: return J.q;
+    case SB_T0: return J.t0;
+    default: return J.t1;
+  }
+}
+
+// axis pass modes
+enum : int {
+  KP_FWD = 1,      // out_i = sum_j B[i][j] in_j   (else B^T)
+  KP_ADD_SP = 2,   // output += sigma^2 p
+  KP_DOT_P = 4,    // partial sums of p^T out (column 0)
+  KP_FORCE = 8     // run after the solve has stopped (final a = B z)
+};
+
+// Sum of column c of the first nr partial rows, by one wave in a fixed order.
+__device__ inline double spec_colsum(const double* __restrict__ part, int nr, int c) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double acc = 0.0;
+  for (int b = lane; b < nr; b += WAVE) acc += part[(size_t)b * SPW + c];
+  return wave_sum(acc);
+}
+
+// G[a][b] = integral over s in [0, 1] of w_a(s) w_b(s), the four Keys weights
+// of a point at fraction s of its cell; 4-point Gauss-Legendre is exact for
+// these degree-6 products.
+__device__ inline void keys_gram(double G[4][4]) {
+  const double xg[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563,
+                        0.8611363115940526};
+  const double wg[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461,
+                        0.3478548451374538};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) G[a][b] = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    double w[4];
+    keys_weights<double>(0.5 * (xg[q] + 1.0), w);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) G[a][b] += 0.5 * wg[q] * w[a] * w[b];
+  }
+}
+
+struct JacobiShared {
+  double c[SPEC_MAXM / 2], s[SPEC_MAXM / 2];
+  int p[SPEC_MAXM / 2], q[SPEC_MAXM / 2];
+  double scr[16];
+  int rotated;
+};
+
+// Symmetric A (mp x mp, mp even, row-major) -> diag by cyclic parallel Jacobi;
+// V <- V J accumulates the rotations.  Each round applies mp/2 disjoint
+// rotations (circle-method pairing): A <- J^T A J one 2 x 2 block per item.
+// Sweeps stop once a whole sweep finds every |a_pq| <= 1e-17 ||A||_F
+// (at most 40 sweeps).  Whole block; ends with a barrier.
+__device__ void jacobi_block(double* __restrict__ A, double* __restrict__ V, int mp,
+                             JacobiShared& sh) {
+  const int t = threadIdx.x, np = mp / 2;
+  double fro = 0.0;
+  for (int idx = t; idx < mp * mp; idx += blockDim.x) fro += A[idx] * A[idx];
+  fro = block_sum(fro, sh.scr);
+  const double thr = 1e-17 * sqrt(fro);
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (t == 0) sh.rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < mp - 1; ++rd) {
+      if (t < np) {
+        // position 0 holds index 0, the others rotate one place per round
+        const int pa = t, pb = mp - 1 - t;
+        int p = pa == 0 ? 0 : ((pa - 1 + rd) % (mp - 1)) + 1;
+        int q = ((pb - 1 + rd) % (mp - 1)) + 1;
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        const double apq = A[p * mp + q];
+        double cc = 1.0, ss = 0.0;
+        if (fabs(apq) > thr) {
+          const double app = A[p * mp + p], aqq = A[q * mp + q];
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          cc = 1.0 / sqrt(tt * tt + 1.0);
+          ss = tt * cc;
+          sh.rotated = 1;
+        }
+        sh.p[t] = p;
+        sh.q[t] = q;
+        sh.c[t] = cc;
+        sh.s[t] = ss;
+      }
+      __syncthreads();
+      for (int it = t; it < np * np; it += blockDim.x) {
+        const int k1 = it / np, k2 = it % np;
+        const double c1 = sh.c[k1], s1 = sh.s[k1], c2 = sh.c[k2], s2 = sh.s[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = sh.p[k1], q1 = sh.q[k1], p2 = sh.p[k2], q2 = sh.q[k2];
+        const double x00 = A[p1 * mp + p2], x01 = A[p1 * mp + q2];
+        const double x10 = A[q1 * mp + p2], x11 = A[q1 * mp + q2];
+        const double y00 = c1 * x00 - s1 * x10, y01 = c1 * x01 - s1 * x11;
+        const double y10 = s1 * x00 + c1 * x10, y11 = s1 * x01 + c1 * x11;
+        A[p1 * mp + p2] = c2 * y00 - s2 * y01;
+        A[q1 * mp + q2] = s2 * y10 + c2 * y11;
+        A[p1 * mp + q2] = (k1 == k2) ? 0.0 : s2 * y00 + c2 * y01;
+        A[q1 * mp + p2] = (k1 == k2) ? 0.0 : c2 * y10 - s2 * y11;
+      }
+      for (int it = t; it < mp * np; it += blockDim.x) {
+        const int i = it / np, k = it % np;
+        const double cc = sh.c[k], ss = sh.s[k];
+        if (ss == 0.0) continue;
+        const int p = sh.p[k], q = sh.q[k];
+        const double vp = V[i * mp + p], vq = V[i * mp + q];
+        V[i * mp + p] = cc * vp - ss * vq;
+        V[i * mp + q] = ss * vp + cc * vq;
+      }
+      __syncthreads();
+    }
+    const int done = !sh.rotated;
+    __syncthreads();
+    if (done) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-axis transform, one block per (GP, axis):
+//   T_e = V diag(lam) V^T;  M = diag(sqrt lam+) V^T S_e V diag(sqrt lam+) = U diag(D) U^T;
+//   B_e = V diag(sqrt lam+) U.
+// Work arrays: W0 (A of the first run, then S_e, then M), W1 (V), W2 (S V, then U).
+// Padding rows / columns (odd m_e) stay zero in A and identity in V and U.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(EIG_THREADS) void k_spec_axis(Tab tab,
+                                                           const SpecJob* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  const int e = lb;
+  const int m = J.m[e], mp = J.ldv[e];
+  const int mm = mp * mp;
+  double* __restrict__ W0 = J.W[e];
+  double* __restrict__ W1 = W0 + mm;
+  double* __restrict__ W2 = W1 + mm;
+  double* __restrict__ Bm = J.B[e];
+  const double* __restrict__ col = J.c64[e];
+  __shared__ JacobiShared sh;
+  __shared__ double sl[SPEC_MAXM];   // sqrt(max(lam, 0))
+  const int t = threadIdx.x;
+  for (int idx = t; idx < mm; idx += blockDim.x) {
+    const int i = idx / mp, j = idx % mp;
+    W0[idx] = (i < m && j < m) ? col[abs(i - j)] : 0.0;
+    W1[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_block(W0, W1, mp, sh);
+  for (int i = t; i < mp; i += blockDim.x) sl[i] = i < m ? sqrt(fmax(W0[i * mp + i], 0.0)) : 0.0;
+  __syncthreads();
+  // W0 = S_e: sum over cells c of G placed at nodes c..c+3, divided by the cell count
+  {
+    double G[4][4];
+    keys_gram(G);
+    const double inv = 1.0 / (double)(m - 3);
+    for (int idx = t; idx < mm; idx += blockDim.x) {
+      const int i = idx / mp, j = idx % mp;
+      double v = 0.0;
+      if (i < m && j < m && abs(i - j) <= 3) {
+        const int c0 = max(max(i, j) - 3, 0), c1 = min(min(i, j), m - 4);
+        for (int c = c0; c <= c1; ++c) v += G[i - c][j - c];
+      }
+      W0[idx] = v * inv;
+    }
+  }
+  __syncthreads();
+  // W2 = S_e V (S_e has bandwidth 3)
+  for (int idx = t; idx < mm; idx += blockDim.x) {
+    const int i = idx / mp, j = idx % mp;
+    double v = 0.0;
+    for (int k = max(i - 3, 0); k <= min(i + 3, mp - 1); ++k) v += W0[i * mp + k] * W1[k * mp + j];
+    W2[idx] = v;
+  }
+  __syncthreads();
+  // W0 = M = diag(sl) V^T (S_e V) diag(sl)
+  for (int idx = t; idx < mm; idx += blockDim.x) {
+    const int i = idx / mp, j = idx % mp;
+    double v = 0.0;
+    if (sl[i] > 0.0 && sl[j] > 0.0)
+      for (int k = 0; k < mp; ++k) v += W1[k * mp + i] * W2[k * mp + j];
+    W0[idx] = sl[i] * v * sl[j];
+  }
+  __syncthreads();
+  // symmetrise (the two products round differently) and start U = I
+  for (int idx = t; idx < mm; idx += blockDim.x) {
+    const int i = idx / mp, j = idx % mp;
+    if (i < j) {
+      const double v = 0.5 * (W0[i * mp + j] + W0[j * mp + i]);
+      W0[i * mp + j] = v;
+      W0[j * mp + i] = v;
+    }
+  }
+  for (int idx = t; idx < mm; idx += blockDim.x) W2[idx] = (idx / mp == idx % mp) ? 1.0 : 0.0;
+  __syncthreads();
+  jacobi_block(W0, W2, mp, sh);
+  for (int i = t; i < m; i += blockDim.x) J.D[e][i] = fmax(W0[i * mp + i], 0.0);
+  // B_e = V diag(sl) U
+  for (int idx = t; idx < mm; idx += blockDim.x) {
+    const int i = idx / mp, j = idx % mp;
+    double v = 0.0;
+    for (int k = 0; k < mp; ++k) v += W1[i * mp + k] * sl[k] * W2[k * mp + j];
+    Bm[idx] = v;
+  }
+}
+
+// pinv and z = 0 over the grid
+__global__ __launch_bounds__(SPB) void k_spec_prep(Tab tab, const SpecJob* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  const int64_t idx = (int64_t)lb * SPB + threadIdx.x;
+  if (idx >= J.mtot) return;
+  double dprod = 1.0;
+  int64_t rem = idx;
+  for (int e = 0; e < J.d; ++e) {
+    const int ie = (int)(rem / J.inner[e]);
+    rem -= (int64_t)ie * J.inner[e];
+    dprod *= J.D[e][ie];
+  }
+  J.pinv[idx] = 1.0 / (J.sigma2 + (double)J.n * dprod);
+  J.z[idx] = 0.0;
+}
+
+// partial sums of y^T y (column 3)
+__global__ __launch_bounds__(SPB) void k_spec_ynorm(Tab tab, const SpecJob* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  __shared__ double scr[16];
+  const int64_t r = (int64_t)lb * SPB + threadIdx.x;
+  const double v = r < J.n ? J.y[r] : 0.0;
+  const double s = block_sum(v * v, scr);
+  if (threadIdx.x == 0) J.part[(size_t)lb * SPW + 3] = s;
+}
+
+// One axis pass: out[o, i, in] = sum_j M[i][j] in[o, j, in] along `axis`
+// (M = B_e or B_e^T), with the mode's post-processing.
+__global__ __launch_bounds__(SPB) void k_spec_kron(Tab tab, const SpecJob* __restrict__ jobs,
+                                                   int axis, int mode, int src, int dst) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  if (!(mode & KP_FORCE) && J.ctl->cg_done) return;
+  const int me = J.m[axis], ld = J.ldv[axis];
+  const int64_t inner = J.inner[axis];
+  const int64_t idx = (int64_t)lb * SPB + threadIdx.x;
+  const bool live = idx < J.mtot;
+  double acc = 0.0;
+  if (live) {
+    const int64_t in_ = idx % inner;
+    const int64_t oi = idx / inner;
+    const int i = (int)(oi % me);
+    const int64_t base = (oi - i) * inner + in_;
+    const double* __restrict__ x = spec_buf(J, src) + base;
+    const double* __restrict__ Bm = J.B[axis];
+    if (mode & KP_FWD) {
+      for (int j = 0; j < me; ++j) acc += Bm[i * ld + j] * x[j * inner];
+    } else {
+      for (int j = 0; j < me; ++j) acc += Bm[j * ld + i] * x[j * inner];
+    }
+    if (mode & KP_ADD_SP) acc += J.sigma2 * J.p[idx];
+    spec_buf(J, dst)[idx] = acc;
+  }
+  if (mode & KP_DOT_P) {
+    __shared__ double scr[16];
+    const double v = live ? J.p[idx] * acc : 0.0;
+    const double s = block_sum(v, scr);
+    if (threadIdx.x == 0) J.part[(size_t)lb * SPW + 0] = s;
+  }
+}
+
+// init = 0: gamma = rz / p^T q (column 0 summed in a fixed order by every
+// block), z += gamma p, r -= gamma q.  Then partial sums of r^T pinv r
+// (column 1) and r^T r (column 2).
+__global__ __launch_bounds__(SPB) void k_spec_update(Tab tab, const SpecJob* __restrict__ jobs,
+                                                     int init) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  if (J.ctl->cg_done) return;
+  __shared__ double scr[16];
+  __shared__ double s_pq;
+  if (!init) {
+    if (threadIdx.x < WAVE) {
+      const double s = spec_colsum(J.part, J.nbm, 0);
+      if (threadIdx.x == 0) s_pq = s;
+    }
+    __syncthreads();
+  }
+  const int64_t idx = (int64_t)lb * SPB + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if (idx < J.mtot) {
+    double rv = J.r[idx];
+    if (!init) {
+      const double gm = J.ctl->rz / s_pq;
+      J.z[idx] += gm * J.p[idx];
+      rv -= gm * J.q[idx];
+      J.r[idx] = rv;
+    }
+    rz = rv * J.pinv[idx] * rv;
+    rr = rv * rv;
+  }
+  const double srz = block_sum(rz, scr);
+  const double srr = block_sum(rr, scr);
+  if (threadIdx.x == 0) {
+    J.part[(size_t)lb * SPW + 1] = srz;
+    J.part[(size_t)lb * SPW + 2] = srr;
+  }
+}
+
+// Scalar step, one wave per GP: convergence, iteration limit, direction ratio.
+__global__ __launch_bounds__(WAVE) void k_spec_ep(Tab tab, const SpecJob* __restrict__ jobs,
+                                                  int init) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  Ctl* ctl = J.ctl;
+  if (ctl->cg_done) return;
+  const double rz = spec_colsum(J.part, J.nbm, 1);
+  const double rr = spec_colsum(J.part, J.nbm, 2);
+  const double yy = init ? spec_colsum(J.part, J.nbn, 3) : 0.0;
+  if (threadIdx.x != 0) return;
+  if (init) {
+    ctl->rr0 = yy;
+    ctl->cg_iters = 0;
+  } else {
+    ctl->cg_iters += 1;
+  }
+  ctl->rr = rr;
+  if (!isfinite(rr) || !isfinite(rz)) {
+    ctl->cg_done = 1;
+    ctl->status |= SF_NONFINITE;
+    return;
+  }
+  if (!(rr > J.tol2 * ctl->rr0)) {
+    ctl->cg_done = 1;
+    return;
+  }
+  if (!init && ctl->cg_iters >= J.maxit) {
+    ctl->cg_done = 1;
+    ctl->status |= SF_CG_NOCONV;
+    return;
+  }
+  ctl->ratio = init ? 0.0 : rz / ctl->rz;
+  ctl->rz = rz;
+}
+
+// p = pinv r + ratio p (p = pinv r on the first step)
+__global__ __launch_bounds__(SPB) void k_spec_dir(Tab tab, const SpecJob* __restrict__ jobs) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  if (J.ctl->cg_done) return;
+  const int64_t idx = (int64_t)lb * SPB + threadIdx.x;
+  if (idx >= J.mtot) return;
+  const double beta = J.ctl->ratio;
+  const double zr = J.pinv[idx] * J.r[idx];
+  J.p[idx] = beta == 0.0 ? zr : zr + beta * J.p[idx];
+}
+
+// a = u in the cache precision
+__global__ __launch_bounds__(SPB) void k_spec_store(Tab tab, const SpecJob* __restrict__ jobs,
+                                                    int src) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SpecJob& J = jobs[gp];
+  const int64_t idx = (int64_t)lb * SPB + threadIdx.x;
+  if (idx >= J.mtot) return;
+  const double v = spec_buf(J, src)[idx];
+  if (J.a_fp64) ((double*)J.a)[idx] = v;
+  else ((float*)J.a)[idx] = (float)v;
+}
+
+__global__ void k_spec_alldone(int G, const SpecJob* __restrict__ jobs, int* flag) {
+  __shared__ int all;
+  if (threadIdx.x == 0) all = 1;
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += blockDim.x)
+    if (!jobs[g].ctl->cg_done) atomicAnd(&all, 0);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = all;
+}
+
+}  // namespace
+
+bool spectral_mean_applies(const love_cache* c) {
+  if (c->d < 2) return false;
+  if (c->cfg.flags & (LOVE_FLAG_PLAIN_CG | LOVE_FLAG_MEAN_KRYLOV)) return false;
+  for (int e = 0; e < c->d; ++e)
+    if (c->mdim[e] > SPEC_MAXM) return false;
+  return true;
+}
+
+love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
+                          const std::vector<const double*>& y64, const std::vector<double*>& un,
+                          hipStream_t s) {
+  const int G = (int)cs.size();
+  const int d = cs[0]->d;
+  std::vector<SpecJob> jobs(G);
+  std::vector<int64_t> b_m(G), b_n(G), b_axis(G, d), b_one(G, 1), b_nodes(G);
+  std::vector<char*> mem(G, nullptr);
+  auto release = [&]() {
+    for (char* p : mem)
+      if (p) (void)hipFreeAsync(p, s);
+  };
+  for (int g = 0; g < G; ++g) {
+    love_cache* c = cs[g];
+    SpecJob J{};
+    J.g = make_grid<double>(c);
+    J.x = x64[g];
+    J.cell_start = c->cell_start;
+    J.y = y64[g];
+    J.n = c->n;
+    J.mtot = c->m;
+    J.d = d;
+    int64_t inner = 1;
+    for (int e = d - 1; e >= 0; --e) {
+      J.m[e] = c->mdim[e];
+      J.ldv[e] = (c->mdim[e] + 1) & ~1;
+      J.inner[e] = inner;
+      inner *= c->mdim[e];
+      J.c64[e] = (const double*)c->toep.ax[e].c64;
+    }
+    J.nbm = (int)cdiv(J.mtot, SPB);
+    J.nbn = (int)cdiv(J.n, SPB);
+    size_t nd = 0;
+    for (int e = 0; e < d; ++e) nd += 4 * (size_t)J.ldv[e] * J.ldv[e] + (size_t)J.ldv[e];
+    nd += 7 * (size_t)J.mtot + (size_t)std::max(J.nbm, J.nbn) * SPW;
+    if (hipMallocAsync((void**)&mem[g], nd * sizeof(double), s) != hipSuccess) {
+      release();
+      return LOVE_ENOMEM;
+    }
+    double* q = (double*)mem[g];
+    for (int e = 0; e < d; ++e) {
+      const size_t l2 = (size_t)J.ldv[e] * J.ldv[e];
+      J.B[e] = q;
+      J.W[e] = q + l2;
+      J.D[e] = q + 4 * l2;
+      q = J.D[e] + J.ldv[e];
+    }
+    J.pinv = q;
+    J.z = J.pinv + J.mtot;
+    J.r = J.z + J.mtot;
+    J.p = J.r + J.mtot;
+    J.q = J.p + J.mtot;
+    J.t0 = J.q + J.mtot;
+    J.t1 = J.t0 + J.mtot;
+    J.part = J.t1 + J.mtot;
+    J.un = un[g];
+    J.sigma2 = c->cfg.noise;
+    const double tol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
+    J.tol2 = tol * tol * c->cfg.noise;
+    J.maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
+    J.ctl = c->ctl;
+    J.a = c->a;
+    J.a_fp64 = c->fp64 ? 1 : 0;
+    jobs[g] = J;
+    b_m[g] = J.nbm;
+    b_n[g] = J.nbn;
+    b_nodes[g] = cdiv(J.mtot, 4);
+  }
+  // W u and W^T v jobs (double)
+  std::vector<GatherJob<double>> ga(G);
+  std::vector<ScatterJob<double>> sy(G), su(G);
+  for (int g = 0; g < G; ++g) {
+    const SpecJob& J = jobs[g];
+    GatherJob<double> Ga{};
+    Ga.g = J.g;
+    Ga.x = J.x;
+    Ga.n = J.n;
+    Ga.kg = (d & 1) ? J.t0 : J.t1;   // output of the last forward pass
+    Ga.out = J.un;
+    Ga.ctl = J.ctl;
+    ga[g] = Ga;
+    ScatterJob<double> S{};
+    S.g = J.g;
+    S.x = J.x;
+    S.cell_start = J.cell_start;
+    S.v = J.y;
+    S.out = J.t0;
+    S.ctl = J.ctl;
+    sy[g] = S;
+    S.v = J.un;
+    su[g] = S;
+  }
+  JobArena A;
+  const size_t o_j = A.add(jobs), o_ga = A.add(ga), o_sy = A.add(sy), o_su = A.add(su);
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) {
+    release();
+    return st;
+  }
+  const SpecJob* dj = A.at<SpecJob>(o_j);
+  const Tab t_m = make_tab(b_m), t_n = make_tab(b_n), t_axis = make_tab(b_axis),
+            t_one = make_tab(b_one), t_nodes = make_tab(b_nodes);
+  const unsigned nbm = tab_blocks(t_m), nbn = tab_blocks(t_n);
+
+  // B^T applied to t0 (d passes ending in `dst`), with `last` mode bits
+  auto backward_passes = [&](int dst, int last) {
+    int src = SB_T0;
+    for (int e = 0; e < d; ++e) {
+      const bool fin = e == d - 1;
+      const int out = fin ? dst : (src == SB_T0 ? SB_T1 : SB_T0);
+      tlaunch("spec_kron", k_spec_kron, nbm, SPB, 0, s, t_m, dj, e, fin ? last : 0, src, out);
+      src = out;
+    }
+  };
+  // B applied to `src` (d passes ending in t0 for odd d, t1 for even d)
+  auto forward_passes = [&](int src, int extra) {
+    int in = src;
+    for (int e = 0; e < d; ++e) {
+      const int out = (e & 1) ? SB_T1 : SB_T0;
+      tlaunch("spec_kron", k_spec_kron, nbm, SPB, 0, s, t_m, dj, e, KP_FWD | extra, in, out);
+      in = out;
+    }
+  };
+
+  ProfScope ps("mean_spectral", s);
+  k_spec_axis<<<tab_blocks(t_axis), EIG_THREADS, 0, s>>>(t_axis, dj);
+  k_spec_prep<<<nbm, SPB, 0, s>>>(t_m, dj);
+  k_spec_ynorm<<<nbn, SPB, 0, s>>>(t_n, dj);
+  // r = b = B^T W^T y ; p = pinv r
+  launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_sy), d, 0, 2, s);
+  backward_passes(SB_R, 0);
+  k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 1);
+  k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 1);
+  k_spec_dir<<<nbm, SPB, 0, s>>>(t_m, dj);
+  int* dflag = nullptr;
+  if (hipMallocAsync((void**)&dflag, sizeof(int), s) != hipSuccess) {
+    A.release(s);
+    release();
+    return LOVE_ENOMEM;
+  }
+  int maxit = 0;
+  for (const auto& J : jobs) maxit = std::max(maxit, J.maxit);
+  const int chunk = 8;
+  int it = 0, hflag = 0;
+  while (it < maxit) {
+    for (int qn = 0; qn < chunk && it < maxit; ++qn, ++it) {
+      forward_passes(SB_P, 0);
+      launch_gather<double>(t_n, A.at<GatherJob<double>>(o_ga), d, 2, s);
+      launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_su), d, 0, 2, s);
+      backward_passes(SB_Q, KP_ADD_SP | KP_DOT_P);
+      k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 0);
+      k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 0);
+      k_spec_dir<<<nbm, SPB, 0, s>>>(t_m, dj);
+    }
+    k_spec_alldone<<<1, 64, 0, s>>>(G, dj, dflag);
+    if (hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      hflag = -1;
+      break;
+    }
+    if (hflag) break;
+  }
+  (void)hipFreeAsync(dflag, s);
+  if (hflag >= 0) {
+    // a = B z
+    forward_passes(SB_Z, KP_FORCE);
+    k_spec_store<<<nbm, SPB, 0, s>>>(t_m, dj, (d & 1) ? SB_T0 : SB_T1);
+  }
+  A.release(s);
+  release();
+  if (hflag < 0) return LOVE_EHIP;
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+}  // namespace love

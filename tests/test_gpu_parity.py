@@ -315,6 +315,95 @@ def test_config4_matern_small():
 
 
 # ---------------------------------------------------------------------------
+# Mean cache on 2-D .. 4-D grids: grid-space solve (B = kron(V_e) diag(sqrt lam))
+# ---------------------------------------------------------------------------
+SF_CG_NOCONV = 16
+
+
+def test_grid_space_mean_2d_mid():
+    """64 x 64 grid, 5e4 points, the 2-D precision-form kernel: the grid-space
+    solve converges in tens of iterations (the oracle's plain CG needs ~4800)
+    and matches the oracle's mean (its CG run to 1e-10, checked converged)."""
+    P = WL.make_problem("c3_mid", d=2, n=50_000, m=(64, 64), kernel="rbf",
+                        lengthscale=(0.05, 0.08), noise=0.0025, k=50, t=4000,
+                        target="sincos4", ynoise=0.05)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P)
+    info = cache.info()
+    print("cg_iters", info.cg_iters, "status", info.status_flags, flush=True)
+    assert not (info.status_flags & SF_CG_NOCONV)
+    assert 0 < info.cg_iters < 100
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float32))
+    # the oracle's plain CG needs ~4800 iterations here
+    oc = O.love_build(P.x.astype(np.float64), P.y.astype(np.float64), spec_of(P), P.k,
+                      cg_tol=1e-10, cg_maxit=20000)
+    assert oc.cg_iters < 20000
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(var), v_ref, O.prior_var(P.xs, spec_of(P)), host(mu), m_ref, P.y)
+    print(e, "oracle cg", oc.cg_iters, flush=True)
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    assert e["e_p_max"] <= 1e-5
+    cache.free()
+
+
+def test_grid_space_mean_3d():
+    """Odd d (the axis passes end in the other buffer): 12^3 grid, 2e4 points,
+    mean and variance against the oracle."""
+    P = WL.make_problem("d3", d=3, n=20_000, m=(12, 12, 12), kernel="rbf",
+                        lengthscale=(0.15, 0.2, 0.25), noise=0.01, k=40, t=3000,
+                        target="sumsin", ynoise=0.1)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P)
+    info = cache.info()
+    print("cg_iters", info.cg_iters, "status", info.status_flags, flush=True)
+    assert not (info.status_flags & SF_CG_NOCONV)
+    assert 0 < info.cg_iters < 100
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float32))
+    oc = oracle_cache(P)
+    assert oc.cg_iters < 5000
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(var), v_ref, O.prior_var(P.xs, spec_of(P)), host(mu), m_ref, P.y)
+    print(e, flush=True)
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    assert e["e_p_max"] <= 1e-5
+    cache.free()
+
+
+@pytest.mark.parametrize("case", ["2d", "4d", "4d_sparse"])
+def test_grid_space_mean_equals_data_space_cg(case):
+    """The two mean solvers (grid space by default for d >= 2, data-space CG on
+    request) give the same predictive mean on reduced 2-D and 4-D workloads;
+    4d_sparse has about 1.5 points per grid node.  The grid-space solve takes
+    fewer iterations in each case."""
+    if case == "2d":
+        P = WL.make_problem("c3_red", d=2, n=20_000, m=(24, 24), kernel="rbf",
+                            lengthscale=(0.05, 0.08), noise=0.0025, k=50, t=2000,
+                            target="sincos4", ynoise=0.05)
+    elif case == "4d":
+        P = WL.make_problem("c4_red", d=4, n=60_000, m=(9,) * 4, kernel="matern52",
+                            lengthscale=(0.2,) * 4, noise=0.01, k=64, t=2000,
+                            target="sumsin", ynoise=0.1)
+    else:
+        P = WL.config(4, scale=0.05)
+    print(P.name, P.n, P.m, flush=True)
+    assert P.n >= int(np.prod(P.m)) > P.k
+    xs = tdev(P.xs[:2000], torch.float32)
+    c1 = build(P)
+    c2 = build(P, flags=B.FLAG_MEAN_KRYLOV, cg_maxit=20000)   # needs > 1000 steps in 2-D
+    i1, i2 = c1.info(), c2.info()
+    print("iters grid", i1.cg_iters, "data", i2.cg_iters, flush=True)
+    assert not (i1.status_flags & SF_CG_NOCONV) and not (i2.status_flags & SF_CG_NOCONV)
+    m1, v1 = c1.predict_mean_var(xs)
+    m2, v2 = c2.predict_mean_var(xs)
+    assert i1.cg_iters < min(100, i2.cg_iters)
+    rms = float(np.sqrt(np.mean(P.y.astype(np.float64) ** 2)))
+    assert float(np.max(np.abs(host(m1) - host(m2)))) / rms <= 1e-4
+    assert torch.equal(v1, v2)      # the variance cache does not depend on the mean solver
+    c1.free()
+    c2.free()
+
+
+# ---------------------------------------------------------------------------
 # Backward
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("cfgi,scale", [(1, 1.0), (4, 0.01)])
