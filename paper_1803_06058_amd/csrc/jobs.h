@@ -194,7 +194,6 @@ struct SpecJob {
   int64_t inner[MAXD];        // product of m over later axes
   const double* c64[MAXD];    // first column of T_e (outputscale folded into axis 0)
   double* B[MAXD];            // B_e, ldv x ldv (row: grid node, column: mode)
-  double* W[MAXD];            // three ldv x ldv work matrices per axis
   double* D[MAXD];            // D_e
   double* pinv;               // mtot: 1 / (sigma^2 + n prod_e D_e)
   double *z, *r, *p, *q, *t0, *t1;   // mtot

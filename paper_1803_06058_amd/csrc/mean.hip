@@ -87,23 +87,25 @@ __device__ inline void keys_gram(double G[4][4]) {
   }
 }
 
+constexpr int HALF = SPEC_MAXM / 2;   // largest half problem
+
 struct JacobiShared {
-  double c[SPEC_MAXM / 2], s[SPEC_MAXM / 2];
-  int p[SPEC_MAXM / 2], q[SPEC_MAXM / 2];
+  double c[HALF / 2], s[HALF / 2];
+  int p[HALF / 2], q[HALF / 2];
   double scr[16];
   int rotated;
 };
 
-// Symmetric A (mp x mp, mp even, row-major) -> diag by cyclic parallel Jacobi;
-// V <- V J accumulates the rotations.  Each round applies mp/2 disjoint
-// rotations (circle-method pairing): A <- J^T A J one 2 x 2 block per item.
-// Sweeps stop once a whole sweep finds every |a_pq| <= 1e-17 ||A||_F
-// (at most 40 sweeps).  Whole block; ends with a barrier.
-__device__ void jacobi_block(double* __restrict__ A, double* __restrict__ V, int mp,
-                             JacobiShared& sh) {
-  const int t = threadIdx.x, np = mp / 2;
+// Symmetric A (mp x mp, mp even, row-major, LDS) -> diag by cyclic parallel
+// Jacobi; V (LDS) <- V J accumulates the rotations.  Each round applies mp/2
+// disjoint rotations (circle-method pairing): A <- J^T A J one 2 x 2 block per
+// item, and every row of V mixes its column pairs.  Sweeps stop once a whole
+// sweep finds every |a_pq| <= 1e-17 ||A||_F (at most 40).  Whole block; ends
+// with a barrier.
+__device__ void jacobi_block(double* A, double* V, int mp, JacobiShared& sh) {
+  const int t = threadIdx.x, np = mp / 2, nt = blockDim.x;
   double fro = 0.0;
-  for (int idx = t; idx < mp * mp; idx += blockDim.x) fro += A[idx] * A[idx];
+  for (int idx = t; idx < mp * mp; idx += nt) fro += A[idx] * A[idx];
   fro = block_sum(fro, sh.scr);
   const double thr = 1e-17 * sqrt(fro);
   __syncthreads();
@@ -137,7 +139,7 @@ __device__ void jacobi_block(double* __restrict__ A, double* __restrict__ V, int
         sh.s[t] = ss;
       }
       __syncthreads();
-      for (int it = t; it < np * np; it += blockDim.x) {
+      for (int it = t; it < np * np; it += nt) {
         const int k1 = it / np, k2 = it % np;
         const double c1 = sh.c[k1], s1 = sh.s[k1], c2 = sh.c[k2], s2 = sh.s[k2];
         if (s1 == 0.0 && s2 == 0.0) continue;
@@ -151,7 +153,7 @@ __device__ void jacobi_block(double* __restrict__ A, double* __restrict__ V, int
         A[p1 * mp + q2] = (k1 == k2) ? 0.0 : s2 * y00 + c2 * y01;
         A[q1 * mp + p2] = (k1 == k2) ? 0.0 : c2 * y10 - s2 * y11;
       }
-      for (int it = t; it < mp * np; it += blockDim.x) {
+      for (int it = t; it < mp * np; it += nt) {
         const int i = it / np, k = it % np;
         const double cc = sh.c[k], ss = sh.s[k];
         if (ss == 0.0) continue;
@@ -168,90 +170,123 @@ __device__ void jacobi_block(double* __restrict__ A, double* __restrict__ V, int
   }
 }
 
+// Entry (i, j) of S_e: sum over cells c of G[i - c][j - c], over the cell count.
+__device__ inline double s_entry(const double (&G)[4][4], int m, int i, int j) {
+  if (abs(i - j) > 3) return 0.0;
+  const int c0 = max(max(i, j) - 3, 0), c1 = min(min(i, j), m - 4);
+  double v = 0.0;
+  for (int c = c0; c <= c1; ++c) v += G[i - c][j - c];
+  return v / (double)(m - 3);
+}
+
+// Entry (i, j) of X restricted to parity pi (0 even, 1 odd) for a centrosymmetric
+// m x m matrix X (X[m-1-i][m-1-j] = X[i][j]): in the basis (e_i +- e_{m-1-i})/sqrt 2,
+// i < m/2, plus e_mid (odd m, even part, index m/2) the matrix splits into
+// X_pi[i][j] = X[i][j] +- X[i][m-1-j], X_+[i][mid] = sqrt2 X[i][mid], X_+[mid][mid] = X[mid][mid].
+template <typename F>
+__device__ inline double half_entry(F X, int m, int pi, int i, int j) {
+  const int h = m / 2;
+  const bool odd = m & 1;
+  if (pi == 0 && odd) {
+    const int mid = h;
+    if (i == h && j == h) return X(mid, mid);
+    if (i == h) return sqrt(2.0) * X(j, mid);
+    if (j == h) return sqrt(2.0) * X(i, mid);
+  }
+  return X(i, j) + (pi == 0 ? 1.0 : -1.0) * X(i, m - 1 - j);
+}
+
 // ---------------------------------------------------------------------------
-// Per-axis transform, one block per (GP, axis):
-//   T_e = V diag(lam) V^T;  M = diag(sqrt lam+) V^T S_e V diag(sqrt lam+) = U diag(D) U^T;
-//   B_e = V diag(sqrt lam+) U.
-// Work arrays: W0 (A of the first run, then S_e, then M), W1 (V), W2 (S V, then U).
-// Padding rows / columns (odd m_e) stay zero in A and identity in V and U.
+// Per-axis transform, one block per (GP, axis, parity).  T_e and S_e are
+// centrosymmetric (Toeplitz; a cell sum of the Keys Gram matrix, which is
+// invariant under s -> 1 - s), so both split into an even and an odd half of
+// size <= 64.  For each half (all in LDS):
+//   T_pi = V diag(lam) V^T;  M = diag(sqrt lam+) V^T S_pi V diag(sqrt lam+) = U diag(D) U^T;
+//   B_pi = V diag(sqrt lam+) U.
+// B_e has the even modes in columns [0, n_even) and the odd ones after them;
+// its rows expand each half back to the grid: row r takes B_pi[min(r, m-1-r)] / sqrt 2,
+// negated on the mirrored row of the odd half, and row mid of the even half as is.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(EIG_THREADS) void k_spec_axis(Tab tab,
                                                            const SpecJob* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const SpecJob& J = jobs[gp];
-  const int e = lb;
-  const int m = J.m[e], mp = J.ldv[e];
-  const int mm = mp * mp;
-  double* __restrict__ W0 = J.W[e];
-  double* __restrict__ W1 = W0 + mm;
-  double* __restrict__ W2 = W1 + mm;
-  double* __restrict__ Bm = J.B[e];
+  const int e = lb >> 1, pi = lb & 1;
+  const int m = J.m[e], ld = J.ldv[e], h = m / 2;
+  const bool odd = m & 1;
+  const int nh = (pi == 0) ? h + (odd ? 1 : 0) : h;   // size of this half
+  const int mp = (nh + 1) & ~1;
+  const int off = pi == 0 ? 0 : h + (odd ? 1 : 0);     // first mode column
   const double* __restrict__ col = J.c64[e];
+  __shared__ double A[HALF * HALF], V[HALF * HALF], W[HALF * HALF];
   __shared__ JacobiShared sh;
-  __shared__ double sl[SPEC_MAXM];   // sqrt(max(lam, 0))
+  __shared__ double sl[HALF];   // sqrt(max(lam, 0))
   const int t = threadIdx.x;
+  const int mm = mp * mp;
+  auto tx = [&](int i, int j) { return col[abs(i - j)]; };
   for (int idx = t; idx < mm; idx += blockDim.x) {
     const int i = idx / mp, j = idx % mp;
-    W0[idx] = (i < m && j < m) ? col[abs(i - j)] : 0.0;
-    W1[idx] = (i == j) ? 1.0 : 0.0;
+    A[idx] = (i < nh && j < nh) ? half_entry(tx, m, pi, i, j) : 0.0;
+    V[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_block(W0, W1, mp, sh);
-  for (int i = t; i < mp; i += blockDim.x) sl[i] = i < m ? sqrt(fmax(W0[i * mp + i], 0.0)) : 0.0;
+  jacobi_block(A, V, mp, sh);
+  for (int i = t; i < mp; i += blockDim.x) sl[i] = i < nh ? sqrt(fmax(A[i * mp + i], 0.0)) : 0.0;
   __syncthreads();
-  // W0 = S_e: sum over cells c of G placed at nodes c..c+3, divided by the cell count
-  {
-    double G[4][4];
-    keys_gram(G);
-    const double inv = 1.0 / (double)(m - 3);
-    for (int idx = t; idx < mm; idx += blockDim.x) {
-      const int i = idx / mp, j = idx % mp;
-      double v = 0.0;
-      if (i < m && j < m && abs(i - j) <= 3) {
-        const int c0 = max(max(i, j) - 3, 0), c1 = min(min(i, j), m - 4);
-        for (int c = c0; c <= c1; ++c) v += G[i - c][j - c];
-      }
-      W0[idx] = v * inv;
-    }
-  }
-  __syncthreads();
-  // W2 = S_e V (S_e has bandwidth 3)
+  double G[4][4];
+  keys_gram(G);
+  auto sx = [&](int i, int j) { return s_entry(G, m, i, j); };
+  // W = S_pi V
   for (int idx = t; idx < mm; idx += blockDim.x) {
     const int i = idx / mp, j = idx % mp;
     double v = 0.0;
-    for (int k = max(i - 3, 0); k <= min(i + 3, mp - 1); ++k) v += W0[i * mp + k] * W1[k * mp + j];
-    W2[idx] = v;
+    if (i < nh)
+      for (int k = 0; k < nh; ++k) v += half_entry(sx, m, pi, i, k) * V[k * mp + j];
+    W[idx] = v;
   }
   __syncthreads();
-  // W0 = M = diag(sl) V^T (S_e V) diag(sl)
+  // A = M = diag(sl) V^T W diag(sl), symmetrised (the two products round differently)
   for (int idx = t; idx < mm; idx += blockDim.x) {
     const int i = idx / mp, j = idx % mp;
-    double v = 0.0;
+    if (i > j) continue;
+    double v = 0.0, w = 0.0;
     if (sl[i] > 0.0 && sl[j] > 0.0)
-      for (int k = 0; k < mp; ++k) v += W1[k * mp + i] * W2[k * mp + j];
-    W0[idx] = sl[i] * v * sl[j];
+      for (int k = 0; k < mp; ++k) {
+        v += V[k * mp + i] * W[k * mp + j];
+        w += V[k * mp + j] * W[k * mp + i];
+      }
+    const double a = 0.5 * sl[i] * (v + w) * sl[j];
+    A[i * mp + j] = a;
+    A[j * mp + i] = a;
   }
   __syncthreads();
-  // symmetrise (the two products round differently) and start U = I
-  for (int idx = t; idx < mm; idx += blockDim.x) {
-    const int i = idx / mp, j = idx % mp;
-    if (i < j) {
-      const double v = 0.5 * (W0[i * mp + j] + W0[j * mp + i]);
-      W0[i * mp + j] = v;
-      W0[j * mp + i] = v;
-    }
-  }
-  for (int idx = t; idx < mm; idx += blockDim.x) W2[idx] = (idx / mp == idx % mp) ? 1.0 : 0.0;
+  for (int idx = t; idx < mm; idx += blockDim.x) W[idx] = (idx / mp == idx % mp) ? 1.0 : 0.0;
   __syncthreads();
-  jacobi_block(W0, W2, mp, sh);
-  for (int i = t; i < m; i += blockDim.x) J.D[e][i] = fmax(W0[i * mp + i], 0.0);
-  // B_e = V diag(sl) U
+  jacobi_block(A, W, mp, sh);
+  for (int j = t; j < nh; j += blockDim.x) J.D[e][off + j] = fmax(A[j * mp + j], 0.0);
+  // A = B_pi = V diag(sl) U (A's diagonal has been read)
+  __syncthreads();
   for (int idx = t; idx < mm; idx += blockDim.x) {
     const int i = idx / mp, j = idx % mp;
     double v = 0.0;
-    for (int k = 0; k < mp; ++k) v += W1[i * mp + k] * sl[k] * W2[k * mp + j];
-    Bm[idx] = v;
+    for (int k = 0; k < mp; ++k) v += V[i * mp + k] * sl[k] * W[k * mp + j];
+    A[idx] = v;
+  }
+  __syncthreads();
+  // expand to the grid rows of B_e
+  const double rs2 = sqrt(0.5);
+  for (int idx = t; idx < m * nh; idx += blockDim.x) {
+    const int r = idx / nh, j = idx % nh;
+    double v;
+    if (odd && r == h) {
+      v = pi == 0 ? A[h * mp + j] : 0.0;
+    } else {
+      const int i = min(r, m - 1 - r);
+      v = A[i * mp + j] * rs2;
+      if (pi == 1 && r != i) v = -v;
+    }
+    J.B[e][(size_t)r * ld + off + j] = v;
   }
 }
 
@@ -449,7 +484,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
   const int G = (int)cs.size();
   const int d = cs[0]->d;
   std::vector<SpecJob> jobs(G);
-  std::vector<int64_t> b_m(G), b_n(G), b_axis(G, d), b_one(G, 1), b_nodes(G);
+  std::vector<int64_t> b_m(G), b_n(G), b_axis(G, 2 * d), b_one(G, 1), b_nodes(G);
   std::vector<char*> mem(G, nullptr);
   auto release = [&]() {
     for (char* p : mem)
@@ -476,7 +511,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     J.nbm = (int)cdiv(J.mtot, SPB);
     J.nbn = (int)cdiv(J.n, SPB);
     size_t nd = 0;
-    for (int e = 0; e < d; ++e) nd += 4 * (size_t)J.ldv[e] * J.ldv[e] + (size_t)J.ldv[e];
+    for (int e = 0; e < d; ++e) nd += (size_t)J.ldv[e] * J.ldv[e] + (size_t)J.ldv[e];
     nd += 7 * (size_t)J.mtot + (size_t)std::max(J.nbm, J.nbn) * SPW;
     if (hipMallocAsync((void**)&mem[g], nd * sizeof(double), s) != hipSuccess) {
       release();
@@ -486,8 +521,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     for (int e = 0; e < d; ++e) {
       const size_t l2 = (size_t)J.ldv[e] * J.ldv[e];
       J.B[e] = q;
-      J.W[e] = q + l2;
-      J.D[e] = q + 4 * l2;
+      J.D[e] = q + l2;
       q = J.D[e] + J.ldv[e];
     }
     J.pinv = q;
