@@ -404,6 +404,43 @@ def test_grid_space_mean_equals_data_space_cg(case):
 
 
 # ---------------------------------------------------------------------------
+# Accuracy against the number of Lanczos steps (Sec. 6, accuracy vs. Lanczos
+# iterations): exponential decrease, then a floor set by float rounding
+# ---------------------------------------------------------------------------
+def test_error_vs_lanczos_steps():
+    """1-D, n = 2e4, m = 1000 (lengthscale 20 grid spacings): SMAE of the FP32
+    GPU variances against the exact KISS-GP variances (route B) for k = 10 ..
+    120.  The error never grows with k, falls by more than 1e4 between k = 20
+    and k = 80, reaches the FP32 floor by k = 100, and follows the FP64 oracle's
+    LOVE at the same k while the truncation error dominates."""
+    P = WL.make_problem("err_vs_k", d=1, n=20_000, m=(1000,), kernel="rbf", lengthscale=(0.02,),
+                        noise=0.01, k=100, t=2000, target="sin6_40", ynoise=0.1)
+    X, y, xs = (a.astype(np.float64) for a in (P.x, P.y, P.xs))
+    _, v_ex = O.exact_route_B(X, y, xs, spec_of(P))
+    prior = O.prior_var(xs, spec_of(P))
+    xs_d = tdev(P.xs, torch.float32)
+    rows = []
+    for k in (10, 20, 40, 60, 80, 100, 120):
+        c = build(P, k=k)
+        _, v = c.predict_mean_var(xs_d)
+        vg = host(v)
+        c.free()
+        oc = O.love_build(X, y, spec_of(P), k, cg_tol=1e-8, cg_maxit=3000)
+        _, vo = O.love_predict(oc, xs)
+        rows.append((k, O.smae(vg, v_ex, y), O.smae(vo, v_ex, y),
+                     float(np.max(np.abs(vg - v_ex) / prior))))
+        print("k %3d  smae gpu %.3e  oracle %.3e  e_p max %.3e" % rows[-1], flush=True)
+    sm = [r[1] for r in rows]
+    for a, b in zip(sm, sm[1:]):
+        assert b <= a * 1.05 + 1e-7
+    assert sm[1] >= 1e4 * sm[4]
+    assert rows[5][3] <= 1e-5 and rows[6][3] <= 1e-5
+    for k, sg, so, _ in rows:
+        if so > 1e-4:
+            assert abs(sg - so) <= 1e-2 * so
+
+
+# ---------------------------------------------------------------------------
 # Backward
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("cfgi,scale", [(1, 1.0), (4, 0.01)])
