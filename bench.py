@@ -281,6 +281,48 @@ def batched_section(B, WL, torch, dev):
             "k_eff_equal": kb == ks}
 
 
+def mvm_large_section(B, torch, dev, n=1 << 25, reps=10):
+    """One Khat v product (scatter W^T, banded Toeplitz, gather W + sigma^2)
+    at 2^25 training points of the 1-D kernel (m = 1e4): large enough for the
+    product to be bound by HBM rather than by launch latency.  The cache is
+    built with k = 2 and no mean (only its sorted rows and plan are used).
+    `us` is the product's kernels (event-timed); `apply_khat_call_us` adds the
+    two permutations between the caller's row order and the sorted one."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    x = torch.rand(n, 1, device=dev, generator=gen)
+    y = torch.sin(6 * math.pi * x[:, 0])
+    cfg = B.config_struct(1, [10000], [0.0], [1.0], kernel="rbf", lengthscale=[0.02], noise=0.01,
+                          k=2, precision="fp32", flags=B.FLAG_NO_MEAN)
+    c = B.build_cache(cfg, x, y)
+    v = torch.randn(n, device=dev, generator=gen)
+    for _ in range(3):
+        c.apply_khat(v)
+    torch.cuda.synchronize()
+    # the product's own kernels (the Lanczos runs these in the sorted row order),
+    # event-timed on their launch stream
+    B.profile_select(["scatter", "toeplitz", "gather"])
+    B.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.apply_khat(v)
+    e1.record()
+    torch.cuda.synchronize()
+    mv = B.profile_read(["scatter", "toeplitz", "gather"])
+    B.profile_enable(False)
+    B.profile_select(None)
+    call_us = e0.elapsed_time(e1) * 1e3 / reps
+    us = sum(mv[k_][1] for k_ in mv) * 1e3 / reps
+    c.free()
+    alg = 4 * n * 2 + 4 * n * 3 + 16 * 10000   # x twice, v twice, out; grid vectors
+    gbps = alg / (us * 1e-6) / 1e9
+    return {"n": n, "m": 10000, "us": round(us, 1), "alg_bytes": alg, "alg_gbps": round(gbps, 1),
+            "frac_hbm": round(gbps / HBM_PEAK_GBS, 3),
+            "per_kernel_us": {k_: round(mv[k_][1] * 1e3 / reps, 1) for k_ in mv},
+            "apply_khat_call_us": round(call_us, 1)}
+
+
 def forms_section(B, WL, torch, dev, reps=3):
     """The other forms of the path at their full sizes, timed on this GPU (median
     of `reps` after one warm-up, host clock around synchronised calls):
@@ -518,6 +560,7 @@ def main():
         out["batched"] = batched_section(B, WL, torch, dev)
     if not a.no_forms:
         out["forms"] = forms_section(B, WL, torch, dev)
+        out["mvm_large"] = mvm_large_section(B, torch, dev)
     if not a.no_cpu_baseline:
         base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries)
         out["cpu_baseline"] = base

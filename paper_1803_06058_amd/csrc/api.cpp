@@ -318,6 +318,10 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   S.cell_start = c->cell_start;
   S.v = (const T*)c->v1;
   S.out = (T*)c->g1;
+  void* cellp = nullptr;
+  const size_t cb = scatter_scratch_bytes(c, sizeof(T));
+  if (cb) LOVE_HIP_TRY(hipMallocAsync(&cellp, cb, s));
+  S.cellp = (T*)cellp;
   GatherJob<T> Ga{};
   Ga.g = S.g;
   Ga.x = S.x;
@@ -331,13 +335,17 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   ToepRun<T> run;
   toep_prepare<T>(A, run, one, {(const T*)c->g1}, {0}, {(T*)c->g2}, {0}, {(T*)c->tscr}, {nullptr});
   love_status st = A.upload(s);
-  if (st != LOVE_OK) return st;
+  if (st != LOVE_OK) {
+    if (cellp) (void)hipFreeAsync(cellp, s);
+    return st;
+  }
   launch_permute<T>(v, (T*)c->v1, c->perm, c->n, 0, s);
   launch_scatter<T>(tab1(cdiv(c->m, 4)), A.at<ScatterJob<T>>(os), c->d, 0, 0, s);
   toep_run<T>(A, run, 0, 0, s);
   launch_gather<T>(tab1(cdiv(c->n, 256)), A.at<GatherJob<T>>(og), c->d, 0, s);
   launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);
   A.release(s);
+  if (cellp) (void)hipFreeAsync(cellp, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 

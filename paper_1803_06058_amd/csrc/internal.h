@@ -220,9 +220,11 @@ love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<con
 template <typename T>
 GridT<T> make_grid(const love_cache* c);
 
+// W^T v; for d >= 3 every job's cellp must hold scatter_scratch_bytes(c, sizeof(T))
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
                     hipStream_t s);
+size_t scatter_scratch_bytes(const love_cache* c, size_t elem);
 template <typename T>
 void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s);
 template <typename T>
@@ -250,11 +252,12 @@ love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t 
 // most SPEC_MAXM points, no flag asking for the data-space CG)
 bool spectral_mean_applies(const love_cache* c);
 // a = K W^T Khat^{-1} y for every GP of the batch; x64 / y64: sorted training
-// data in double, un: n doubles of scratch per GP; sets ctl->cg_iters and the
+// data in double, un: n doubles of scratch per GP, cellp: the scatter scratch
+// (scatter_scratch_bytes, double); sets ctl->cg_iters and the
 // CG status bits.  Synchronises `s` every few iterations.
 love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
                           const std::vector<const double*>& y64, const std::vector<double*>& un,
-                          hipStream_t s);
+                          const std::vector<double*>& cellp, hipStream_t s);
 
 // --- queries (query.hip) -----------------------------------------------------
 template <typename T>

@@ -47,6 +47,7 @@ struct ScatterJob {
   T* out;                     // m
   int64_t out_js;
   const Ctl* ctl;
+  T* cellp;                   // d >= 3: 4^d x ctot partial products (scatter_scratch_bytes)
 };
 
 // out = W kg + sigma2 * vsig (vsig nullable)

@@ -1835,6 +1835,7 @@ struct GpBufs {
          *cdvec = nullptr;
   int nbg = 0;
   int64_t rpbg = 0;
+  void* cellp = nullptr;   // scatter scratch for d >= 3 (sized for double)
   char* mem = nullptr;
 };
 
@@ -1857,7 +1858,9 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
                             2 * (size_t)m + (size_t)ts + (size_t)nb * LDP + 2 * LDP);
     if (!plain) db += sizeof(double) * ((size_t)b.nbg + 2) * kpad * kpad;
   }
-  LOVE_HIP_TRY(hipMallocAsync((void**)&b.mem, tb + db, s));
+  const size_t cb = (scatter_scratch_bytes(c, sizeof(double)) + 255) & ~size_t(255);
+  LOVE_HIP_TRY(hipMallocAsync((void**)&b.mem, tb + db + cb, s));
+  if (cb) b.cellp = b.mem + tb + db;
   T* t = (T*)b.mem;
   b.Q = t;   // Q and G first: their columns start on 16-byte boundaries
   if (b.ldg) {
@@ -1994,6 +1997,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     S.out = J.gpath ? b.G : b.gv;
     S.out_js = J.gpath ? b.ldg : 0;
     S.ctl = c->ctl;
+    S.cellp = (T*)b.cellp;
     sc[g] = S;
     GatherJob<T> Ga{};
     Ga.g = J.g;
@@ -2100,6 +2104,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       S.v2 = b.cp;
       S.out = b.cgv;
       S.ctl = c->ctl;
+      S.cellp = (double*)b.cellp;
       csc[g] = S;
       S.v = b.xs;
       S.v2 = nullptr;
@@ -2206,13 +2211,14 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     for (auto* c : cs) spec = spec && spectral_mean_applies(c);
     if (spec) {
       std::vector<const double*> sx(G), sy(G);
-      std::vector<double*> su(G);
+      std::vector<double*> su(G), scp(G);
       for (int g = 0; g < G; ++g) {
         sx[g] = bufs[g].x64;
         sy[g] = bufs[g].y64;
         su[g] = bufs[g].cz;
+        scp[g] = (double*)bufs[g].cellp;
       }
-      love_status ss = spectral_mean(cs, sx, sy, su, s);
+      love_status ss = spectral_mean(cs, sx, sy, su, scp, s);
       if (ss != LOVE_OK) {
         A.release(s);
         for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);

@@ -480,7 +480,7 @@ bool spectral_mean_applies(const love_cache* c) {
 
 love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
                           const std::vector<const double*>& y64, const std::vector<double*>& un,
-                          hipStream_t s) {
+                          const std::vector<double*>& cellp, hipStream_t s) {
   const int G = (int)cs.size();
   const int d = cs[0]->d;
   std::vector<SpecJob> jobs(G);
@@ -565,6 +565,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     S.v = J.y;
     S.out = J.t0;
     S.ctl = J.ctl;
+    S.cellp = cellp[g];
     sy[g] = S;
     S.v = J.un;
     su[g] = S;

@@ -155,16 +155,134 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
   if (lane == 0) J.out[(int64_t)j * J.out_js + u] = acc;
 }
 
+// ----------------------------------------------------------------------------
+// W^T v in two stages for d >= 3, where a row touches 4^d >= 64 nodes and a
+// cell holds few rows, so visiting every row once per node (above) repeats
+// each row 4^d times.  Stage 1, one lane per stencil cell c: the cell's rows
+// (contiguous in the sorted order) give the 4^d partial products
+//   P[o][c] = sum over rows of val * prod_e w_e[o_e],
+// stored offset-major so a wave writes consecutive cells.  Stage 2, one
+// thread per node u: out[u] = sum over o of P[o][c(u - o)] for the cells that
+// exist, o ascending.  Both summation orders are fixed: deterministic.
+// ----------------------------------------------------------------------------
+size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
+  if (c->d < 3) return 0;
+  return ((size_t)1 << (2 * c->d)) * (size_t)c->ctot * elem;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter_cells(Tab tab,
+                                                       const ScatterJob<T>* __restrict__ jobs,
+                                                       int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const GridT<T>& g = J.g;
+  const int64_t c = (int64_t)lb * 256 + threadIdx.x;
+  if (c >= g.ctot) return;
+  const T* __restrict__ x = J.x;
+  const T* __restrict__ v = J.v + (int64_t)j * J.v_js;
+  const T* __restrict__ v2 = J.v2;
+  const bool comb = (mode & 4) && v2;
+  const T ratio = comb ? (T)J.ctl->ratio : T(0);
+  const int32_t r0 = J.cell_start[c], r1 = J.cell_start[c + 1];
+  constexpr int NC = 1 << (2 * (D - 1));   // offsets per value of o_0
+  T* __restrict__ P = J.cellp;
+  const int64_t ctot = g.ctot;
+#pragma unroll 1
+  for (int o0 = 0; o0 < 4; ++o0) {
+    T acc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = T(0);
+    for (int32_t r = r0; r < r1; ++r) {
+      T w[D][4];
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        T sf;
+        (void)stencil_at(g, e, x[(int64_t)r * D + e], sf);
+        keys_weights<T>(sf, w[e]);
+      }
+      T val = v[r];
+      if (comb) val = (T)(v[r] + ratio * v2[r]);
+      const T a0 = val * w[0][o0];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        T prod = a0;
+#pragma unroll
+        for (int e = 1; e < D; ++e) prod *= w[e][(q >> (2 * (D - 1 - e))) & 3];
+        acc[q] += prod;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) P[(int64_t)(o0 * NC + q) * ctot + c] = acc[q];
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
+                                                       const ScatterJob<T>* __restrict__ jobs,
+                                                       int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const GridT<T>& g = J.g;
+  const int64_t u = (int64_t)lb * 256 + threadIdx.x;
+  if (u >= g.mtot) return;
+  int ue[D];
+  {
+    int64_t rem = u;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      ue[e] = (int)(rem / g.nstride[e]);
+      rem -= (int64_t)ue[e] * g.nstride[e];
+    }
+  }
+  constexpr int NO = 1 << (2 * D);
+  const T* __restrict__ P = J.cellp;
+  const int64_t ctot = g.ctot;
+  T acc = T(0);
+#pragma unroll 16
+  for (int o = 0; o < NO; ++o) {
+    int64_t cidx = 0;
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int ce = ue[e] - ((o >> (2 * (D - 1 - e))) & 3);
+      ok = ok && ce >= 0 && ce < g.cells[e];
+      cidx += (int64_t)ce * g.cstride[e];
+    }
+    acc += ok ? P[(int64_t)o * ctot + cidx] : T(0);
+  }
+  J.out[(int64_t)j * J.out_js + u] = acc;
+}
+
+// tab: cdiv(m, 4) blocks per GP (one wave per node).  For d >= 3 the two
+// stages take cdiv(4 * blocks, 256) blocks per GP, which covers both the
+// nodes and the cells (ctot < m); the jobs' cellp must be set.
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
                     hipStream_t s) {
   const unsigned nb = tab_blocks(tab);
   if (nb == 0) return;
+  if (d >= 3) {
+    std::vector<int64_t> b(tab.G);
+    for (int g = 0; g < tab.G; ++g) b[g] = cdiv(tab.off[g + 1] - tab.off[g], 64);
+    const Tab t2 = make_tab(b);
+    const unsigned n2 = tab_blocks(t2);
+    if (d == 3) {
+      tlaunch("scatter_cells", k_scatter_cells<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
+      tlaunch("scatter", k_scatter_nodes<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
+    } else {
+      tlaunch("scatter_cells", k_scatter_cells<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+      tlaunch("scatter", k_scatter_nodes<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+    }
+    return;
+  }
   switch (d) {
     case 1: tlaunch("scatter", k_scatter<T, 1>, nb, 256, 0, s, tab, jobs, j, mode); break;
     case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
-    case 3: tlaunch("scatter", k_scatter<T, 3>, nb, 256, 0, s, tab, jobs, j, mode); break;
-    case 4: tlaunch("scatter", k_scatter<T, 4>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
 template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t);
