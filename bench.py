@@ -40,13 +40,17 @@ SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": 
                 "lz_finalize": "lanczos.hip", "lz_cdots": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
                 "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip",
                 "sp_band_rt": "lanczos.hip", "sp_reduce_sum": "lanczos.hip", "rtilde": "lanczos.hip",
-                "scatter": "mvm.hip", "gather": "mvm.hip", "toep_band": "mvm.hip",
+                "scatter": "mvm.hip", "scatter_cells": "mvm.hip", "gather": "mvm.hip",
+                "toep_band": "mvm.hip",
                 "toep_reduce": "mvm.hip", "toep_band64": "mvm.hip", "toep_reduce64": "mvm.hip",
                 "predict": "query.hip", "sample": "query.hip", "sample_f": "query.hip", "setup_sort": "sort.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_pmc_traffic.txt")
+# the kernels of one Khat v product (two-stage W^T v where cells are heavy or d >= 3)
+MVM_SCOPES = ["scatter_cells", "scatter", "toeplitz", "gather"]
 METRIC = "predictive variances/sec and cache-build ms at stated error vs FP64; MVM HBM GB/s"
 # single-kernel timing scopes of the library (each wraps exactly one kernel launch)
-KERNELS = ["lz_udots", "lz_gdots", "lz_cdots", "lz_finalize", "scatter", "gather", "predict", "sample",
+KERNELS = ["lz_udots", "lz_gdots", "lz_cdots", "lz_finalize", "scatter", "scatter_cells", "gather",
+           "predict", "sample",
            "sample_f",
            "rtilde", "setup_sort", "colsum", "sp_apply", "rt_dots", "sp_udots", "sp_finalize",
            "toep_band", "toep_reduce", "toep_band64", "toep_reduce64", "sp_band_rt",
@@ -301,7 +305,7 @@ def mvm_large_section(B, torch, dev, n=1 << 25, reps=10):
     torch.cuda.synchronize()
     # the product's own kernels (the Lanczos runs these in the sorted row order),
     # event-timed on their launch stream
-    B.profile_select(["scatter", "toeplitz", "gather"])
+    B.profile_select(MVM_SCOPES)
     B.profile_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -309,7 +313,7 @@ def mvm_large_section(B, torch, dev, n=1 << 25, reps=10):
         c.apply_khat(v)
     e1.record()
     torch.cuda.synchronize()
-    mv = B.profile_read(["scatter", "toeplitz", "gather"])
+    mv = B.profile_read(MVM_SCOPES)
     B.profile_enable(False)
     B.profile_select(None)
     call_us = e0.elapsed_time(e1) * 1e3 / reps
@@ -483,13 +487,13 @@ def main():
     torch.cuda.synchronize()
     q_ms = ev0.elapsed_time(ev1) / nrep
     B.profile_enable(False)
-    B.profile_select(["scatter", "toeplitz", "gather"])
+    B.profile_select(MVM_SCOPES)
     B.profile_enable(True)
     v = torch.randn(P.n, device=dev)
     for _ in range(20):
         c.apply_khat(v)
     torch.cuda.synchronize()
-    mv = B.profile_read(["scatter", "toeplitz", "gather"])
+    mv = B.profile_read(MVM_SCOPES)
     B.profile_enable(False)
     B.profile_select(None)
     mvm_ms = sum(mv[k_][1] for k_ in mv) / 20

@@ -220,11 +220,14 @@ love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<con
 template <typename T>
 GridT<T> make_grid(const love_cache* c);
 
-// W^T v; for d >= 3 every job's cellp must hold scatter_scratch_bytes(c, sizeof(T))
+// W^T v.  two_stage (forced for d >= 3): per-cell partial products, then
+// per-node sums; every job's cellp must then hold scatter_scratch_bytes(c, sizeof(T)).
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
-                    hipStream_t s);
-size_t scatter_scratch_bytes(const love_cache* c, size_t elem);
+                    hipStream_t s, bool two_stage);
+bool scatter_two_stage(const love_cache* c);
+bool scatter_two_stage(const std::vector<love_cache*>& cs);   // every GP of a batch
+size_t scatter_scratch_bytes(const love_cache* c, size_t elem);   // 0 unless two stages
 template <typename T>
 void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s);
 template <typename T>

@@ -2137,6 +2137,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   const Tab t_rows = make_tab(b_rows), t_nodes = make_tab(b_nodes), t_m = make_tab(b_m),
             t_one = make_tab(b_one), t_gd = make_tab(b_gd), t_cd = make_tab(b_cd);
   for (int g = 0; g < G; ++g) k_ctl_init<<<1, 1, 0, s>>>(cs[g]->ctl);
+  const bool two_st = scatter_two_stage(cs);
   // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
   {
     ProfScope ps("probe", s);
@@ -2149,7 +2150,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   }
   // --- Lanczos steps -------------------------------------------------------------
   for (int j = 0; j < kmax; ++j) {
-    launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s);
+    launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
     toep_run<T>(A, t_step, j, 1, s);
     if (tab_blocks(t_cd))
       tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(t_cd), RBLK, 0, s, t_cd, dlz, j);
@@ -2245,7 +2246,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     int it = 0;
     while (it < maxit) {
       for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
-        launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s);
+        launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s, two_st);
         toep_run<double>(A, t_cg, 0, 2, s);
         k_cg_ap<T, D><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
         k_pcg_update<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
@@ -2259,7 +2260,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       if (hflag) break;
     }
     (void)hipFreeAsync(dflag, s);
-    launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s);
+    launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s, two_st);
     toep_run<double>(A, t_cg, 0, 0, s);
     k_cg_store_a<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, dcg);
     }

@@ -607,7 +607,8 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
   k_spec_prep<<<nbm, SPB, 0, s>>>(t_m, dj);
   k_spec_ynorm<<<nbn, SPB, 0, s>>>(t_n, dj);
   // r = b = B^T W^T y ; p = pinv r
-  launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_sy), d, 0, 2, s);
+  const bool two_st = scatter_two_stage(cs);
+  launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_sy), d, 0, 2, s, two_st);
   backward_passes(SB_R, 0);
   k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 1);
   k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 1);
@@ -626,7 +627,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     for (int qn = 0; qn < chunk && it < maxit; ++qn, ++it) {
       forward_passes(SB_P, 0);
       launch_gather<double>(t_n, A.at<GatherJob<double>>(o_ga), d, 2, s);
-      launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_su), d, 0, 2, s);
+      launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_su), d, 0, 2, s, two_st);
       backward_passes(SB_Q, KP_ADD_SP | KP_DOT_P);
       k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 0);
       k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 0);

@@ -165,9 +165,90 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
 // thread per node u: out[u] = sum over o of P[o][c(u - o)] for the cells that
 // exist, o ascending.  Both summation orders are fixed: deterministic.
 // ----------------------------------------------------------------------------
+// Two stages for d >= 3, and for d <= 2 once cells hold 64 rows or more on
+// average (then stage 1 takes one wave per cell and each row is read once,
+// against four times by the one-wave-per-node kernel).
+bool scatter_two_stage(const love_cache* c) {
+  return c->d >= 3 || c->n >= 64 * c->ctot;
+}
+bool scatter_two_stage(const std::vector<love_cache*>& cs) {
+  for (auto* c : cs)
+    if (!scatter_two_stage(c)) return false;
+  return !cs.empty();
+}
 size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
-  if (c->d < 3) return 0;
+  if (!scatter_two_stage(c)) return 0;
   return ((size_t)1 << (2 * c->d)) * (size_t)c->ctot * elem;
+}
+
+// Stage 1 for heavy cells (d <= 2): one wave per cell, lanes stride its rows
+// in batches of eight (loads first); each lane keeps the 4^D partial products
+// and the wave sums them in a fixed butterfly.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
+                                                            const ScatterJob<T>* __restrict__ jobs,
+                                                            int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
+  const GridT<T>& g = J.g;
+  const int64_t c = (int64_t)lb * (256 / WAVE) + threadIdx.x / WAVE;
+  if (c >= g.ctot) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  using GT = const __attribute__((address_space(1))) T;
+  GT* gx = (GT*)J.x;
+  GT* gv = (GT*)(J.v + (int64_t)j * J.v_js);
+  GT* gv2 = (GT*)J.v2;
+  const bool comb = (mode & 4) && J.v2;
+  const T ratio = comb ? (T)J.ctl->ratio : T(0);
+  const int32_t r0 = J.cell_start[c], r1 = J.cell_start[c + 1];
+  constexpr int NO = 1 << (2 * D);
+  constexpr int UB = 8;
+  T cb[D];   // stencil base of the cell's rows (fraction = (x - lo) invh - c_e)
+  {
+    int64_t rem = c;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int64_t ce = rem / g.cstride[e];
+      rem -= ce * g.cstride[e];
+      cb[e] = (T)ce;
+    }
+  }
+  T acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) acc[o] = T(0);
+  for (int32_t rs = r0 + lane; rs < r1; rs += UB * WAVE) {
+    T xr[UB][D], vr[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      const int64_t r = min(rs + q * WAVE, r1 - 1);
+#pragma unroll
+      for (int e = 0; e < D; ++e) xr[q][e] = gx[r * D + e];
+      vr[q] = gv[r];
+      if (comb) vr[q] = (T)(vr[q] + ratio * gv2[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      if (rs + q * WAVE >= r1) break;
+      T w[D][4];
+#pragma unroll
+      for (int e = 0; e < D; ++e) keys_weights<T>((xr[q][e] - g.lo[e]) * g.invh[e] - cb[e], w[e]);
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        T prod = vr[q];
+#pragma unroll
+        for (int e = 0; e < D; ++e) prod *= w[e][(o >> (2 * (D - 1 - e))) & 3];
+        acc[o] += prod;
+      }
+    }
+  }
+  T* __restrict__ P = J.cellp;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const T s = wave_sum(acc[o]);
+    if (lane == 0) P[(int64_t)o * g.ctot + c] = s;
+  }
 }
 
 template <typename T, int D>
@@ -190,6 +271,18 @@ __global__ __launch_bounds__(256) void k_scatter_cells(Tab tab,
   constexpr int NC = 1 << (2 * (D - 1));   // offsets per value of o_0
   T* __restrict__ P = J.cellp;
   const int64_t ctot = g.ctot;
+  // the rows of cell c have stencil base c_e on every axis, so the fraction is
+  // (x - lo) invh - c_e, the value stencil_at forms for them
+  T cb[D];
+  {
+    int64_t rem = c;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int64_t ce = rem / g.cstride[e];
+      rem -= ce * g.cstride[e];
+      cb[e] = (T)ce;
+    }
+  }
 #pragma unroll 1
   for (int o0 = 0; o0 < 4; ++o0) {
     T acc[NC];
@@ -198,11 +291,8 @@ __global__ __launch_bounds__(256) void k_scatter_cells(Tab tab,
     for (int32_t r = r0; r < r1; ++r) {
       T w[D][4];
 #pragma unroll
-      for (int e = 0; e < D; ++e) {
-        T sf;
-        (void)stencil_at(g, e, x[(int64_t)r * D + e], sf);
-        keys_weights<T>(sf, w[e]);
-      }
+      for (int e = 0; e < D; ++e)
+        keys_weights<T>((x[(int64_t)r * D + e] - g.lo[e]) * g.invh[e] - cb[e], w[e]);
       T val = v[r];
       if (comb) val = (T)(v[r] + ratio * v2[r]);
       const T a0 = val * w[0][o0];
@@ -258,25 +348,38 @@ __global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
   J.out[(int64_t)j * J.out_js + u] = acc;
 }
 
-// tab: cdiv(m, 4) blocks per GP (one wave per node).  For d >= 3 the two
-// stages take cdiv(4 * blocks, 256) blocks per GP, which covers both the
-// nodes and the cells (ctot < m); the jobs' cellp must be set.
+// tab: cdiv(m, 4) blocks per GP (one wave per node).  Two stages: the
+// wave-per-cell stage 1 (d <= 2) fits in the same tab (ctot < m); the
+// lane-per-cell stage 1 (d >= 3) and stage 2 take cdiv(4 * blocks, 256)
+// blocks per GP, which covers both the nodes and the cells; the jobs' cellp
+// must be set.
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
-                    hipStream_t s) {
+                    hipStream_t s, bool two_stage) {
   const unsigned nb = tab_blocks(tab);
   if (nb == 0) return;
-  if (d >= 3) {
+  if (two_stage || d >= 3) {
     std::vector<int64_t> b(tab.G);
     for (int g = 0; g < tab.G; ++g) b[g] = cdiv(tab.off[g + 1] - tab.off[g], 64);
     const Tab t2 = make_tab(b);
     const unsigned n2 = tab_blocks(t2);
-    if (d == 3) {
-      tlaunch("scatter_cells", k_scatter_cells<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
-      tlaunch("scatter", k_scatter_nodes<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
-    } else {
-      tlaunch("scatter_cells", k_scatter_cells<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
-      tlaunch("scatter", k_scatter_nodes<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+    switch (d) {
+      case 1:
+        tlaunch("scatter_cells", k_scatter_cells_wave<T, 1>, nb, 256, 0, s, tab, jobs, j, mode);
+        tlaunch("scatter", k_scatter_nodes<T, 1>, n2, 256, 0, s, t2, jobs, j, mode);
+        break;
+      case 2:
+        tlaunch("scatter_cells", k_scatter_cells_wave<T, 2>, nb, 256, 0, s, tab, jobs, j, mode);
+        tlaunch("scatter", k_scatter_nodes<T, 2>, n2, 256, 0, s, t2, jobs, j, mode);
+        break;
+      case 3:
+        tlaunch("scatter_cells", k_scatter_cells<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
+        tlaunch("scatter", k_scatter_nodes<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
+        break;
+      default:
+        tlaunch("scatter_cells", k_scatter_cells<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+        tlaunch("scatter", k_scatter_nodes<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+        break;
     }
     return;
   }
@@ -285,12 +388,16 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
     case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
-template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t);
-template void launch_scatter<double>(const Tab&, const ScatterJob<double>*, int, int, int, hipStream_t);
+template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t,
+                                    bool);
+template void launch_scatter<double>(const Tab&, const ScatterJob<double>*, int, int, int,
+                                     hipStream_t, bool);
 
 // ----------------------------------------------------------------------------
-// W u (+ sigma^2 v): one thread per sorted row.
+// W u (+ sigma^2 v): GR sorted rows per thread (rows lb 256 GR + t + 256 q),
+// all of whose x and v loads are issued before any stencil is formed.
 // ----------------------------------------------------------------------------
+constexpr int GR = 4;
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_gather(Tab tab, const GatherJob<T>* __restrict__ jobs,
                                                 int mode) {
@@ -298,22 +405,38 @@ __global__ __launch_bounds__(256) void k_gather(Tab tab, const GatherJob<T>* __r
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const GatherJob<T>& J = jobs[gp];
   if (ctl_skip(J.ctl, mode)) return;
-  const int64_t r = (int64_t)lb * blockDim.x + threadIdx.x;
-  if (r >= J.n) return;
-  T acc = gather_row_dev<T, D>(J.g, J.x, r, J.kg);
-  if (J.vsig) acc += J.sigma2 * J.vsig[r];
-  J.out[r] = acc;
+  const int64_t r0 = (int64_t)lb * 256 * GR + threadIdx.x;
+  const T* __restrict__ x = J.x;
+  const T* __restrict__ vs = J.vsig;
+  T xr[GR][D], vv[GR];
+#pragma unroll
+  for (int q = 0; q < GR; ++q) {
+    const int64_t r = min(r0 + 256 * q, J.n - 1);
+#pragma unroll
+    for (int e = 0; e < D; ++e) xr[q][e] = x[r * D + e];
+    vv[q] = vs ? vs[r] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < GR; ++q) {
+    const int64_t r = r0 + 256 * q;
+    if (r >= J.n) break;
+    J.out[r] = gather_row_vals<T, D>(J.g, xr[q], J.kg) + J.sigma2 * vv[q];
+  }
 }
 
+// tab: cdiv(n, 256) blocks per GP; the kernel takes 256 GR rows per block.
 template <typename T>
 void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s) {
-  const unsigned nb = tab_blocks(tab);
-  if (nb == 0) return;
+  if (tab_blocks(tab) == 0) return;
+  std::vector<int64_t> b(tab.G);
+  for (int g = 0; g < tab.G; ++g) b[g] = cdiv(tab.off[g + 1] - tab.off[g], GR);
+  const Tab t2 = make_tab(b);
+  const unsigned nb = tab_blocks(t2);
   switch (d) {
-    case 1: tlaunch("gather", k_gather<T, 1>, nb, 256, 0, s, tab, jobs, mode); break;
-    case 2: tlaunch("gather", k_gather<T, 2>, nb, 256, 0, s, tab, jobs, mode); break;
-    case 3: tlaunch("gather", k_gather<T, 3>, nb, 256, 0, s, tab, jobs, mode); break;
-    case 4: tlaunch("gather", k_gather<T, 4>, nb, 256, 0, s, tab, jobs, mode); break;
+    case 1: tlaunch("gather", k_gather<T, 1>, nb, 256, 0, s, t2, jobs, mode); break;
+    case 2: tlaunch("gather", k_gather<T, 2>, nb, 256, 0, s, t2, jobs, mode); break;
+    case 3: tlaunch("gather", k_gather<T, 3>, nb, 256, 0, s, t2, jobs, mode); break;
+    case 4: tlaunch("gather", k_gather<T, 4>, nb, 256, 0, s, t2, jobs, mode); break;
   }
 }
 template void launch_gather<float>(const Tab&, const GatherJob<float>*, int, int, hipStream_t);

@@ -27,14 +27,13 @@ __device__ inline bool ctl_skip(const Ctl* ctl, int mode) {
 
 // (W u)[r] for one row: tensor-product cubic stencil, 4^D grid values.
 template <typename T, int D>
-__device__ inline T gather_row_dev(const GridT<T>& g, const T* __restrict__ x, int64_t r,
-                                   const T* __restrict__ kg) {
+__device__ inline T gather_row_vals(const GridT<T>& g, const T (&xr)[D], const T* __restrict__ kg) {
   T w[D][4];
   int64_t base = 0;
 #pragma unroll
   for (int e = 0; e < D; ++e) {
     T s;
-    const int j = stencil_at(g, e, x[r * D + e], s);
+    const int j = stencil_at(g, e, xr[e], s);
     keys_weights(s, w[e]);
     base += (int64_t)j * g.nstride[e];
   }
@@ -54,6 +53,14 @@ __device__ inline T gather_row_dev(const GridT<T>& g, const T* __restrict__ x, i
     acc += wp * (w[D - 1][0] * p[0] + w[D - 1][1] * p[1] + w[D - 1][2] * p[2] + w[D - 1][3] * p[3]);
   }
   return acc;
+}
+template <typename T, int D>
+__device__ inline T gather_row_dev(const GridT<T>& g, const T* __restrict__ x, int64_t r,
+                                   const T* __restrict__ kg) {
+  T xr[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) xr[e] = x[r * D + e];
+  return gather_row_vals<T, D>(g, xr, kg);
 }
 
 }  // namespace love

@@ -72,6 +72,52 @@ def test_apply_khat_parity(cfgi, scale):
     cache.free()
 
 
+@pytest.mark.parametrize("case", ["1d_f32", "1d_f64", "2d_f32"])
+def test_apply_khat_heavy_cells_parity(case):
+    """Cells holding >= 64 rows on average take the two-stage W^T v (one wave
+    per cell, then per-node sums): 1-D with ~330 rows per cell and 2-D with
+    ~620, against the dense product."""
+    if case == "2d_f32":
+        P = WL.make_problem("heavy2d", d=2, n=50_000, m=(12, 12), kernel="rbf",
+                            lengthscale=(0.2, 0.3), noise=0.01, k=8, t=10,
+                            target="sincos4", ynoise=0.05)
+    else:
+        f64 = case == "1d_f64"
+        P = WL.make_problem("heavy1d", d=1, n=20_000, m=(64,), kernel="rbf",
+                            lengthscale=(0.1,), noise=0.01, k=8, t=10, target="sin6",
+                            ynoise=0.1, dtype="f64" if f64 else "f32",
+                            precision="fp64" if f64 else "fp32")
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P, flags=B.FLAG_NO_MEAN)
+    spec = spec_of(P)
+    v = np.random.default_rng(1).standard_normal(P.n)
+    dt = torch_dtype(P)
+    vv = v.astype(np.float32 if dt == torch.float32 else np.float64)
+    out = host(cache.apply_khat(tdev(vv, dt)))
+    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    assert rel <= (1e-12 if dt == torch.float64 else 1e-5), rel
+    cache.free()
+
+
+def test_heavy_cells_build_parity():
+    """A whole build (float Lanczos, double mean CG) through the two-stage
+    W^T v: 1-D, 2e4 points on 64 nodes (~330 rows per cell), against the
+    oracle."""
+    P = WL.make_problem("heavy1d", d=1, n=20_000, m=(64,), kernel="rbf", lengthscale=(0.1,),
+                        noise=0.01, k=40, t=2000, target="sin6", ynoise=0.1)
+    print(P.name, P.n, P.m, flush=True)
+    cache = build(P)
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(var), v_ref, O.prior_var(P.xs, spec_of(P)), host(mu), m_ref, P.y)
+    print(cache.info().k_eff, e, flush=True)
+    assert e["e_p_max"] <= 1e-5
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    cache.free()
+
+
 # ---------------------------------------------------------------------------
 # Full build + query
 # ---------------------------------------------------------------------------
