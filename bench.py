@@ -37,7 +37,8 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 # source file of each timing scope (the stored counter readings are void once it changes)
 SCOPE_SOURCE = {"colsum": "lanczos.hip", "lz_udots": "lanczos.hip", "lz_gdots": "lanczos.hip",
-                "lz_finalize": "lanczos.hip", "lz_cdots": "lanczos.hip", "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
+                "lz_finalize": "lanczos.hip", "lz_cdots": "lanczos.hip",
+                "sp_apply": "lanczos.hip", "rt_dots": "lanczos.hip",
                 "sp_udots": "lanczos.hip", "sp_finalize": "lanczos.hip",
                 "sp_band_rt": "lanczos.hip", "sp_reduce_sum": "lanczos.hip", "rtilde": "lanczos.hip",
                 "scatter": "mvm.hip", "scatter_cells": "mvm.hip", "gather": "mvm.hip",

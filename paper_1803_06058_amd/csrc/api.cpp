@@ -341,7 +341,7 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   }
   launch_permute<T>(v, (T*)c->v1, c->perm, c->n, 0, s);
   launch_scatter<T>(tab1(cdiv(c->m, 4)), A.at<ScatterJob<T>>(os), c->d, 0, 0, s,
-                    scatter_two_stage(c));
+                    scatter_kinds(one));
   toep_run<T>(A, run, 0, 0, s);
   launch_gather<T>(tab1(cdiv(c->n, 256)), A.at<GatherJob<T>>(og), c->d, 0, s);
   launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);

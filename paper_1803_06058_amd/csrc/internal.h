@@ -220,13 +220,16 @@ love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<con
 template <typename T>
 GridT<T> make_grid(const love_cache* c);
 
-// W^T v.  two_stage (forced for d >= 3): per-cell partial products, then
-// per-node sums; every job's cellp must then hold scatter_scratch_bytes(c, sizeof(T)).
+// W^T v.  A GP takes two stages (per-cell partial products, then per-node
+// sums) when scatter_two_stage(c); its job's cellp then holds
+// scatter_scratch_bytes(c, sizeof(T)), and is null otherwise.  kinds: the
+// SCATTER_* bits of the batch (scatter_kinds).
+enum : int { SCATTER_NODES = 1, SCATTER_TWO_STAGE = 2 };
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
-                    hipStream_t s, bool two_stage);
+                    hipStream_t s, int kinds);
 bool scatter_two_stage(const love_cache* c);
-bool scatter_two_stage(const std::vector<love_cache*>& cs);   // every GP of a batch
+int scatter_kinds(const std::vector<love_cache*>& cs);
 size_t scatter_scratch_bytes(const love_cache* c, size_t elem);   // 0 unless two stages
 template <typename T>
 void launch_gather(const Tab& tab, const GatherJob<T>* jobs, int d, int mode, hipStream_t s);

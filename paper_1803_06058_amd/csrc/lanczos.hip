@@ -2137,7 +2137,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   const Tab t_rows = make_tab(b_rows), t_nodes = make_tab(b_nodes), t_m = make_tab(b_m),
             t_one = make_tab(b_one), t_gd = make_tab(b_gd), t_cd = make_tab(b_cd);
   for (int g = 0; g < G; ++g) k_ctl_init<<<1, 1, 0, s>>>(cs[g]->ctl);
-  const bool two_st = scatter_two_stage(cs);
+  const int two_st = scatter_kinds(cs);
   // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
   {
     ProfScope ps("probe", s);

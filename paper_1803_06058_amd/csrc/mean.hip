@@ -607,7 +607,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
   k_spec_prep<<<nbm, SPB, 0, s>>>(t_m, dj);
   k_spec_ynorm<<<nbn, SPB, 0, s>>>(t_n, dj);
   // r = b = B^T W^T y ; p = pinv r
-  const bool two_st = scatter_two_stage(cs);
+  const int two_st = scatter_kinds(cs);
   launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_sy), d, 0, 2, s, two_st);
   backward_passes(SB_R, 0);
   k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 1);

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const ScatterJob<T>& J = jobs[gp];
-  if (ctl_skip(J.ctl, mode)) return;
+  if (ctl_skip(J.ctl, mode) || J.cellp) return;   // cellp set: the two-stage kernels
   const GridT<T>& g = J.g;
   const T* __restrict__ x = J.x;
   const T* __restrict__ v = J.v + (int64_t)j * J.v_js;
@@ -171,10 +171,10 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
 bool scatter_two_stage(const love_cache* c) {
   return c->d >= 3 || c->n >= 64 * c->ctot;
 }
-bool scatter_two_stage(const std::vector<love_cache*>& cs) {
-  for (auto* c : cs)
-    if (!scatter_two_stage(c)) return false;
-  return !cs.empty();
+int scatter_kinds(const std::vector<love_cache*>& cs) {
+  int k = 0;
+  for (auto* c : cs) k |= scatter_two_stage(c) ? SCATTER_TWO_STAGE : SCATTER_NODES;
+  return k;
 }
 size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
   if (!scatter_two_stage(c)) return 0;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const ScatterJob<T>& J = jobs[gp];
-  if (ctl_skip(J.ctl, mode)) return;
+  if (ctl_skip(J.ctl, mode) || !J.cellp) return;
   const GridT<T>& g = J.g;
   const int64_t c = (int64_t)lb * (256 / WAVE) + threadIdx.x / WAVE;
   if (c >= g.ctot) return;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_scatter_cells(Tab tab,
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const ScatterJob<T>& J = jobs[gp];
-  if (ctl_skip(J.ctl, mode)) return;
+  if (ctl_skip(J.ctl, mode) || !J.cellp) return;
   const GridT<T>& g = J.g;
   const int64_t c = (int64_t)lb * 256 + threadIdx.x;
   if (c >= g.ctot) return;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const ScatterJob<T>& J = jobs[gp];
-  if (ctl_skip(J.ctl, mode)) return;
+  if (ctl_skip(J.ctl, mode) || !J.cellp) return;
   const GridT<T>& g = J.g;
   const int64_t u = (int64_t)lb * 256 + threadIdx.x;
   if (u >= g.mtot) return;
@@ -348,17 +348,18 @@ __global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
   J.out[(int64_t)j * J.out_js + u] = acc;
 }
 
-// tab: cdiv(m, 4) blocks per GP (one wave per node).  Two stages: the
-// wave-per-cell stage 1 (d <= 2) fits in the same tab (ctot < m); the
-// lane-per-cell stage 1 (d >= 3) and stage 2 take cdiv(4 * blocks, 256)
-// blocks per GP, which covers both the nodes and the cells; the jobs' cellp
-// must be set.
+// tab: cdiv(m, 4) blocks per GP (one wave per node).  A job with cellp set
+// takes the two stages, the others the one-wave-per-node kernel; `kinds`
+// (SCATTER_*) says which launches the batch needs, and each kernel skips the
+// other kind's jobs.  The wave-per-cell stage 1 (d <= 2) fits in the same tab
+// (ctot < m); the lane-per-cell stage 1 (d >= 3) and stage 2 take
+// cdiv(4 * blocks, 256) blocks per GP, which covers both nodes and cells.
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
-                    hipStream_t s, bool two_stage) {
+                    hipStream_t s, int kinds) {
   const unsigned nb = tab_blocks(tab);
   if (nb == 0) return;
-  if (two_stage || d >= 3) {
+  if (kinds & SCATTER_TWO_STAGE) {
     std::vector<int64_t> b(tab.G);
     for (int g = 0; g < tab.G; ++g) b[g] = cdiv(tab.off[g + 1] - tab.off[g], 64);
     const Tab t2 = make_tab(b);
@@ -381,17 +382,17 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
         tlaunch("scatter", k_scatter_nodes<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
     }
-    return;
   }
+  if (!(kinds & SCATTER_NODES) || d >= 3) return;
   switch (d) {
     case 1: tlaunch("scatter", k_scatter<T, 1>, nb, 256, 0, s, tab, jobs, j, mode); break;
     case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
 template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t,
-                                    bool);
+                                    int);
 template void launch_scatter<double>(const Tab&, const ScatterJob<double>*, int, int, int,
-                                     hipStream_t, bool);
+                                     hipStream_t, int);
 
 // ----------------------------------------------------------------------------
 // W u (+ sigma^2 v): GR sorted rows per thread (rows lb 256 GR + t + 256 q),
