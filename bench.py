@@ -69,6 +69,9 @@ def parse():
                     help="skip the 64-GP batched-build measurement")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the bf16-split (2-D) and differentiable (4-D) timings")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="only time the bf16-split (2-D) and differentiable (4-D) forms and the "
+                         "large Khat v product (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run three 256 MiB device-to-device copies (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -403,6 +406,10 @@ def main():
     from paper_1803_06058_amd import workloads as WL
 
     dev = torch.device("cuda", 0)
+    if a.forms_only:
+        print(json.dumps({"forms": forms_section(B, WL, torch, dev),
+                          "mvm_large": mvm_large_section(B, torch, dev)}), flush=True)
+        return
     P = WL.config(2)
     cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
                           lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
