@@ -387,8 +387,8 @@ def forms_section(B, WL, torch, dev, reps=3):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
-              "sharding across GPUs is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {a.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
