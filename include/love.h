@@ -249,6 +249,13 @@ love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* 
 /* Query counters and status (synchronises the stream the cache was built on). */
 love_status love_cache_info(const love_cache* c, love_cache_info_t* info);
 
+/* k_eff and k_eff_sample (the rows z of love_sample_posterior needs) without
+ * synchronising: the values recorded when a synchronous build (no
+ * LOVE_FLAG_ASYNC) or an import returned.  After an asynchronous build the
+ * first call reads them like love_cache_info (synchronising the build stream).
+ * Out-pointers are host memory; EINVAL on NULL. */
+love_status love_cache_keff(const love_cache* c, int32_t* k_eff, int32_t* k_eff_sample);
+
 /* Copy cache contents into caller device buffers (enqueued on `stream`). */
 love_status love_cache_export(const love_cache* c, const love_export* e, void* stream);
 
@@ -265,7 +272,10 @@ love_status love_cache_export(const love_cache* c, const love_export* e, void* s
 love_status love_cache_import(const love_config* cfg, const love_import* im, void* stream,
                               love_cache** out);
 
-/* Release a cache (synchronises its build stream first).  NULL is a no-op. */
+/* Release a cache, stream-ordered on its build stream: work queued on that
+ * stream before the call finishes first, and the host does not wait.  Work on
+ * other streams that reads the cache must be complete (or ordered before the
+ * build stream's current point) when this is called.  NULL is a no-op. */
 void love_cache_free(love_cache* c);
 
 /* Per-kernel timing with HIP events recorded around each launch on the

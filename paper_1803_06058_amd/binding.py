@@ -63,7 +63,7 @@ SYMBOLS = [
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
     "love_predict_covar_block",
     "love_sample_posterior", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
-    "love_cache_info", "love_cache_export", "love_cache_import", "love_cache_free",
+    "love_cache_info", "love_cache_keff", "love_cache_export", "love_cache_import", "love_cache_free",
     "love_profile_enable",
     "love_profile_read", "love_profile_select",
 ]
@@ -112,6 +112,8 @@ def load_library():
     L.love_apply_kuu.argtypes = [vp, vp, vp, vp]
     L.love_cache_info.restype = i32
     L.love_cache_info.argtypes = [vp, C.POINTER(love_cache_info_t)]
+    L.love_cache_keff.restype = i32
+    L.love_cache_keff.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.love_cache_export.restype = i32
     L.love_cache_export.argtypes = [vp, C.POINTER(love_export), vp]
     L.love_cache_import.restype = i32
@@ -190,6 +192,9 @@ class LoveCache:
         self.cfg = cfg
         self.d = cfg.d
         self.dtype = _dtype(cfg.precision)
+        self.m = 1
+        for e in range(cfg.d):
+            self.m *= int(cfg.m[e])
 
     # -- lifetime --------------------------------------------------------
     def free(self):
@@ -246,12 +251,19 @@ class LoveCache:
                "predict_covar_block")
         return cov
 
+    def keff(self):
+        """(k_eff, k_eff_sample); no device synchronisation after a synchronous build."""
+        k = C.c_int32()
+        ks = C.c_int32()
+        _check(load_library().love_cache_keff(self._h, C.byref(k), C.byref(ks)), "cache_keff")
+        return k.value, ks.value
+
     def sample_posterior(self, xs: torch.Tensor, z: torch.Tensor, out=None):
         t = self._xs(xs)
         _need(z, torch.float32, None, "z")
         if z.dim() != 2:
             raise ValueError("z must be k_sample x s")
-        if z.shape[0] < self.info().k_eff_sample:
+        if z.shape[0] < self.keff()[1]:
             raise ValueError("z needs at least k_eff_sample rows")
         s = z.shape[1]
         if out is None:
@@ -269,8 +281,7 @@ class LoveCache:
         gx = torch.empty(t, self.d, device=xs.device, dtype=self.dtype)
         grt = None
         if want_grt:
-            info = self.info()
-            grt = torch.zeros(info.m, info.k_eff, device=xs.device, dtype=torch.float32)
+            grt = torch.zeros(self.m, self.keff()[0], device=xs.device, dtype=torch.float32)
         _check(load_library().love_predict_backward(self._h, _ptr(xs), t, _ptr(g_mean), _ptr(g_var),
                                                     _ptr(gx), _ptr(grt), C.c_void_p(_stream())),
                "predict_backward")

@@ -97,9 +97,12 @@ void prof_end(const char* name, hipStream_t s) {
   if (p.pending.size() > 4096) drain(p);
 }
 
+// Cache memory comes from the device's stream-ordered pool on the cache's
+// stream (no device-wide synchronisation; the pool keeps freed memory for the
+// next build) and goes back to it in love_cache_free.
 bool dev_reserve(love_cache* c, size_t bytes) {
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return false;
+  if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) return false;
   c->allocs.push_back(p);
   c->block = (char*)p;
   c->block_size = bytes;
@@ -116,7 +119,7 @@ void* dev_alloc(love_cache* c, size_t bytes) {
     return p;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) return nullptr;
   c->allocs.push_back(p);
   return p;
 }
@@ -229,21 +232,32 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   return LOVE_OK;
 }
 
+// Stream-ordered release on the cache's stream: work queued there before the
+// call completes first; the host does not wait.
 static void destroy(love_cache* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
-  for (void* p : c->allocs) (void)hipFree(p);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != c->device) (void)hipSetDevice(c->device);
+  for (void* p : c->allocs) (void)hipFreeAsync(p, c->stream);
+  if (cur != c->device) (void)hipSetDevice(cur);
   delete c;
 }
 
 static love_status finish_status(love_cache* c) {
-  Ctl h;
-  unsigned st[4];
-  LOVE_HIP_TRY(hipMemcpyAsync(&h, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-  LOVE_HIP_TRY(hipMemcpyAsync(st, c->status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  // ctl, ctl_s and the status words are contiguous: one copy
+  struct {
+    Ctl h, hs;
+    unsigned st[4];
+  } b;
+  static_assert(sizeof(b) == 2 * sizeof(Ctl) + 4 * sizeof(unsigned), "control block layout");
+  LOVE_HIP_TRY(hipMemcpyAsync(&b, c->ctl, sizeof(b), hipMemcpyDeviceToHost, c->stream));
   LOVE_HIP_TRY(hipStreamSynchronize(c->stream));
-  const unsigned all = h.status | st[0];
+  const Ctl& h = b.h;
+  c->keff_h = h.k_eff;
+  c->kseff_h = c->ks > 0 ? b.hs.k_chol : 0;
+  c->keff_known = 1;
+  const unsigned all = h.status | b.st[0];
   if (all & SF_DOMAIN) return LOVE_EDOMAIN;
   if (all & SF_NONFINITE) return LOVE_ENONFINITE;
   if (h.k_eff < 1) return LOVE_ENOTPD;
@@ -551,6 +565,21 @@ love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
   return LOVE_OK;
 }
 
+love_status love_cache_keff(const love_cache* c, int32_t* k_eff, int32_t* k_eff_sample) {
+  if (!c || !k_eff || !k_eff_sample) return LOVE_EINVAL;
+  if (!c->keff_known) {
+    love_cache_info_t info;
+    love_status st = love_cache_info(c, &info);
+    if (st != LOVE_OK) return st;
+    *k_eff = info.k_eff;
+    *k_eff_sample = info.k_eff_sample;
+    return LOVE_OK;
+  }
+  *k_eff = c->keff_h;
+  *k_eff_sample = c->kseff_h;
+  return LOVE_OK;
+}
+
 love_status love_cache_export(const love_cache* c, const love_export* e, void* stream) {
   if (!c || !e) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -631,6 +660,9 @@ love_status love_cache_import(const love_config* cfg, const love_import* im, voi
     return st;
   }
   c->n = 0;   // no training rows: love_apply_khat is unavailable
+  c->keff_h = im->k_eff;
+  c->kseff_h = im->k_eff_sample;
+  c->keff_known = 1;
   *out = c;
   return LOVE_OK;
 }

@@ -118,6 +118,10 @@ struct love_cache {
   // one device block for the cache's buffers, handed out in order (dev_alloc)
   char* block = nullptr;
   size_t block_size = 0, block_used = 0;
+  // k_eff and k_eff_sample as recorded on the host when a synchronous build or
+  // an import finished (keff_known = 0: not yet read)
+  int keff_known = 0;
+  int32_t keff_h = 0, kseff_h = 0;
 };
 
 namespace love {

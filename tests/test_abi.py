@@ -112,6 +112,8 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.love_sample_posterior(None, C.c_void_p(8), 1, C.c_void_p(8), 1, C.c_void_p(8), None) == -1
     assert lib.love_predict_backward(None, C.c_void_p(8), 1, None, None, C.c_void_p(8), None, None) == -1
     assert lib.love_cache_info(None, None) == -1
+    k1, k2 = C.c_int32(), C.c_int32()
+    assert lib.love_cache_keff(None, C.byref(k1), C.byref(k2)) == -1
     assert lib.love_apply_khat(None, None, None, None) == -1
     assert lib.love_build_cache_batched(0, None, None, None, None, None, None) == -1
     lib.love_cache_free(None)   # no-op

@@ -604,6 +604,19 @@ def test_batched_grid_and_row_first_pass_equal_single():
         c.free()
 
 
+def test_keff_without_sync_matches_info():
+    """love_cache_keff returns the counts a synchronous build recorded, and
+    reads them from the device after an asynchronous build."""
+    P = WL.config(2, scale=0.02, k_sample=40, s=8)
+    c1 = build(P)
+    i1 = c1.info()
+    assert c1.keff() == (i1.k_eff, i1.k_eff_sample) and i1.k_eff_sample > 0
+    c2 = build(P, flags=B.FLAG_ASYNC)
+    assert c2.keff() == (i1.k_eff, i1.k_eff_sample)
+    c1.free()
+    c2.free()
+
+
 @pytest.mark.parametrize("case", ["fp32_sampler", "fp64", "bf16split"])
 def test_cache_import_roundtrip(case):
     """export -> import: the imported cache (no training data) answers every
@@ -620,6 +633,7 @@ def test_cache_import_roundtrip(case):
     imp = B.import_cache(cfg_of(P), parts)
     i0, i1 = cache.info(), imp.info()
     assert (i1.k_eff, i1.k_eff_sample, i1.n) == (i0.k_eff, i0.k_eff_sample, 0)
+    assert cache.keff() == imp.keff() == (i0.k_eff, i0.k_eff_sample)
     xs = tdev(P.xs[:5000], dt)
     m0, v0 = cache.predict_mean_var(xs)
     m1, v1 = imp.predict_mean_var(xs)
