@@ -1100,16 +1100,10 @@ __global__ void k_pcg_matrix(Tab tab, const CgJob<TQ>* __restrict__ jobs) {
   }
 }
 
-// flag = 1 when every GP's CG is done; one block
+// flags[g] = 1 once GP g's CG is done; one block
 template <typename TQ>
-__global__ void k_cg_alldone(int G, const CgJob<TQ>* __restrict__ jobs, int* flag) {
-  __shared__ int all;
-  if (threadIdx.x == 0) all = 1;
-  __syncthreads();
-  for (int g = threadIdx.x; g < G; g += blockDim.x)
-    if (!jobs[g].ctl->cg_done) atomicAnd(&all, 0);
-  __syncthreads();
-  if (threadIdx.x == 0) *flag = all;
+__global__ void k_cg_flags(int G, const CgJob<TQ>* __restrict__ jobs, int* flags) {
+  for (int g = threadIdx.x; g < G; g += blockDim.x) flags[g] = jobs[g].ctl->cg_done ? 1 : 0;
 }
 
 // a[u] = gm[u] in the cache precision
@@ -2149,18 +2143,45 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     k_lz_start<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dlz);
   }
   // --- Lanczos steps -------------------------------------------------------------
+  // A GP whose k steps are done drops out of the launch tables (its blocks
+  // would only return at once); GPs stopped early by breakdown return through
+  // their control block.
+  Tab a_nodes = t_nodes, a_cd = t_cd, a_gd = t_gd, a_rows = t_rows;
+  ToepRun<T> a_step = t_step;
+  std::vector<int> a_nv1 = nv1, a_nv2 = nv2;
   for (int j = 0; j < kmax; ++j) {
-    launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
-    toep_run<T>(A, t_step, j, 1, s);
-    if (tab_blocks(t_cd))
-      tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(t_cd), RBLK, 0, s, t_cd, dlz, j);
-    if (tab_blocks(t_gd)) {
-      tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_gd), RBLK, 0, s, t_gd, dlz, j);
-      launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+    bool drop = false;
+    for (int g = 0; g < G; ++g) drop = drop || cs[g]->k == j;
+    if (drop) {
+      auto keep = [&](const Tab& t) {
+        std::vector<int64_t> b(G);
+        for (int g = 0; g < G; ++g) b[g] = cs[g]->k > j ? t.off[g + 1] - t.off[g] : 0;
+        return make_tab(b);
+      };
+      a_nodes = keep(t_nodes);
+      a_cd = keep(t_cd);
+      a_gd = keep(t_gd);
+      a_rows = keep(t_rows);
+      for (int e = 0; e < t_step.d; ++e) {
+        a_step.ax[e].band = keep(t_step.ax[e].band);
+        a_step.ax[e].reduce = keep(t_step.ax[e].reduce);
+        a_step.ax[e].lines = keep(t_step.ax[e].lines);
+        a_step.ax[e].fft = keep(t_step.ax[e].fft);
+      }
+      for (int g = 0; g < G; ++g)
+        if (cs[g]->k <= j) a_nv1[g] = a_nv2[g] = -(1 << 20);
     }
-    tlaunch("lz_udots", k_lz_udots<T, D>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
-    launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
-    tlaunch("lz_finalize", k_lz_finalize<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz, j);
+    launch_scatter<T>(a_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
+    toep_run<T>(A, a_step, j, 1, s);
+    if (tab_blocks(a_cd))
+      tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(a_cd), RBLK, 0, s, a_cd, dlz, j);
+    if (tab_blocks(a_gd)) {
+      tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(a_gd), RBLK, 0, s, a_gd, dlz, j);
+      launch_colsum(A.at<SumJob>(o_coef), a_nv1, j, 1, s);
+    }
+    tlaunch("lz_udots", k_lz_udots<T, D>, tab_blocks(a_rows), RBLK, 0, s, a_rows, dlz, j);
+    launch_colsum(A.at<SumJob>(o_c2), a_nv2, j, 1, s);
+    tlaunch("lz_finalize", k_lz_finalize<T>, tab_blocks(a_rows), RBLK, 0, s, a_rows, dlz, j);
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
   k_tri_chol<T><<<tab_blocks(t_one), 64, 0, s>>>(t_one, dlz, 0.0);
@@ -2234,8 +2255,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 1);
     k_pcg_apply<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
     int* dflag = nullptr;
-    LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int), s));
-    int hflag = 0;
+    LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int) * G, s));
+    std::vector<int> hflag(G, 0);
     int maxit = 0;
     bool any_plain = false;
     for (int g = 0; g < G; ++g) {
@@ -2243,21 +2264,43 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       any_plain = any_plain || plain[g];
     }
     const int chunk = any_plain ? 8 : 4;
+    // launch tables of the GPs still iterating: at every check the converged
+    // GPs drop out (their blocks would only return at once)
+    Tab a_nodes = t_nodes, a_rows = t_rows, a_one = t_one;
+    ToepRun<double> a_cg = t_cg;
+    std::vector<int> a_nvq = nvq;
     int it = 0;
     while (it < maxit) {
       for (int q = 0; q < chunk && it < maxit; ++q, ++it) {
-        launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s, two_st);
-        toep_run<double>(A, t_cg, 0, 2, s);
-        k_cg_ap<T, D><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
-        k_pcg_update<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
-        launch_colsum(dscg, nvq, 0, 2, s);
-        k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 0);
-        k_pcg_apply<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
+        launch_scatter<double>(a_nodes, A.at<ScatterJob<double>>(o_csc), D, 0, 2 | 4, s, two_st);
+        toep_run<double>(A, a_cg, 0, 2, s);
+        k_cg_ap<T, D><<<tab_blocks(a_rows), RBLK, 0, s>>>(a_rows, dcg);
+        k_pcg_update<T><<<tab_blocks(a_rows), RBLK, 0, s>>>(a_rows, dcg);
+        launch_colsum(dscg, a_nvq, 0, 2, s);
+        k_pcg_ep<T><<<tab_blocks(a_one), BLK, 0, s>>>(a_one, dcg, 0);
+        k_pcg_apply<T><<<tab_blocks(a_rows), RBLK, 0, s>>>(a_rows, dcg);
       }
-      k_cg_alldone<T><<<1, 64, 0, s>>>(G, dcg, dflag);
-      LOVE_HIP_TRY(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      k_cg_flags<T><<<1, 64, 0, s>>>(G, dcg, dflag);
+      LOVE_HIP_TRY(hipMemcpyAsync(hflag.data(), dflag, sizeof(int) * G, hipMemcpyDeviceToHost, s));
       LOVE_HIP_TRY(hipStreamSynchronize(s));
-      if (hflag) break;
+      int live = 0;
+      for (int g = 0; g < G; ++g) live += hflag[g] ? 0 : 1;
+      if (!live) break;
+      auto keep = [&](const Tab& t) {
+        std::vector<int64_t> b(G);
+        for (int g = 0; g < G; ++g) b[g] = hflag[g] ? 0 : t.off[g + 1] - t.off[g];
+        return make_tab(b);
+      };
+      a_nodes = keep(t_nodes);
+      a_rows = keep(t_rows);
+      a_one = keep(t_one);
+      for (int e = 0; e < t_cg.d; ++e) {
+        a_cg.ax[e].band = keep(t_cg.ax[e].band);
+        a_cg.ax[e].reduce = keep(t_cg.ax[e].reduce);
+        a_cg.ax[e].lines = keep(t_cg.ax[e].lines);
+        a_cg.ax[e].fft = keep(t_cg.ax[e].fft);
+      }
+      for (int g = 0; g < G; ++g) a_nvq[g] = hflag[g] ? 0 : nvq[g];
     }
     (void)hipFreeAsync(dflag, s);
     launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s, two_st);
