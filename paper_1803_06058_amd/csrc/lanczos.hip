@@ -2263,7 +2263,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       maxit = std::max(maxit, cg[g].maxit);
       any_plain = any_plain || plain[g];
     }
-    const int chunk = any_plain ? 8 : 4;
+    // iterations between convergence checks: 4 (8 for plain CG) at first,
+    // doubling after each check up to 16 (a long tail then costs few syncs)
+    int chunk = any_plain ? 8 : 4;
     // launch tables of the GPs still iterating: at every check the converged
     // GPs drop out (their blocks would only return at once)
     Tab a_nodes = t_nodes, a_rows = t_rows, a_one = t_one;
@@ -2286,6 +2288,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       int live = 0;
       for (int g = 0; g < G; ++g) live += hflag[g] ? 0 : 1;
       if (!live) break;
+      chunk = std::min(16, 2 * chunk);
       auto keep = [&](const Tab& t) {
         std::vector<int64_t> b(G);
         for (int g = 0; g < G; ++g) b[g] = hflag[g] ? 0 : t.off[g + 1] - t.off[g];

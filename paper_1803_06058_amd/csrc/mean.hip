@@ -621,7 +621,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
   }
   int maxit = 0;
   for (const auto& J : jobs) maxit = std::max(maxit, J.maxit);
-  const int chunk = 8;
+  int chunk = 4;   // iterations between convergence checks, doubling up to 16
   int it = 0, hflag = 0;
   while (it < maxit) {
     for (int qn = 0; qn < chunk && it < maxit; ++qn, ++it) {
@@ -640,6 +640,7 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
       break;
     }
     if (hflag) break;
+    chunk = std::min(16, 2 * chunk);
   }
   (void)hipFreeAsync(dflag, s);
   if (hflag >= 0) {
