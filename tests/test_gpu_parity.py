@@ -415,6 +415,85 @@ def test_grid_space_mean_3d():
     cache.free()
 
 
+def test_grid_space_mean_fp64_parity():
+    """Double 2-D build (grid-space mean in double, tolerance 1e-12 of
+    sigma ||y||): mean and variance against the oracle at double tolerance."""
+    P = WL.make_problem("d2_f64", d=2, n=4000, m=(16, 16), kernel="rbf", lengthscale=(0.15, 0.2),
+                        noise=0.01, k=60, t=1000, target="sincos4", ynoise=0.05, dtype="f64",
+                        precision="fp64")
+    cache = build(P)
+    info = cache.info()
+    print("cg_iters", info.cg_iters, flush=True)
+    assert not (info.status_flags & SF_CG_NOCONV)
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float64))
+    oc = O.love_build(P.x, P.y, spec_of(P), P.k, cg_tol=1e-13, cg_maxit=20000)
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(var), v_ref, O.prior_var(P.xs, spec_of(P)), host(mu), m_ref, P.y)
+    print(e, flush=True)
+    assert e["e_p_max"] <= 1e-10
+    assert e["mean_err_rel_rms_y"] <= 1e-9
+    cache.free()
+
+
+def test_batched_2d_grid_space_equals_single():
+    """Two 2-D GPs of different size in one batch: the grid-space mean and the
+    Kronecker operator run batched and give each GP its own build bit for bit."""
+    Ps = [WL.make_problem("b2d_%d" % i, d=2, n=n, m=m, kernel="rbf", lengthscale=(0.1, 0.15),
+                          noise=0.005, k=k, t=1000, target="sincos4", ynoise=0.05, seed=i)
+          for i, (n, m, k) in enumerate([(20_000, (24, 24), 40), (8_000, (16, 20), 30)])]
+    cfgs = [cfg_of(P) for P in Ps]
+    xs = [tdev(P.x, torch.float32) for P in Ps]
+    ys = [tdev(P.y, torch.float32) for P in Ps]
+    caches = B.build_cache_batched(cfgs, xs, ys)
+    qs = [tdev(P.xs, torch.float32) for P in Ps]
+    for g, P in enumerate(Ps):
+        single = build(P)
+        m0, v0 = caches[g].predict_mean_var(qs[g])
+        m1, v1 = single.predict_mean_var(qs[g])
+        assert caches[g].info().cg_iters == single.info().cg_iters
+        assert torch.equal(v0, v1) and torch.equal(m0, m1)
+        single.free()
+    for c in caches:
+        c.free()
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_apply_khat_3d_parity(f64):
+    """3-D product (two-stage W^T v, lane per cell) against the dense product."""
+    P = WL.make_problem("d3op", d=3, n=6000, m=(8, 9, 10), kernel="matern52",
+                        lengthscale=(0.3, 0.25, 0.2), noise=0.01, k=8, t=10, target="sumsin",
+                        ynoise=0.1, dtype="f64" if f64 else "f32", precision="fp64" if f64 else "fp32")
+    cache = build(P, flags=B.FLAG_NO_MEAN)
+    spec = spec_of(P)
+    v = np.random.default_rng(2).standard_normal(P.n)
+    dt = torch_dtype(P)
+    vv = v.astype(np.float64 if f64 else np.float32)
+    out = host(cache.apply_khat(tdev(vv, dt)))
+    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    assert rel <= (1e-12 if f64 else 1e-5), rel
+    cache.free()
+
+
+def test_batched_3d_equals_single():
+    """Two 3-D GPs in one batch (two-stage W^T v in the Lanczos and the mean
+    solve): each equals its own build bit for bit."""
+    Ps = [WL.make_problem("b3d_%d" % i, d=3, n=n, m=m, kernel="rbf", lengthscale=(0.2, 0.25, 0.3),
+                          noise=0.01, k=30, t=500, target="sumsin", ynoise=0.1, seed=i)
+          for i, (n, m) in enumerate([(6000, (10, 10, 10)), (3000, (8, 9, 8))])]
+    caches = B.build_cache_batched([cfg_of(P) for P in Ps], [tdev(P.x, torch.float32) for P in Ps],
+                                   [tdev(P.y, torch.float32) for P in Ps])
+    for g, P in enumerate(Ps):
+        q = tdev(P.xs, torch.float32)
+        single = build(P)
+        m0, v0 = caches[g].predict_mean_var(q)
+        m1, v1 = single.predict_mean_var(q)
+        assert torch.equal(v0, v1) and torch.equal(m0, m1)
+        single.free()
+    for c in caches:
+        c.free()
+
+
 @pytest.mark.parametrize("case", ["2d", "4d", "4d_sparse"])
 def test_grid_space_mean_equals_data_space_cg(case):
     """The two mean solvers (grid space by default for d >= 2, data-space CG on
