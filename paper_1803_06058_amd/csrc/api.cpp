@@ -298,6 +298,22 @@ static hipStream_t side_stream() {
   return st;
 }
 
+// One non-blocking stream per device for the grid-space mean solve, which runs
+// beside the Lanczos (default priority).
+hipStream_t love::mean_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  streams[dev] = st;
+  return st;
+}
+
 // Build a batch of caches (same d and precision) with one launch per phase.
 template <typename T>
 static love_status build_batch(const std::vector<love_cache*>& cs, const void* const* xs,

@@ -261,13 +261,43 @@ love_status build_batch_lanczos(const std::vector<love_cache*>& cs, hipStream_t 
 // true when the cache's mean is solved in grid space (d >= 2, every axis at
 // most SPEC_MAXM points, no flag asking for the data-space CG)
 bool spectral_mean_applies(const love_cache* c);
-// a = K W^T Khat^{-1} y for every GP of the batch; x64 / y64: sorted training
-// data in double, un: n doubles of scratch per GP, cellp: the scatter scratch
-// (scatter_scratch_bytes, double); sets ctl->cg_iters and the
-// CG status bits.  Synchronises `s` every few iterations.
-love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
-                          const std::vector<const double*>& y64, const std::vector<double*>& un,
-                          const std::vector<double*>& cellp, hipStream_t s);
+// a = K W^T Khat^{-1} y for every GP of the batch, on a stream of its own
+// beside the Lanczos (the solve needs only x, y and the grid).  start()
+// enqueues the set-up and the first FIRST_CHUNK iterations without waiting;
+// finish() checks convergence (the host waits on the solve's stream), runs
+// further iterations as needed and stores a; the caller then joins the
+// streams and calls merge() on the build stream, which writes cg_iters and the
+// solve's status bits into each cache's control block.  x64 / y64: sorted
+// training data in double; un: n doubles of scratch per GP; release() frees
+// everything on the given stream.
+class SpectralMean {
+ public:
+  static constexpr int FIRST_CHUNK = 16;
+  love_status start(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
+                    const std::vector<const double*>& y64, const std::vector<double*>& un,
+                    hipStream_t s);
+  love_status finish();
+  void merge(hipStream_t s);
+  void release(hipStream_t s);
+
+ private:
+  void forward_passes(int src, int extra);
+  void backward_passes(int dst, int last);
+  void iterations(int count);
+  hipStream_t s_ = nullptr;
+  int G_ = 0, d_ = 0, it_ = 0, maxit_ = 0, kinds_ = 0;
+  bool uploaded_ = false;
+  std::vector<SpecJob> jobs_;
+  std::vector<char*> mem_;
+  std::vector<double*> cellp_;
+  JobArena A_;
+  const SpecJob* dj_ = nullptr;
+  size_t o_j_ = 0, o_ga_ = 0, o_su_ = 0;
+  Tab t_m_{}, t_n_{}, t_one_{}, t_nodes_{};
+  int* dflag_ = nullptr;
+};
+// the non-blocking stream the grid-space mean solve runs on (one per device)
+hipStream_t mean_stream();
 
 // --- queries (query.hip) -----------------------------------------------------
 template <typename T>

@@ -203,7 +203,8 @@ struct SpecJob {
   int nbm, nbn;               // row counts of the partials over m and over n
   double sigma2, tol2;
   int maxit;
-  Ctl* ctl;
+  Ctl* ctl;                   // the solve's own control block
+  Ctl* ctl_out;               // the cache's: gets cg_iters, done and the solve's status bits
   void* a;                    // cache mean vector (m, cache precision)
   int a_fp64;
 };

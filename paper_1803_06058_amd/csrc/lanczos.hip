@@ -2131,6 +2131,57 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   const Tab t_rows = make_tab(b_rows), t_nodes = make_tab(b_nodes), t_m = make_tab(b_m),
             t_one = make_tab(b_one), t_gd = make_tab(b_gd), t_cd = make_tab(b_cd);
   for (int g = 0; g < G; ++g) k_ctl_init<<<1, 1, 0, s>>>(cs[g]->ctl);
+  // Grid-space mean solve (Kronecker grids): it needs only x, y and the grid,
+  // so it starts here on its own stream and runs beside the Lanczos.
+  bool spec = mean;
+  for (auto* c : cs) spec = spec && spectral_mean_applies(c);
+  SpectralMean sm;
+  hipStream_t s_mean = s;
+  hipEvent_t ev_mfork = nullptr, ev_mjoin = nullptr;
+  // On any return before the join, the solve's stream is waited for (it
+  // writes into the cache) and its buffers released.
+  struct MeanGuard {
+    SpectralMean* sm;
+    hipStream_t ms, s;
+    hipEvent_t *fork, *join;
+    bool armed = false;
+    ~MeanGuard() {
+      if (armed) {
+        (void)hipStreamSynchronize(ms);
+        sm->release(s);
+      }
+      if (*fork) (void)hipEventDestroy(*fork);
+      if (*join) (void)hipEventDestroy(*join);
+    }
+  } guard{&sm, s, s, &ev_mfork, &ev_mjoin};
+  auto fail = [&](love_status code) {
+    A.release(s);
+    for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
+    return code;
+  };
+  if (spec) {
+    hipStream_t ms = mean_stream();
+    if (ms && hipEventCreateWithFlags(&ev_mfork, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&ev_mjoin, hipEventDisableTiming) == hipSuccess &&
+        hipEventRecord(ev_mfork, s) == hipSuccess && hipStreamWaitEvent(ms, ev_mfork, 0) == hipSuccess)
+      s_mean = ms;
+    guard.ms = s_mean;
+    guard.armed = true;
+    const Tab t_cvx = make_tab(b_cvx), t_cvy = make_tab(b_cvy);
+    if (tab_blocks(t_cvx)) {
+      k_convert_b<<<tab_blocks(t_cvx), 256, 0, s_mean>>>(t_cvx, A.at<ConvJob>(o_cvx));
+      k_convert_b<<<tab_blocks(t_cvy), 256, 0, s_mean>>>(t_cvy, A.at<ConvJob>(o_cvy));
+    }
+    std::vector<const double*> sx(G), sy(G);
+    std::vector<double*> su(G);
+    for (int g = 0; g < G; ++g) {
+      sx[g] = bufs[g].x64;
+      sy[g] = bufs[g].y64;
+      su[g] = bufs[g].cz;
+    }
+    love_status ss = sm.start(cs, sx, sy, su, s_mean);
+    if (ss != LOVE_OK) return fail(ss);
+  }
   const int two_st = scatter_kinds(cs);
   // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
   {
@@ -2218,7 +2269,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     const CgJob<T>* dcg = A.at<CgJob<T>>(o_cg);
     const Tab t_cvx = make_tab(b_cvx), t_cvy = make_tab(b_cvy), t_gram = make_tab(b_gram),
               t_cmat = make_tab(b_cmat);
-    if (tab_blocks(t_cvx)) {
+    if (tab_blocks(t_cvx) && !spec) {
       k_convert_b<<<tab_blocks(t_cvx), 256, 0, s>>>(t_cvx, A.at<ConvJob>(o_cvx));
       k_convert_b<<<tab_blocks(t_cvy), 256, 0, s>>>(t_cvy, A.at<ConvJob>(o_cvy));
     }
@@ -2229,23 +2280,16 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       k_tinv<T><<<tab_blocks(t_one), MAXK, 0, s>>>(t_one, dcg);
       k_pcg_matrix<T><<<tab_blocks(t_cmat), 256, 0, s>>>(t_cmat, dcg);
     }
-    bool spec = true;
-    for (auto* c : cs) spec = spec && spectral_mean_applies(c);
     if (spec) {
-      std::vector<const double*> sx(G), sy(G);
-      std::vector<double*> su(G), scp(G);
-      for (int g = 0; g < G; ++g) {
-        sx[g] = bufs[g].x64;
-        sy[g] = bufs[g].y64;
-        su[g] = bufs[g].cz;
-        scp[g] = (double*)bufs[g].cellp;
+      love_status ss = sm.finish();
+      if (ss != LOVE_OK) return fail(ss);
+      if (s_mean != s) {
+        LOVE_HIP_TRY(hipEventRecord(ev_mjoin, s_mean));
+        LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_mjoin, 0));
       }
-      love_status ss = spectral_mean(cs, sx, sy, su, scp, s);
-      if (ss != LOVE_OK) {
-        A.release(s);
-        for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
-        return ss;
-      }
+      sm.merge(s);
+      sm.release(s);
+      guard.armed = false;
     }
     if (!spec) {
     const SumJob* dscg = A.at<SumJob>(o_scg);

@@ -458,6 +458,18 @@ __global__ __launch_bounds__(SPB) void k_spec_store(Tab tab, const SpecJob* __re
   else ((float*)J.a)[idx] = (float)v;
 }
 
+// The solve's counters into the cache's control block (run on the build stream
+// once both streams have joined): iterations, done, and its status bits.
+__global__ void k_spec_merge(int G, const SpecJob* __restrict__ jobs) {
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const Ctl* own = jobs[g].ctl;
+    Ctl* out = jobs[g].ctl_out;
+    out->cg_iters = own->cg_iters;
+    out->cg_done = 1;
+    out->status |= own->status & (SF_NONFINITE | SF_CG_NOCONV);
+  }
+}
+
 __global__ void k_spec_alldone(int G, const SpecJob* __restrict__ jobs, int* flag) {
   __shared__ int all;
   if (threadIdx.x == 0) all = 1;
@@ -478,18 +490,17 @@ bool spectral_mean_applies(const love_cache* c) {
   return true;
 }
 
-love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<const double*>& x64,
-                          const std::vector<const double*>& y64, const std::vector<double*>& un,
-                          const std::vector<double*>& cellp, hipStream_t s) {
-  const int G = (int)cs.size();
-  const int d = cs[0]->d;
-  std::vector<SpecJob> jobs(G);
+love_status SpectralMean::start(const std::vector<love_cache*>& cs,
+                                const std::vector<const double*>& x64,
+                                const std::vector<const double*>& y64,
+                                const std::vector<double*>& un, hipStream_t s) {
+  s_ = s;
+  G_ = (int)cs.size();
+  d_ = cs[0]->d;
+  const int G = G_, d = d_;
+  jobs_.assign(G, SpecJob{});
+  mem_.assign(G, nullptr);
   std::vector<int64_t> b_m(G), b_n(G), b_axis(G, 2 * d), b_one(G, 1), b_nodes(G);
-  std::vector<char*> mem(G, nullptr);
-  auto release = [&]() {
-    for (char* p : mem)
-      if (p) (void)hipFreeAsync(p, s);
-  };
   for (int g = 0; g < G; ++g) {
     love_cache* c = cs[g];
     SpecJob J{};
@@ -510,14 +521,20 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     }
     J.nbm = (int)cdiv(J.mtot, SPB);
     J.nbn = (int)cdiv(J.n, SPB);
-    size_t nd = 0;
+    // own control block and scatter scratch: the solve runs beside the Lanczos
+    static_assert(sizeof(Ctl) <= 256, "control block slot");
+    size_t nd = 32;   // the control block's 256-byte slot
     for (int e = 0; e < d; ++e) nd += (size_t)J.ldv[e] * J.ldv[e] + (size_t)J.ldv[e];
     nd += 7 * (size_t)J.mtot + (size_t)std::max(J.nbm, J.nbn) * SPW;
-    if (hipMallocAsync((void**)&mem[g], nd * sizeof(double), s) != hipSuccess) {
-      release();
-      return LOVE_ENOMEM;
-    }
-    double* q = (double*)mem[g];
+    const size_t sb = scatter_scratch_bytes(c, sizeof(double));
+    const size_t cb = sb ? (sb + 255) / 256 * 32 : 0;   // doubles, whole 256-byte blocks
+    nd += cb;
+    if (hipMallocAsync((void**)&mem_[g], nd * sizeof(double), s) != hipSuccess) return LOVE_ENOMEM;
+    double* q = (double*)mem_[g];
+    J.ctl = (Ctl*)q;
+    q += 32;
+    cellp_.push_back(cb ? q : nullptr);
+    q += cb;
     for (int e = 0; e < d; ++e) {
       const size_t l2 = (size_t)J.ldv[e] * J.ldv[e];
       J.B[e] = q;
@@ -537,19 +554,20 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     const double tol = c->cfg.cg_tol > 0 ? c->cfg.cg_tol : (c->fp64 ? 1e-12 : 1e-6);
     J.tol2 = tol * tol * c->cfg.noise;
     J.maxit = c->cfg.cg_maxit > 0 ? c->cfg.cg_maxit : 1000;
-    J.ctl = c->ctl;
+    J.ctl_out = c->ctl;
     J.a = c->a;
     J.a_fp64 = c->fp64 ? 1 : 0;
-    jobs[g] = J;
+    jobs_[g] = J;
     b_m[g] = J.nbm;
     b_n[g] = J.nbn;
     b_nodes[g] = cdiv(J.mtot, 4);
+    LOVE_HIP_TRY(hipMemsetAsync(J.ctl, 0, sizeof(Ctl), s));
   }
   // W u and W^T v jobs (double)
   std::vector<GatherJob<double>> ga(G);
   std::vector<ScatterJob<double>> sy(G), su(G);
   for (int g = 0; g < G; ++g) {
-    const SpecJob& J = jobs[g];
+    const SpecJob& J = jobs_[g];
     GatherJob<double> Ga{};
     Ga.g = J.g;
     Ga.x = J.x;
@@ -565,93 +583,106 @@ love_status spectral_mean(const std::vector<love_cache*>& cs, const std::vector<
     S.v = J.y;
     S.out = J.t0;
     S.ctl = J.ctl;
-    S.cellp = cellp[g];
+    S.cellp = cellp_[g];
     sy[g] = S;
     S.v = J.un;
     su[g] = S;
   }
-  JobArena A;
-  const size_t o_j = A.add(jobs), o_ga = A.add(ga), o_sy = A.add(sy), o_su = A.add(su);
-  love_status st = A.upload(s);
-  if (st != LOVE_OK) {
-    release();
-    return st;
-  }
-  const SpecJob* dj = A.at<SpecJob>(o_j);
-  const Tab t_m = make_tab(b_m), t_n = make_tab(b_n), t_axis = make_tab(b_axis),
-            t_one = make_tab(b_one), t_nodes = make_tab(b_nodes);
-  const unsigned nbm = tab_blocks(t_m), nbn = tab_blocks(t_n);
-
-  // B^T applied to t0 (d passes ending in `dst`), with `last` mode bits
-  auto backward_passes = [&](int dst, int last) {
-    int src = SB_T0;
-    for (int e = 0; e < d; ++e) {
-      const bool fin = e == d - 1;
-      const int out = fin ? dst : (src == SB_T0 ? SB_T1 : SB_T0);
-      tlaunch("spec_kron", k_spec_kron, nbm, SPB, 0, s, t_m, dj, e, fin ? last : 0, src, out);
-      src = out;
-    }
-  };
-  // B applied to `src` (d passes ending in t0 for odd d, t1 for even d)
-  auto forward_passes = [&](int src, int extra) {
-    int in = src;
-    for (int e = 0; e < d; ++e) {
-      const int out = (e & 1) ? SB_T1 : SB_T0;
-      tlaunch("spec_kron", k_spec_kron, nbm, SPB, 0, s, t_m, dj, e, KP_FWD | extra, in, out);
-      in = out;
-    }
-  };
+  o_j_ = A_.add(jobs_);
+  o_ga_ = A_.add(ga);
+  const size_t o_sy = A_.add(sy);
+  o_su_ = A_.add(su);
+  love_status st = A_.upload(s);
+  if (st != LOVE_OK) return st;
+  uploaded_ = true;
+  dj_ = A_.at<SpecJob>(o_j_);
+  t_m_ = make_tab(b_m);
+  t_n_ = make_tab(b_n);
+  t_one_ = make_tab(b_one);
+  t_nodes_ = make_tab(b_nodes);
+  const Tab t_axis = make_tab(b_axis);
+  kinds_ = scatter_kinds(cs);
+  for (const auto& J : jobs_) maxit_ = std::max(maxit_, J.maxit);
+  LOVE_HIP_TRY(hipMallocAsync((void**)&dflag_, sizeof(int), s));
 
   ProfScope ps("mean_spectral", s);
-  k_spec_axis<<<tab_blocks(t_axis), EIG_THREADS, 0, s>>>(t_axis, dj);
-  k_spec_prep<<<nbm, SPB, 0, s>>>(t_m, dj);
-  k_spec_ynorm<<<nbn, SPB, 0, s>>>(t_n, dj);
+  k_spec_axis<<<tab_blocks(t_axis), EIG_THREADS, 0, s>>>(t_axis, dj_);
+  k_spec_prep<<<tab_blocks(t_m_), SPB, 0, s>>>(t_m_, dj_);
+  k_spec_ynorm<<<tab_blocks(t_n_), SPB, 0, s>>>(t_n_, dj_);
   // r = b = B^T W^T y ; p = pinv r
-  const int two_st = scatter_kinds(cs);
-  launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_sy), d, 0, 2, s, two_st);
+  launch_scatter<double>(t_nodes_, A_.at<ScatterJob<double>>(o_sy), d, 0, 2, s, kinds_);
   backward_passes(SB_R, 0);
-  k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 1);
-  k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 1);
-  k_spec_dir<<<nbm, SPB, 0, s>>>(t_m, dj);
-  int* dflag = nullptr;
-  if (hipMallocAsync((void**)&dflag, sizeof(int), s) != hipSuccess) {
-    A.release(s);
-    release();
-    return LOVE_ENOMEM;
+  k_spec_update<<<tab_blocks(t_m_), SPB, 0, s>>>(t_m_, dj_, 1);
+  k_spec_ep<<<tab_blocks(t_one_), WAVE, 0, s>>>(t_one_, dj_, 1);
+  k_spec_dir<<<tab_blocks(t_m_), SPB, 0, s>>>(t_m_, dj_);
+  iterations(FIRST_CHUNK);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+// B^T applied to t0 (d passes ending in `dst`), with `last` mode bits
+void SpectralMean::backward_passes(int dst, int last) {
+  int src = SB_T0;
+  for (int e = 0; e < d_; ++e) {
+    const bool fin = e == d_ - 1;
+    const int out = fin ? dst : (src == SB_T0 ? SB_T1 : SB_T0);
+    tlaunch("spec_kron", k_spec_kron, tab_blocks(t_m_), SPB, 0, s_, t_m_, dj_, e, fin ? last : 0,
+            src, out);
+    src = out;
   }
-  int maxit = 0;
-  for (const auto& J : jobs) maxit = std::max(maxit, J.maxit);
-  int chunk = 4;   // iterations between convergence checks, doubling up to 16
-  int it = 0, hflag = 0;
-  while (it < maxit) {
-    for (int qn = 0; qn < chunk && it < maxit; ++qn, ++it) {
-      forward_passes(SB_P, 0);
-      launch_gather<double>(t_n, A.at<GatherJob<double>>(o_ga), d, 2, s);
-      launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_su), d, 0, 2, s, two_st);
-      backward_passes(SB_Q, KP_ADD_SP | KP_DOT_P);
-      k_spec_update<<<nbm, SPB, 0, s>>>(t_m, dj, 0);
-      k_spec_ep<<<tab_blocks(t_one), WAVE, 0, s>>>(t_one, dj, 0);
-      k_spec_dir<<<nbm, SPB, 0, s>>>(t_m, dj);
-    }
-    k_spec_alldone<<<1, 64, 0, s>>>(G, dj, dflag);
-    if (hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-      hflag = -1;
-      break;
-    }
-    if (hflag) break;
+}
+
+// B applied to `src` (d passes ending in t0 for odd d, t1 for even d)
+void SpectralMean::forward_passes(int src, int extra) {
+  int in = src;
+  for (int e = 0; e < d_; ++e) {
+    const int out = (e & 1) ? SB_T1 : SB_T0;
+    tlaunch("spec_kron", k_spec_kron, tab_blocks(t_m_), SPB, 0, s_, t_m_, dj_, e, KP_FWD | extra,
+            in, out);
+    in = out;
+  }
+}
+
+void SpectralMean::iterations(int count) {
+  for (int qn = 0; qn < count && it_ < maxit_; ++qn, ++it_) {
+    forward_passes(SB_P, 0);
+    launch_gather<double>(t_n_, A_.at<GatherJob<double>>(o_ga_), d_, 2, s_);
+    launch_scatter<double>(t_nodes_, A_.at<ScatterJob<double>>(o_su_), d_, 0, 2, s_, kinds_);
+    backward_passes(SB_Q, KP_ADD_SP | KP_DOT_P);
+    k_spec_update<<<tab_blocks(t_m_), SPB, 0, s_>>>(t_m_, dj_, 0);
+    k_spec_ep<<<tab_blocks(t_one_), WAVE, 0, s_>>>(t_one_, dj_, 0);
+    k_spec_dir<<<tab_blocks(t_m_), SPB, 0, s_>>>(t_m_, dj_);
+  }
+}
+
+love_status SpectralMean::finish() {
+  int chunk = 4;   // iterations between convergence checks after the first chunk, doubling to 16
+  int hflag = 0;
+  while (true) {
+    k_spec_alldone<<<1, 64, 0, s_>>>(G_, dj_, dflag_);
+    LOVE_HIP_TRY(hipMemcpyAsync(&hflag, dflag_, sizeof(int), hipMemcpyDeviceToHost, s_));
+    LOVE_HIP_TRY(hipStreamSynchronize(s_));
+    if (hflag || it_ >= maxit_) break;
+    iterations(chunk);
     chunk = std::min(16, 2 * chunk);
   }
-  (void)hipFreeAsync(dflag, s);
-  if (hflag >= 0) {
-    // a = B z
-    forward_passes(SB_Z, KP_FORCE);
-    k_spec_store<<<nbm, SPB, 0, s>>>(t_m, dj, (d & 1) ? SB_T0 : SB_T1);
-  }
-  A.release(s);
-  release();
-  if (hflag < 0) return LOVE_EHIP;
+  // a = B z
+  forward_passes(SB_Z, KP_FORCE);
+  k_spec_store<<<tab_blocks(t_m_), SPB, 0, s_>>>(t_m_, dj_, (d_ & 1) ? SB_T0 : SB_T1);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+
+void SpectralMean::merge(hipStream_t s) {
+  if (uploaded_) k_spec_merge<<<1, 64, 0, s>>>(G_, dj_);
+}
+
+void SpectralMean::release(hipStream_t s) {
+  if (dflag_) (void)hipFreeAsync(dflag_, s);
+  dflag_ = nullptr;
+  A_.release(s);
+  for (char* p : mem_)
+    if (p) (void)hipFreeAsync(p, s);
+  mem_.clear();
+  uploaded_ = false;
 }
 
 }  // namespace love
