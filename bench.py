@@ -331,6 +331,41 @@ def mvm_large_section(B, torch, dev, n=1 << 25, reps=10):
             "apply_khat_call_us": round(call_us, 1)}
 
 
+def lanczos_large_section(B, torch, dev, n=1 << 21):
+    """The build's dominant row kernel where its bytes, not launch latency,
+    set its time: one 1-D GP with 2^21 points (m = 1e4, k = 100, no mean and
+    no sampler), k_lz_udots event-timed over the build against its
+    algorithmic bytes (Q_{0..j} read once per step)."""
+    from types import SimpleNamespace
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    x = torch.rand(n, 1, device=dev, generator=gen)
+    y = torch.sin(6 * math.pi * x[:, 0]) + 0.1 * torch.randn(n, device=dev, generator=gen)
+    cfg = B.config_struct(1, [10000], [0.0], [1.0], kernel="rbf", lengthscale=[0.02], noise=0.01,
+                          k=100, precision="fp32", flags=B.FLAG_NO_MEAN)
+    B.build_cache(cfg, x, y).free()              # warm-up
+    torch.cuda.synchronize()
+    B.profile_select(["lz_udots"])
+    B.profile_enable(True)
+    t0 = time.perf_counter()
+    c = B.build_cache(cfg, x, y)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ud = B.profile_read(["lz_udots"])["lz_udots"]
+    B.profile_enable(False)
+    B.profile_select(None)
+    k_eff = c.keff()[0]
+    c.free()
+    P = SimpleNamespace(n=n, m=(10000,), d=1)
+    alg = alg_bytes("lz_udots", P, k_eff, ud[0])
+    us = ud[1] * 1e3 / max(1, ud[0])
+    gbps = alg / max(1, ud[0]) / (us * 1e-6) / 1e9
+    return {"n": n, "m": 10000, "k": 100, "k_eff": k_eff, "build_ms": round((t1 - t0) * 1e3, 2),
+            "lz_udots": {"launches": int(ud[0]), "avg_us": round(us, 1),
+                         "alg_bytes_per_launch": int(alg / max(1, ud[0])),
+                         "achieved_gbps": round(gbps, 1), "frac_hbm": round(gbps / HBM_PEAK_GBS, 3)}}
+
+
 def forms_section(B, WL, torch, dev, reps=3):
     """The other forms of the path at their full sizes, timed on this GPU (median
     of `reps` after one warm-up, host clock around synchronised calls):
@@ -408,7 +443,8 @@ def main():
     dev = torch.device("cuda", 0)
     if a.forms_only:
         print(json.dumps({"forms": forms_section(B, WL, torch, dev),
-                          "mvm_large": mvm_large_section(B, torch, dev)}), flush=True)
+                          "mvm_large": mvm_large_section(B, torch, dev),
+                          "lanczos_large": lanczos_large_section(B, torch, dev)}), flush=True)
         return
     P = WL.config(2)
     cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
@@ -573,6 +609,7 @@ def main():
     if not a.no_forms:
         out["forms"] = forms_section(B, WL, torch, dev)
         out["mvm_large"] = mvm_large_section(B, torch, dev)
+        out["lanczos_large"] = lanczos_large_section(B, torch, dev)
     if not a.no_cpu_baseline:
         base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries)
         out["cpu_baseline"] = base
