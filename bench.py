@@ -128,13 +128,13 @@ def _stored_profile():
     only while its source file hashes as recorded (the dominant entry only
     while every recorded source does)."""
     import hashlib
-    out = {"scale": {}, "kernels": {}, "dominant": None}
+    out = {"scale": {}, "kernels": {}, "dominant": None, "second": None}
     if not os.path.exists(TRAFFIC_FILE):
         return out
     fields = {}
     for line in open(TRAFFIC_FILE):
         parts = line.split()
-        if len(parts) >= 2 and parts[0] in ("scale", "sha256", "kernel", "dominant"):
+        if len(parts) >= 2 and parts[0] in ("scale", "sha256", "kernel", "dominant", "second"):
             fields.setdefault(parts[0], []).append(parts[1:])
     same = {}
     for src, sha in fields.get("sha256", []):
@@ -146,6 +146,8 @@ def _stored_profile():
             out["kernels"][rec[0]] = (float(rec[1]), float(rec[2]))
     if fields.get("dominant") and same and all(same.values()):
         out["dominant"] = fields["dominant"][0][0]
+        if fields.get("second"):
+            out["second"] = fields["second"][0][0]
     return out
 
 
@@ -484,9 +486,11 @@ def main():
     # kernel trace of this same code when there is one (event pairs add the
     # dispatch latency to every launch, which would favour kernels launched
     # often), else from the event timings of the warm-up steps
-    dominant = _stored_profile()["dominant"]
-    if dominant not in KERNELS:
-        dominant = max(KERNELS, key=lambda k_: warm[k_][1])
+    stored = _stored_profile()
+    dominant, second = stored["dominant"], stored["second"]
+    if dominant not in KERNELS or second not in KERNELS:
+        ranked = sorted(KERNELS, key=lambda k_: -warm[k_][1])
+        dominant, second = ranked[0], ranked[1]
     # timed region: K steps with timing off give ms_per_step and value (event
     # objects on thousands of launches per step would slow the host down)
     torch.cuda.synchronize()
@@ -497,16 +501,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / a.steps
-    # the same K steps again, each launch of the dominant kernel carrying a HIP
-    # event pair that takes the kernel's own start and end timestamps on its
-    # launch stream (hipExtLaunchKernel): its average duration
-    B.profile_select([dominant])
+    # the same K steps again, each launch of the dominant kernel (and of the
+    # runner-up) carrying a HIP event pair that takes the kernel's own start
+    # and end timestamps on its launch stream (hipExtLaunchKernel): their
+    # average durations
+    B.profile_select([dominant, second])
     B.profile_enable(True)
     for _ in range(a.steps):
         c = step()
         c.free()
     torch.cuda.synchronize()
-    dom = B.profile_read([dominant])[dominant]
+    recs = B.profile_read([dominant, second])
     B.profile_enable(False)
 
     # component timings (separate, after the timed region): build alone, queries alone, one MVM
@@ -558,31 +563,39 @@ def main():
     c.free()
 
     k_eff = info.k_eff
-    calls_step = dom[0] / a.steps
-    avg_us = dom[1] * 1e3 / max(1, dom[0])
-    roof = None
-    if dominant in ("toep_band", "toep_band64"):
-        # VALU-bound banded product: 2 (2 bw + 1) flops per output, m outputs per step
-        m_tot = int(math.prod(P.m))
-        bw = int(round(dominant_bw(P, dominant == "toep_band64")))
-        flops = 2.0 * (2 * bw + 1) * m_tot
-        achieved = flops / (avg_us * 1e-6) / 1e12
-        peak = FP64_PEAK_TFLOPS if dominant == "toep_band64" else FP32_PEAK_TFLOPS
-        roof = {"kernel": dominant, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                "traffic": stored_traffic(dominant), "launches": int(dom[0]),
-                "avg_launch_us": round(avg_us, 3), "alg_flops_per_launch": int(flops)}
-    else:
-        bytes_step = alg_bytes(dominant, P, k_eff, calls_step, info.k_eff_sample)
-        if bytes_step is not None and dom[1] > 0:
-            achieved = bytes_step * a.steps / (dom[1] * 1e-3) / 1e9
-            roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": stored_traffic(dominant), "launches": int(dom[0]),
-                    "avg_launch_us": round(avg_us, 3),
-                    "alg_bytes_per_launch": int(bytes_step / max(1.0, calls_step))}
-    if roof is not None and roof["traffic"] is not None:
-        roof["traffic_gbps"] = round(roof["traffic"] / (avg_us * 1e-6) / 1e9, 1)
+
+    def roofline(name, rec):
+        calls_step = rec[0] / a.steps
+        avg_us = rec[1] * 1e3 / max(1, rec[0])
+        r = None
+        if name in ("toep_band", "toep_band64"):
+            # VALU-bound banded product: 2 (2 bw + 1) flops per output, m outputs per step
+            bw = int(round(dominant_bw(P, name == "toep_band64")))
+            flops = 2.0 * (2 * bw + 1) * int(math.prod(P.m))
+            achieved = flops / (avg_us * 1e-6) / 1e12
+            peak = FP64_PEAK_TFLOPS if name == "toep_band64" else FP32_PEAK_TFLOPS
+            r = {"kernel": name, "bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                 "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                 "traffic": stored_traffic(name), "launches": int(rec[0]),
+                 "avg_launch_us": round(avg_us, 3), "alg_flops_per_launch": int(flops)}
+        else:
+            bytes_step = alg_bytes(name, P, k_eff, calls_step, info.k_eff_sample)
+            if bytes_step is not None and rec[1] > 0:
+                achieved = bytes_step * a.steps / (rec[1] * 1e-3) / 1e9
+                r = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": stored_traffic(name), "launches": int(rec[0]),
+                     "avg_launch_us": round(avg_us, 3),
+                     "alg_bytes_per_launch": int(bytes_step / max(1.0, calls_step))}
+        if r is not None and r["traffic"] is not None:
+            r["traffic_gbps"] = round(r["traffic"] / (avg_us * 1e-6) / 1e9, 1)
+        return r
+
+    roof = roofline(dominant, recs[dominant])
+    if roof is not None:
+        # the kernel with the next largest total time (the two trade places
+        # from run to run at this workload)
+        roof["runner_up"] = roofline(second, recs[second])
 
     out = {
         "metric": METRIC, "value": round(P.t / (ms_per_step * 1e-3), 1),
