@@ -123,6 +123,11 @@ struct LzJob {
   int klast;                  // k - 1
   int nb;                     // row blocks of 64 rpl rows
   int rpl;                    // rows per lane of the row kernels (1 or 4)
+  // psum = 1: the second pass sums the first pass's partial rows itself
+  // (block 0 stores coef) and writes its own rows to partial2, which the
+  // finalize step sums (no column-sum launches; for small nb)
+  int psum;
+  double* partial2;           // nb x LDP
 };
 
 // Rt[u, :] = (L^{-1} R[:, u])^T

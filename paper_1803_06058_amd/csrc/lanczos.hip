@@ -326,6 +326,16 @@ __global__ __launch_bounds__(BLK) void k_colsum(Tab tab, const SumJob* __restric
 // GP, so a GP's row blocking (hence its summation order) is the same in a
 // batch as in its own build.
 // LOVE_ROWS_PER_LANE=1|4 overrides (tuning).
+// Whether a Lanczos run over nb row blocks sums its partial rows inside the
+// consuming kernels (every block adds all nb rows, so the cost grows as nb^2)
+// rather than in column-sum launches: measured about even at 160 blocks and
+// slower at 391.  LOVE_PSUM_MAX_NB=<blocks> overrides the limit (tuning).
+static bool lz_psum(int64_t nb) {
+  const char* env = std::getenv("LOVE_PSUM_MAX_NB");
+  const int64_t lim = env ? std::atoll(env) : 160;
+  return nb <= lim;
+}
+
 static int rows_per_lane(int64_t rows) {
   const char* env = std::getenv("LOVE_ROWS_PER_LANE");
   if (env && (env[0] == '1' || env[0] == '4')) return env[0] - '0';
@@ -505,6 +515,33 @@ __device__ __forceinline__ void gpass_coef(const LzJob<T>& J, int j, int lb, dou
   }
 }
 
+// cl[c] = sum of the rows b < nrows of part (stride LDP) at column c, for
+// c < ncols <= LDP.  Columns go in chunks of 128 (64 for a last chunk of
+// <= 64); each chunk's rows are added in a fixed order (RBLK / chunk width
+// interleaved row sets, then the sets in order), so every block gets the
+// same sums.
+__device__ __forceinline__ void rows_sum(const double* part, int nrows, int ncols, double* cl) {
+  __shared__ double ps[RBLK];
+  for (int c0 = 0; c0 < ncols; c0 += 128) {
+    const int sh = ncols - c0 <= 64 ? 6 : 7;
+    const int w = 1 << sh, np = RBLK >> sh;
+    const int c = threadIdx.x & (w - 1), p = threadIdx.x >> sh;
+    double s = 0.0;
+    if (c0 + c < ncols) {
+#pragma unroll 8
+      for (int b = p; b < nrows; b += np) s += part[(size_t)b * LDP + c0 + c];
+    }
+    ps[threadIdx.x] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < w && c0 + (int)threadIdx.x < ncols) {
+      double t = 0.0;
+      for (int q = 0; q < np; ++q) t += ps[q * w + threadIdx.x];
+      cl[c0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
 // Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].  With the
 // grid-space first pass, v = W R_j + sigma^2 q_j is formed here and c comes
 // from the cdots rows.
@@ -530,6 +567,11 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
       vrow = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) +
              J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
     gpass_coef<T>(J, j, lb, cl);
+  } else if (J.psum) {
+    if (t < RBK && row < J.n) vrow = J.v[row];
+    rows_sum(J.partial, J.nb, ncols, cl);
+    if (lb == 0)
+      for (int c = threadIdx.x; c < ncols; c += RBLK) J.coef[c] = cl[c];
   } else {
     if (t < RBK && row < J.n) vrow = J.v[row];
     for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
@@ -551,7 +593,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   __syncthreads();
   double vv[RPL];
   lane_rows<RPL>(rl, vv);
-  double* prow = J.partial + (size_t)lb * LDP;
+  double* prow = (J.psum ? J.partial2 : J.partial) + (size_t)lb * LDP;
   coldots_regs<T, RPL>(qr, ncols, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
@@ -577,11 +619,16 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   __shared__ double red[CWV][REDW];
   __shared__ double s_beta;
   __shared__ int s_stop;
+  __shared__ double c2l[LDP];
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t r0 = (int64_t)lb * RBK, rowL = r0 + RPL * lane;
   QRegs<T, RPL> qr;
   qregs_load<T, RPL>(qr, J.Q, J.ldq, j + 1, rowL);
   const double* c2rr = J.c2;
+  if (J.psum) {
+    rows_sum(J.partial2, J.nb, j + 2, c2l);
+    c2rr = c2l;
+  }
   for (int c = threadIdx.x; c <= j; c += RBLK) cl[c] = c2rr[c];
   if (threadIdx.x < WAVE) {
     double c2n = 0.0;
@@ -1677,12 +1724,12 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   const int64_t ldq = cdiv(m, RB) * RB;
   const int64_t nb = ldq / (WAVE * RPL);
   double *Q, *v, *r, *kv, *gv, *sv, *alpha, *beta, *vout, *lam, *lasc, *dscr, *tsc, *partial,
-      *coef, *c2, *amax;
+      *partial2, *coef, *c2, *amax;
   char* buf = nullptr;
   {
     size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 8 * LDP +
                                      3 * MAXK * MAXK + (size_t)toeplitz_scratch_elems(c) +
-                                     (size_t)nb * LDP);
+                                     2 * (size_t)nb * LDP);
     LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
     Q = (double*)buf;
     v = Q + (size_t)ldq * ks;
@@ -1701,6 +1748,7 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     dscr = vout + MAXK * MAXK;
     tsc = dscr + 2 * MAXK * MAXK;
     partial = tsc + toeplitz_scratch_elems(c);
+    partial2 = partial + (size_t)nb * LDP;
   }
   Ctl* ctl = c->ctl_s;
   const Ctl* cm = c->ctl;
@@ -1721,6 +1769,8 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   J.klast = ks - 1;
   J.nb = (int)nb;
   J.rpl = RPL;
+  J.psum = lz_psum(nb) ? 1 : 0;
+  J.partial2 = partial2;
   SumJob js_rt{partial, sv, ctl, (int)nb, c->k};
   SumJob js_coef{partial, coef, ctl, (int)nb, 1};
   SumJob js_c2{partial, c2, ctl, (int)nb, 2};
@@ -1776,9 +1826,9 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     }
     tlaunch("sp_apply", k_sp_apply_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, kv, c->rt,
             rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl);
-    launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+    if (!J.psum) launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
     tlaunch("sp_udots", k_lz_udots<double, 1>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
-    launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
+    if (!J.psum) launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
     tlaunch("sp_finalize", k_lz_finalize<double>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
   }
   {
@@ -1940,7 +1990,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   std::vector<const Ctl*> ctls(G);
   std::vector<int64_t> b_rows(G), b_nodes(G), b_m(G), b_one(G, 1), b_grid(G);
   std::vector<int> nv1(G, 1);
-  const std::vector<int> nv2(G, 2);   // columns of the coef / c2 sums at j = 0
+  std::vector<int> nv2(G, 2);   // columns of the coef / c2 sums at j = 0
   std::vector<int64_t> b_gd(G), b_cd(G), js_in(G);
   int kmax = 0;
   for (int g = 0; g < G; ++g) {
@@ -2014,6 +2064,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     rj[g] = Rj;
     s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
     nv1[g] = J.gpath ? -(1 << 20) : 1;   // no first-pass sums on the grid-space path
+    if (J.gpath && lz_psum(nb)) {
+      lz[g].psum = 1;
+      lz[g].partial2 = b.partial;   // udots reads only the cdots rows here
+      nv2[g] = -(1 << 20);
+    }
     b_gd[g] = J.gpath ? 0 : nb;
     b_cd[g] = J.nbc;
     js_in[g] = J.gpath ? b.ldg : 0;

@@ -304,6 +304,38 @@ def test_sampler_eigensolver_paths_agree(scale):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("scale", [0.05, 1.0])
+def test_partial_sum_routes_agree(scale, monkeypatch):
+    """The Lanczos runs add their per-block partial rows either in column-sum
+    launches or inside the consuming kernels (chosen by row-block count;
+    LOVE_PSUM_MAX_NB moves the limit).  Both routes give the same variances
+    and sampler covariance up to summation order, and both meet the oracle."""
+    P = WL.config(2, scale=scale, s=16)
+    xs = P.xs_sample[:300]
+    spec = spec_of(P)
+    Ws = O.interp_matrix(xs.astype(np.float64), spec)
+    p = O.prior_var(xs, spec)
+    oc = oracle_cache(P)
+    _, v_ref = O.love_predict(oc, xs)
+    res = []
+    for lim in ("0", "1000000"):
+        monkeypatch.setenv("LOVE_PSUM_MAX_NB", lim)
+        cache = build(P)
+        inf = cache.info()
+        _, var = cache.predict_mean_var(tdev(xs, torch.float32))
+        F = Ws @ host(cache.export()["s"])
+        res.append((inf.k_eff, inf.k_eff_sample, host(var), F @ F.T))
+        cache.free()
+    monkeypatch.delenv("LOVE_PSUM_MAX_NB")
+    (k0, ks0, v0, c0), (k1, ks1, v1, c1) = res
+    assert (k0, ks0) == (k1, ks1)
+    print(k0, ks0, np.max(np.abs(v0 - v1) / p), flush=True)
+    assert np.max(np.abs(v0 - v1) / p) <= 1e-6
+    assert np.max(np.abs(c0 - c1) / np.sqrt(np.outer(p, p))) <= 1e-6
+    for v in (v0, v1):
+        assert np.max(np.abs(v - v_ref) / p) <= 1e-5
+
+
 def test_sampler_monte_carlo():
     """Sample mean and covariance of 20000 GPU draws at 12 points against the
     implied covariance (statistical tolerance, 6 standard errors)."""
