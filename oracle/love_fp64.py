@@ -20,6 +20,7 @@ Processes", ICML 2018):
   * LOVE sampling matrix S ...................... Sec. 3.3, eqs. pred_covar_ski_interp_form12,
                                                     lancapprox, pred_covar_ski_interp_form
   * full reorthogonalisation .................... Sec. 5, "Numerical stability of Lanczos"
+  * additive kernel compositions ................ Sec. 3.4, eq. multi_dimensional_kernel_block
 
 Readings of points the paper leaves open (each is listed in the design notes):
   grid      padded regular grid, h = (hi-lo)/(m-3), u_j = lo + (j-1) h
@@ -37,6 +38,9 @@ Readings of points the paper leaves open (each is listed in the design notes):
             zero) S = Q' V diag(max(lam, 0))^{1/2} from T' = V diag(lam) V^T,
             which gives the same S S^T whenever the Cholesky exists
   noise     `noise` is sigma^2 (a variance)
+  additive  k(x, x') = outputscale * sum_d k_d(x_d, x'_d): one 1-D component per
+            dimension on that dimension's grid; the stacked grid holds the
+            axes one after another (axis 0 first), K is block diagonal
 """
 from __future__ import annotations
 
@@ -57,7 +61,8 @@ class Spec:
     """A KISS-GP problem: regular grid, product stationary kernel, noise.
 
     m[d], lo[d], hi[d]: grid points and data domain per dimension (Sec. 2.3).
-    kernel: "rbf" or "matern52" (product over dimensions).
+    kernel: "rbf" or "matern52" (product over dimensions, or a sum of 1-D
+    components when additive: Sec. 3.4).
     lengthscale[d], outputscale, noise (= sigma^2, eq. pred_covar).
     """
     m: Tuple[int, ...]
@@ -67,6 +72,7 @@ class Spec:
     lengthscale: Tuple[float, ...] = (0.1,)
     outputscale: float = 1.0
     noise: float = 0.01
+    additive: bool = False
 
     @property
     def d(self) -> int:
@@ -74,7 +80,11 @@ class Spec:
 
     @property
     def mtot(self) -> int:
-        return int(np.prod(self.m))
+        return int(np.sum(self.m)) if self.additive else int(np.prod(self.m))
+
+    def offset(self, dim: int) -> int:
+        """First index of axis `dim`'s block in the stacked additive grid."""
+        return int(np.sum(self.m[:dim]))
 
     def h(self, dim: int) -> float:
         return (self.hi[dim] - self.lo[dim]) / (self.m[dim] - 3)
@@ -130,11 +140,16 @@ def stencil_axis(x, spec: Spec, dim: int):
 
 
 def interp_matrix(X, spec: Spec) -> sp.csr_matrix:
-    """W (n x m): row i is w(x_i)^T with 4^d non-zeros (eq. ski, transposed)."""
+    """W (n x m): row i is w(x_i)^T with 4^d non-zeros (eq. ski, transposed).
+
+    Additive (Sec. 3.4): row i stacks the d per-axis vectors w^(e)(x_ie),
+    4 d non-zeros (eq. multi_dimensional_kernel_block)."""
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
     if X.shape[1] != spec.d:
         X = X.reshape(-1, spec.d)
     n, d = X.shape
+    if spec.additive:
+        return _stacked(X, spec, [stencil_axis(X[:, e], spec, e)[1] for e in range(d)])
     cols = np.zeros((n, 1), dtype=np.int64)
     vals = np.ones((n, 1), dtype=np.float64)
     for dim in range(d):
@@ -147,11 +162,30 @@ def interp_matrix(X, spec: Spec) -> sp.csr_matrix:
     return W
 
 
+def _stacked(X, spec: Spec, wts) -> sp.csr_matrix:
+    """Additive block form: axis e's 4 weights wts[e] at columns offset(e) + j_e + 0..3."""
+    n, d = X.shape
+    cols, vals = [], []
+    for e in range(d):
+        j, _, _ = stencil_axis(X[:, e], spec, e)
+        cols.append(spec.offset(e) + j[:, None] + np.arange(4)[None, :])
+        vals.append(wts[e])
+    cols = np.concatenate(cols, axis=1)
+    vals = np.concatenate(vals, axis=1)
+    rows = np.repeat(np.arange(n), cols.shape[1])
+    return sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(n, spec.mtot))
+
+
 def interp_grad_matrices(X, spec: Spec) -> List[sp.csr_matrix]:
-    """d W / d x_dim for each dim: same sparsity, derivative weights in dim `dim`."""
+    """d W / d x_dim for each dim: same sparsity, derivative weights in dim `dim`.
+
+    Additive: only axis dim's block depends on x_dim (the others are zero)."""
     X = np.atleast_2d(np.asarray(X, dtype=np.float64)).reshape(-1, spec.d)
     n, d = X.shape
     per = [stencil_axis(X[:, e], spec, e) for e in range(d)]
+    if spec.additive:
+        return [_stacked(X, spec, [per[e][2] if e == dim else np.zeros_like(per[e][1])
+                                   for e in range(d)]) for dim in range(d)]
     out = []
     for dim in range(d):
         cols = np.zeros((n, 1), dtype=np.int64)
@@ -186,7 +220,11 @@ def toeplitz_column(spec: Spec, dim: int) -> np.ndarray:
 
 
 def K_dense(spec: Spec) -> np.ndarray:
-    """Dense K_UU = outputscale * kron(T_1, ..., T_d) (small grids only)."""
+    """Dense K_UU = outputscale * kron(T_1, ..., T_d) (small grids only);
+    additive: outputscale * blockdiag(T_1, ..., T_d)."""
+    if spec.additive:
+        return spec.outputscale * sla.block_diag(
+            *[sla.toeplitz(toeplitz_column(spec, e)) for e in range(spec.d)])
     K = np.ones((1, 1))
     for dim in range(spec.d):
         K = np.kron(K, sla.toeplitz(toeplitz_column(spec, dim)))
@@ -201,6 +239,19 @@ def K_apply(spec: Spec, G: np.ndarray) -> np.ndarray:
     G = np.asarray(G, dtype=np.float64)
     vec = G.ndim == 1
     B = 1 if vec else G.shape[1]
+    if spec.additive:
+        # block diagonal: each axis's own block of the stacked grid (Sec. 3.4)
+        G2 = G.reshape(spec.mtot, B)
+        Y = np.empty_like(G2)
+        for e in range(spec.d):
+            blk = slice(spec.offset(e), spec.offset(e) + spec.m[e])
+            c = toeplitz_column(spec, e)
+            if spec.m[e] <= 512:
+                Y[blk] = sla.toeplitz(c) @ G2[blk]
+            else:
+                Y[blk] = sla.matmul_toeplitz((c, c), G2[blk], check_finite=False)
+        Y = spec.outputscale * Y
+        return Y[:, 0] if vec else Y
     Y = G.reshape(*spec.m, B)
     for dim in range(spec.d):
         c = toeplitz_column(spec, dim)
@@ -220,8 +271,16 @@ def prior_var(Xs, spec: Spec) -> np.ndarray:
     """p(x*) = w*^T K_UU w*  (interpolated prior variance, the k_{x*x*} term).
 
     For tensor-product w and Kronecker K this is outputscale * prod_d w_d^T T_d w_d,
-    where only the 4x4 block of T_d on the stencil nodes enters."""
+    where only the 4x4 block of T_d on the stencil nodes enters; additive:
+    outputscale * sum_d w_d^T T_d w_d."""
     Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64)).reshape(-1, spec.d)
+    if spec.additive:
+        p = np.zeros(Xs.shape[0])
+        for dim in range(spec.d):
+            _, w, _ = stencil_axis(Xs[:, dim], spec, dim)
+            T4 = sla.toeplitz(toeplitz_column(spec, dim)[:4])
+            p += np.einsum("ia,ab,ib->i", w, T4, w)
+        return spec.outputscale * p
     p = np.full(Xs.shape[0], spec.outputscale)
     for dim in range(spec.d):
         _, w, _ = stencil_axis(Xs[:, dim], spec, dim)
@@ -234,6 +293,13 @@ def prior_var(Xs, spec: Spec) -> np.ndarray:
 def prior_var_grad(Xs, spec: Spec) -> np.ndarray:
     """d p / d x*_dim (t x d)."""
     Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64)).reshape(-1, spec.d)
+    if spec.additive:
+        g = np.empty_like(Xs)
+        for dim in range(spec.d):
+            _, w, dw = stencil_axis(Xs[:, dim], spec, dim)
+            T4 = sla.toeplitz(toeplitz_column(spec, dim)[:4])
+            g[:, dim] = 2.0 * spec.outputscale * np.einsum("ia,ab,ib->i", dw, T4, w)
+        return g
     per = []
     for dim in range(spec.d):
         _, w, dw = stencil_axis(Xs[:, dim], spec, dim)

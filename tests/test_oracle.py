@@ -359,6 +359,111 @@ def test_predict_grad_fd():
 
 
 # ---------------------------------------------------------------------------
+# Additive compositions (Sec. 3.4, eq. multi_dimensional_kernel_block)
+# ---------------------------------------------------------------------------
+def additive_problem(n=150, m=(14, 23), ell=(0.15, 0.25), kernel="rbf", noise=0.05, seed=5, t=40):
+    rng = np.random.default_rng(seed)
+    d = len(m)
+    x = rng.uniform(0, 1, size=(n, d))
+    y = np.sin(5 * x).sum(1) + 0.1 * rng.standard_normal(n)
+    xs = rng.uniform(0, 1, size=(t, d))
+    spec = O.Spec(tuple(m), (0.0,) * d, (1.0,) * d, kernel, tuple(ell), 1.3, noise, True)
+    return spec, x, y, xs
+
+
+def component(spec, e):
+    """Axis e alone as a 1-D problem (pinned by the 1-D tests above)."""
+    return O.Spec((spec.m[e],), (spec.lo[e],), (spec.hi[e],), spec.kernel, (spec.lengthscale[e],),
+                  spec.outputscale, spec.noise)
+
+
+@pytest.mark.parametrize("kernel", ["rbf", "matern52"])
+def test_additive_is_sum_of_1d_components(kernel):
+    """The block form equals the sum of the d one-dimensional SKI kernels:
+    W K W^T = sum_e W_e K_e W_e^T, p(x*) = sum_e p_e(x*_e), and the stacked
+    interpolation row has 4 d entries, 4 per axis, each group summing to 1."""
+    spec, x, y, xs = additive_problem(m=(14, 23, 9), ell=(0.15, 0.25, 0.4), kernel=kernel, n=90)
+    W = O.interp_matrix(x, spec)
+    assert W.shape == (90, 14 + 23 + 9)
+    assert (np.diff(W.indptr) == 12).all()
+    Wd = W.toarray()
+    for e, (a, b) in enumerate([(0, 14), (14, 37), (37, 46)]):
+        assert np.allclose(Wd[:, a:b].sum(1), 1.0, atol=1e-14)
+    A = O.Operator(x, spec).dense()
+    ref = spec.noise * np.eye(90)
+    for e in range(3):
+        c = component(spec, e)
+        ref += O.Operator(x[:, e:e + 1], c).dense() - spec.noise * np.eye(90)
+    assert np.max(np.abs(A - ref)) < 1e-12
+    p = O.prior_var(xs, spec)
+    pe = sum(O.prior_var(xs[:, e:e + 1], component(spec, e)) for e in range(3))
+    assert np.max(np.abs(p - pe)) < 1e-13
+    g = np.random.default_rng(0).standard_normal(spec.mtot)
+    assert np.max(np.abs(O.K_apply(spec, g) - O.K_dense(spec) @ g)) < 1e-12
+
+
+def test_additive_one_axis_equals_product():
+    spec, x, y, xs = additive_problem(m=(30,), ell=(0.1,))
+    prod = component(spec, 0)
+    assert spec.mtot == prod.mtot == 30
+    assert abs(O.interp_matrix(x, spec) - O.interp_matrix(x, prod)).max() == 0
+    c1 = O.love_build(x, y, spec, k=20)
+    c2 = O.love_build(x, y, prod, k=20)
+    m1, v1 = O.love_predict(c1, xs)
+    m2, v2 = O.love_predict(c2, xs)
+    assert np.array_equal(v1, v2) and np.array_equal(m1, m2)
+
+
+def test_additive_ski_converges_to_exact_kernel():
+    """Cubic interpolation of each component: |W K W^T - sum_e k_e| falls by
+    about 2^3 each time the grids are refined twofold."""
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, 1, (60, 2))
+    ell = (0.2, 0.3)
+    exact = 1.3 * sum(np.exp(-0.5 * ((x[:, e][:, None] - x[:, e][None, :]) / ell[e]) ** 2)
+                      for e in range(2))
+    errs = []
+    for m in (20, 40, 80, 160):
+        spec = O.Spec((m, m + 7), (0.0, 0.0), (1.0, 1.0), "rbf", ell, 1.3, 0.05, True)
+        W = O.interp_matrix(x, spec).toarray()
+        errs.append(np.max(np.abs(W @ O.K_dense(spec) @ W.T - exact)))
+    assert errs[0] < 3e-3
+    for a, b in zip(errs, errs[1:]):
+        assert a / b > 6.0
+
+
+def test_additive_love_saturates_to_exact():
+    """k = n Lanczos steps: LOVE on the block form equals the exact
+    (route A) KISS-GP mean and variance of the additive model."""
+    spec, x, y, xs = additive_problem(n=60, noise=0.3)
+    cache = O.love_build(x, y, spec, k=60)
+    m, v = O.love_predict(cache, xs)
+    mA, vA = O.exact_route_A(x, y, xs, spec)
+    p = O.prior_var(xs, spec)
+    assert np.max(np.abs(v - vA) / p) < 1e-10
+    assert np.max(np.abs(m - mA)) < 1e-9
+    mB, vB = O.exact_route_B(x, y, xs, spec)
+    assert np.max(np.abs(vB - vA) / p) < 1e-9
+
+
+def test_additive_predict_grad_fd():
+    spec, x, y, xs = additive_problem(n=200, m=(10, 12))
+    cache = O.love_build(x, y, spec, k=30)
+    rng = np.random.default_rng(2)
+    gm, gv = rng.standard_normal(xs.shape[0]), rng.standard_normal(xs.shape[0])
+    g = O.love_predict_grad(cache, xs, gm, gv)
+    h = 1e-6
+    for e in range(2):
+        xp, xm = xs.copy(), xs.copy()
+        xp[:, e] += h
+        xm[:, e] -= h
+        mp, vp = O.love_predict(cache, xp)
+        mm, vm = O.love_predict(cache, xm)
+        fd = gm * (mp - mm) / (2 * h) + gv * (vp - vm) / (2 * h)
+        assert np.max(np.abs(fd - g[:, e])) < 1e-5 * (1 + np.max(np.abs(g[:, e])))
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: each plausible slip in the oracle must break a pin above.
 # ---------------------------------------------------------------------------
 def _ok(fn):
@@ -409,6 +514,18 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with monkeypatch.context() as mp:
         mp.setattr(O, "lanczos", lanczos_noreorth)
         assert not _ok(test_lanczos_invariants_config1)
+    # (6) additive blocks placed as if every axis had axis 0's size (overlapping)
+    with monkeypatch.context() as mp:
+        mp.setattr(O.Spec, "offset", lambda self, dim: self.m[0] * dim)
+        assert not _ok(lambda: test_additive_is_sum_of_1d_components("rbf"))
+    # (7) additive prior taken as a product, as for tensor-product grids
+    orig_pv = O.prior_var
+    def pv_prod(Xs, spec):
+        return orig_pv(Xs, O.Spec(spec.m, spec.lo, spec.hi, spec.kernel, spec.lengthscale,
+                                  spec.outputscale, spec.noise, False))
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "prior_var", pv_prod)
+        assert not _ok(test_additive_love_saturates_to_exact)
     # (5) mean cache missing the K factor
     with monkeypatch.context() as mp:
         mp.setattr(O, "mean_cache", lambda op, y, tol=1e-12, maxit=2000:
