@@ -91,6 +91,17 @@ typedef enum {
 #define LOVE_FLAG_EIG_QL 8u         /* sampler: eigenvectors of T' by implicit QL (slow path)     */
 #define LOVE_FLAG_MEAN_KRYLOV 16u   /* mean solve: data-space CG even where the grid-space solve
                                        applies (d >= 2 with every m_i <= 128)                     */
+#define LOVE_FLAG_ADDITIVE 32u      /* additive composition (Sec. 3.4, eq.
+                                       multi_dimensional_kernel_block):
+                                       k(x, x') = outputscale * sum_i k_i(x_i, x'_i), one 1-D
+                                       component per dimension on that dimension's grid.  The
+                                       grid vectors (Rt rows, the mean cache a, S rows) stack the
+                                       axes one after another, axis 0 first: m = sum_i m_i, and
+                                       K is block diagonal.  Builds, love_predict_mean_var(_batched),
+                                       love_apply_khat / _kuu, export and import support it; the
+                                       covariance, sampling and backward entry points return
+                                       LOVE_EUNSUPPORTED for such a cache.  Every GP of a batched
+                                       build must agree on this flag.                             */
 
 typedef struct {
   int32_t d;                        /* input dimension, 1..4                                     */

@@ -6,6 +6,7 @@ pointers and the current HIP stream are handed to the native library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -17,6 +18,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16split": 2}
 KERNELS = {"rbf": 0, "matern52": 1}
 TOEPLITZ_MODES = {"auto": 0, "direct": 1, "fft": 2}
 FLAG_ASYNC, FLAG_NO_MEAN, FLAG_PLAIN_CG, FLAG_EIG_QL, FLAG_MEAN_KRYLOV = 1, 2, 4, 8, 16
+FLAG_ADDITIVE = 32   # additive composition: grid vectors stack the axes, m = sum of m_i
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "EDOMAIN", -3: "ENOTPD", -4: "ENOMEM", -5: "EHIP",
           -6: "ENONFINITE", -7: "EUNSUPPORTED"}
@@ -192,9 +194,8 @@ class LoveCache:
         self.cfg = cfg
         self.d = cfg.d
         self.dtype = _dtype(cfg.precision)
-        self.m = 1
-        for e in range(cfg.d):
-            self.m *= int(cfg.m[e])
+        sizes = [int(cfg.m[e]) for e in range(cfg.d)]
+        self.m = sum(sizes) if cfg.flags & FLAG_ADDITIVE else math.prod(sizes)
 
     # -- lifetime --------------------------------------------------------
     def free(self):

@@ -131,14 +131,21 @@ void* dev_alloc(love_cache* c, size_t bytes) {
 static love_status validate(const love_config* cfg) {
   if (!cfg) return LOVE_EINVAL;
   if (cfg->d < 1 || cfg->d > LOVE_MAX_DIM) return LOVE_EINVAL;
-  int64_t mt = 1, ct = 1;
+  const bool add = cfg->flags & LOVE_FLAG_ADDITIVE;
+  int64_t mt = add ? 0 : 1, ct = add ? 0 : 1;
   for (int e = 0; e < cfg->d; ++e) {
     if (cfg->m[e] < 4) return LOVE_EINVAL;
     if (!(cfg->hi[e] > cfg->lo[e]) || !std::isfinite(cfg->lo[e]) || !std::isfinite(cfg->hi[e]))
       return LOVE_EINVAL;
     if (!(cfg->lengthscale[e] > 0) || !std::isfinite(cfg->lengthscale[e])) return LOVE_EINVAL;
-    mt *= cfg->m[e];
-    ct *= cfg->m[e] - 3;
+    if (add) {
+      if (cfg->m[e] > (1 << 24)) return LOVE_EINVAL;
+      mt += cfg->m[e];
+      ct += cfg->m[e] - 3;
+    } else {
+      mt *= cfg->m[e];
+      ct *= cfg->m[e] - 3;
+    }
     if (mt > (int64_t(1) << 31) || ct > (int64_t(1) << 30)) return LOVE_EINVAL;
   }
   if (!(cfg->outputscale > 0) || !std::isfinite(cfg->outputscale)) return LOVE_EINVAL;
@@ -161,15 +168,23 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->n = n;
   c->stream = s;
   (void)hipGetDevice(&c->device);
-  int64_t m = 1, ct = 1;
+  c->add = (cfg->flags & LOVE_FLAG_ADDITIVE) != 0;
+  int64_t m = c->add ? 0 : 1, ct = c->add ? 0 : 1;
   for (int e = 0; e < 4; ++e) {
     if (e < c->d) {
       c->mdim[e] = cfg->m[e];
       c->lo[e] = cfg->lo[e];
       c->hi[e] = cfg->hi[e];
       c->invh[e] = (double)(cfg->m[e] - 3) / (cfg->hi[e] - cfg->lo[e]);
-      m *= cfg->m[e];
-      ct *= cfg->m[e] - 3;
+      if (c->add) {
+        c->aoff[e] = m;
+        c->acoff[e] = ct;
+        m += cfg->m[e];
+        ct += cfg->m[e] - 3;
+      } else {
+        m *= cfg->m[e];
+        ct *= cfg->m[e] - 3;
+      }
     } else {
       c->mdim[e] = 1;
       c->lo[e] = c->hi[e] = 0.0;
@@ -189,8 +204,9 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   {
     // everything the cache keeps, in one block: the buffers below, the
     // Toeplitz coefficient columns and first-four table, the Toeplitz scratch
+    const size_t nperm = (size_t)n * (c->add ? c->d : 1);
     size_t want = dev_round(es * (size_t)n * c->d) + dev_round(es * (size_t)n) +
-                  dev_round(4 * (size_t)n) + dev_round(4 * (size_t)(ct + 1)) +
+                  dev_round(4 * nperm) + dev_round(4 * (size_t)(ct + 1)) +
                   dev_round(2 * sizeof(Ctl) + 4 * sizeof(unsigned)) + dev_round(sizeof(double)) +
                   2 * dev_round(sizeof(double) * LOVE_MAX_K) +
                   dev_round((split ? 2 : es) * (size_t)m * c->kpad) +
@@ -205,7 +221,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   }
   c->x = dev_alloc(c, es * (size_t)n * c->d);
   c->y = dev_alloc(c, es * (size_t)n);
-  c->perm = (int32_t*)dev_alloc(c, 4 * (size_t)n);
+  c->perm = (int32_t*)dev_alloc(c, 4 * (size_t)n * (c->add ? c->d : 1));
   c->cell_start = (int32_t*)dev_alloc(c, 4 * (size_t)(ct + 1));
   // the two control blocks and the status words are contiguous (one clear)
   c->ctl = (Ctl*)dev_alloc(c, 2 * sizeof(Ctl) + 4 * sizeof(unsigned));
@@ -369,12 +385,15 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
     if (cellp) (void)hipFreeAsync(cellp, s);
     return st;
   }
-  launch_permute<T>(v, (T*)c->v1, c->perm, c->n, 0, s);
+  // rows of an additive cache stay in caller order (perm holds the axes' cell lists)
+  if (c->add) LOVE_HIP_TRY(hipMemcpyAsync(c->v1, v, sizeof(T) * c->n, hipMemcpyDeviceToDevice, s));
+  else launch_permute<T>(v, (T*)c->v1, c->perm, c->n, 0, s);
   launch_scatter<T>(tab1(cdiv(c->m, 4)), A.at<ScatterJob<T>>(os), c->d, 0, 0, s,
                     scatter_kinds(one));
   toep_run<T>(A, run, 0, 0, s);
   launch_gather<T>(tab1(cdiv(c->n, 256)), A.at<GatherJob<T>>(og), c->d, 0, s);
-  launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);
+  if (c->add) LOVE_HIP_TRY(hipMemcpyAsync(out, c->v2, sizeof(T) * c->n, hipMemcpyDeviceToDevice, s));
+  else launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);
   A.release(s);
   if (cellp) (void)hipFreeAsync(cellp, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
@@ -426,6 +445,8 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
     if (cfgs[g].precision != cfgs[0].precision || cfgs[g].d != cfgs[0].d) return LOVE_EINVAL;
     if (!xs[g] || !ys[g] || ns[g] < 1 || ns[g] > INT32_MAX) return LOVE_EINVAL;
     if ((cfgs[g].flags & LOVE_FLAG_NO_MEAN) != (cfgs[0].flags & LOVE_FLAG_NO_MEAN))
+      return LOVE_EINVAL;
+    if ((cfgs[g].flags & LOVE_FLAG_ADDITIVE) != (cfgs[0].flags & LOVE_FLAG_ADDITIVE))
       return LOVE_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -499,6 +520,7 @@ love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* ca
 love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
                                      int64_t t, void* cov, void* stream) {
   if (!c || t < 0 || (t > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
+  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64) return covar_pairs<double>(c, (const double*)xa, (const double*)xb, t, (double*)cov, s);
   return covar_pairs<float>(c, (const float*)xa, (const float*)xb, t, (float*)cov, s);
@@ -507,6 +529,7 @@ love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const 
 love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
                                      const void* xb, int64_t tb, void* cov, void* stream) {
   if (!c || ta < 0 || tb < 0 || (ta > 0 && tb > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
+  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64)
     return covar_block<double>(c, (const double*)xa, ta, (const double*)xb, tb, (double*)cov, s);
@@ -516,7 +539,7 @@ love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_
 love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
                                   int64_t ns, void* out, void* stream) {
   if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;
-  if (c->ks <= 0) return LOVE_EUNSUPPORTED;
+  if (c->ks <= 0 || c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64) return sample<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
   return sample<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
@@ -526,6 +549,7 @@ love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t
                                   const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
                                   void* stream) {
   if (!c || t < 0 || (t > 0 && (!xs || !g_xs))) return LOVE_EINVAL;
+  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64)
     return backward<double>(c, (const double*)xs, t, (const double*)g_mean, (const double*)g_var,

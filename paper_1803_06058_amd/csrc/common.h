@@ -32,6 +32,12 @@ struct GridT {
   // to 1).
   int cell_f;
   float lo_f[MAXD], invh_f[MAXD];
+  // additive composition: add = 1, the grid is the axes' 1-D grids one after
+  // another (axis e's nodes from aoff[e], its cells from acoff[e]); the rows
+  // are in caller order and aperm lists each axis's rows by cell
+  int add;
+  int64_t aoff[MAXD], acoff[MAXD];
+  const int32_t* aperm;
 };
 
 // Keys cubic convolution weights (a = -1/2) for a point at fraction s in [0,1]

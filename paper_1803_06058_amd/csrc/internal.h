@@ -87,11 +87,16 @@ struct love_cache {
   // geometry (double master copy)
   double lo[4], hi[4], invh[4];
   int mdim[4];
+  // additive composition (LOVE_FLAG_ADDITIVE): the grid stacks the axes;
+  // axis e's nodes start at aoff[e], its stencil cells at acoff[e]
+  bool add = false;
+  int64_t aoff[4] = {0, 0, 0, 0}, acoff[4] = {0, 0, 0, 0};
   // sorted training data
   void* x = nullptr;          // n x d, sorted by cell
   void* y = nullptr;          // n, sorted
-  int32_t* perm = nullptr;    // sorted position -> caller row
-  int32_t* cell_start = nullptr;  // ctot + 1
+  int32_t* perm = nullptr;    // sorted position -> caller row (additive: d x n, axis e's rows
+                              // in order of their axis-e cell, caller order within a cell)
+  int32_t* cell_start = nullptr;  // ctot + 1 (additive: positions in perm)
   int64_t ctot = 0;
   love::ToepPlan toep;
   double c4[4][4];            // first four entries of each axis column (outputscale in axis 0)

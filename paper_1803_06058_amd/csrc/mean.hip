@@ -483,7 +483,7 @@ __global__ void k_spec_alldone(int G, const SpecJob* __restrict__ jobs, int* fla
 }  // namespace
 
 bool spectral_mean_applies(const love_cache* c) {
-  if (c->d < 2) return false;
+  if (c->d < 2 || c->add) return false;   // needs the Kronecker (product) structure
   if (c->cfg.flags & (LOVE_FLAG_PLAIN_CG | LOVE_FLAG_MEAN_KRYLOV)) return false;
   for (int e = 0; e < c->d; ++e)
     if (c->mdim[e] > SPEC_MAXM) return false;

@@ -50,6 +50,18 @@ GridT<T> make_grid(const love_cache* c) {
   g.mtot = ns;
   g.ctot = cs;
   g.cell_f = c->fp64 ? 0 : 1;
+  if (c->add) {
+    g.add = 1;
+    g.mtot = c->m;
+    g.ctot = c->ctot;
+    for (int e = 0; e < MAXD; ++e) {
+      g.aoff[e] = c->aoff[e];
+      g.acoff[e] = c->acoff[e];
+      g.nstride[e] = 0;
+      g.cstride[e] = 0;
+    }
+    g.aperm = c->perm;
+  }
   return g;
 }
 template GridT<float> make_grid<float>(const love_cache*);
@@ -104,6 +116,67 @@ __device__ __forceinline__ T scatter_rows(const GridT<T>& g, const T* x, const T
   return acc;
 }
 
+// Additive composition: node ul of axis e gathers the rows of axis-e cells
+// ul - 3 .. ul, listed (by row index) in g.aperm at positions [r0, re); lane
+// positions go r0, r0 + WAVE, ... in batches of four whose loads go out first.
+template <typename T, int D, bool COMB>
+__device__ __forceinline__ T scatter_rows_add(const GridT<T>& g, int e, int ul, const T* x,
+                                              const T* v, const T* v2, T ratio, int32_t r0,
+                                              int32_t re) {
+  using GT = const __attribute__((address_space(1))) T;
+  using GI = const __attribute__((address_space(1))) int32_t;
+  GT* gx = (GT*)x;
+  GT* gv = (GT*)v;
+  GT* gv2 = (GT*)v2;
+  GI* gp = (GI*)g.aperm;
+  constexpr int UB = 4;
+  T acc = T(0);
+  for (int32_t rs = r0; rs < re; rs += UB * WAVE) {
+    int32_t rr[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) rr[q] = gp[min(rs + q * WAVE, re - 1)];
+    T xr[UB], vr[UB], v2r[UB];
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      xr[q] = gx[(int64_t)rr[q] * D + e];
+      vr[q] = gv[rr[q]];
+      if constexpr (COMB) v2r[q] = gv2[rr[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < UB; ++q) {
+      T sq;
+      const int jj = stencil_at(g, e, xr[q], sq);
+      const T w = keys_weight_at(ul - jj, sq);
+      T val = vr[q];
+      if constexpr (COMB) val = (T)(vr[q] + ratio * v2r[q]);
+      acc += (rs + q * WAVE < re) ? w * val : T(0);
+    }
+  }
+  return acc;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void scatter_node_add(const ScatterJob<T>& J, int64_t u, int j,
+                                                 bool comb, T ratio) {
+  const GridT<T>& g = J.g;
+  const int lane = threadIdx.x & (WAVE - 1);
+  int e = 0;
+#pragma unroll
+  for (int q = 1; q < D; ++q) e = u >= g.aoff[q] ? q : e;
+  const int ul = (int)(u - g.aoff[e]);
+  const int cl = max(ul - 3, 0), ch = min(ul, g.cells[e] - 1);
+  T acc = T(0);
+  if (cl <= ch) {
+    const int32_t rb = J.cell_start[g.acoff[e] + cl];
+    const int32_t re = J.cell_start[g.acoff[e] + ch + 1];
+    const T* v = J.v + (int64_t)j * J.v_js;
+    if (comb) acc = scatter_rows_add<T, D, true>(g, e, ul, J.x, v, J.v2, ratio, rb + lane, re);
+    else acc = scatter_rows_add<T, D, false>(g, e, ul, J.x, v, J.v2, ratio, rb + lane, re);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) J.out[(int64_t)j * J.out_js + u] = acc;
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* __restrict__ jobs,
                                                  int j, int mode) {
@@ -120,6 +193,10 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t u = (int64_t)lb * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (u >= g.mtot) return;
+  if (g.add) {
+    scatter_node_add<T, D>(J, u, j, comb, ratio);
+    return;
+  }
   constexpr int RUNS = 1 << (2 * (D - 1));
   constexpr int LPR = WAVE / RUNS;
   const int run = lane / LPR, sub = lane % LPR;
@@ -169,6 +246,7 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
 // average (then stage 1 takes one wave per cell and each row is read once,
 // against four times by the one-wave-per-node kernel).
 bool scatter_two_stage(const love_cache* c) {
+  if (c->add) return false;   // additive: per-axis rows through perm, one wave per node
   return c->d >= 3 || c->n >= 64 * c->ctot;
 }
 int scatter_kinds(const std::vector<love_cache*>& cs) {
@@ -383,10 +461,13 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
         break;
     }
   }
-  if (!(kinds & SCATTER_NODES) || d >= 3) return;
+  if (!(kinds & SCATTER_NODES)) return;
   switch (d) {
     case 1: tlaunch("scatter", k_scatter<T, 1>, nb, 256, 0, s, tab, jobs, j, mode); break;
     case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
+    // d >= 3 reaches the one-wave-per-node kernel only for additive compositions
+    case 3: tlaunch("scatter", k_scatter<T, 3>, nb, 256, 0, s, tab, jobs, j, mode); break;
+    case 4: tlaunch("scatter", k_scatter<T, 4>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
 template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t,
@@ -551,8 +632,10 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
                   const std::vector<T*>& scratch, const std::vector<const Ctl*>& ctl) {
   const int G = (int)cs.size();
   const int d = cs[0]->d;
+  const bool add = cs[0]->add;   // a batch agrees on the composition
   run.d = d;
-  // axes applied last-to-first; intermediate results ping-pong through the scratch halves
+  // axes applied last-to-first; intermediate results ping-pong through the scratch halves.
+  // Additive: every axis maps its own block of in to the same block of out.
   for (int e = d - 1, step = 0; e >= 0; --e, ++step) {
     std::vector<ToepJob<T>> jobs(G);
     std::vector<int64_t> nband(G, 0), nred(G, 0), nlines(G, 0), nfft(G, 0);
@@ -563,10 +646,11 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
       ToepJob<T> J{};
       T* buf0 = scratch[g];
       T* buf1 = scratch[g] + c->m;
-      const bool first = (e == d - 1), last = (e == 0);
-      J.in = first ? in[g] : ((step - 1) % 2 == 0 ? buf0 : buf1);
+      const bool first = add || (e == d - 1), last = add || (e == 0);
+      const int64_t off = add ? c->aoff[e] : 0;
+      J.in = first ? in[g] + off : ((step - 1) % 2 == 0 ? buf0 : buf1);
       J.in_js = first ? in_js[g] : 0;
-      J.out = last ? out[g] : (step % 2 == 0 ? buf0 : buf1);
+      J.out = last ? out[g] + off : (step % 2 == 0 ? buf0 : buf1);
       J.out_js = last ? out_js[g] : 0;
       J.c = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
       J.spec = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
@@ -766,19 +850,20 @@ love_status toeplitz_plan(love_cache* c) {
   for (int e = c->d - 1; e >= 0; --e) {
     ToepAxis& ax = p.ax[e];
     ax.L = c->mdim[e];
-    ax.inner = inner;
-    ax.outer = c->m / (inner * ax.L);
+    // additive: K is block diagonal, each axis one line of its own block, and
+    // every block carries the outputscale
+    ax.inner = c->add ? 1 : inner;
+    ax.outer = c->add ? 1 : c->m / (inner * ax.L);
     inner *= ax.L;
+    const double scale = (e == 0 || c->add) ? c->cfg.outputscale : 1.0;
     const double h = 1.0 / c->invh[e];
     std::vector<double> col(ax.L);
-    for (int i = 0; i < ax.L; ++i)
-      col[i] = kern1d(c->cfg.kernel, i * h, c->cfg.lengthscale[e]) * (e == 0 ? c->cfg.outputscale : 1.0);
+    for (int i = 0; i < ax.L; ++i) col[i] = kern1d(c->cfg.kernel, i * h, c->cfg.lengthscale[e]) * scale;
     for (int i = 0; i < 4; ++i) c->c4[e][i] = col[i];
     ax.c64 = dev_alloc(c, sizeof(double) * ax.L);
     ax.c32 = dev_alloc(c, sizeof(float) * ax.L);
     if (!ax.c64 || !ax.c32) return LOVE_ENOMEM;
-    cj.ax[e] = CoefAxis{(double*)ax.c64, (float*)ax.c32, ax.L, h, c->cfg.lengthscale[e],
-                        e == 0 ? c->cfg.outputscale : 1.0};
+    cj.ax[e] = CoefAxis{(double*)ax.c64, (float*)ax.c32, ax.L, h, c->cfg.lengthscale[e], scale};
     maxL = std::max(maxL, ax.L);
     int mode = c->cfg.toeplitz;
     if (mode == LOVE_TOEPLITZ_AUTO) mode = autotune_choose(c, e);

@@ -25,9 +25,23 @@ __device__ inline bool ctl_skip(const Ctl* ctl, int mode) {
   return false;
 }
 
-// (W u)[r] for one row: tensor-product cubic stencil, 4^D grid values.
+// (W u)[r] for one row: tensor-product cubic stencil, 4^D grid values (4 D
+// for an additive composition, Sec. 3.4).
 template <typename T, int D>
 __device__ inline T gather_row_vals(const GridT<T>& g, const T (&xr)[D], const T* __restrict__ kg) {
+  if (g.add) {
+    // additive composition: the four nodes of every axis's own block
+    T acc = T(0);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      T s, w[4];
+      const int j = stencil_at(g, e, xr[e], s);
+      keys_weights(s, w);
+      const T* p = kg + g.aoff[e] + j;
+      acc += w[0] * p[0] + w[1] * p[1] + w[2] * p[2] + w[3] * p[3];
+    }
+    return acc;
+  }
   T w[D][4];
   int64_t base = 0;
 #pragma unroll

@@ -172,19 +172,89 @@ __device__ inline void predict_body(const PredJob<T>& J, int64_t lb) {
   }
 }
 
+// Additive composition (Sec. 3.4): the stacked interpolation vector has the
+// four nodes of each axis's own block, 4 D rows of Rt in all, and the prior
+// is the sum of the axes' w_e^T T_e w_e (outputscale in every c4 row).
+template <typename T, int D, int SPLIT, int CPL>
+__device__ inline void predict_body_add(const PredJob<T>& J, int64_t lb) {
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int64_t p = lb * PPB + threadIdx.x / PLQ;
+  const bool live = p < J.t;
+  const int64_t pc = live ? p : J.t - 1;
+  const GridT<T>& g = J.g;
+  const int kpad = J.kpad;
+  const T* acache = J.a;
+  double w[D][4];
+  int64_t base[D];
+  bool ok = true;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = J.xs[pc * D + e];
+    ok = ok && in_domain(xe, g.lo[e], g.hi[e]);
+    if (!(xe == xe)) xe = g.lo[e];
+    T sv, wt[4];
+    const int j = stencil_at(g, e, xe, sv);
+    keys_weights(sv, wt);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) w[e][o] = (double)wt[o];
+    base[e] = g.aoff[e] + j;
+  }
+  static_assert(4 * D <= PLQ, "one mean term per lane");
+  double u[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) u[q] = 0.0;
+  double mu = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4 * D; ++a) {
+    const double wa = w[a >> 2][a & 3];
+    const int64_t node = base[a >> 2] + (a & 3);
+    double r[CPL];
+    rt_row<T, SPLIT, CPL>(J.rt, J.rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) u[q] += wa * r[q];
+    if (a == sub && acache) mu += wa * (double)acache[node];
+  }
+  double uu = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) uu += u[q] * u[q];
+  uu = group_sum(uu, PLQ);
+  mu = group_sum(mu, PLQ);
+  if (sub == 0 && live) {
+    double pr = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) pr += quad4(J.c4 + 4 * e, w[e], w[e]);
+    if (ok) {
+      J.var[p] = (T)(pr - uu);
+      if (J.mean) J.mean[p] = (T)mu;
+    } else {
+      J.var[p] = (T)NAN;
+      if (J.mean) J.mean[p] = (T)NAN;
+      atomicOr(J.status, SF_DOMAIN);
+    }
+  }
+}
+
+template <typename T, int D, int SPLIT>
+__device__ __forceinline__ void predict_any(const PredJob<T>& J, int64_t lb) {
+  if (J.g.add) {
+    if (J.kpad > 64) predict_body_add<T, D, SPLIT, 8>(J, lb);
+    else predict_body_add<T, D, SPLIT, 4>(J, lb);
+  } else {
+    if (J.kpad > 64) predict_body<T, D, SPLIT, 8>(J, lb);
+    else predict_body<T, D, SPLIT, 4>(J, lb);
+  }
+}
+
 template <typename T, int D, int SPLIT>
 __global__ __launch_bounds__(256) void k_predict(PredJob<T> J) {
-  if (J.kpad > 64) predict_body<T, D, SPLIT, 8>(J, blockIdx.x);
-  else predict_body<T, D, SPLIT, 4>(J, blockIdx.x);
+  predict_any<T, D, SPLIT>(J, blockIdx.x);
 }
 
 template <typename T, int D, int SPLIT>
 __global__ __launch_bounds__(256) void k_predict_b(Tab tab, const PredJob<T>* __restrict__ jobs) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
-  const PredJob<T>& J = jobs[gp];
-  if (J.kpad > 64) predict_body<T, D, SPLIT, 8>(J, lb);
-  else predict_body<T, D, SPLIT, 4>(J, lb);
+  predict_any<T, D, SPLIT>(jobs[gp], lb);
 }
 
 template <typename T>

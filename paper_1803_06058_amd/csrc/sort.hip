@@ -244,12 +244,141 @@ love_status sort_impl(const std::vector<love_cache*>& cs, const std::vector<cons
   return LOVE_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Additive compositions: the rows stay in caller order; every (row, axis)
+// pair is a virtual row keyed by its axis-e stencil cell (axis e's cells
+// follow those of axis e - 1), so one stable sort lists, axis by axis, the
+// rows of every cell.  A GP's virtual rows occupy [row_off, row_off + d n).
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void k_cells_add(Tab tab, const SortJob<T>* __restrict__ jobs,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            uint32_t* __restrict__ count) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SortJob<T>& J = jobs[gp];
+  const int64_t i = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (i >= J.n) return;
+  const GridT<T>& g = J.g;
+  unsigned bad = 0;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = J.x[i * D + e];
+    if (!in_domain(xe, g.lo[e], g.hi[e])) bad |= SF_DOMAIN;
+    if (!(xe == xe)) xe = g.lo[e];
+    T s;
+    const int jj = stencil_at(g, e, xe, s);
+    const uint32_t key = J.cell_off + (uint32_t)(g.acoff[e] + jj);
+    const int64_t v = J.row_off + (int64_t)e * J.n + i;
+    keys[v] = key;
+    vals[v] = (uint32_t)i;
+    atomicAdd(&count[key], 1u);
+  }
+  const T yi = J.y[i];
+  if (!isfinite((double)yi)) bad |= SF_NONFINITE;
+  if (bad) atomicOr(J.status, bad);
+}
+
+// rows copied in caller order; perm = the sorted virtual rows' row indices
+template <typename T, int D>
+__global__ void k_copy_add(Tab tab, const SortJob<T>* __restrict__ jobs,
+                           const uint32_t* __restrict__ order) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const SortJob<T>& J = jobs[gp];
+  const int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
+  if (p >= J.n) return;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    J.xs[p * D + e] = J.x[p * D + e];
+    J.perm[(int64_t)e * J.n + p] = (int32_t)order[J.row_off + (int64_t)e * J.n + p];
+  }
+  J.ys[p] = J.y[p];
+}
+
+template <typename T, int D>
+love_status sort_add_impl(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,
+                          const std::vector<const T*>& ys, hipStream_t s) {
+  const int G = (int)cs.size();
+  std::vector<SortJob<T>> jobs(G);
+  std::vector<int64_t> brow(G), bcell(G);
+  int64_t N = 0, K = 0;
+  for (int g = 0; g < G; ++g) {
+    love_cache* c = cs[g];
+    SortJob<T> J{};
+    J.g = make_grid<T>(c);
+    J.x = xs[g];
+    J.y = ys[g];
+    J.xs = (T*)c->x;
+    J.ys = (T*)c->y;
+    J.perm = c->perm;
+    J.cell_start = c->cell_start;
+    J.n = c->n;
+    J.row_off = N;
+    J.ctot = c->ctot;
+    J.cell_off = (uint32_t)K;
+    J.status = c->status;
+    jobs[g] = J;
+    brow[g] = cdiv(c->n, 256);
+    bcell[g] = cdiv(c->ctot + 1, 256);
+    N += c->n * D;
+    K += c->ctot;
+  }
+  if (N >= (int64_t(1) << 31) || K >= (int64_t(1) << 31)) return LOVE_EINVAL;
+  JobArena A;
+  const size_t jo = A.add(jobs);
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  const SortJob<T>* dj = A.at<SortJob<T>>(jo);
+  const Tab trow = make_tab(brow), tcell = make_tab(bcell);
+  const int nb = (int)cdiv(N, RS_TILE);
+  uint32_t *k0, *v0, *k1, *v1, *hist, *cnt;
+  size_t bytes = sizeof(uint32_t) * (4 * (size_t)N + (size_t)RS_BINS * nb + (size_t)K + 1);
+  char* buf = nullptr;
+  LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+  k0 = (uint32_t*)buf;
+  v0 = k0 + N;
+  k1 = v0 + N;
+  v1 = k1 + N;
+  hist = v1 + N;
+  cnt = hist + (size_t)RS_BINS * nb;
+  LOVE_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (K + 1), s));
+  k_cells_add<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, k0, v0, cnt);
+  int bits = 1;
+  while ((int64_t(1) << bits) < K) ++bits;
+  const int passes = (bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    k_rs_hist<<<nb, RS_BLOCK, 0, s>>>(k0, N, shift, hist, nb);
+    k_scan_exclusive<<<1, 1024, 0, s>>>(hist, (int64_t)RS_BINS * nb, nullptr);
+    k_rs_scatter<<<nb, RS_BLOCK, 0, s>>>(k0, v0, k1, v1, N, shift, hist, nb);
+    std::swap(k0, k1);
+    std::swap(v0, v1);
+  }
+  k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, K + 1, nullptr);
+  k_cell_start<T><<<tab_blocks(tcell), 256, 0, s>>>(tcell, dj, cnt);
+  k_copy_add<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, v0);
+  LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  A.release(s);
+  LOVE_HIP_TRY(hipGetLastError());
+  return LOVE_OK;
+}
+
 }  // namespace
 
 template <typename T>
 love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,
                        const std::vector<const T*>& ys, hipStream_t s) {
   ProfScope ps("setup_sort", s);
+  if (cs[0]->add) {
+    switch (cs[0]->d) {
+      case 1: return sort_add_impl<T, 1>(cs, xs, ys, s);
+      case 2: return sort_add_impl<T, 2>(cs, xs, ys, s);
+      case 3: return sort_add_impl<T, 3>(cs, xs, ys, s);
+      case 4: return sort_add_impl<T, 4>(cs, xs, ys, s);
+    }
+    return LOVE_EINVAL;
+  }
   switch (cs[0]->d) {
     case 1: return sort_impl<T, 1>(cs, xs, ys, s);
     case 2: return sort_impl<T, 2>(cs, xs, ys, s);

@@ -40,6 +40,7 @@ class Problem:
     xs_sample: Optional[np.ndarray] = None   # t_s x d
     z: Optional[np.ndarray] = None           # k_sample x s
     precision: str = "fp32"         # "fp64" | "fp32" | "bf16split"
+    additive: bool = False          # sum of 1-D components (Sec. 3.4) instead of a product
     extra: Dict = field(default_factory=dict)
 
     @property
@@ -64,6 +65,11 @@ def _target(kind: str, x: np.ndarray) -> np.ndarray:
         return np.sin(4 * np.pi * x[:, 0]) * np.cos(4 * np.pi * x[:, 1])
     if kind == "sumsin":
         return sum(np.sin(2 * np.pi * x[:, i] * (i + 1)) for i in range(x.shape[1]))
+    if kind == "styblinski_tang":
+        # the additive Styblinski-Tang test function on [-5, 5]^d (x in [0, 1]^d
+        # mapped there), divided by 40 to unit scale
+        u = 10.0 * x - 5.0
+        return 0.5 * np.sum(u ** 4 - 16.0 * u ** 2 + 5.0 * u, axis=1) / 40.0
     raise ValueError(kind)
 
 
@@ -71,7 +77,7 @@ def make_problem(name: str, *, d: int, n: int, m: Tuple[int, ...], kernel: str,
                  lengthscale: Tuple[float, ...], noise: float, k: int, t: int,
                  target: str, ynoise: float, dtype: str = "f32", precision: str = "fp32",
                  outputscale: float = 1.0, xs_linspace: bool = False, k_sample: int = 0,
-                 t_sample: int = 0, s: int = 0, seed: int = 0) -> Problem:
+                 t_sample: int = 0, s: int = 0, seed: int = 0, additive: bool = False) -> Problem:
     rng = np.random.default_rng(seed)
     x = rng.uniform(0.0, 1.0, size=(n, d))
     y = _target(target, x) + ynoise * rng.standard_normal(n)
@@ -90,7 +96,7 @@ def make_problem(name: str, *, d: int, n: int, m: Tuple[int, ...], kernel: str,
     return Problem(name=name, d=d, m=tuple(m), lo=(0.0,) * d, hi=(1.0,) * d, kernel=kernel,
                    lengthscale=tuple(lengthscale), outputscale=outputscale, noise=noise, k=k,
                    dtype=dtype, x=cast(x), y=cast(y), xs=cast(xs), k_sample=k_sample,
-                   xs_sample=cast(xs_s), z=cast(z), precision=precision)
+                   xs_sample=cast(xs_s), z=cast(z), precision=precision, additive=additive)
 
 
 # The five workloads.  `scale` < 1 shrinks n, t (and the 1-D grid) for tests
@@ -125,6 +131,18 @@ def config(idx: int, seed: int = 0, scale: float = 1.0, **over) -> Problem:
         raise ValueError("config 5 is a batch; use batched_config()")
     kw.update(over)
     return make_problem(name, seed=seed, **kw)
+
+
+# Additive composition (Sec. 3.4): one RBF component per dimension, 100 grid
+# points each, as in the paper's additive Bayesian-optimisation model; the
+# target is the (additive) Styblinski-Tang function.  d <= 4 here.
+def additive_config(d: int = 4, n: int = 100_000, m: int = 100, k: int = 50, t: int = 1_000_000,
+                    seed: int = 0, **over) -> Problem:
+    kw = dict(d=d, n=n, m=(m,) * d, kernel="rbf", lengthscale=(0.15,) * d, noise=0.01, k=k, t=t,
+              target="styblinski_tang", ynoise=0.1, dtype="f32", precision="fp32",
+              additive=True)
+    kw.update(over)
+    return make_problem(f"add{d}d_n{n}_m{m}_k{k}", seed=seed, **kw)
 
 
 def batched_config(G: int = 64, seed: int = 0, scale: float = 1.0, t_per_gp: int = 100_000,

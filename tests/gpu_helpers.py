@@ -20,6 +20,8 @@ def cfg_of(P, **over):
     kw = dict(kernel=P.kernel, lengthscale=list(P.lengthscale), outputscale=P.outputscale,
               noise=P.noise, k=P.k, k_sample=P.k_sample, precision=P.precision)
     kw.update(over)
+    if P.additive:
+        kw["flags"] = kw.get("flags", 0) | B.FLAG_ADDITIVE
     return B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), **kw)
 
 
@@ -36,7 +38,7 @@ def build(P, **over):
 
 
 def spec_of(P):
-    return O.Spec(P.m, P.lo, P.hi, P.kernel, P.lengthscale, P.outputscale, P.noise)
+    return O.Spec(P.m, P.lo, P.hi, P.kernel, P.lengthscale, P.outputscale, P.noise, P.additive)
 
 
 def oracle_cache(P, k=None, cg_tol=1e-10):
