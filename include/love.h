@@ -97,11 +97,10 @@ typedef enum {
                                        component per dimension on that dimension's grid.  The
                                        grid vectors (Rt rows, the mean cache a, S rows) stack the
                                        axes one after another, axis 0 first: m = sum_i m_i, and
-                                       K is block diagonal.  Builds, love_predict_mean_var(_batched),
-                                       love_apply_khat / _kuu, export and import support it; the
-                                       covariance, sampling and backward entry points return
-                                       LOVE_EUNSUPPORTED for such a cache.  Every GP of a batched
-                                       build must agree on this flag.                             */
+                                       K is block diagonal; every entry point takes the block form
+                                       (a query point's interpolation vector has 4 d entries, its
+                                       prior is the sum of the axes' terms).  Every GP of a batched
+                                       build must agree on this flag (LOVE_EINVAL otherwise).     */
 
 typedef struct {
   int32_t d;                        /* input dimension, 1..4                                     */

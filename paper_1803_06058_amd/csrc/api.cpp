@@ -520,7 +520,6 @@ love_status love_predict_mean_var_batched(int32_t G, const love_cache* const* ca
 love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const void* xb,
                                      int64_t t, void* cov, void* stream) {
   if (!c || t < 0 || (t > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
-  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64) return covar_pairs<double>(c, (const double*)xa, (const double*)xb, t, (double*)cov, s);
   return covar_pairs<float>(c, (const float*)xa, (const float*)xb, t, (float*)cov, s);
@@ -529,7 +528,6 @@ love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const 
 love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
                                      const void* xb, int64_t tb, void* cov, void* stream) {
   if (!c || ta < 0 || tb < 0 || (ta > 0 && tb > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
-  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64)
     return covar_block<double>(c, (const double*)xa, ta, (const double*)xb, tb, (double*)cov, s);
@@ -539,7 +537,7 @@ love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_
 love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
                                   int64_t ns, void* out, void* stream) {
   if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;
-  if (c->ks <= 0 || c->add) return LOVE_EUNSUPPORTED;
+  if (c->ks <= 0) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64) return sample<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
   return sample<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
@@ -549,7 +547,6 @@ love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t
                                   const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
                                   void* stream) {
   if (!c || t < 0 || (t > 0 && (!xs || !g_xs))) return LOVE_EINVAL;
-  if (c->add) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   if (c->fp64)
     return backward<double>(c, (const double*)xs, t, (const double*)g_mean, (const double*)g_var,

@@ -60,6 +60,59 @@ __device__ inline bool point_stencil(const GridT<T>& g, const T* __restrict__ xp
   return ok;
 }
 
+// point_stencil that also returns each axis's stencil base jb[e]
+template <typename T, int D>
+__device__ inline bool point_stencil_j(const GridT<T>& g, const T* __restrict__ xp, double w[D][4],
+                                       double dw[D][4], int (&jb)[D], int64_t& base, bool want_dw) {
+  bool ok = true;
+  base = 0;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = xp[e];
+    ok = ok && in_domain(xe, g.lo[e], g.hi[e]);
+    if (!(xe == xe)) xe = g.lo[e];
+    T s;
+    const int j = stencil_at(g, e, xe, s);
+    T wt[4];
+    keys_weights(s, wt);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) w[e][o] = (double)wt[o];
+    if (want_dw) {
+      T dt[4];
+      keys_dweights(s, dt);
+#pragma unroll
+      for (int o = 0; o < 4; ++o) dw[e][o] = (double)dt[o] * (double)g.invh[e];
+    }
+    jb[e] = j;
+    base += (int64_t)j * g.nstride[e];
+  }
+  return ok;
+}
+
+// Stencil entries of one point: 4^D grid nodes of the tensor-product grid,
+// or (ADD, Sec. 3.4) the four nodes of each axis's own block, 4 D in all.
+template <int D, bool ADD>
+struct Entries {
+  static constexpr int N = ADD ? 4 * D : 1 << (2 * D);
+};
+template <typename T, int D, bool ADD>
+__device__ inline void stn_entry(const GridT<T>& g, const double (&w)[D][4], int64_t base,
+                                 const int (&jb)[D], int a, double& wa, int64_t& node) {
+  if constexpr (ADD) {
+    wa = w[a >> 2][a & 3];
+    node = g.aoff[a >> 2] + jb[a >> 2] + (a & 3);
+  } else {
+    wa = 1.0;
+    node = base;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int o = (a >> (2 * (D - 1 - e))) & 3;
+      wa *= w[e][o];
+      node += (int64_t)o * g.nstride[e];
+    }
+  }
+}
+
 // w_e^T T_e(4x4) v_e with T_e(4x4)[a][b] = c4[e][|a-b|]
 __device__ inline double quad4(const double* c4e, const double* a, const double* b) {
   double s = 0.0;
@@ -338,7 +391,7 @@ template love_status predict_batch<double>(const std::vector<const love_cache*>&
 // The prior term uses the full first column of each axis factor, since the
 // two stencils may be far apart.
 // ----------------------------------------------------------------------------
-template <typename T, int D, int SPLIT>
+template <typename T, int D, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_covar_pairs(
     GridT<T> g, const T* __restrict__ xa, const T* __restrict__ xb, int64_t t,
     const void* __restrict__ rt, const uint16_t* __restrict__ rt_lo, int kpad,
@@ -349,22 +402,17 @@ __global__ __launch_bounds__(256) void k_covar_pairs(
   if (p >= t) return;
   double wa[D][4], wb[D][4], dd[D][4];
   int64_t ba, bb;
-  bool ok = point_stencil<T, D>(g, xa + p * D, wa, dd, ba, false);
-  ok = point_stencil<T, D>(g, xb + p * D, wb, dd, bb, false) && ok;
-  constexpr int NA = 1 << (2 * D);
+  int ja_[D], jb_[D];
+  bool ok = point_stencil_j<T, D>(g, xa + p * D, wa, dd, ja_, ba, false);
+  ok = point_stencil_j<T, D>(g, xb + p * D, wb, dd, jb_, bb, false) && ok;
+  constexpr int NA = Entries<D, ADD>::N;
   const bool two = kpad > WAVE;
   double ua0 = 0, ua1 = 0, ub0 = 0, ub1 = 0;
   for (int a = 0; a < NA; ++a) {
-    double fa = 1.0, fb = 1.0;
-    int64_t na = ba, nb = bb;
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-      const int o = (a >> (2 * (D - 1 - e))) & 3;
-      fa *= wa[e][o];
-      fb *= wb[e][o];
-      na += (int64_t)o * g.nstride[e];
-      nb += (int64_t)o * g.nstride[e];
-    }
+    double fa, fb;
+    int64_t na, nb;
+    stn_entry<T, D, ADD>(g, wa, ba, ja_, a, fa, na);
+    stn_entry<T, D, ADD>(g, wb, bb, jb_, a, fb, nb);
     ua0 += fa * rt_load<T, SPLIT>(rt, rt_lo, na * kpad + lane);
     ub0 += fb * rt_load<T, SPLIT>(rt, rt_lo, nb * kpad + lane);
     if (two) {
@@ -375,11 +423,10 @@ __global__ __launch_bounds__(256) void k_covar_pairs(
   const double uv = wave_sum(ua0 * ub0 + ua1 * ub1);
   if (lane == 0) {
     const double* cols[4] = {c0, c1, c2, c3};
-    double pr = 1.0;
+    double pr = ADD ? 0.0 : 1.0;   // additive: sum of the axes' terms
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-      int ja = (int)((ba / g.nstride[e]) % g.m[e]);
-      int jb = (int)((bb / g.nstride[e]) % g.m[e]);
+      const int ja = ja_[e], jb = jb_[e];
       double sacc = 0.0;
       for (int o = 0; o < 4; ++o)
         for (int q = 0; q < 4; ++q) {
@@ -387,7 +434,8 @@ __global__ __launch_bounds__(256) void k_covar_pairs(
           lag = lag < 0 ? -lag : lag;
           sacc += wa[e][o] * wb[e][q] * cols[e][lag];
         }
-      pr *= sacc;
+      if (ADD) pr += sacc;
+      else pr *= sacc;
     }
     if (ok) cov[p] = (T)(pr - uv);
     else {
@@ -407,19 +455,26 @@ love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t
   const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
   const double* cc[4];
   for (int e = 0; e < 4; ++e) cc[e] = (const double*)(e < c->d ? c->toep.ax[e].c64 : nullptr);
-#define LAUNCH_C(D)                                                                                \
+#define LAUNCH_C(D, ADD)                                                                           \
   if (split)                                                                                       \
-    k_covar_pairs<T, D, 1><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, (const uint16_t*)c->rt_lo,    \
+    k_covar_pairs<T, D, 1, ADD><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, (const uint16_t*)c->rt_lo, \
                                                 c->kpad, cc[0], cc[1], cc[2], cc[3], cov, c->status); \
   else                                                                                             \
-    k_covar_pairs<T, D, 0><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, nullptr, c->kpad, cc[0], cc[1], \
-                                                cc[2], cc[3], cov, c->status);
-  switch (c->d) {
-    case 1: LAUNCH_C(1); break;
-    case 2: LAUNCH_C(2); break;
-    case 3: LAUNCH_C(3); break;
-    case 4: LAUNCH_C(4); break;
+    k_covar_pairs<T, D, 0, ADD><<<grid, 256, 0, s>>>(g, xa, xb, t, c->rt, nullptr, c->kpad, cc[0],  \
+                                                cc[1], cc[2], cc[3], cov, c->status);
+#define LAUNCH_CA(D)                                                                               \
+  if (c->add) {                                                                                    \
+    LAUNCH_C(D, true)                                                                              \
+  } else {                                                                                         \
+    LAUNCH_C(D, false)                                                                             \
   }
+  switch (c->d) {
+    case 1: LAUNCH_CA(1); break;
+    case 2: LAUNCH_CA(2); break;
+    case 3: LAUNCH_CA(3); break;
+    case 4: LAUNCH_CA(4); break;
+  }
+#undef LAUNCH_CA
 #undef LAUNCH_C
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
@@ -436,7 +491,7 @@ template <int D>
 struct CovRec {
   static constexpr int W = 0, J = 4 * D, OK = 5 * D, N = 5 * D + 1;   // doubles per point
 };
-template <typename T, int D, int SPLIT, int CPL>
+template <typename T, int D, int SPLIT, int CPL, bool ADD>
 __device__ inline void covar_u_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
                                     const void* __restrict__ rt,
                                     const uint16_t* __restrict__ rt_lo, int kpad,
@@ -447,21 +502,17 @@ __device__ inline void covar_u_body(const GridT<T>& g, const T* __restrict__ xs,
   const int64_t pc = live ? p : t - 1;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, false);
-  constexpr int NA = 1 << (2 * D);
+  int jb[D];
+  const bool ok = point_stencil_j<T, D>(g, xs + pc * D, w, dw, jb, base, false);
+  constexpr int NA = Entries<D, ADD>::N;
   double u[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) u[q] = 0.0;
 #pragma unroll 4
   for (int a = 0; a < NA; ++a) {
-    double wa = 1.0;
-    int64_t node = base;
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-      const int o = (a >> (2 * (D - 1 - e))) & 3;
-      wa *= w[e][o];
-      node += (int64_t)o * g.nstride[e];
-    }
+    double wa;
+    int64_t node;
+    stn_entry<T, D, ADD>(g, w, base, jb, a, wa, node);
     double r[CPL];
     rt_row<T, SPLIT, CPL>(rt, rt_lo, node * kpad + sub * CPL, r);
 #pragma unroll
@@ -472,29 +523,26 @@ __device__ inline void covar_u_body(const GridT<T>& g, const T* __restrict__ xs,
   for (int q = 0; q < CPL; ++q) U[p * kpad + sub * CPL + q] = u[q];
   if (sub == 0) {
     double* rp = rec + p * CovRec<D>::N;
-    int64_t rem = base;
 #pragma unroll
     for (int e = 0; e < D; ++e) {
 #pragma unroll
       for (int o = 0; o < 4; ++o) rp[CovRec<D>::W + 4 * e + o] = w[e][o];
-      const int64_t je = rem / g.nstride[e];
-      rem -= je * g.nstride[e];
-      rp[CovRec<D>::J + e] = (double)je;
+      rp[CovRec<D>::J + e] = (double)jb[e];
     }
     rp[CovRec<D>::OK] = ok ? 1.0 : 0.0;
   }
 }
-template <typename T, int D, int SPLIT>
+template <typename T, int D, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_covar_u(GridT<T> g, const T* __restrict__ xs, int64_t t,
                                                  const void* __restrict__ rt,
                                                  const uint16_t* __restrict__ rt_lo, int kpad,
                                                  double* __restrict__ U, double* __restrict__ rec) {
-  if (kpad > 64) covar_u_body<T, D, SPLIT, 128 / PLQ>(g, xs, t, rt, rt_lo, kpad, U, rec);
-  else covar_u_body<T, D, SPLIT, 64 / PLQ>(g, xs, t, rt, rt_lo, kpad, U, rec);
+  if (kpad > 64) covar_u_body<T, D, SPLIT, 128 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, U, rec);
+  else covar_u_body<T, D, SPLIT, 64 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, U, rec);
 }
 
 constexpr int CB = 32;   // pairs per tile side
-template <typename T, int D>
+template <typename T, int D, bool ADD>
 __global__ __launch_bounds__(256) void k_covar_block(
     const double* __restrict__ Ua, const double* __restrict__ ra, int64_t ta,
     const double* __restrict__ Ub, const double* __restrict__ rb, int64_t tb, int kpad,
@@ -537,7 +585,7 @@ __global__ __launch_bounds__(256) void k_covar_block(
     if (i >= ta || j >= tb) continue;
     double dot = 0.0;
     for (int c = 0; c < keff; ++c) dot += A[ii][c] * Bt[jj][c];
-    double pr = 1.0;
+    double pr = ADD ? 0.0 : 1.0;   // additive: sum of the axes' terms
 #pragma unroll
     for (int e = 0; e < D; ++e) {
       const int ja = (int)RA[ii][CovRec<D>::J + e], jb = (int)RB[jj][CovRec<D>::J + e];
@@ -550,7 +598,8 @@ __global__ __launch_bounds__(256) void k_covar_block(
           lag = lag < 0 ? -lag : lag;
           se += RA[ii][CovRec<D>::W + 4 * e + o] * RB[jj][CovRec<D>::W + 4 * e + q] * cols[e][lag];
         }
-      pr *= se;
+      if (ADD) pr += se;
+      else pr *= se;
     }
     const bool ok = RA[ii][CovRec<D>::OK] != 0.0 && RB[jj][CovRec<D>::OK] != 0.0;
     cov[i * tb + j] = ok ? (T)(pr - dot) : (T)NAN;
@@ -578,26 +627,29 @@ love_status covar_block(const love_cache* c, const T* xa, int64_t ta, const T* x
   const double* cc[4];
   for (int e = 0; e < 4; ++e) cc[e] = (const double*)(e < d ? c->toep.ax[e].c64 : nullptr);
   dim3 grid((unsigned)cdiv(tb, CB), (unsigned)cdiv(ta, CB));
-#define LAUNCH_CV(D)                                                                              \
+#define LAUNCH_CV(D, ADD)                                                                         \
   {                                                                                               \
     const unsigned na = (unsigned)cdiv(ta, PPB), nb = (unsigned)cdiv(tb, PPB);                     \
     if (split) {                                                                                  \
-      tlaunch("covar_u", k_covar_u<T, D, 1>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra);   \
-      tlaunch("covar_u", k_covar_u<T, D, 1>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb);   \
+      tlaunch("covar_u", k_covar_u<T, D, 1, ADD>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra); \
+      tlaunch("covar_u", k_covar_u<T, D, 1, ADD>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb); \
     } else {                                                                                      \
-      tlaunch("covar_u", k_covar_u<T, D, 0>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra);   \
-      tlaunch("covar_u", k_covar_u<T, D, 0>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb);   \
+      tlaunch("covar_u", k_covar_u<T, D, 0, ADD>, na, 256, 0, s, g, xa, ta, c->rt, lo, kpad, Ua, ra); \
+      tlaunch("covar_u", k_covar_u<T, D, 0, ADD>, nb, 256, 0, s, g, xb, tb, c->rt, lo, kpad, Ub, rb); \
     }                                                                                             \
-    tlaunch("covar_block", k_covar_block<T, D>, grid, 256, 0, s, (const double*)Ua,               \
+    tlaunch("covar_block", k_covar_block<T, D, ADD>, grid, 256, 0, s, (const double*)Ua,          \
             (const double*)ra, ta, (const double*)Ub, (const double*)rb, tb, kpad,                \
             (const Ctl*)c->ctl, cc[0], cc[1], cc[2], cc[3], cov, c->status);                      \
   }
+#define LAUNCH_CVA(D)                                                                              \
+  if (c->add) LAUNCH_CV(D, true) else LAUNCH_CV(D, false)
   switch (d) {
-    case 1: LAUNCH_CV(1); break;
-    case 2: LAUNCH_CV(2); break;
-    case 3: LAUNCH_CV(3); break;
-    case 4: LAUNCH_CV(4); break;
+    case 1: LAUNCH_CVA(1); break;
+    case 2: LAUNCH_CVA(2); break;
+    case 3: LAUNCH_CVA(3); break;
+    case 4: LAUNCH_CVA(4); break;
   }
+#undef LAUNCH_CVA
 #undef LAUNCH_CV
   LOVE_HIP_TRY(hipFreeAsync(U, s));
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
@@ -617,7 +669,7 @@ template love_status covar_pairs<double>(const love_cache*, const double*, const
 // Lanes as in the predictive variances: 16 per point, lane sub holding the
 // CPL = kpad / 16 consecutive columns from sub CPL of every stencil row.
 // ----------------------------------------------------------------------------
-template <typename T, int D, int SPLIT, int CPL>
+template <typename T, int D, int SPLIT, int CPL, bool ADD>
 __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
                                      const void* __restrict__ rt,
                                      const uint16_t* __restrict__ rt_lo, int kpad,
@@ -631,8 +683,9 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
   const int64_t pc = live ? p : t - 1;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, true);
-  constexpr int NA = 1 << (2 * D);
+  int jb[D];
+  const bool ok = point_stencil_j<T, D>(g, xs + pc * D, w, dw, jb, base, true);
+  constexpr int NA = Entries<D, ADD>::N;
   double u[CPL], v[D][CPL], dmu[D];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
@@ -642,7 +695,24 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
   }
 #pragma unroll
   for (int e = 0; e < D; ++e) dmu[e] = 0.0;
-  for (int a = 0; a < NA; ++a) {
+  if constexpr (ADD) {
+    // axis e's own four rows: w for u, dw for v_e (the other axes' blocks do
+    // not depend on x_e)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int e = a >> 2, o = a & 3;
+      const int64_t node = g.aoff[e] + jb[e] + o;
+      double r[CPL];
+      rt_row<T, SPLIT, CPL>(rt, rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        u[q] += w[e][o] * r[q];
+        v[e][q] += dw[e][o] * r[q];
+      }
+      if (a == sub && acache) dmu[e] += dw[e][o] * (double)acache[node];
+    }
+  }
+  for (int a = 0; a < (ADD ? 0 : NA); ++a) {
     int o[D];
     int64_t node = base;
 #pragma unroll
@@ -684,10 +754,10 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
     uv = group_sum(uv, PLQ);
     const double dm = group_sum(dmu[e], PLQ);
     if (sub == 0 && live) {
-      double dp = dq[e];
+      double dp = dq[e];   // additive: the prior is a sum, so only axis e's term moves
 #pragma unroll
       for (int f = 0; f < D; ++f)
-        if (f != e) dp *= qd[f];
+        if (f != e && !ADD) dp *= qd[f];
       const double gval = gmean * dm + gvar * (dp - 2.0 * uv);
       gx[p * D + e] = ok ? (T)gval : (T)NAN;
     }
@@ -696,14 +766,9 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
   if (grt && live && ok && gvar != 0.0) {
     const int keff = ctl->k_eff;
     for (int a = 0; a < NA; ++a) {
-      int64_t node = base;
-      double wa = 1.0;
-#pragma unroll
-      for (int e = 0; e < D; ++e) {
-        const int o = (a >> (2 * (D - 1 - e))) & 3;
-        node += (int64_t)o * g.nstride[e];
-        wa *= w[e][o];
-      }
+      double wa;
+      int64_t node;
+      stn_entry<T, D, ADD>(g, w, base, jb, a, wa, node);
       const double f = -2.0 * gvar * wa;
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
@@ -713,7 +778,7 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
     }
   }
 }
-template <typename T, int D, int SPLIT>
+template <typename T, int D, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
                                                   const void* __restrict__ rt,
                                                   const uint16_t* __restrict__ rt_lo, int kpad,
@@ -724,11 +789,11 @@ __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restric
                                                   T* __restrict__ gx, float* __restrict__ grt,
                                                   unsigned* __restrict__ status) {
   if (kpad > 64)
-    backward_body<T, D, SPLIT, 128 / PLQ>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv, gx,
-                                          grt, status);
+    backward_body<T, D, SPLIT, 128 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv,
+                                               gx, grt, status);
   else
-    backward_body<T, D, SPLIT, 64 / PLQ>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv, gx,
-                                         grt, status);
+    backward_body<T, D, SPLIT, 64 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv,
+                                              gx, grt, status);
 }
 
 template <typename T>
@@ -740,21 +805,28 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
   const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
   const Ctl* ctl = c->ctl;
-#define LAUNCH_B(D)                                                                               \
+#define LAUNCH_B(D, ADD)                                                                          \
   if (split)                                                                                      \
-    tlaunch("backward", k_backward<T, D, 1>, nb, 256, 0, s, g, xs, t, c->rt,                      \
+    tlaunch("backward", k_backward<T, D, 1, ADD>, nb, 256, 0, s, g, xs, t, c->rt,                 \
             (const uint16_t*)c->rt_lo, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt, \
             c->status);                                                                           \
   else                                                                                            \
-    tlaunch("backward", k_backward<T, D, 0>, nb, 256, 0, s, g, xs, t, c->rt,                      \
+    tlaunch("backward", k_backward<T, D, 0, ADD>, nb, 256, 0, s, g, xs, t, c->rt,                 \
             (const uint16_t*)nullptr, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt,  \
             c->status);
-  switch (c->d) {
-    case 1: LAUNCH_B(1); break;
-    case 2: LAUNCH_B(2); break;
-    case 3: LAUNCH_B(3); break;
-    case 4: LAUNCH_B(4); break;
+#define LAUNCH_BA(D)                                                                               \
+  if (c->add) {                                                                                    \
+    LAUNCH_B(D, true)                                                                              \
+  } else {                                                                                         \
+    LAUNCH_B(D, false)                                                                             \
   }
+  switch (c->d) {
+    case 1: LAUNCH_BA(1); break;
+    case 2: LAUNCH_BA(2); break;
+    case 3: LAUNCH_BA(3); break;
+    case 4: LAUNCH_BA(4); break;
+  }
+#undef LAUNCH_BA
 #undef LAUNCH_B
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
@@ -770,7 +842,7 @@ template love_status backward<double>(const love_cache*, const double*, int64_t,
 //                tiles in LDS, 4 x 4 outputs per thread; the number of
 //                factor columns (k_chol) is read on the device.
 // ----------------------------------------------------------------------------
-template <typename T, int D, int CPL>
+template <typename T, int D, int CPL, bool ADD>
 __device__ inline void sample_f_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
                                      const float* __restrict__ S, int kspad,
                                      const T* __restrict__ acache, float* __restrict__ F,
@@ -782,22 +854,18 @@ __device__ inline void sample_f_body(const GridT<T>& g, const T* __restrict__ xs
   const int64_t pc = live ? p : t - 1;
   double w[D][4], dw[D][4];
   int64_t base;
-  const bool ok = point_stencil<T, D>(g, xs + pc * D, w, dw, base, false);
-  constexpr int NA = 1 << (2 * D);
+  int jb[D];
+  const bool ok = point_stencil_j<T, D>(g, xs + pc * D, w, dw, jb, base, false);
+  constexpr int NA = Entries<D, ADD>::N;
   double f[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) f[q] = 0.0;
   double mu = 0.0;
 #pragma unroll 4
   for (int a = 0; a < NA; ++a) {
-    double wa = 1.0;
-    int64_t node = base;
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-      const int o = (a >> (2 * (D - 1 - e))) & 3;
-      wa *= w[e][o];
-      node += (int64_t)o * g.nstride[e];
-    }
+    double wa;
+    int64_t node;
+    stn_entry<T, D, ADD>(g, w, base, jb, a, wa, node);
     double r[CPL];
     rt_row<float, 0, CPL>(S, nullptr, node * kspad + sub * CPL, r);
 #pragma unroll
@@ -815,14 +883,15 @@ __device__ inline void sample_f_body(const GridT<T>& g, const T* __restrict__ xs
     if (!ok) atomicOr(status, SF_DOMAIN);
   }
 }
-template <typename T, int D>
+template <typename T, int D, bool ADD>
 __global__ __launch_bounds__(256) void k_sample_f(GridT<T> g, const T* __restrict__ xs, int64_t t,
                                                   const float* __restrict__ S, int kspad,
                                                   const T* __restrict__ acache,
                                                   float* __restrict__ F, float* __restrict__ mu,
                                                   unsigned* __restrict__ status) {
-  if (kspad > 64) sample_f_body<T, D, 128 / PLQ>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
-  else sample_f_body<T, D, 64 / PLQ>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
+  if (kspad > 64)
+    sample_f_body<T, D, 128 / PLQ, ADD>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
+  else sample_f_body<T, D, 64 / PLQ, ADD>(g, xs, t, S, kspad, acache, F, mu, status, blockIdx.x);
 }
 
 constexpr int SM_T = 64;   // points per output tile
@@ -911,10 +980,18 @@ love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, 
   float* mu = F + (size_t)t * kspad;
   const unsigned nbf = (unsigned)cdiv(t, PPB);
   switch (c->d) {
-    case 1: tlaunch("sample_f", k_sample_f<T, 1>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
-    case 2: tlaunch("sample_f", k_sample_f<T, 2>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
-    case 3: tlaunch("sample_f", k_sample_f<T, 3>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
-    case 4: tlaunch("sample_f", k_sample_f<T, 4>, nbf, 256, 0, s, g, xs, t, (const float*)c->S, kspad, a, F, mu, c->status); break;
+#define LAUNCH_SF(D)                                                                              \
+  if (c->add)                                                                                     \
+    tlaunch("sample_f", k_sample_f<T, D, true>, nbf, 256, 0, s, g, xs, t, (const float*)c->S,     \
+            kspad, a, F, mu, c->status);                                                          \
+  else                                                                                            \
+    tlaunch("sample_f", k_sample_f<T, D, false>, nbf, 256, 0, s, g, xs, t, (const float*)c->S,    \
+            kspad, a, F, mu, c->status);
+    case 1: LAUNCH_SF(1); break;
+    case 2: LAUNCH_SF(2); break;
+    case 3: LAUNCH_SF(3); break;
+    case 4: LAUNCH_SF(4); break;
+#undef LAUNCH_SF
   }
   const int64_t njt = cdiv(ns, SM_J);
   dim3 grid((unsigned)cdiv(t, SM_T), (unsigned)std::min<int64_t>(njt, 65535));

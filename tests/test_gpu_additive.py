@@ -141,15 +141,11 @@ def test_additive_sampler_cache_parity():
     err = np.max(np.abs(Sig - ref) / np.sqrt(np.outer(p, p)))
     print(cache.info().k_eff_sample, osm.k_chol, err, flush=True)
     assert err <= 1e-5
-    with pytest.raises(B.LoveError) as ei:
-        cache.sample_posterior(tdev(P.xs_sample, torch.float32), tdev(P.z, torch.float32))
-    assert ei.value.code == -7
     cache.free()
 
 
-def test_additive_mixed_batch_and_unsupported_calls():
-    """A batch must agree on the composition; the covariance, sampling and
-    backward entry points refuse an additive cache."""
+def test_additive_mixed_batch_rejected():
+    """A batch must agree on the composition."""
     Pa = add_problem(2, 1000, (20, 20), k=10, t=16)
     Pp = WL.make_problem("p2", d=2, n=1000, m=(20, 20), kernel="rbf", lengthscale=(0.15, 0.15),
                          noise=0.01, k=10, t=16, target="sincos4", ynoise=0.1)
@@ -157,14 +153,84 @@ def test_additive_mixed_batch_and_unsupported_calls():
         B.build_cache_batched([cfg_of(Pa), cfg_of(Pp)], [tdev(Pa.x, torch.float32), tdev(Pp.x, torch.float32)],
                               [tdev(Pa.y, torch.float32), tdev(Pp.y, torch.float32)])
     assert ei.value.code == -1
-    cache = build(Pa)
-    q = tdev(Pa.xs, torch.float32)
-    calls = [lambda: cache.predict_covar_pairs(q, q), lambda: cache.predict_covar_block(q, q),
-             lambda: cache.predict_backward(q, None, torch.ones(16, device=q.device))]
-    for call in calls:
-        with pytest.raises(B.LoveError) as ei:
-            call()
-        assert ei.value.code == -7
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_additive_covariance_parity(f64):
+    """Paired and block covariances (Alg. 1 with w_i != w_j on the block
+    form: the prior term is the sum over axes of w_i,e^T T_e w_j,e) against
+    the oracle; a block of a ragged set (300 x 200) and near-diagonal pairs."""
+    P = add_problem(3, 3000, (30, 40, 25), k=40, f64=f64)
+    dt = torch_dtype(P)
+    cache = build(P)
+    oc = oracle_cache(P)
+    spec = spec_of(P)
+    rng = np.random.default_rng(4)
+    xa = rng.uniform(0, 1, (2000, 3)).astype(P.np_dtype)
+    xb = np.clip(xa + rng.normal(0, 0.02, xa.shape), 0, 1).astype(P.np_dtype)
+    cov = host(cache.predict_covar_pairs(tdev(xa, dt), tdev(xb, dt)))
+    ref = O.love_covariance(oc, xa.astype(np.float64), xb.astype(np.float64))
+    pn = np.sqrt(O.prior_var(xa, spec) * O.prior_var(xb, spec))
+    tol = 1e-10 if f64 else 1e-5
+    assert np.max(np.abs(cov - ref) / pn) <= tol
+    A, Bq = xa[:300], xb[:200]
+    blk = host(cache.predict_covar_block(tdev(A, dt), tdev(Bq, dt)))
+    xi = np.repeat(A, 200, axis=0).astype(np.float64)
+    xj = np.tile(Bq, (300, 1)).astype(np.float64)
+    refb = O.love_covariance(oc, xi, xj).reshape(300, 200)
+    pb = np.sqrt(np.outer(O.prior_var(A, spec), O.prior_var(Bq, spec)))
+    assert np.max(np.abs(blk - refb) / pb) <= tol
+    _, var = cache.predict_mean_var(tdev(A, dt))
+    same = host(cache.predict_covar_block(tdev(A, dt), tdev(A, dt)))
+    pa = O.prior_var(A, spec)
+    assert np.max(np.abs(np.diag(same) - host(var)) / pa) <= (1e-12 if f64 else 1e-6)
+    cache.free()
+
+
+def test_additive_sample_draw_parity():
+    """Draws mu(X*) + W* S z on the block form: the draw kernel against the
+    same S and a taken from the cache (float rounding only)."""
+    P = add_problem(2, 3000, (40, 50), k=40, k_sample=100, t_sample=500, s=64)
+    cache = build(P)
+    ex = cache.export()
+    S, a = host(ex["s"]), host(ex["a"])
+    out = host(cache.sample_posterior(tdev(P.xs_sample, torch.float32), tdev(P.z, torch.float32)))
+    Ws = O.interp_matrix(P.xs_sample.astype(np.float64), spec_of(P))
+    ref = (Ws @ a)[:, None] + Ws @ (S @ P.z[: S.shape[1]].astype(np.float64))
+    assert out.shape == (500, 64)
+    assert np.max(np.abs(out - ref)) <= 1e-5 * (1 + np.max(np.abs(ref)))
+    cache.free()
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_additive_backward_parity(f64):
+    """d(sum g_mean mean + g_var var)/dx* on the block form (only axis e's
+    block moves with x_e) against the oracle's gradient, and the autograd
+    wrapper."""
+    P = add_problem(3, 3000, (30, 40, 25), k=40, f64=f64)
+    dt = torch_dtype(P)
+    cache = build(P)
+    xs = np.clip(P.xs[:1500], 1e-3, 1 - 1e-3).astype(P.np_dtype)
+    rng = np.random.default_rng(3)
+    gm = rng.standard_normal(xs.shape[0]).astype(P.np_dtype)
+    gv = rng.standard_normal(xs.shape[0]).astype(P.np_dtype)
+    gx, grt = cache.predict_backward(tdev(xs, dt), tdev(gm, dt), tdev(gv, dt), want_grt=True)
+    oc = oracle_cache(P)
+    ref = O.love_predict_grad(oc, xs.astype(np.float64), gm.astype(np.float64), gv.astype(np.float64))
+    rel = np.max(np.abs(host(gx) - ref)) / np.max(np.abs(ref))
+    print(rel, flush=True)
+    assert rel <= (1e-9 if f64 else 1e-4)
+    # d var / d Rt = -2 sum_points g_var w u^T over the stacked rows
+    rt = host(cache.export()["rt64" if f64 else "rt"])
+    Ws = O.interp_matrix(xs.astype(np.float64), spec_of(P))
+    U = Ws @ rt
+    refg = -2.0 * (Ws.T @ (gv.astype(np.float64)[:, None] * U))
+    relg = np.max(np.abs(host(grt) - refg)) / np.max(np.abs(refg))
+    assert relg <= 1e-4
+    xt = tdev(xs, dt).requires_grad_(True)
+    mu, var = B.LovePredict.apply(xt, cache)
+    (mu * tdev(gm, dt) + var * tdev(gv, dt)).sum().backward()
+    assert torch.allclose(xt.grad, gx.view_as(xt))
     cache.free()
 
 
