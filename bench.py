@@ -371,9 +371,10 @@ def lanczos_large_section(B, torch, dev, n=1 << 21):
 def forms_section(B, WL, torch, dev, reps=3):
     """The other forms of the path at their full sizes, timed on this GPU (median
     of `reps` after one warm-up, host clock around synchronised calls):
-    bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances) and
+    bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances),
     differentiable (4-D product Matern-5/2, n = 2e5, m = 20^4, k = 64, forward
-    and backward at 262,144 points)."""
+    and backward at 262,144 points) and additive (Sec. 3.4: sum of four 1-D RBF
+    components, n = 1e5, m = 100 per axis, k = 50, 1e6 variances)."""
     import statistics
     out = {}
 
@@ -390,11 +391,12 @@ def forms_section(B, WL, torch, dev, reps=3):
                 r.free()
         return statistics.median(ts)
 
-    for name, idx in (("bf16split_2d", 3), ("differentiable_4d", 4)):
-        P = WL.config(idx)
+    for name, idx in (("bf16split_2d", 3), ("differentiable_4d", 4), ("additive_4d", 0)):
+        P = WL.config(idx) if idx else WL.additive_config()
         cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
                               lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
-                              precision=P.precision)
+                              precision=P.precision,
+                              flags=B.FLAG_ADDITIVE if P.additive else 0)
         x = torch.from_numpy(P.x).to(dev)
         y = torch.from_numpy(P.y).to(dev)
         xs = torch.from_numpy(P.xs).to(dev)
@@ -403,7 +405,8 @@ def forms_section(B, WL, torch, dev, reps=3):
         mu = torch.empty(P.t, device=dev, dtype=x.dtype)
         var = torch.empty(P.t, device=dev, dtype=x.dtype)
         t_fwd = timed(lambda: c.predict_mean_var(xs, out=(mu, var)))
-        rec = {"n": P.n, "m": int(math.prod(P.m)), "d": P.d, "k": P.k, "t": P.t,
+        rec = {"n": P.n, "m": int(sum(P.m) if P.additive else math.prod(P.m)), "d": P.d,
+               "k": P.k, "t": P.t,
                "precision": P.precision, "build_ms": round(t_build * 1e3, 3),
                "predict_ms": round(t_fwd * 1e3, 4),
                "variances_per_s": round(P.t / t_fwd, 1)}
