@@ -85,18 +85,30 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
     f = 4
     nb = -(-n // 256) if -(-n // 256) >= 256 else -(-n // 64)   # row blocks of the main run
     mb = -(-m // 256) if -(-m // 256) >= 256 else -(-m // 64)   # row blocks of the sampler
+    # runs of at most PSUM_NB row blocks add their partial rows inside udots / finalize
+    # (no column-sum launches); the rows are then read by those kernels
+    PSUM_NB = 160
+    main_ps = m <= n and nb <= PSUM_NB
+    samp_ps = mb <= PSUM_NB
     if name == "colsum":        # partial rows read (main: c2, and c unless m <= n; sampler: c, c2)
-        main = sum(8 * nb * (j + 2) + (0 if m <= n else 8 * nb * (j + 1)) for j in range(k_eff))
-        samp = sum(8 * mb * ((j + 1) + (j + 2)) for j in range(ks_eff))
+        main = 0 if main_ps else sum(8 * nb * (j + 2) + (0 if m <= n else 8 * nb * (j + 1))
+                                     for j in range(k_eff))
+        samp = 0 if samp_ps else sum(8 * mb * ((j + 1) + (j + 2)) for j in range(ks_eff))
         return main + samp
+    if name == "sp_band_rt":    # banded K q_j and Rt^T q_j: q_j, Rt (float), the s partial rows
+        return ks_eff * (f * m * k_eff + 16 * m + 8 * mb * k_eff)
+    if name == "sp_reduce_sum":  # K q_j out (one segment in), the s partial rows
+        return ks_eff * (16 * m + 8 * mb * k_eff)
     if name == "sp_apply":      # Rt (float), kv, v, Q'_{0..j} (double)
         return sum(f * m * k_eff + 16 * m + 8 * m * (j + 1) for j in range(ks_eff))
     if name == "rt_dots":
         return ks_eff * (f * m * k_eff + 8 * m)
     if name == "sp_udots":
-        return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff))
+        return sum(8 * m * (j + 1) + 16 * m + (8 * mb * (j + 1) if samp_ps else 0)
+                   for j in range(ks_eff))
     if name == "sp_finalize":
-        return sum(8 * m * (j + 1) + 16 * m for j in range(ks_eff - 1))
+        return sum(8 * m * (j + 1) + 16 * m + (8 * mb * (j + 2) if samp_ps else 0)
+                   for j in range(ks_eff - 1))
     if name == "lz_udots":      # read Q_{0..j} once; v from x and R_j (m <= n) or v; write r',
         gpath = m <= n          # partial rows
         return sum(f * n * (j + 1) + (f * n * d + f * m if gpath else f * n) + f * n +
