@@ -202,6 +202,7 @@ struct ToepRun {
     size_t smem_lines = 0, smem_fft = 0;
   };
   int d = 0;
+  int jpg = 1;   // table entries (jobs) per GP: d when an additive batch runs in one pass
   Axis ax[MAXD];
 };
 
@@ -233,7 +234,7 @@ GridT<T> make_grid(const love_cache* c);
 // sums) when scatter_two_stage(c); its job's cellp then holds
 // scatter_scratch_bytes(c, sizeof(T)), and is null otherwise.  kinds: the
 // SCATTER_* bits of the batch (scatter_kinds).
-enum : int { SCATTER_NODES = 1, SCATTER_TWO_STAGE = 2 };
+enum : int { SCATTER_NODES = 1, SCATTER_TWO_STAGE = 2, SCATTER_ADDITIVE = 4 };
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
                     hipStream_t s, int kinds);

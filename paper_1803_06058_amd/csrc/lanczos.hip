@@ -2268,11 +2268,18 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       a_cd = keep(t_cd);
       a_gd = keep(t_gd);
       a_rows = keep(t_rows);
+      // Toeplitz tables hold t_step.jpg entries per GP
+      auto keep_t = [&](const Tab& t) {
+        std::vector<int64_t> b(t.G);
+        for (int i = 0; i < t.G; ++i)
+          b[i] = cs[i / t_step.jpg]->k > j ? t.off[i + 1] - t.off[i] : 0;
+        return make_tab(b);
+      };
       for (int e = 0; e < t_step.d; ++e) {
-        a_step.ax[e].band = keep(t_step.ax[e].band);
-        a_step.ax[e].reduce = keep(t_step.ax[e].reduce);
-        a_step.ax[e].lines = keep(t_step.ax[e].lines);
-        a_step.ax[e].fft = keep(t_step.ax[e].fft);
+        a_step.ax[e].band = keep_t(t_step.ax[e].band);
+        a_step.ax[e].reduce = keep_t(t_step.ax[e].reduce);
+        a_step.ax[e].lines = keep_t(t_step.ax[e].lines);
+        a_step.ax[e].fft = keep_t(t_step.ax[e].fft);
       }
       for (int g = 0; g < G; ++g)
         if (cs[g]->k <= j) a_nv1[g] = a_nv2[g] = -(1 << 20);
@@ -2396,11 +2403,17 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       a_nodes = keep(t_nodes);
       a_rows = keep(t_rows);
       a_one = keep(t_one);
+      // Toeplitz tables hold t_cg.jpg entries per GP
+      auto keep_t = [&](const Tab& t) {
+        std::vector<int64_t> b(t.G);
+        for (int i = 0; i < t.G; ++i) b[i] = hflag[i / t_cg.jpg] ? 0 : t.off[i + 1] - t.off[i];
+        return make_tab(b);
+      };
       for (int e = 0; e < t_cg.d; ++e) {
-        a_cg.ax[e].band = keep(t_cg.ax[e].band);
-        a_cg.ax[e].reduce = keep(t_cg.ax[e].reduce);
-        a_cg.ax[e].lines = keep(t_cg.ax[e].lines);
-        a_cg.ax[e].fft = keep(t_cg.ax[e].fft);
+        a_cg.ax[e].band = keep_t(t_cg.ax[e].band);
+        a_cg.ax[e].reduce = keep_t(t_cg.ax[e].reduce);
+        a_cg.ax[e].lines = keep_t(t_cg.ax[e].lines);
+        a_cg.ax[e].fft = keep_t(t_cg.ax[e].fft);
       }
       for (int g = 0; g < G; ++g) a_nvq[g] = hflag[g] ? 0 : nvq[g];
     }

@@ -117,9 +117,10 @@ __device__ __forceinline__ T scatter_rows(const GridT<T>& g, const T* x, const T
 }
 
 // Additive composition: node ul of axis e gathers the rows of axis-e cells
-// ul - 3 .. ul, listed (by row index) in g.aperm at positions [r0, re); lane
-// positions go r0, r0 + WAVE, ... in batches of four whose loads go out first.
-template <typename T, int D, bool COMB>
+// ul - 3 .. ul, listed (by row index) in g.aperm at positions [r0, re); a
+// thread's positions go r0, r0 + ST, ... in batches of four whose loads go
+// out first.
+template <typename T, int D, bool COMB, int ST>
 __device__ __forceinline__ T scatter_rows_add(const GridT<T>& g, int e, int ul, const T* x,
                                               const T* v, const T* v2, T ratio, int32_t r0,
                                               int32_t re) {
@@ -131,10 +132,10 @@ __device__ __forceinline__ T scatter_rows_add(const GridT<T>& g, int e, int ul, 
   GI* gp = (GI*)g.aperm;
   constexpr int UB = 4;
   T acc = T(0);
-  for (int32_t rs = r0; rs < re; rs += UB * WAVE) {
+  for (int32_t rs = r0; rs < re; rs += UB * ST) {
     int32_t rr[UB];
 #pragma unroll
-    for (int q = 0; q < UB; ++q) rr[q] = gp[min(rs + q * WAVE, re - 1)];
+    for (int q = 0; q < UB; ++q) rr[q] = gp[min(rs + q * ST, re - 1)];
     T xr[UB], vr[UB], v2r[UB];
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
@@ -149,17 +150,27 @@ __device__ __forceinline__ T scatter_rows_add(const GridT<T>& g, int e, int ul, 
       const T w = keys_weight_at(ul - jj, sq);
       T val = vr[q];
       if constexpr (COMB) val = (T)(vr[q] + ratio * v2r[q]);
-      acc += (rs + q * WAVE < re) ? w * val : T(0);
+      acc += (rs + q * ST < re) ? w * val : T(0);
     }
   }
   return acc;
 }
 
+// One block of 256 threads per stacked node u (a node's rows are those of
+// four cells of its axis, ~4 n / m_e of them); thread sums, then the wave
+// sums, then the four waves in order.  mode bits as for k_scatter.
 template <typename T, int D>
-__device__ __forceinline__ void scatter_node_add(const ScatterJob<T>& J, int64_t u, int j,
-                                                 bool comb, T ratio) {
+__global__ __launch_bounds__(256) void k_scatter_add(Tab tab, const ScatterJob<T>* __restrict__ jobs,
+                                                     int j, int mode) {
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode)) return;
   const GridT<T>& g = J.g;
-  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t u = lb;
+  if (u >= g.mtot) return;
+  const bool comb = (mode & 4) && J.v2;
+  const T ratio = comb ? (T)J.ctl->ratio : T(0);
   int e = 0;
 #pragma unroll
   for (int q = 1; q < D; ++q) e = u >= g.aoff[q] ? q : e;
@@ -170,11 +181,20 @@ __device__ __forceinline__ void scatter_node_add(const ScatterJob<T>& J, int64_t
     const int32_t rb = J.cell_start[g.acoff[e] + cl];
     const int32_t re = J.cell_start[g.acoff[e] + ch + 1];
     const T* v = J.v + (int64_t)j * J.v_js;
-    if (comb) acc = scatter_rows_add<T, D, true>(g, e, ul, J.x, v, J.v2, ratio, rb + lane, re);
-    else acc = scatter_rows_add<T, D, false>(g, e, ul, J.x, v, J.v2, ratio, rb + lane, re);
+    const int32_t r0 = rb + (int32_t)threadIdx.x;
+    if (comb) acc = scatter_rows_add<T, D, true, 256>(g, e, ul, J.x, v, J.v2, ratio, r0, re);
+    else acc = scatter_rows_add<T, D, false, 256>(g, e, ul, J.x, v, J.v2, ratio, r0, re);
   }
+  __shared__ T ws[256 / WAVE];
   acc = wave_sum(acc);
-  if (lane == 0) J.out[(int64_t)j * J.out_js + u] = acc;
+  if ((threadIdx.x & (WAVE - 1)) == 0) ws[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T tot = T(0);
+#pragma unroll
+    for (int w = 0; w < 256 / WAVE; ++w) tot += ws[w];
+    J.out[(int64_t)j * J.out_js + u] = tot;
+  }
 }
 
 template <typename T, int D>
@@ -193,10 +213,6 @@ __global__ __launch_bounds__(256) void k_scatter(Tab tab, const ScatterJob<T>* _
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t u = (int64_t)lb * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (u >= g.mtot) return;
-  if (g.add) {
-    scatter_node_add<T, D>(J, u, j, comb, ratio);
-    return;
-  }
   constexpr int RUNS = 1 << (2 * (D - 1));
   constexpr int LPR = WAVE / RUNS;
   const int run = lane / LPR, sub = lane % LPR;
@@ -251,7 +267,8 @@ bool scatter_two_stage(const love_cache* c) {
 }
 int scatter_kinds(const std::vector<love_cache*>& cs) {
   int k = 0;
-  for (auto* c : cs) k |= scatter_two_stage(c) ? SCATTER_TWO_STAGE : SCATTER_NODES;
+  for (auto* c : cs)
+    k |= c->add ? SCATTER_ADDITIVE : scatter_two_stage(c) ? SCATTER_TWO_STAGE : SCATTER_NODES;
   return k;
 }
 size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
@@ -461,13 +478,24 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
         break;
     }
   }
-  if (!(kinds & SCATTER_NODES)) return;
+  if (kinds & SCATTER_ADDITIVE) {
+    // a batch agrees on the composition: every job is additive; one block per node
+    std::vector<int64_t> b(tab.G);
+    for (int g = 0; g < tab.G; ++g) b[g] = 4 * (tab.off[g + 1] - tab.off[g]);
+    const Tab ta = make_tab(b);
+    const unsigned na = tab_blocks(ta);
+    switch (d) {
+      case 1: tlaunch("scatter", k_scatter_add<T, 1>, na, 256, 0, s, ta, jobs, j, mode); break;
+      case 2: tlaunch("scatter", k_scatter_add<T, 2>, na, 256, 0, s, ta, jobs, j, mode); break;
+      case 3: tlaunch("scatter", k_scatter_add<T, 3>, na, 256, 0, s, ta, jobs, j, mode); break;
+      case 4: tlaunch("scatter", k_scatter_add<T, 4>, na, 256, 0, s, ta, jobs, j, mode); break;
+    }
+    return;
+  }
+  if (!(kinds & SCATTER_NODES) || d >= 3) return;
   switch (d) {
     case 1: tlaunch("scatter", k_scatter<T, 1>, nb, 256, 0, s, tab, jobs, j, mode); break;
     case 2: tlaunch("scatter", k_scatter<T, 2>, nb, 256, 0, s, tab, jobs, j, mode); break;
-    // d >= 3 reaches the one-wave-per-node kernel only for additive compositions
-    case 3: tlaunch("scatter", k_scatter<T, 3>, nb, 256, 0, s, tab, jobs, j, mode); break;
-    case 4: tlaunch("scatter", k_scatter<T, 4>, nb, 256, 0, s, tab, jobs, j, mode); break;
   }
 }
 template void launch_scatter<float>(const Tab&, const ScatterJob<float>*, int, int, int, hipStream_t,
@@ -633,68 +661,80 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
   const int G = (int)cs.size();
   const int d = cs[0]->d;
   const bool add = cs[0]->add;   // a batch agrees on the composition
-  run.d = d;
-  // axes applied last-to-first; intermediate results ping-pong through the scratch halves.
-  // Additive: every axis maps its own block of in to the same block of out.
-  for (int e = d - 1, step = 0; e >= 0; --e, ++step) {
-    std::vector<ToepJob<T>> jobs(G);
-    std::vector<int64_t> nband(G, 0), nred(G, 0), nlines(G, 0), nfft(G, 0);
+  // One job: axis e of GP g at pass `step`, with its block counts per backend.
+  // Products: axes applied last-to-first, intermediate results ping-pong
+  // through the scratch halves.  Additive: axis e maps its own block of in to
+  // the same block of out, with its own slice of the segment scratch.
+  struct Counts {
+    int64_t band = 0, red = 0, lines = 0, fft = 0;
     size_t smem_lines = 0, smem_fft = 0;
-    for (int g = 0; g < G; ++g) {
-      const love_cache* c = cs[g];
-      const ToepAxis& ax = c->toep.ax[e];
-      ToepJob<T> J{};
-      T* buf0 = scratch[g];
-      T* buf1 = scratch[g] + c->m;
-      const bool first = add || (e == d - 1), last = add || (e == 0);
-      const int64_t off = add ? c->aoff[e] : 0;
-      J.in = first ? in[g] + off : ((step - 1) % 2 == 0 ? buf0 : buf1);
-      J.in_js = first ? in_js[g] : 0;
-      J.out = last ? out[g] + off : (step % 2 == 0 ? buf0 : buf1);
-      J.out_js = last ? out_js[g] : 0;
-      J.c = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
-      J.spec = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
-      J.partial = scratch[g] + 2 * c->m;
-      J.L = ax.L;
-      J.bw = sizeof(T) == 8 ? ax.bw64 : ax.bw32;
-      J.inner = ax.inner;
-      J.outer = ax.outer;
-      J.scale = T(1);
-      J.ctl = ctl[g];
-      const int be = axis_backend(ax);
-      if (be == 0) {
-        const int ntiles = (int)cdiv(ax.L, TB_OUT);
-        const int band = std::min(ax.L, TB_OUT + 2 * J.bw);
-        // segments: enough blocks to cover the chip (~512), each at least 256 inputs
-        int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
-                                                               cdiv(band, 256)));
-        {
-          // LOVE_TOEP_NSEG=q fixes the segment count (tuning)
-          static const int forced = [] {
-            const char* e = std::getenv("LOVE_TOEP_NSEG");
-            return e ? std::atoi(e) : 0;
-          }();
-          if (forced > 0) nseg = forced;
-        }
-        nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
-        nseg = std::min(nseg, TB_NSEG_MAX);
-        J.ntiles = ntiles;
-        J.nseg = nseg;
-        J.seglen = (int)cdiv(band, nseg);
-        nband[g] = (int64_t)ntiles * nseg * ax.outer;
-        if (nseg > 1) nred[g] = cdiv((int64_t)ax.L * ax.outer, TB_RED);
-      } else if (be == 1) {
-        nlines[g] = cdiv(ax.outer * ax.inner, WAVE);
-        smem_lines = std::max(smem_lines, sizeof(T) * ((size_t)ax.L * WAVE + ax.L));
-      } else {
-        int N = ax.fft_n, logN = 0;
-        while ((1 << logN) < N) ++logN;
-        J.N = N;
-        J.logN = logN;
-        nfft[g] = cdiv(ax.outer * ax.inner, 2);
-        smem_fft = std::max(smem_fft, sizeof(T) * 2 * (size_t)N);
+  };
+  auto make_job = [&](int g, int e, int step, Counts& n) {
+    const love_cache* c = cs[g];
+    const ToepAxis& ax = c->toep.ax[e];
+    ToepJob<T> J{};
+    T* buf0 = scratch[g];
+    T* buf1 = scratch[g] + c->m;
+    const bool first = add || (e == d - 1), last = add || (e == 0);
+    const int64_t off = add ? c->aoff[e] : 0;
+    J.in = first ? in[g] + off : ((step - 1) % 2 == 0 ? buf0 : buf1);
+    J.in_js = first ? in_js[g] : 0;
+    J.out = last ? out[g] + off : (step % 2 == 0 ? buf0 : buf1);
+    J.out_js = last ? out_js[g] : 0;
+    J.c = (const T*)(sizeof(T) == 8 ? ax.c64 : ax.c32);
+    J.spec = (const T*)(sizeof(T) == 8 ? ax.spec64 : ax.spec32);
+    J.partial = scratch[g] + 2 * c->m + (int64_t)TB_NSEG_MAX * off;
+    J.L = ax.L;
+    J.bw = sizeof(T) == 8 ? ax.bw64 : ax.bw32;
+    J.inner = ax.inner;
+    J.outer = ax.outer;
+    J.scale = T(1);
+    J.ctl = ctl[g];
+    const int be = axis_backend(ax);
+    if (be == 0) {
+      const int ntiles = (int)cdiv(ax.L, TB_OUT);
+      const int band = std::min(ax.L, TB_OUT + 2 * J.bw);
+      // segments: enough blocks to cover the chip (~512), each at least 256 inputs
+      int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
+                                                             cdiv(band, 256)));
+      {
+        // LOVE_TOEP_NSEG=q fixes the segment count (tuning)
+        static const int forced = [] {
+          const char* ev = std::getenv("LOVE_TOEP_NSEG");
+          return ev ? std::atoi(ev) : 0;
+        }();
+        if (forced > 0) nseg = forced;
       }
-      jobs[g] = J;
+      nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
+      nseg = std::min(nseg, TB_NSEG_MAX);
+      J.ntiles = ntiles;
+      J.nseg = nseg;
+      J.seglen = (int)cdiv(band, nseg);
+      n.band = (int64_t)ntiles * nseg * ax.outer;
+      if (nseg > 1) n.red = cdiv((int64_t)ax.L * ax.outer, TB_RED);
+    } else if (be == 1) {
+      n.lines = cdiv(ax.outer * ax.inner, WAVE);
+      n.smem_lines = sizeof(T) * ((size_t)ax.L * WAVE + ax.L);
+    } else {
+      int N = ax.fft_n, logN = 0;
+      while ((1 << logN) < N) ++logN;
+      J.N = N;
+      J.logN = logN;
+      n.fft = cdiv(ax.outer * ax.inner, 2);
+      n.smem_fft = sizeof(T) * 2 * (size_t)N;
+    }
+    return J;
+  };
+  auto store = [&](int step, const std::vector<ToepJob<T>>& jobs, const std::vector<Counts>& n) {
+    std::vector<int64_t> nband, nred, nlines, nfft;
+    size_t sl = 0, sf = 0;
+    for (const Counts& q : n) {
+      nband.push_back(q.band);
+      nred.push_back(q.red);
+      nlines.push_back(q.lines);
+      nfft.push_back(q.fft);
+      sl = std::max(sl, q.smem_lines);
+      sf = std::max(sf, q.smem_fft);
     }
     auto& A_ = run.ax[step];
     A_.jobs = A.add(jobs);
@@ -702,8 +742,28 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
     A_.reduce = make_tab(nred);
     A_.lines = make_tab(nlines);
     A_.fft = make_tab(nfft);
-    A_.smem_lines = smem_lines;
-    A_.smem_fft = smem_fft;
+    A_.smem_lines = sl;
+    A_.smem_fft = sf;
+  };
+  if (add && (int64_t)G * d <= MAXG) {
+    // additive: the d independent blocks of every GP in one pass (one launch
+    // per backend), job g d + e
+    run.d = 1;
+    run.jpg = d;
+    std::vector<ToepJob<T>> jobs(G * d);
+    std::vector<Counts> n(G * d);
+    for (int g = 0; g < G; ++g)
+      for (int e = 0; e < d; ++e) jobs[g * d + e] = make_job(g, e, 0, n[g * d + e]);
+    store(0, jobs, n);
+    return;
+  }
+  run.d = d;
+  run.jpg = 1;
+  for (int e = d - 1, step = 0; e >= 0; --e, ++step) {
+    std::vector<ToepJob<T>> jobs(G);
+    std::vector<Counts> n(G);
+    for (int g = 0; g < G; ++g) jobs[g] = make_job(g, e, step, n[g]);
+    store(step, jobs, n);
   }
 }
 
