@@ -83,6 +83,51 @@ def test_additive_apply_khat_and_kuu_parity(f64):
     cache.free()
 
 
+@pytest.mark.parametrize("toeplitz", ["direct", "fft"])
+def test_additive_toeplitz_backends(toeplitz):
+    """Long axes (m_i > 256) take the banded direct product or the FFT, short
+    ones the line kernel; all blocks of a GP run as jobs of one pass.  K g and
+    Khat v against the oracle's block operator."""
+    P = add_problem(3, 20000, (300, 280, 40), k=8)
+    cache = build(P, flags=B.FLAG_NO_MEAN, toeplitz=toeplitz)
+    spec = spec_of(P)
+    modes = list(cache.info().toeplitz_mode)[:3]
+    assert modes == ([1, 1, 1] if toeplitz == "direct" else [2, 2, 2])
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(spec.mtot).astype(np.float32)
+    outk = host(cache.apply_kuu(tdev(g, torch.float32)))
+    refk = O.K_apply(spec, g.astype(np.float64))
+    assert np.max(np.abs(outk - refk)) / np.max(np.abs(refk)) <= 1e-5
+    v = rng.standard_normal(P.n).astype(np.float32)
+    out = host(cache.apply_khat(tdev(v, torch.float32)))
+    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(v.astype(np.float64))
+    assert np.max(np.abs(out - ref)) / np.max(np.abs(ref)) <= 1e-5
+    cache.free()
+
+
+def test_additive_sampler_banded_axes():
+    """Sampler on a stacked grid of two long axes (banded direct product, so
+    the sampler's fused band + Rt^T q launch runs both blocks): k' = 60 < m =
+    700, so both sides are truncated approximations of W*(K - R^T R')W*^T; the
+    GPU's truncation error must be of the oracle's size."""
+    P = add_problem(2, 20000, (300, 400), k=60, k_sample=60, t_sample=300, s=4,
+                    lengthscale=(0.05, 0.08))
+    cache = build(P, toeplitz="direct")
+    S = host(cache.export()["s"])
+    oc = oracle_cache(P)
+    osm = O.love_sampler(oc, P.k_sample)
+    xs = P.xs_sample.astype(np.float64)
+    spec = spec_of(P)
+    Wd = O.interp_matrix(xs, spec).toarray()
+    target = Wd @ (O.K_dense(spec) - oc.R.T @ oc.Rp) @ Wd.T
+    F = Wd @ S
+    err_gpu = np.max(np.abs(F @ F.T - target))
+    err_or = np.max(np.abs(O.sample_covariance_implied(oc, osm, xs) - target))
+    print(cache.info().k_eff_sample, err_gpu, err_or, flush=True)
+    assert err_gpu <= 3 * err_or + 1e-5
+    cache.free()
+
+
 def test_additive_one_axis_matches_product():
     """d = 1: the additive path (cell lists, block plan) and the product path
     build the same model."""
