@@ -119,6 +119,27 @@ def test_host_validation_rejects_bad_arguments(lib):
     lib.love_cache_free(None)   # no-op
 
 
+def test_additive_validation(lib):
+    """Additive compositions: the stacked grid's sizes are checked as sums,
+    and a batch must agree on the composition (both before any device call)."""
+    from paper_1803_06058_amd import binding as B
+    out = C.c_void_p()
+    big = B.config_struct(2, [1 << 25, 100], [0.0, 0.0], [1.0, 1.0], lengthscale=[0.1], k=10,
+                          flags=B.FLAG_ADDITIVE)
+    assert lib.love_build_cache(C.byref(big), C.c_void_p(8), C.c_void_p(8), 10, None, C.byref(out)) == -1
+    small = B.config_struct(2, [3, 100], [0.0, 0.0], [1.0, 1.0], lengthscale=[0.1], k=10,
+                            flags=B.FLAG_ADDITIVE)                        # m < 4 on an axis
+    assert lib.love_build_cache(C.byref(small), C.c_void_p(8), C.c_void_p(8), 10, None, C.byref(out)) == -1
+    a = B.config_struct(2, [50, 60], [0.0, 0.0], [1.0, 1.0], lengthscale=[0.1], k=10,
+                        flags=B.FLAG_ADDITIVE)
+    p = B.config_struct(2, [50, 60], [0.0, 0.0], [1.0, 1.0], lengthscale=[0.1], k=10)
+    cfgs = (B.love_config * 2)(a, p)
+    ptrs = (C.c_void_p * 2)(8, 8)
+    ns = (C.c_int64 * 2)(10, 10)
+    outs = (C.c_void_p * 2)()
+    assert lib.love_build_cache_batched(2, cfgs, ptrs, ptrs, ns, None, outs) == -1
+
+
 def test_python_binding_refuses_cpu_tensors(lib):
     import torch
     from paper_1803_06058_amd import binding as B
