@@ -276,9 +276,10 @@ size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
   return ((size_t)1 << (2 * c->d)) * (size_t)c->ctot * elem;
 }
 
-// Stage 1 for heavy cells (d <= 2): one wave per cell, lanes stride its rows
-// in batches of eight (loads first); each lane keeps the 4^D partial products
-// and the wave sums them in a fixed butterfly.
+// Stage 1 for heavy cells (d <= 2): one block of 256 threads per cell (a wave
+// per cell left too few, too long waves for an even finish); threads stride
+// its rows in batches (loads first), keep the 4^D partial products, and the
+// block sums them: a fixed butterfly per wave, then the four waves in order.
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
                                                             const ScatterJob<T>* __restrict__ jobs,
@@ -288,9 +289,10 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
   const ScatterJob<T>& J = jobs[gp];
   if (ctl_skip(J.ctl, mode) || !J.cellp) return;
   const GridT<T>& g = J.g;
-  const int64_t c = (int64_t)lb * (256 / WAVE) + threadIdx.x / WAVE;
+  const int64_t c = lb;
   if (c >= g.ctot) return;
   const int lane = threadIdx.x & (WAVE - 1);
+  constexpr int NT = 256;
   using GT = const __attribute__((address_space(1))) T;
   GT* gx = (GT*)J.x;
   GT* gv = (GT*)(J.v + (int64_t)j * J.v_js);
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
   const T ratio = comb ? (T)J.ctl->ratio : T(0);
   const int32_t r0 = J.cell_start[c], r1 = J.cell_start[c + 1];
   constexpr int NO = 1 << (2 * D);
-  constexpr int UB = 8;
+  constexpr int UB = D == 1 ? 16 : 8;
   T cb[D];   // stencil base of the cell's rows (fraction = (x - lo) invh - c_e)
   {
     int64_t rem = c;
@@ -313,11 +315,11 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
   T acc[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = T(0);
-  for (int32_t rs = r0 + lane; rs < r1; rs += UB * WAVE) {
+  for (int32_t rs = r0 + (int32_t)threadIdx.x; rs < r1; rs += UB * NT) {
     T xr[UB][D], vr[UB];
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
-      const int64_t r = min(rs + q * WAVE, r1 - 1);
+      const int64_t r = min(rs + q * NT, r1 - 1);
 #pragma unroll
       for (int e = 0; e < D; ++e) xr[q][e] = gx[r * D + e];
       vr[q] = gv[r];
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
     }
 #pragma unroll
     for (int q = 0; q < UB; ++q) {
-      if (rs + q * WAVE >= r1) break;
+      if (rs + q * NT >= r1) break;
       T w[D][4];
 #pragma unroll
       for (int e = 0; e < D; ++e) keys_weights<T>((xr[q][e] - g.lo[e]) * g.invh[e] - cb[e], w[e]);
@@ -338,11 +340,19 @@ __global__ __launch_bounds__(256) void k_scatter_cells_wave(Tab tab,
       }
     }
   }
-  T* __restrict__ P = J.cellp;
+  __shared__ T ws[NT / WAVE][NO];
+  const int w = threadIdx.x / WAVE;
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    const T s = wave_sum(acc[o]);
-    if (lane == 0) P[(int64_t)o * g.ctot + c] = s;
+    const T sw = wave_sum(acc[o]);
+    if (lane == 0) ws[w][o] = sw;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NO) {
+    T tot = T(0);
+#pragma unroll
+    for (int q = 0; q < NT / WAVE; ++q) tot += ws[q][threadIdx.x];
+    J.cellp[(int64_t)threadIdx.x * g.ctot + c] = tot;
   }
 }
 
@@ -446,9 +456,10 @@ __global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
 // tab: cdiv(m, 4) blocks per GP (one wave per node).  A job with cellp set
 // takes the two stages, the others the one-wave-per-node kernel; `kinds`
 // (SCATTER_*) says which launches the batch needs, and each kernel skips the
-// other kind's jobs.  The wave-per-cell stage 1 (d <= 2) fits in the same tab
-// (ctot < m); the lane-per-cell stage 1 (d >= 3) and stage 2 take
-// cdiv(4 * blocks, 256) blocks per GP, which covers both nodes and cells.
+// other kind's jobs.  The block-per-cell stage 1 (d <= 2) and the additive
+// kernel (block per node) take 4 blocks per tab block (covering ctot < m and
+// m); the lane-per-cell stage 1 (d >= 3) and stage 2 take cdiv(4 * blocks,
+// 256) blocks per GP, which covers both nodes and cells.
 template <typename T>
 void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int mode,
                     hipStream_t s, int kinds) {
@@ -459,13 +470,19 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
     for (int g = 0; g < tab.G; ++g) b[g] = cdiv(tab.off[g + 1] - tab.off[g], 64);
     const Tab t2 = make_tab(b);
     const unsigned n2 = tab_blocks(t2);
+    // heavy-cell stage 1 (d <= 2): one block per cell; 4 blocks per node block
+    // of the tab covers ctot < m cells
+    std::vector<int64_t> bc(tab.G);
+    for (int g = 0; g < tab.G; ++g) bc[g] = 4 * (tab.off[g + 1] - tab.off[g]);
+    const Tab tc = make_tab(bc);
+    const unsigned nc = tab_blocks(tc);
     switch (d) {
       case 1:
-        tlaunch("scatter_cells", k_scatter_cells_wave<T, 1>, nb, 256, 0, s, tab, jobs, j, mode);
+        tlaunch("scatter_cells", k_scatter_cells_wave<T, 1>, nc, 256, 0, s, tc, jobs, j, mode);
         tlaunch("scatter", k_scatter_nodes<T, 1>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
       case 2:
-        tlaunch("scatter_cells", k_scatter_cells_wave<T, 2>, nb, 256, 0, s, tab, jobs, j, mode);
+        tlaunch("scatter_cells", k_scatter_cells_wave<T, 2>, nc, 256, 0, s, tc, jobs, j, mode);
         tlaunch("scatter", k_scatter_nodes<T, 2>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
       case 3:
@@ -507,7 +524,7 @@ template void launch_scatter<double>(const Tab&, const ScatterJob<double>*, int,
 // W u (+ sigma^2 v): GR sorted rows per thread (rows lb 256 GR + t + 256 q),
 // all of whose x and v loads are issued before any stencil is formed.
 // ----------------------------------------------------------------------------
-constexpr int GR = 4;
+constexpr int GR = 8;
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_gather(Tab tab, const GatherJob<T>* __restrict__ jobs,
                                                 int mode) {
