@@ -189,6 +189,50 @@ def test_additive_sampler_cache_parity():
     cache.free()
 
 
+def test_additive_bf16split_parity():
+    """The BF16 hi + lo split cache on the block form (e_p <= 1e-3, the split
+    cache's bound)."""
+    P = WL.make_problem("add2d_split", d=2, n=3000, m=(60, 45), kernel="rbf", lengthscale=(0.15, 0.15),
+                        noise=0.01, k=40, t=2000, target="styblinski_tang", ynoise=0.1,
+                        precision="bf16split", additive=True)
+    cache = build(P)
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, P.xs.astype(np.float64))
+    p = O.prior_var(P.xs, spec_of(P))
+    e = errors(host(var), v_ref, p, host(mu), m_ref, P.y)
+    print(e, flush=True)
+    assert e["e_p_max"] <= 1e-3
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    cache.free()
+
+
+def test_additive_large_batch_per_axis_passes():
+    """17 additive 4-D GPs hold 68 axis blocks, more than one pass takes: the
+    batch runs one Toeplitz pass per axis, and each GP still equals its own
+    build (one pass for its 4 blocks) bit for bit."""
+    Ps = [add_problem(4, 400 + 37 * i, (10 + i % 3, 12, 9 + i % 2, 11), k=12 + i % 5, t=64, seed=10 + i)
+          for i in range(17)]
+    caches = B.build_cache_batched([cfg_of(P) for P in Ps], [tdev(P.x, torch.float32) for P in Ps],
+                                   [tdev(P.y, torch.float32) for P in Ps])
+    for g in (0, 7, 16):
+        P = Ps[g]
+        q = tdev(P.xs, torch.float32)
+        single = build(P)
+        m0, v0 = caches[g].predict_mean_var(q)
+        m1, v1 = single.predict_mean_var(q)
+        assert caches[g].info().cg_iters == single.info().cg_iters
+        assert torch.equal(v0, v1) and torch.equal(m0, m1)
+        single.free()
+    P = Ps[16]
+    oc = oracle_cache(P)
+    _, v_ref = O.love_predict(oc, P.xs.astype(np.float64))
+    _, v = caches[16].predict_mean_var(tdev(P.xs, torch.float32))
+    assert np.max(np.abs(host(v) - v_ref) / O.prior_var(P.xs, spec_of(P))) <= 1e-5
+    for c in caches:
+        c.free()
+
+
 def test_additive_mixed_batch_rejected():
     """A batch must agree on the composition."""
     Pa = add_problem(2, 1000, (20, 20), k=10, t=16)
