@@ -140,7 +140,8 @@ typedef struct {
   int32_t k_eff_sample;             /* columns of S                                               */
   int32_t cg_iters;                 /* CG iterations of the mean solve                            */
   int32_t d;
-  int64_t n, m;
+  int64_t n, m;                     /* training rows; grid points (product of the m_i, or their
+                                       sum for LOVE_FLAG_ADDITIVE: the rows of rt, a and s)       */
   double beta_last;                 /* last Lanczos off-diagonal                                  */
   double ortho_loss;                /* max |Q^T Q - I| of the Lanczos vectors (NaN: not computed,
                                        i.e. without the preconditioned mean solve)                */
