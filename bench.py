@@ -383,7 +383,8 @@ def lanczos_large_section(B, torch, dev, n=1 << 21):
 def forms_section(B, WL, torch, dev, reps=3):
     """The other forms of the path at their full sizes, timed on this GPU (median
     of `reps` after one warm-up, host clock around synchronised calls):
-    bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances),
+    fp64 (1-D, n = 1000, m = 100, k = 50, 1000 variances: latency-bound, its
+    time is the figure), bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances),
     differentiable (4-D product Matern-5/2, n = 2e5, m = 20^4, k = 64, forward
     and backward at 262,144 points) and additive (Sec. 3.4: sum of four 1-D RBF
     components, n = 1e5, m = 100 per axis, k = 50, 1e6 variances)."""
@@ -403,7 +404,8 @@ def forms_section(B, WL, torch, dev, reps=3):
                 r.free()
         return statistics.median(ts)
 
-    for name, idx in (("bf16split_2d", 3), ("differentiable_4d", 4), ("additive_4d", 0)):
+    for name, idx in (("fp64_1d_small", 1), ("bf16split_2d", 3), ("differentiable_4d", 4),
+                      ("additive_4d", 0)):
         P = WL.config(idx) if idx else WL.additive_config()
         cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
                               lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
