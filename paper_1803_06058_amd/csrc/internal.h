@@ -200,6 +200,11 @@ struct ToepRun {
     size_t jobs = 0;
     Tab band{}, reduce{}, lines{}, fft{};
     size_t smem_lines = 0, smem_fft = 0;
+    // the first job's banded segments (nseg0 > 1: partial0 holds nseg0 x L0
+    // values that the segment sums add), for consumers that add them themselves
+    int nseg0 = 0;
+    int64_t L0 = 0;
+    const void* partial0 = nullptr;
   };
   int d = 0;
   int jpg = 1;   // table entries (jobs) per GP: d when an additive batch runs in one pass

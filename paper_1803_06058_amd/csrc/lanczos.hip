@@ -1293,7 +1293,11 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
                                                        const double* __restrict__ Q, int64_t ldq,
                                                        int ncols, double* __restrict__ vout,
                                                        double* __restrict__ partial,
-                                                       const Ctl* ctl) {
+                                                       const Ctl* ctl,
+                                                       const double* __restrict__ rtpart,
+                                                       int nbr,
+                                                       const double* __restrict__ kseg,
+                                                       int nseg, int64_t segL) {
   if (ctl->stop) return;
   constexpr int RBK = WAVE * RPL;
   constexpr int NW = RBLK / WAVE;
@@ -1304,8 +1308,24 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
   using RV = decltype(rt_raw<TR, SPLIT>(nullptr, nullptr, 0));
   __shared__ double vl[RBK];
   __shared__ double sl[2 * WAVE];
+  __shared__ double kl[RBK];
   const int64_t r0 = (int64_t)blockIdx.x * RBK;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (kseg) {
+    // K q on the block's rows from the banded segments (a fixed number of
+    // masked loads, issued first), added in segment order as the segment-sum
+    // kernel adds them (scale 1)
+    if ((int)threadIdx.x < RBK) {
+      const int64_t u = min<int64_t>(r0 + threadIdx.x, m - 1);
+      double sv_[TB_NSEG_MAX];
+#pragma unroll
+      for (int q = 0; q < TB_NSEG_MAX; ++q) sv_[q] = q < nseg ? kseg[(int64_t)q * segL + u] : 0.0;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < TB_NSEG_MAX; ++q) acc += sv_[q];
+      kl[threadIdx.x] = acc;
+    }
+  }
   QRegs<double, RPL> qr;   // Q' tile for the dots
   qregs_load<double, RPL>(qr, Q, ldq, ncols, r0 + RPL * lane);
   RV a0[NIT][NR], a1[NIT][NR];
@@ -1320,7 +1340,14 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
     }
   }
   const int keff = ctl_main->k_eff;
-  for (int c = threadIdx.x; c < 2 * WAVE; c += RBLK) sl[c] = c < keff ? sv[c] : 0.0;
+  if (rtpart) {
+    // s = Rt^T q from the nbr partial rows (the segment-sum launch is skipped)
+    rows_sum(rtpart, nbr, 2 * WAVE, sl);
+    for (int c = threadIdx.x; c < 2 * WAVE; c += RBLK)
+      if (c >= keff) sl[c] = 0.0;
+  } else {
+    for (int c = threadIdx.x; c < 2 * WAVE; c += RBLK) sl[c] = c < keff ? sv[c] : 0.0;
+  }
   __syncthreads();
   const double s0 = sl[lane], s1 = sl[lane + WAVE];
 #pragma unroll
@@ -1335,7 +1362,7 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
       const int64_t u = r0 + rb + i;
       double val = 0.0;
       if (u < m) {
-        val = kv[u] - tot;
+        val = (kseg ? kl[rb + i] : kv[u]) - tot;
         vout[u] = val;
       }
       vl[rb + i] = val;
@@ -1797,8 +1824,8 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     k_rt_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, gv, c->rt, rlo, c->kpad, cm,
                                                             partial, ctl);
     launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
-    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(m, kv, c->rt, rlo, c->kpad, cm,
-                                                                  sv, Q, ldq, 0, v, partial, ctl);
+    k_sp_apply_dots<TR, SPLIT, RPL><<<(unsigned)nb, RBLK, 0, s>>>(
+        m, kv, c->rt, rlo, c->kpad, cm, sv, Q, ldq, 0, v, partial, ctl, nullptr, 0, nullptr, 0, 0);
     k_lz_norm<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ);
     k_lz_bnorm<double><<<1, WAVE, 0, s>>>(t1, dJ);
     k_lz_start<double><<<(unsigned)nb, RBLK, 0, s>>>(tnb, dJ);
@@ -1807,6 +1834,11 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   const auto& ax0 = t_step.ax[0];
   const bool fuse = t_step.d == 1 && tab_blocks(ax0.band) > 0 && tab_blocks(ax0.lines) == 0 &&
                     tab_blocks(ax0.fft) == 0;
+  // one banded job and in-kernel partial sums: the apply kernel also adds the
+  // banded segments of its rows and the Rt^T q partial rows (which then go to
+  // the second partial buffer), and the segment-sum launch is skipped
+  const bool fold = fuse && J.psum && ax0.band.G == 1;
+  const double* kseg = (fold && ax0.nseg0 > 1) ? (const double*)ax0.partial0 : nullptr;
   for (int j = 0; j < ks; ++j) {
     ProfScope ps("sampler_step", s);
     const double* qj = Q + (size_t)j * ldq;
@@ -1814,10 +1846,11 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
       const ToepJob<double>* tj = A.at<ToepJob<double>>(ax0.jobs);
       const unsigned nbb = tab_blocks(ax0.band), nrb = tab_blocks(ax0.reduce);
       tlaunch("sp_band_rt", k_sp_band_rt<TR, SPLIT, RPL>, nbb + (unsigned)nb, RBLK, 0, s,
-              ax0.band, tj, j, (int)nbb, m, qj, c->rt, rlo, c->kpad, cm, partial,
+              ax0.band, tj, j, (int)nbb, m, qj, c->rt, rlo, c->kpad, cm, fold ? partial2 : partial,
               (const Ctl*)ctl);
-      tlaunch("sp_reduce_sum", k_sp_reduce_sum, nrb + (unsigned)cdiv(c->k, BLK / WAVE), BLK, 0,
-              s, ax0.reduce, tj, j, (int)nrb, A.at<SumJob>(o_rt), (const Ctl*)ctl);
+      if (!fold)
+        tlaunch("sp_reduce_sum", k_sp_reduce_sum, nrb + (unsigned)cdiv(c->k, BLK / WAVE), BLK, 0,
+                s, ax0.reduce, tj, j, (int)nrb, A.at<SumJob>(o_rt), (const Ctl*)ctl);
     } else {
       toep_run<double>(A, t_step, j, 1, s);
       tlaunch("rt_dots", k_rt_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, qj, c->rt, rlo,
@@ -1825,7 +1858,9 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
       launch_colsum(A.at<SumJob>(o_rt), nvk, 0, 1, s);
     }
     tlaunch("sp_apply", k_sp_apply_dots<TR, SPLIT, RPL>, (unsigned)nb, RBLK, 0, s, m, kv, c->rt,
-            rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl);
+            rlo, c->kpad, cm, sv, Q, ldq, j + 1, v, partial, (const Ctl*)ctl,
+            fold ? (const double*)partial2 : (const double*)nullptr, (int)nb, kseg,
+            (int)ax0.nseg0, (int64_t)ax0.L0);
     if (!J.psum) launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
     tlaunch("sp_udots", k_lz_udots<double, 1>, (unsigned)nb, RBLK, 0, s, tnb, dJ, j);
     if (!J.psum) launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);

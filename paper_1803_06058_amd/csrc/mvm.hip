@@ -761,6 +761,9 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
     A_.fft = make_tab(nfft);
     A_.smem_lines = sl;
     A_.smem_fft = sf;
+    A_.nseg0 = jobs.empty() ? 0 : jobs[0].nseg;
+    A_.L0 = jobs.empty() ? 0 : jobs[0].L;
+    A_.partial0 = jobs.empty() ? nullptr : jobs[0].partial;
   };
   if (add && (int64_t)G * d <= MAXG) {
     // additive: the d independent blocks of every GP in one pass (one launch
