@@ -99,8 +99,10 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
         return ks_eff * (f * m * k_eff + 16 * m + 8 * mb * k_eff)
     if name == "sp_reduce_sum":  # K q_j out (one segment in), the s partial rows
         return ks_eff * (16 * m + 8 * mb * k_eff)
-    if name == "sp_apply":      # Rt (float), kv, v, Q'_{0..j} (double)
-        return sum(f * m * k_eff + 16 * m + 8 * m * (j + 1) for j in range(ks_eff))
+    if name == "sp_apply":      # Rt (float), K q, v, Q'_{0..j} (double); with in-kernel sums also
+        # the Rt^T q partial rows (the segment-sum launch is then skipped)
+        return sum(f * m * k_eff + 16 * m + 8 * m * (j + 1) + (8 * mb * k_eff if samp_ps else 0)
+                   for j in range(ks_eff))
     if name == "rt_dots":
         return ks_eff * (f * m * k_eff + 8 * m)
     if name == "sp_udots":
