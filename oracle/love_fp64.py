@@ -15,8 +15,11 @@ Processes", ICML 2018):
   * constant-time mean a = K W^T Khat^-1 y ...... Sec. 2.3, eq. pred_mean_ski
   * exact KISS-GP covariance (naive cache C) .... Sec. 3.1, eqs. pred_covar_approx,
                                                     pred_covar_ski_cache
-  * LOVE cache R, R' and the O(k) query ......... Sec. 3.2, eq. pred_covar_ski_fast,
-                                                    Algorithm 1
+  * LOVE cache and the O(k) query .............. Sec. 3.2, eqs. pred_covar_ski_cache,
+                                                    pred_covar_ski_fast, lanczos_solve
+  * Lanczos restart with a new probe ............ Sec. 5, "Ensuring Lanczos solves are accurate"
+  * gradients w.r.t. x*, Rt and hyper-parameters  derived from eqs. pred_mean_ski,
+                                                    pred_covar_approx, pred_covar_ski_fast
   * LOVE sampling matrix S ...................... Sec. 3.3, eqs. pred_covar_ski_interp_form12,
                                                     lancapprox, pred_covar_ski_interp_form
   * full reorthogonalisation .................... Sec. 5, "Numerical stability of Lanczos"
@@ -41,6 +44,13 @@ Readings of points the paper leaves open (each is listed in the design notes):
   additive  k(x, x') = outputscale * sum_d k_d(x_d, x'_d): one 1-D component per
             dimension on that dimension's grid; the stacked grid holds the
             axes one after another (axis 0 first), K is block diagonal
+  cache     one m x k factor Rt = K W^T Q L^{-T} with R^T R' = Rt Rt^T (T = L L^T)
+  restart   the solve is checked on run-averaged columns of W K; the new probe is
+            the residual of the worst one; the two Krylov blocks are combined by
+            the projected matrix H = Q^T Khat Q and its dense Cholesky factor
+  hyper     hyper-parameters: lengthscale per dimension, outputscale, sigma^2;
+            gradients of the LOVE variance take every solve Khat^{-1} as the
+            cached Lanczos solve Q H^{-1} Q^T
 """
 from __future__ import annotations
 
@@ -315,22 +325,116 @@ def prior_var_grad(Xs, spec: Spec) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# The training operator  Khat = W K W^T + sigma^2 I  (Alg. 1 input mvm_K_XX)
+# Derivatives of the grid kernel with respect to its hyper-parameters
 # ---------------------------------------------------------------------------
-class Operator:
+def kernel_1d_dell(r, kind: str, ell: float):
+    """d k(r) / d ell for the 1-D kernels of kernel_1d.
+
+    RBF: k = exp(-r^2 / (2 ell^2)), so dk/dell = k r^2 / ell^3.
+    Matern-5/2: k = (1 + z + z^2/3) e^{-z} with z = sqrt(5) r / ell; dk/dz =
+    -z (1 + z) e^{-z} / 3 and dz/dell = -z / ell, so dk/dell = z^2 (1 + z) e^{-z} / (3 ell)."""
+    r = np.abs(np.asarray(r, dtype=np.float64))
+    if kind == "rbf":
+        return np.exp(-0.5 * (r / ell) ** 2) * r * r / ell ** 3
+    if kind == "matern52":
+        z = math.sqrt(5.0) * r / ell
+        return z * z * (1.0 + z) * np.exp(-z) / (3.0 * ell)
+    raise ValueError(kind)
+
+
+def hyper_names(spec: Spec) -> List[str]:
+    """Hyper-parameters in the order the gradients are returned: one lengthscale
+    per dimension, then the outputscale, then the noise variance sigma^2."""
+    return [f"lengthscale{e}" for e in range(spec.d)] + ["outputscale", "noise"]
+
+
+def _toeplitz_apply(c: np.ndarray, G2: np.ndarray) -> np.ndarray:
+    """Symmetric Toeplitz matrix with first column c times G2 (dense for short
+    axes, scipy's FFT Toeplitz product for long ones)."""
+    if c.shape[0] <= 512:
+        return sla.toeplitz(c) @ G2
+    return sla.matmul_toeplitz((c, c), G2, check_finite=False)
+
+
+def K_apply_dtheta(spec: Spec, which: int, G: np.ndarray) -> np.ndarray:
+    """(d K_UU / d theta_which) @ G for G of shape (m,) or (m, B), theta in
+    hyper_names order: the product form differentiates one Kronecker factor,
+    the additive form one diagonal block; d K / d outputscale = K / outputscale;
+    the noise does not enter K_UU (zero)."""
+    G = np.asarray(G, dtype=np.float64)
+    if which == spec.d + 1:
+        return np.zeros_like(G)
+    if which == spec.d:
+        return K_apply(spec, G) / spec.outputscale
+    vec = G.ndim == 1
+    B = 1 if vec else G.shape[1]
+    e = which
+    dcol = kernel_1d_dell(np.arange(spec.m[e]) * spec.h(e), spec.kernel, spec.lengthscale[e])
+    if spec.additive:
+        G2 = G.reshape(spec.mtot, B)
+        Y = np.zeros_like(G2)
+        blk = slice(spec.offset(e), spec.offset(e) + spec.m[e])
+        Y[blk] = _toeplitz_apply(dcol, G2[blk])
+    else:
+        Y = G.reshape(*spec.m, B)
+        for dim in range(spec.d):
+            c = dcol if dim == e else toeplitz_column(spec, dim)
+            Y = np.moveaxis(Y, dim, 0)
+            sh = Y.shape
+            Y = np.moveaxis(_toeplitz_apply(c, Y.reshape(sh[0], -1)).reshape(sh), 0, dim)
+        Y = Y.reshape(spec.mtot, B)
+    Y = spec.outputscale * Y
+    return Y[:, 0] if vec else Y
+
+
+def prior_var_dtheta(Xs, spec: Spec) -> np.ndarray:
+    """d p(x*) / d theta (t x (d + 2), hyper_names order), p = w*^T K w*: only the
+    4 x 4 blocks of the axis matrices on each point's stencil enter."""
+    Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64)).reshape(-1, spec.d)
+    t, d = Xs.shape
+    quad, dquad = [], []
+    for e in range(d):
+        _, w, _ = stencil_axis(Xs[:, e], spec, e)
+        r = np.arange(4) * spec.h(e)
+        T4 = sla.toeplitz(toeplitz_column(spec, e)[:4])
+        D4 = sla.toeplitz(kernel_1d_dell(r, spec.kernel, spec.lengthscale[e]))
+        quad.append(np.einsum("ia,ab,ib->i", w, T4, w))
+        dquad.append(np.einsum("ia,ab,ib->i", w, D4, w))
+    out = np.zeros((t, d + 2))
+    s = spec.outputscale
+    for e in range(d):
+        if spec.additive:
+            out[:, e] = s * dquad[e]
+        else:
+            prod = np.full(t, s)
+            for f in range(d):
+                prod = prod * (dquad[f] if f == e else quad[f])
+            out[:, e] = prod
+    out[:, d] = prior_var(Xs, spec) / s
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The KISS-GP training operator (Sec. 2.3, eq. ski)
+# ---------------------------------------------------------------------------
+class KissOperator:
+    """Khat = W K W^T + sigma^2 I with W the n x m interpolation matrix
+    (the transpose of the paper's m x n W_X), and the grid-side product
+    K W^T V (the paper's K_UU W_X V, an approximation of K_UX V)."""
+
     def __init__(self, X, spec: Spec):
         self.spec = spec
         self.W = interp_matrix(X, spec)
         self.WT = self.W.T.tocsr()
         self.n = self.W.shape[0]
 
-    def mvm_K_UX(self, V):
-        """K_UU W^T V  (Alg. 1 input mvm_K_UX)."""
+    def to_grid(self, V):
+        """K W^T V: n-space vectors mapped onto the grid (m x ...)."""
         return K_apply(self.spec, self.WT @ V)
 
-    def mvm_K_XX(self, V):
+    def khat(self, V):
         """(W K W^T + sigma^2 I) V."""
-        return self.W @ self.mvm_K_UX(V) + self.spec.noise * V
+        return self.W @ self.to_grid(V) + self.spec.noise * V
 
     def dense(self) -> np.ndarray:
         Wd = self.W.toarray()
@@ -344,7 +448,7 @@ def exact_route_A(X, y, Xs, spec: Spec):
     """Dense n-space: mean and variance from eqs. pred_mean_ski / pred_covar_approx.
 
     Returns (mean, var) with var = p(x*) - k~_{X x*}^T Khat^{-1} k~_{X x*}."""
-    op = Operator(X, spec)
+    op = KissOperator(X, spec)
     A = op.dense()
     L = np.linalg.cholesky(A)
     Wd = op.W.toarray()
@@ -362,7 +466,7 @@ def exact_route_A(X, y, Xs, spec: Spec):
 def exact_route_B(X, y, Xs, spec: Spec):
     """m-space identity: Sigma_U = K - K W^T Khat^{-1} W K = B (I + BW^TWB/sigma^2)^{-1} B,
     B = K^{1/2}.  var = ||L_B^{-1} B w*||^2; mean through Woodbury.  No cancellation."""
-    op = Operator(X, spec)
+    op = KissOperator(X, spec)
     s2 = spec.noise
     K = K_dense(spec)
     lam, U = np.linalg.eigh(K)
@@ -387,13 +491,46 @@ def exact_route_B(X, y, Xs, spec: Spec):
 
 def exact_covariance_grid(X, spec: Spec) -> np.ndarray:
     """Sigma_U = K - K W^T Khat^{-1} W K (m x m), the grid-space posterior covariance."""
-    op = Operator(X, spec)
+    op = KissOperator(X, spec)
     K = K_dense(spec)
     A = op.dense()
     KWt = K @ op.W.toarray().T
     L = np.linalg.cholesky(A)
     V = sla.solve_triangular(L, KWt.T, lower=True)
     return K - V.T @ V
+
+
+def _var_hyper_grad(spec: Spec, W, Xs, Z, g) -> np.ndarray:
+    """sum_i g_i d var_i / d theta (hyper_names order) for
+    var_i = w_i^T K w_i - w_i^T K W^T z_i, z_i = Khat^{-1} W K w_i (column i of
+    Z, n x t), by the product rule:
+      d var_i = w_i^T dK w_i - 2 w_i^T dK W^T z_i + z_i^T (W dK W^T + d sigma^2 I) z_i
+    (the last term has a plus sign because d(A^{-1}) = -A^{-1} dA A^{-1}).
+    W is the training interpolation matrix (n x m, sparse)."""
+    Ws = interp_matrix(Xs, spec)
+    g = np.asarray(g, dtype=np.float64)
+    Y = np.asarray(W.T @ Z)                         # m x t : W^T z_i
+    dp = prior_var_dtheta(Xs, spec)                 # t x (d + 2) : w_i^T dK w_i
+    out = np.zeros(spec.d + 2)
+    for th in range(spec.d + 2):
+        DY = K_apply_dtheta(spec, th, Y)
+        cross = np.asarray(Ws.multiply(DY.T).sum(axis=1)).ravel()      # w_i^T dK W^T z_i
+        quad = np.sum(Y * DY, axis=0)                                   # z_i^T W dK W^T z_i
+        if th == spec.d + 1:
+            quad = quad + np.sum(Z * Z, axis=0)
+        out[th] = np.sum(g * (dp[:, th] - 2.0 * cross + quad))
+    return out
+
+
+def exact_var_hyper_grad(X, Xs, spec: Spec, g_var) -> np.ndarray:
+    """Gradient of sum_i g_i var(x*_i) with respect to the hyper-parameters
+    (hyper_names order) for the exact KISS-GP variance
+    var = w^T K w - w^T K W^T Khat^{-1} W K w (eqs. pred_covar_approx,
+    pred_covar_ski_cache), with z_i = Khat^{-1} W K w_i from a dense solve."""
+    op = KissOperator(X, spec)
+    Ws = interp_matrix(Xs, spec)
+    Z = np.linalg.solve(op.dense(), op.W @ K_apply(spec, Ws.T.toarray()))
+    return _var_hyper_grad(spec, op.W, Xs, Z, g_var)
 
 
 # ---------------------------------------------------------------------------
@@ -419,10 +556,10 @@ def cg(matvec, b, tol=1e-12, maxit=2000):
     return x, it
 
 
-def mean_cache(op: Operator, y, tol=1e-12, maxit=2000):
+def mean_cache(op: KissOperator, y, tol=1e-12, maxit=2000):
     """a = K_UU W^T (W K W^T + sigma^2 I)^{-1} y (eq. pred_mean_ski), solve by CG."""
-    sol, it = cg(op.mvm_K_XX, y, tol=tol, maxit=maxit)
-    return op.mvm_K_UX(sol), it
+    sol, it = cg(op.khat, y, tol=tol, maxit=maxit)
+    return op.to_grid(sol), it
 
 
 # ---------------------------------------------------------------------------
@@ -440,19 +577,26 @@ class LanczosResult:
         return np.diag(self.alpha[:k]) + np.diag(self.beta[: k - 1], 1) + np.diag(self.beta[: k - 1], -1)
 
 
-def lanczos(matvec, b, k: int, tol: float = 1e-12) -> LanczosResult:
+def lanczos(matvec, b, k: int, tol: float = 1e-12, basis=None) -> LanczosResult:
     """k steps of Lanczos on the symmetric operator `matvec` with probe `b`.
 
     q_1 = b/||b||; alpha_j = q_j^T A q_j; r = A q_j - alpha_j q_j - beta_{j-1} q_{j-1};
     r is then orthogonalised against every previous q twice (classical
     Gram-Schmidt, two passes); beta_j = ||r||; q_{j+1} = r / beta_j.
-    Stops early (k_eff < k) when beta_j <= tol * max_i |alpha_i|."""
+    Stops early (k_eff < k) when beta_j <= tol * max_i |alpha_i|.
+
+    basis (n x p, orthonormal columns, optional): vectors of an earlier run
+    that every new vector, b included, is also orthogonalised against (the
+    second block of a restart, Sec. 5 "Ensuring Lanczos solves are accurate")."""
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
-    k = min(k, n)
+    P = np.zeros((n, 0)) if basis is None else basis
+    k = min(k, n - P.shape[1])
     Q = np.zeros((n, k))
     alpha = np.zeros(k)
     beta = np.zeros(k)
+    for _ in range(2):
+        b = b - P @ (P.T @ b)
     Q[:, 0] = b / np.linalg.norm(b)
     k_eff = k
     for j in range(k):
@@ -462,7 +606,7 @@ def lanczos(matvec, b, k: int, tol: float = 1e-12) -> LanczosResult:
         r = w - alpha[j] * q
         if j > 0:
             r -= beta[j - 1] * Q[:, j - 1]
-        Qj = Q[:, : j + 1]
+        Qj = np.concatenate([P, Q[:, : j + 1]], axis=1)
         for _ in range(2):
             r -= Qj @ (Qj.T @ r)
         beta[j] = np.linalg.norm(r)
@@ -494,80 +638,163 @@ def tridiag_cholesky(alpha: np.ndarray, beta: np.ndarray) -> Tuple[np.ndarray, n
 
 
 # ---------------------------------------------------------------------------
-# Sec. 3.2 + Algorithm 1: the LOVE cache
+# Sec. 3.2: the LOVE cache
+#
+# C = K W^T Khat^{-1} W K (eq. pred_covar_ski_cache).  The Lanczos solve of
+# eq. lanczos_solve replaces Khat^{-1} by Q T^{-1} Q^T; with T = L L^T this is
+# C ~ (K W^T Q L^{-T}) (K W^T Q L^{-T})^T.  The cache is the one m x k factor
+# Rt = K W^T Q L^{-T}: the paper's R^T R' equals Rt Rt^T, and a (co)variance
+# is w_i^T K w_j - (Rt^T w_i) . (Rt^T w_j) (eq. pred_covar_ski_fast).
 # ---------------------------------------------------------------------------
 @dataclass
 class LoveCache:
     spec: Spec
-    R: np.ndarray           # k x m,  R  = Q_k^T W^T K   (Alg. 1)
-    Rp: np.ndarray          # k x m,  R' = T_k^{-1} R    (Alg. 1, Cholesky solve)
-    a: np.ndarray           # m,      mean cache (eq. pred_mean_ski)
-    lanczos: LanczosResult
+    Rt: np.ndarray          # m x k, C ~ Rt Rt^T
+    a: np.ndarray           # m, mean cache (eq. pred_mean_ski)
+    lanczos: LanczosResult  # Q of every block; alpha, beta of the first
+    L: np.ndarray           # k x k lower factor of the projected matrix H = Q^T Khat Q
     cg_iters: int
+    restarts: int = 0
+    residuals: np.ndarray = field(default_factory=lambda: np.zeros(0))  # check residuals per round
+
+    @property
+    def k(self) -> int:
+        return self.Rt.shape[1]
 
 
-def probe_vector(op: Operator) -> np.ndarray:
-    """b = (1/m) W K 1, the average column of W_X^T K_UU (Sec. 3.2 / Alg. 1 input)."""
+def probe_vector(op: KissOperator) -> np.ndarray:
+    """b = (1/m) W K 1, the average column of W K (Sec. 3.2)."""
     m = op.spec.mtot
     return op.W @ K_apply(op.spec, np.ones(m)) / m
 
 
+def check_groups(spec: Spec, groups: int) -> List[np.ndarray]:
+    """Grid nodes split into `groups` runs of consecutive (flattened) indices."""
+    bounds = np.linspace(0, spec.mtot, groups + 1).round().astype(np.int64)
+    return [np.arange(bounds[g], bounds[g + 1]) for g in range(groups) if bounds[g + 1] > bounds[g]]
+
+
+def solve_residuals(op: KissOperator, Q: np.ndarray, H: np.ndarray, groups: int):
+    """Accuracy of the Lanczos solve Khat^{-1} c ~ Q H^{-1} Q^T c (eq.
+    lanczos_solve) on the columns of W K the cache stands for: for each run g of
+    grid nodes, c_g = W K 1_g / |g| (the average column of W K over the run), its
+    relative residual ||c_g - Khat Q H^{-1} Q^T c_g|| / ||c_g||, and the
+    residual vector.  Returns (relative residuals, residual vectors n x G)."""
+    spec = op.spec
+    C = np.empty((op.n, 0))
+    cols = []
+    for idx in check_groups(spec, groups):
+        e = np.zeros(spec.mtot)
+        e[idx] = 1.0 / idx.size
+        cols.append(op.W @ K_apply(spec, e))
+    C = np.stack(cols, axis=1)
+    Xs = Q @ np.linalg.solve(H, Q.T @ C)
+    Rr = C - op.khat(Xs)
+    rel = np.linalg.norm(Rr, axis=0) / np.linalg.norm(C, axis=0)
+    return rel, Rr
+
+
 def love_build(X, y, spec: Spec, k: int, tol: float = 1e-12, cg_tol: float = 1e-12,
-               cg_maxit: int = 2000) -> LoveCache:
-    """Precomputation of Algorithm 1: Lanczos on Khat with probe b, Cholesky of T,
-    R = (mvm_K_UX(Q_k))^T, R' = cholesky_solve(R, L); plus the mean cache a."""
-    op = Operator(X, spec)
-    b = probe_vector(op)
-    lz = lanczos(op.mvm_K_XX, b, k, tol)
+               cg_maxit: int = 2000, restart_tol: float = 0.0, restart_k: int = 0,
+               max_restarts: int = 1, check_groups_n: int = 8) -> LoveCache:
+    """The LOVE pre-computation (Sec. 3.2): k Lanczos steps on Khat from the
+    probe b = (1/m) W K 1, the Cholesky factor of the projected matrix, the
+    factor Rt = K W^T Q L^{-T}, and the mean cache a.
+
+    Restart (Sec. 5, "Ensuring Lanczos solves are accurate"): with
+    restart_tol > 0 the solve is checked on the run-averaged columns of W K
+    (solve_residuals); while the worst relative residual exceeds restart_tol
+    (and at most max_restarts times) restart_k further Lanczos steps are taken
+    from a new probe, that run's residual vector, orthogonalised against all
+    earlier vectors.  Q then holds both blocks, H = Q^T Khat Q is no longer
+    tridiagonal (the blocks couple), and L is its dense Cholesky factor."""
+    op = KissOperator(X, spec)
+    lz = lanczos(op.khat, probe_vector(op), k, tol)
     ldiag, lsub = tridiag_cholesky(lz.alpha, lz.beta)
+    Q = lz.Q
     L = np.diag(ldiag) + np.diag(lsub, -1)
-    R = op.mvm_K_UX(lz.Q).T                           # k x m
-    Rp = sla.cho_solve((L, True), R)                  # T^{-1} R
+    restarts = 0
+    res_hist = []
+    if restart_tol > 0.0:
+        for _ in range(max_restarts + 1):
+            H = L @ L.T
+            rel, Rr = solve_residuals(op, Q, H, check_groups_n)
+            res_hist.append(float(np.max(rel)))
+            if np.max(rel) <= restart_tol or restarts == max_restarts or Q.shape[1] >= op.n:
+                break
+            worst = int(np.argmax(rel))
+            lz2 = lanczos(op.khat, Rr[:, worst], restart_k, tol, basis=Q)
+            Q = np.concatenate([Q, lz2.Q], axis=1)
+            H = Q.T @ op.khat(Q)
+            H = 0.5 * (H + H.T)
+            L = np.linalg.cholesky(H)
+            restarts += 1
+        lz = LanczosResult(Q, lz.alpha, lz.beta, lz.k_eff)
+    Rt = sla.solve_triangular(L, op.to_grid(Q).T, lower=True).T
     a, it = mean_cache(op, y, tol=cg_tol, maxit=cg_maxit)
-    return LoveCache(spec, R, Rp, a, lz, it)
+    return LoveCache(spec, Rt, a, lz, L, it, restarts, np.array(res_hist))
 
 
 def love_predict(cache: LoveCache, Xs):
-    """Constant-time mean w*^T a and variance p(x*) - (R w*)^T (R' w*) (Alg. 1, i = j)."""
+    """Constant-time mean w*^T a (eq. pred_mean_ski) and variance
+    p(x*) - ||Rt^T w*||^2 (eq. pred_covar_ski_fast with i = j)."""
     Ws = interp_matrix(Xs, cache.spec)
-    u = (Ws @ cache.R.T)                              # t x k : rows are (R w*)^T
-    v = (Ws @ cache.Rp.T)                             # t x k : rows are (R' w*)^T
-    var = prior_var(Xs, cache.spec) - np.sum(u * v, axis=1)
+    u = Ws @ cache.Rt                                 # t x k
+    var = prior_var(Xs, cache.spec) - np.sum(u * u, axis=1)
     mean = Ws @ cache.a
     return mean, var
 
 
 def love_covariance(cache: LoveCache, Xi, Xj):
-    """Cross-covariance k(x*_i, x*_j) = w_i^T K w_j - (R w_i)^T (R' w_j) for paired points."""
+    """Cross-covariance w_i^T K w_j - (Rt^T w_i) . (Rt^T w_j) for paired points."""
     Wi = interp_matrix(Xi, cache.spec)
     Wj = interp_matrix(Xj, cache.spec)
     kij = np.asarray((Wi.multiply(K_apply(cache.spec, Wj.T.toarray()).T)).sum(axis=1)).ravel()
-    u = Wi @ cache.R.T
-    v = Wj @ cache.Rp.T
-    return kij - np.sum(u * v, axis=1)
+    return kij - np.sum((Wi @ cache.Rt) * (Wj @ cache.Rt), axis=1)
 
 
 def love_predict_grad(cache: LoveCache, Xs, g_mean=None, g_var=None):
     """Gradient of sum(g_mean * mean + g_var * var) with respect to x* (t x d).
 
-    d mean/dx = (dw/dx)^T a;  d var/dx = dp/dx - (R dw)^T(R' w) - (R w)^T(R' dw)."""
+    d mean/dx = (dw/dx)^T a;  d var/dx = dp/dx - 2 (Rt^T w) . (Rt^T dw/dx)."""
     Xs = np.atleast_2d(np.asarray(Xs, dtype=np.float64)).reshape(-1, cache.spec.d)
     t, d = Xs.shape
     g_mean = np.zeros(t) if g_mean is None else np.asarray(g_mean, dtype=np.float64)
     g_var = np.zeros(t) if g_var is None else np.asarray(g_var, dtype=np.float64)
     Ws = interp_matrix(Xs, cache.spec)
     dWs = interp_grad_matrices(Xs, cache.spec)
-    u = Ws @ cache.R.T
-    v = Ws @ cache.Rp.T
+    u = Ws @ cache.Rt
     dp = prior_var_grad(Xs, cache.spec)
     out = np.empty((t, d))
     for dim in range(d):
-        du = dWs[dim] @ cache.R.T
-        dv = dWs[dim] @ cache.Rp.T
+        du = dWs[dim] @ cache.Rt
         dmean = dWs[dim] @ cache.a
-        dvar = dp[:, dim] - np.sum(du * v, axis=1) - np.sum(u * dv, axis=1)
+        dvar = dp[:, dim] - 2.0 * np.sum(u * du, axis=1)
         out[:, dim] = g_mean * dmean + g_var * dvar
     return out
+
+
+def love_grad_rt(cache: LoveCache, Xs, g_var) -> np.ndarray:
+    """d(sum_i g_i var(x*_i)) / d Rt (m x k): var_i depends on Rt only through
+    -||Rt^T w_i||^2, whose derivative is -2 w_i (Rt^T w_i)^T."""
+    Ws = interp_matrix(Xs, cache.spec)
+    u = Ws @ cache.Rt
+    g = np.asarray(g_var, dtype=np.float64)
+    return -2.0 * (Ws.T @ (g[:, None] * u))
+
+
+def love_var_hyper_grad(cache: LoveCache, X, Xs, g_var) -> np.ndarray:
+    """Gradient of sum_i g_i var(x*_i) with respect to the hyper-parameters
+    (hyper_names order) through the LOVE cache: the product rule of
+    exact_var_hyper_grad with every solve Khat^{-1} taken as the cached Lanczos
+    solve Q H^{-1} Q^T (eq. lanczos_solve, H = L L^T), so
+    z_i = Q L^{-T} L^{-1} Q^T W K w_i = Q L^{-T} u_i with u_i = Rt^T w_i.  Equal to
+    the exact gradient once the Krylov space holds every column of W K."""
+    spec = cache.spec
+    op = KissOperator(X, spec)
+    U = interp_matrix(Xs, spec) @ cache.Rt                                     # t x k
+    Z = cache.lanczos.Q @ sla.solve_triangular(cache.L.T, U.T, lower=False)   # n x t
+    return _var_hyper_grad(spec, op.W, Xs, Z, g_var)
 
 
 # ---------------------------------------------------------------------------
@@ -579,36 +806,52 @@ class SamplerCache:
     lanczos: LanczosResult
     k_chol: int            # columns of S
     used_cholesky: bool
+    probe: np.ndarray      # b', the second Lanczos probe
 
 
-def love_sampler(cache: LoveCache, k_sample: int, tol: float = 1e-12) -> SamplerCache:
-    """Lanczos on K - R^T R' (eq. lancapprox) with probe (1/m)(K - R^T R') 1,
-    then S = Q' L_{T'} (eq. pred_covar_ski_interp_form).  If T' is not
-    numerically positive definite, S = Q' V sqrt(max(lam, 0)) instead (columns
-    with lam <= 0 dropped), which has the same S S^T as the Cholesky route
-    whenever that exists."""
+def sampler_operator(cache: LoveCache):
+    """v -> (K - R^T R') v = (K - Rt Rt^T) v, the test-independent part of the
+    predictive covariance (eq. pred_covar_ski_interp_form12)."""
     spec = cache.spec
-    m = spec.mtot
+    return lambda v: K_apply(spec, v) - cache.Rt @ (cache.Rt.T @ v)
 
-    def mvm(v):
-        return K_apply(spec, v) - cache.R.T @ (cache.Rp @ v)
 
-    b = mvm(np.ones(m)) / m
+def sampler_probe(cache: LoveCache) -> np.ndarray:
+    """b' = (1/m) (K - R^T R') 1: the average column of the sampler's operator,
+    chosen as the first probe (1/m) W K 1 is for Khat (Sec. 3.3 names no probe)."""
+    m = cache.spec.mtot
+    return sampler_operator(cache)(np.ones(m)) / m
+
+
+def love_sampler(cache: LoveCache, k_sample: int, tol: float = 1e-12,
+                 factor: str = "auto") -> SamplerCache:
+    """Lanczos on K - R^T R' (eq. lancapprox) from sampler_probe, then
+    S = Q' L_{T'} (eq. pred_covar_ski_interp_form).  factor = "auto" takes the
+    Cholesky factor when T' is numerically positive definite, else
+    S = Q' V diag(max(lam, 0))^{1/2} from T' = V diag(lam) V^T (columns with
+    lam <= 0 dropped), which has the same S S^T whenever the Cholesky exists;
+    "cholesky" / "eigh" force one branch ("cholesky" raises LinAlgError when T'
+    is not positive definite)."""
+    mvm = sampler_operator(cache)
+    b = sampler_probe(cache)
     lz = lanczos(mvm, b, k_sample, tol)
     T = lz.T()
     amax = np.max(np.abs(lz.alpha))
-    try:
-        ldiag, lsub = tridiag_cholesky(lz.alpha, lz.beta)
-        if np.min(ldiag ** 2) <= tol * amax:
-            raise np.linalg.LinAlgError("numerically singular")
-        L = np.diag(ldiag) + np.diag(lsub, -1)
-        S = lz.Q @ L
-        return SamplerCache(S, lz, S.shape[1], True)
-    except np.linalg.LinAlgError:
-        lam, V = np.linalg.eigh(T)
-        keep = lam > 0
-        S = lz.Q @ (V[:, keep] * np.sqrt(lam[keep]))
-        return SamplerCache(S, lz, S.shape[1], False)
+    if factor in ("auto", "cholesky"):
+        try:
+            ldiag, lsub = tridiag_cholesky(lz.alpha, lz.beta)
+            if np.min(ldiag ** 2) <= tol * amax:
+                raise np.linalg.LinAlgError("numerically singular")
+            L = np.diag(ldiag) + np.diag(lsub, -1)
+            S = lz.Q @ L
+            return SamplerCache(S, lz, S.shape[1], True, b)
+        except np.linalg.LinAlgError:
+            if factor == "cholesky":
+                raise
+    lam, V = np.linalg.eigh(T)
+    keep = lam > 0
+    S = lz.Q @ (V[:, keep] * np.sqrt(lam[keep]))
+    return SamplerCache(S, lz, S.shape[1], False, b)
 
 
 def love_sample(cache: LoveCache, sampler: SamplerCache, Xs, Z):
@@ -632,3 +875,12 @@ def sample_covariance_implied(cache: LoveCache, sampler: SamplerCache, Xs) -> np
 def smae(pred, ref, y):
     """Scaled mean absolute error: mean |pred - ref| / Var(y) (Sec. 4 footnote)."""
     return float(np.mean(np.abs(np.asarray(pred) - np.asarray(ref))) / np.var(np.asarray(y, dtype=np.float64)))
+
+
+def sample_covariance_mae(samples, ref_cov) -> float:
+    """Element-wise mean absolute error between the sample covariance of the
+    columns of `samples` (t x s) and a reference t x t covariance (the
+    sample-accuracy metric of the sampling experiments, Sec. 4)."""
+    S = np.asarray(samples, dtype=np.float64)
+    emp = np.cov(S)
+    return float(np.mean(np.abs(emp - np.asarray(ref_cov, dtype=np.float64))))

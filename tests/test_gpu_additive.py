@@ -72,7 +72,7 @@ def test_additive_apply_khat_and_kuu_parity(f64):
     rng = np.random.default_rng(2)
     v = rng.standard_normal(P.n).astype(np.float64 if f64 else np.float32)
     out = host(cache.apply_khat(tdev(v, dt)))
-    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(v.astype(np.float64))
+    ref = O.KissOperator(P.x.astype(np.float64), spec).khat(v.astype(np.float64))
     rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     assert rel <= (1e-12 if f64 else 1e-5), rel
     g = rng.standard_normal(spec.mtot).astype(np.float64 if f64 else np.float32)
@@ -100,7 +100,7 @@ def test_additive_toeplitz_backends(toeplitz):
     assert np.max(np.abs(outk - refk)) / np.max(np.abs(refk)) <= 1e-5
     v = rng.standard_normal(P.n).astype(np.float32)
     out = host(cache.apply_khat(tdev(v, torch.float32)))
-    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(v.astype(np.float64))
+    ref = O.KissOperator(P.x.astype(np.float64), spec).khat(v.astype(np.float64))
     assert np.max(np.abs(out - ref)) / np.max(np.abs(ref)) <= 1e-5
     cache.free()
 
@@ -119,7 +119,7 @@ def test_additive_sampler_banded_axes():
     xs = P.xs_sample.astype(np.float64)
     spec = spec_of(P)
     Wd = O.interp_matrix(xs, spec).toarray()
-    target = Wd @ (O.K_dense(spec) - oc.R.T @ oc.Rp) @ Wd.T
+    target = Wd @ (O.K_dense(spec) - oc.Rt @ oc.Rt.T) @ Wd.T
     F = Wd @ S
     err_gpu = np.max(np.abs(F @ F.T - target))
     err_or = np.max(np.abs(O.sample_covariance_implied(oc, osm, xs) - target))

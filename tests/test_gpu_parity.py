@@ -66,7 +66,7 @@ def test_apply_khat_parity(cfgi, scale):
     dt = torch_dtype(P)
     vv = v.astype(np.float32 if dt == torch.float32 else np.float64)
     out = host(cache.apply_khat(tdev(vv, dt)))
-    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    ref = O.KissOperator(P.x.astype(np.float64), spec).khat(vv.astype(np.float64))
     rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     assert rel <= (1e-12 if dt == torch.float64 else 1e-5), rel
     cache.free()
@@ -94,7 +94,7 @@ def test_apply_khat_heavy_cells_parity(case):
     dt = torch_dtype(P)
     vv = v.astype(np.float32 if dt == torch.float32 else np.float64)
     out = host(cache.apply_khat(tdev(vv, dt)))
-    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    ref = O.KissOperator(P.x.astype(np.float64), spec).khat(vv.astype(np.float64))
     rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     assert rel <= (1e-12 if dt == torch.float64 else 1e-5), rel
     cache.free()
@@ -270,7 +270,7 @@ def test_sampler_truncated_vs_oracle():
     osm = O.love_sampler(oc, P.k_sample)
     sub = slice(0, 300)
     Wd = Ws[sub].toarray()
-    target = Wd @ (O.K_dense(spec) - oc.R.T @ oc.Rp) @ Wd.T
+    target = Wd @ (O.K_dense(spec) - oc.Rt @ oc.Rt.T) @ Wd.T
     F = Ws[sub] @ S
     err_gpu = np.max(np.abs(F @ F.T - target))
     err_or = np.max(np.abs(O.sample_covariance_implied(oc, osm, xs[sub].astype(np.float64)) - target))
@@ -501,7 +501,7 @@ def test_apply_khat_3d_parity(f64):
     dt = torch_dtype(P)
     vv = v.astype(np.float64 if f64 else np.float32)
     out = host(cache.apply_khat(tdev(vv, dt)))
-    ref = O.Operator(P.x.astype(np.float64), spec).mvm_K_XX(vv.astype(np.float64))
+    ref = O.KissOperator(P.x.astype(np.float64), spec).khat(vv.astype(np.float64))
     rel = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
     assert rel <= (1e-12 if f64 else 1e-5), rel
     cache.free()

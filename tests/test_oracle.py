@@ -209,9 +209,9 @@ def test_exact_covariance_grid_psd_and_consistent():
 # ---------------------------------------------------------------------------
 def test_cg_matches_direct_solve():
     spec, x, y, xs = small_problem(d=1, n=300, m=30)
-    op = O.Operator(x, spec)
+    op = O.KissOperator(x, spec)
     A = op.dense()
-    sol, it = O.cg(op.mvm_K_XX, y, tol=1e-13, maxit=5000)
+    sol, it = O.cg(op.khat, y, tol=1e-13, maxit=5000)
     assert np.max(np.abs(sol - np.linalg.solve(A, y))) < 1e-8
     a, _ = O.mean_cache(op, y)
     Ws = O.interp_matrix(xs, spec)
@@ -225,13 +225,13 @@ def test_cg_matches_direct_solve():
 def test_lanczos_invariants_config1():
     P = WL.config(1)
     spec = spec_of(P)
-    op = O.Operator(P.x, spec)
+    op = O.KissOperator(P.x, spec)
     b = O.probe_vector(op)
-    lz = O.lanczos(op.mvm_K_XX, b, 25)
+    lz = O.lanczos(op.khat, b, 25)
     Q, T = lz.Q, lz.T()
     k = lz.k_eff
     assert np.max(np.abs(Q.T @ Q - np.eye(k))) < 1e-13
-    AQ = op.mvm_K_XX(Q)
+    AQ = op.khat(Q)
     assert np.max(np.abs(Q.T @ AQ - T)) < 1e-9 * np.max(np.abs(T))
     # q_1 parallel to b
     assert abs(abs(Q[:, 0] @ b) / np.linalg.norm(b) - 1) < 1e-14
@@ -285,14 +285,27 @@ def test_love_sandwich_monotone_in_k():
         prev = v
 
 
-def test_love_R_Rprime_shapes_and_symmetry():
+def test_love_factor_equals_R_Rprime_of_the_paper():
+    """The cache's one factor Rt must reproduce the paper's two factors
+    (Sec. 3.2): R = Q^T W^T K (k x m) and R' = T^{-1} R, computed here with a
+    dense solve of T, satisfy R^T R' = Rt Rt^T; the product is symmetric PSD and
+    never exceeds the exact C = K W^T Khat^{-1} W K (Rayleigh-Ritz on span(Q))."""
     spec, x, y, xs = small_problem(d=2, n=300, m=8)
     cache = O.love_build(x, y, spec, k=12)
-    k = cache.lanczos.k_eff
-    assert cache.R.shape == (k, spec.mtot) and cache.Rp.shape == (k, spec.mtot)
-    C = cache.R.T @ cache.Rp          # approximates K W^T Khat^{-1} W K, must be symmetric PSD
+    lz = cache.lanczos
+    k = lz.k_eff
+    assert cache.Rt.shape == (spec.mtot, k)
+    Wd = O.interp_matrix(x, spec).toarray()
+    K = dense_kernel_from_coords(spec)
+    R = lz.Q.T @ Wd @ K                                  # k x m
+    Rp = np.linalg.solve(lz.T(), R)                      # T^{-1} R
+    C = R.T @ Rp
+    assert np.max(np.abs(C - cache.Rt @ cache.Rt.T)) < 1e-11 * np.max(np.abs(C))
     assert np.max(np.abs(C - C.T)) < 1e-10 * np.max(np.abs(C))
-    assert np.linalg.eigvalsh(0.5 * (C + C.T)).min() > -1e-10
+    A = Wd @ K @ Wd.T + spec.noise * np.eye(x.shape[0])
+    C_exact = K @ Wd.T @ np.linalg.solve(A, Wd @ K)
+    lam = np.linalg.eigvalsh(C_exact - cache.Rt @ cache.Rt.T)
+    assert lam.min() > -1e-10 * np.max(np.abs(C_exact))
 
 
 def test_love_covariance_pairs_vs_exact():
@@ -389,11 +402,11 @@ def test_additive_is_sum_of_1d_components(kernel):
     Wd = W.toarray()
     for e, (a, b) in enumerate([(0, 14), (14, 37), (37, 46)]):
         assert np.allclose(Wd[:, a:b].sum(1), 1.0, atol=1e-14)
-    A = O.Operator(x, spec).dense()
+    A = O.KissOperator(x, spec).dense()
     ref = spec.noise * np.eye(90)
     for e in range(3):
         c = component(spec, e)
-        ref += O.Operator(x[:, e:e + 1], c).dense() - spec.noise * np.eye(90)
+        ref += O.KissOperator(x[:, e:e + 1], c).dense() - spec.noise * np.eye(90)
     assert np.max(np.abs(A - ref)) < 1e-12
     p = O.prior_var(xs, spec)
     pe = sum(O.prior_var(xs[:, e:e + 1], component(spec, e)) for e in range(3))
@@ -464,13 +477,314 @@ def test_additive_predict_grad_fd():
 
 
 # ---------------------------------------------------------------------------
+# Probe vectors (Sec. 3.2 first probe; Sec. 3.3 second probe) and the sampler
+# ---------------------------------------------------------------------------
+def bruteforce_W(X, spec):
+    """Dense interpolation matrix straight from the Keys kernel of the
+    node distances: product over axes (tensor grid) or the stacked per-axis
+    blocks (additive form, Sec. 3.4)."""
+    X = np.atleast_2d(X)
+    grids = [O.grid_nodes(spec, e) for e in range(spec.d)]
+    if spec.additive:
+        return np.concatenate([O.keys_psi(np.abs(X[:, e][:, None] - grids[e][None, :]) / spec.h(e))
+                               for e in range(spec.d)], axis=1)
+    mesh = np.stack(np.meshgrid(*grids, indexing="ij"), -1).reshape(-1, spec.d)
+    Wb = np.ones((X.shape[0], mesh.shape[0]))
+    for e in range(spec.d):
+        Wb *= O.keys_psi(np.abs(X[:, e][:, None] - mesh[:, e][None, :]) / spec.h(e))
+    return Wb
+
+
+def bruteforce_K(spec):
+    if not spec.additive:
+        return dense_kernel_from_coords(spec)
+    return sla.block_diag(*[dense_kernel_from_coords(component_of(spec, e)) for e in range(spec.d)])
+
+
+def component_of(spec, e):
+    return O.Spec((spec.m[e],), (spec.lo[e],), (spec.hi[e],), spec.kernel, (spec.lengthscale[e],),
+                  spec.outputscale, spec.noise)
+
+
+@pytest.mark.parametrize("form", ["1d", "2d", "2d_matern", "additive"])
+def test_probe_vector_vs_bruteforce(form):
+    """b = (1/m) W K 1 (Sec. 3.2): the average column of W K, from the Keys
+    weights of the node distances and the kernel on grid coordinates.  The first
+    Lanczos vector must be b / ||b||."""
+    if form == "additive":
+        spec, x, y, xs = additive_problem(n=120, m=(11, 14))
+    else:
+        d = 1 if form == "1d" else 2
+        spec, x, y, xs = small_problem(d=d, n=150, m=13 if d == 1 else 7,
+                                       kernel="matern52" if "matern" in form else "rbf")
+    Wb = bruteforce_W(x, spec)
+    Kb = bruteforce_K(spec)
+    b_ref = Wb @ Kb @ np.ones(spec.mtot) / spec.mtot
+    b = O.probe_vector(O.KissOperator(x, spec))
+    assert np.max(np.abs(b - b_ref)) < 1e-13 * np.max(np.abs(b_ref))
+    cache = O.love_build(x, y, spec, k=5)
+    q1 = cache.lanczos.Q[:, 0]
+    assert np.max(np.abs(q1 - b_ref / np.linalg.norm(b_ref))) < 1e-13
+
+
+def literal_R_Rprime(cache, x):
+    """The paper's two factors R = Q^T W^T K and R' = T^{-1} R (Sec. 3.2), from
+    brute-force W and K and a dense solve of T."""
+    lz = cache.lanczos
+    R = lz.Q.T @ bruteforce_W(x, cache.spec) @ bruteforce_K(cache.spec)
+    return R, np.linalg.solve(lz.T(), R)
+
+
+def test_sampler_probe_vs_dense():
+    """b' = (1/m) (K - R^T R') 1 (Sec. 3.3, mirroring the first probe), with
+    R, R' formed literally; the sampler's first Lanczos vector is b'/||b'||."""
+    spec, x, y, xs = small_problem(d=1, n=150, m=25, noise=0.05)
+    cache = O.love_build(x, y, spec, k=10)
+    R, Rp = literal_R_Rprime(cache, x)
+    B = bruteforce_K(spec) - R.T @ Rp
+    b_ref = B @ np.ones(spec.mtot) / spec.mtot
+    assert np.max(np.abs(O.sampler_probe(cache) - b_ref)) < 1e-12 * np.max(np.abs(b_ref))
+    sm = O.love_sampler(cache, k_sample=8)
+    assert np.max(np.abs(sm.lanczos.Q[:, 0] - b_ref / np.linalg.norm(b_ref))) < 1e-12
+
+
+def test_sampler_cholesky_branch_truncated():
+    """Truncated second Lanczos (k' below the rank): T' is positive definite,
+    "auto" takes the Cholesky branch, and S S^T = Q' (Q'^T B Q') Q'^T with B the
+    dense K - R^T R' (eqs. lancapprox, pred_covar_ski_interp_form).  The
+    eigendecomposition branch gives the same S S^T."""
+    spec, x, y, xs = small_problem(d=1, n=150, m=25, noise=0.05)
+    cache = O.love_build(x, y, spec, k=10)
+    R, Rp = literal_R_Rprime(cache, x)
+    B = bruteforce_K(spec) - R.T @ Rp
+    sm = O.love_sampler(cache, k_sample=6)
+    assert sm.used_cholesky and sm.k_chol == 6
+    Qp = sm.lanczos.Q
+    ref = Qp @ (Qp.T @ B @ Qp) @ Qp.T
+    SS = sm.S @ sm.S.T
+    assert np.max(np.abs(SS - ref)) < 1e-11 * np.max(np.abs(B))
+    se = O.love_sampler(cache, k_sample=6, factor="eigh")
+    assert not se.used_cholesky
+    assert np.max(np.abs(se.S @ se.S.T - SS)) < 1e-11 * np.max(np.abs(B))
+
+
+def test_sampler_eigh_branch_singular():
+    """A smooth kernel on a fine grid makes K - R^T R' numerically singular, so
+    T' is not positive definite: "auto" takes the clipped eigendecomposition
+    (reading of Sec. 3.3's Cholesky), "cholesky" refuses, and the implied grid
+    covariance S S^T still equals the dense K - R^T R' (its numerical range is
+    spanned by k' Lanczos vectors)."""
+    spec, x, y, xs = small_problem(d=1, n=60, m=40, ell=0.4, noise=0.05)
+    cache = O.love_build(x, y, spec, k=60)
+    R, Rp = literal_R_Rprime(cache, x)
+    B = bruteforce_K(spec) - R.T @ Rp
+    sm = O.love_sampler(cache, k_sample=40)
+    assert not sm.used_cholesky
+    with pytest.raises(np.linalg.LinAlgError):
+        O.love_sampler(cache, k_sample=40, factor="cholesky")
+    assert np.max(np.abs(sm.S @ sm.S.T - B)) < 1e-9 * np.max(np.abs(B))
+
+
+def test_smae_hand_computed():
+    """SMAE = mean absolute error / Var(y) (Sec. 4 footnote): |d| = 0, 1, 3 has
+    mean 4/3, and y = (0, 4) has variance 4 (standard deviation 2), so 1/3."""
+    assert O.smae([1.0, 2.0, 4.0], [1.0, 1.0, 1.0], [0.0, 4.0]) == pytest.approx(1.0 / 3.0, rel=1e-15)
+    # sample-covariance MAE: two samples (1, -1) and (-1, 1) of two points have
+    # covariance [[2, -2], [-2, 2]]; against the identity the errors are 1, 2, 2, 1
+    s = np.array([[1.0, -1.0], [-1.0, 1.0]])
+    assert O.sample_covariance_mae(s, np.eye(2)) == pytest.approx(1.5, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Gradient with respect to the cache, and with respect to hyper-parameters
+# ---------------------------------------------------------------------------
+def test_grad_rt_fd():
+    spec, x, y, xs = small_problem(d=2, n=200, m=8)
+    cache = O.love_build(x, y, spec, k=10)
+    g = np.random.default_rng(4).standard_normal(xs.shape[0])
+    G = O.love_grad_rt(cache, xs, g)
+    assert G.shape == cache.Rt.shape
+    rng = np.random.default_rng(5)
+    base = cache.Rt.copy()
+    touched = np.unique(O.interp_matrix(xs, spec).indices)
+    for _ in range(12):
+        a = int(rng.choice(touched))
+        c = int(rng.integers(cache.k))
+        h = 1e-6
+        cache.Rt = base.copy(); cache.Rt[a, c] += h
+        vp = O.love_predict(cache, xs)[1]
+        cache.Rt = base.copy(); cache.Rt[a, c] -= h
+        vm = O.love_predict(cache, xs)[1]
+        fd = np.sum(g * (vp - vm)) / (2 * h)
+        assert abs(fd - G[a, c]) < 1e-6 * (1 + abs(G[a, c]))
+    cache.Rt = base
+    untouched = np.setdiff1d(np.arange(spec.mtot), touched)
+    assert np.all(G[untouched] == 0)
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern52"])
+def test_kernel_dell_fd(kind):
+    r = np.linspace(0, 2.5, 40)
+    ell, h = 0.37, 1e-6
+    fd = (O.kernel_1d(r, kind, ell + h) - O.kernel_1d(r, kind, ell - h)) / (2 * h)
+    assert np.max(np.abs(O.kernel_1d_dell(r, kind, ell) - fd)) < 1e-8
+
+
+@pytest.mark.parametrize("form", ["2d", "3d_matern", "additive"])
+def test_K_apply_dtheta_fd(form):
+    """d K / d theta applied to vectors against central differences of the
+    kernel on grid coordinates in each hyper-parameter."""
+    if form == "additive":
+        spec, x, y, xs = additive_problem(n=50, m=(9, 12))
+    elif form == "2d":
+        spec, x, y, xs = small_problem(d=2, m=7)
+    else:
+        spec, x, y, xs = small_problem(d=3, m=5, kernel="matern52")
+    G = np.random.default_rng(0).standard_normal((spec.mtot, 2))
+    h = 1e-6
+    for th in range(spec.d + 2):
+        def K_at(delta):
+            ls = list(spec.lengthscale) * (spec.d if len(spec.lengthscale) == 1 else 1)
+            os_, nz = spec.outputscale, spec.noise
+            if th < spec.d:
+                ls[th] += delta
+            elif th == spec.d:
+                os_ += delta
+            else:
+                nz += delta
+            return bruteforce_K(O.Spec(spec.m, spec.lo, spec.hi, spec.kernel, tuple(ls), os_, nz,
+                                       spec.additive))
+        fd = (K_at(h) - K_at(-h)) @ G / (2 * h)
+        assert np.max(np.abs(O.K_apply_dtheta(spec, th, G) - fd)) < 1e-7 * (1 + np.max(np.abs(fd)))
+
+
+def _spec_shift(spec, th, delta):
+    ls = list(spec.lengthscale)
+    os_, nz = spec.outputscale, spec.noise
+    if th < spec.d:
+        ls[th] += delta
+    elif th == spec.d:
+        os_ += delta
+    else:
+        nz += delta
+    return O.Spec(spec.m, spec.lo, spec.hi, spec.kernel, tuple(ls), os_, nz, spec.additive)
+
+
+def test_prior_var_dtheta_fd():
+    for spec, x, y, xs in (small_problem(d=2, m=9), additive_problem(n=40, m=(9, 12))):
+        D = O.prior_var_dtheta(xs, spec)
+        h = 1e-6
+        for th in range(spec.d + 2):
+            fd = (O.prior_var(xs, _spec_shift(spec, th, h)) - O.prior_var(xs, _spec_shift(spec, th, -h))) / (2 * h)
+            assert np.max(np.abs(D[:, th] - fd)) < 1e-7
+
+
+@pytest.mark.parametrize("form", ["1d", "2d_matern", "additive"])
+def test_exact_var_hyper_grad_fd(form):
+    """The product-rule gradient of the exact KISS-GP variance against central
+    differences of route A (dense Cholesky) in every hyper-parameter."""
+    if form == "additive":
+        spec, x, y, xs = additive_problem(n=80, m=(9, 12), t=15)
+    elif form == "1d":
+        spec, x, y, xs = small_problem(d=1, n=80, m=20, t=15)
+    else:
+        spec, x, y, xs = small_problem(d=2, n=80, m=7, kernel="matern52", t=15)
+    g = np.random.default_rng(1).standard_normal(xs.shape[0])
+    G = O.exact_var_hyper_grad(x, xs, spec, g)
+    h = 1e-5
+    for th in range(spec.d + 2):
+        vp = O.exact_route_A(x, y, xs, _spec_shift(spec, th, h))[1]
+        vm = O.exact_route_A(x, y, xs, _spec_shift(spec, th, -h))[1]
+        fd = np.sum(g * (vp - vm)) / (2 * h)
+        assert abs(G[th] - fd) < 1e-6 * (1 + abs(fd)), (th, G[th], fd)
+
+
+def test_love_var_hyper_grad_converges_to_exact():
+    """Through the cache the gradient equals the exact one once the Krylov
+    space is invariant (k = n), and approaches it as k grows."""
+    spec, x, y, xs = small_problem(d=1, n=60, m=30, noise=0.05, t=20)
+    g = np.random.default_rng(2).standard_normal(xs.shape[0])
+    G_ex = O.exact_var_hyper_grad(x, xs, spec, g)
+    full = O.love_var_hyper_grad(O.love_build(x, y, spec, k=60), x, xs, g)
+    assert np.max(np.abs(full - G_ex)) < 1e-8 * (1 + np.max(np.abs(G_ex)))
+    errs = [np.max(np.abs(O.love_var_hyper_grad(O.love_build(x, y, spec, k=k), x, xs, g) - G_ex))
+            for k in (4, 8, 16)]
+    assert errs[2] < errs[0]
+
+
+# ---------------------------------------------------------------------------
+# Restart with a new probe (Sec. 5, "Ensuring Lanczos solves are accurate")
+# ---------------------------------------------------------------------------
+def clustered_problem(n1=600, n2=15, m=80, ell=0.04, seed=0):
+    """Most training points on the left, a few far to the right: the first
+    probe's Krylov space resolves the right cluster late."""
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([rng.uniform(0, 0.45, n1), rng.uniform(0.8, 1.0, n2)])[:, None]
+    y = np.sin(8 * x[:, 0]) + 0.1 * rng.standard_normal(x.shape[0])
+    xs = np.linspace(0, 1, 120)[:, None]
+    spec = O.Spec((m,), (0.0,), (1.0,), "rbf", (ell,), 1.0, 0.01)
+    return spec, x, y, xs
+
+
+def test_restart_projection_and_factor():
+    """After a restart Q holds both blocks, orthonormal; L L^T is the projected
+    matrix Q^T Khat Q of the dense Khat (no longer tridiagonal: the blocks
+    couple); Rt Rt^T = K W^T Q H^{-1} Q^T W K."""
+    spec, x, y, xs = clustered_problem()
+    c = O.love_build(x, y, spec, 20, restart_tol=1e-6, restart_k=20)
+    assert c.restarts == 1 and c.k == 40
+    Q = c.lanczos.Q
+    assert np.max(np.abs(Q.T @ Q - np.eye(40))) < 1e-13
+    Wb, Kb = bruteforce_W(x, spec), bruteforce_K(spec)
+    A = Wb @ Kb @ Wb.T + spec.noise * np.eye(x.shape[0])
+    H = Q.T @ A @ Q
+    assert np.max(np.abs(c.L @ c.L.T - H)) < 1e-10 * np.max(np.abs(H))
+    assert np.max(np.abs(np.triu(H[20:, :20], 1))) > 1e-6 * np.max(np.abs(H))   # coupled blocks
+    F = Kb @ Wb.T @ Q
+    ref = F @ np.linalg.solve(H, F.T)
+    assert np.max(np.abs(c.Rt @ c.Rt.T - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_restart_sandwich_and_accuracy():
+    """The restarted Krylov space contains the first one, so (Rayleigh-Ritz)
+    exact <= var(restart) <= var(first block) <= prior; the restart reduces the
+    checked residual, and beats a single run with as many steps here."""
+    spec, x, y, xs = clustered_problem()
+    c0 = O.love_build(x, y, spec, 20)
+    c1 = O.love_build(x, y, spec, 20, restart_tol=1e-6, restart_k=20)
+    c2 = O.love_build(x, y, spec, 40)
+    _, v0 = O.love_predict(c0, xs)
+    _, v1 = O.love_predict(c1, xs)
+    _, v2 = O.love_predict(c2, xs)
+    _, vA = O.exact_route_A(x, y, xs, spec)
+    p = O.prior_var(xs, spec)
+    assert (v1 >= vA - 1e-13).all() and (v1 <= v0 + 1e-13).all() and (v0 <= p + 1e-13).all()
+    assert c1.residuals[1] < 1e-3 * c1.residuals[0]
+    assert np.max(np.abs(v1 - vA) / p) < 0.1 * np.max(np.abs(v2 - vA) / p)
+
+
+def test_restart_not_taken_when_accurate_and_exact_when_full():
+    spec, x, y, xs = clustered_problem(n1=40, n2=5)
+    c = O.love_build(x, y, spec, 45, restart_tol=1e-6, restart_k=10)
+    assert c.restarts == 0 and c.residuals[0] < 1e-6
+    c = O.love_build(x, y, spec, 25, restart_tol=1e-12, restart_k=20)
+    _, v = O.love_predict(c, xs)
+    _, vA = O.exact_route_A(x, y, xs, spec)
+    # the second block stops early once its Krylov space is invariant; the
+    # answer is then exact
+    assert c.restarts == 1 and np.max(np.abs(v - vA) / O.prior_var(xs, spec)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: each plausible slip in the oracle must break a pin above.
 # ---------------------------------------------------------------------------
 def _ok(fn):
+    # a slip is caught when a pin fails, or when the pinned computation breaks
+    # down (a factorisation that no longer exists)
     try:
         fn()
         return True
-    except AssertionError:
+    except (AssertionError, np.linalg.LinAlgError):
         return False
 
 
@@ -489,7 +803,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
         assert not _ok(test_keys_polynomial_reproduction)
     # (2) noise term dropped from the operator
     with monkeypatch.context() as mp:
-        mp.setattr(O.Operator, "mvm_K_XX", lambda self, V: self.W @ self.mvm_K_UX(V))
+        mp.setattr(O.KissOperator, "khat", lambda self, V: self.W @ self.to_grid(V))
         assert not _ok(test_lanczos_exact_at_k_equals_n)
     # (3) transposed stencil (weights reversed)
     orig = O.stencil_axis
@@ -526,8 +840,46 @@ def test_planted_mistakes_are_caught(monkeypatch):
     with monkeypatch.context() as mp:
         mp.setattr(O, "prior_var", pv_prod)
         assert not _ok(test_additive_love_saturates_to_exact)
+    # (8) probe without K: b = (1/m) W 1
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "probe_vector", lambda op: op.W @ np.ones(op.spec.mtot) / op.spec.mtot)
+        assert not _ok(lambda: test_probe_vector_vs_bruteforce("2d"))
+    # (9) probe as the average column of Khat instead of W K
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "probe_vector", lambda op: op.khat(np.ones(op.n)) / op.n)
+        assert not _ok(lambda: test_probe_vector_vs_bruteforce("1d"))
+    # (10) SMAE scaled by the standard deviation of y instead of its variance
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "smae", lambda pred, ref, y: float(np.mean(np.abs(np.asarray(pred) - np.asarray(ref)))
+                                                         / np.std(np.asarray(y, dtype=np.float64))))
+        assert not _ok(test_smae_hand_computed)
+    # (11) sampler probe without the R^T R' term: (1/m) K 1
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "sampler_probe", lambda cache: O.K_apply(cache.spec, np.ones(cache.spec.mtot))
+                   / cache.spec.mtot)
+        assert not _ok(test_sampler_probe_vs_dense)
+    # (12) d var / d Rt with the wrong sign
+    orig_grt = O.love_grad_rt
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "love_grad_rt", lambda cache, Xs, g: -orig_grt(cache, Xs, g))
+        assert not _ok(test_grad_rt_fd)
+    # (13) hyper-parameter gradient without the prior term w^T dK w
+    orig_pd = O.prior_var_dtheta
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "prior_var_dtheta", lambda Xs, spec: 0.0 * orig_pd(Xs, spec))
+        assert not _ok(lambda: test_exact_var_hyper_grad_fd("1d"))
+    # (14) RBF lengthscale derivative missing a factor 1/ell
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "kernel_1d_dell", lambda r, kind, ell: np.exp(-0.5 * (np.abs(r) / ell) ** 2)
+                   * r * r / ell ** 2)
+        assert not _ok(lambda: test_kernel_dell_fd("rbf"))
+    # (15) restart block not orthogonalised against the first block
+    orig_lz = O.lanczos
+    with monkeypatch.context() as mp:
+        mp.setattr(O, "lanczos", lambda matvec, b, k, tol=1e-12, basis=None: orig_lz(matvec, b, k, tol))
+        assert not _ok(test_restart_projection_and_factor)
     # (5) mean cache missing the K factor
     with monkeypatch.context() as mp:
         mp.setattr(O, "mean_cache", lambda op, y, tol=1e-12, maxit=2000:
-                   (op.WT @ O.cg(op.mvm_K_XX, y, tol=tol, maxit=maxit)[0], 0))
+                   (op.WT @ O.cg(op.khat, y, tol=tol, maxit=maxit)[0], 0))
         assert not _ok(test_cg_matches_direct_solve)
