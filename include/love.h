@@ -42,6 +42,26 @@
  *   - A built cache is immutable; concurrent queries on different streams are
  *     safe.  Calls that allocate (build, free) are not thread-safe with respect
  *     to the same cache.
+ *   - Device memory.  The build, batched build, import and covariance-block
+ *     entry points take a `const love_allocator*`.  NULL selects the device's
+ *     stream-ordered pool (hipMallocAsync / hipFreeAsync).  Otherwise every
+ *     device buffer of the call, the cache and its transient workspace alike,
+ *     comes from alloc() and goes back through free(); a cache keeps its
+ *     allocator (the struct is copied; ctx must stay valid until
+ *     love_cache_free) and the calls on it that need scratch (sampling, the
+ *     backward, paired covariances, the operator products) use it as well.
+ *     The library allocates each block on a stream and releases it on that same
+ *     stream once every other stream that used it has been joined into it, so
+ *     a stream-ordered allocator (torch's caching allocator, a hipMallocAsync
+ *     pool) may reuse a freed block for later work on that stream at once.
+ *     Streams passed to the callbacks may be library-internal (the sampler and
+ *     the grid-space mean solve run on side streams).
+ *   - Environment.  LOVE_AUTOTUNE=0 replaces the autotuner's timing runs by a
+ *     size rule (LOVE_TOEPLITZ_AUTO only).  LOVE_PSUM_MAX_NB=<blocks> sets the
+ *     row-block count up to which a Lanczos run adds its partial dot-product
+ *     rows inside the consuming kernels instead of separate column-sum launches
+ *     (default 160).  Both change only the order of floating-point sums, so
+ *     results move at rounding level.
  */
 #ifndef LOVE_H_
 #define LOVE_H_
@@ -53,7 +73,7 @@
 extern "C" {
 #endif
 
-#define LOVE_ABI_VERSION 1
+#define LOVE_ABI_VERSION 2
 #define LOVE_MAX_DIM 4
 #define LOVE_MAX_K 128
 
@@ -81,7 +101,10 @@ typedef enum {
 typedef enum {
   LOVE_TOEPLITZ_AUTO = 0,   /* per-axis choice by the built-in autotuner                       */
   LOVE_TOEPLITZ_DIRECT = 1, /* O(m_i^2) per line, register-blocked, all CUs                    */
-  LOVE_TOEPLITZ_FFT = 2     /* circulant embedding, LDS-resident radix-2 FFT, O(m_i log m_i)  */
+  LOVE_TOEPLITZ_FFT = 2     /* circulant embedding, LDS-resident radix-2 FFT, O(m_i log m_i).
+                               Available while the circulant length (the power of two
+                               >= 2 m_i - 1) is at most 8192; an explicit request beyond
+                               that makes the build return LOVE_EUNSUPPORTED            */
 } love_toeplitz_mode;
 
 /* Flags (love_config.flags) */
@@ -126,6 +149,21 @@ typedef struct {
 } love_config;
 
 typedef struct love_cache love_cache;   /* opaque */
+
+/* Caller-supplied device memory (see "Device memory" above).
+ *   alloc(bytes, stream, ctx): a device block of at least `bytes` bytes, aligned
+ *     to 256 bytes, usable by work enqueued on `stream` (a hipStream_t) after
+ *     the call; NULL on failure (the entry point then returns LOVE_ENOMEM).
+ *   free(ptr, stream, ctx): release a block from alloc(); work already
+ *     enqueued on `stream` may still use it, and the block may be reused by
+ *     work enqueued on `stream` afterwards.
+ * Both must be non-NULL (LOVE_EINVAL otherwise); they are called from the
+ * thread of the entry point, never from a stream callback. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} love_allocator;
 
 /* Status bits (love_cache_info_t.status_flags) */
 #define LOVE_SF_DOMAIN 1u           /* a point outside [lo, hi] was seen                          */
@@ -183,12 +221,13 @@ const char* love_status_string(love_status s);
 /* Build the LOVE cache (Alg. 1 precomputation, Sec. 3.2) and, if
  * cfg->k_sample > 0, the sampling matrix S (Sec. 3.3).
  *   x : n x d training inputs, y : n targets (device, precision's type).
+ *   alloc : device memory source (NULL: the device's stream-ordered pool).
  *   out : receives the new cache; untouched on error.
  * Errors: EINVAL (arguments), EDOMAIN (x outside [lo, hi]), ENONFINITE (non-finite
  * x, y, or Lanczos breakdown into NaN), ENOMEM, EHIP.  A T that is not positive
  * definite truncates k_eff and sets LOVE_SF_NOTPD (not an error). */
 love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
-                             void* stream, love_cache** out);
+                             const love_allocator* alloc, void* stream, love_cache** out);
 
 /* Build G independent caches (a1-a11 of the build for every GP) with every
  * phase launched once for all GPs, in lock step over the Lanczos and CG
@@ -202,7 +241,8 @@ love_status love_build_cache(const love_config* cfg, const void* x, const void* 
  * single-GP build on the same inputs bit for bit (love_build_cache is the
  * batch of one). */
 love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
-                                     const void* const* ys, const int64_t* ns, void* stream,
+                                     const void* const* ys, const int64_t* ns,
+                                     const love_allocator* alloc, void* stream,
                                      love_cache** out);
 
 /* Constant-time predictive mean and variance (eq. pred_mean_ski; eq.
@@ -227,10 +267,12 @@ love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const 
  * double.  xa : ta x d, xb : tb x d (cache precision, device); cov : ta x tb
  * row-major, caller-owned.  ta <= 65535 * 32.  A point outside [lo, hi]
  * gives NaN in its row / column and sets LOVE_SF_DOMAIN.  The call allocates
- * (ta + tb) (kpad + 5 d + 1) doubles of stream-ordered scratch and frees it
- * on the stream.  Errors: EINVAL for bad sizes or NULL buffers. */
+ * (ta + tb) (kpad + 5 d + 1) doubles of scratch on `stream` from `alloc`
+ * (NULL: the cache's own memory source) and frees it on the stream.
+ * Errors: EINVAL for bad sizes or NULL buffers, ENOMEM. */
 love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
-                                     const void* xb, int64_t tb, void* cov, void* stream);
+                                     const void* xb, int64_t tb, void* cov,
+                                     const love_allocator* alloc, void* stream);
 
 /* Posterior samples (eq. sample with S of eq. pred_covar_ski_interp_form):
  * out[i, j] = mu(xs_i) + sum_a w_a(xs_i) (S z_j)[a].
@@ -276,17 +318,19 @@ love_status love_cache_export(const love_cache* c, const love_export* e, void* s
  * work as on the cache that was exported; love_apply_khat needs the training
  * rows and returns LOVE_EUNSUPPORTED.  cfg gives the grid, kernel and
  * precision (cfg->k and cfg->k_sample are replaced by the imported column
- * counts).  For the BF16 split the float Rt is split again into hi + lo,
+ * counts); alloc as for love_build_cache.  For the BF16 split the float Rt is split again into hi + lo,
  * whose sum reproduces it.  Enqueued on `stream`; the imported buffers may be
  * released once the stream has passed this call.
  * Errors: EINVAL (bad config, counts or NULL buffers), ENOMEM, EHIP. */
-love_status love_cache_import(const love_config* cfg, const love_import* im, void* stream,
-                              love_cache** out);
+love_status love_cache_import(const love_config* cfg, const love_import* im,
+                              const love_allocator* alloc, void* stream, love_cache** out);
 
 /* Release a cache, stream-ordered on its build stream: work queued on that
  * stream before the call finishes first, and the host does not wait.  Work on
  * other streams that reads the cache must be complete (or ordered before the
- * build stream's current point) when this is called.  NULL is a no-op. */
+ * build stream's current point) when this is called.  The memory goes back
+ * through the allocator the cache was built (or imported) with.  NULL is a
+ * no-op. */
 void love_cache_free(love_cache* c);
 
 /* Per-kernel timing with HIP events recorded around each launch on the

@@ -60,6 +60,72 @@ class love_import(C.Structure):
                 ("a", C.c_void_p), ("s", C.c_void_p)]
 
 
+# love_allocator: device memory callbacks (alloc(bytes, stream, ctx), free(ptr, stream, ctx), ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class love_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class TorchAllocator:
+    """A love_allocator over torch's caching allocator: blocks come from
+    torch.cuda.caching_allocator_alloc on the stream the library names and go
+    back through caching_allocator_delete (stream-ordered reuse on that stream,
+    which is what the library's release order assumes).  Counts the calls."""
+
+    def __init__(self):
+        self.allocs = 0
+        self.frees = 0
+        self.live = 0
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            except Exception:
+                return None
+            self.allocs += 1
+            self.live += 1
+            return p
+
+        def _free(ptr, stream, ctx):
+            self.frees += 1
+            self.live -= 1
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = love_allocator(self._alloc, self._free, None)
+
+    def ref(self):
+        return C.byref(self.struct)
+
+
+_TORCH_ALLOC: Optional[TorchAllocator] = None
+
+
+def torch_allocator() -> TorchAllocator:
+    """The process-wide TorchAllocator (kept alive as long as any cache may use it)."""
+    global _TORCH_ALLOC
+    if _TORCH_ALLOC is None:
+        _TORCH_ALLOC = TorchAllocator()
+    return _TORCH_ALLOC
+
+
+def _alloc_arg(allocator):
+    """allocator argument of the entry points: "torch" (the process-wide
+    TorchAllocator), None (the library's own stream-ordered pool) or a
+    TorchAllocator instance."""
+    if allocator is None:
+        return None, None
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be 'torch', None or a TorchAllocator")
+        allocator = torch_allocator()
+    return allocator.ref(), allocator
+
+
 SYMBOLS = [
     "love_abi_version", "love_status_string", "love_build_cache", "love_build_cache_batched",
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
@@ -91,10 +157,11 @@ def load_library():
     L.love_status_string.restype = C.c_char_p
     L.love_status_string.argtypes = [i32]
     L.love_build_cache.restype = i32
-    L.love_build_cache.argtypes = [C.POINTER(love_config), vp, vp, i64, vp, C.POINTER(vp)]
+    AP = C.POINTER(love_allocator)
+    L.love_build_cache.argtypes = [C.POINTER(love_config), vp, vp, i64, AP, vp, C.POINTER(vp)]
     L.love_build_cache_batched.restype = i32
     L.love_build_cache_batched.argtypes = [i32, C.POINTER(love_config), C.POINTER(vp),
-                                           C.POINTER(vp), C.POINTER(i64), vp, C.POINTER(vp)]
+                                           C.POINTER(vp), C.POINTER(i64), AP, vp, C.POINTER(vp)]
     L.love_predict_mean_var.restype = i32
     L.love_predict_mean_var.argtypes = [vp, vp, i64, vp, vp, vp]
     L.love_predict_mean_var_batched.restype = i32
@@ -103,7 +170,7 @@ def load_library():
     L.love_predict_covar_pairs.restype = i32
     L.love_predict_covar_pairs.argtypes = [vp, vp, vp, i64, vp, vp]
     L.love_predict_covar_block.restype = i32
-    L.love_predict_covar_block.argtypes = [vp, vp, i64, vp, i64, vp, vp]
+    L.love_predict_covar_block.argtypes = [vp, vp, i64, vp, i64, vp, AP, vp]
     L.love_sample_posterior.restype = i32
     L.love_sample_posterior.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     L.love_predict_backward.restype = i32
@@ -119,7 +186,7 @@ def load_library():
     L.love_cache_export.restype = i32
     L.love_cache_export.argtypes = [vp, C.POINTER(love_export), vp]
     L.love_cache_import.restype = i32
-    L.love_cache_import.argtypes = [C.POINTER(love_config), C.POINTER(love_import), vp,
+    L.love_cache_import.argtypes = [C.POINTER(love_config), C.POINTER(love_import), AP, vp,
                                     C.POINTER(vp)]
     L.love_cache_free.restype = None
     L.love_cache_free.argtypes = [vp]
@@ -189,8 +256,9 @@ def _need(t: torch.Tensor, dtype, shape, name: str):
 class LoveCache:
     """A built LOVE cache (owned by the native library)."""
 
-    def __init__(self, handle: int, cfg: love_config):
+    def __init__(self, handle: int, cfg: love_config, allocator=None):
         self._h = C.c_void_p(handle)
+        self._allocator = allocator   # keeps the callbacks alive while the cache lives
         self.cfg = cfg
         self.d = cfg.d
         self.dtype = _dtype(cfg.precision)
@@ -204,6 +272,9 @@ class LoveCache:
         self._h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():   # torch may be gone: leave the memory to process exit
+            return
         try:
             self.free()
         except Exception:
@@ -242,13 +313,16 @@ class LoveCache:
                                                        C.c_void_p(_stream())), "predict_covar_pairs")
         return cov
 
-    def predict_covar_block(self, xa: torch.Tensor, xb: torch.Tensor):
-        """cov[i, j] = k(xa_i, xb_j) for every pair (ta x tb)."""
+    def predict_covar_block(self, xa: torch.Tensor, xb: torch.Tensor, allocator="cache"):
+        """cov[i, j] = k(xa_i, xb_j) for every pair (ta x tb).  allocator: "cache"
+        (the cache's own memory source), "torch", None (library pool) or a
+        TorchAllocator."""
         ta = self._xs(xa, "xa")
         tb = self._xs(xb, "xb")
         cov = torch.empty(ta, tb, device=xa.device, dtype=self.dtype)
+        aref, _ = (None, None) if allocator == "cache" else _alloc_arg(allocator)
         _check(load_library().love_predict_covar_block(self._h, _ptr(xa), ta, _ptr(xb), tb,
-                                                       _ptr(cov), C.c_void_p(_stream())),
+                                                       _ptr(cov), aref, C.c_void_p(_stream())),
                "predict_covar_block")
         return cov
 
@@ -328,9 +402,13 @@ class LoveCache:
         return out
 
 
-def build_cache(cfg: love_config, x: torch.Tensor, y: torch.Tensor) -> LoveCache:
-    """love_build_cache on device tensors x (n x d) and y (n)."""
+def build_cache(cfg: love_config, x: torch.Tensor, y: torch.Tensor,
+                allocator="torch") -> LoveCache:
+    """love_build_cache on device tensors x (n x d) and y (n).  allocator:
+    "torch" (torch's caching allocator backs the cache and its workspace),
+    None (the library's stream-ordered pool) or a TorchAllocator."""
     L = load_library()
+    aref, aobj = _alloc_arg(allocator)
     dt = _dtype(cfg.precision)
     n = x.shape[0]
     if x.dim() == 1 and cfg.d == 1:
@@ -338,12 +416,12 @@ def build_cache(cfg: love_config, x: torch.Tensor, y: torch.Tensor) -> LoveCache
     _need(x, dt, (n, cfg.d), "x")
     _need(y, dt, (n,), "y")
     h = C.c_void_p()
-    _check(L.love_build_cache(C.byref(cfg), _ptr(x), _ptr(y), n, C.c_void_p(_stream()), C.byref(h)),
-           "build_cache")
-    return LoveCache(h.value, cfg)
+    _check(L.love_build_cache(C.byref(cfg), _ptr(x), _ptr(y), n, aref, C.c_void_p(_stream()),
+                              C.byref(h)), "build_cache")
+    return LoveCache(h.value, cfg, aobj)
 
 
-def import_cache(cfg: love_config, parts: Dict[str, torch.Tensor]) -> LoveCache:
+def import_cache(cfg: love_config, parts: Dict[str, torch.Tensor], allocator="torch") -> LoveCache:
     """love_cache_import from the dict LoveCache.export() returns (device
     tensors: rt (m x k_eff float) or rt64, a, optional alpha, beta, s)."""
     L = load_library()
@@ -357,14 +435,16 @@ def import_cache(cfg: love_config, parts: Dict[str, torch.Tensor]) -> LoveCache:
                      _ptr(parts.get("rt64")) if cfg.precision == 0 else None,
                      _ptr(parts.get("a")), _ptr(s))
     h = C.c_void_p()
-    _check(L.love_cache_import(C.byref(cfg), C.byref(im), C.c_void_p(_stream()), C.byref(h)),
+    aref, aobj = _alloc_arg(allocator)
+    _check(L.love_cache_import(C.byref(cfg), C.byref(im), aref, C.c_void_p(_stream()), C.byref(h)),
            "cache_import")
-    return LoveCache(h.value, cfg)
+    return LoveCache(h.value, cfg, aobj)
 
 
 def build_cache_batched(cfgs: List[love_config], xs: List[torch.Tensor],
-                        ys: List[torch.Tensor]) -> List[LoveCache]:
+                        ys: List[torch.Tensor], allocator="torch") -> List[LoveCache]:
     L = load_library()
+    aref, aobj = _alloc_arg(allocator)
     G = len(cfgs)
     arr = (love_config * G)(*cfgs)
     xp = (C.c_void_p * G)(*[x.data_ptr() for x in xs])
@@ -375,9 +455,9 @@ def build_cache_batched(cfgs: List[love_config], xs: List[torch.Tensor],
         _need(xs[g], dt, (xs[g].shape[0], cfgs[g].d), f"xs[{g}]")
         _need(ys[g], dt, (xs[g].shape[0],), f"ys[{g}]")
     out = (C.c_void_p * G)()
-    _check(L.love_build_cache_batched(G, arr, xp, yp, ns, C.c_void_p(_stream()), out),
+    _check(L.love_build_cache_batched(G, arr, xp, yp, ns, aref, C.c_void_p(_stream()), out),
            "build_cache_batched")
-    return [LoveCache(out[g], cfgs[g]) for g in range(G)]
+    return [LoveCache(out[g], cfgs[g], aobj) for g in range(G)]
 
 
 def predict_mean_var_batched(caches: List[LoveCache], xs: List[torch.Tensor], outs=None):

@@ -97,12 +97,37 @@ void prof_end(const char* name, hipStream_t s) {
   if (p.pending.size() > 4096) drain(p);
 }
 
-// Cache memory comes from the device's stream-ordered pool on the cache's
-// stream (no device-wide synchronisation; the pool keeps freed memory for the
-// next build) and goes back to it in love_cache_free.
-bool dev_reserve(love_cache* c, size_t bytes) {
+void* mem_alloc(const MemSource& m, size_t bytes, hipStream_t s) {
+  if (m.user) return m.a.alloc(bytes, (void*)s, m.a.ctx);
   void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) return false;
+  return hipMallocAsync(&p, bytes, s) == hipSuccess ? p : nullptr;
+}
+
+void mem_free(const MemSource& m, void* p, hipStream_t s) {
+  if (!p) return;
+  if (m.user) m.a.free(p, (void*)s, m.a.ctx);
+  else (void)hipFreeAsync(p, s);
+}
+
+namespace {
+const MemSource& pool_source() {
+  static const MemSource pool{};
+  return pool;
+}
+thread_local const MemSource* t_mem = nullptr;
+}  // namespace
+
+const MemSource& cur_mem() { return t_mem ? *t_mem : pool_source(); }
+
+MemScope::MemScope(const MemSource& m) : prev_(t_mem), mine_(m) { t_mem = &mine_; }
+MemScope::~MemScope() { t_mem = prev_; }
+
+// Cache memory comes from the build call's source on the cache's stream (the
+// device's stream-ordered pool keeps freed memory for the next build, with no
+// device-wide synchronisation) and goes back to it in love_cache_free.
+bool dev_reserve(love_cache* c, size_t bytes) {
+  void* p = mem_alloc(c->mem, bytes, c->stream);
+  if (!p) return false;
   c->allocs.push_back(p);
   c->block = (char*)p;
   c->block_size = bytes;
@@ -118,8 +143,8 @@ void* dev_alloc(love_cache* c, size_t bytes) {
     c->block_used += bytes;
     return p;
   }
-  void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, c->stream) != hipSuccess) return nullptr;
+  void* p = mem_alloc(c->mem, bytes, c->stream);
+  if (!p) return nullptr;
   c->allocs.push_back(p);
   return p;
 }
@@ -163,6 +188,7 @@ static int kround(int k) { return k <= 64 ? 64 : 128; }
 
 static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, hipStream_t s) {
   c->cfg = *cfg;
+  c->mem = cur_mem();
   c->fp64 = cfg->precision == LOVE_P_FP64;
   c->d = cfg->d;
   c->n = n;
@@ -255,7 +281,7 @@ static void destroy(love_cache* c) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != c->device) (void)hipSetDevice(c->device);
-  for (void* p : c->allocs) (void)hipFreeAsync(p, c->stream);
+  for (void* p : c->allocs) mem_free(c->mem, p, c->stream);
   if (cur != c->device) (void)hipSetDevice(cur);
   delete c;
 }
@@ -366,7 +392,7 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   S.out = (T*)c->g1;
   void* cellp = nullptr;
   const size_t cb = scatter_scratch_bytes(c, sizeof(T));
-  if (cb) LOVE_HIP_TRY(hipMallocAsync(&cellp, cb, s));
+  if (cb && !(cellp = ws_alloc(cb, s))) return LOVE_ENOMEM;
   S.cellp = (T*)cellp;
   GatherJob<T> Ga{};
   Ga.g = S.g;
@@ -382,7 +408,7 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   toep_prepare<T>(A, run, one, {(const T*)c->g1}, {0}, {(T*)c->g2}, {0}, {(T*)c->tscr}, {nullptr});
   love_status st = A.upload(s);
   if (st != LOVE_OK) {
-    if (cellp) (void)hipFreeAsync(cellp, s);
+    ws_free(cellp, s);
     return st;
   }
   // rows of an additive cache stay in caller order (perm holds the axes' cell lists)
@@ -395,7 +421,7 @@ static love_status apply_khat_t(const love_cache* c, const T* v, T* out, hipStre
   if (c->add) LOVE_HIP_TRY(hipMemcpyAsync(out, c->v2, sizeof(T) * c->n, hipMemcpyDeviceToDevice, s));
   else launch_permute<T>((const T*)c->v2, out, c->perm, c->n, 1, s);
   A.release(s);
-  if (cellp) (void)hipFreeAsync(cellp, s);
+  ws_free(cellp, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 
@@ -430,15 +456,28 @@ const char* love_status_string(love_status s) {
   return "unknown status";
 }
 
+// The memory source an entry point was given (NULL: the device's pool).
+static bool mem_source(const love_allocator* a, MemSource* m) {
+  *m = MemSource{};
+  if (!a) return true;
+  if (!a->alloc || !a->free) return false;
+  m->a = *a;
+  m->user = true;
+  return true;
+}
+
 love_status love_build_cache(const love_config* cfg, const void* x, const void* y, int64_t n,
-                             void* stream, love_cache** out) {
-  return love_build_cache_batched(1, cfg, &x, &y, &n, stream, out);
+                             const love_allocator* alloc, void* stream, love_cache** out) {
+  return love_build_cache_batched(1, cfg, &x, &y, &n, alloc, stream, out);
 }
 
 love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const void* const* xs,
-                                     const void* const* ys, const int64_t* ns, void* stream,
+                                     const void* const* ys, const int64_t* ns,
+                                     const love_allocator* alloc, void* stream,
                                      love_cache** out) {
   if (G < 1 || !cfgs || !xs || !ys || !ns || !out) return LOVE_EINVAL;
+  MemSource ms;
+  if (!mem_source(alloc, &ms)) return LOVE_EINVAL;
   for (int g = 0; g < G; ++g) {
     love_status st = validate(&cfgs[g]);
     if (st != LOVE_OK) return st;
@@ -451,6 +490,7 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
   }
   hipStream_t s = (hipStream_t)stream;
   device_setup();
+  MemScope scope(ms);
   std::vector<love_cache*> made;
   auto fail = [&](love_status st) {
     for (auto* p : made) destroy(p);
@@ -521,14 +561,19 @@ love_status love_predict_covar_pairs(const love_cache* c, const void* xa, const 
                                      int64_t t, void* cov, void* stream) {
   if (!c || t < 0 || (t > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
   if (c->fp64) return covar_pairs<double>(c, (const double*)xa, (const double*)xb, t, (double*)cov, s);
   return covar_pairs<float>(c, (const float*)xa, (const float*)xb, t, (float*)cov, s);
 }
 
 love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_t ta,
-                                     const void* xb, int64_t tb, void* cov, void* stream) {
+                                     const void* xb, int64_t tb, void* cov,
+                                     const love_allocator* alloc, void* stream) {
   if (!c || ta < 0 || tb < 0 || (ta > 0 && tb > 0 && (!xa || !xb || !cov))) return LOVE_EINVAL;
+  MemSource ms;
+  if (!mem_source(alloc, &ms)) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(alloc ? ms : c->mem);
   if (c->fp64)
     return covar_block<double>(c, (const double*)xa, ta, (const double*)xb, tb, (double*)cov, s);
   return covar_block<float>(c, (const float*)xa, ta, (const float*)xb, tb, (float*)cov, s);
@@ -539,6 +584,7 @@ love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t
   if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;
   if (c->ks <= 0) return LOVE_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
   if (c->fp64) return sample<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
   return sample<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
 }
@@ -548,6 +594,7 @@ love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t
                                   void* stream) {
   if (!c || t < 0 || (t > 0 && (!xs || !g_xs))) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
   if (c->fp64)
     return backward<double>(c, (const double*)xs, t, (const double*)g_mean, (const double*)g_var,
                             (double*)g_xs, g_rt, s);
@@ -559,6 +606,7 @@ love_status love_apply_khat(const love_cache* c, const void* v, void* out, void*
   if (!c || !v || !out) return LOVE_EINVAL;
   if (c->n == 0) return LOVE_EUNSUPPORTED;   // imported cache: no training rows
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
   ProfScope ps("apply_khat", s);
   if (c->fp64) return apply_khat_t<double>(c, (const double*)v, (double*)out, s);
   return apply_khat_t<float>(c, (const float*)v, (float*)out, s);
@@ -567,6 +615,7 @@ love_status love_apply_khat(const love_cache* c, const void* v, void* out, void*
 love_status love_apply_kuu(const love_cache* c, const void* g, void* out, void* stream) {
   if (!c || !g || !out) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
   if (c->fp64) return apply_kuu_t<double>(c, (const double*)g, (double*)out, s);
   return apply_kuu_t<float>(c, (const float*)g, (float*)out, s);
 }
@@ -644,10 +693,12 @@ love_status love_cache_export(const love_cache* c, const love_export* e, void* s
   return LOVE_OK;
 }
 
-love_status love_cache_import(const love_config* cfg, const love_import* im, void* stream,
-                              love_cache** out) {
+love_status love_cache_import(const love_config* cfg, const love_import* im,
+                              const love_allocator* alloc, void* stream, love_cache** out) {
   if (!cfg || !im || !out) return LOVE_EINVAL;
   *out = nullptr;
+  MemSource ms;
+  if (!mem_source(alloc, &ms)) return LOVE_EINVAL;
   love_status st = validate(cfg);
   if (st != LOVE_OK) return st;
   if (im->k_eff < 1 || im->k_eff > LOVE_MAX_K || im->k_eff_sample < 0 ||
@@ -658,6 +709,7 @@ love_status love_cache_import(const love_config* cfg, const love_import* im, voi
   if ((im->k_eff_sample > 0) != (im->s != nullptr)) return LOVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   device_setup();
+  MemScope scope(ms);
   love_config cf = *cfg;
   cf.k = im->k_eff;
   cf.k_sample = im->k_eff_sample;

@@ -164,10 +164,9 @@ love_status fft_plan_axis(love_cache* c, ToepAxis& ax, int e, const std::vector<
     N <<= 1;
     ++logN;
   }
-  if (N > fft_max_n(true)) {   // the double tables must fit too (sampler and mean run in double)
-    ax.mode = LOVE_TOEPLITZ_DIRECT;
-    return LOVE_OK;
-  }
+  // the double tables must fit in LDS too (sampler and mean run in double);
+  // the autotuner never picks the FFT beyond that, an explicit request fails
+  if (N > fft_max_n(true)) return LOVE_EUNSUPPORTED;
   std::vector<std::complex<double>> cext(N, 0.0);
   for (int i = 0; i < ax.L; ++i) cext[i] = col[i];
   for (int i = 1; i < ax.L; ++i) cext[N - i] = col[i];
@@ -280,9 +279,9 @@ int autotune_choose(love_cache* c, int e) {
   const int64_t mt = c->m;
   int choice = LOVE_TOEPLITZ_DIRECT;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
-      hipMalloc(&bin, sizeof(float) * mt) == hipSuccess &&
-      hipMalloc(&bout, sizeof(float) * mt) == hipSuccess &&
-      hipMalloc(&bscr, sizeof(float) * toeplitz_scratch_elems(c)) == hipSuccess) {
+      (bin = (float*)ws_alloc(sizeof(float) * mt, s)) != nullptr &&
+      (bout = (float*)ws_alloc(sizeof(float) * mt, s)) != nullptr &&
+      (bscr = (float*)ws_alloc(sizeof(float) * toeplitz_scratch_elems(c), s)) != nullptr) {
     (void)hipMemsetAsync(bin, 0, sizeof(float) * mt, s);
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
@@ -294,10 +293,13 @@ int autotune_choose(love_cache* c, int e) {
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
   }
-  if (bin) (void)hipFree(bin);
-  if (bout) (void)hipFree(bout);
-  if (bscr) (void)hipFree(bscr);
-  if (s) (void)hipStreamDestroy(s);
+  if (s) {
+    ws_free(bin, s);
+    ws_free(bout, s);
+    ws_free(bscr, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune[key] = choice;
   return choice;

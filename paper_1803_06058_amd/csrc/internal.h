@@ -73,8 +73,41 @@ struct ToepPlan {
 
 }  // namespace love
 
+namespace love {
+// Where the device memory of a library call comes from: the caller's
+// love_allocator when one was given, else the device's stream-ordered pool
+// (hipMallocAsync / hipFreeAsync).  A block is released on the stream that
+// allocated it, after every stream that used it has been joined into that one.
+struct MemSource {
+  love_allocator a{};
+  bool user = false;
+};
+void* mem_alloc(const MemSource& m, size_t bytes, hipStream_t s);
+void mem_free(const MemSource& m, void* p, hipStream_t s);
+// The memory source of the calling thread's current entry point (set by a
+// MemScope there; the library's pool outside any scope).
+const MemSource& cur_mem();
+class MemScope {
+ public:
+  explicit MemScope(const MemSource& m);
+  ~MemScope();
+  MemScope(const MemScope&) = delete;
+  MemScope& operator=(const MemScope&) = delete;
+
+ private:
+  const MemSource* prev_;
+  MemSource mine_;
+};
+// Workspace of the current call: allocated and released on stream s.
+inline void* ws_alloc(size_t bytes, hipStream_t s) { return mem_alloc(cur_mem(), bytes, s); }
+inline void ws_free(void* p, hipStream_t s) {
+  if (p) mem_free(cur_mem(), p, s);
+}
+}  // namespace love
+
 struct love_cache {
   love_config cfg;
+  love::MemSource mem;        // source of the cache's memory (kept for love_cache_free)
   bool fp64 = false;
   int d = 1;
   int64_t n = 0, m = 0;
@@ -173,7 +206,8 @@ class JobArena {
   }
   love_status upload(hipStream_t s) {
     if (host_.empty()) return LOVE_OK;
-    if (hipMallocAsync((void**)&dev_, host_.size(), s) != hipSuccess) return LOVE_ENOMEM;
+    dev_ = (char*)ws_alloc(host_.size(), s);
+    if (!dev_) return LOVE_ENOMEM;
     LOVE_HIP_TRY(hipMemcpyAsync(dev_, host_.data(), host_.size(), hipMemcpyHostToDevice, s));
     return LOVE_OK;
   }
@@ -182,7 +216,7 @@ class JobArena {
     return reinterpret_cast<const J*>(dev_ + off);
   }
   void release(hipStream_t s) {
-    if (dev_) (void)hipFreeAsync(dev_, s);
+    ws_free(dev_, s);
     dev_ = nullptr;
   }
   ~JobArena() = default;

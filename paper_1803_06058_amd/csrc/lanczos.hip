@@ -325,22 +325,18 @@ __global__ __launch_bounds__(BLK) void k_colsum(Tab tab, const SumJob* __restric
 // (64-row blocks) so small problems still spread over the chip.  Chosen per
 // GP, so a GP's row blocking (hence its summation order) is the same in a
 // batch as in its own build.
-// LOVE_ROWS_PER_LANE=1|4 overrides (tuning).
 // Whether a Lanczos run over nb row blocks sums its partial rows inside the
 // consuming kernels (every block adds all nb rows, so the cost grows as nb^2)
 // rather than in column-sum launches: measured about even at 160 blocks and
-// slower at 391.  LOVE_PSUM_MAX_NB=<blocks> overrides the limit (tuning).
+// slower at 391.  The environment variable LOVE_PSUM_MAX_NB=<blocks> moves the
+// limit (declared in love.h).
 static bool lz_psum(int64_t nb) {
   const char* env = std::getenv("LOVE_PSUM_MAX_NB");
   const int64_t lim = env ? std::atoll(env) : 160;
   return nb <= lim;
 }
 
-static int rows_per_lane(int64_t rows) {
-  const char* env = std::getenv("LOVE_ROWS_PER_LANE");
-  if (env && (env[0] == '1' || env[0] == '4')) return env[0] - '0';
-  return cdiv(rows, 256) >= 256 ? 4 : 1;
-}
+static int rows_per_lane(int64_t rows) { return cdiv(rows, 256) >= 256 ? 4 : 1; }
 
 // launch over G GPs with nv_g + nv_add columns each (nv_g equal to the jobs' nv)
 static void launch_colsum(const SumJob* jobs, const std::vector<int>& nv, int nv_add, int mode,
@@ -1757,7 +1753,8 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     size_t bytes = sizeof(double) * ((size_t)ldq * ks + 4 * (size_t)ldq + 8 * LDP +
                                      3 * MAXK * MAXK + (size_t)toeplitz_scratch_elems(c) +
                                      2 * (size_t)nb * LDP);
-    LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+    buf = (char*)ws_alloc(bytes, s);
+    if (!buf) return LOVE_ENOMEM;
     Q = (double*)buf;
     v = Q + (size_t)ldq * ks;
     r = v + ldq;
@@ -1876,7 +1873,7 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     k_s_from_eig<<<sgrid, 256, 0, s>>>(m, Q, ldq, vout, lam, c->S, c->kspad, ctl);
   }
   A.release(s);
-  LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  ws_free(buf, s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }
@@ -1938,7 +1935,8 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
     if (!plain) db += sizeof(double) * ((size_t)b.nbg + 2) * kpad * kpad;
   }
   const size_t cb = (scatter_scratch_bytes(c, sizeof(double)) + 255) & ~size_t(255);
-  LOVE_HIP_TRY(hipMallocAsync((void**)&b.mem, tb + db + cb, s));
+  b.mem = (char*)ws_alloc(tb + db + cb, s);
+  if (!b.mem) return LOVE_ENOMEM;
   if (cb) b.cellp = b.mem + tb + db;
   T* t = (T*)b.mem;
   b.Q = t;   // Q and G first: their columns start on 16-byte boundaries
@@ -2008,7 +2006,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     love_status st = alloc_gp<T>(cs[g], bufs[g], mean, plain[g], s);
     if (st != LOVE_OK) {
       for (auto& b : bufs)
-        if (b.mem) (void)hipFreeAsync(b.mem, s);
+        ws_free(b.mem, s);
       return st;
     }
   }
@@ -2122,6 +2120,36 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     kmax = std::max(kmax, c->k);
   }
   JobArena A;
+  SpectralMean sm;
+  // Every return releases the build's workspace on s: first the side streams
+  // are joined into s (the samplers' and the mean solve's kernels read these
+  // buffers), then the job arrays and the GP buffers are freed.
+  struct Cleanup {
+    hipStream_t s;
+    JobArena* A;
+    std::vector<GpBufs<T>>* bufs;
+    SpectralMean* sm;
+    hipStream_t side = nullptr;       // sampler stream, while its work is not joined
+    hipEvent_t side_join = nullptr;
+    hipStream_t ms = nullptr;         // mean-solve stream, while the solve is live
+    bool mean_live = false;
+    std::vector<hipEvent_t> events;
+    ~Cleanup() {
+      if (side) {
+        if (!side_join || hipEventRecord(side_join, side) != hipSuccess ||
+            hipStreamWaitEvent(s, side_join, 0) != hipSuccess)
+          (void)hipStreamSynchronize(side);
+      }
+      if (mean_live) {
+        (void)hipStreamSynchronize(ms);
+        sm->release(s);
+      }
+      A->release(s);
+      for (auto& b : *bufs) ws_free(b.mem, s);
+      for (hipEvent_t e : events)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } clean{s, &A, &bufs, &sm};
   const size_t o_lz = A.add(lz), o_sc = A.add(sc), o_ga = A.add(ga), o_fi = A.add(fi),
                o_rj = A.add(rj), o_coef = A.add(s_coef), o_c2 = A.add(s_c2);
   ToepRun<T> t_probe, t_step;
@@ -2225,38 +2253,18 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   // so it starts here on its own stream and runs beside the Lanczos.
   bool spec = mean;
   for (auto* c : cs) spec = spec && spectral_mean_applies(c);
-  SpectralMean sm;
   hipStream_t s_mean = s;
   hipEvent_t ev_mfork = nullptr, ev_mjoin = nullptr;
-  // On any return before the join, the solve's stream is waited for (it
-  // writes into the cache) and its buffers released.
-  struct MeanGuard {
-    SpectralMean* sm;
-    hipStream_t ms, s;
-    hipEvent_t *fork, *join;
-    bool armed = false;
-    ~MeanGuard() {
-      if (armed) {
-        (void)hipStreamSynchronize(ms);
-        sm->release(s);
-      }
-      if (*fork) (void)hipEventDestroy(*fork);
-      if (*join) (void)hipEventDestroy(*join);
-    }
-  } guard{&sm, s, s, &ev_mfork, &ev_mjoin};
-  auto fail = [&](love_status code) {
-    A.release(s);
-    for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
-    return code;
-  };
   if (spec) {
     hipStream_t ms = mean_stream();
     if (ms && hipEventCreateWithFlags(&ev_mfork, hipEventDisableTiming) == hipSuccess &&
         hipEventCreateWithFlags(&ev_mjoin, hipEventDisableTiming) == hipSuccess &&
         hipEventRecord(ev_mfork, s) == hipSuccess && hipStreamWaitEvent(ms, ev_mfork, 0) == hipSuccess)
       s_mean = ms;
-    guard.ms = s_mean;
-    guard.armed = true;
+    clean.events.push_back(ev_mfork);
+    clean.events.push_back(ev_mjoin);
+    clean.ms = s_mean;
+    clean.mean_live = true;
     const Tab t_cvx = make_tab(b_cvx), t_cvy = make_tab(b_cvy);
     if (tab_blocks(t_cvx)) {
       k_convert_b<<<tab_blocks(t_cvx), 256, 0, s_mean>>>(t_cvx, A.at<ConvJob>(o_cvx));
@@ -2270,7 +2278,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       su[g] = bufs[g].cz;
     }
     love_status ss = sm.start(cs, sx, sy, su, s_mean);
-    if (ss != LOVE_OK) return fail(ss);
+    if (ss != LOVE_OK) return ss;
   }
   const int two_st = scatter_kinds(cs);
   // --- probe b = (1/m) W K 1 ; q_0 = b / ||b|| -----------------------------------
@@ -2349,9 +2357,13 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   if (any_s) {
     if (side) {
       LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      clean.events.push_back(ev_fork);
       LOVE_HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+      clean.events.push_back(ev_join);
       LOVE_HIP_TRY(hipEventRecord(ev_fork, s));
       LOVE_HIP_TRY(hipStreamWaitEvent(s_side, ev_fork, 0));
+      clean.side = s_side;
+      clean.side_join = ev_join;
     }
     for (auto* c : cs) {
       if (c->ks <= 0) continue;
@@ -2379,14 +2391,14 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     }
     if (spec) {
       love_status ss = sm.finish();
-      if (ss != LOVE_OK) return fail(ss);
+      if (ss != LOVE_OK) return ss;
       if (s_mean != s) {
         LOVE_HIP_TRY(hipEventRecord(ev_mjoin, s_mean));
         LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_mjoin, 0));
       }
       sm.merge(s);
+      clean.mean_live = false;
       sm.release(s);
-      guard.armed = false;
     }
     if (!spec) {
     const SumJob* dscg = A.at<SumJob>(o_scg);
@@ -2396,7 +2408,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     k_pcg_ep<T><<<tab_blocks(t_one), BLK, 0, s>>>(t_one, dcg, 1);
     k_pcg_apply<T><<<tab_blocks(t_rows), RBLK, 0, s>>>(t_rows, dcg);
     int* dflag = nullptr;
-    LOVE_HIP_TRY(hipMallocAsync((void**)&dflag, sizeof(int) * G, s));
+    dflag = (int*)ws_alloc(sizeof(int) * G, s);
+    if (!dflag) return LOVE_ENOMEM;
     std::vector<int> hflag(G, 0);
     int maxit = 0;
     bool any_plain = false;
@@ -2452,7 +2465,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       }
       for (int g = 0; g < G; ++g) a_nvq[g] = hflag[g] ? 0 : nvq[g];
     }
-    (void)hipFreeAsync(dflag, s);
+    ws_free(dflag, s);
     launch_scatter<double>(t_nodes, A.at<ScatterJob<double>>(o_cfin), D, 0, 0, s, two_st);
     toep_run<double>(A, t_cg, 0, 0, s);
     k_cg_store_a<T><<<tab_blocks(t_m), 256, 0, s>>>(t_m, dcg);
@@ -2460,13 +2473,10 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   }
   if (side) {
     LOVE_HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
-    (void)hipEventDestroy(ev_fork);
-    (void)hipEventDestroy(ev_join);
+    clean.side = nullptr;
   }
-  A.release(s);
-  for (auto& b : bufs) (void)hipFreeAsync(b.mem, s);
   LOVE_HIP_TRY(hipGetLastError());
-  return LOVE_OK;
+  return LOVE_OK;   // the workspace is released by `clean`
 }
 
 template <typename T>

@@ -529,7 +529,8 @@ love_status SpectralMean::start(const std::vector<love_cache*>& cs,
     const size_t sb = scatter_scratch_bytes(c, sizeof(double));
     const size_t cb = sb ? (sb + 255) / 256 * 32 : 0;   // doubles, whole 256-byte blocks
     nd += cb;
-    if (hipMallocAsync((void**)&mem_[g], nd * sizeof(double), s) != hipSuccess) return LOVE_ENOMEM;
+    mem_[g] = (char*)ws_alloc(nd * sizeof(double), s);
+    if (!mem_[g]) return LOVE_ENOMEM;
     double* q = (double*)mem_[g];
     J.ctl = (Ctl*)q;
     q += 32;
@@ -603,7 +604,8 @@ love_status SpectralMean::start(const std::vector<love_cache*>& cs,
   const Tab t_axis = make_tab(b_axis);
   kinds_ = scatter_kinds(cs);
   for (const auto& J : jobs_) maxit_ = std::max(maxit_, J.maxit);
-  LOVE_HIP_TRY(hipMallocAsync((void**)&dflag_, sizeof(int), s));
+  dflag_ = (int*)ws_alloc(sizeof(int), s);
+  if (!dflag_) return LOVE_ENOMEM;
 
   ProfScope ps("mean_spectral", s);
   k_spec_axis<<<tab_blocks(t_axis), EIG_THREADS, 0, s>>>(t_axis, dj_);
@@ -676,11 +678,22 @@ void SpectralMean::merge(hipStream_t s) {
 }
 
 void SpectralMean::release(hipStream_t s) {
-  if (dflag_) (void)hipFreeAsync(dflag_, s);
+  // The buffers were allocated on the solve's stream and are freed there,
+  // after the build stream's last use of them (merge): the solve's stream
+  // first waits for `s`.
+  hipStream_t fs = s_ ? s_ : s;
+  if (fs != s) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(fs, ev, 0) != hipSuccess)
+      (void)hipStreamSynchronize(s);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  ws_free(dflag_, fs);
   dflag_ = nullptr;
-  A_.release(s);
+  A_.release(fs);
   for (char* p : mem_)
-    if (p) (void)hipFreeAsync(p, s);
+    ws_free(p, fs);
   mem_.clear();
   uploaded_ = false;
 }

@@ -714,14 +714,6 @@ void toep_prepare(JobArena& A, ToepRun<T>& run, const std::vector<love_cache*>& 
       // segments: enough blocks to cover the chip (~512), each at least 256 inputs
       int nseg = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(512, ntiles * ax.outer),
                                                              cdiv(band, 256)));
-      {
-        // LOVE_TOEP_NSEG=q fixes the segment count (tuning)
-        static const int forced = [] {
-          const char* ev = std::getenv("LOVE_TOEP_NSEG");
-          return ev ? std::atoi(ev) : 0;
-        }();
-        if (forced > 0) nseg = forced;
-      }
       nseg = std::max(nseg, (int)cdiv(band, TB_SEG));
       nseg = std::min(nseg, TB_NSEG_MAX);
       J.ntiles = ntiles;

@@ -617,7 +617,8 @@ love_status covar_block(const love_cache* c, const T* xa, int64_t ta, const T* x
   const int d = c->d, kpad = c->kpad, nrec = 5 * d + 1;
   double* U = nullptr;
   const size_t per = (size_t)kpad + nrec;
-  LOVE_HIP_TRY(hipMallocAsync((void**)&U, sizeof(double) * per * (size_t)(ta + tb), s));
+  U = (double*)ws_alloc(sizeof(double) * per * (size_t)(ta + tb), s);
+  if (!U) return LOVE_ENOMEM;
   double* Ua = U;
   double* Ub = Ua + (size_t)kpad * ta;
   double* ra = Ub + (size_t)kpad * tb;
@@ -651,7 +652,7 @@ love_status covar_block(const love_cache* c, const T* xa, int64_t ta, const T* x
   }
 #undef LAUNCH_CVA
 #undef LAUNCH_CV
-  LOVE_HIP_TRY(hipFreeAsync(U, s));
+  ws_free(U, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 template love_status covar_block<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
@@ -976,7 +977,8 @@ love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, 
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
   const int kspad = c->kspad;
   float* F = nullptr;
-  LOVE_HIP_TRY(hipMallocAsync((void**)&F, sizeof(float) * (size_t)t * (kspad + 1), s));
+  F = (float*)ws_alloc(sizeof(float) * (size_t)t * (kspad + 1), s);
+  if (!F) return LOVE_ENOMEM;
   float* mu = F + (size_t)t * kspad;
   const unsigned nbf = (unsigned)cdiv(t, PPB);
   switch (c->d) {
@@ -997,7 +999,7 @@ love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, 
   dim3 grid((unsigned)cdiv(t, SM_T), (unsigned)std::min<int64_t>(njt, 65535));
   tlaunch("sample", k_sample_mm<T>, grid, 256, 0, s, (const float*)F, (const float*)mu, kspad,
           (const Ctl*)c->ctl_s, z, ns, t, njt, out);
-  LOVE_HIP_TRY(hipFreeAsync(F, s));
+  ws_free(F, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 template love_status sample<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);

@@ -215,7 +215,8 @@ love_status sort_impl(const std::vector<love_cache*>& cs, const std::vector<cons
   uint32_t *k0, *v0, *k1, *v1, *hist, *cnt;
   size_t bytes = sizeof(uint32_t) * (4 * (size_t)N + (size_t)RS_BINS * nb + (size_t)K + 1);
   char* buf = nullptr;
-  LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+  buf = (char*)ws_alloc(bytes, s);
+  if (!buf) return LOVE_ENOMEM;
   k0 = (uint32_t*)buf;
   v0 = k0 + N;
   k1 = v0 + N;
@@ -238,7 +239,7 @@ love_status sort_impl(const std::vector<love_cache*>& cs, const std::vector<cons
   k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, K + 1, nullptr);
   k_cell_start<T><<<tab_blocks(tcell), 256, 0, s>>>(tcell, dj, cnt);
   k_gather_sorted<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, v0);
-  LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  ws_free(buf, s);
   A.release(s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
@@ -335,7 +336,8 @@ love_status sort_add_impl(const std::vector<love_cache*>& cs, const std::vector<
   uint32_t *k0, *v0, *k1, *v1, *hist, *cnt;
   size_t bytes = sizeof(uint32_t) * (4 * (size_t)N + (size_t)RS_BINS * nb + (size_t)K + 1);
   char* buf = nullptr;
-  LOVE_HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+  buf = (char*)ws_alloc(bytes, s);
+  if (!buf) return LOVE_ENOMEM;
   k0 = (uint32_t*)buf;
   v0 = k0 + N;
   k1 = v0 + N;
@@ -358,7 +360,7 @@ love_status sort_add_impl(const std::vector<love_cache*>& cs, const std::vector<
   k_scan_exclusive<<<1, 1024, 0, s>>>(cnt, K + 1, nullptr);
   k_cell_start<T><<<tab_blocks(tcell), 256, 0, s>>>(tcell, dj, cnt);
   k_copy_add<T, D><<<tab_blocks(trow), 256, 0, s>>>(trow, dj, v0);
-  LOVE_HIP_TRY(hipFreeAsync(buf, s));
+  ws_free(buf, s);
   A.release(s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;

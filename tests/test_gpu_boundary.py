@@ -1,0 +1,114 @@
+"""The C ABI's memory and backend contracts on the GPU: builds, imports and
+covariance blocks through a caller-supplied love_allocator (torch's caching
+allocator) equal the library-pool results bit for bit and return every block
+they took; an explicit FFT request the LDS-resident FFT cannot meet is
+refused."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1803_06058_amd import binding as B
+from paper_1803_06058_amd import workloads as WL
+
+from gpu_helpers import cfg_of, tdev, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+def _build(P, allocator, **over):
+    dt = torch_dtype(P)
+    return B.build_cache(cfg_of(P, **over), tdev(P.x, dt), tdev(P.y, dt), allocator=allocator)
+
+
+def _contents(cache, xs):
+    ex = cache.export()
+    _, var = cache.predict_mean_var(xs)
+    torch.cuda.synchronize()
+    return {k: v.cpu() for k, v in ex.items()} | {"var": var.cpu()}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_build_through_torch_allocator(precision):
+    P = WL.config(2, scale=0.05, s=16, dtype="f64" if precision == "fp64" else "f32",
+                  precision=precision)
+    print(P.name, P.n, P.m, precision, flush=True)
+    dt = torch_dtype(P)
+    xs = tdev(P.xs[:4000], dt)
+    ref_cache = _build(P, None)
+    ref = _contents(ref_cache, xs)
+    ref_cache.free()
+    torch.cuda.synchronize()
+    ta = B.TorchAllocator()
+    base = torch.cuda.memory_allocated()
+    c = _build(P, ta)
+    held = torch.cuda.memory_allocated() - base
+    got = _contents(c, xs)
+    print("allocator calls", ta.allocs, ta.frees, ta.live, "held", held, flush=True)
+    assert ta.allocs > 0 and ta.live >= 1 and held > 0
+    for k in ref:
+        assert torch.equal(ref[k], got[k]), k
+    # the query-side calls on this cache take their scratch from it too
+    c.sample_posterior(tdev(P.xs_sample[:100], dt), tdev(P.z, torch.float32))
+    c.predict_covar_block(xs[:50], xs[50:90])
+    torch.cuda.synchronize()
+    c.free()
+    torch.cuda.synchronize()
+    assert ta.live == 0 and ta.allocs == ta.frees
+    assert torch.cuda.memory_allocated() == base
+
+
+def test_batched_import_and_covar_block_through_allocator():
+    Ps = WL.batched_config(G=3, scale=0.05, t_per_gp=2000)
+    cfgs = [cfg_of(P) for P in Ps]
+    xs = [tdev(P.x, torch.float32) for P in Ps]
+    ys = [tdev(P.y, torch.float32) for P in Ps]
+    ta = B.TorchAllocator()
+    base = torch.cuda.memory_allocated()
+    a = B.build_cache_batched(cfgs, xs, ys, allocator=None)
+    b = B.build_cache_batched(cfgs, xs, ys, allocator=ta)
+    for ca, cb, P in zip(a, b, Ps):
+        q = tdev(P.xs[:1000], torch.float32)
+        assert torch.equal(ca.predict_mean_var(q)[1], cb.predict_mean_var(q)[1])
+        # import through the allocator; the covariance block with an explicit allocator
+        imp = B.import_cache(cfg_of(P), cb.export(), allocator=ta)
+        blk_ref = ca.predict_covar_block(q[:40], q[40:70], allocator=None)
+        blk = imp.predict_covar_block(q[:40], q[40:70], allocator=ta)
+        assert torch.equal(blk_ref, blk)
+        imp.free()
+    for c in a + b:
+        c.free()
+    torch.cuda.synchronize()
+    print("allocator calls", ta.allocs, ta.frees, ta.live, flush=True)
+    assert ta.live == 0 and ta.allocs == ta.frees > 0
+    assert torch.cuda.memory_allocated() == base
+
+
+def test_failing_allocator_reports_enomem():
+    """An allocator that refuses every request makes the build return
+    LOVE_ENOMEM (no cache, nothing left behind)."""
+    P = WL.config(2, scale=0.02, k_sample=0)
+    refuse = B.love_allocator(B.ALLOC_FN(lambda n, s, ctx: None),
+                              B.FREE_FN(lambda p, s, ctx: None), None)
+
+    class Refuse:
+        def ref(self):
+            import ctypes
+            return ctypes.byref(refuse)
+
+    with pytest.raises(B.LoveError) as ei:
+        _build(P, Refuse())
+    assert ei.value.code == -4
+
+
+def test_explicit_fft_beyond_lds_refused():
+    """m = 5000 needs a circulant of 16384 points, beyond the LDS-resident
+    FFT: an explicit FFT request is refused (LOVE_EUNSUPPORTED), the automatic
+    choice takes the direct product."""
+    P = WL.config(2, scale=0.5, k_sample=0)          # m = 5000
+    assert P.m[0] == 5000
+    with pytest.raises(B.LoveError) as ei:
+        _build(P, None, toeplitz="fft", k=4, flags=B.FLAG_NO_MEAN)
+    assert ei.value.code == -7
+    c = _build(P, None, toeplitz="auto", k=4, flags=B.FLAG_NO_MEAN)
+    assert c.info().toeplitz_mode[0] == 1
+    c.free()
