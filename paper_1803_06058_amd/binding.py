@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import sys
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -272,7 +273,6 @@ class LoveCache:
         self._h = None
 
     def __del__(self):
-        import sys
         if sys.is_finalizing():   # torch may be gone: leave the memory to process exit
             return
         try:

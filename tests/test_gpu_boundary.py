@@ -75,6 +75,8 @@ def test_batched_import_and_covar_block_through_allocator():
         blk = imp.predict_covar_block(q[:40], q[40:70], allocator=ta)
         assert torch.equal(blk_ref, blk)
         imp.free()
+    # the loop's last query and output tensors are torch's, not the library's
+    del q, blk_ref, blk
     for c in a + b:
         c.free()
     torch.cuda.synchronize()
