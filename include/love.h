@@ -73,7 +73,7 @@
 extern "C" {
 #endif
 
-#define LOVE_ABI_VERSION 2
+#define LOVE_ABI_VERSION 3
 #define LOVE_MAX_DIM 4
 #define LOVE_MAX_K 128
 
@@ -86,8 +86,14 @@ enum {
   LOVE_ENOMEM = -4,        /* device allocation failed                                       */
   LOVE_EHIP = -5,          /* a HIP runtime call failed                                      */
   LOVE_ENONFINITE = -6,    /* non-finite training input or Lanczos coefficient               */
-  LOVE_EUNSUPPORTED = -7   /* valid request the library does not support (e.g. no sampler)   */
+  LOVE_EUNSUPPORTED = -7,  /* valid request the library does not support (e.g. no sampler)   */
+  LOVE_ELIMIT = -8         /* request exceeds a fixed limit of the call (the static scratch of
+                              love_sample_posterior_noalloc)                                    */
 };
+
+/* Bytes of the fixed device scratch array behind love_sample_posterior_noalloc
+ * (one copy per device, held until the process ends). */
+#define LOVE_NOALLOC_SCRATCH_BYTES (8u << 20)
 
 typedef enum { LOVE_RBF = 0, LOVE_MATERN52 = 1 } love_kernel;   /* product over dimensions */
 
@@ -282,6 +288,28 @@ love_status love_predict_covar_block(const love_cache* c, const void* xa, int64_
  * Errors: EUNSUPPORTED if the cache has no sampler. */
 love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t, const float* z,
                                   int64_t s, void* out, void* stream);
+
+/* love_sample_posterior for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * love_sample_posterior, but the t x (kspad + 1) floats of intermediate
+ * W_{X*} S and means live in a fixed device array of
+ * LOVE_NOALLOC_SCRATCH_BYTES instead of memory from the cache's allocator;
+ * no hipMalloc, hipFree or allocating library routine is called.
+ *   kspad = 64 if min(k_sample, m) <= 64, else 128, so t may be at most
+ *   32263 (kspad 64) or 16256 (kspad 128) points per call; a larger t returns
+ *   LOVE_ELIMIT before any device work (split the points over several calls).
+ *   The array's address is looked up once per device (hipGetSymbolAddress)
+ *   on the first call made with that device current; the call runs on the
+ *   current device, which must be the cache's (EINVAL otherwise).
+ *   Every call on one device shares that device's array and leaves its
+ *   contents behind: calls that overlap on one device (several streams or
+ *   threads, or a graph replayed beside another call) race and must be
+ *   serialised by the caller.
+ * Errors: as love_sample_posterior, plus ELIMIT; EHIP if the symbol lookup
+ * fails. */
+love_status love_sample_posterior_noalloc(const love_cache* c, const void* xs, int64_t t,
+                                          const float* z, int64_t s, void* out, void* stream);
 
 /* Backward of love_predict_mean_var: given upstream gradients g_mean, g_var
  * (t each, either nullable), writes g_xs (t x d) = d(sum g_mean*mean + g_var*var)/d xs,

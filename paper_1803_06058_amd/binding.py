@@ -22,7 +22,7 @@ FLAG_ASYNC, FLAG_NO_MEAN, FLAG_PLAIN_CG, FLAG_EIG_QL, FLAG_MEAN_KRYLOV = 1, 2, 4
 FLAG_ADDITIVE = 32   # additive composition: grid vectors stack the axes, m = sum of m_i
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "EDOMAIN", -3: "ENOTPD", -4: "ENOMEM", -5: "EHIP",
-          -6: "ENONFINITE", -7: "EUNSUPPORTED"}
+          -6: "ENONFINITE", -7: "EUNSUPPORTED", -8: "ELIMIT"}
 
 
 class LoveError(RuntimeError):
@@ -131,7 +131,7 @@ SYMBOLS = [
     "love_abi_version", "love_status_string", "love_build_cache", "love_build_cache_batched",
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
     "love_predict_covar_block",
-    "love_sample_posterior", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
+    "love_sample_posterior", "love_sample_posterior_noalloc", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
     "love_cache_info", "love_cache_keff", "love_cache_export", "love_cache_import", "love_cache_free",
     "love_profile_enable",
     "love_profile_read", "love_profile_select",
@@ -174,6 +174,8 @@ def load_library():
     L.love_predict_covar_block.argtypes = [vp, vp, i64, vp, i64, vp, AP, vp]
     L.love_sample_posterior.restype = i32
     L.love_sample_posterior.argtypes = [vp, vp, i64, vp, i64, vp, vp]
+    L.love_sample_posterior_noalloc.restype = i32
+    L.love_sample_posterior_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     L.love_predict_backward.restype = i32
     L.love_predict_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
     L.love_apply_khat.restype = i32
@@ -345,6 +347,22 @@ class LoveCache:
             out = torch.empty(t, s, device=xs.device, dtype=self.dtype)
         _check(load_library().love_sample_posterior(self._h, _ptr(xs), t, _ptr(z), s, _ptr(out),
                                                     C.c_void_p(_stream())), "sample_posterior")
+        return out
+
+    def sample_posterior_noalloc(self, xs: torch.Tensor, z: torch.Tensor, out: torch.Tensor):
+        """love_sample_posterior_noalloc: the library allocates nothing; the
+        caller passes the t x s output."""
+        t = self._xs(xs)
+        _need(z, torch.float32, None, "z")
+        if z.dim() != 2:
+            raise ValueError("z must be k_sample x s")
+        if z.shape[0] < self.keff()[1]:
+            raise ValueError("z needs at least k_eff_sample rows")
+        s = z.shape[1]
+        _need(out, self.dtype, (t, s), "out")
+        _check(load_library().love_sample_posterior_noalloc(
+            self._h, _ptr(xs), t, _ptr(z), s, _ptr(out), C.c_void_p(_stream())),
+            "sample_posterior_noalloc")
         return out
 
     def predict_backward(self, xs: torch.Tensor, g_mean: Optional[torch.Tensor],

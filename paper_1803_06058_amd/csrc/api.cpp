@@ -452,6 +452,7 @@ const char* love_status_string(love_status s) {
     case LOVE_EHIP: return "HIP runtime error";
     case LOVE_ENONFINITE: return "non-finite value";
     case LOVE_EUNSUPPORTED: return "unsupported request";
+    case LOVE_ELIMIT: return "request exceeds a fixed limit of the call";
   }
   return "unknown status";
 }
@@ -587,6 +588,18 @@ love_status love_sample_posterior(const love_cache* c, const void* xs, int64_t t
   MemScope scope(c->mem);
   if (c->fp64) return sample<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
   return sample<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
+}
+
+love_status love_sample_posterior_noalloc(const love_cache* c, const void* xs, int64_t t,
+                                          const float* z, int64_t ns, void* out, void* stream) {
+  if (!c || t < 0 || ns < 0 || (t > 0 && ns > 0 && (!xs || !z || !out))) return LOVE_EINVAL;
+  if (c->ks <= 0) return LOVE_EUNSUPPORTED;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LOVE_EHIP;
+  if (dev != c->device) return LOVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->fp64) return sample_noalloc<double>(c, (const double*)xs, t, z, ns, (double*)out, s);
+  return sample_noalloc<float>(c, (const float*)xs, t, z, ns, (float*)out, s);
 }
 
 love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t,

@@ -359,9 +359,16 @@ template <typename T>
 love_status covar_pairs(const love_cache* c, const T* xa, const T* xb, int64_t t, T* cov,
                         hipStream_t s);
 
+// scratch: t x (kspad + 1) floats for F and mu, or NULL to take them from the
+// call's memory source
 template <typename T>
 love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns,
-                   T* out, hipStream_t s);
+                   T* out, hipStream_t s, float* scratch = nullptr);
+// The same on the device's fixed scratch array (no allocation); LOVE_ELIMIT
+// when t x (kspad + 1) floats exceed it.  The current device must be the cache's.
+template <typename T>
+love_status sample_noalloc(const love_cache* c, const T* xs, int64_t t, const float* z,
+                           int64_t ns, T* out, hipStream_t s);
 
 template <typename T>
 love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, const T* gv,

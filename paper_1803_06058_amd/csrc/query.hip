@@ -10,6 +10,7 @@
 // in double.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -971,13 +972,13 @@ __global__ __launch_bounds__(256) void k_sample_mm(const float* __restrict__ F,
 
 template <typename T>
 love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns, T* out,
-                   hipStream_t s) {
+                   hipStream_t s, float* scratch) {
   if (t == 0 || ns == 0) return LOVE_OK;
   GridT<T> g = make_grid<T>(c);
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
   const int kspad = c->kspad;
-  float* F = nullptr;
-  F = (float*)ws_alloc(sizeof(float) * (size_t)t * (kspad + 1), s);
+  float* F = scratch;
+  if (!F) F = (float*)ws_alloc(sizeof(float) * (size_t)t * (kspad + 1), s);
   if (!F) return LOVE_ENOMEM;
   float* mu = F + (size_t)t * kspad;
   const unsigned nbf = (unsigned)cdiv(t, PPB);
@@ -999,11 +1000,51 @@ love_status sample(const love_cache* c, const T* xs, int64_t t, const float* z, 
   dim3 grid((unsigned)cdiv(t, SM_T), (unsigned)std::min<int64_t>(njt, 65535));
   tlaunch("sample", k_sample_mm<T>, grid, 256, 0, s, (const float*)F, (const float*)mu, kspad,
           (const Ctl*)c->ctl_s, z, ns, t, njt, out);
-  ws_free(F, s);
+  if (!scratch) ws_free(F, s);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
-template love_status sample<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
-template love_status sample<double>(const love_cache*, const double*, int64_t, const float*, int64_t, double*, hipStream_t);
+template love_status sample<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t, float*);
+template love_status sample<double>(const love_cache*, const double*, int64_t, const float*, int64_t, double*, hipStream_t, float*);
+
+// ----------------------------------------------------------------------------
+// Fixed device scratch of the sampling entry point that allocates nothing
+// (love_sample_posterior_noalloc): F and mu of the sample path above.  Every
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: host code
+// uses only the address hipGetSymbolAddress returns for the current device,
+// looked up once per device and kept in scratch_dev.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) float scratch[LOVE_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+static std::mutex scratch_mu;
+static std::vector<float*> scratch_dev;   // device ordinal -> address of its copy
+
+static love_status scratch_of_current_device(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LOVE_EHIP;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if ((int)scratch_dev.size() <= dev) scratch_dev.resize(dev + 1, nullptr);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LOVE_EHIP;
+    scratch_dev[dev] = (float*)p;
+  }
+  *out = scratch_dev[dev];
+  return LOVE_OK;
+}
+
+template <typename T>
+love_status sample_noalloc(const love_cache* c, const T* xs, int64_t t, const float* z, int64_t ns,
+                           T* out, hipStream_t s) {
+  const size_t need = sizeof(float) * (size_t)t * (size_t)(c->kspad + 1);
+  if (need > (size_t)LOVE_NOALLOC_SCRATCH_BYTES) return LOVE_ELIMIT;
+  float* F = nullptr;
+  const love_status st = scratch_of_current_device(&F);
+  if (st != LOVE_OK) return st;
+  return sample<T>(c, xs, t, z, ns, out, s, F);
+}
+template love_status sample_noalloc<float>(const love_cache*, const float*, int64_t, const float*, int64_t, float*, hipStream_t);
+template love_status sample_noalloc<double>(const love_cache*, const double*, int64_t, const float*, int64_t, double*, hipStream_t);
 
 
 // Rt (m x kpad, stored precision) -> dst (m x keff, float)
