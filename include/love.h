@@ -314,9 +314,13 @@ love_status love_sample_posterior_noalloc(const love_cache* c, const void* xs, i
 /* Backward of love_predict_mean_var: given upstream gradients g_mean, g_var
  * (t each, either nullable), writes g_xs (t x d) = d(sum g_mean*mean + g_var*var)/d xs,
  * through the derivative interpolation weights, and, if g_rt is not NULL,
- * ACCUMULATES d(sum g_var*var)/d Rt into g_rt (m x k_eff row-major float; the
- * caller zeroes it; accumulation uses float atomics, so its summation order
- * is not deterministic). */
+ * ADDS d(sum g_var*var)/d Rt = -2 sum_i g_var,i w(x*_i) (Rt^T w(x*_i))^T to g_rt
+ * (m x k_eff row-major float; the caller zeroes it).  The g_rt sum is formed
+ * per grid node over the query points sorted by stencil cell, in double and in
+ * a fixed order, so it is bitwise reproducible; it takes t x kpad floats plus
+ * (t, or d t for LOVE_FLAG_ADDITIVE) + cells + 1 32-bit words of scratch from
+ * the cache's memory source.  Out-of-domain points contribute nothing.
+ * Errors: EINVAL, ENOMEM (scratch), EHIP. */
 love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t,
                                   const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
                                   void* stream);

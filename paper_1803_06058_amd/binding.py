@@ -274,8 +274,8 @@ class LoveCache:
             load_library().love_cache_free(self._h)
         self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():   # torch may be gone: leave the memory to process exit
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():   # torch may be gone: leave the memory to process exit
             return
         try:
             self.free()

@@ -260,6 +260,13 @@ love_status toeplitz_plan(love_cache* c);
 void toeplitz_set_attrs();
 
 // --- setup (sort.hip) -------------------------------------------------------
+// Query points xs (t x d) sorted by stencil cell: order[pos] (t entries, or
+// d t for an additive composition, one per point and axis) is the point of
+// the pos-th entry in (cell, entry) order and cstart[c] (ctot + 1) the first
+// position of cell c (additive: axis e's cells from acoff[e]).
+template <typename T>
+love_status sort_points(const love_cache* c, const T* xs, int64_t t, uint32_t* order,
+                        uint32_t* cstart, hipStream_t s);
 // Sort the rows of every GP of the batch by stencil cell (one sort for all).
 template <typename T>
 love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,

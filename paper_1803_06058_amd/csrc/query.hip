@@ -667,7 +667,9 @@ template love_status covar_pairs<double>(const love_cache*, const double*, const
 //   d mean / dx_e = sum_a dW_a^e a[node_a]
 //   d var  / dx_e = dp/dx_e - 2 u . v_e,  u = Rt^T w, v_e = Rt^T dw/dx_e
 //   dp/dx_e = 2 (dw_e)^T T_e w_e * prod_{f != e} w_f^T T_f w_f
-// Optional dRt: += -2 g_var W_a u  (float atomics).
+// Optional dRt = sum_i -2 g_var,i w(x*_i) u_i^T: this kernel writes each
+// point's row H_i = -2 g_var,i u_i (float, kpad columns; zero for points
+// outside the domain), k_grt_gather sums the rows per grid node.
 // Lanes as in the predictive variances: 16 per point, lane sub holding the
 // CPL = kpad / 16 consecutive columns from sub CPL of every stencil row.
 // ----------------------------------------------------------------------------
@@ -678,7 +680,7 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
                                      const Ctl* __restrict__ ctl, const T* __restrict__ acache,
                                      const double* __restrict__ c4, const T* __restrict__ gm,
                                      const T* __restrict__ gv, T* __restrict__ gx,
-                                     float* __restrict__ grt, unsigned* __restrict__ status) {
+                                     float* __restrict__ H, unsigned* __restrict__ status) {
   const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
   const int64_t p = (int64_t)blockIdx.x * PPB + threadIdx.x / PLQ;
   const bool live = p < t;
@@ -765,20 +767,95 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
     }
   }
   if (!ok && live && sub == 0) atomicOr(status, SF_DOMAIN);
-  if (grt && live && ok && gvar != 0.0) {
-    const int keff = ctl->k_eff;
-    for (int a = 0; a < NA; ++a) {
-      double wa;
-      int64_t node;
-      stn_entry<T, D, ADD>(g, w, base, jb, a, wa, node);
-      const double f = -2.0 * gvar * wa;
+  if (H && live) {
+    const double f = ok ? -2.0 * gvar : 0.0;
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int col = sub * CPL + q;
-        if (col < keff) atomicAdd(&grt[node * keff + col], (float)(f * u[q]));
+    for (int q = 0; q < CPL; q += 4)
+      *reinterpret_cast<float4*>(H + p * kpad + sub * CPL + q) =
+          make_float4((float)(f * u[q]), (float)(f * u[q + 1]), (float)(f * u[q + 2]),
+                      (float)(f * u[q + 3]));
+  }
+}
+
+// dRt[node, :] += sum w_node(x*_i) H_i over the points i whose stencil holds
+// the node: one wave per grid node, lane l summing columns l (and l + 64) in
+// double over the cells around the node (stencil offsets ascending) and, in a
+// cell, over its points in sorted order, so the result does not depend on
+// scheduling.  order / cstart come from sort_points.
+template <typename T, int D, bool ADD>
+__global__ __launch_bounds__(256) void k_grt_gather(GridT<T> g, const T* __restrict__ xs,
+                                                    const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ cstart,
+                                                    const float* __restrict__ H, int kpad,
+                                                    const Ctl* __restrict__ ctl,
+                                                    float* __restrict__ grt) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t node = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+  if (node >= g.mtot) return;
+  const bool two = kpad > WAVE;
+  double acc0 = 0.0, acc1 = 0.0;
+  if constexpr (ADD) {
+    int e = 0;
+#pragma unroll
+    for (int f = 1; f < D; ++f)
+      if (node >= g.aoff[f]) e = f;
+    const int i = (int)(node - g.aoff[e]);
+    for (int o = 0; o < 4; ++o) {
+      const int cl = i - o;
+      if (cl < 0 || cl >= g.cells[e]) continue;
+      const int64_t key = g.acoff[e] + cl;
+      for (uint32_t pos = cstart[key], en = cstart[key + 1]; pos < en; ++pos) {
+        const int64_t pt = order[pos];
+        T xe = xs[pt * D + e];
+        if (!(xe == xe)) xe = g.lo[e];
+        T sv;
+        (void)stencil_at(g, e, xe, sv);
+        const double wv = (double)keys_weight_at<T>(o, sv);
+        const float* hr = H + pt * kpad;
+        acc0 += wv * (double)hr[lane];
+        if (two) acc1 += wv * (double)hr[lane + WAVE];
+      }
+    }
+  } else {
+    int ie[D];
+    int64_t r = node;
+#pragma unroll
+    for (int e = D - 1; e >= 0; --e) {
+      ie[e] = (int)(r % g.m[e]);
+      r /= g.m[e];
+    }
+    for (int a = 0; a < (1 << (2 * D)); ++a) {
+      int oe[D];
+      int64_t cell = 0;
+      bool valid = true;
+#pragma unroll
+      for (int e = 0; e < D; ++e) {
+        oe[e] = (a >> (2 * (D - 1 - e))) & 3;
+        const int cl = ie[e] - oe[e];
+        valid = valid && cl >= 0 && cl < g.cells[e];
+        cell += (int64_t)cl * g.cstride[e];
+      }
+      if (!valid) continue;
+      for (uint32_t pos = cstart[cell], en = cstart[cell + 1]; pos < en; ++pos) {
+        const int64_t pt = order[pos];
+        double wv = 1.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          T xe = xs[pt * D + e];
+          if (!(xe == xe)) xe = g.lo[e];
+          T sv;
+          (void)stencil_at(g, e, xe, sv);
+          wv *= (double)keys_weight_at<T>(oe[e], sv);
+        }
+        const float* hr = H + pt * kpad;
+        acc0 += wv * (double)hr[lane];
+        if (two) acc1 += wv * (double)hr[lane + WAVE];
       }
     }
   }
+  const int keff = ctl->k_eff;
+  if (lane < keff) grt[node * keff + lane] += (float)acc0;
+  if (two && lane + WAVE < keff) grt[node * keff + lane + WAVE] += (float)acc1;
 }
 template <typename T, int D, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
@@ -788,14 +865,14 @@ __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restric
                                                   const T* __restrict__ acache,
                                                   const double* __restrict__ c4,
                                                   const T* __restrict__ gm, const T* __restrict__ gv,
-                                                  T* __restrict__ gx, float* __restrict__ grt,
+                                                  T* __restrict__ gx, float* __restrict__ H,
                                                   unsigned* __restrict__ status) {
   if (kpad > 64)
     backward_body<T, D, SPLIT, 128 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv,
-                                               gx, grt, status);
+                                               gx, H, status);
   else
     backward_body<T, D, SPLIT, 64 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, ctl, acache, c4, gm, gv,
-                                              gx, grt, status);
+                                              gx, H, status);
 }
 
 template <typename T>
@@ -807,14 +884,28 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
   const T* a = (c->cfg.flags & LOVE_FLAG_NO_MEAN) ? nullptr : (const T*)c->a;
   const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
   const Ctl* ctl = c->ctl;
+  // dRt workspace: H (t x kpad float), the sorted point entries, cell starts
+  float* H = nullptr;
+  uint32_t *order = nullptr, *cst = nullptr;
+  if (grt) {
+    if (t >= (int64_t(1) << 31) / 4) return LOVE_EINVAL;
+    const int64_t nv = c->add ? (int64_t)c->d * t : t;
+    const size_t hbytes = sizeof(float) * (size_t)t * c->kpad;
+    const size_t obytes = (sizeof(uint32_t) * (size_t)nv + 255) & ~size_t(255);
+    char* buf = (char*)ws_alloc(hbytes + obytes + sizeof(uint32_t) * ((size_t)c->ctot + 1), s);
+    if (!buf) return LOVE_ENOMEM;
+    H = (float*)buf;
+    order = (uint32_t*)(buf + hbytes);
+    cst = (uint32_t*)(buf + hbytes + obytes);
+  }
 #define LAUNCH_B(D, ADD)                                                                          \
   if (split)                                                                                      \
     tlaunch("backward", k_backward<T, D, 1, ADD>, nb, 256, 0, s, g, xs, t, c->rt,                 \
-            (const uint16_t*)c->rt_lo, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt, \
+            (const uint16_t*)c->rt_lo, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, H,   \
             c->status);                                                                           \
   else                                                                                            \
     tlaunch("backward", k_backward<T, D, 0, ADD>, nb, 256, 0, s, g, xs, t, c->rt,                 \
-            (const uint16_t*)nullptr, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, grt,  \
+            (const uint16_t*)nullptr, c->kpad, ctl, a, (const double*)c->c4_dev, gm, gv, gx, H,    \
             c->status);
 #define LAUNCH_BA(D)                                                                               \
   if (c->add) {                                                                                    \
@@ -830,6 +921,28 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
   }
 #undef LAUNCH_BA
 #undef LAUNCH_B
+  if (grt) {
+    love_status st = sort_points<T>(c, xs, t, order, cst, s);
+    if (st == LOVE_OK) {
+      const unsigned nbg = (unsigned)cdiv(g.mtot, 256 / WAVE);
+#define LAUNCH_G(D)                                                                                \
+  if (c->add)                                                                                      \
+    tlaunch("grt_gather", k_grt_gather<T, D, true>, nbg, 256, 0, s, g, xs, (const uint32_t*)order, \
+            (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt);                             \
+  else                                                                                             \
+    tlaunch("grt_gather", k_grt_gather<T, D, false>, nbg, 256, 0, s, g, xs,                        \
+            (const uint32_t*)order, (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt);
+      switch (c->d) {
+        case 1: LAUNCH_G(1); break;
+        case 2: LAUNCH_G(2); break;
+        case 3: LAUNCH_G(3); break;
+        case 4: LAUNCH_G(4); break;
+      }
+#undef LAUNCH_G
+    }
+    ws_free(H, s);
+    if (st != LOVE_OK) return st;
+  }
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
 template love_status backward<float>(const love_cache*, const float*, int64_t, const float*, const float*, float*, float*, hipStream_t);

@@ -366,7 +366,96 @@ love_status sort_add_impl(const std::vector<love_cache*>& cs, const std::vector<
   return LOVE_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Query points sorted by stencil cell (the backward's d var / d Rt gathers a
+// grid node's contributions from the points of the cells around it).  Entry
+// i < t is point i keyed by its flattened cell; for an additive composition
+// entry e t + p is point p keyed by acoff[e] + its axis-e cell.  Stable, so
+// the order is (cell, entry); order[pos] is the point of the pos-th entry.
+// ----------------------------------------------------------------------------
+template <typename T, int D, bool ADD>
+__global__ void k_point_cells(GridT<T> g, const T* __restrict__ xs, int64_t t,
+                              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                              uint32_t* __restrict__ count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= t) return;
+  int64_t cell = 0;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    T xe = xs[p * D + e];
+    if (!(xe == xe)) xe = g.lo[e];
+    T sv;
+    const int j = stencil_at(g, e, xe, sv);
+    if constexpr (ADD) {
+      const uint32_t key = (uint32_t)(g.acoff[e] + j);
+      keys[(int64_t)e * t + p] = key;
+      vals[(int64_t)e * t + p] = (uint32_t)p;
+      atomicAdd(&count[key], 1u);
+    } else {
+      cell += (int64_t)j * g.cstride[e];
+    }
+  }
+  if constexpr (!ADD) {
+    keys[p] = (uint32_t)cell;
+    vals[p] = (uint32_t)p;
+    atomicAdd(&count[cell], 1u);
+  }
+}
+
+template <typename T, int D, bool ADD>
+love_status sort_points_impl(const love_cache* c, const T* xs, int64_t t, uint32_t* order,
+                             uint32_t* cstart, hipStream_t s) {
+  const GridT<T> g = make_grid<T>(c);
+  const int64_t N = ADD ? (int64_t)D * t : t, K = c->ctot;
+  if (N >= (int64_t(1) << 31) || K >= (int64_t(1) << 31)) return LOVE_EINVAL;
+  const int nb = (int)cdiv(N, RS_TILE);
+  int bits = 1;
+  while ((int64_t(1) << bits) < K) ++bits;
+  const int passes = (bits + 7) / 8;
+  const size_t bytes = sizeof(uint32_t) * (3 * (size_t)N + (size_t)RS_BINS * nb);
+  uint32_t* buf = (uint32_t*)ws_alloc(bytes, s);
+  if (!buf) return LOVE_ENOMEM;
+  // values ping-pong between scratch and `order`, starting where the last
+  // pass ends in `order`
+  uint32_t *k0 = buf, *k1 = k0 + N, *vs = k1 + N, *hist = vs + N;
+  uint32_t* v0 = (passes % 2) ? vs : order;
+  uint32_t* v1 = (passes % 2) ? order : vs;
+  LOVE_HIP_TRY(hipMemsetAsync(cstart, 0, sizeof(uint32_t) * (K + 1), s));
+  k_point_cells<T, D, ADD><<<(unsigned)cdiv(t, 256), 256, 0, s>>>(g, xs, t, k0, v0, cstart);
+  for (int q = 0; q < passes; ++q) {
+    const int shift = 8 * q;
+    k_rs_hist<<<nb, RS_BLOCK, 0, s>>>(k0, N, shift, hist, nb);
+    k_scan_exclusive<<<1, 1024, 0, s>>>(hist, (int64_t)RS_BINS * nb, nullptr);
+    k_rs_scatter<<<nb, RS_BLOCK, 0, s>>>(k0, v0, k1, v1, N, shift, hist, nb);
+    std::swap(k0, k1);
+    std::swap(v0, v1);
+  }
+  k_scan_exclusive<<<1, 1024, 0, s>>>(cstart, K + 1, nullptr);
+  ws_free(buf, s);
+  LOVE_HIP_TRY(hipGetLastError());
+  return LOVE_OK;
+}
+
 }  // namespace
+
+template <typename T>
+love_status sort_points(const love_cache* c, const T* xs, int64_t t, uint32_t* order,
+                        uint32_t* cstart, hipStream_t s) {
+#define SP_CASE(D)                                                              \
+  case D:                                                                       \
+    return c->add ? sort_points_impl<T, D, true>(c, xs, t, order, cstart, s)   \
+                  : sort_points_impl<T, D, false>(c, xs, t, order, cstart, s);
+  switch (c->d) {
+    SP_CASE(1)
+    SP_CASE(2)
+    SP_CASE(3)
+    SP_CASE(4)
+  }
+#undef SP_CASE
+  return LOVE_EINVAL;
+}
+template love_status sort_points<float>(const love_cache*, const float*, int64_t, uint32_t*, uint32_t*, hipStream_t);
+template love_status sort_points<double>(const love_cache*, const double*, int64_t, uint32_t*, uint32_t*, hipStream_t);
 
 template <typename T>
 love_status setup_sort(const std::vector<love_cache*>& cs, const std::vector<const T*>& xs,

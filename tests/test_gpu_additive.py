@@ -309,13 +309,14 @@ def test_additive_backward_parity(f64):
     rel = np.max(np.abs(host(gx) - ref)) / np.max(np.abs(ref))
     print(rel, flush=True)
     assert rel <= (1e-9 if f64 else 1e-4)
-    # d var / d Rt = -2 sum_points g_var w u^T over the stacked rows
+    # d var / d Rt over the stacked rows, compared as G Rt^T (basis independent)
     rt = host(cache.export()["rt64" if f64 else "rt"])
-    Ws = O.interp_matrix(xs.astype(np.float64), spec_of(P))
-    U = Ws @ rt
-    refg = -2.0 * (Ws.T @ (gv.astype(np.float64)[:, None] * U))
-    relg = np.max(np.abs(host(grt) - refg)) / np.max(np.abs(refg))
-    assert relg <= 1e-4
+    refg = O.love_grad_rt(oc, xs.astype(np.float64), gv.astype(np.float64)) @ oc.Rt.T
+    relg = np.max(np.abs(host(grt) @ rt.T - refg)) / np.max(np.abs(refg))
+    print("d var / d Rt", relg, flush=True)
+    assert relg <= (1e-6 if f64 else 1e-4)
+    _, grt2 = cache.predict_backward(tdev(xs, dt), tdev(gm, dt), tdev(gv, dt), want_grt=True)
+    assert torch.equal(grt, grt2)
     xt = tdev(xs, dt).requires_grad_(True)
     mu, var = B.LovePredict.apply(xt, cache)
     (mu * tdev(gm, dt) + var * tdev(gv, dt)).sum().backward()

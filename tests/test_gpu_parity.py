@@ -624,6 +624,35 @@ def test_backward_parity(cfgi, scale):
     cache.free()
 
 
+@pytest.mark.parametrize("cfgi,scale,tol", [(1, 1.0, 1e-6), (2, 0.02, 1e-4), (3, 0.01, 3e-3),
+                                            (4, 0.01, 1e-4)])
+def test_grad_rt_parity(cfgi, scale, tol):
+    """d(sum g_var var)/d Rt = -2 W*^T diag(g) W* Rt (love_grad_rt) on product
+    grids.  Rt is only defined up to the Krylov basis (the float and double
+    Lanczos vectors differ), so the comparison is on G Rt^T, which is
+    -2 W*^T diag(g) W* Rt Rt^T on both sides and, Rt having full column rank,
+    zero only if G is.  The gradient is float and summed per grid node in a
+    fixed order: two calls agree bit for bit."""
+    P = WL.config(cfgi, scale=scale)
+    cache = build(P)
+    dt = torch_dtype(P)
+    xs = P.xs[:3000]
+    gv = np.random.default_rng(8).standard_normal(xs.shape[0]).astype(P.np_dtype)
+    xt, gt = tdev(xs, dt), tdev(gv, dt)
+    _, g1 = cache.predict_backward(xt, None, gt, want_grt=True)
+    _, g2 = cache.predict_backward(xt, None, gt, want_grt=True)
+    assert torch.equal(g1, g2)
+    ex = cache.export()
+    rt = host(ex["rt64"] if dt == torch.float64 else ex["rt"])
+    oc = oracle_cache(P)
+    ref = O.love_grad_rt(oc, xs.astype(np.float64), gv.astype(np.float64)) @ oc.Rt.T
+    got = host(g1) @ rt.T
+    rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(P.name, P.m, cache.info().k_eff, oc.k, rel, flush=True)
+    assert rel <= tol
+    cache.free()
+
+
 # ---------------------------------------------------------------------------
 # Determinism, batching, edge cases
 # ---------------------------------------------------------------------------
