@@ -263,8 +263,15 @@ def test_sampler_draw_and_saturated_parity():
 
 
 def test_sampler_truncated_vs_oracle():
-    """k' = 100 < m = 200: both sides are truncated Lanczos approximations of
-    W*(K - R^T R')W*^T; the GPU's truncation error must be of the oracle's size."""
+    """k' = 100 < m = 200: both sides truncate the second Lanczos at the same
+    k', half the grid, where the Krylov space has not converged and its
+    unconverged part follows the rounding of each side's operator (the float
+    cache against the double one).  Element by element, the GPU's implied
+    covariance W* S S^T W*^T is then within 1.5x the oracle's own truncation
+    error (|oracle - W*(K - R^T R')W*^T|, relative to the prior) of the
+    oracle's, and as close to W*(K - R^T R')W*^T as the oracle is.  The
+    full-size 1-D workload (m = 1e4, k' = 100), where the spectrum has decayed
+    by k', is compared to 1e-5 of the prior in test_gpu_fullsize.py."""
     P, cache, ex, S, a, xs, spec, out, Ws = _sampler_case(0.02)
     oc = oracle_cache(P)
     osm = O.love_sampler(oc, P.k_sample)
@@ -272,10 +279,15 @@ def test_sampler_truncated_vs_oracle():
     Wd = Ws[sub].toarray()
     target = Wd @ (O.K_dense(spec) - oc.Rt @ oc.Rt.T) @ Wd.T
     F = Ws[sub] @ S
-    err_gpu = np.max(np.abs(F @ F.T - target))
-    err_or = np.max(np.abs(O.sample_covariance_implied(oc, osm, xs[sub].astype(np.float64)) - target))
-    print(err_gpu, err_or, flush=True)
-    assert err_gpu <= 3 * err_or + 1e-5
+    sig_or = O.sample_covariance_implied(oc, osm, xs[sub].astype(np.float64))
+    p = O.prior_var(xs[sub], spec)
+    scale = np.sqrt(np.outer(p, p))
+    e_go = np.max(np.abs(F @ F.T - sig_or) / scale)
+    e_gt = np.max(np.abs(F @ F.T - target) / scale)
+    e_ot = np.max(np.abs(sig_or - target) / scale)
+    print(cache.info().k_eff_sample, osm.k_chol, e_go, e_gt, e_ot, flush=True)
+    assert e_go <= 1.5 * e_ot
+    assert e_gt <= 1.5 * e_ot
     cache.free()
 
 
