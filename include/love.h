@@ -130,6 +130,9 @@ typedef enum {
                                        (a query point's interpolation vector has 4 d entries, its
                                        prior is the sum of the axes' terms).  Every GP of a batched
                                        build must agree on this flag (LOVE_EINVAL otherwise).     */
+#define LOVE_FLAG_HYPER 64u         /* also keep B = W^T Q L^{-T} (m x k, cache precision) for
+                                       love_predict_var_hyper_grad; Rt = K B.  Does not change
+                                       any other result of the cache                              */
 
 typedef struct {
   int32_t d;                        /* input dimension, 1..4                                     */
@@ -324,6 +327,25 @@ love_status love_sample_posterior_noalloc(const love_cache* c, const void* xs, i
 love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t,
                                   const void* g_mean, const void* g_var, void* g_xs, float* g_rt,
                                   void* stream);
+
+/* Gradient of sum_i g_var[i] var(xs_i) with respect to the hyper-parameters,
+ * through the cache (Sec. 3.2: the cache is built during training; eqs.
+ * pred_covar_approx, pred_covar_ski_cache, pred_covar_ski_fast).  Every solve
+ * Khat^{-1} in the derivative of the variance is taken as the cached Lanczos
+ * solve Q T^{-1} Q^T (eq. lanczos_solve), as the cached variance itself does:
+ *   d/dtheta sum g_i var_i = sum g_i dp_i/dtheta + <dK/dtheta B, B M - 2 P>
+ *                            + [theta = sigma^2] sum g_i ||L^{-T} u_i||^2,
+ * with u_i = Rt^T w_i, M = sum g_i u_i u_i^T, P = sum g_i w_i u_i^T (the
+ * last term takes Q^T Q = I).  theta order in grad (device, d + 2 doubles):
+ * lengthscale_0 .. lengthscale_{d-1}, outputscale, noise sigma^2.  For an
+ * additive composition the lengthscale of axis e moves block e only.
+ *   xs : t x d, g_var : t (precision's type, device); points outside the
+ *   domain contribute nothing.  Scratch: about (t + 3 m) kpad + t d doubles
+ *   from the cache's memory source.
+ * Errors: EUNSUPPORTED if the cache was built without LOVE_FLAG_HYPER (or
+ * imported), EINVAL, ENOMEM, EHIP. */
+love_status love_predict_var_hyper_grad(const love_cache* c, const void* xs, int64_t t,
+                                        const void* g_var, double* grad, void* stream);
 
 /* out = Khat v = (W K W^T + sigma^2 I) v in the caller's training-row order (n). */
 love_status love_apply_khat(const love_cache* c, const void* v, void* out, void* stream);

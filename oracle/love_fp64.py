@@ -500,18 +500,22 @@ def exact_covariance_grid(X, spec: Spec) -> np.ndarray:
     return K - V.T @ V
 
 
-def _var_hyper_grad(spec: Spec, W, Xs, Z, g) -> np.ndarray:
+def _var_hyper_grad(spec: Spec, W, Xs, Z, g, with_scale: bool = False):
     """sum_i g_i d var_i / d theta (hyper_names order) for
     var_i = w_i^T K w_i - w_i^T K W^T z_i, z_i = Khat^{-1} W K w_i (column i of
     Z, n x t), by the product rule:
       d var_i = w_i^T dK w_i - 2 w_i^T dK W^T z_i + z_i^T (W dK W^T + d sigma^2 I) z_i
     (the last term has a plus sign because d(A^{-1}) = -A^{-1} dA A^{-1}).
-    W is the training interpolation matrix (n x m, sparse)."""
+    W is the training interpolation matrix (n x m, sparse).  with_scale also
+    returns sum_i |g_i| (|w_i^T dK w_i| + 2 |w_i^T dK W^T z_i| + |third term|)
+    per theta: the three terms nearly cancel (the variance is a small
+    remainder of the prior), and this is the size rounding errors scale with."""
     Ws = interp_matrix(Xs, spec)
     g = np.asarray(g, dtype=np.float64)
     Y = np.asarray(W.T @ Z)                         # m x t : W^T z_i
     dp = prior_var_dtheta(Xs, spec)                 # t x (d + 2) : w_i^T dK w_i
     out = np.zeros(spec.d + 2)
+    scale = np.zeros(spec.d + 2)
     for th in range(spec.d + 2):
         DY = K_apply_dtheta(spec, th, Y)
         cross = np.asarray(Ws.multiply(DY.T).sum(axis=1)).ravel()      # w_i^T dK W^T z_i
@@ -519,7 +523,8 @@ def _var_hyper_grad(spec: Spec, W, Xs, Z, g) -> np.ndarray:
         if th == spec.d + 1:
             quad = quad + np.sum(Z * Z, axis=0)
         out[th] = np.sum(g * (dp[:, th] - 2.0 * cross + quad))
-    return out
+        scale[th] = np.sum(np.abs(g) * (np.abs(dp[:, th]) + 2.0 * np.abs(cross) + np.abs(quad)))
+    return (out, scale) if with_scale else out
 
 
 def exact_var_hyper_grad(X, Xs, spec: Spec, g_var) -> np.ndarray:
@@ -783,7 +788,7 @@ def love_grad_rt(cache: LoveCache, Xs, g_var) -> np.ndarray:
     return -2.0 * (Ws.T @ (g[:, None] * u))
 
 
-def love_var_hyper_grad(cache: LoveCache, X, Xs, g_var) -> np.ndarray:
+def love_var_hyper_grad(cache: LoveCache, X, Xs, g_var, with_scale: bool = False):
     """Gradient of sum_i g_i var(x*_i) with respect to the hyper-parameters
     (hyper_names order) through the LOVE cache: the product rule of
     exact_var_hyper_grad with every solve Khat^{-1} taken as the cached Lanczos
@@ -794,7 +799,7 @@ def love_var_hyper_grad(cache: LoveCache, X, Xs, g_var) -> np.ndarray:
     op = KissOperator(X, spec)
     U = interp_matrix(Xs, spec) @ cache.Rt                                     # t x k
     Z = cache.lanczos.Q @ sla.solve_triangular(cache.L.T, U.T, lower=False)   # n x t
-    return _var_hyper_grad(spec, op.W, Xs, Z, g_var)
+    return _var_hyper_grad(spec, op.W, Xs, Z, g_var, with_scale)
 
 
 # ---------------------------------------------------------------------------

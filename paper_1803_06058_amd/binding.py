@@ -20,6 +20,7 @@ KERNELS = {"rbf": 0, "matern52": 1}
 TOEPLITZ_MODES = {"auto": 0, "direct": 1, "fft": 2}
 FLAG_ASYNC, FLAG_NO_MEAN, FLAG_PLAIN_CG, FLAG_EIG_QL, FLAG_MEAN_KRYLOV = 1, 2, 4, 8, 16
 FLAG_ADDITIVE = 32   # additive composition: grid vectors stack the axes, m = sum of m_i
+FLAG_HYPER = 64      # keep B = W^T Q L^{-T} for the hyper-parameter gradient
 
 STATUS = {0: "ok", -1: "EINVAL", -2: "EDOMAIN", -3: "ENOTPD", -4: "ENOMEM", -5: "EHIP",
           -6: "ENONFINITE", -7: "EUNSUPPORTED", -8: "ELIMIT"}
@@ -131,7 +132,8 @@ SYMBOLS = [
     "love_abi_version", "love_status_string", "love_build_cache", "love_build_cache_batched",
     "love_predict_mean_var", "love_predict_mean_var_batched", "love_predict_covar_pairs",
     "love_predict_covar_block",
-    "love_sample_posterior", "love_sample_posterior_noalloc", "love_predict_backward", "love_apply_khat", "love_apply_kuu",
+    "love_sample_posterior", "love_sample_posterior_noalloc", "love_predict_backward",
+    "love_predict_var_hyper_grad", "love_apply_khat", "love_apply_kuu",
     "love_cache_info", "love_cache_keff", "love_cache_export", "love_cache_import", "love_cache_free",
     "love_profile_enable",
     "love_profile_read", "love_profile_select",
@@ -178,6 +180,8 @@ def load_library():
     L.love_sample_posterior_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, vp]
     L.love_predict_backward.restype = i32
     L.love_predict_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+    L.love_predict_var_hyper_grad.restype = i32
+    L.love_predict_var_hyper_grad.argtypes = [vp, vp, i64, vp, vp, vp]
     L.love_apply_khat.restype = i32
     L.love_apply_khat.argtypes = [vp, vp, vp, vp]
     L.love_apply_kuu.restype = i32
@@ -379,6 +383,17 @@ class LoveCache:
                                                     _ptr(gx), _ptr(grt), C.c_void_p(_stream())),
                "predict_backward")
         return gx, grt
+
+    def predict_var_hyper_grad(self, xs: torch.Tensor, g_var: torch.Tensor) -> torch.Tensor:
+        """d(sum g_var * var)/d theta, theta = (lengthscales, outputscale, noise):
+        a (d + 2,) float64 tensor (the cache needs FLAG_HYPER)."""
+        t = self._xs(xs)
+        _need(g_var, self.dtype, (t,), "g_var")
+        out = torch.empty(self.d + 2, device=xs.device, dtype=torch.float64)
+        _check(load_library().love_predict_var_hyper_grad(self._h, _ptr(xs), t, _ptr(g_var),
+                                                          _ptr(out), C.c_void_p(_stream())),
+               "predict_var_hyper_grad")
+        return out
 
     def apply_khat(self, v: torch.Tensor):
         out = torch.empty_like(v)

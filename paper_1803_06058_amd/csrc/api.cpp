@@ -238,6 +238,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
                   dev_round((split ? 2 : es) * (size_t)m * c->kpad) +
                   (split ? dev_round(2 * (size_t)m * c->kpad) : 0) + dev_round(es * (size_t)m) +
                   (c->ks > 0 ? dev_round(sizeof(float) * (size_t)m * c->kspad) : 0) +
+                  ((cfg->flags & LOVE_FLAG_HYPER) ? dev_round(es * (size_t)m * c->kpad) : 0) +
                   2 * dev_round(es * (size_t)n) + 2 * dev_round(es * (size_t)m) +
                   dev_round(sizeof(double) * 16) +
                   dev_round(sizeof(double) * (size_t)toeplitz_scratch_elems(c));
@@ -260,6 +261,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   if (split) c->rt_lo = dev_alloc(c, 2 * (size_t)m * c->kpad);
   c->a = dev_alloc(c, es * (size_t)m);
   if (c->ks > 0) c->S = (float*)dev_alloc(c, sizeof(float) * (size_t)m * c->kspad);
+  if (cfg->flags & LOVE_FLAG_HYPER) c->B = dev_alloc(c, es * (size_t)m * c->kpad);
   c->v1 = dev_alloc(c, es * (size_t)n);
   c->v2 = dev_alloc(c, es * (size_t)n);
   c->g1 = dev_alloc(c, es * (size_t)m);
@@ -267,7 +269,7 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->tscr = nullptr;  // allocated after the Toeplitz plan
   if (!c->x || !c->y || !c->perm || !c->cell_start || !c->ctl || !c->ctl_s || !c->status || !c->ortho ||
       !c->alpha || !c->beta || !c->rt || (split && !c->rt_lo) || !c->a || (c->ks > 0 && !c->S) ||
-      !c->v1 || !c->v2 || !c->g1 || !c->g2)
+      !c->v1 || !c->v2 || !c->g1 || !c->g2 || ((cfg->flags & LOVE_FLAG_HYPER) && !c->B))
     return LOVE_ENOMEM;
   LOVE_HIP_TRY(hipMemsetAsync(c->ctl, 0, 2 * sizeof(Ctl) + 4 * sizeof(unsigned), s));
   LOVE_HIP_TRY(hipMemsetAsync(c->a, 0, es * (size_t)m, s));
@@ -613,6 +615,18 @@ love_status love_predict_backward(const love_cache* c, const void* xs, int64_t t
                             (double*)g_xs, g_rt, s);
   return backward<float>(c, (const float*)xs, t, (const float*)g_mean, (const float*)g_var,
                          (float*)g_xs, g_rt, s);
+}
+
+love_status love_predict_var_hyper_grad(const love_cache* c, const void* xs, int64_t t,
+                                        const void* g_var, double* grad, void* stream) {
+  if (!c || t < 0 || !grad || (t > 0 && (!xs || !g_var))) return LOVE_EINVAL;
+  if (!c->B) return LOVE_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  MemScope scope(c->mem);
+  ProfScope ps("hyper_grad", s);
+  if (c->fp64)
+    return hyper_grad<double>(c, (const double*)xs, t, (const double*)g_var, grad, s);
+  return hyper_grad<float>(c, (const float*)xs, t, (const float*)g_var, grad, s);
 }
 
 love_status love_apply_khat(const love_cache* c, const void* v, void* out, void* stream) {

@@ -138,6 +138,7 @@ struct love_cache {
   void* rt = nullptr;         // m x kpad (T) ; for bf16 split: hi plane (uint16)
   void* rt_lo = nullptr;      // bf16 split: lo plane (uint16)
   void* a = nullptr;          // m (T)
+  void* B = nullptr;          // LOVE_FLAG_HYPER: m x kpad (T), W^T Q L^{-T} (Rt = K B)
   float* S = nullptr;         // m x kspad
   double* alpha = nullptr;    // k
   double* beta = nullptr;     // k
@@ -380,6 +381,12 @@ love_status sample_noalloc(const love_cache* c, const T* xs, int64_t t, const fl
 template <typename T>
 love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, const T* gv,
                      T* gx, float* grt, hipStream_t s);
+
+// d (sum g_var var) / d theta, theta = (lengthscales, outputscale, sigma^2)
+// into grad (device, d + 2 doubles); needs the cache's B (LOVE_FLAG_HYPER)
+template <typename T>
+love_status hyper_grad(const love_cache* c, const T* xs, int64_t t, const T* gv, double* grad,
+                       hipStream_t s);
 
 love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t s);
 // imported Rt into the cache layout and the control blocks of an imported cache

@@ -133,7 +133,8 @@ struct LzJob {
 // Rt[u, :] = (L^{-1} R[:, u])^T
 template <typename T>
 struct RtJob {
-  const T* R;
+  const T* R;                 // k x ld row-major (row i: column i of the factor's input)
+  int64_t ld;                 // row stride of R (0: m)
   const double* ldiag;
   const double* lsub;
   void* rt;

@@ -737,7 +737,8 @@ __global__ void k_tri_chol(Tab tab, const LzJob<T>* __restrict__ jobs, double re
 
 // Rt[u, :] = (L^{-1} R[:, u])^T : bidiagonal forward substitution per grid node.
 // split = 1 stores bf16 hi = rne(z), lo = rne(z - hi).
-// Rt[u, :] = (L^{-1} R[:, u])^T.  One wave per 64 grid rows, lane = row: the
+// Rt[u, :] = (L^{-1} R[:, u])^T (and, for the hyper-parameter gradient, B
+// from G = W^T Q the same way).  One wave per 64 grid rows, lane = row: the
 // forward substitution runs down the k columns (loads of R coalesced over the
 // rows), the rows are staged in LDS and leave as one contiguous 64 x kpad slab
 // (coalesced stores), in the cache precision or as bf16 hi + bf16 lo.
@@ -751,7 +752,7 @@ __global__ __launch_bounds__(RT_ROWS) void k_rtilde(Tab tab, const RtJob<T>* __r
   __shared__ T tile[RT_ROWS * TS];
   __shared__ double ld[MAXK], ls[MAXK];
   const int k = J.ctl->k_eff, kpad = J.kpad;
-  const int64_t m = J.m;
+  const int64_t m = J.m, rs = J.ld ? J.ld : J.m;
   const int t = threadIdx.x;
   for (int i = t; i < k; i += RT_ROWS) {
     ld[i] = J.ldiag[i];
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(RT_ROWS) void k_rtilde(Tab tab, const RtJob<T>* __r
   for (int i = 0; i < kpad; ++i) {
     double val = 0.0;
     if (i < k && u < m) {
-      const double rv = (double)J.R[(int64_t)i * m + u];
+      const double rv = (double)J.R[(int64_t)i * rs + u];
       z = (rv - (i > 0 ? ls[i - 1] * z : 0.0)) / ld[i];
       val = z;
     }
@@ -1899,9 +1900,10 @@ namespace {
 template <typename T>
 struct GpBufs {
   T *Q = nullptr, *R = nullptr, *v = nullptr, *r = nullptr, *gv = nullptr, *gm = nullptr,
-    *tsc = nullptr, *G = nullptr;
+    *tsc = nullptr, *G = nullptr, *Gh = nullptr;
   double* gpart = nullptr;
   int64_t ldg = 0;     // 0: no grid-space first pass
+  int64_t ldgh = 0;    // column stride of Gh (W^T Q for B without the grid-space pass)
   double *partial = nullptr, *coef = nullptr, *c2 = nullptr, *amax = nullptr, *ldiag = nullptr,
          *lsub = nullptr;
   // mean solve (double)
@@ -1924,8 +1926,9 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   b.rpbg = cdiv(n, (int64_t)b.nbg);
   // grid-space first pass when the grid is no larger than the data
   b.ldg = m <= n ? cdiv(m, RB) * RB : 0;
+  b.ldgh = (c->B && !b.ldg) ? cdiv(m, RB) * RB : 0;
   size_t tb = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
-                           (size_t)ts + (size_t)b.ldg * k);
+                           (size_t)ts + (size_t)b.ldg * k + (size_t)b.ldgh * k);
   tb = (tb + 255) & ~size_t(255);
   size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP + (b.ldg ? (size_t)64 * LDP : 0));
   if (mean) {
@@ -1950,6 +1953,7 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   b.gv = b.r + ldq;
   b.gm = b.gv + m;
   b.tsc = b.gm + m;
+  if (b.ldgh) b.Gh = b.tsc + ts;
   double* q = (double*)(b.mem + tb);
   b.partial = q;
   b.coef = b.partial + (size_t)nb * LDP;
@@ -2015,7 +2019,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   std::vector<ScatterJob<T>> sc(G);
   std::vector<GatherJob<T>> ga(G);
   std::vector<FillJob<T>> fi(G);
-  std::vector<RtJob<T>> rj(G);
+  std::vector<RtJob<T>> rj(G), bj(G);
+  std::vector<ScatterJob<T>> sch(G);
+  std::vector<int64_t> b_hy(G, 0), b_hsc(G, 0);   // hyper: B rows, scatter node blocks
   std::vector<SumJob> s_coef(G), s_c2(G);
   std::vector<const T*> t_in_probe(G), t_in_step(G);
   std::vector<T*> t_out_probe(G), t_out_step(G), t_scr(G);
@@ -2095,6 +2101,25 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     Rj.split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
     Rj.ctl = c->ctl;
     rj[g] = Rj;
+    if (c->B) {
+      // B = (L^{-1} G^T)^T from G = W^T Q: the grid-space first pass keeps G;
+      // otherwise its columns are scattered after the Lanczos run
+      RtJob<T> Bj = Rj;
+      Bj.R = b.ldg ? b.G : b.Gh;
+      Bj.ld = b.ldg ? b.ldg : b.ldgh;
+      Bj.rt = c->B;
+      Bj.rt_lo = nullptr;
+      Bj.split = 0;
+      bj[g] = Bj;
+      b_hy[g] = cdiv(c->m, RT_ROWS);
+      if (!b.ldg) {
+        ScatterJob<T> Sh = S;
+        Sh.out = b.Gh;
+        Sh.out_js = b.ldgh;
+        sch[g] = Sh;
+        b_hsc[g] = cdiv(c->m, 4);   // as the step's scatter table
+      }
+    }
     s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
     nv1[g] = J.gpath ? -(1 << 20) : 1;   // no first-pass sums on the grid-space path
     if (J.gpath && lz_psum(nb)) {
@@ -2151,7 +2176,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     }
   } clean{s, &A, &bufs, &sm};
   const size_t o_lz = A.add(lz), o_sc = A.add(sc), o_ga = A.add(ga), o_fi = A.add(fi),
-               o_rj = A.add(rj), o_coef = A.add(s_coef), o_c2 = A.add(s_c2);
+               o_rj = A.add(rj), o_coef = A.add(s_coef), o_c2 = A.add(s_c2),
+               o_bj = A.add(bj), o_sch = A.add(sch);
   ToepRun<T> t_probe, t_step;
   toep_prepare<T>(A, t_probe, cs, t_in_probe, js0, t_out_probe, js0, t_scr,
                   std::vector<const Ctl*>(G, nullptr));
@@ -2346,6 +2372,21 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     for (int g = 0; g < G; ++g) b_rt[g] = cdiv(cs[g]->m, RT_ROWS);
     const Tab t_rt = make_tab(b_rt);
     tlaunch("rtilde", k_rtilde<T>, tab_blocks(t_rt), RT_ROWS, 0, s, t_rt, A.at<RtJob<T>>(o_rj));
+  }
+  // --- B = W^T Q L^{-T} for the hyper-parameter gradient (LOVE_FLAG_HYPER) ------
+  {
+    int kh = 0;
+    for (int g = 0; g < G; ++g)
+      if (b_hsc[g]) kh = std::max(kh, cs[g]->k);
+    for (int j = 0; j < kh; ++j) {
+      std::vector<int64_t> b(G);
+      for (int g = 0; g < G; ++g) b[g] = j < cs[g]->k ? b_hsc[g] : 0;
+      launch_scatter<T>(make_tab(b), A.at<ScatterJob<T>>(o_sch), D, j, 0, s, two_st);
+    }
+    const Tab t_hy = make_tab(b_hy);
+    if (tab_blocks(t_hy))
+      tlaunch("rtilde", k_rtilde<T>, tab_blocks(t_hy), RT_ROWS, 0, s, t_hy,
+              A.at<RtJob<T>>(o_bj));
   }
   // The samplers (grid space, need Rt) and the mean solve (needs Q) are
   // independent chains of small kernels: the samplers run on a side stream

@@ -782,13 +782,16 @@ __device__ inline void backward_body(const GridT<T>& g, const T* __restrict__ xs
 // double over the cells around the node (stencil offsets ascending) and, in a
 // cell, over its points in sorted order, so the result does not depend on
 // scheduling.  order / cstart come from sort_points.
-template <typename T, int D, bool ADD>
+// With pscale, row i is taken as fac * pscale[i] * H_i (H then holds u_i).
+template <typename T, int D, bool ADD, typename TH, typename TO>
 __global__ __launch_bounds__(256) void k_grt_gather(GridT<T> g, const T* __restrict__ xs,
                                                     const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ cstart,
-                                                    const float* __restrict__ H, int kpad,
+                                                    const TH* __restrict__ H, int kpad,
                                                     const Ctl* __restrict__ ctl,
-                                                    float* __restrict__ grt) {
+                                                    TO* __restrict__ grt,
+                                                    const double* __restrict__ pscale,
+                                                    double fac) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t node = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
   if (node >= g.mtot) return;
@@ -810,8 +813,9 @@ __global__ __launch_bounds__(256) void k_grt_gather(GridT<T> g, const T* __restr
         if (!(xe == xe)) xe = g.lo[e];
         T sv;
         (void)stencil_at(g, e, xe, sv);
-        const double wv = (double)keys_weight_at<T>(o, sv);
-        const float* hr = H + pt * kpad;
+        double wv = (double)keys_weight_at<T>(o, sv);
+        if (pscale) wv *= fac * pscale[pt];
+        const TH* hr = H + pt * kpad;
         acc0 += wv * (double)hr[lane];
         if (two) acc1 += wv * (double)hr[lane + WAVE];
       }
@@ -847,15 +851,16 @@ __global__ __launch_bounds__(256) void k_grt_gather(GridT<T> g, const T* __restr
           (void)stencil_at(g, e, xe, sv);
           wv *= (double)keys_weight_at<T>(oe[e], sv);
         }
-        const float* hr = H + pt * kpad;
+        if (pscale) wv *= fac * pscale[pt];
+        const TH* hr = H + pt * kpad;
         acc0 += wv * (double)hr[lane];
         if (two) acc1 += wv * (double)hr[lane + WAVE];
       }
     }
   }
   const int keff = ctl->k_eff;
-  if (lane < keff) grt[node * keff + lane] += (float)acc0;
-  if (two && lane + WAVE < keff) grt[node * keff + lane + WAVE] += (float)acc1;
+  if (lane < keff) grt[node * keff + lane] += (TO)acc0;
+  if (two && lane + WAVE < keff) grt[node * keff + lane + WAVE] += (TO)acc1;
 }
 template <typename T, int D, int SPLIT, bool ADD>
 __global__ __launch_bounds__(256) void k_backward(GridT<T> g, const T* __restrict__ xs, int64_t t,
@@ -925,13 +930,15 @@ love_status backward(const love_cache* c, const T* xs, int64_t t, const T* gm, c
     love_status st = sort_points<T>(c, xs, t, order, cst, s);
     if (st == LOVE_OK) {
       const unsigned nbg = (unsigned)cdiv(g.mtot, 256 / WAVE);
-#define LAUNCH_G(D)                                                                                \
-  if (c->add)                                                                                      \
-    tlaunch("grt_gather", k_grt_gather<T, D, true>, nbg, 256, 0, s, g, xs, (const uint32_t*)order, \
-            (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt);                             \
-  else                                                                                             \
-    tlaunch("grt_gather", k_grt_gather<T, D, false>, nbg, 256, 0, s, g, xs,                        \
-            (const uint32_t*)order, (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt);
+#define LAUNCH_G(D)                                                                              \
+  if (c->add)                                                                                    \
+    tlaunch("grt_gather", k_grt_gather<T, D, true, float, float>, nbg, 256, 0, s, g, xs,         \
+            (const uint32_t*)order, (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt,    \
+            (const double*)nullptr, 0.0);                                                        \
+  else                                                                                           \
+    tlaunch("grt_gather", k_grt_gather<T, D, false, float, float>, nbg, 256, 0, s, g, xs,        \
+            (const uint32_t*)order, (const uint32_t*)cst, (const float*)H, c->kpad, ctl, grt,    \
+            (const double*)nullptr, 0.0);
       switch (c->d) {
         case 1: LAUNCH_G(1); break;
         case 2: LAUNCH_G(2); break;
@@ -1228,5 +1235,484 @@ love_status rt_export_f32(const love_cache* c, float* dst, int keff, hipStream_t
   else k_rt_export<float, 0><<<grid, 256, 0, s>>>(c->m, c->rt, nullptr, c->kpad, keff, dst);
   return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
 }
+
+}  // namespace love
+
+namespace love {
+
+// ----------------------------------------------------------------------------
+// Gradient of sum_i g_i var(x*_i) with respect to the hyper-parameters
+// theta = (lengthscale_0 .. lengthscale_{d-1}, outputscale, sigma^2) through
+// the cache.  Every solve Khat^{-1} in the derivative of
+// var_i = w_i^T K w_i - w_i^T K W^T Khat^{-1} W K w_i is taken as the cached
+// Lanczos solve Q L^{-T} L^{-1} Q^T (eq. lanczos_solve, T = L L^T), so
+// z_i = Q L^{-T} u_i with u_i = Rt^T w_i, W^T z_i = B u_i (B = W^T Q L^{-T},
+// Rt = K B), and
+//   d/dtheta sum_i g_i var_i = sum_i g_i dp_i/dtheta + <dK/dtheta B, Y>_F
+//                              + [theta = sigma^2] sum_i g_i ||L^{-T} u_i||^2,
+//   Y = B M - 2 P,  M = sum_i g_i u_i u_i^T (k x k),  P = sum_i g_i w_i u_i^T.
+// (||z_i||^2 = ||L^{-T} u_i||^2 takes Q^T Q = I.)  -2 P is the backward's
+// d var / d Rt; dK/dtheta B is a Kronecker (or block) Toeplitz product with
+// the differentiated axis column.  All sums are per-block partials added in
+// a fixed order.
+// ----------------------------------------------------------------------------
+struct HyperPt {
+  double t4[MAXD][4];   // first four entries of each unscaled axis column T_e
+  double d4[MAXD][4];   // ... of d T_e / d lengthscale_e
+  double s;             // outputscale
+};
+
+__device__ inline double quad4s(const double (&c)[4], const double (&w)[4]) {
+  double q = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) q += w[a] * c[a > b ? a - b : b - a] * w[b];
+  return q;
+}
+
+// per point: u (double, kpad columns) into U, g_i (0 outside the domain) into
+// gw; per block: partial row of sum_i g_i dp_i/dtheta (d + 1 values)
+template <typename T, int D, int SPLIT, int CPL, bool ADD>
+__device__ inline void hyper_points_body(const GridT<T>& g, const T* __restrict__ xs, int64_t t,
+                                         const void* __restrict__ rt,
+                                         const uint16_t* __restrict__ rt_lo, int kpad,
+                                         const T* __restrict__ gv, HyperPt hp,
+                                         double* __restrict__ U, double* __restrict__ gw,
+                                         double* __restrict__ dpp) {
+  __shared__ double red[PPB][MAXD + 1];
+  const int lane = threadIdx.x & (WAVE - 1), sub = lane & (PLQ - 1);
+  const int pl = threadIdx.x / PLQ;
+  const int64_t p = (int64_t)blockIdx.x * PPB + pl;
+  const bool live = p < t;
+  const int64_t pc = live ? p : t - 1;
+  double w[D][4], dw[D][4];
+  int64_t base;
+  int jb[D];
+  const bool ok = point_stencil_j<T, D>(g, xs + pc * D, w, dw, jb, base, false);
+  constexpr int NA = Entries<D, ADD>::N;
+  double u[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) u[q] = 0.0;
+  for (int a = 0; a < NA; ++a) {
+    double wa;
+    int64_t node;
+    stn_entry<T, D, ADD>(g, w, base, jb, a, wa, node);
+    double r[CPL];
+    rt_row<T, SPLIT, CPL>(rt, rt_lo, node * kpad + sub * CPL, r);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) u[q] += wa * r[q];
+  }
+  const double gi = (live && ok) ? (double)gv[p] : 0.0;
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) U[p * kpad + sub * CPL + q] = ok ? u[q] : 0.0;
+    if (sub == 0) gw[p] = gi;
+  }
+  if (sub == 0) {
+    double qd[D], dq[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      qd[e] = quad4s(hp.t4[e], w[e]);
+      dq[e] = quad4s(hp.d4[e], w[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      double v = hp.s * dq[e];
+      if (!ADD) {
+#pragma unroll
+        for (int f = 0; f < D; ++f)
+          if (f != e) v *= qd[f];
+      }
+      red[pl][e] = gi * v;
+    }
+    double ps = ADD ? 0.0 : 1.0;
+#pragma unroll
+    for (int f = 0; f < D; ++f) ps = ADD ? ps + qd[f] : ps * qd[f];
+    red[pl][D] = gi * ps;
+  }
+  __syncthreads();
+  if (threadIdx.x <= D) {
+    double s = 0.0;
+    for (int q = 0; q < PPB; ++q) s += red[q][threadIdx.x];
+    dpp[(int64_t)blockIdx.x * (MAXD + 1) + threadIdx.x] = s;
+  }
+}
+template <typename T, int D, int SPLIT, bool ADD>
+__global__ __launch_bounds__(256) void k_hyper_points(GridT<T> g, const T* __restrict__ xs,
+                                                      int64_t t, const void* __restrict__ rt,
+                                                      const uint16_t* __restrict__ rt_lo, int kpad,
+                                                      const T* __restrict__ gv, HyperPt hp,
+                                                      double* __restrict__ U,
+                                                      double* __restrict__ gw,
+                                                      double* __restrict__ dpp) {
+  if (kpad > 64)
+    hyper_points_body<T, D, SPLIT, 128 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, gv, hp, U, gw, dpp);
+  else
+    hyper_points_body<T, D, SPLIT, 64 / PLQ, ADD>(g, xs, t, rt, rt_lo, kpad, gv, hp, U, gw, dpp);
+}
+
+// M partial of one chunk of HG_CHUNK points: Mp[chunk][a kpad + b] = sum g_i U_ia U_ib.
+// Thread e holds entries e, e + 256, ..; HG_TILE points at a time in LDS.
+constexpr int HG_CHUNK = 1024;
+constexpr int HG_TILE = 32;
+__global__ __launch_bounds__(256) void k_hyper_gram(const double* __restrict__ U,
+                                                    const double* __restrict__ gw, int64_t t,
+                                                    int kpad, double* __restrict__ Mp) {
+  __shared__ double ut[HG_TILE][MAXK];
+  __shared__ double gt[HG_TILE];
+  constexpr int NE = MAXK * MAXK / 256;
+  const int ne = kpad * kpad / 256;
+  double acc[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) acc[q] = 0.0;
+  const int64_t p0 = (int64_t)blockIdx.x * HG_CHUNK;
+  const int64_t p1 = p0 + HG_CHUNK < t ? p0 + HG_CHUNK : t;
+  for (int64_t pb = p0; pb < p1; pb += HG_TILE) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < HG_TILE * kpad; idx += 256) {
+      const int r = idx / kpad, cl = idx - r * kpad;
+      ut[r][cl] = pb + r < p1 ? U[(pb + r) * kpad + cl] : 0.0;
+    }
+    if (threadIdx.x < HG_TILE) gt[threadIdx.x] = pb + threadIdx.x < p1 ? gw[pb + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int r = 0; r < HG_TILE; ++r) {
+      const double gr = gt[r];
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        if (q < ne) {
+          const int e = threadIdx.x + 256 * q, a = e / kpad, b = e - a * kpad;
+          acc[q] += gr * ut[r][a] * ut[r][b];
+        }
+      }
+    }
+  }
+  for (int q = 0; q < ne; ++q)
+    Mp[(int64_t)blockIdx.x * kpad * kpad + threadIdx.x + 256 * q] = acc[q];
+}
+
+// M[e] = sum over chunks of Mp[chunk][e] (chunk order)
+__global__ void k_hyper_gram_sum(const double* __restrict__ Mp, int nch, int ne,
+                                 double* __restrict__ M) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += Mp[(int64_t)c * ne + e];
+  M[e] = s;
+}
+
+// Y[node, b] = sum_{a < keff} B[node, a] M[a, b] + P2[node, b] (b < keff; 0 beyond)
+template <typename T>
+__global__ void k_hyper_y(const T* __restrict__ B, const double* __restrict__ M,
+                          const double* __restrict__ P2, const Ctl* __restrict__ ctl, int64_t m,
+                          int kpad, double* __restrict__ Y) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kpad) return;
+  const int64_t node = idx / kpad;
+  const int b = (int)(idx - node * kpad);
+  const int keff = ctl->k_eff;
+  double y = 0.0;
+  if (b < keff) {
+    for (int a = 0; a < keff; ++a) y += (double)B[node * kpad + a] * M[a * kpad + b];
+    y += P2[node * keff + b];
+  }
+  Y[idx] = y;
+}
+
+// One axis of a Kronecker (or block) Toeplitz product on m x kpad rows:
+// out[node, c] = sum_{|j - i| <= bw} col[|j - i|] in[node + (j - i) stride, c],
+// i the node's index along the axis.  Product grids: axis e of the grid.
+// Additive grids: only the rows of one block [lo_node, hi_node) (one axis's
+// own 1-D grid, stride 1) are formed; the other rows are left as they are.
+template <typename TI>
+__global__ void k_hyper_axis(const TI* __restrict__ in, double* __restrict__ out, int64_t m,
+                             int kpad, int64_t lo_node, int64_t hi_node, int64_t stride, int len,
+                             const double* __restrict__ col, int bw) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kpad) return;
+  const int64_t node = idx / kpad;
+  const int c = (int)(idx - node * kpad);
+  if (node < lo_node || node >= hi_node) return;
+  const int i = (int)(((node - lo_node) / stride) % len);
+  const int j0 = i - bw > 0 ? i - bw : 0, j1 = i + bw < len - 1 ? i + bw : len - 1;
+  double acc = 0.0;
+  for (int jj = j0; jj <= j1; ++jj) {
+    const int dd = jj > i ? jj - i : i - jj;
+    acc += col[dd] * (double)in[(node + (int64_t)(jj - i) * stride) * kpad + c];
+  }
+  out[idx] = acc;
+}
+
+// per-block partials of <a, b> over len values
+__global__ void k_hyper_dot(const double* __restrict__ a, const double* __restrict__ b,
+                            int64_t len, double* __restrict__ part) {
+  const int64_t i0 = (int64_t)blockIdx.x * 256 * 8 + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t i = i0 + 256 * q;
+    if (i < len) s += a[i] * b[i];
+  }
+  s = wave_sum(s);
+  __shared__ double ws[256 / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) ws[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) t += ws[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// The combine step, one block: the sums of the point and dot partials, and
+// sum_i g_i ||L^{-T} u_i||^2 = sum_c x_c^T M x_c with x_c column c of L^{-1}
+// (L from alpha, beta as in the build's Cholesky).  grad: d + 2 values.
+__global__ __launch_bounds__(MAXK) void k_hyper_final(
+    const double* __restrict__ dpp, int nbp, const double* __restrict__ dotp, int nbd,
+    const double* __restrict__ alpha, const double* __restrict__ beta, const Ctl* __restrict__ ctl,
+    const double* __restrict__ M, int kpad, double* __restrict__ X, int d, double s,
+    double* __restrict__ grad) {
+  __shared__ double ld[MAXK], ls[MAXK], qc[MAXK];
+  const int k = ctl->k_eff, tid = threadIdx.x;
+  if (tid == 0) {
+    double prev = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double piv = alpha[i] - prev * prev;
+      ld[i] = sqrt(piv);
+      prev = (i + 1 < k) ? beta[i] / ld[i] : 0.0;
+      ls[i] = prev;
+    }
+  }
+  __syncthreads();
+  // column tid of L^{-1}: x_tid = 1 / l_tid, x_i = -ls_{i-1} x_{i-1} / ld_i (i > tid)
+  if (tid < k) {
+    double x = 0.0;
+    for (int i = 0; i < k; ++i) {
+      x = i < tid ? 0.0 : (i == tid ? 1.0 / ld[i] : -ls[i - 1] * x / ld[i]);
+      X[(int64_t)i * kpad + tid] = x;
+    }
+  }
+  __syncthreads();
+  double q = 0.0;
+  if (tid < k) {
+    for (int a = tid; a < k; ++a) {
+      double y = 0.0;
+      for (int b = tid; b < k; ++b) y += M[a * kpad + b] * X[(int64_t)b * kpad + tid];
+      q += X[(int64_t)a * kpad + tid] * y;
+    }
+  }
+  qc[tid] = tid < k ? q : 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    double noise = 0.0;
+    for (int c = 0; c < k; ++c) noise += qc[c];
+    for (int th = 0; th <= d; ++th) {
+      double pt = 0.0, dt = 0.0;
+      for (int b = 0; b < nbp; ++b) pt += dpp[(int64_t)b * (MAXD + 1) + th];
+      for (int b = 0; b < nbd; ++b) dt += dotp[(int64_t)th * nbd + b];
+      grad[th] = pt + (th < d ? s * dt : dt);
+    }
+    grad[d + 1] = noise;
+  }
+}
+
+static double kernel_value(int kind, double r, double ell) {
+  r = fabs(r);
+  if (kind == LOVE_RBF) return exp(-0.5 * (r / ell) * (r / ell));
+  const double z = sqrt(5.0) * r / ell;
+  return (1.0 + z + z * z / 3.0) * exp(-z);
+}
+static double kernel_dell(int kind, double r, double ell) {
+  r = fabs(r);
+  if (kind == LOVE_RBF) return exp(-0.5 * (r / ell) * (r / ell)) * r * r / (ell * ell * ell);
+  const double z = sqrt(5.0) * r / ell;
+  return z * z * (1.0 + z) * exp(-z) / (3.0 * ell);
+}
+// largest lag whose coefficient still matters in double (|c| > 1e-17 max|c|)
+static int band_of(const std::vector<double>& c) {
+  double mx = 0.0;
+  for (double v : c) mx = std::max(mx, fabs(v));
+  int bw = (int)c.size() - 1;
+  while (bw > 0 && !(fabs(c[bw]) > 1e-17 * mx)) --bw;
+  return bw;
+}
+
+template <typename T>
+love_status hyper_grad(const love_cache* c, const T* xs, int64_t t, const T* gv, double* grad,
+                       hipStream_t s) {
+  const int d = c->d, kpad = c->kpad;
+  const int64_t m = c->m;
+  const double os = c->cfg.outputscale;
+  // host: unscaled axis columns and their lengthscale derivatives
+  std::vector<double> cols;
+  std::vector<int64_t> coff(2 * d);
+  std::vector<int> bws(2 * d);
+  HyperPt hp{};
+  hp.s = os;
+  for (int e = 0; e < d; ++e) {
+    const int L = c->mdim[e];
+    const double h = 1.0 / c->invh[e], ell = c->cfg.lengthscale[e];
+    std::vector<double> tc(L), dc(L);
+    for (int i = 0; i < L; ++i) {
+      tc[i] = kernel_value(c->cfg.kernel, i * h, ell);
+      dc[i] = kernel_dell(c->cfg.kernel, i * h, ell);
+    }
+    for (int a = 0; a < 4; ++a) {
+      hp.t4[e][a] = a < L ? tc[a] : 0.0;
+      hp.d4[e][a] = a < L ? dc[a] : 0.0;
+    }
+    coff[2 * e] = (int64_t)cols.size();
+    bws[2 * e] = band_of(tc);
+    cols.insert(cols.end(), tc.begin(), tc.end());
+    coff[2 * e + 1] = (int64_t)cols.size();
+    bws[2 * e + 1] = band_of(dc);
+    cols.insert(cols.end(), dc.begin(), dc.end());
+  }
+  JobArena A;
+  const size_t o_cols = A.add(cols);
+  love_status st = A.upload(s);
+  if (st != LOVE_OK) return st;
+  const double* dcols = A.at<double>(o_cols);
+  const int64_t tt = t > 0 ? t : 1;
+  const int nbp = (int)cdiv(tt, PPB), nch = (int)cdiv(tt, HG_CHUNK);
+  const int64_t mk = m * kpad;
+  const int nbd = (int)cdiv(mk, 256 * 8);
+  // scratch (doubles unless noted)
+  const size_t n_u = (size_t)tt * kpad, n_g = tt, n_dpp = (size_t)nbp * (MAXD + 1),
+               n_mp = (size_t)nch * kpad * kpad, n_m = (size_t)kpad * kpad,
+               n_dot = (size_t)(d + 1) * nbd, n_x = (size_t)kpad * kpad;
+  const size_t dbytes = sizeof(double) * (n_u + n_g + n_dpp + n_mp + n_m + 3 * (size_t)mk +
+                                          n_dot + n_x);
+  const size_t p2bytes = sizeof(double) * (size_t)mk;
+  const int64_t nv = c->add ? (int64_t)d * tt : tt;
+  const size_t obytes = (sizeof(uint32_t) * (size_t)nv + 255) & ~size_t(255);
+  const size_t cbytes = sizeof(uint32_t) * ((size_t)c->ctot + 1);
+  if (nv >= (int64_t(1) << 31)) {
+    A.release(s);
+    return LOVE_EINVAL;
+  }
+  char* buf = (char*)ws_alloc(dbytes + p2bytes + obytes + cbytes, s);
+  if (!buf) {
+    A.release(s);
+    return LOVE_ENOMEM;
+  }
+  double* U = (double*)buf;
+  double* gw = U + n_u;
+  double* dpp = gw + n_g;
+  double* Mp = dpp + n_dpp;
+  double* M = Mp + n_mp;
+  double* Y = M + n_m;
+  double* V1 = Y + mk;
+  double* V2 = V1 + mk;
+  double* dotp = V2 + mk;
+  double* X = dotp + n_dot;
+  double* P2 = (double*)(buf + dbytes);
+  uint32_t* order = (uint32_t*)(buf + dbytes + p2bytes);
+  uint32_t* cst = (uint32_t*)(buf + dbytes + p2bytes + obytes);
+  const Ctl* ctl = c->ctl;
+  GridT<T> g = make_grid<T>(c);
+  const bool split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
+  LOVE_HIP_TRY(hipMemsetAsync(P2, 0, sizeof(double) * (size_t)mk, s));
+  if (t > 0) {
+#define LAUNCH_HP(D, ADD)                                                                         \
+  if (split)                                                                                      \
+    tlaunch("hyper_points", k_hyper_points<T, D, 1, ADD>, nbp, 256, 0, s, g, xs, t, c->rt,        \
+            (const uint16_t*)c->rt_lo, kpad, gv, hp, U, gw, dpp);                                 \
+  else                                                                                            \
+    tlaunch("hyper_points", k_hyper_points<T, D, 0, ADD>, nbp, 256, 0, s, g, xs, t, c->rt,        \
+            (const uint16_t*)nullptr, kpad, gv, hp, U, gw, dpp);
+#define LAUNCH_HPA(D)   \
+  if (c->add) {         \
+    LAUNCH_HP(D, true)  \
+  } else {              \
+    LAUNCH_HP(D, false) \
+  }
+    switch (d) {
+      case 1: LAUNCH_HPA(1); break;
+      case 2: LAUNCH_HPA(2); break;
+      case 3: LAUNCH_HPA(3); break;
+      case 4: LAUNCH_HPA(4); break;
+    }
+#undef LAUNCH_HPA
+#undef LAUNCH_HP
+    k_hyper_gram<<<nch, 256, 0, s>>>(U, gw, t, kpad, Mp);
+    // -2 P = -2 sum_i g_i w_i u_i^T: the backward's deterministic per-node
+    // gather over the cell-sorted points, here in double from U and g
+    st = sort_points<T>(c, xs, t, order, cst, s);
+    if (st != LOVE_OK) {
+      ws_free(buf, s);
+      A.release(s);
+      return st;
+    }
+    const unsigned nbg = (unsigned)cdiv(m, 256 / WAVE);
+#define LAUNCH_G(D)                                                                            \
+  if (c->add)                                                                                  \
+    k_grt_gather<T, D, true, double, double><<<nbg, 256, 0, s>>>(                              \
+        g, xs, (const uint32_t*)order, (const uint32_t*)cst, (const double*)U, kpad, ctl, P2,  \
+        (const double*)gw, -2.0);                                                              \
+  else                                                                                         \
+    k_grt_gather<T, D, false, double, double><<<nbg, 256, 0, s>>>(                             \
+        g, xs, (const uint32_t*)order, (const uint32_t*)cst, (const double*)U, kpad, ctl, P2,  \
+        (const double*)gw, -2.0);
+    switch (d) {
+      case 1: LAUNCH_G(1); break;
+      case 2: LAUNCH_G(2); break;
+      case 3: LAUNCH_G(3); break;
+      case 4: LAUNCH_G(4); break;
+    }
+#undef LAUNCH_G
+  } else {
+    LOVE_HIP_TRY(hipMemsetAsync(dpp, 0, sizeof(double) * n_dpp, s));
+    LOVE_HIP_TRY(hipMemsetAsync(Mp, 0, sizeof(double) * n_mp, s));
+  }
+  const int ne = kpad * kpad;
+  k_hyper_gram_sum<<<(unsigned)cdiv(ne, 256), 256, 0, s>>>(Mp, nch, ne, M);
+  const unsigned nbm = (unsigned)cdiv(mk, 256);
+  k_hyper_y<T><<<nbm, 256, 0, s>>>((const T*)c->B, M, P2, ctl, m, kpad, Y);
+  // <dK/dtheta B, Y> for theta = lengthscale_e (e < d) and the outputscale (e = d)
+  for (int th = 0; th <= d; ++th) {
+    if (c->add) {
+      // block form: theta = lengthscale_e forms block e with d T_e; the
+      // outputscale's K / s forms every block with its own T_f
+      LOVE_HIP_TRY(hipMemsetAsync(V1, 0, sizeof(double) * (size_t)mk, s));
+      for (int f = 0; f < d; ++f) {
+        if (th < d && f != th) continue;
+        const int use = th < d ? 2 * f + 1 : 2 * f;
+        k_hyper_axis<T><<<nbm, 256, 0, s>>>((const T*)c->B, V1, m, kpad, c->aoff[f],
+                                            c->aoff[f] + c->mdim[f], 1, c->mdim[f],
+                                            dcols + coff[use], bws[use]);
+      }
+      k_hyper_dot<<<nbd, 256, 0, s>>>(V1, Y, mk, dotp + (size_t)th * nbd);
+    } else {
+      const double* src = nullptr;   // nullptr: read B
+      double* dst = V1;
+      int64_t stride = 1;
+      std::vector<int64_t> strides(d);
+      for (int f = d - 1; f >= 0; --f) {
+        strides[f] = stride;
+        stride *= c->mdim[f];
+      }
+      for (int f = 0; f < d; ++f) {
+        const int use = (th == f) ? 2 * f + 1 : 2 * f;
+        if (src)
+          k_hyper_axis<double><<<nbm, 256, 0, s>>>(src, dst, m, kpad, 0, m, strides[f], c->mdim[f],
+                                                   dcols + coff[use], bws[use]);
+        else
+          k_hyper_axis<T><<<nbm, 256, 0, s>>>((const T*)c->B, dst, m, kpad, 0, m, strides[f],
+                                              c->mdim[f], dcols + coff[use], bws[use]);
+        src = dst;
+        dst = (dst == V1) ? V2 : V1;
+      }
+      k_hyper_dot<<<nbd, 256, 0, s>>>(src, Y, mk, dotp + (size_t)th * nbd);
+    }
+  }
+  k_hyper_final<<<1, MAXK, 0, s>>>(dpp, nbp, dotp, nbd, c->alpha, c->beta, ctl, M, kpad, X, d, os,
+                                   grad);
+  ws_free(buf, s);
+  A.release(s);
+  return hipGetLastError() == hipSuccess ? LOVE_OK : LOVE_EHIP;
+}
+template love_status hyper_grad<float>(const love_cache*, const float*, int64_t, const float*, double*, hipStream_t);
+template love_status hyper_grad<double>(const love_cache*, const double*, int64_t, const double*, double*, hipStream_t);
 
 }  // namespace love
