@@ -176,17 +176,10 @@ def stored_traffic(scope):
                        write_kib * prof["scale"]["WRITE_SIZE"]))
 
 
-def cpu_baseline(P, gpu_mean, gpu_var, nq):
-    """The FP64 oracle, as written, on a bounded sample of the same workload."""
+def _oracle_sample_run(O, P, spec, x64, y64, nq, ns_draw):
+    """One timed pass of the oracle over the bounded sample: full build, the
+    sampler, nq of the t variance queries and ns_draw of the sample rows."""
     import numpy as np
-    from oracle import love_fp64 as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
-    spec = O.Spec(P.m, P.lo, P.hi, P.kernel, P.lengthscale, P.outputscale, P.noise)
-    x64, y64 = P.x.astype(np.float64), P.y.astype(np.float64)
     t0 = time.perf_counter()
     oc = O.love_build(x64, y64, spec, P.k, cg_tol=1e-6, cg_maxit=5000)
     t1 = time.perf_counter()
@@ -196,13 +189,72 @@ def cpu_baseline(P, gpu_mean, gpu_var, nq):
     xq = P.xs[idx].astype(np.float64)
     m_ref, v_ref = O.love_predict(oc, xq)
     t3 = time.perf_counter()
-    ns_draw = 500
     O.love_sample(oc, osm, P.xs_sample[:ns_draw].astype(np.float64), P.z.astype(np.float64))
     t4 = time.perf_counter()
     ts = P.xs_sample.shape[0]
     total = (t1 - t0) + (t2 - t1) + (t3 - t2) * P.t / nq + (t4 - t3) * ts / ns_draw
+    times = {"build_s": t1 - t0, "sampler_s": t2 - t1, "query_s": t3 - t2, "draw_s": t4 - t3}
+    return oc, osm, idx, m_ref, v_ref, total, times
+
+
+def sample_accuracy(O, P, spec, oc, osm, samples):
+    """The sample-accuracy metric of the sampling experiments (Sec. 4, Table 3):
+    element-wise MAE between the covariance of the GPU's s posterior draws at
+    the t sample points and (a) the covariance they are drawn from in the
+    oracle, W* S S^T W*^T, (b) the oracle's LOVE predictive covariance
+    W* (K - Rt Rt^T) W*^T.  Beside them, the Monte Carlo level of (a): the
+    mean over entries of sqrt((S_ii S_jj + S_ij^2) / s)."""
+    import numpy as np
+    xs = P.xs_sample.astype(np.float64)
+    Ws = O.interp_matrix(xs, spec)
+    F = Ws @ osm.S
+    implied = F @ F.T
+    U = Ws @ oc.Rt
+    WK = np.asarray(Ws @ O.K_dense(spec))
+    love_cov = np.asarray(Ws @ WK.T) - U @ U.T
+    del WK
+    s = samples.shape[1]
+    mae_implied = O.sample_covariance_mae(samples, implied)
+    mae_love = O.sample_covariance_mae(samples, love_cov)
+    d = np.diag(implied)
+    mc = float(np.mean(np.sqrt((np.outer(d, d) + implied ** 2) / s)))
+    return {"samples": int(s), "points": int(xs.shape[0]),
+            "cov_mae_vs_implied": mae_implied, "cov_mae_vs_love_covariance": mae_love,
+            "monte_carlo_level": mc,
+            "implied_vs_love_covariance_mae": float(np.mean(np.abs(implied - love_cov))),
+            "reference": "FP64 oracle at the same k and k' (Sec. 3.3 sampler)"}
+
+
+def cpu_baseline(P, gpu_mean, gpu_var, nq, samples=None):
+    """The FP64 oracle, as written, on a bounded sample of the same workload:
+    on all of this host's cores, then again on one core.  Also the accuracy
+    of the GPU's variances, means and (if given) samples against it."""
+    import numpy as np
+    from oracle import love_fp64 as O
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count() or 1
+    spec = O.Spec(P.m, P.lo, P.hi, P.kernel, P.lengthscale, P.outputscale, P.noise)
+    x64, y64 = P.x.astype(np.float64), P.y.astype(np.float64)
+    ns_draw = 500
+    oc, osm, idx, m_ref, v_ref, total, times = _oracle_sample_run(O, P, spec, x64, y64, nq, ns_draw)
+    t0, t1, t2 = 0.0, times["build_s"], times["build_s"] + times["sampler_s"]
+    t3 = t2 + times["query_s"]
+    t4 = t3 + times["draw_s"]
+    ts = P.xs_sample.shape[0]
+    one_core = None
+    if threadpool_limits is not None:
+        nq1 = max(1000, nq // 4)
+        with threadpool_limits(limits=1):
+            _, _, _, _, _, total1, times1 = _oracle_sample_run(O, P, spec, x64, y64, nq1, ns_draw)
+        one_core = {"value": P.t / total1, "unit": "predictive variances/s", "cores": 1,
+                    "sample": f"as the all-core sample with {nq1} queries",
+                    **{k_: round(v_, 3) for k_, v_ in times1.items()}}
     # accuracy of the GPU outputs at the sampled points (FP64 oracle, same k)
-    p = O.prior_var(xq, spec)
+    p = O.prior_var(P.xs[idx].astype(np.float64), spec)
     gv = gpu_var[idx].astype(np.float64)
     gm = gpu_mean[idx].astype(np.float64)
     dv = np.abs(gv - v_ref)
@@ -226,7 +278,54 @@ def cpu_baseline(P, gpu_mean, gpu_var, nq):
                    f"full count"),
         "build_s": t1 - t0, "sampler_s": t2 - t1,
     }
+    if one_core is not None:
+        base["one_core"] = one_core
+    if samples is not None:
+        acc["samples"] = sample_accuracy(O, P, spec, oc, osm, samples)
     return base, acc
+
+
+def forms_accuracy(O, side):
+    """Errors of each form's GPU outputs against the FP64 oracle (same k):
+    e_p = |dvar| / prior, e_v = |dvar| / var (max, p99, median), SMAE of the
+    variances (mean |dvar| / Var(y)), mean error max / RMS(y).  The 2-D and
+    4-D references are the oracle's answers stored by
+    tests/golden/make_fullsize.py (its mean solve needs thousands of CG
+    iterations there); the 1-D FP64 and additive ones are computed here."""
+    import numpy as np
+    out = {}
+    for name, r in side.items():
+        P = r["P"]
+        spec = O.Spec(P.m, P.lo, P.hi, P.kernel, P.lengthscale, P.outputscale, P.noise, P.additive)
+        y64 = P.y.astype(np.float64)
+        idx = r["idx"]
+        if r.get("golden") is not None:
+            G = r["golden"]
+            m_ref, v_ref, p = G["mean"], G["var"], G["prior"]
+            ref_src = "stored FP64 oracle values (tests/golden)"
+        else:
+            oc = O.love_build(P.x.astype(np.float64), y64, spec, P.k, cg_tol=1e-10, cg_maxit=20000)
+            xq = P.xs[idx].astype(np.float64)
+            m_ref, v_ref = O.love_predict(oc, xq)
+            p = O.prior_var(xq, spec)
+            ref_src = "FP64 oracle computed here"
+        dv = np.abs(r["var"] - v_ref)
+        acc = {"points": int(idx.shape[0]), "e_p_max": float(np.max(dv / p)),
+               "e_v_max": float(np.max(dv / v_ref)),
+               "e_v_p99": float(np.percentile(dv / v_ref, 99)),
+               "e_v_median": float(np.median(dv / v_ref)),
+               "smae_var": float(np.mean(dv) / np.var(y64)),
+               "mean_err_max_over_rms_y": float(np.max(np.abs(r["mean"] - m_ref))
+                                                / np.sqrt(np.mean(y64 ** 2))),
+               "reference": ref_src}
+        if r.get("dmean") is not None:
+            G = r["golden"]
+            acc["dmean_err_rel_max"] = float(np.max(np.abs(r["dmean"] - G["dmean"]))
+                                             / np.max(np.abs(G["dmean"])))
+            acc["dvar_err_over_term_size_max"] = float(np.max(np.abs(r["dvar"] - G["dvar"])
+                                                              / G["dvar_scale"]))
+        out[name] = acc
+    return out
 
 
 def dominant_bw(P, dbl):
@@ -382,16 +481,22 @@ def lanczos_large_section(B, torch, dev, n=1 << 21):
                          "achieved_gbps": round(gbps, 1), "frac_hbm": round(gbps / HBM_PEAK_GBS, 3)}}
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
 def forms_section(B, WL, torch, dev, reps=3):
     """The other forms of the path at their full sizes, timed on this GPU (median
     of `reps` after one warm-up, host clock around synchronised calls):
     fp64 (1-D, n = 1000, m = 100, k = 50, 1000 variances: latency-bound, its
-    time is the figure), bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6 variances),
-    differentiable (4-D product Matern-5/2, n = 2e5, m = 20^4, k = 64, forward
-    and backward at 262,144 points) and additive (Sec. 3.4: sum of four 1-D RBF
-    components, n = 1e5, m = 100 per axis, k = 50, 1e6 variances)."""
+    time is the figure), bf16split (2-D, n = 5e5, m = 128^2, k = 100, 2e6
+    variances) beside the plain FP32 form on the same workload, differentiable
+    (4-D product Matern-5/2, n = 2e5, m = 20^4, k = 64, forward and backward at
+    262,144 points) and additive (Sec. 3.4: sum of four 1-D RBF components,
+    n = 1e5, m = 100 per axis, k = 50, 1e6 variances).  Returns the timing rows
+    and, per form, its outputs at the points its accuracy is measured on."""
     import statistics
-    out = {}
+    import numpy as np
+    out, side = {}, {}
 
     def timed(fn):
         fn()
@@ -406,9 +511,16 @@ def forms_section(B, WL, torch, dev, reps=3):
                 r.free()
         return statistics.median(ts)
 
-    for name, idx in (("fp64_1d_small", 1), ("bf16split_2d", 3), ("differentiable_4d", 4),
-                      ("additive_4d", 0)):
+    def host(t):
+        return t.detach().cpu().numpy().astype(np.float64)
+
+    forms = (("fp64_1d_small", 1, None, None), ("bf16split_2d", 3, None, "c3_full.npz"),
+             ("fp32_2d", 3, "fp32", "c3_full.npz"), ("differentiable_4d", 4, None, "c4_full.npz"),
+             ("additive_4d", 0, None, None))
+    for name, idx, prec, gold in forms:
         P = WL.config(idx) if idx else WL.additive_config()
+        if prec is not None:
+            P.precision = prec
         cfg = B.config_struct(P.d, list(P.m), list(P.lo), list(P.hi), kernel=P.kernel,
                               lengthscale=list(P.lengthscale), noise=P.noise, k=P.k,
                               precision=P.precision,
@@ -429,15 +541,34 @@ def forms_section(B, WL, torch, dev, reps=3):
         inf = c.info()
         rec.update({"k_eff": inf.k_eff, "cg_iters": inf.cg_iters,
                     "cg_converged": not (inf.status_flags & 16)})
+        G = None
+        if gold is not None and os.path.exists(os.path.join(GOLDEN_DIR, gold)):
+            G = dict(np.load(os.path.join(GOLDEN_DIR, gold), allow_pickle=False))
+            sel = G["idx"]
+        elif P.t <= 2000:
+            sel = np.arange(P.t)
+        else:
+            sel = np.sort(np.random.default_rng(11).choice(P.t, 2000, replace=False))
+        sel_t = torch.from_numpy(sel).to(dev)
+        sd = {"P": P, "idx": sel, "golden": G, "mean": host(mu[sel_t]), "var": host(var[sel_t])}
         if idx == 4:
             gm = torch.ones(P.t, device=dev, dtype=x.dtype)
             gv = torch.ones(P.t, device=dev, dtype=x.dtype)
             t_bwd = timed(lambda: c.predict_backward(xs, gm, gv))
             rec["backward_ms"] = round(t_bwd * 1e3, 4)
             rec["backward_over_forward"] = round(t_bwd / t_fwd, 2)
+            xsel = xs[sel_t].contiguous()
+            one = torch.ones(sel.shape[0], device=dev, dtype=x.dtype)
+            zero = torch.zeros_like(one)
+            sd["dmean"] = host(c.predict_backward(xsel, one, zero)[0])
+            sd["dvar"] = host(c.predict_backward(xsel, zero, one)[0])
         c.free()
         out[name] = rec
-    return out
+        side[name] = sd
+    b, f = out["bf16split_2d"], out["fp32_2d"]
+    out["bf16split_vs_fp32_2d"] = {"build_ratio": round(b["build_ms"] / f["build_ms"], 3),
+                                   "predict_ratio": round(b["predict_ms"] / f["predict_ms"], 3)}
+    return out, side
 
 
 def main():
@@ -463,7 +594,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     if a.forms_only:
-        print(json.dumps({"forms": forms_section(B, WL, torch, dev),
+        forms, _ = forms_section(B, WL, torch, dev)
+        print(json.dumps({"forms": forms,
                           "mvm_large": mvm_large_section(B, torch, dev),
                           "lanczos_large": lanczos_large_section(B, torch, dev)}), flush=True)
         return
@@ -578,6 +710,7 @@ def main():
     mvm_bytes = 4 * P.n * P.d * 2 + 4 * P.n * 3 + 16 * m_tot
     gpu_mean = mu.cpu().numpy()
     gpu_var = var.cpu().numpy()
+    gpu_samples = smp.cpu().numpy()
     info = c.info()
     c.free()
 
@@ -638,14 +771,19 @@ def main():
     }
     if not a.no_batched:
         out["batched"] = batched_section(B, WL, torch, dev)
+    side = None
     if not a.no_forms:
-        out["forms"] = forms_section(B, WL, torch, dev)
+        out["forms"], side = forms_section(B, WL, torch, dev)
         out["mvm_large"] = mvm_large_section(B, torch, dev)
         out["lanczos_large"] = lanczos_large_section(B, torch, dev)
     if not a.no_cpu_baseline:
-        base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries)
+        base, acc = cpu_baseline(P, gpu_mean, gpu_var, a.cpu_queries, samples=gpu_samples)
         out["cpu_baseline"] = base
         out["accuracy_vs_fp64_oracle"] = acc
+        if side is not None:
+            from oracle import love_fp64 as O
+            for name, e in forms_accuracy(O, side).items():
+                out["forms"][name]["accuracy"] = e
     print(json.dumps(out), flush=True)
 
 
