@@ -47,7 +47,8 @@ struct ScatterJob {
   T* out;                     // m
   int64_t out_js;
   const Ctl* ctl;
-  T* cellp;                   // d >= 3: 4^d x ctot partial products (scatter_scratch_bytes)
+  T* cellp;                   // two-stage W^T v scratch (scatter_scratch_bytes): d >= 3 the
+                              // tiles' extended-box node partials, else 4^d x ctot products
 };
 
 // out = W kg + sigma2 * vsig (vsig nullable)

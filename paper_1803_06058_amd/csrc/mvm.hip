@@ -271,8 +271,24 @@ int scatter_kinds(const std::vector<love_cache*>& cs) {
     k |= c->add ? SCATTER_ADDITIVE : scatter_two_stage(c) ? SCATTER_TWO_STAGE : SCATTER_NODES;
   return k;
 }
+// d >= 3: cells in tiles of TC^d, each tile's node partials over its
+// (TC + 3)^d extended node box
+template <int D>
+struct TileShape {
+  static constexpr int TC = D == 4 ? 4 : 6;   // cells per axis of a tile
+  static constexpr int EXT = TC + 3;          // nodes per axis a tile's cells touch
+  static constexpr int NCELL = D == 4 ? 256 : 216;
+  static constexpr int NEXT = D == 4 ? 2401 : 729;
+};
+static int64_t scatter_tiles(const love_cache* c, int tc) {
+  int64_t nt = 1;
+  for (int e = 0; e < c->d; ++e) nt *= cdiv(c->mdim[e] - 3, tc);
+  return nt;
+}
 size_t scatter_scratch_bytes(const love_cache* c, size_t elem) {
   if (!scatter_two_stage(c)) return 0;
+  if (c->d == 4) return (size_t)scatter_tiles(c, TileShape<4>::TC) * TileShape<4>::NEXT * elem;
+  if (c->d == 3) return (size_t)scatter_tiles(c, TileShape<3>::TC) * TileShape<3>::NEXT * elem;
   return ((size_t)1 << (2 * c->d)) * (size_t)c->ctot * elem;
 }
 
@@ -414,6 +430,297 @@ __global__ __launch_bounds__(256) void k_scatter_cells(Tab tab,
   }
 }
 
+// ----------------------------------------------------------------------------
+// W^T v for d >= 3 by tiles: a block takes a tile of TC^d stencil cells and
+// forms the tile's contribution to the (TC + 3)^d nodes those cells touch.
+// The tile's rows (TC^(d-1) contiguous runs of the cell-sorted order) are
+// staged in LDS once.  Then, for a chunk of OC stencil offsets at a time,
+// one thread per cell forms P[o][c] = sum over its rows of
+// val * prod_e w_e[o_e] into LDS, and each thread adds, for the pencils of
+// box nodes along the last axis it owns, P of the cell u - o over the
+// chunk's offsets (o ascending), in registers.  The box partials go out once
+// per tile (a few MB instead of 4^d x cells values); k_scatter_halo adds,
+// per node, the partials of the (at most 2 per axis) tiles whose boxes hold
+// it, tiles in order.  Both orders are fixed: deterministic.
+// ----------------------------------------------------------------------------
+constexpr int ST_RMAX = 1024;   // rows of a tile staged in LDS (more: read from memory)
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter_tiles(Tab tab,
+                                                       const ScatterJob<T>* __restrict__ jobs,
+                                                       int j, int mode) {
+  using TS = TileShape<D>;
+  constexpr int TC = TS::TC, EXT = TS::EXT, NCELL = TS::NCELL, NEXT = TS::NEXT;
+  constexpr int NO = 1 << (2 * D);
+  constexpr int OCMAX = 32768 / (NCELL * (int)sizeof(T));
+  constexpr int OC = OCMAX >= 64 ? 64 : (OCMAX >= 32 ? 32 : 16);
+  static_assert(OC <= NO && NO % OC == 0, "chunks tile the offsets");
+  constexpr int NRUN = NCELL / TC;                 // runs of TC cells along the last axis
+  constexpr int NPEN = NEXT / EXT;                 // pencils of EXT box nodes along it
+  constexpr int PPT = (NPEN + 255) / 256;          // pencils per thread
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode) || !J.cellp) return;
+  const GridT<T>& g = J.g;
+  int nt[D];
+  int64_t ntot = 1;
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    nt[e] = (g.cells[e] + TC - 1) / TC;
+    ntot *= nt[e];
+  }
+  const int64_t tile = lb;
+  if (tile >= ntot) return;
+  int t0[D];   // first cell of the tile per axis
+  {
+    int64_t rem = tile;
+#pragma unroll
+    for (int e = D - 1; e >= 0; --e) {
+      t0[e] = (int)(rem % nt[e]) * TC;
+      rem /= nt[e];
+    }
+  }
+  __shared__ T Pl[OC][NCELL];
+  __shared__ T xr[ST_RMAX][D + 1];   // staged rows: coordinates and value
+  __shared__ int run_off[NRUN + 1];
+  __shared__ int run_row[NRUN];      // first sorted row of each run
+  const int tid = threadIdx.x;
+  const int ncl = min(TC, g.cells[D - 1] - t0[D - 1]);   // cells of each run inside the grid
+  const T* __restrict__ x = J.x;
+  const T* __restrict__ v = J.v + (int64_t)j * J.v_js;
+  const T* __restrict__ v2 = J.v2;
+  const bool comb = (mode & 4) && v2;
+  const T ratio = comb ? (T)J.ctl->ratio : T(0);
+  // runs: run k = cells (k's first-axes cells, t0 .. t0 + ncl - 1 on the last axis)
+  if (tid < NRUN) {
+    int rem = tid;
+    int64_t c0 = 0;
+    bool in = true;
+#pragma unroll
+    for (int e = D - 2; e >= 0; --e) {
+      const int ce = t0[e] + rem % TC;
+      rem /= TC;
+      in = in && ce < g.cells[e];
+      c0 += (int64_t)ce * g.cstride[e];
+    }
+    c0 += t0[D - 1];
+    const int a = in ? J.cell_start[c0] : 0, b = in ? J.cell_start[c0 + ncl] : 0;
+    run_row[tid] = a;
+    run_off[tid + 1] = b - a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    run_off[0] = 0;
+    for (int k = 0; k < NRUN; ++k) run_off[k + 1] += run_off[k];
+  }
+  __syncthreads();
+  const int nrow = run_off[NRUN];
+  const bool staged = nrow <= ST_RMAX;
+  if (staged) {
+    for (int i = tid; i < nrow; i += 256) {
+      int lo = 0, hi = NRUN - 1;   // run holding staged row i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (run_off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      const int64_t r = run_row[lo] + (i - run_off[lo]);
+#pragma unroll
+      for (int e = 0; e < D; ++e) xr[i][e] = x[r * D + e];
+      xr[i][D] = comb ? (T)(v[r] + ratio * v2[r]) : v[r];
+    }
+  }
+  // this thread's cell: its rows, staged positions (or sorted rows) [rb, re)
+  int cl[D];
+  int rb = 0, re = 0;
+  int64_t gb = 0;
+  if (tid < NCELL) {
+    int rem = tid;
+#pragma unroll
+    for (int e = D - 1; e >= 0; --e) {
+      cl[e] = rem % TC;
+      rem /= TC;
+    }
+    const int k = tid / TC;   // run (the last axis is fastest)
+    bool in = t0[D - 1] + cl[D - 1] < g.cells[D - 1];
+    int64_t cidx = 0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      in = in && t0[e] + cl[e] < g.cells[e];
+      cidx += (int64_t)(t0[e] + cl[e]) * g.cstride[e];
+    }
+    if (in) {
+      const int a = J.cell_start[cidx], b = J.cell_start[cidx + 1];
+      gb = a;
+      rb = a - run_row[k] + run_off[k];
+      re = rb + (b - a);
+    }
+  }
+  T cb[D];
+#pragma unroll
+  for (int e = 0; e < D; ++e) cb[e] = (T)(t0[e] + (tid < NCELL ? cl[e] : 0));
+  // pencils owned: q -> pencil tid + 256 q, box coordinates of its first D-1 axes
+  T pacc[PPT][EXT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q)
+#pragma unroll
+    for (int b = 0; b < EXT; ++b) pacc[q][b] = T(0);
+  __syncthreads();
+  for (int oc0 = 0; oc0 < NO; oc0 += OC) {
+    // phase 1: this cell's P[o] for o in [oc0, oc0 + OC)
+    if (tid < NCELL) {
+      T acc[OC];
+#pragma unroll
+      for (int q = 0; q < OC; ++q) acc[q] = T(0);
+      for (int i = rb; i < re; ++i) {
+        T xv[D + 1];
+        if (staged) {
+#pragma unroll
+          for (int e = 0; e <= D; ++e) xv[e] = xr[i][e];
+        } else {
+          const int64_t r = gb + (i - rb);
+#pragma unroll
+          for (int e = 0; e < D; ++e) xv[e] = x[r * D + e];
+          xv[D] = comb ? (T)(v[r] + ratio * v2[r]) : v[r];
+        }
+        T w[D][4];
+#pragma unroll
+        for (int e = 0; e < D; ++e) keys_weights<T>((xv[e] - g.lo[e]) * g.invh[e] - cb[e], w[e]);
+#pragma unroll
+        for (int q = 0; q < OC; ++q) {
+          const int o = oc0 + q;
+          T prod = xv[D];
+#pragma unroll
+          for (int e = 0; e < D; ++e) prod *= w[e][(o >> (2 * (D - 1 - e))) & 3];
+          acc[q] += prod;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < OC; ++q) Pl[q][tid] = acc[q];
+    }
+    __syncthreads();
+    // phase 2: each owned pencil (box coordinates b_0 .. b_{D-2}, all EXT of
+    // b_{D-1}) adds P[o][cell b - o]; the chunk fixes or ranges the leading
+    // offset digits, the last digit runs over 0..3 (OC >= 16)
+    int dlo[D - 1], dhi[D - 1];
+#pragma unroll
+    for (int e = 0; e < D - 1; ++e) {
+      const int p4 = 1 << (2 * (D - 1 - e));
+      if (OC >= 4 * p4) {
+        dlo[e] = 0;
+        dhi[e] = 3;
+      } else if (OC >= p4) {
+        dlo[e] = (oc0 / p4) & 3;
+        dhi[e] = dlo[e] + OC / p4 - 1;
+      } else {
+        dlo[e] = dhi[e] = (oc0 / p4) & 3;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int pen = tid + 256 * q;
+      if (pen >= NPEN) break;
+      int bl[D - 1];
+      {
+        int rem = pen;
+#pragma unroll
+        for (int e = D - 2; e >= 0; --e) {
+          bl[e] = rem % EXT;
+          rem /= EXT;
+        }
+      }
+      int lo[D - 1], hi[D - 1];
+#pragma unroll
+      for (int e = 0; e < D - 1; ++e) {
+        lo[e] = max(dlo[e], bl[e] - TC + 1);
+        hi[e] = min(dhi[e], bl[e]);
+      }
+      if constexpr (D == 4) {
+        for (int d0 = lo[0]; d0 <= hi[0]; ++d0)
+          for (int d1 = lo[1]; d1 <= hi[1]; ++d1)
+            for (int d2 = lo[2]; d2 <= hi[2]; ++d2) {
+              const int qo = d0 * 64 + d1 * 16 + d2 * 4 - oc0;
+              const int cb3 = (((bl[0] - d0) * TC + (bl[1] - d1)) * TC + (bl[2] - d2)) * TC;
+#pragma unroll
+              for (int d3 = 0; d3 < 4; ++d3)
+#pragma unroll
+                for (int c3 = 0; c3 < TC; ++c3) pacc[q][c3 + d3] += Pl[qo + d3][cb3 + c3];
+            }
+      } else {
+        for (int d0 = lo[0]; d0 <= hi[0]; ++d0)
+          for (int d1 = lo[1]; d1 <= hi[1]; ++d1) {
+            const int qo = d0 * 16 + d1 * 4 - oc0;
+            const int cb2 = ((bl[0] - d0) * TC + (bl[1] - d1)) * TC;
+#pragma unroll
+            for (int d2 = 0; d2 < 4; ++d2)
+#pragma unroll
+              for (int c2 = 0; c2 < TC; ++c2) pacc[q][c2 + d2] += Pl[qo + d2][cb2 + c2];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  T* __restrict__ NP = J.cellp + tile * NEXT;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int pen = tid + 256 * q;
+    if (pen >= NPEN) break;
+#pragma unroll
+    for (int b = 0; b < EXT; ++b) NP[pen * EXT + b] = pacc[q][b];
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter_halo(Tab tab,
+                                                      const ScatterJob<T>* __restrict__ jobs,
+                                                      int j, int mode) {
+  using TS = TileShape<D>;
+  constexpr int TC = TS::TC, EXT = TS::EXT, NEXT = TS::NEXT;
+  int gp, lb;
+  if (!tab_find(tab, blockIdx.x, gp, lb)) return;
+  const ScatterJob<T>& J = jobs[gp];
+  if (ctl_skip(J.ctl, mode) || !J.cellp) return;
+  const GridT<T>& g = J.g;
+  const int64_t u = (int64_t)lb * 256 + threadIdx.x;
+  if (u >= g.mtot) return;
+  int ue[D], nt[D], tlo[D], thi[D];
+  {
+    int64_t rem = u;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      ue[e] = (int)(rem / g.nstride[e]);
+      rem -= (int64_t)ue[e] * g.nstride[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    nt[e] = (g.cells[e] + TC - 1) / TC;
+    // tiles t with t TC <= ue < t TC + EXT
+    int lo = ue[e] - EXT + 1 > 0 ? (ue[e] - EXT + 1 + TC - 1) / TC : 0;
+    int hi = ue[e] / TC;
+    hi = hi < nt[e] - 1 ? hi : nt[e] - 1;
+    tlo[e] = lo;
+    thi[e] = hi;
+  }
+  const T* __restrict__ NP = J.cellp;
+  T acc = T(0);
+  // up to 2^D tiles, in lexicographic order
+  for (int a = 0; a < (1 << D); ++a) {
+    int64_t tflat = 0;
+    int bflat = 0;
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      const int te = tlo[e] + ((a >> (D - 1 - e)) & 1);
+      ok = ok && te <= thi[e];
+      tflat = tflat * nt[e] + te;
+      bflat = bflat * EXT + (ue[e] - te * TC);
+    }
+    if (ok) acc += NP[tflat * NEXT + bflat];
+  }
+  J.out[(int64_t)j * J.out_js + u] = acc;
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter_nodes(Tab tab,
                                                        const ScatterJob<T>* __restrict__ jobs,
@@ -485,13 +792,20 @@ void launch_scatter(const Tab& tab, const ScatterJob<T>* jobs, int d, int j, int
         tlaunch("scatter_cells", k_scatter_cells_wave<T, 2>, nc, 256, 0, s, tc, jobs, j, mode);
         tlaunch("scatter", k_scatter_nodes<T, 2>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
-      case 3:
-        tlaunch("scatter_cells", k_scatter_cells<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
-        tlaunch("scatter", k_scatter_nodes<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
+      case 3: {
+        // tiles of 6^3 cells: at most cdiv(m, 64) per GP (ceil((m_e - 3) / 6) <= m_e / 4)
+        std::vector<int64_t> bt(tab.G);
+        for (int g = 0; g < tab.G; ++g) bt[g] = cdiv(4 * (tab.off[g + 1] - tab.off[g]), 64);
+        const Tab tt = make_tab(bt);
+        tlaunch("scatter_cells", k_scatter_tiles<T, 3>, tab_blocks(tt), 256, 0, s, tt, jobs, j,
+                mode);
+        tlaunch("scatter", k_scatter_halo<T, 3>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
+      }
       default:
-        tlaunch("scatter_cells", k_scatter_cells<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
-        tlaunch("scatter", k_scatter_nodes<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+        // tiles of 4^4 cells: at most cdiv(m, 256) per GP (ceil((m_e - 3) / 4) <= m_e / 4)
+        tlaunch("scatter_cells", k_scatter_tiles<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
+        tlaunch("scatter", k_scatter_halo<T, 4>, n2, 256, 0, s, t2, jobs, j, mode);
         break;
     }
   }
