@@ -73,7 +73,7 @@
 extern "C" {
 #endif
 
-#define LOVE_ABI_VERSION 3
+#define LOVE_ABI_VERSION 4
 #define LOVE_MAX_DIM 4
 #define LOVE_MAX_K 128
 
@@ -155,6 +155,21 @@ typedef struct {
                                        tol ||y|| (2-norm) of the exact solve                     */
   int32_t cg_maxit;                 /* <= 0: 1000                                                */
   uint32_t flags;                   /* LOVE_FLAG_*                                               */
+  /* Restart with a new probe (Sec. 5, "Ensuring Lanczos solves are accurate").
+   * With restart_tol > 0 the Lanczos solve Q T^{-1} Q^T is checked, after the k
+   * steps, on restart_groups averaged columns of W K (column g: W K 1_g / |g|,
+   * 1_g the indicator of the g-th of restart_groups runs of consecutive grid
+   * nodes).  While the worst relative residual ||c - Khat Q H^{-1} Q^T c|| / ||c||
+   * exceeds restart_tol (at most restart_max times), restart_k further Lanczos
+   * steps are taken from that residual, orthogonalised against every earlier
+   * vector; the cache then uses H = Q^T Khat Q over both blocks (no longer
+   * tridiagonal) and its dense Cholesky factor.  Single-GP builds only
+   * (love_build_cache_batched: LOVE_EUNSUPPORTED).  k + restart_max restart_k
+   * <= LOVE_MAX_K.  The check synchronises the host once per round.         */
+  double restart_tol;               /* <= 0: no check                                            */
+  int32_t restart_k;                /* steps per restart (>= 1 when restart_tol > 0)             */
+  int32_t restart_max;              /* <= 0: 1                                                   */
+  int32_t restart_groups;           /* <= 0: 8                                                   */
 } love_config;
 
 typedef struct love_cache love_cache;   /* opaque */
@@ -196,6 +211,8 @@ typedef struct {
   uint32_t toeplitz_mode[LOVE_MAX_DIM]; /* backend chosen per axis (1 direct, 2 fft)          */
   uint32_t fft_len[LOVE_MAX_DIM];   /* circulant length per axis when FFT is used                 */
   size_t bytes;                     /* device bytes held by the cache                             */
+  int32_t restarts;                 /* restarts taken (love_config.restart_tol)                   */
+  double solve_residual;            /* worst relative residual of the last check (NaN: none)      */
 } love_cache_info_t;
 
 /* Buffers the cache contents can be copied into (all device, caller-owned, any may be NULL). */

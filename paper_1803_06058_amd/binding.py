@@ -38,7 +38,8 @@ class love_config(C.Structure):
         ("kernel", C.c_int32), ("lengthscale", C.c_double * 4), ("outputscale", C.c_double),
         ("noise", C.c_double), ("k", C.c_int32), ("k_sample", C.c_int32),
         ("precision", C.c_int32), ("toeplitz", C.c_int32), ("cg_tol", C.c_double),
-        ("cg_maxit", C.c_int32), ("flags", C.c_uint32),
+        ("cg_maxit", C.c_int32), ("flags", C.c_uint32), ("restart_tol", C.c_double),
+        ("restart_k", C.c_int32), ("restart_max", C.c_int32), ("restart_groups", C.c_int32),
     ]
 
 
@@ -47,7 +48,8 @@ class love_cache_info_t(C.Structure):
         ("k_eff", C.c_int32), ("k_eff_sample", C.c_int32), ("cg_iters", C.c_int32),
         ("d", C.c_int32), ("n", C.c_int64), ("m", C.c_int64), ("beta_last", C.c_double),
         ("ortho_loss", C.c_double), ("status_flags", C.c_uint32), ("toeplitz_mode", C.c_uint32 * 4),
-        ("fft_len", C.c_uint32 * 4), ("bytes", C.c_size_t),
+        ("fft_len", C.c_uint32 * 4), ("bytes", C.c_size_t), ("restarts", C.c_int32),
+        ("solve_residual", C.c_double),
     ]
 
 
@@ -224,7 +226,9 @@ def config_struct(d: int, m: Sequence[int], lo: Sequence[float], hi: Sequence[fl
                   kernel: str = "rbf", lengthscale: Sequence[float] = (0.1,),
                   outputscale: float = 1.0, noise: float = 0.01, k: int = 50,
                   k_sample: int = 0, precision: str = "fp32", toeplitz: str = "auto",
-                  cg_tol: float = 0.0, cg_maxit: int = 0, flags: int = 0) -> love_config:
+                  cg_tol: float = 0.0, cg_maxit: int = 0, flags: int = 0,
+                  restart_tol: float = 0.0, restart_k: int = 0, restart_max: int = 0,
+                  restart_groups: int = 0) -> love_config:
     c = love_config()
     c.d = d
     for e in range(d):
@@ -242,6 +246,10 @@ def config_struct(d: int, m: Sequence[int], lo: Sequence[float], hi: Sequence[fl
     c.cg_tol = cg_tol
     c.cg_maxit = cg_maxit
     c.flags = flags
+    c.restart_tol = restart_tol
+    c.restart_k = restart_k
+    c.restart_max = restart_max
+    c.restart_groups = restart_groups
     return c
 
 

@@ -181,6 +181,14 @@ static love_status validate(const love_config* cfg) {
   if (cfg->precision < LOVE_P_FP64 || cfg->precision > LOVE_P_FP32_BF16SPLIT) return LOVE_EINVAL;
   if (cfg->toeplitz < LOVE_TOEPLITZ_AUTO || cfg->toeplitz > LOVE_TOEPLITZ_FFT) return LOVE_EINVAL;
   if (cfg->cg_tol < 0 || !std::isfinite(cfg->cg_tol)) return LOVE_EINVAL;
+  if (!std::isfinite(cfg->restart_tol)) return LOVE_EINVAL;
+  if (cfg->restart_tol > 0 && (cfg->flags & LOVE_FLAG_HYPER)) return LOVE_EUNSUPPORTED;
+  if (cfg->restart_tol > 0) {
+    const int rmax = cfg->restart_max > 0 ? cfg->restart_max : 1;
+    if (cfg->restart_k < 1 || (int64_t)cfg->k + (int64_t)rmax * cfg->restart_k > LOVE_MAX_K)
+      return LOVE_EINVAL;
+    if (cfg->restart_groups > (1 << 16)) return LOVE_EINVAL;
+  }
   return LOVE_OK;
 }
 
@@ -220,7 +228,15 @@ static love_status init_cache(love_cache* c, const love_config* cfg, int64_t n, 
   c->m = m;
   c->ctot = ct;
   c->ldq = cdiv(n, RB) * RB;
-  c->k = (int)std::min<int64_t>(cfg->k, n);
+  // k: Lanczos vectors the buffers hold (the first run's k1 plus the
+  // restarts' steps); the first run takes k1
+  c->k1 = (int)std::min<int64_t>(cfg->k, n);
+  if (cfg->restart_tol > 0) {
+    c->restart_max = cfg->restart_max > 0 ? cfg->restart_max : 1;
+    c->restart_groups = cfg->restart_groups > 0 ? cfg->restart_groups : 8;
+    c->restart_k = cfg->restart_k;
+  }
+  c->k = (int)std::min<int64_t>((int64_t)c->k1 + (int64_t)c->restart_max * c->restart_k, n);
   c->kpad = kround(c->k);
   c->ks = (int)std::min<int64_t>(cfg->k_sample, m);
   c->kspad = c->ks > 0 ? kround(c->ks) : 0;
@@ -490,6 +506,7 @@ love_status love_build_cache_batched(int32_t G, const love_config* cfgs, const v
       return LOVE_EINVAL;
     if ((cfgs[g].flags & LOVE_FLAG_ADDITIVE) != (cfgs[0].flags & LOVE_FLAG_ADDITIVE))
       return LOVE_EINVAL;
+    if (G > 1 && cfgs[g].restart_tol > 0) return LOVE_EUNSUPPORTED;   // restarts: single builds
   }
   hipStream_t s = (hipStream_t)stream;
   device_setup();
@@ -675,6 +692,8 @@ love_status love_cache_info(const love_cache* c, love_cache_info_t* info) {
     info->fft_len[e] = (uint32_t)(c->toep.ax[e].mode == 2 ? c->toep.ax[e].fft_n : 0);
   }
   info->bytes = c->bytes;
+  info->restarts = c->restarts;
+  info->solve_residual = c->solve_residual;
   return LOVE_OK;
 }
 

@@ -112,7 +112,13 @@ struct love_cache {
   int d = 1;
   int64_t n = 0, m = 0;
   int64_t ldq = 0;            // n rounded up to the row-block size
-  int k = 0, kpad = 0;        // Lanczos steps requested; row stride of Rt
+  int k = 0, kpad = 0;        // Lanczos vectors the buffers hold; row stride of Rt
+  int k1 = 0;                 // steps of the first Lanczos run (k unless restarts are allowed)
+  // restart with a new probe (love_config.restart_*): rounds allowed, steps
+  // per round, check groups; rounds taken and the last check's worst residual
+  int restart_max = 0, restart_k = 0, restart_groups = 0;
+  int restarts = 0;
+  double solve_residual = NAN;
   int ks = 0, kspad = 0;      // sampler steps; row stride of S
   hipStream_t stream = nullptr;
   int device = 0;

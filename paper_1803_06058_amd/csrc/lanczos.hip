@@ -1892,6 +1892,244 @@ static love_status sampler_dispatch(love_cache* c, hipStream_t s) {
 }
 
 // ============================================================================
+// Restart with a new probe (Sec. 5, "Ensuring Lanczos solves are accurate").
+// After the first run the Lanczos solve Q H^{-1} Q^T is checked on the
+// averaged columns c_g = W K 1_g / |g| of W K (1_g: the indicator of the g-th
+// run of consecutive grid nodes); if the worst relative residual
+// ||c_g - Khat Q H^{-1} Q^T c_g|| / ||c_g|| is too large, more Lanczos steps
+// start from that residual (orthogonalised twice against every earlier
+// vector; the step kernels then orthogonalise against both blocks), and
+// H = Q^T Khat Q = G^T R^T + sigma^2 Q^T Q (G = W^T Q, rows of R = K W^T q_j)
+// with its dense Cholesky factor replaces the tridiagonal T.  Single GP.
+// ============================================================================
+// gv = 1_[lo, hi) / (hi - lo) over the m grid nodes
+template <typename T>
+__global__ void k_rs_group(T* __restrict__ gv, int64_t m, int64_t lo, int64_t hi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) gv[i] = (i >= lo && i < hi) ? (T)(1.0 / (double)(hi - lo)) : T(0);
+}
+
+// D[i * ldd + g] = Q[:, i] . Y[:, g] over n rows, i < k, g < ng; one block per (i, g)
+template <typename T>
+__global__ __launch_bounds__(256) void k_rs_dots(const T* __restrict__ Q, int64_t ldq,
+                                                 const T* __restrict__ Y, int64_t ldy, int64_t n,
+                                                 int ng, double* __restrict__ D, int ldd) {
+  __shared__ double scr[16];
+  const int i = blockIdx.x, g = blockIdx.y;
+  const T* q = Q + (int64_t)i * ldq;
+  const T* y = Y + (int64_t)g * ldy;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) acc += (double)q[r] * (double)y[r];
+  acc = block_sum(acc, scr);
+  if (threadIdx.x == 0) D[(int64_t)i * ldd + g] = acc;
+}
+
+// X[:, g] = Q[:, :k] Yk[:, g] (rows past n zero); Yk is k x ldy (column g at g)
+template <typename T>
+__global__ void k_rs_combine(const T* __restrict__ Q, int64_t ldq, int k,
+                             const double* __restrict__ Yk, int ldy, int ng,
+                             T* __restrict__ X, int64_t ldx, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ldx) return;
+  for (int g = 0; g < ng; ++g) {
+    double a = 0.0;
+    if (r < n)
+      for (int i = 0; i < k; ++i) a += (double)Q[(int64_t)i * ldq + r] * Yk[(int64_t)i * ldy + g];
+    X[(int64_t)g * ldx + r] = (T)a;
+  }
+}
+
+// solve (L L^T) y = b for ng right-hand sides in place (B: k x ldb, column g
+// at g); L dense lower, k x MAXK row-major, k = ctl->k_eff.  One thread per
+// right-hand side.
+__global__ void k_rs_solve(const double* __restrict__ L, const Ctl* __restrict__ ctl,
+                           double* __restrict__ B, int ldb, int ng) {
+  const int g = threadIdx.x;
+  if (g >= ng) return;
+  const int k = ctl->k_eff;
+  for (int i = 0; i < k; ++i) {
+    double z = B[(int64_t)i * ldb + g];
+    for (int l = 0; l < i; ++l) z -= L[i * MAXK + l] * B[(int64_t)l * ldb + g];
+    B[(int64_t)i * ldb + g] = z / L[i * MAXK + i];
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double z = B[(int64_t)i * ldb + g];
+    for (int l = i + 1; l < k; ++l) z -= L[l * MAXK + i] * B[(int64_t)l * ldb + g];
+    B[(int64_t)i * ldb + g] = z / L[i * MAXK + i];
+  }
+}
+
+// dense L (k x MAXK) from the bidiagonal Cholesky factor (ldiag, lsub)
+__global__ void k_rs_dense_bidiag(const double* __restrict__ ld, const double* __restrict__ ls,
+                                  const Ctl* __restrict__ ctl, double* __restrict__ L) {
+  const int k = ctl->k_eff;
+  for (int e = threadIdx.x; e < MAXK * MAXK; e += blockDim.x) {
+    const int i = e / MAXK, l = e % MAXK;
+    double v = 0.0;
+    if (i < k && l < k) v = (i == l) ? ld[i] : (i == l + 1 ? ls[l] : 0.0);
+    L[e] = v;
+  }
+}
+
+// nrm[2 g] = ||C_g - KX_g||, nrm[2 g + 1] = ||C_g||; Rr_g = C_g - KX_g; one block per g
+template <typename T>
+__global__ __launch_bounds__(256) void k_rs_resid(const T* __restrict__ C, const T* __restrict__ KX,
+                                                  T* __restrict__ Rr, int64_t ld, int64_t n,
+                                                  double* __restrict__ nrm) {
+  __shared__ double scr[16];
+  const int g = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t r = threadIdx.x; r < ld; r += 256) {
+    const int64_t i = (int64_t)g * ld + r;
+    const double c = r < n ? (double)C[i] : 0.0;
+    const double d = r < n ? c - (double)KX[i] : 0.0;
+    Rr[i] = (T)d;
+    a += d * d;
+    b += c * c;
+  }
+  a = block_sum(a, scr);
+  __syncthreads();
+  b = block_sum(b, scr);
+  if (threadIdx.x == 0) {
+    nrm[2 * g] = sqrt(a);
+    nrm[2 * g + 1] = sqrt(b);
+  }
+}
+
+// v -= Q[:, :k] c (one Gram-Schmidt pass; c from k_rs_dots), rows < n
+template <typename T>
+__global__ void k_rs_sub(T* __restrict__ v, const T* __restrict__ Q, int64_t ldq, int k,
+                         const double* __restrict__ c, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double a = (double)v[r];
+  for (int i = 0; i < k; ++i) a -= (double)Q[(int64_t)i * ldq + r] * c[i];
+  v[r] = (T)a;
+}
+
+// q = v / ||v|| into column j of Q (padding rows zero); one block
+template <typename T>
+__global__ __launch_bounds__(256) void k_rs_start(const T* __restrict__ v, int64_t n, int64_t ldq,
+                                                  T* __restrict__ qj) {
+  __shared__ double scr[16];
+  double a = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) a += (double)v[r] * (double)v[r];
+  a = block_sum(a, scr);
+  const double inv = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
+  for (int64_t r = threadIdx.x; r < ldq; r += 256) qj[r] = r < n ? (T)((double)v[r] * inv) : T(0);
+}
+
+// H[i][j] = G_i . R_j + sigma^2 q_i . q_j for i <= j < k (mirrored); one block per pair
+template <typename T>
+__global__ __launch_bounds__(256) void k_rs_h(const T* __restrict__ G, int64_t ldg,
+                                              const T* __restrict__ R, int64_t m,
+                                              const T* __restrict__ Q, int64_t ldq, int64_t n,
+                                              double sigma2, const Ctl* __restrict__ ctl,
+                                              double* __restrict__ H) {
+  __shared__ double scr[16];
+  const int i = blockIdx.x, j = blockIdx.y;
+  const int k = ctl->k_eff;
+  if (i > j || j >= k) return;
+  double a = 0.0, b = 0.0;
+  for (int64_t u = threadIdx.x; u < m; u += 256)
+    a += (double)G[(int64_t)i * ldg + u] * (double)R[(int64_t)j * m + u];
+  for (int64_t r = threadIdx.x; r < n; r += 256)
+    b += (double)Q[(int64_t)i * ldq + r] * (double)Q[(int64_t)j * ldq + r];
+  a = block_sum(a, scr);
+  __syncthreads();
+  b = block_sum(b, scr);
+  if (threadIdx.x == 0) {
+    const double h = a + sigma2 * b;
+    H[i * MAXK + j] = h;
+    H[j * MAXK + i] = h;
+  }
+}
+
+// Dense Cholesky H = L L^T (k = ctl->k_eff <= MAXK) in double in LDS, column
+// by column; a pivot <= rel_tol max|H_ii| truncates k_eff there (SF_NOTPD).
+// Also Linv = L^{-1}.  L and Linv: k x MAXK row-major (zero above the diagonal).
+__global__ __launch_bounds__(MAXK) void k_rs_chol(const double* __restrict__ H, Ctl* ctl,
+                                                  double rel_tol, double* __restrict__ L,
+                                                  double* __restrict__ Linv) {
+  __shared__ double A[MAXK][MAXK + 1];
+  __shared__ int s_keep;
+  const int k = ctl->k_eff, t = threadIdx.x;
+  for (int e = t; e < MAXK * MAXK; e += MAXK) {
+    const int i = e / MAXK, l = e % MAXK;
+    A[i][l] = (i < k && l < k) ? H[i * MAXK + l] : 0.0;
+  }
+  if (t == 0) s_keep = k;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < k; ++i) dmax = fmax(dmax, fabs(A[i][i]));
+  for (int c = 0; c < k; ++c) {
+    if (c >= s_keep) break;
+    if (t == 0) {
+      double d = A[c][c];
+      for (int l = 0; l < c; ++l) d -= A[c][l] * A[c][l];
+      if (!(d > rel_tol * dmax) || !isfinite(d)) {
+        s_keep = c;
+      } else {
+        A[c][c] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (c >= s_keep) break;
+    if (t > c && t < k) {
+      double v = A[t][c];
+      for (int l = 0; l < c; ++l) v -= A[t][l] * A[c][l];
+      A[t][c] = v / A[c][c];
+    }
+    __syncthreads();
+  }
+  const int kk = s_keep;
+  // write L; Linv column t by forward substitution of L x = e_t
+  for (int e = t; e < MAXK * MAXK; e += MAXK) {
+    const int i = e / MAXK, l = e % MAXK;
+    L[e] = (i < kk && l <= i) ? A[i][l] : 0.0;
+  }
+  for (int i = 0; i < MAXK; ++i) Linv[i * MAXK + t] = 0.0;
+  if (t < kk) {
+    for (int i = t; i < kk; ++i) {
+      double z = (i == t) ? 1.0 : 0.0;
+      for (int l = t; l < i; ++l) z -= A[i][l] * Linv[l * MAXK + t];
+      Linv[i * MAXK + t] = z / A[i][i];
+    }
+  }
+  if (t == 0 && kk < k) {
+    ctl->k_eff = kk;
+    ctl->status |= SF_NOTPD;
+  }
+}
+
+// Rt[u, i] = sum_{l <= i} Linv[i][l] R[l][u] for i < k_eff (0 beyond), in the
+// cache precision or as bf16 hi + bf16 lo; thread per (u, i)
+template <typename T>
+__global__ void k_rs_rtilde(const T* __restrict__ R, int64_t m, const double* __restrict__ Linv,
+                            const Ctl* __restrict__ ctl, int kpad, int split, void* rt,
+                            uint16_t* __restrict__ rt_lo) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kpad) return;
+  const int64_t u = idx / kpad;
+  const int i = (int)(idx - u * kpad);
+  const int k = ctl->k_eff;
+  double z = 0.0;
+  if (i < k)
+    for (int l = 0; l <= i; ++l) z += Linv[i * MAXK + l] * (double)R[(int64_t)l * m + u];
+  if (split) {
+    const float f = (float)z;
+    const uint16_t hi = f32_to_bf16_rne(f);
+    ((uint16_t*)rt)[idx] = hi;
+    rt_lo[idx] = f32_to_bf16_rne(f - bf16_to_f32(hi));
+  } else {
+    ((T*)rt)[idx] = (T)z;
+  }
+}
+
+__global__ void k_rs_set(int* __restrict__ p, int v) { *p = v; }
+__global__ void k_rs_unstop(Ctl* ctl) { ctl->stop = 0; }
+
+// ============================================================================
 // Batched build: Lanczos + Rt + mean cache for G GPs in lock step.
 // ============================================================================
 namespace {
@@ -1926,7 +2164,7 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   b.rpbg = cdiv(n, (int64_t)b.nbg);
   // grid-space first pass when the grid is no larger than the data
   b.ldg = m <= n ? cdiv(m, RB) * RB : 0;
-  b.ldgh = (c->B && !b.ldg) ? cdiv(m, RB) * RB : 0;
+  b.ldgh = ((c->B || c->restart_max > 0) && !b.ldg) ? cdiv(m, RB) * RB : 0;
   size_t tb = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
                            (size_t)ts + (size_t)b.ldg * k + (size_t)b.ldgh * k);
   tb = (tb + 255) & ~size_t(255);
@@ -2063,7 +2301,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     J.lsub = b.lsub;
     J.ctl = c->ctl;
     J.tol = c->tol_lanczos;
-    J.klast = c->k - 1;
+    J.klast = c->k1 - 1;
     J.nb = (int)nb;
     J.gpath = b.ldg ? 1 : 0;
     J.G = b.G;
@@ -2101,9 +2339,16 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     Rj.split = c->cfg.precision == LOVE_P_FP32_BF16SPLIT;
     Rj.ctl = c->ctl;
     rj[g] = Rj;
+    if (b.ldgh) {
+      // G = W^T Q after the run, column by column, where the grid-space first
+      // pass does not keep it (the factor B and the restart's H need it)
+      ScatterJob<T> Sh = S;
+      Sh.out = b.Gh;
+      Sh.out_js = b.ldgh;
+      sch[g] = Sh;
+    }
     if (c->B) {
-      // B = (L^{-1} G^T)^T from G = W^T Q: the grid-space first pass keeps G;
-      // otherwise its columns are scattered after the Lanczos run
+      // B = (L^{-1} G^T)^T from G = W^T Q
       RtJob<T> Bj = Rj;
       Bj.R = b.ldg ? b.G : b.Gh;
       Bj.ld = b.ldg ? b.ldg : b.ldgh;
@@ -2112,13 +2357,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       Bj.split = 0;
       bj[g] = Bj;
       b_hy[g] = cdiv(c->m, RT_ROWS);
-      if (!b.ldg) {
-        ScatterJob<T> Sh = S;
-        Sh.out = b.Gh;
-        Sh.out_js = b.ldgh;
-        sch[g] = Sh;
-        b_hsc[g] = cdiv(c->m, 4);   // as the step's scatter table
-      }
+      if (!b.ldg) b_hsc[g] = cdiv(c->m, 4);   // as the step's scatter table
     }
     s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
     nv1[g] = J.gpath ? -(1 << 20) : 1;   // no first-pass sums on the grid-space path
@@ -2142,7 +2381,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     b_nodes[g] = cdiv(c->m, 4);
     b_m[g] = cdiv(c->m, 256);
     b_grid[g] = cdiv(c->n, 256);
-    kmax = std::max(kmax, c->k);
+    kmax = std::max(kmax, c->k1);
   }
   JobArena A;
   SpectralMean sm;
@@ -2210,7 +2449,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       C.gv = b.cgv;
       C.gm = b.cgm;
       C.Q = b.Q;
-      C.kq = plain[g] ? 0 : c->k;
+      C.kq = plain[g] ? 0 : c->k1;
       C.kpad = c->kpad;
       C.ldiag = b.ldiag;
       C.lsub = b.lsub;
@@ -2326,11 +2565,11 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   std::vector<int> a_nv1 = nv1, a_nv2 = nv2;
   for (int j = 0; j < kmax; ++j) {
     bool drop = false;
-    for (int g = 0; g < G; ++g) drop = drop || cs[g]->k == j;
+    for (int g = 0; g < G; ++g) drop = drop || cs[g]->k1 == j;
     if (drop) {
       auto keep = [&](const Tab& t) {
         std::vector<int64_t> b(G);
-        for (int g = 0; g < G; ++g) b[g] = cs[g]->k > j ? t.off[g + 1] - t.off[g] : 0;
+        for (int g = 0; g < G; ++g) b[g] = cs[g]->k1 > j ? t.off[g + 1] - t.off[g] : 0;
         return make_tab(b);
       };
       a_nodes = keep(t_nodes);
@@ -2341,7 +2580,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
       auto keep_t = [&](const Tab& t) {
         std::vector<int64_t> b(t.G);
         for (int i = 0; i < t.G; ++i)
-          b[i] = cs[i / t_step.jpg]->k > j ? t.off[i + 1] - t.off[i] : 0;
+          b[i] = cs[i / t_step.jpg]->k1 > j ? t.off[i + 1] - t.off[i] : 0;
         return make_tab(b);
       };
       for (int e = 0; e < t_step.d; ++e) {
@@ -2351,7 +2590,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
         a_step.ax[e].fft = keep_t(t_step.ax[e].fft);
       }
       for (int g = 0; g < G; ++g)
-        if (cs[g]->k <= j) a_nv1[g] = a_nv2[g] = -(1 << 20);
+        if (cs[g]->k1 <= j) a_nv1[g] = a_nv2[g] = -(1 << 20);
     }
     launch_scatter<T>(a_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
     toep_run<T>(A, a_step, j, 1, s);
@@ -2367,7 +2606,164 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   }
   // --- T = L L^T ; Rt = (L^{-1} R)^T ---------------------------------------------
   k_tri_chol<T><<<tab_blocks(t_one), 64, 0, s>>>(t_one, dlz, 0.0);
-  {
+  // --- restart with a new probe when the solve check fails (single GP) ----------
+  bool dense_rt = false;
+  double* rs_linv = nullptr;
+  char* rs_mem = nullptr;
+  JobArena A_rs, A_rs2;
+  struct RsRelease {   // the restart's workspace goes back on every return path
+    char*& mem;
+    JobArena& a1;
+    JobArena& a2;
+    hipStream_t st;
+    ~RsRelease() {
+      ws_free(mem, st);
+      a1.release(st);
+      a2.release(st);
+    }
+  } rs_release{rs_mem, A_rs, A_rs2, s};
+  if (G == 1 && cs[0]->restart_max > 0) {
+    love_cache* c = cs[0];
+    GpBufs<T>& b = bufs[0];
+    const int Gc = c->restart_groups;
+    const int64_t n = c->n, m = c->m, ldq = c->ldq;
+    const size_t tcol = sizeof(T) * (size_t)ldq * Gc;
+    const size_t dsz = sizeof(double) * (3 * (size_t)MAXK * MAXK + (size_t)MAXK * Gc + 2 * (size_t)Gc +
+                                         MAXK);
+    rs_mem = (char*)ws_alloc(4 * tcol + dsz, s);
+    if (!rs_mem) return LOVE_ENOMEM;
+    T* Cm = (T*)rs_mem;
+    T* KX = (T*)(rs_mem + tcol);
+    T* Rr = (T*)(rs_mem + 2 * tcol);
+    T* X = (T*)(rs_mem + 3 * tcol);
+    double* Ld = (double*)(rs_mem + 4 * tcol);
+    rs_linv = Ld + MAXK * MAXK;
+    double* Hd = rs_linv + MAXK * MAXK;
+    double* Dm = Hd + MAXK * MAXK;
+    double* nrm = Dm + (size_t)MAXK * Gc;
+    double* cvec = nrm + 2 * Gc;
+    // jobs: the groups' W K 1_g / |g| and Khat x_g columns, the x_g scatters
+    std::vector<GatherJob<T>> gj(2 * Gc);
+    std::vector<ScatterJob<T>> sj(Gc);
+    for (int g = 0; g < Gc; ++g) {
+      GatherJob<T> a = ga[0];
+      a.kg = b.gm;
+      a.vsig = nullptr;
+      a.sigma2 = T(0);
+      a.out = Cm + (size_t)g * ldq;
+      a.ctl = nullptr;
+      gj[g] = a;
+      a.vsig = X + (size_t)g * ldq;
+      a.sigma2 = (T)c->cfg.noise;
+      a.out = KX + (size_t)g * ldq;
+      gj[Gc + g] = a;
+      ScatterJob<T> sx = sc[0];
+      sx.v = X + (size_t)g * ldq;
+      sx.v_js = 0;
+      sx.out = b.gv;
+      sx.out_js = 0;
+      sx.ctl = nullptr;
+      sj[g] = sx;
+    }
+    const size_t o_gj = A_rs.add(gj), o_sj = A_rs.add(sj);
+    love_status st = A_rs.upload(s);
+    if (st != LOVE_OK) return st;
+    const Tab tab_m = tab1(cdiv(m, 4)), tab_n = tab1(cdiv(n, 256));
+    k_rs_dense_bidiag<<<1, 256, 0, s>>>(b.ldiag, b.lsub, c->ctl, Ld);
+    // the checked columns c_g = W K 1_g / |g| (runs of the m grid nodes, bounds
+    // rounded half to even)
+    const double step = (double)m / Gc;
+    for (int g = 0; g < Gc; ++g) {
+      const int64_t lo = (int64_t)std::nearbyint(g * step);
+      const int64_t hi = g + 1 == Gc ? m : (int64_t)std::nearbyint((g + 1) * step);
+      k_rs_group<T><<<(unsigned)cdiv(m, 256), 256, 0, s>>>(b.gv, m, lo, hi);
+      toep_run<T>(A, t_probe, 0, 0, s);
+      launch_gather<T>(tab_n, A_rs.at<GatherJob<T>>(o_gj) + g, D, 0, s);
+    }
+    const T* Gsrc = b.ldg ? b.G : b.Gh;
+    const int64_t ldgs = b.ldg ? b.ldg : b.ldgh;
+    const CgJob<T>* dcg0 = A.at<CgJob<T>>(o_cg);
+    for (int round = 0;; ++round) {
+      Ctl hc;
+      LOVE_HIP_TRY(hipMemcpyAsync(&hc, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+      LOVE_HIP_TRY(hipStreamSynchronize(s));
+      const int kq = hc.k_eff;
+      if (kq < 1) break;
+      // x_g = Q H^{-1} Q^T c_g, then the residuals c_g - Khat x_g
+      k_rs_dots<T><<<dim3((unsigned)kq, (unsigned)Gc), 256, 0, s>>>(b.Q, ldq, Cm, ldq, n, Gc, Dm, Gc);
+      k_rs_solve<<<1, 64 * (int)cdiv(Gc, 64), 0, s>>>(Ld, c->ctl, Dm, Gc, Gc);
+      k_rs_combine<T><<<(unsigned)cdiv(ldq, 256), 256, 0, s>>>(b.Q, ldq, kq, Dm, Gc, Gc, X, ldq, n);
+      for (int g = 0; g < Gc; ++g) {
+        launch_scatter<T>(tab_m, A_rs.at<ScatterJob<T>>(o_sj) + g, D, 0, 0, s, two_st);
+        toep_run<T>(A, t_probe, 0, 0, s);
+        launch_gather<T>(tab_n, A_rs.at<GatherJob<T>>(o_gj) + Gc + g, D, 0, s);
+      }
+      k_rs_resid<T><<<(unsigned)Gc, 256, 0, s>>>(Cm, KX, Rr, ldq, n, nrm);
+      std::vector<double> hn(2 * Gc);
+      LOVE_HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * Gc, hipMemcpyDeviceToHost, s));
+      LOVE_HIP_TRY(hipStreamSynchronize(s));
+      int worst = 0;
+      double wrel = -1.0;
+      for (int g = 0; g < Gc; ++g) {
+        const double rel = hn[2 * g + 1] > 0.0 ? hn[2 * g] / hn[2 * g + 1] : 0.0;
+        if (rel > wrel) {
+          wrel = rel;
+          worst = g;
+        }
+      }
+      c->solve_residual = wrel;
+      if (!(wrel > c->cfg.restart_tol) || round == c->restart_max || kq >= n ||
+          kq + c->restart_k > c->k)
+        break;
+      // new probe: the worst residual, orthogonalised twice against Q
+      T* vr = Rr + (size_t)worst * ldq;
+      for (int pass = 0; pass < 2; ++pass) {
+        k_rs_dots<T><<<dim3((unsigned)kq, 1), 256, 0, s>>>(b.Q, ldq, vr, ldq, n, 1, cvec, 1);
+        k_rs_sub<T><<<(unsigned)cdiv(n, 256), 256, 0, s>>>(vr, b.Q, ldq, kq, cvec, n);
+      }
+      k_rs_start<T><<<1, 256, 0, s>>>(vr, n, ldq, b.Q + (size_t)kq * ldq);
+      // the preconditioner of the mean solve keeps the first run's vectors
+      if (round == 0 && mean && !plain[0])
+        k_rs_set<<<1, 1, 0, s>>>(&(const_cast<CgJob<T>*>(dcg0)->kq), kq);
+      k_rs_unstop<<<1, 1, 0, s>>>(c->ctl);
+      LzJob<T> J2 = lz[0];
+      J2.klast = kq + c->restart_k - 1;
+      A_rs2.release(s);
+      A_rs2 = JobArena();
+      const size_t o_l2 = A_rs2.add(std::vector<LzJob<T>>{J2});
+      st = A_rs2.upload(s);
+      if (st != LOVE_OK) return st;
+      const LzJob<T>* dlz2 = A_rs2.at<LzJob<T>>(o_l2);
+      for (int j = kq; j < kq + c->restart_k; ++j) {
+        launch_scatter<T>(t_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
+        toep_run<T>(A, t_step, j, 1, s);
+        if (tab_blocks(t_cd))
+          tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(t_cd), RBLK, 0, s, t_cd, dlz2, j);
+        if (tab_blocks(t_gd)) {
+          tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_gd), RBLK, 0, s, t_gd, dlz2, j);
+          launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
+        }
+        tlaunch("lz_udots", k_lz_udots<T, D>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz2, j);
+        launch_colsum(A.at<SumJob>(o_c2), nv2, j, 1, s);
+        tlaunch("lz_finalize", k_lz_finalize<T>, tab_blocks(t_rows), RBLK, 0, s, t_rows, dlz2, j);
+      }
+      // H = Q^T Khat Q over every vector so far, its dense Cholesky factor
+      if (!b.ldg)
+        for (int j = 0; j < kq + c->restart_k; ++j)
+          launch_scatter<T>(tab_m, A.at<ScatterJob<T>>(o_sch), D, j, 0, s, two_st);
+      k_rs_h<T><<<dim3((unsigned)c->k, (unsigned)c->k), 256, 0, s>>>(
+          Gsrc, ldgs, b.R, m, b.Q, ldq, n, c->cfg.noise, c->ctl, Hd);
+      k_rs_chol<<<1, MAXK, 0, s>>>(Hd, c->ctl, 0.0, Ld, rs_linv);
+      dense_rt = true;
+      c->restarts = round + 1;
+    }
+  }
+  if (dense_rt) {
+    love_cache* c = cs[0];
+    tlaunch("rtilde", k_rs_rtilde<T>, (unsigned)cdiv(c->m * c->kpad, 256), 256, 0, s,
+            (const T*)bufs[0].R, c->m, (const double*)rs_linv, (const Ctl*)c->ctl, c->kpad,
+            c->cfg.precision == LOVE_P_FP32_BF16SPLIT ? 1 : 0, c->rt, (uint16_t*)c->rt_lo);
+  } else {
     std::vector<int64_t> b_rt(G);
     for (int g = 0; g < G; ++g) b_rt[g] = cdiv(cs[g]->m, RT_ROWS);
     const Tab t_rt = make_tab(b_rt);

@@ -38,7 +38,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status_strings(lib):
-    assert lib.love_abi_version() == 3
+    assert lib.love_abi_version() == 4
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert lib.love_status_string(code)
     assert lib.love_status_string(12345) == b"unknown status"
