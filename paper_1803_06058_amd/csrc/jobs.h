@@ -112,6 +112,9 @@ struct LzJob {
   int64_t ldg;
   double* gpart;              // nbc x LDP
   int nbc;
+  // gcs = 1 (grids of more than GPASS_NBC_SUM tiles): a column-sum launch
+  // adds the nbc rows into c2 before the second pass, which reads them there
+  int gcs;
   double* coef;               // LDP
   double* c2;                 // LDP
   double* amax;               // LDP

@@ -434,6 +434,18 @@ __global__ __launch_bounds__(RBLK) void k_lz_gdots(Tab tab, const LzJob<T>* __re
   else lz_gdots_body<T, D, 1>(J, lb, j);
 }
 
+// Blocks of the grid-space first pass: one per 256-row tile up to
+// GPASS_NBC_SUM tiles, whose partial rows the second pass adds itself;
+// larger grids take one block per tile (at most GPASS_NBC_MAX) and a
+// column-sum launch adds their rows (the second pass would otherwise read
+// them all in every block).
+constexpr int GPASS_NBC_SUM = 64;
+constexpr int GPASS_NBC_MAX = 1024;
+static inline int gpass_blocks(int64_t m) {
+  const int64_t t = cdiv(m, RB);
+  return (int)(t <= GPASS_NBC_SUM ? t : std::min<int64_t>(t, GPASS_NBC_MAX));
+}
+
 // Grid-space first pass: partial rows of G_{0..j}^T R_j over the GP's nbc
 // blocks; block lb takes the 256-row tiles lb, lb + nbc, ... (lane: 4 rows),
 // the waves split the columns as in coldots and keep one running sum per
@@ -562,7 +574,16 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
     if (t < RBK && row < J.n)
       vrow = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) +
              J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
-    gpass_coef<T>(J, j, lb, cl);
+    if (J.gcs) {
+      // the first pass's rows summed by the column-sum launch (into c2)
+      for (int c = threadIdx.x; c < ncols; c += RBLK) {
+        const double t = J.c2[c] + (c == j ? (double)J.sigma2 : 0.0);
+        cl[c] = t;
+        if (lb == 0) J.coef[c] = t;
+      }
+    } else {
+      gpass_coef<T>(J, j, lb, cl);
+    }
   } else if (J.psum) {
     if (t < RBK && row < J.n) vrow = J.v[row];
     rows_sum(J.partial, J.nb, ncols, cl);
@@ -593,9 +614,13 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   coldots_regs<T, RPL>(qr, ncols, vv, prow);
   if (threadIdx.x == 0) prow[ncols] = rrb;
 }
+// The 4-D float instance is held to 128 registers (four waves per SIMD, two
+// blocks per CU) at the cost of a small spill: measured faster than one
+// block per CU at 153 registers.
 template <typename T, int D>
-__global__ __launch_bounds__(RBLK) void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs,
-                                                  int j) {
+__global__ __launch_bounds__(RBLK)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && D == 4 ? 4 : 1)))
+void k_lz_udots(Tab tab, const LzJob<T>* __restrict__ jobs, int j) {
   int gp, lb;
   if (!tab_find(tab, blockIdx.x, gp, lb)) return;
   const LzJob<T>& J = jobs[gp];
@@ -2168,7 +2193,8 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   size_t tb = sizeof(T) * ((size_t)ldq * k + (size_t)k * m + 2 * (size_t)ldq + 2 * (size_t)m +
                            (size_t)ts + (size_t)b.ldg * k + (size_t)b.ldgh * k);
   tb = (tb + 255) & ~size_t(255);
-  size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP + (b.ldg ? (size_t)64 * LDP : 0));
+  size_t db = sizeof(double) * ((size_t)nb * LDP + 6 * LDP +
+                                (b.ldg ? (size_t)gpass_blocks(m) * LDP : 0));
   if (mean) {
     const bool own = sizeof(T) != 8;
     db += sizeof(double) * ((own ? (size_t)n * (c->d + 1) : 0) + 5 * (size_t)ldq +
@@ -2202,7 +2228,7 @@ love_status alloc_gp(love_cache* c, GpBufs<T>& b, bool mean, bool plain, hipStre
   q = b.lsub + LDP + LDP;
   if (b.ldg) {
     b.gpart = q;
-    q += (size_t)64 * LDP;
+    q += (size_t)gpass_blocks(m) * LDP;
   }
   if (mean) {
     if (sizeof(T) != 8) {
@@ -2268,6 +2294,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   std::vector<int64_t> b_rows(G), b_nodes(G), b_m(G), b_one(G, 1), b_grid(G);
   std::vector<int> nv1(G, 1);
   std::vector<int> nv2(G, 2);   // columns of the coef / c2 sums at j = 0
+  std::vector<int> nvg(G, 1);   // the large-grid first-pass sums
+  std::vector<SumJob> s_gco(G);
+  bool any_gcs = false;
   std::vector<int64_t> b_gd(G), b_cd(G), js_in(G);
   int kmax = 0;
   for (int g = 0; g < G; ++g) {
@@ -2307,7 +2336,8 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     J.G = b.G;
     J.ldg = b.ldg;
     J.gpart = b.gpart;
-    J.nbc = b.ldg ? (int)std::min<int64_t>(64, cdiv(c->m, RB)) : 0;
+    J.nbc = b.ldg ? gpass_blocks(c->m) : 0;
+    J.gcs = J.nbc > GPASS_NBC_SUM ? 1 : 0;
     lz[g] = J;
     ScatterJob<T> S{};
     S.g = J.g;
@@ -2361,6 +2391,9 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
     }
     s_coef[g] = SumJob{b.partial, b.coef, c->ctl, (int)nb, 1};
     nv1[g] = J.gpath ? -(1 << 20) : 1;   // no first-pass sums on the grid-space path
+    s_gco[g] = SumJob{b.gpart, b.c2, c->ctl, J.nbc, 1};
+    nvg[g] = J.gcs ? 1 : -(1 << 20);
+    any_gcs = any_gcs || J.gcs;
     if (J.gpath && lz_psum(nb)) {
       lz[g].psum = 1;
       lz[g].partial2 = b.partial;   // udots reads only the cdots rows here
@@ -2416,6 +2449,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   } clean{s, &A, &bufs, &sm};
   const size_t o_lz = A.add(lz), o_sc = A.add(sc), o_ga = A.add(ga), o_fi = A.add(fi),
                o_rj = A.add(rj), o_coef = A.add(s_coef), o_c2 = A.add(s_c2),
+               o_gco = A.add(s_gco),
                o_bj = A.add(bj), o_sch = A.add(sch);
   ToepRun<T> t_probe, t_step;
   toep_prepare<T>(A, t_probe, cs, t_in_probe, js0, t_out_probe, js0, t_scr,
@@ -2562,7 +2596,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
   // their control block.
   Tab a_nodes = t_nodes, a_cd = t_cd, a_gd = t_gd, a_rows = t_rows;
   ToepRun<T> a_step = t_step;
-  std::vector<int> a_nv1 = nv1, a_nv2 = nv2;
+  std::vector<int> a_nv1 = nv1, a_nv2 = nv2, a_nvg = nvg;
   for (int j = 0; j < kmax; ++j) {
     bool drop = false;
     for (int g = 0; g < G; ++g) drop = drop || cs[g]->k1 == j;
@@ -2590,12 +2624,13 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
         a_step.ax[e].fft = keep_t(t_step.ax[e].fft);
       }
       for (int g = 0; g < G; ++g)
-        if (cs[g]->k1 <= j) a_nv1[g] = a_nv2[g] = -(1 << 20);
+        if (cs[g]->k1 <= j) a_nv1[g] = a_nv2[g] = a_nvg[g] = -(1 << 20);
     }
     launch_scatter<T>(a_nodes, A.at<ScatterJob<T>>(o_sc), D, j, 1, s, two_st);
     toep_run<T>(A, a_step, j, 1, s);
     if (tab_blocks(a_cd))
       tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(a_cd), RBLK, 0, s, a_cd, dlz, j);
+    if (any_gcs) launch_colsum(A.at<SumJob>(o_gco), a_nvg, j, 1, s);
     if (tab_blocks(a_gd)) {
       tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(a_gd), RBLK, 0, s, a_gd, dlz, j);
       launch_colsum(A.at<SumJob>(o_coef), a_nv1, j, 1, s);
@@ -2739,6 +2774,7 @@ static love_status batch_impl(const std::vector<love_cache*>& cs, hipStream_t s,
         toep_run<T>(A, t_step, j, 1, s);
         if (tab_blocks(t_cd))
           tlaunch("lz_cdots", k_lz_cdots<T>, tab_blocks(t_cd), RBLK, 0, s, t_cd, dlz2, j);
+        if (any_gcs) launch_colsum(A.at<SumJob>(o_gco), nvg, j, 1, s);
         if (tab_blocks(t_gd)) {
           tlaunch("lz_gdots", k_lz_gdots<T, D>, tab_blocks(t_gd), RBLK, 0, s, t_gd, dlz2, j);
           launch_colsum(A.at<SumJob>(o_coef), nv1, j, 1, s);
