@@ -561,6 +561,11 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   __shared__ double red[CWV][REDW];
   __shared__ double rl[RBK];
   __shared__ double scr[16];
+  // 3-D and 4-D stencils (64 and 256 nodes per row) with 256-row blocks: two
+  // threads per row, each gathering half of the stencil
+  constexpr bool SPLIT = D >= 3 && RPL == 4;
+  static_assert(!SPLIT || RBLK == 2 * WAVE * RPL, "two threads per row");
+  __shared__ T gh[2][WAVE * RPL];
   const int ncols = j + 1;
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)lb * RBK;
@@ -571,9 +576,22 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
   qregs_load<T, RPL>(qr, J.Q, J.ldq, ncols, rowL);
   T vrow = T(0);
   if (J.gpath) {
-    if (t < RBK && row < J.n)
-      vrow = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) +
-             J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
+    if constexpr (SPLIT) {
+      const int rr = t & (RBK - 1), hf = t / RBK;
+      const int64_t gr = r0 + rr;
+      T part = T(0);
+      if (gr < J.n) {
+        T xr[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) xr[e] = J.x[gr * D + e];
+        part = gather_row_part<T, D>(J.g, xr, J.R + (int64_t)j * J.m, hf);
+      }
+      gh[hf][rr] = part;
+    } else {
+      if (t < RBK && row < J.n)
+        vrow = gather_row_dev<T, D>(J.g, J.x, row, J.R + (int64_t)j * J.m) +
+               J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
+    }
     if (J.gcs) {
       // the first pass's rows summed by the column-sum launch (into c2)
       for (int c = threadIdx.x; c < ncols; c += RBLK) {
@@ -594,6 +612,10 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
     for (int c = threadIdx.x; c < ncols; c += RBLK) cl[c] = J.coef[c];
   }
   __syncthreads();
+  if constexpr (SPLIT) {
+    if (J.gpath && t < RBK && row < J.n)
+      vrow = (gh[0][t] + gh[1][t]) + J.sigma2 * J.Q[(int64_t)j * J.ldq + row];
+  }
   colproj_regs<T, RPL>(qr, ncols, cl, red);
   __syncthreads();
   double rv = 0.0;
