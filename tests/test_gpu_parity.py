@@ -459,6 +459,30 @@ def test_grid_space_mean_3d():
     cache.free()
 
 
+def test_large_grid_first_pass_3d():
+    """A 28^3 grid (21,952 nodes: 86 tiles of 256 rows, the last one ragged)
+    under 70,001 points: the grid-space first pass takes one block per tile and
+    a column-sum launch adds their rows, and with 256-row blocks (n >= 65,536)
+    the second pass gathers each row's 64-node stencil with two threads.
+    Mean and variance against the oracle at 3000 points."""
+    P = WL.make_problem("d3_big", d=3, n=70_001, m=(28, 28, 28), kernel="rbf",
+                        lengthscale=(0.1, 0.12, 0.15), noise=0.2, k=30, t=3000,
+                        target="sumsin", ynoise=0.1)
+    print(P.name, P.n, P.m, flush=True)
+    assert -(-int(np.prod(P.m)) // 256) > 64 and P.n >= 65_536
+    cache = build(P)
+    info = cache.info()
+    mu, var = cache.predict_mean_var(tdev(P.xs, torch.float32))
+    oc = oracle_cache(P)
+    m_ref, v_ref = O.love_predict(oc, P.xs)
+    e = errors(host(var), v_ref, O.prior_var(P.xs, spec_of(P)), host(mu), m_ref, P.y)
+    print("k_eff", info.k_eff, oc.lanczos.k_eff, e, flush=True)
+    assert info.k_eff == oc.lanczos.k_eff
+    assert e["mean_err_rel_rms_y"] <= 1e-4
+    assert e["e_p_max"] <= 1e-5
+    cache.free()
+
+
 def test_grid_space_mean_fp64_parity():
     """Double 2-D build (grid-space mean in double, tolerance 1e-12 of
     sigma ||y||): mean and variance against the oracle at double tolerance."""
@@ -525,6 +549,26 @@ def test_batched_3d_equals_single():
     Ps = [WL.make_problem("b3d_%d" % i, d=3, n=n, m=m, kernel="rbf", lengthscale=(0.2, 0.25, 0.3),
                           noise=0.01, k=30, t=500, target="sumsin", ynoise=0.1, seed=i)
           for i, (n, m) in enumerate([(6000, (10, 10, 10)), (3000, (8, 9, 8))])]
+    caches = B.build_cache_batched([cfg_of(P) for P in Ps], [tdev(P.x, torch.float32) for P in Ps],
+                                   [tdev(P.y, torch.float32) for P in Ps])
+    for g, P in enumerate(Ps):
+        q = tdev(P.xs, torch.float32)
+        single = build(P)
+        m0, v0 = caches[g].predict_mean_var(q)
+        m1, v1 = single.predict_mean_var(q)
+        assert torch.equal(v0, v1) and torch.equal(m0, m1)
+        single.free()
+    for c in caches:
+        c.free()
+
+
+def test_batched_large_grid_equals_single():
+    """A GP whose grid-space first pass needs the column-sum launch (28^3
+    nodes under 70,001 points) batched with one that sums its rows in the
+    second pass (12^3 under 20,000): each equals its own build bit for bit."""
+    Ps = [WL.make_problem("blg_%d" % i, d=3, n=n, m=m, kernel="rbf", lengthscale=(0.1, 0.12, 0.15),
+                          noise=0.2, k=30, t=500, target="sumsin", ynoise=0.1, seed=i)
+          for i, (n, m) in enumerate([(70_001, (28, 28, 28)), (20_000, (12, 12, 12))])]
     caches = B.build_cache_batched([cfg_of(P) for P in Ps], [tdev(P.x, torch.float32) for P in Ps],
                                    [tdev(P.y, torch.float32) for P in Ps])
     for g, P in enumerate(Ps):
