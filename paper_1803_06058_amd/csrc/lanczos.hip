@@ -527,7 +527,10 @@ __device__ __forceinline__ void gpass_coef(const LzJob<T>& J, int j, int lb, dou
 // c < ncols <= LDP.  Columns go in chunks of 128 (64 for a last chunk of
 // <= 64); each chunk's rows are added in a fixed order (RBLK / chunk width
 // interleaved row sets, then the sets in order), so every block gets the
-// same sums.
+// same sums.  BATCH > 0: a thread issues its rows BATCH masked loads at a
+// time (the same sums in the same order; more registers, fewer round trips
+// to rows other blocks just wrote).
+template <int BATCH = 0>
 __device__ __forceinline__ void rows_sum(const double* part, int nrows, int ncols, double* cl) {
   __shared__ double ps[RBLK];
   for (int c0 = 0; c0 < ncols; c0 += 128) {
@@ -536,8 +539,21 @@ __device__ __forceinline__ void rows_sum(const double* part, int nrows, int ncol
     const int c = threadIdx.x & (w - 1), p = threadIdx.x >> sh;
     double s = 0.0;
     if (c0 + c < ncols) {
+      if constexpr (BATCH > 0) {
+        for (int b0 = p; b0 < nrows; b0 += BATCH * np) {
+          double v[BATCH];
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q) {
+            const int b = b0 + q * np;
+            v[q] = b < nrows ? part[(size_t)b * LDP + c0 + c] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < BATCH; ++q) s += v[q];
+        }
+      } else {
 #pragma unroll 8
-      for (int b = p; b < nrows; b += np) s += part[(size_t)b * LDP + c0 + c];
+        for (int b = p; b < nrows; b += np) s += part[(size_t)b * LDP + c0 + c];
+      }
     }
     ps[threadIdx.x] = s;
     __syncthreads();
@@ -553,6 +569,12 @@ __device__ __forceinline__ void rows_sum(const double* part, int nrows, int ncol
 // Second pass: r' = v - Q c ; partial rows of [Q^T r', ||r'||^2].  With the
 // grid-space first pass, v = W R_j + sigma^2 q_j is formed here and c comes
 // from the cdots rows.
+// Row-sum load batches of the in-kernel sums: the double runs (the sampler's,
+// at most 160 blocks, never register-bound) batch 20 loads; the float main
+// runs keep the short loop, whose register count keeps two blocks per CU.
+template <typename T>
+constexpr int RS_BATCH_OF = sizeof(T) == 8 ? 20 : 0;
+
 template <typename T, int D, int RPL>
 __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) {
   if (J.ctl->stop) return;
@@ -604,7 +626,7 @@ __device__ __forceinline__ void lz_udots_body(const LzJob<T>& J, int lb, int j) 
     }
   } else if (J.psum) {
     if (t < RBK && row < J.n) vrow = J.v[row];
-    rows_sum(J.partial, J.nb, ncols, cl);
+    rows_sum<RS_BATCH_OF<T>>(J.partial, J.nb, ncols, cl);
     if (lb == 0)
       for (int c = threadIdx.x; c < ncols; c += RBLK) J.coef[c] = cl[c];
   } else {
@@ -669,7 +691,7 @@ __device__ __forceinline__ void lz_finalize_body(const LzJob<T>& J, int lb, int 
   qregs_load<T, RPL>(qr, J.Q, J.ldq, j + 1, rowL);
   const double* c2rr = J.c2;
   if (J.psum) {
-    rows_sum(J.partial2, J.nb, j + 2, c2l);
+    rows_sum<RS_BATCH_OF<T>>(J.partial2, J.nb, j + 2, c2l);
     c2rr = c2l;
   }
   for (int c = threadIdx.x; c <= j; c += RBLK) cl[c] = c2rr[c];
@@ -1386,7 +1408,7 @@ __global__ __launch_bounds__(RBLK) void k_sp_apply_dots(int64_t m, const double*
   const int keff = ctl_main->k_eff;
   if (rtpart) {
     // s = Rt^T q from the nbr partial rows (the segment-sum launch is skipped)
-    rows_sum(rtpart, nbr, 2 * WAVE, sl);
+    rows_sum<20>(rtpart, nbr, 2 * WAVE, sl);
     for (int c = threadIdx.x; c < 2 * WAVE; c += RBLK)
       if (c >= keff) sl[c] = 0.0;
   } else {
