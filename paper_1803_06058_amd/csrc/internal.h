@@ -215,6 +215,7 @@ class JobArena {
     if (host_.empty()) return LOVE_OK;
     dev_ = (char*)ws_alloc(host_.size(), s);
     if (!dev_) return LOVE_ENOMEM;
+    st_ = s;
     LOVE_HIP_TRY(hipMemcpyAsync(dev_, host_.data(), host_.size(), hipMemcpyHostToDevice, s));
     return LOVE_OK;
   }
@@ -226,11 +227,32 @@ class JobArena {
     ws_free(dev_, s);
     dev_ = nullptr;
   }
-  ~JobArena() = default;
+  // A table not released by its owner (an error return) goes back on the
+  // stream it was uploaded on, after the work queued there.
+  ~JobArena() {
+    if (dev_) ws_free(dev_, st_);
+  }
+  JobArena() = default;
+  JobArena(const JobArena&) = delete;
+  JobArena& operator=(const JobArena&) = delete;
+  JobArena(JobArena&& o) noexcept : host_(std::move(o.host_)), dev_(o.dev_), st_(o.st_) {
+    o.dev_ = nullptr;
+  }
+  JobArena& operator=(JobArena&& o) noexcept {
+    if (this != &o) {
+      if (dev_) ws_free(dev_, st_);
+      host_ = std::move(o.host_);
+      dev_ = o.dev_;
+      st_ = o.st_;
+      o.dev_ = nullptr;
+    }
+    return *this;
+  }
 
  private:
   std::vector<char> host_;
   char* dev_ = nullptr;
+  hipStream_t st_ = nullptr;
 };
 
 // A K_UU application prepared for G GPs (one entry per axis; each backend is

@@ -1869,6 +1869,16 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
   SumJob js_coef{partial, coef, ctl, (int)nb, 1};
   SumJob js_c2{partial, c2, ctl, (int)nb, 2};
   JobArena A;
+  // the workspace and the job tables go back on every return path
+  struct SpRelease {
+    char* buf;
+    JobArena& a;
+    hipStream_t st;
+    ~SpRelease() {
+      a.release(st);
+      ws_free(buf, st);
+    }
+  } sp_release{buf, A, s};
   const size_t o_lz = A.add(std::vector<LzJob<double>>{J});
   const size_t o_rt = A.add(std::vector<SumJob>{js_rt});
   const size_t o_coef = A.add(std::vector<SumJob>{js_coef});
@@ -1942,8 +1952,6 @@ static love_status sampler_impl(love_cache* c, hipStream_t s) {
     dim3 sgrid((unsigned)cdiv(m, 256), (unsigned)cdiv(c->kspad, 16));
     k_s_from_eig<<<sgrid, 256, 0, s>>>(m, Q, ldq, vout, lam, c->S, c->kspad, ctl);
   }
-  A.release(s);
-  ws_free(buf, s);
   LOVE_HIP_TRY(hipGetLastError());
   return LOVE_OK;
 }

@@ -3,6 +3,8 @@ covariance blocks through a caller-supplied love_allocator (torch's caching
 allocator) equal the library-pool results bit for bit and return every block
 they took; an explicit FFT request the LDS-resident FFT cannot meet is
 refused."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -114,3 +116,70 @@ def test_explicit_fft_beyond_lds_refused():
     c = _build(P, None, toeplitz="auto", k=4, flags=B.FLAG_NO_MEAN)
     assert c.info().toeplitz_mode[0] == 1
     c.free()
+
+
+class _RefuseNth:
+    """A love_allocator over torch's caching allocator that refuses its n-th
+    request (n = 0: none) and counts the blocks it has handed out and not had
+    back."""
+
+    def __init__(self, n):
+        self.n, self.calls, self.live = n, 0, 0
+
+        def _alloc(nbytes, stream, ctx):
+            self.calls += 1
+            if self.calls == self.n:
+                return None
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            self.live += 1
+            return p
+
+        def _free(ptr, stream, ctx):
+            self.live -= 1
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._a, self._f = B.ALLOC_FN(_alloc), B.FREE_FN(_free)
+        self.struct = B.love_allocator(self._a, self._f, None)
+
+    def ref(self):
+        return C.byref(self.struct)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_refused_allocation_returns_enomem_and_releases_every_block(batched):
+    """Each device allocation of a build refused in turn (a single build, and a
+    batch of two GPs whose samplers run on the side stream): the build returns
+    ENOMEM, every block handed out comes back once the stream is done, and a
+    build afterwards gives the same variances as before."""
+    P = WL.config(2, scale=0.05, s=16)
+    dt = torch_dtype(P)
+    x, y = tdev(P.x, dt), tdev(P.y, dt)
+    xs = tdev(P.xs[:2000], dt)
+
+    def run(alloc):
+        if batched:
+            return B.build_cache_batched([cfg_of(P)] * 2, [x, x], [y, y], allocator=alloc)
+        return [B.build_cache(cfg_of(P), x, y, allocator=alloc)]
+
+    def variances(cs):
+        out = [c.predict_mean_var(xs)[1].cpu() for c in cs]
+        for c in cs:
+            c.free()
+        torch.cuda.synchronize()
+        return out
+
+    ref = variances(run(None))
+    count = _RefuseNth(0)
+    variances(run(count))
+    n = count.calls
+    print("allocations per build", n, flush=True)
+    assert n >= 2 and count.live == 0
+    for k in range(1, n + 1):
+        a = _RefuseNth(k)
+        with pytest.raises(B.LoveError) as ei:
+            run(a)
+        torch.cuda.synchronize()
+        assert ei.value.code == -4, (k, ei.value.code)
+        assert a.live == 0, (k, a.live)
+    for u, v in zip(variances(run(_RefuseNth(0))), ref):
+        assert torch.equal(u, v)
