@@ -183,3 +183,38 @@ def test_refused_allocation_returns_enomem_and_releases_every_block(batched):
         assert a.live == 0, (k, a.live)
     for u, v in zip(variances(run(_RefuseNth(0))), ref):
         assert torch.equal(u, v)
+
+
+def test_refused_query_workspace_returns_enomem_and_keeps_the_cache():
+    """The query calls that take workspace from the cache's allocator (samples,
+    covariance block, backward with d var / d Rt, hyper-parameter gradient),
+    each with its first workspace request refused: ENOMEM, every block handed
+    out for the call comes back, and the same call afterwards gives the
+    answer of an unrefused call."""
+    P = WL.config(2, scale=0.05, s=16)
+    dt = torch_dtype(P)
+    a = _RefuseNth(0)
+    c = B.build_cache(cfg_of(P, flags=B.FLAG_HYPER), tdev(P.x, dt), tdev(P.y, dt), allocator=a)
+    xs = tdev(P.xs[:500], dt)
+    g = torch.ones(500, device=xs.device, dtype=dt)
+    calls = {
+        "sample": lambda: c.sample_posterior(tdev(P.xs_sample[:100], dt), tdev(P.z, torch.float32)),
+        "covar_block": lambda: c.predict_covar_block(xs[:40], xs[40:70]),
+        "backward_grt": lambda: c.predict_backward(xs, g, g, want_grt=True)[1],
+        "hyper_grad": lambda: c.predict_var_hyper_grad(xs, g),
+    }
+    for name, f in calls.items():
+        ref = f().clone()
+        torch.cuda.synchronize()
+        held = a.live
+        a.n = a.calls + 1
+        with pytest.raises(B.LoveError) as ei:
+            f()
+        torch.cuda.synchronize()
+        print(name, "code", ei.value.code, "live", a.live, "held", held, flush=True)
+        assert ei.value.code == -4, name
+        assert a.live == held, name
+        assert torch.equal(f(), ref), name
+    c.free()
+    torch.cuda.synchronize()
+    assert a.live == 0
