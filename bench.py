@@ -115,9 +115,10 @@ def alg_bytes(name, P, k_eff, calls_per_step, ks_eff=0):
         gpath = m <= n          # partial rows
         return sum(f * n * (j + 1) + (f * n * d + f * m if gpath else f * n) + f * n +
                    8 * nb * (j + 2) for j in range(k_eff))
-    if name == "lz_cdots":      # read G_{0..j} (m rows) and R_j; partial rows
-        return sum(f * m * (j + 1) + f * m + 8 * min(64, -(-m // 256)) * (j + 1)
-                   for j in range(k_eff))
+    if name == "lz_cdots":      # read G_{0..j} (m rows) and R_j; partial rows (one per
+        tiles = -(-m // 256)    # 256-row tile up to 64 tiles, else up to 1024)
+        nbc = tiles if tiles <= 64 else min(tiles, 1024)
+        return sum(f * m * (j + 1) + f * m + 8 * nbc * (j + 1) for j in range(k_eff))
     if name == "lz_gdots":      # read x, R_j, q_j, Q_{0..j}; write v
         return sum(f * n * d + f * m + f * n * (j + 1) + 2 * f * n for j in range(k_eff))
     if name == "lz_finalize":   # read r', Q_{0..j}; write q_{j+1}
